@@ -1,0 +1,297 @@
+/*
+ * gs.h -- C ABI of the MI355X (gfx950) differentiable 3D Gaussian-splatting
+ * rasterizer: the per-iteration hot path of the CaRtGS mapping back-end.
+ *
+ * The paper (CaRtGS, Sec. III-B) renders a keyframe from Gaussian primitives
+ * with position p, quaternion q, scale s, opacity sigma and degree-3 SH
+ * colour by alpha blending, Eq. (1), and refines the primitives by the loss
+ * gradients of Eqs. (9)-(11) propagated back through the blend, Eqs. (2)-(4)
+ * (Sec. III-C-1); the optimiser is that of 3DGS, which the paper retains
+ * (Sec. IV-A).  One mapping iteration is
+ *
+ *     gs_preprocess -> gs_bin_sort -> gs_render_fwd -> gs_render_bwd
+ *     (-> gs_adam_step)
+ *
+ * over one or more keyframes ("views").
+ *
+ * Conventions (all entry points):
+ *   - Every function returns gs_status; GS_OK on success.  Argument checks
+ *     are synchronous and happen before anything is enqueued; on error
+ *     nothing is enqueued and gs_last_error() (thread-local) describes it.
+ *   - Device-side conditions never fail a call.  They are reported through
+ *     int32 flags inside the workspace (gs_flags_ptr): pair-capacity overflow
+ *     and the count of Gaussians culled for non-finite parameters.  After an
+ *     overflow, the downstream kernels of that iteration see zero pairs and
+ *     their outputs are invalid; the caller re-plans with a larger capacity.
+ *   - Ownership: every buffer is owned by the caller.  Calls never allocate
+ *     device memory, never free it and never synchronise with the host.
+ *     Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *     null stream) and is safe to capture with hipStreamBeginCapture.  The
+ *     only library-owned objects are gs_graph handles (host objects holding
+ *     an instantiated HIP graph), which the caller destroys.
+ *   - Floating-point data are float32; image buffers are concatenated over
+ *     views in view order: colour planar [3][H][W] per view, depth, T_final
+ *     and last [H][W] per view.
+ *   - Calls on distinct workspaces are independent and may run concurrently;
+ *     calls that share a workspace must be stream-ordered.
+ */
+#ifndef GS_H_
+#define GS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gs_status;
+#define GS_OK 0
+#define GS_ERR_INVALID_ARG 1  /* null/misaligned pointer, bad size, plan mismatch */
+#define GS_ERR_UNSUPPORTED 2  /* sh_degree > 3, tile shape not 8x8/16x16/16x8, ... */
+#define GS_ERR_HIP 3          /* a HIP runtime call or kernel launch failed */
+
+#define GS_MAX_VIEWS 64
+/* Device camera record, 20 float32 per view:
+ *   fx fy cx cy | R[9] (world->camera rotation, row-major) | t[3] | near | bg[3]
+ * x_cam = R x_world + t; image x right, y down, z forward; pixel (i, j)
+ * is sampled at (i + 0.5, j + 0.5).  Image sizes come from the plan. */
+#define GS_CAMERA_FLOATS 20
+
+/* gs_raster_cfg.flags */
+#define GS_CUTOFF_3SIGMA (1u << 0)    /* tile box from 3 sqrt(lambda_max) instead of the
+                                         exact alpha >= 1/255 box (comparison only) */
+#define GS_FUSED_L1 (1u << 1)         /* gs_render_bwd derives dL/dC, dL/dD from the L1
+                                         loss against the targets instead of inputs */
+#define GS_ACCUMULATE_GRADS (1u << 2) /* gs_render_bwd adds into the gradient buffers */
+#define GS_PERSISTENT (1u << 3)       /* render kernels pull tile chunks from a device
+                                         work queue (longest tiles first) */
+
+/* Gaussian parameters (Sec. III-B): SoA, float32, device pointers. */
+typedef struct gs_gaussians {
+  const float* means;          /* [n][3] world position p */
+  const float* log_scales;     /* [n][3] s = exp(log_scales) */
+  const float* quats;          /* [n][4] (w, x, y, z); normalised inside */
+  const float* opacity_logits; /* [n]    opacity = sigmoid(logit) */
+  const float* sh;             /* [n][(deg+1)^2][3] real SH coefficients */
+  int64_t n;
+  int32_t sh_degree;           /* 0..3 */
+} gs_gaussians;
+
+/* Gradients, same layout as gs_gaussians, device pointers (all required). */
+typedef struct gs_gaussian_grads {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacity_logits;
+  float* sh;
+} gs_gaussian_grads;
+
+typedef struct gs_raster_cfg {
+  int32_t tile_w;       /* 8 or 16 */
+  int32_t tile_h;       /* 8 or 16 (16x16, 16x8, 8x8) */
+  int32_t chunk;        /* tiles per work item in GS_PERSISTENT mode, 1..16 */
+  int32_t lds_batch;    /* records staged in LDS per batch: 64, 128 or 256 */
+  uint32_t flags;       /* GS_* flags above */
+  float lambda_depth;   /* weight of the depth term of the fused L1 loss */
+} gs_raster_cfg;
+
+/* Execution plan: sizes, per-view tile/pixel offsets and the workspace
+ * layout.  Caller-allocated, filled by gs_plan_init, read-only afterwards;
+ * host memory, opaque. */
+typedef struct gs_plan {
+  uint64_t opaque[640];
+} gs_plan;
+
+/* Fill `plan` for n Gaussians of SH degree sh_degree rendered into n_views
+ * views of sizes view_wh (host array [n_views][2] = width, height), with up
+ * to pair_capacity (Gaussian, tile) pairs in total over all views.
+ * Errors: GS_ERR_INVALID_ARG (n < 0, n_views not in 1..GS_MAX_VIEWS, a
+ * width/height not in 1..16384, pair_capacity not in 1..2^31-1, more than
+ * 2^31-1 records or pixels), GS_ERR_UNSUPPORTED (degree or tile shape). */
+gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_views,
+                       const int32_t* view_wh, const gs_raster_cfg* cfg,
+                       int64_t pair_capacity);
+
+/* Bytes of device workspace the plan needs (256-byte aligned base). */
+size_t gs_workspace_size(const gs_plan* plan);
+
+/* Queries: total pixels over views, pixel offset of a view, total tiles. */
+int64_t gs_plan_total_pixels(const gs_plan* plan);
+int64_t gs_plan_pixel_offset(const gs_plan* plan, int32_t view);
+int64_t gs_plan_total_tiles(const gs_plan* plan);
+
+/* Device pointer to the int32 flags inside `ws`:
+ *   [0] pair-capacity overflow (0/1)   [1] Gaussians culled as non-finite
+ *   [2] pair count P of the last gs_bin_sort (valid if [0] == 0)
+ *   [3] summed visible (view, Gaussian) records of the last gs_preprocess
+ *   [6] pairs the last gs_bin_sort needed (saturated at 2^31-1) */
+int32_t* gs_flags_ptr(const gs_plan* plan, void* ws);
+
+/* Byte offset inside the workspace of an intermediate array, for
+ * inspection by tests and tools (-1 for an unknown region):
+ *   GS_WS_RECORDS       [n_views*n] 64-byte records: f64 mean x, y; f64
+ *                       -a/2, -b, -c/2 of the conic [[a,b],[b,c]]; f32
+ *                       opacity, depth, r, g, b, pad
+ *   GS_WS_RECTS         [n_views*n] u16 x0, y0, x1, y1 (tile box, exclusive)
+ *   GS_WS_TILES_TOUCHED [n_views*n] u32
+ *   GS_WS_PAIR_OFFSETS  [n_views*n] u32, first pair of each visible record
+ *   GS_WS_SORTED_KEYS   [P] u64 after gs_bin_sort
+ *   GS_WS_SORTED_VALS   [P] u32 (pair index in generation order)
+ *   GS_WS_SORTED_RECS   [P] u32 (record index v*n + i of each sorted pair)
+ *   GS_WS_RANGES        [total_tiles][2] u32 */
+#define GS_WS_RECORDS 0
+#define GS_WS_RECTS 1
+#define GS_WS_TILES_TOUCHED 2
+#define GS_WS_PAIR_OFFSETS 3
+#define GS_WS_SORTED_KEYS 4
+#define GS_WS_SORTED_VALS 5
+#define GS_WS_SORTED_RECS 6
+#define GS_WS_RANGES 7
+int64_t gs_plan_ws_offset(const gs_plan* plan, int32_t region);
+
+/* a1. Per (view, Gaussian): activations, quaternion rotation, 3D covariance,
+ * camera transform, near cull (z <= near), EWA 2D covariance with 0.3 px^2
+ * dilation and Jacobian clamped at 1.3x the half FOV, conic, exact tile box
+ * of the alpha >= 1/255 ellipse, SH colour clamped at 0, depth.  Gaussians
+ * with non-finite parameters or a zero quaternion are culled and counted.
+ * (Sec. III-B: parameters p, q, s, sigma, SH; alpha from a projected 2D
+ * Gaussian times opacity.)  cams_dev: device [n_views][GS_CAMERA_FLOATS].
+ * g->n and g->sh_degree must equal the plan's. */
+gs_status gs_preprocess(const gs_plan* plan, const gs_gaussians* g, const float* cams_dev,
+                        void* ws, void* stream);
+
+/* a2. Tile binning: exclusive scan of tiles touched, duplication of one
+ * (global tile id << 32 | float32 bits of depth) key per (Gaussian, tile) in
+ * Gaussian-major, row-major tile order, stable LSD radix sort over the key
+ * bits in use, per-tile [start, end) ranges.  Ties in depth keep Gaussian
+ * order, so the sorted list is unique and bit-exact.  Overflow of the plan's
+ * pair capacity sets flag [0]. */
+gs_status gs_bin_sort(const gs_plan* plan, void* ws, void* stream);
+
+/* a3. Front-to-back compositing of Eq. (1) per pixel over its tile's sorted
+ * list: alpha = min(0.99, o G); skip if the exponent is positive or alpha <
+ * 1/255; stop before blending when T (1 - alpha) < 1e-4.  Outputs (device,
+ * concatenated over views): color [3][H][W] = sum c alpha T + T_final bg,
+ * depth [H][W] = sum z alpha T (camera z, unnormalised), T_final [H][W],
+ * last [H][W] = 1 + position in the tile list of the last blended Gaussian
+ * (0 if none).  If target_rgb is non-null, loss_per_view[v] receives the L1
+ * loss mean|C - C*| + lambda_depth mean|D - D*| (depth term only if
+ * target_depth is non-null); loss_per_view may be null otherwise.  cams_dev
+ * supplies the background colour of each view. */
+gs_status gs_render_fwd(const gs_plan* plan, void* ws, const float* cams_dev, float* color,
+                        float* depth, float* T_final, uint32_t* last, const float* target_rgb,
+                        const float* target_depth, float* loss_per_view, void* stream);
+
+/* a4-a6. Backward of one iteration (Eqs. (2)-(4)).  Per pixel, back to front
+ * from its last blended Gaussian, with the transmittance recomputed by
+ * division from T_final; per-pair gradients are reduced across each
+ * wavefront and tile, then per Gaussian in a fixed order (deterministic),
+ * and carried through the projection to the parameters.  Upstream gradients
+ * are dL_dcolor [3][H][W] and dL_ddepth [H][W] (nullable: zero), or, with
+ * GS_FUSED_L1, those of the L1 loss of gs_render_fwd against target_rgb and
+ * target_depth (sign(0) = 0).  `out` is overwritten (GS_ACCUMULATE_GRADS:
+ * added to).  dL_dpose (nullable) receives [n_views][6] = (rho, phi), the
+ * gradient w.r.t. a left perturbation R <- Exp(phi) R, t <- Exp(phi) t + rho
+ * of each view's pose at zero (overwritten).  The forward buffers must be
+ * those written by gs_render_fwd with the same plan and workspace. */
+gs_status gs_render_bwd(const gs_plan* plan, const gs_gaussians* g, const float* cams_dev,
+                        void* ws, const float* color, const float* depth,
+                        const float* T_final, const uint32_t* last,
+                        const float* dL_dcolor, const float* dL_ddepth,
+                        const float* target_rgb, const float* target_depth,
+                        const gs_gaussian_grads* out, float* dL_dpose, void* stream);
+
+/* The two stages of gs_render_bwd as separate calls (same arguments, same
+ * checks).  a5: gs_render_bwd_raster runs the per-pixel backward and leaves
+ * one 10-float partial gradient (rgb, depth, opacity, conic a b c, mean x y)
+ * per (tile, Gaussian) pair in the workspace.  a6: gs_project_bwd reduces
+ * those partials per Gaussian in a fixed order and applies the chain rule to
+ * the parameters and the camera tangents. */
+gs_status gs_render_bwd_raster(const gs_plan* plan, void* ws, const float* cams_dev,
+                               const float* color, const float* depth, const float* T_final,
+                               const uint32_t* last, const float* dL_dcolor,
+                               const float* dL_ddepth, const float* target_rgb,
+                               const float* target_depth, void* stream);
+gs_status gs_project_bwd(const gs_plan* plan, const gs_gaussians* g, const float* cams_dev,
+                         void* ws, const gs_gaussian_grads* out, float* dL_dpose, void* stream);
+
+/* a7. One Adam step over several parameter groups in a single launch
+ * (torch.optim.Adam semantics without weight decay, the 3DGS optimiser):
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= lr / (1 - b1^t) * m / (sqrt(v) / sqrt(1 - b2^t) + eps).
+ * Groups are a host array of device pointers.  If a group has
+ * opacity_reg != 0, the gradient of lambda_o * mean_i |sigmoid(p_i)| over
+ * reg_count Gaussians (Eq. (10)) is added to g first (p is a logit).
+ * Hyper-parameters are doubles: 1 - beta and the bias corrections are formed
+ * in double precision and rounded once, as torch does for float32 params.
+ * step_dev (nullable): device int32 step counter; when given, t = *step_dev
+ * + 1 is read on the device and written back after the update (for graph
+ * replays), and `step` is ignored.  Pointers must be 16-byte aligned. */
+typedef struct gs_param_group {
+  float* p;
+  const float* g;
+  float* m;
+  float* v;
+  int64_t n;
+  float lr;
+  int32_t opacity_reg;
+} gs_param_group;
+
+gs_status gs_adam_step(const gs_param_group* groups, int32_t n_groups, int32_t step,
+                       double beta1, double beta2, double eps, double lambda_o,
+                       int64_t reg_count, int32_t* step_dev, void* stream);
+
+/* Stand-alone stable LSD radix sort of n (key, value) pairs on the low
+ * key_bits bits of the keys (1..64), the same kernels gs_bin_sort uses.
+ * keys/vals are device arrays, sorted in place; tmp is device scratch of
+ * gs_sort_tmp_bytes(n) bytes. */
+size_t gs_sort_tmp_bytes(int64_t n);
+gs_status gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits,
+                        void* tmp, void* stream);
+
+/* a8. Whole-iteration hipGraph.  The descriptor names every buffer of one
+ * mapping iteration; gs_graph_create captures gs_preprocess, gs_bin_sort,
+ * gs_render_fwd, gs_render_bwd and (if n_adam_groups > 0) gs_adam_step on
+ * `stream` and instantiates the graph.  Poses, parameters and targets live
+ * in device memory, so replays see their current values.  Adam needs
+ * step_dev (the device step counter) so replays advance the bias correction. */
+typedef struct gs_iteration {
+  const gs_plan* plan;
+  void* ws;
+  gs_gaussians gaussians;
+  const float* cams_dev;
+  float* color;
+  float* depth;
+  float* T_final;
+  uint32_t* last;
+  const float* target_rgb;
+  const float* target_depth;
+  float* loss_per_view;
+  const float* dL_dcolor;
+  const float* dL_ddepth;
+  gs_gaussian_grads grads;
+  float* dL_dpose;
+  const gs_param_group* adam_groups; /* host array, copied at creation */
+  int32_t n_adam_groups;
+  int32_t* step_dev;
+  double beta1, beta2, eps, lambda_o;
+  int64_t reg_count;
+} gs_iteration;
+
+typedef struct gs_graph gs_graph;
+
+gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream);
+gs_status gs_graph_create(const gs_iteration* it, void* stream, gs_graph** out);
+gs_status gs_graph_launch(gs_graph* graph, void* stream);
+gs_status gs_graph_destroy(gs_graph* graph);
+
+const char* gs_status_string(gs_status s);
+const char* gs_last_error(void);
+int32_t gs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H_ */

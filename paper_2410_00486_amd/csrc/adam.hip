@@ -1,0 +1,129 @@
+// a7: Adam over several parameter groups in one launch (the 3DGS optimiser,
+// retained by the paper, Sec. IV-A), with the optional opacity regulariser
+// of Eq. (10) folded into the gradient of the opacity-logit group.
+// Bound by HBM: 28 bytes per parameter (p, g, m, v read; p, m, v written).
+#include "gs_internal.h"
+
+namespace gs {
+
+constexpr int kAdamMaxGroups = 8;
+constexpr int kAdamThreads = 256;
+constexpr int kAdamVec = 4;  // float4 per thread
+
+struct AdamGroupArg {
+  float* p;
+  const float* g;
+  float* m;
+  float* v;
+  int64_t n;
+  int64_t block0;  // first block of this group
+  float lr;
+  int32_t reg;
+};
+
+struct AdamArgs {
+  AdamGroupArg grp[kAdamMaxGroups];
+  int32_t n_groups;
+  int32_t step;
+  double beta1d, beta2d;  // for the bias corrections
+  float beta1, beta2;     // multipliers of m and v
+  float omb1, omb2;       // 1 - beta, formed in double
+  float eps;
+  float reg_scale;        // lambda_o / reg_count
+  const int32_t* step_dev;
+};
+
+namespace {
+
+__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, const AdamArgs& a,
+                                         float step_size, float inv_bc2s, int reg) {
+  if (reg) {
+    const float o = 1.0f / (1.0f + expf(-p));
+    g += a.reg_scale * o * (1.0f - o);
+  }
+  const float b1 = a.beta1, b2 = a.beta2, eps = a.eps;
+  m = b1 * m + a.omb1 * g;
+  v = b2 * v + a.omb2 * g * g;
+  const float denom = sqrtf(v) * inv_bc2s + eps;
+  p = p - step_size * (m / denom);
+}
+
+__global__ void __launch_bounds__(kAdamThreads) k_adam(AdamArgs a) {
+  int gi = 0;
+  while (gi + 1 < a.n_groups && (int64_t)blockIdx.x >= a.grp[gi + 1].block0) ++gi;
+  const AdamGroupArg G = a.grp[gi];
+  const int step = a.step_dev ? (*a.step_dev + 1) : a.step;
+  const double bc1 = 1.0 - pow(a.beta1d, (double)step);
+  const double bc2 = 1.0 - pow(a.beta2d, (double)step);
+  const float step_size = (float)((double)G.lr / bc1);
+  const float inv_bc2s = (float)(1.0 / sqrt(bc2));
+  const int64_t e0 = ((int64_t)blockIdx.x - G.block0) * (kAdamThreads * kAdamVec) +
+                     (int64_t)threadIdx.x * kAdamVec;
+  if (e0 + kAdamVec <= G.n) {
+    float4 p = *reinterpret_cast<float4*>(G.p + e0);
+    const float4 g = *reinterpret_cast<const float4*>(G.g + e0);
+    float4 m = *reinterpret_cast<float4*>(G.m + e0);
+    float4 v = *reinterpret_cast<float4*>(G.v + e0);
+    adam_one(p.x, g.x, m.x, v.x, a, step_size, inv_bc2s, G.reg);
+    adam_one(p.y, g.y, m.y, v.y, a, step_size, inv_bc2s, G.reg);
+    adam_one(p.z, g.z, m.z, v.z, a, step_size, inv_bc2s, G.reg);
+    adam_one(p.w, g.w, m.w, v.w, a, step_size, inv_bc2s, G.reg);
+    *reinterpret_cast<float4*>(G.p + e0) = p;
+    *reinterpret_cast<float4*>(G.m + e0) = m;
+    *reinterpret_cast<float4*>(G.v + e0) = v;
+  } else {
+    for (int64_t e = e0; e < G.n; ++e) {
+      float p = G.p[e], m = G.m[e], v = G.v[e];
+      adam_one(p, G.g[e], m, v, a, step_size, inv_bc2s, G.reg);
+      G.p[e] = p;
+      G.m[e] = m;
+      G.v[e] = v;
+    }
+  }
+}
+
+__global__ void k_step_advance(int32_t* step_dev) { *step_dev += 1; }
+
+}  // namespace
+
+int64_t adam_blocks(int64_t n) {
+  return (n + kAdamThreads * kAdamVec - 1) / (kAdamThreads * kAdamVec);
+}
+
+hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, double beta1,
+                       double beta2, double eps, double lambda_o, int64_t reg_count,
+                       int32_t* step_dev, hipStream_t s) {
+  for (int base = 0; base < n_groups; base += kAdamMaxGroups) {
+    AdamArgs a{};
+    const int ng = n_groups - base < kAdamMaxGroups ? n_groups - base : kAdamMaxGroups;
+    int64_t blocks = 0;
+    for (int k = 0; k < ng; ++k) {
+      const gs_param_group& G = groups[base + k];
+      a.grp[k] = AdamGroupArg{G.p, G.g, G.m, G.v, G.n, blocks, G.lr, G.opacity_reg};
+      blocks += adam_blocks(G.n);
+    }
+    a.n_groups = ng;
+    a.step = step;
+    a.beta1d = beta1;
+    a.beta2d = beta2;
+    a.beta1 = (float)beta1;
+    a.beta2 = (float)beta2;
+    a.omb1 = (float)(1.0 - beta1);
+    a.omb2 = (float)(1.0 - beta2);
+    a.eps = (float)eps;
+    a.reg_scale = (lambda_o != 0.0 && reg_count > 0) ? (float)(lambda_o / (double)reg_count) : 0.0f;
+    if (a.reg_scale == 0.0f)
+      for (int k = 0; k < ng; ++k) a.grp[k].reg = 0;
+    a.step_dev = step_dev;
+    if (blocks > 0) hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(kAdamThreads), 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (step_dev) {
+    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(1), 0, s, step_dev);
+    return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
+}  // namespace gs

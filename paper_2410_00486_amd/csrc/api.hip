@@ -1,0 +1,512 @@
+// C ABI of the rasterizer library: plan and workspace layout, argument
+// checks, the entry points of one mapping iteration, the stand-alone sort,
+// and whole-iteration HIP graphs.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gs_internal.h"
+
+namespace gs {
+hipError_t launch_preprocess(const Plan& P, const gs_gaussians& g, const float* cams, void* ws,
+                             hipStream_t s);
+hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s);
+hipError_t launch_radix_sort(uint64_t* keys0, uint64_t* keys1, uint32_t* vals0, uint32_t* vals1,
+                             const int32_t* cnt, uint32_t* hist, uint32_t* digit_tot,
+                             int64_t nb_cap, int key_bits, bool iota, int* which, hipStream_t s);
+hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t s);
+uint32_t* sorted_vals(const Plan& P, void* ws);
+hipError_t launch_render_fwd(const Plan& P, void* ws, const float* cams, float* color,
+                             float* depth, float* T_final, uint32_t* last,
+                             const float* target_rgb, const float* target_depth,
+                             float* loss_per_view, const uint32_t* order, int32_t* queue,
+                             int grid, hipStream_t s);
+hipError_t launch_render_bwd(const Plan& P, void* ws, const float* cams, const float* color,
+                             const float* depth, const float* T_final, const uint32_t* last,
+                             const float* dL_dcolor, const float* dL_ddepth,
+                             const float* target_rgb, const float* target_depth, int fused,
+                             const uint32_t* sorted_vals, const uint32_t* order, int32_t* queue,
+                             int grid, hipStream_t s);
+size_t render_bwd_lds_bytes(const Plan& P);
+hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float* cams, void* ws,
+                              const gs_gaussian_grads& out, float* dL_dpose, int accumulate,
+                              hipStream_t s);
+hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, double beta1,
+                       double beta2, double eps, double lambda_o, int64_t reg_count,
+                       int32_t* step_dev, hipStream_t s);
+hipError_t launch_tile_order(const Plan& P, void* ws, hipStream_t s);
+}  // namespace gs
+
+using namespace gs;
+
+namespace {
+
+thread_local std::string g_err;
+
+gs_status fail(gs_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+gs_status fail(gs_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+gs_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return GS_OK;
+  return fail(GS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int ceil_log2(int64_t v) {
+  int b = 0;
+  while ((int64_t(1) << b) < v) ++b;
+  return b;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+gs_status check_plan(const gs_plan* plan) {
+  if (!plan) return fail(GS_ERR_INVALID_ARG, "plan is null");
+  if (plan_of(plan)->magic != kPlanMagic) return fail(GS_ERR_INVALID_ARG, "plan is not initialised");
+  return GS_OK;
+}
+
+gs_status check_ws(const Plan& P, void* ws) {
+  if (!ws) return fail(GS_ERR_INVALID_ARG, "workspace is null");
+  if (!aligned(ws, 256)) return fail(GS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  (void)P;
+  return GS_OK;
+}
+
+gs_status check_gaussians(const Plan& P, const gs_gaussians* g) {
+  if (!g) return fail(GS_ERR_INVALID_ARG, "gaussians is null");
+  if (g->n != P.n) return fail(GS_ERR_INVALID_ARG, "gaussians.n (%lld) != plan n (%lld)", (long long)g->n, (long long)P.n);
+  if (g->sh_degree != P.deg) return fail(GS_ERR_INVALID_ARG, "sh_degree %d != plan degree %d", g->sh_degree, P.deg);
+  if (P.n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh))
+    return fail(GS_ERR_INVALID_ARG, "a Gaussian parameter pointer is null");
+  if (!aligned(g->quats, 16)) return fail(GS_ERR_INVALID_ARG, "quats must be 16-byte aligned");
+  return GS_OK;
+}
+
+int device_cus() {
+  static int cus = 0;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      cus = prop.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  });
+  return cus;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t gs_version(void) { return 1; }
+
+const char* gs_status_string(gs_status s) {
+  switch (s) {
+    case GS_OK: return "GS_OK";
+    case GS_ERR_INVALID_ARG: return "GS_ERR_INVALID_ARG";
+    case GS_ERR_UNSUPPORTED: return "GS_ERR_UNSUPPORTED";
+    case GS_ERR_HIP: return "GS_ERR_HIP";
+    default: return "GS_ERR_UNKNOWN";
+  }
+}
+
+const char* gs_last_error(void) { return g_err.c_str(); }
+
+gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_views,
+                       const int32_t* view_wh, const gs_raster_cfg* cfg, int64_t pair_capacity) {
+  if (!plan || !view_wh || !cfg) return fail(GS_ERR_INVALID_ARG, "plan, view_wh and cfg must be non-null");
+  std::memset(plan, 0, sizeof(*plan));
+  if (n < 0) return fail(GS_ERR_INVALID_ARG, "n must be >= 0");
+  if (sh_degree < 0 || sh_degree > 3) return fail(GS_ERR_UNSUPPORTED, "sh_degree must be 0..3");
+  if (n_views < 1 || n_views > GS_MAX_VIEWS) return fail(GS_ERR_INVALID_ARG, "n_views must be 1..%d", GS_MAX_VIEWS);
+  const int tw = cfg->tile_w, th = cfg->tile_h;
+  if (!((tw == 16 && th == 16) || (tw == 16 && th == 8) || (tw == 8 && th == 8)))
+    return fail(GS_ERR_UNSUPPORTED, "tile shape %dx%d not supported (16x16, 16x8, 8x8)", tw, th);
+  if (cfg->lds_batch < 32 || cfg->lds_batch > 256 || (cfg->lds_batch % 32) != 0)
+    return fail(GS_ERR_UNSUPPORTED, "lds_batch must be a multiple of 32 in 32..256");
+  if (cfg->chunk < 1 || cfg->chunk > 16) return fail(GS_ERR_INVALID_ARG, "chunk must be 1..16");
+  if (pair_capacity < 1 || pair_capacity > INT32_MAX) return fail(GS_ERR_INVALID_ARG, "pair_capacity must be 1..2^31-1");
+  Plan* P = plan_of(plan);
+  P->n = n;
+  P->deg = sh_degree;
+  P->K = (sh_degree + 1) * (sh_degree + 1);
+  P->n_views = n_views;
+  P->n_rec = n * n_views;
+  if (P->n_rec > INT32_MAX) return fail(GS_ERR_INVALID_ARG, "n * n_views must be < 2^31");
+  P->pair_cap = pair_capacity;
+  P->cfg = *cfg;
+  ViewTable& vt = P->vt;
+  vt.n_views = n_views;
+  vt.tw = tw;
+  vt.th = th;
+  int64_t tiles = 0, pix = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const int W = view_wh[2 * v], H = view_wh[2 * v + 1];
+    if (W < 1 || H < 1 || W > 16384 || H > 16384) return fail(GS_ERR_INVALID_ARG, "view %d size %dx%d out of range", v, W, H);
+    ViewInfo& vi = vt.v[v];
+    vi.W = W;
+    vi.H = H;
+    vi.tiles_x = (W + tw - 1) / tw;
+    vi.tiles_y = (H + th - 1) / th;
+    vi.tile_off = (int32_t)tiles;
+    vi.pix_off = (int32_t)pix;
+    tiles += (int64_t)vi.tiles_x * vi.tiles_y;
+    pix += (int64_t)W * H;
+    if (tiles > INT32_MAX / 2 || pix > INT32_MAX / 3) return fail(GS_ERR_INVALID_ARG, "too many pixels or tiles");
+  }
+  vt.total_tiles = (int32_t)tiles;
+  vt.total_pix = pix;
+  P->tile_bits = std::max(1, ceil_log2(tiles));
+  P->key_bits = 32 + P->tile_bits;
+  P->sort_passes = (P->key_bits + kRadixBits - 1) / kRadixBits;
+  P->scan_blocks = (P->n_rec + kScanTile - 1) / kScanTile;
+  P->sort_blocks_cap = (pair_capacity + kSortTile - 1) / kSortTile;
+  P->proj_blocks = (n + kProjThreads - 1) / kProjThreads;
+  const int64_t order_blocks = (tiles + kSortTile - 1) / kSortTile;
+  const int64_t hist_blocks = std::max(P->sort_blocks_cap, order_blocks);
+
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + std::max<size_t>(bytes, 1), 256);
+    return at;
+  };
+  const size_t cap = (size_t)pair_capacity, nrec = (size_t)P->n_rec, T = (size_t)tiles;
+  P->off_flags = take(F_COUNT * 4 * 4);
+  P->off_rec = take(nrec * sizeof(Rec));
+  P->off_rect = take(nrec * 8);
+  P->off_tt = take(nrec * 4);
+  P->off_poff = take(nrec * 4);
+  P->off_scan = take((size_t)std::max<int64_t>(P->scan_blocks, 1) * 8);
+  P->off_keys0 = take(cap * 8);
+  P->off_keys1 = take(cap * 8);
+  P->off_vals0 = take(cap * 4);
+  P->off_vals1 = take(cap * 4);
+  P->off_pair_rec = take(cap * 4);
+  P->off_sorted_rec = take(cap * 4);
+  P->off_hist = take((size_t)kRadix * hist_blocks * 4);
+  P->off_digit_tot = take(kRadix * 4);
+  P->off_ranges = take(T * 2 * 4);
+  P->off_tile_last = take(T * 4);
+  P->off_tile_loss = take(T * 2 * 4);
+  P->off_grad_pair = take(cap * kPairGrad * 4);
+  P->off_pose_part = take((size_t)n_views * std::max<int64_t>(P->proj_blocks, 1) * 6 * 8);
+  P->off_order = take(T * 4);
+  P->off_order_tmp = take(T * (8 + 8 + 4 + 4) + 256);
+  P->ws_size = o;
+  P->magic = kPlanMagic;
+  return GS_OK;
+}
+
+size_t gs_workspace_size(const gs_plan* plan) {
+  if (check_plan(plan) != GS_OK) return 0;
+  return plan_of(plan)->ws_size;
+}
+
+int64_t gs_plan_total_pixels(const gs_plan* plan) {
+  if (check_plan(plan) != GS_OK) return -1;
+  return plan_of(plan)->vt.total_pix;
+}
+
+int64_t gs_plan_pixel_offset(const gs_plan* plan, int32_t view) {
+  if (check_plan(plan) != GS_OK) return -1;
+  const Plan* P = plan_of(plan);
+  if (view < 0 || view >= P->n_views) return -1;
+  return P->vt.v[view].pix_off;
+}
+
+int64_t gs_plan_total_tiles(const gs_plan* plan) {
+  if (check_plan(plan) != GS_OK) return -1;
+  return plan_of(plan)->vt.total_tiles;
+}
+
+int64_t gs_plan_ws_offset(const gs_plan* plan, int32_t region) {
+  if (check_plan(plan) != GS_OK) return -1;
+  const Plan& P = *plan_of(plan);
+  const int passes = P.sort_passes;
+  switch (region) {
+    case GS_WS_RECORDS: return (int64_t)P.off_rec;
+    case GS_WS_RECTS: return (int64_t)P.off_rect;
+    case GS_WS_TILES_TOUCHED: return (int64_t)P.off_tt;
+    case GS_WS_PAIR_OFFSETS: return (int64_t)P.off_poff;
+    case GS_WS_SORTED_KEYS: return (int64_t)((passes & 1) ? P.off_keys1 : P.off_keys0);
+    case GS_WS_SORTED_VALS: return (int64_t)((passes & 1) ? P.off_vals1 : P.off_vals0);
+    case GS_WS_SORTED_RECS: return (int64_t)P.off_sorted_rec;
+    case GS_WS_RANGES: return (int64_t)P.off_ranges;
+    default: return -1;
+  }
+}
+
+int32_t* gs_flags_ptr(const gs_plan* plan, void* ws) {
+  if (check_plan(plan) != GS_OK || !ws) return nullptr;
+  return ws_at<int32_t>(ws, plan_of(plan)->off_flags);
+}
+
+gs_status gs_preprocess(const gs_plan* plan, const gs_gaussians* g, const float* cams_dev,
+                        void* ws, void* stream) {
+  gs_status st;
+  if ((st = check_plan(plan)) != GS_OK) return st;
+  const Plan& P = *plan_of(plan);
+  if ((st = check_ws(P, ws)) != GS_OK) return st;
+  if ((st = check_gaussians(P, g)) != GS_OK) return st;
+  if (!cams_dev) return fail(GS_ERR_INVALID_ARG, "cams_dev is null");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int32_t* fl = ws_at<int32_t>(ws, P.off_flags);
+  // flags 0..3 are per-iteration: clear them with a kernel (graph-safe)
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(fl), 0u, 4, s);
+  if (e == hipSuccess) e = launch_preprocess(P, *g, cams_dev, ws, s);
+  return hip_check(e, "gs_preprocess");
+}
+
+gs_status gs_bin_sort(const gs_plan* plan, void* ws, void* stream) {
+  gs_status st;
+  if ((st = check_plan(plan)) != GS_OK) return st;
+  const Plan& P = *plan_of(plan);
+  if ((st = check_ws(P, ws)) != GS_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_bin_sort(P, ws, s);
+  if (e == hipSuccess && (P.cfg.flags & GS_PERSISTENT)) e = launch_tile_order(P, ws, s);
+  return hip_check(e, "gs_bin_sort");
+}
+
+static int persistent_grid(const Plan& P, bool bwd) {
+  (void)bwd;
+  const int per_cu = (P.cfg.tile_w * P.cfg.tile_h == 256) ? 4 : 8;
+  const int64_t items = (P.vt.total_tiles + P.cfg.chunk - 1) / P.cfg.chunk;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)device_cus() * per_cu));
+}
+
+gs_status gs_render_fwd(const gs_plan* plan, void* ws, const float* cams_dev, float* color,
+                        float* depth, float* T_final, uint32_t* last, const float* target_rgb,
+                        const float* target_depth, float* loss_per_view, void* stream) {
+  gs_status st;
+  if ((st = check_plan(plan)) != GS_OK) return st;
+  const Plan& P = *plan_of(plan);
+  if ((st = check_ws(P, ws)) != GS_OK) return st;
+  if (!cams_dev) return fail(GS_ERR_INVALID_ARG, "cams_dev is null");
+  if (!color || !depth || !T_final || !last) return fail(GS_ERR_INVALID_ARG, "output image pointer is null");
+  if (target_rgb && !loss_per_view) return fail(GS_ERR_INVALID_ARG, "target_rgb given without loss_per_view");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool pers = (P.cfg.flags & GS_PERSISTENT) != 0;
+  int32_t* fl = ws_at<int32_t>(ws, P.off_flags);
+  hipError_t e = hipSuccess;
+  if (pers) e = launch_set_i32(fl + F_QUEUE_FWD, 0, s);
+  if (e == hipSuccess)
+    e = launch_render_fwd(P, ws, cams_dev, color, depth, T_final, last, target_rgb, target_depth,
+                          loss_per_view, pers ? ws_at<uint32_t>(ws, P.off_order) : nullptr,
+                          pers ? fl + F_QUEUE_FWD : nullptr,
+                          pers ? persistent_grid(P, false) : P.vt.total_tiles, s);
+  return hip_check(e, "gs_render_fwd");
+}
+
+}  // extern "C"
+
+extern "C" {
+
+gs_status gs_render_bwd_raster(const gs_plan* plan, void* ws, const float* cams_dev,
+                               const float* color, const float* depth, const float* T_final,
+                               const uint32_t* last, const float* dL_dcolor,
+                               const float* dL_ddepth, const float* target_rgb,
+                               const float* target_depth, void* stream) {
+  gs_status st;
+  if ((st = check_plan(plan)) != GS_OK) return st;
+  const Plan& P = *plan_of(plan);
+  if ((st = check_ws(P, ws)) != GS_OK) return st;
+  if (!cams_dev) return fail(GS_ERR_INVALID_ARG, "cams_dev is null");
+  if (!color || !depth || !T_final || !last) return fail(GS_ERR_INVALID_ARG, "forward buffers must be non-null");
+  const bool fused = (P.cfg.flags & GS_FUSED_L1) != 0;
+  if (fused && !target_rgb) return fail(GS_ERR_INVALID_ARG, "GS_FUSED_L1 needs target_rgb");
+  if (!fused && !dL_dcolor) return fail(GS_ERR_INVALID_ARG, "dL_dcolor is null (and GS_FUSED_L1 not set)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool pers = (P.cfg.flags & GS_PERSISTENT) != 0;
+  int32_t* fl = ws_at<int32_t>(ws, P.off_flags);
+  hipError_t e = hipSuccess;
+  if (pers) e = launch_set_i32(fl + F_QUEUE_BWD, 0, s);
+  if (e == hipSuccess)
+    e = launch_render_bwd(P, ws, cams_dev, color, depth, T_final, last, dL_dcolor, dL_ddepth,
+                          target_rgb, target_depth, fused ? 1 : 0, sorted_vals(P, ws),
+                          pers ? ws_at<uint32_t>(ws, P.off_order) : nullptr,
+                          pers ? fl + F_QUEUE_BWD : nullptr,
+                          pers ? persistent_grid(P, true) : P.vt.total_tiles, s);
+  return hip_check(e, "gs_render_bwd_raster");
+}
+
+gs_status gs_project_bwd(const gs_plan* plan, const gs_gaussians* g, const float* cams_dev,
+                         void* ws, const gs_gaussian_grads* out, float* dL_dpose, void* stream) {
+  gs_status st;
+  if ((st = check_plan(plan)) != GS_OK) return st;
+  const Plan& P = *plan_of(plan);
+  if ((st = check_ws(P, ws)) != GS_OK) return st;
+  if ((st = check_gaussians(P, g)) != GS_OK) return st;
+  if (!cams_dev) return fail(GS_ERR_INVALID_ARG, "cams_dev is null");
+  if (!out || (P.n > 0 && (!out->means || !out->log_scales || !out->quats || !out->opacity_logits || !out->sh)))
+    return fail(GS_ERR_INVALID_ARG, "gradient output pointers must be non-null");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return hip_check(launch_project_bwd(P, *g, cams_dev, ws, *out, dL_dpose,
+                                      (P.cfg.flags & GS_ACCUMULATE_GRADS) ? 1 : 0, s),
+                   "gs_project_bwd");
+}
+
+gs_status gs_render_bwd(const gs_plan* plan, const gs_gaussians* g, const float* cams_dev,
+                        void* ws, const float* color, const float* depth,
+                        const float* T_final, const uint32_t* last,
+                        const float* dL_dcolor, const float* dL_ddepth,
+                        const float* target_rgb, const float* target_depth,
+                        const gs_gaussian_grads* out, float* dL_dpose, void* stream) {
+  gs_status st;
+  if ((st = check_plan(plan)) != GS_OK) return st;
+  const Plan& P = *plan_of(plan);
+  if ((st = check_gaussians(P, g)) != GS_OK) return st;
+  if (!out || (P.n > 0 && (!out->means || !out->log_scales || !out->quats || !out->opacity_logits || !out->sh)))
+    return fail(GS_ERR_INVALID_ARG, "gradient output pointers must be non-null");
+  st = gs_render_bwd_raster(plan, ws, cams_dev, color, depth, T_final, last, dL_dcolor,
+                            dL_ddepth, target_rgb, target_depth, stream);
+  if (st != GS_OK) return st;
+  return gs_project_bwd(plan, g, cams_dev, ws, out, dL_dpose, stream);
+}
+
+gs_status gs_adam_step(const gs_param_group* groups, int32_t n_groups, int32_t step,
+                       double beta1, double beta2, double eps, double lambda_o,
+                       int64_t reg_count, int32_t* step_dev, void* stream) {
+  if (n_groups < 0 || (n_groups > 0 && !groups)) return fail(GS_ERR_INVALID_ARG, "bad group array");
+  if (!step_dev && step < 1) return fail(GS_ERR_INVALID_ARG, "step must be >= 1");
+  if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps >= 0.0))
+    return fail(GS_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+  for (int k = 0; k < n_groups; ++k) {
+    const gs_param_group& G = groups[k];
+    if (G.n < 0) return fail(GS_ERR_INVALID_ARG, "group %d: n < 0", k);
+    if (G.n > 0 && (!G.p || !G.g || !G.m || !G.v)) return fail(GS_ERR_INVALID_ARG, "group %d: null pointer", k);
+    if (!aligned(G.p, 16) || !aligned(G.g, 16) || !aligned(G.m, 16) || !aligned(G.v, 16))
+      return fail(GS_ERR_INVALID_ARG, "group %d: pointers must be 16-byte aligned", k);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return hip_check(launch_adam(groups, n_groups, step, beta1, beta2, eps, lambda_o, reg_count,
+                               step_dev, s),
+                   "gs_adam_step");
+}
+
+size_t gs_sort_tmp_bytes(int64_t n) {
+  if (n < 0) return 0;
+  const int64_t nb = std::max<int64_t>(1, (n + kSortTile - 1) / kSortTile);
+  size_t o = 0;
+  o = align_up(o + (size_t)n * 8 + 8, 256);
+  o = align_up(o + (size_t)n * 4 + 4, 256);
+  o = align_up(o + (size_t)kRadix * nb * 4, 256);
+  o = align_up(o + kRadix * 4, 256);
+  o = align_up(o + 16, 256);
+  return o;
+}
+
+gs_status gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits, void* tmp,
+                        void* stream) {
+  if (n < 0 || n > INT32_MAX) return fail(GS_ERR_INVALID_ARG, "n must be 0..2^31-1");
+  if (key_bits < 1 || key_bits > 64) return fail(GS_ERR_INVALID_ARG, "key_bits must be 1..64");
+  if (n == 0) return GS_OK;
+  if (!keys || !vals || !tmp) return fail(GS_ERR_INVALID_ARG, "null pointer");
+  if (!aligned(tmp, 256)) return fail(GS_ERR_INVALID_ARG, "tmp must be 256-byte aligned");
+  const int64_t nb = std::max<int64_t>(1, (n + kSortTile - 1) / kSortTile);
+  size_t o = 0;
+  char* base = static_cast<char*>(tmp);
+  uint64_t* k1 = reinterpret_cast<uint64_t*>(base + o);
+  o = align_up(o + (size_t)n * 8 + 8, 256);
+  uint32_t* v1 = reinterpret_cast<uint32_t*>(base + o);
+  o = align_up(o + (size_t)n * 4 + 4, 256);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(base + o);
+  o = align_up(o + (size_t)kRadix * nb * 4, 256);
+  uint32_t* dtot = reinterpret_cast<uint32_t*>(base + o);
+  o = align_up(o + kRadix * 4, 256);
+  int32_t* cnt = reinterpret_cast<int32_t*>(base + o);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_set_i32(cnt, (int32_t)n, s);
+  int which = 0;
+  if (e == hipSuccess)
+    e = launch_radix_sort(keys, k1, vals, v1, cnt, hist, dtot, nb, key_bits, false, &which, s);
+  if (e == hipSuccess && which == 1) {
+    e = hipMemcpyAsync(keys, k1, (size_t)n * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(vals, v1, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
+  }
+  return hip_check(e, "gs_sort_pairs");
+}
+
+gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
+  if (!it) return fail(GS_ERR_INVALID_ARG, "iteration is null");
+  gs_status st = gs_preprocess(it->plan, &it->gaussians, it->cams_dev, it->ws, stream);
+  if (st != GS_OK) return st;
+  st = gs_bin_sort(it->plan, it->ws, stream);
+  if (st != GS_OK) return st;
+  st = gs_render_fwd(it->plan, it->ws, it->cams_dev, it->color, it->depth, it->T_final, it->last,
+                     it->target_rgb, it->target_depth, it->loss_per_view, stream);
+  if (st != GS_OK) return st;
+  st = gs_render_bwd(it->plan, &it->gaussians, it->cams_dev, it->ws, it->color, it->depth,
+                     it->T_final, it->last, it->dL_dcolor, it->dL_ddepth, it->target_rgb,
+                     it->target_depth, &it->grads, it->dL_dpose, stream);
+  if (st != GS_OK) return st;
+  if (it->n_adam_groups > 0)
+    st = gs_adam_step(it->adam_groups, it->n_adam_groups, 1, it->beta1, it->beta2, it->eps,
+                      it->lambda_o, it->reg_count, it->step_dev, stream);
+  return st;
+}
+
+struct gs_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+gs_status gs_graph_create(const gs_iteration* it, void* stream, gs_graph** out) {
+  if (!it || !out) return fail(GS_ERR_INVALID_ARG, "null argument");
+  if (!stream) return fail(GS_ERR_INVALID_ARG, "graph capture needs a non-null stream");
+  if (it->n_adam_groups > 0 && !it->step_dev)
+    return fail(GS_ERR_INVALID_ARG, "a captured Adam step needs step_dev");
+  *out = nullptr;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_check(e, "hipStreamBeginCapture");
+  gs_status st = gs_iteration_enqueue(it, stream);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(s, &graph);
+  if (st != GS_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_check(e, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hip_check(e, "hipGraphInstantiate");
+  }
+  gs_graph* gr = new gs_graph{graph, exec};
+  *out = gr;
+  return GS_OK;
+}
+
+gs_status gs_graph_launch(gs_graph* graph, void* stream) {
+  if (!graph) return fail(GS_ERR_INVALID_ARG, "graph is null");
+  return hip_check(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
+}
+
+gs_status gs_graph_destroy(gs_graph* graph) {
+  if (!graph) return GS_OK;
+  hipError_t e1 = hipGraphExecDestroy(graph->exec);
+  hipError_t e2 = hipGraphDestroy(graph->graph);
+  delete graph;
+  if (e1 != hipSuccess) return hip_check(e1, "hipGraphExecDestroy");
+  return hip_check(e2, "hipGraphDestroy");
+}
+
+}  // extern "C"

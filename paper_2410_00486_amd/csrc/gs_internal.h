@@ -1,0 +1,149 @@
+// Internal definitions of the gfx950 rasterizer library: the plan stored in
+// gs_plan's opaque words, the 64-byte projected record, the per-view tables
+// passed to kernels by value, and wave64 helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/gs.h"
+
+namespace gs {
+
+constexpr int kWave = 64;
+constexpr int kMaxViews = GS_MAX_VIEWS;
+constexpr uint32_t kPlanMagic = 0x67735031u;  // "gsP1"
+
+// Flags in the workspace (int32).  See gs_flags_ptr.
+enum Flag : int {
+  F_OVERFLOW = 0,
+  F_NONFINITE = 1,
+  F_PAIRS = 2,
+  F_VISIBLE = 3,
+  F_QUEUE_FWD = 4,
+  F_QUEUE_BWD = 5,
+  F_PAIRS_WANTED = 6,
+  F_COUNT = 16
+};
+
+// Per-view geometry of the tile grid and of the concatenated image buffers.
+struct ViewInfo {
+  int32_t W, H;
+  int32_t tiles_x, tiles_y;
+  int32_t tile_off;  // first global tile id of this view
+  int32_t pix_off;   // first pixel of this view in the concatenated buffers
+};
+
+struct ViewTable {
+  int32_t n_views;
+  int32_t total_tiles;
+  int32_t tw, th;
+  int64_t total_pix;
+  ViewInfo v[kMaxViews];
+};
+
+// Projected (view, Gaussian) record, 64 bytes.  The 2D mean and the conic are
+// kept in FP64: the per-pixel quadratic form d^T Sigma'^-1 d is evaluated in
+// FP64 (full rate on CDNA), which removes the cancellation of an FP32
+// evaluation at large pixel coordinates and for elongated footprints.  The
+// conic is stored pre-scaled so that power = ca dx^2 + cb dx dy + cc dy^2,
+// i.e. ca = -a/2, cb = -b, cc = -c/2 for the conic [[a, b], [b, c]].
+struct __align__(16) Rec {
+  double mx, my;
+  double ca, cb;
+  double cc;
+  float o, z;        // opacity, camera-space depth
+  float r, g, b;     // colour after the clamp at 0
+  uint32_t pad;
+};
+static_assert(sizeof(Rec) == 64, "record must be 64 bytes");
+
+// Per-pair gradient partial written by the backward raster kernel:
+// rgb(3), depth, opacity, conic a b c, mean x y (+2 pad), 48 bytes.
+constexpr int kPairGrad = 12;
+
+struct Plan {
+  uint32_t magic;
+  int32_t deg, K, n_views;
+  int64_t n;        // Gaussians
+  int64_t n_rec;    // n_views * n
+  int64_t pair_cap;
+  gs_raster_cfg cfg;
+  int32_t tile_bits, key_bits, sort_passes, pad0;
+  int64_t scan_blocks;      // blocks of the record scan
+  int64_t sort_blocks_cap;  // radix-sort blocks at full capacity
+  int64_t proj_blocks;      // blocks of the projection backward
+  ViewTable vt;
+  // workspace layout (byte offsets from the 256-aligned base)
+  size_t off_flags, off_rec, off_rect, off_tt, off_poff, off_scan;
+  size_t off_keys0, off_keys1, off_vals0, off_vals1, off_pair_rec, off_sorted_rec;
+  size_t off_hist, off_digit_tot, off_ranges, off_tile_last, off_tile_loss;
+  size_t off_grad_pair, off_pose_part, off_order, off_order_tmp;
+  size_t ws_size;
+};
+static_assert(sizeof(Plan) <= sizeof(gs_plan), "plan does not fit gs_plan");
+
+inline const Plan* plan_of(const gs_plan* p) { return reinterpret_cast<const Plan*>(p->opaque); }
+inline Plan* plan_of(gs_plan* p) { return reinterpret_cast<Plan*>(p->opaque); }
+
+template <typename T>
+inline T* ws_at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// Radix sort geometry: 256 threads x 16 keys per block, 8-bit digits.
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+// Record scan geometry.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+constexpr int kProjThreads = 128;
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int l = lane_id();
+  return (l == 0) ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+// Wave64 sum with the result valid in every lane: butterfly over xor
+// distances 1..32.  Lanes that are inactive must hold 0.
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t x) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t y = __shfl_xor(x, o, kWave);
+    x = x > y ? x : y;
+  }
+  return x;
+}
+
+// Host-side launch helpers (defined in the .hip files).
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
+
+}  // namespace gs

@@ -1,0 +1,252 @@
+// a1: per-Gaussian projection for every view (CaRtGS Sec. III-B: primitives
+// p, q, s, sigma, SH; alpha comes from a projected 2D Gaussian times the
+// opacity).  One thread per Gaussian loops over the views, so the geometry
+// parameters are read from HBM once per iteration whatever the batch size;
+// SH coefficients are read only when the Gaussian is visible in a view.
+// All projection arithmetic is FP64 (the kernel is bound by HBM, and FP64
+// runs at the FP32 rate on CDNA vector units).
+#include "gs_internal.h"
+
+namespace gs {
+namespace {
+
+constexpr double kSH0 = 0.28209479177387814;   // 1/(2 sqrt(pi))
+constexpr double kSH1 = 0.4886025119029199;    // sqrt(3/(4 pi))
+constexpr double kSH2a = 1.0925484305920792;   // sqrt(15/pi)/2
+constexpr double kSH2b = 0.31539156525252005;  // sqrt(5/pi)/4
+constexpr double kSH2c = 0.5462742152960396;   // sqrt(15/pi)/4
+constexpr double kSH3a = 0.5900435899266435;   // sqrt(35/(2 pi))/4
+constexpr double kSH3b = 2.890611442640554;    // sqrt(105/pi)/2
+constexpr double kSH3c = 0.4570457994644658;   // sqrt(21/(2 pi))/4
+constexpr double kSH3d = 0.3731763325901154;   // sqrt(7/pi)/4
+constexpr double kSH3e = 1.445305721320277;    // sqrt(105/pi)/4
+
+// Real orthonormal SH with the Condon-Shortley phase at unit direction (x,y,z).
+template <int DEG>
+__device__ __forceinline__ void sh_basis(double x, double y, double z, double* Y) {
+  Y[0] = kSH0;
+  if (DEG >= 1) {
+    Y[1] = -kSH1 * y;
+    Y[2] = kSH1 * z;
+    Y[3] = -kSH1 * x;
+  }
+  if (DEG >= 2) {
+    const double xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = kSH2a * x * y;
+    Y[5] = -kSH2a * y * z;
+    Y[6] = kSH2b * (2.0 * zz - xx - yy);
+    Y[7] = -kSH2a * x * z;
+    Y[8] = kSH2c * (xx - yy);
+    if (DEG >= 3) {
+      Y[9] = -kSH3a * y * (3.0 * xx - yy);
+      Y[10] = kSH3b * x * y * z;
+      Y[11] = -kSH3c * y * (4.0 * zz - xx - yy);
+      Y[12] = kSH3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+      Y[13] = -kSH3c * x * (4.0 * zz - xx - yy);
+      Y[14] = kSH3e * z * (xx - yy);
+      Y[15] = -kSH3a * x * (xx - 3.0 * yy);
+    }
+  }
+}
+
+__device__ __forceinline__ bool finite_f(float v) { return __builtin_isfinite(v); }
+
+template <int DEG>
+__global__ void __launch_bounds__(256) k_preprocess(
+    const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, int64_t n, const float* __restrict__ cams, ViewTable vt,
+    uint32_t flags, Rec* __restrict__ rec, ushort4* __restrict__ rect,
+    uint32_t* __restrict__ tt, int32_t* __restrict__ fl) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+
+  const float pf[3] = {means[3 * i], means[3 * i + 1], means[3 * i + 2]};
+  const float lf[3] = {log_scales[3 * i], log_scales[3 * i + 1], log_scales[3 * i + 2]};
+  const float4 qf = *reinterpret_cast<const float4*>(quats + 4 * i);
+  const float bf = logits[i];
+  bool ok = finite_f(pf[0]) && finite_f(pf[1]) && finite_f(pf[2]) && finite_f(lf[0]) &&
+            finite_f(lf[1]) && finite_f(lf[2]) && finite_f(qf.x) && finite_f(qf.y) &&
+            finite_f(qf.z) && finite_f(qf.w) && finite_f(bf);
+  int nonfinite = ok ? 0 : 1;
+
+  // normalised quaternion, rotation, world covariance (symmetric, 6 entries)
+  double qw = qf.x, qx = qf.y, qy = qf.z, qz = qf.w;
+  const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  ok = ok && (qn > 0.0);
+  double S00 = 0, S01 = 0, S02 = 0, S11 = 0, S12 = 0, S22 = 0, o = 0;
+  const double p[3] = {pf[0], pf[1], pf[2]};
+  if (ok) {
+    qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+    const double R00 = 1 - 2 * (qy * qy + qz * qz), R01 = 2 * (qx * qy - qw * qz), R02 = 2 * (qx * qz + qw * qy);
+    const double R10 = 2 * (qx * qy + qw * qz), R11 = 1 - 2 * (qx * qx + qz * qz), R12 = 2 * (qy * qz - qw * qx);
+    const double R20 = 2 * (qx * qz - qw * qy), R21 = 2 * (qy * qz + qw * qx), R22 = 1 - 2 * (qx * qx + qy * qy);
+    const double s0 = exp(2.0 * (double)lf[0]), s1 = exp(2.0 * (double)lf[1]), s2 = exp(2.0 * (double)lf[2]);
+    S00 = R00 * R00 * s0 + R01 * R01 * s1 + R02 * R02 * s2;
+    S01 = R00 * R10 * s0 + R01 * R11 * s1 + R02 * R12 * s2;
+    S02 = R00 * R20 * s0 + R01 * R21 * s1 + R02 * R22 * s2;
+    S11 = R10 * R10 * s0 + R11 * R11 * s1 + R12 * R12 * s2;
+    S12 = R10 * R20 * s0 + R11 * R21 * s1 + R12 * R22 * s2;
+    S22 = R20 * R20 * s0 + R21 * R21 * s1 + R22 * R22 * s2;
+    o = 1.0 / (1.0 + exp(-(double)bf));
+  }
+  const bool sigma3 = (flags & GS_CUTOFF_3SIGMA) != 0;
+  bool sh_loaded = false;
+  double col[3] = {0, 0, 0};
+  (void)col;
+  float shv[K * 3];
+  int visible_count = 0;
+
+  for (int v = 0; v < vt.n_views; ++v) {
+    const ViewInfo vi = vt.v[v];
+    const int64_t ri = (int64_t)v * n + i;
+    uint32_t count = 0;
+    if (ok) {
+      const float* c = cams + (int64_t)v * GS_CAMERA_FLOATS;
+      const double fx = c[0], fy = c[1], cx = c[2], cy = c[3];
+      const double W0 = c[4], W1 = c[5], W2 = c[6], W3 = c[7], W4 = c[8], W5 = c[9];
+      const double W6 = c[10], W7 = c[11], W8 = c[12];
+      const double t0 = c[13], t1 = c[14], t2 = c[15], near_z = c[16];
+      const double tx = W0 * p[0] + W1 * p[1] + W2 * p[2] + t0;
+      const double ty = W3 * p[0] + W4 * p[1] + W5 * p[2] + t1;
+      const double tz = W6 * p[0] + W7 * p[1] + W8 * p[2] + t2;
+      bool vis = tz > near_z;
+      double mx = 0, my = 0, A = 0, B = 0, C = 0, det = 0;
+      if (vis) {
+        mx = fx * tx / tz + cx;
+        my = fy * ty / tz + cy;
+        const double limx = 1.3 * (double)vi.W / (2.0 * fx);
+        const double limy = 1.3 * (double)vi.H / (2.0 * fy);
+        const double u = fmin(limx, fmax(-limx, tx / tz));
+        const double w = fmin(limy, fmax(-limy, ty / tz));
+        // rows of T2 = J W
+        const double j00 = fx / tz, j02 = -fx * u / tz, j11 = fy / tz, j12 = -fy * w / tz;
+        const double a0 = j00 * W0 + j02 * W6, a1 = j00 * W1 + j02 * W7, a2 = j00 * W2 + j02 * W8;
+        const double b0 = j11 * W3 + j12 * W6, b1 = j11 * W4 + j12 * W7, b2 = j11 * W5 + j12 * W8;
+        // Sigma a, Sigma b
+        const double Sa0 = S00 * a0 + S01 * a1 + S02 * a2;
+        const double Sa1 = S01 * a0 + S11 * a1 + S12 * a2;
+        const double Sa2 = S02 * a0 + S12 * a1 + S22 * a2;
+        const double Sb0 = S00 * b0 + S01 * b1 + S02 * b2;
+        const double Sb1 = S01 * b0 + S11 * b1 + S12 * b2;
+        const double Sb2 = S02 * b0 + S12 * b1 + S22 * b2;
+        A = a0 * Sa0 + a1 * Sa1 + a2 * Sa2 + 0.3;
+        B = 0.5 * ((a0 * Sb0 + a1 * Sb1 + a2 * Sb2) + (b0 * Sa0 + b1 * Sa1 + b2 * Sa2));
+        C = b0 * Sb0 + b1 * Sb1 + b2 * Sb2 + 0.3;
+        det = A * C - B * B;
+        vis = (det > 0.0) && (o >= 1.0 / 255.0);
+      }
+      int x0 = 0, y0 = 0, x1 = 0, y1 = 0;
+      if (vis) {
+        double hx, hy;
+        if (sigma3) {
+          const double mid = 0.5 * (A + C);
+          const double lmax = mid + sqrt(fmax(0.1, mid * mid - det));
+          hx = hy = 3.0 * sqrt(lmax);
+        } else {
+          const double kappa = sqrt(2.0 * log(255.0 * o));
+          hx = kappa * sqrt(A);
+          hy = kappa * sqrt(C);
+        }
+        hx = hx * (1.0 + 1e-4) + 1e-3;
+        hy = hy * (1.0 + 1e-4) + 1e-3;
+        const double tw = vt.tw, th = vt.th;
+        x0 = (int)fmax(0.0, fmin((double)vi.tiles_x, floor((mx - hx) / tw)));
+        y0 = (int)fmax(0.0, fmin((double)vi.tiles_y, floor((my - hy) / th)));
+        x1 = (int)fmax(0.0, fmin((double)vi.tiles_x, floor((mx + hx) / tw) + 1.0));
+        y1 = (int)fmax(0.0, fmin((double)vi.tiles_y, floor((my + hy) / th) + 1.0));
+        vis = (x1 > x0) && (y1 > y0);
+      }
+      if (vis && !sh_loaded) {
+        // first view in which the Gaussian is visible: fetch and check SH
+        sh_loaded = true;
+        const float* shp = sh + (int64_t)i * (K * 3);
+        bool shok = true;
+#pragma unroll
+        for (int k = 0; k < K * 3; ++k) {
+          shv[k] = shp[k];
+          shok = shok && finite_f(shv[k]);
+        }
+        if (!shok) {
+          ok = false;
+          vis = false;
+          nonfinite = 1;
+        }
+      }
+      if (vis) {
+        // view direction from the camera centre c = -W^T t
+        const double cxw = -(W0 * t0 + W3 * t1 + W6 * t2);
+        const double cyw = -(W1 * t0 + W4 * t1 + W7 * t2);
+        const double czw = -(W2 * t0 + W5 * t1 + W8 * t2);
+        const double dx = p[0] - cxw, dy = p[1] - cyw, dz = p[2] - czw;
+        const double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+        double Y[16];
+        sh_basis<DEG>(dx * inv, dy * inv, dz * inv, Y);
+        float rgb[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < K; ++k) acc += (double)shv[3 * k + ch] * Y[k];
+          rgb[ch] = (float)fmax(0.0, acc + 0.5);
+        }
+        Rec r;
+        r.mx = mx;
+        r.my = my;
+        r.ca = -0.5 * (C / det);
+        r.cb = B / det;
+        r.cc = -0.5 * (A / det);
+        r.o = (float)o;
+        r.z = (float)tz;
+        r.r = rgb[0];
+        r.g = rgb[1];
+        r.b = rgb[2];
+        r.pad = 0;
+        rec[ri] = r;
+        rect[ri] = make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)x1,
+                                (unsigned short)y1);
+        count = (uint32_t)((x1 - x0) * (y1 - y0));
+        ++visible_count;
+      }
+    }
+    tt[ri] = count;
+  }
+  // per-wave aggregated statistics
+  const uint64_t nf = ballot64(nonfinite != 0);
+  int vis_sum = visible_count;
+#pragma unroll
+  for (int o2 = 1; o2 < kWave; o2 <<= 1) vis_sum += __shfl_xor(vis_sum, o2, kWave);
+  if (lane_id() == 0) {
+    if (nf) atomicAdd(&fl[F_NONFINITE], (int)__popcll(nf));
+    if (vis_sum) atomicAdd(&fl[F_VISIBLE], vis_sum);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_preprocess(const Plan& P, const gs_gaussians& g, const float* cams,
+                             void* ws, hipStream_t s) {
+  const int threads = 256;
+  const int64_t blocks = (P.n + threads - 1) / threads;
+  if (blocks == 0) return hipSuccess;
+  Rec* rec = ws_at<Rec>(ws, P.off_rec);
+  ushort4* rect = ws_at<ushort4>(ws, P.off_rect);
+  uint32_t* tt = ws_at<uint32_t>(ws, P.off_tt);
+  int32_t* fl = ws_at<int32_t>(ws, P.off_flags);
+  const uint32_t flags = P.cfg.flags;
+#define GS_PRE(D)                                                                          \
+  hipLaunchKernelGGL(k_preprocess<D>, dim3((unsigned)blocks), dim3(threads), 0, s, g.means, \
+                     g.log_scales, g.quats, g.opacity_logits, g.sh, P.n, cams, P.vt, flags,  \
+                     rec, rect, tt, fl)
+  switch (P.deg) {
+    case 0: GS_PRE(0); break;
+    case 1: GS_PRE(1); break;
+    case 2: GS_PRE(2); break;
+    default: GS_PRE(3); break;
+  }
+#undef GS_PRE
+  return hipGetLastError();
+}
+
+}  // namespace gs

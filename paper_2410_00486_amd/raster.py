@@ -1,0 +1,435 @@
+"""Python binding of the gfx950 rasterizer: plans, workspaces, the five
+entry points of a mapping iteration, HIP graphs, and a torch.autograd
+Function with the camera-tangent gradient.
+
+PyTorch provides device memory and the current stream; every step of the
+path runs in libgs.so.  Nothing here computes pixels or gradients.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_DEFAULT_TILE = (16, 16)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t: torch.Tensor, name: str, dtype=torch.float32):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+    return t
+
+
+class Plan:
+    """Host-side execution plan (sizes, tile grid, workspace layout)."""
+
+    def __init__(self, n: int, sh_degree: int, view_wh: Sequence[Tuple[int, int]],
+                 tile=_DEFAULT_TILE, lds_batch: int = 256, chunk: int = 2, flags: int = 0,
+                 lambda_depth: float = 0.1, pair_capacity: int = 1 << 20):
+        self.n, self.sh_degree = int(n), int(sh_degree)
+        self.view_wh = [(int(w), int(h)) for (w, h) in view_wh]
+        self.tile = (int(tile[0]), int(tile[1]))
+        self.lds_batch, self.chunk, self.flags = int(lds_batch), int(chunk), int(flags)
+        self.lambda_depth = float(lambda_depth)
+        self.pair_capacity = int(pair_capacity)
+        self.c = L.GsPlan()
+        self.cfg = L.GsRasterCfg(self.tile[0], self.tile[1], self.chunk, self.lds_batch,
+                                 self.flags, self.lambda_depth)
+        wh = (ctypes.c_int32 * (2 * len(self.view_wh)))(*[v for p in self.view_wh for v in p])
+        L.check(L.lib().gs_plan_init(ctypes.byref(self.c), self.n, self.sh_degree,
+                                     len(self.view_wh), wh, ctypes.byref(self.cfg),
+                                     self.pair_capacity))
+        self.ws_bytes = int(L.lib().gs_workspace_size(ctypes.byref(self.c)))
+        self.total_pixels = int(L.lib().gs_plan_total_pixels(ctypes.byref(self.c)))
+        self.total_tiles = int(L.lib().gs_plan_total_tiles(ctypes.byref(self.c)))
+        self.pixel_offsets = [int(L.lib().gs_plan_pixel_offset(ctypes.byref(self.c), v))
+                              for v in range(len(self.view_wh))]
+
+    @property
+    def n_views(self):
+        return len(self.view_wh)
+
+    def replace(self, **kw) -> "Plan":
+        args = dict(n=self.n, sh_degree=self.sh_degree, view_wh=self.view_wh, tile=self.tile,
+                    lds_batch=self.lds_batch, chunk=self.chunk, flags=self.flags,
+                    lambda_depth=self.lambda_depth, pair_capacity=self.pair_capacity)
+        args.update(kw)
+        return Plan(**args)
+
+    def ws_offset(self, region: int) -> int:
+        return int(L.lib().gs_plan_ws_offset(ctypes.byref(self.c), region))
+
+    def new_workspace(self, device="cuda") -> torch.Tensor:
+        ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        if ws.data_ptr() % 256:
+            raise RuntimeError("workspace allocation is not 256-byte aligned")
+        return ws
+
+    def flags_of(self, ws: torch.Tensor) -> np.ndarray:
+        """Device flags (synchronises the current stream)."""
+        ptr = L.lib().gs_flags_ptr(ctypes.byref(self.c), _ptr(ws))
+        off = ptr - ws.data_ptr()
+        return ws[off:off + 64].view(torch.int32).cpu().numpy()
+
+    def region(self, ws: torch.Tensor, region: int, dtype, count: int) -> torch.Tensor:
+        off = self.ws_offset(region)
+        nbytes = count * torch.empty((), dtype=dtype).element_size()
+        return ws[off:off + nbytes].view(dtype)
+
+    def split_views(self, img: torch.Tensor, channels: int = 1) -> List[torch.Tensor]:
+        out = []
+        for (w, h), off in zip(self.view_wh, self.pixel_offsets):
+            out.append(img[channels * off:channels * (off + w * h)].view(channels, h, w)
+                       if channels > 1 else img[off:off + w * h].view(h, w))
+        return out
+
+
+class Gaussians:
+    """Device parameters (contiguous float32 CUDA tensors)."""
+
+    FIELDS = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+    def __init__(self, means, log_scales, quats, opacity_logits, sh, sh_degree):
+        self.means = _need(means, "means")
+        self.log_scales = _need(log_scales, "log_scales")
+        self.quats = _need(quats, "quats")
+        self.opacity_logits = _need(opacity_logits, "opacity_logits")
+        self.sh = _need(sh, "sh")
+        self.sh_degree = int(sh_degree)
+        n = self.means.shape[0]
+        k = (self.sh_degree + 1) ** 2
+        if (self.means.shape != (n, 3) or self.log_scales.shape != (n, 3)
+                or self.quats.shape != (n, 4) or self.opacity_logits.numel() != n
+                or self.sh.numel() != n * k * 3):
+            raise ValueError("parameter shapes must be [n,3], [n,3], [n,4], [n], [n,(deg+1)^2,3]")
+
+    @property
+    def n(self):
+        return int(self.means.shape[0])
+
+    def c(self) -> L.GsGaussians:
+        return L.GsGaussians(self.means.data_ptr(), self.log_scales.data_ptr(),
+                             self.quats.data_ptr(), self.opacity_logits.data_ptr(),
+                             self.sh.data_ptr(), self.n, self.sh_degree)
+
+    def tensors(self):
+        return [getattr(self, f) for f in self.FIELDS]
+
+    @staticmethod
+    def from_scene(scene, device="cuda") -> "Gaussians":
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+        return Gaussians(t(scene.means), t(scene.log_scales), t(scene.quats),
+                         t(scene.opacity_logits),
+                         t(scene.sh.reshape(scene.n, (scene.sh_degree + 1) ** 2, 3)),
+                         scene.sh_degree)
+
+    def zeros_like(self) -> "Gaussians":
+        return Gaussians(*[torch.zeros_like(x) for x in self.tensors()], self.sh_degree)
+
+    def grads_c(self) -> L.GsGaussianGrads:
+        return L.GsGaussianGrads(*[x.data_ptr() for x in self.tensors()])
+
+
+def cameras_tensor(cams, device="cuda") -> torch.Tensor:
+    """[V, 20] float32 device camera records from objects with as_array()."""
+    arr = np.stack([np.asarray(c.as_array() if hasattr(c, "as_array") else c, np.float32)
+                    for c in cams])
+    if arr.shape[1] != L.GS_CAMERA_FLOATS:
+        raise ValueError("camera records must have 20 floats")
+    return torch.from_numpy(arr).to(device).contiguous()
+
+
+class Frame:
+    """Forward outputs of one iteration, concatenated over views."""
+
+    def __init__(self, plan: Plan, device="cuda"):
+        P = plan.total_pixels
+        self.color = torch.empty(3 * P, dtype=torch.float32, device=device)
+        self.depth = torch.empty(P, dtype=torch.float32, device=device)
+        self.T_final = torch.empty(P, dtype=torch.float32, device=device)
+        self.last = torch.empty(P, dtype=torch.int32, device=device)
+        self.loss = torch.zeros(plan.n_views, dtype=torch.float32, device=device)
+
+
+# ---------------------------------------------------------------- entry points
+
+def _check_cams(plan: Plan, cams: torch.Tensor):
+    _need(cams, "cams")
+    if cams.numel() != plan.n_views * L.GS_CAMERA_FLOATS:
+        raise ValueError(f"cams must hold {plan.n_views} x {L.GS_CAMERA_FLOATS} floats")
+
+
+def _check_ws(plan: Plan, ws: torch.Tensor):
+    if not (ws.is_cuda and ws.numel() >= plan.ws_bytes):
+        raise ValueError("workspace too small for the plan")
+
+
+def preprocess(plan: Plan, ws: torch.Tensor, g: Gaussians, cams: torch.Tensor, stream=None):
+    _check_cams(plan, cams)
+    _check_ws(plan, ws)
+    if g.n != plan.n or g.sh_degree != plan.sh_degree:
+        raise ValueError("Gaussians do not match the plan")
+    gc = g.c()
+    L.check(L.lib().gs_preprocess(ctypes.byref(plan.c), ctypes.byref(gc), _ptr(cams), _ptr(ws),
+                                  _stream(stream)))
+
+
+def bin_sort(plan: Plan, ws: torch.Tensor, stream=None):
+    _check_ws(plan, ws)
+    L.check(L.lib().gs_bin_sort(ctypes.byref(plan.c), _ptr(ws), _stream(stream)))
+
+
+def _check_img(t, n, name):
+    if t is not None and (not t.is_cuda or t.numel() != n or not t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous CUDA tensor of {n} elements")
+
+
+def render_fwd(plan: Plan, ws: torch.Tensor, cams: torch.Tensor, out: Frame,
+               target_rgb=None, target_depth=None, stream=None):
+    _check_cams(plan, cams)
+    _check_ws(plan, ws)
+    P = plan.total_pixels
+    for t, n, name in ((out.color, 3 * P, "color"), (out.depth, P, "depth"),
+                       (out.T_final, P, "T_final"), (out.last, P, "last"),
+                       (target_rgb, 3 * P, "target_rgb"), (target_depth, P, "target_depth")):
+        _check_img(t, n, name)
+    L.check(L.lib().gs_render_fwd(
+        ctypes.byref(plan.c), _ptr(ws), _ptr(cams), _ptr(out.color), _ptr(out.depth),
+        _ptr(out.T_final), _ptr(out.last), _ptr(target_rgb), _ptr(target_depth),
+        _ptr(out.loss) if target_rgb is not None else None, _stream(stream)))
+
+
+def render_bwd(plan: Plan, ws: torch.Tensor, g: Gaussians, cams: torch.Tensor, fr: Frame,
+               grads: Gaussians, dL_dcolor=None, dL_ddepth=None, target_rgb=None,
+               target_depth=None, dL_dpose=None, stream=None):
+    _check_cams(plan, cams)
+    _check_ws(plan, ws)
+    P = plan.total_pixels
+    for t, n, name in ((dL_dcolor, 3 * P, "dL_dcolor"), (dL_ddepth, P, "dL_ddepth"),
+                       (target_rgb, 3 * P, "target_rgb"), (target_depth, P, "target_depth")):
+        _check_img(t, n, name)
+    if dL_dpose is not None and dL_dpose.numel() != 6 * plan.n_views:
+        raise ValueError("dL_dpose must hold n_views x 6 floats")
+    for a, b in zip(g.tensors(), grads.tensors()):
+        if a.shape != b.shape:
+            raise ValueError("gradient buffers must match the parameter shapes")
+    gc = g.c()
+    out = grads.grads_c()
+    L.check(L.lib().gs_render_bwd(
+        ctypes.byref(plan.c), ctypes.byref(gc), _ptr(cams), _ptr(ws), _ptr(fr.color),
+        _ptr(fr.depth), _ptr(fr.T_final), _ptr(fr.last), _ptr(dL_dcolor), _ptr(dL_ddepth),
+        _ptr(target_rgb), _ptr(target_depth), ctypes.byref(out), _ptr(dL_dpose),
+        _stream(stream)))
+
+
+def render_bwd_raster(plan: Plan, ws: torch.Tensor, cams: torch.Tensor, fr: Frame,
+                      dL_dcolor=None, dL_ddepth=None, target_rgb=None, target_depth=None,
+                      stream=None):
+    """Stage a5 only: per-pair partial gradients into the workspace."""
+    _check_cams(plan, cams)
+    _check_ws(plan, ws)
+    L.check(L.lib().gs_render_bwd_raster(
+        ctypes.byref(plan.c), _ptr(ws), _ptr(cams), _ptr(fr.color), _ptr(fr.depth),
+        _ptr(fr.T_final), _ptr(fr.last), _ptr(dL_dcolor), _ptr(dL_ddepth), _ptr(target_rgb),
+        _ptr(target_depth), _stream(stream)))
+
+
+def project_bwd(plan: Plan, ws: torch.Tensor, g: Gaussians, cams: torch.Tensor,
+                grads: Gaussians, dL_dpose=None, stream=None):
+    """Stage a6 only: per-Gaussian reduction and chain rule."""
+    _check_cams(plan, cams)
+    _check_ws(plan, ws)
+    gc = g.c()
+    out = grads.grads_c()
+    L.check(L.lib().gs_project_bwd(ctypes.byref(plan.c), ctypes.byref(gc), _ptr(cams), _ptr(ws),
+                                   ctypes.byref(out), _ptr(dL_dpose), _stream(stream)))
+
+
+def adam_groups(params: Gaussians, grads: Gaussians, m: Gaussians, v: Gaussians, lrs: dict,
+                opacity_reg: bool = False):
+    arr = (L.GsParamGroup * 5)()
+    for k, f in enumerate(Gaussians.FIELDS):
+        p = getattr(params, f)
+        arr[k] = L.GsParamGroup(p.data_ptr(), getattr(grads, f).data_ptr(),
+                                getattr(m, f).data_ptr(), getattr(v, f).data_ptr(), p.numel(),
+                                float(lrs[f]), 1 if (opacity_reg and f == "opacity_logits") else 0)
+    return arr
+
+
+def adam_step(groups, step: int, beta1=0.9, beta2=0.999, eps=1e-15, lambda_o=0.0,
+              reg_count=0, step_dev: Optional[torch.Tensor] = None, stream=None):
+    L.check(L.lib().gs_adam_step(groups, len(groups), int(step), beta1, beta2, eps, lambda_o,
+                                 int(reg_count), _ptr(step_dev), _stream(stream)))
+
+
+def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, key_bits: int, stream=None):
+    """Stable in-place LSD radix sort of uint64 keys (int64 tensor) and uint32
+    values (int32 tensor) on the low key_bits bits."""
+    if keys.dtype != torch.int64 or vals.dtype != torch.int32 or keys.numel() != vals.numel():
+        raise ValueError("keys must be int64 and vals int32 of equal length")
+    n = keys.numel()
+    tmp = torch.empty(max(int(L.lib().gs_sort_tmp_bytes(n)), 256), dtype=torch.uint8,
+                      device=keys.device)
+    L.check(L.lib().gs_sort_pairs(_ptr(keys), _ptr(vals), n, int(key_bits), _ptr(tmp),
+                                  _stream(stream)))
+
+
+# ---------------------------------------------------------------- iterations
+
+class Iteration:
+    """All buffers of one mapping iteration over the plan's views, runnable
+    eagerly (enqueue) or as a captured HIP graph (capture + replay)."""
+
+    def __init__(self, plan: Plan, g: Gaussians, cams: torch.Tensor, target_rgb=None,
+                 target_depth=None, dL_dcolor=None, dL_ddepth=None, pose_grad=False,
+                 adam_lrs: Optional[dict] = None, lambda_o: float = 0.0, device="cuda"):
+        self.plan, self.g, self.cams = plan, g, cams
+        _check_cams(plan, cams)
+        if g.n != plan.n or g.sh_degree != plan.sh_degree:
+            raise ValueError("Gaussians do not match the plan")
+        P = plan.total_pixels
+        for t, n, name in ((dL_dcolor, 3 * P, "dL_dcolor"), (dL_ddepth, P, "dL_ddepth"),
+                           (target_rgb, 3 * P, "target_rgb"), (target_depth, P, "target_depth")):
+            _check_img(t, n, name)
+        self.ws = plan.new_workspace(device)
+        self.frame = Frame(plan, device)
+        self.grads = g.zeros_like()
+        self.target_rgb, self.target_depth = target_rgb, target_depth
+        self.dL_dcolor, self.dL_ddepth = dL_dcolor, dL_ddepth
+        self.dL_dpose = (torch.zeros(plan.n_views, 6, dtype=torch.float32, device=device)
+                         if pose_grad else None)
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=device)
+        self._graph = None
+        self._groups = None
+        if adam_lrs is not None:
+            self.m, self.v = g.zeros_like(), g.zeros_like()
+            self._groups = adam_groups(g, self.grads, self.m, self.v, adam_lrs, lambda_o != 0.0)
+        it = L.GsIteration()
+        it.plan = ctypes.pointer(plan.c)
+        it.ws = self.ws.data_ptr()
+        it.gaussians = g.c()
+        it.cams_dev = cams.data_ptr()
+        fr = self.frame
+        it.color, it.depth, it.T_final, it.last = (fr.color.data_ptr(), fr.depth.data_ptr(),
+                                                   fr.T_final.data_ptr(), fr.last.data_ptr())
+        it.target_rgb = None if target_rgb is None else target_rgb.data_ptr()
+        it.target_depth = None if target_depth is None else target_depth.data_ptr()
+        it.loss_per_view = fr.loss.data_ptr() if target_rgb is not None else None
+        it.dL_dcolor = None if dL_dcolor is None else dL_dcolor.data_ptr()
+        it.dL_ddepth = None if dL_ddepth is None else dL_ddepth.data_ptr()
+        it.grads = self.grads.grads_c()
+        it.dL_dpose = None if self.dL_dpose is None else self.dL_dpose.data_ptr()
+        if self._groups is not None:
+            it.adam_groups = ctypes.cast(self._groups, ctypes.POINTER(L.GsParamGroup))
+            it.n_adam_groups = len(self._groups)
+        it.step_dev = self.step_dev.data_ptr()
+        it.beta1, it.beta2, it.eps, it.lambda_o = 0.9, 0.999, 1e-15, float(lambda_o)
+        it.reg_count = g.n
+        self.c = it
+
+    def enqueue(self, stream=None):
+        L.check(L.lib().gs_iteration_enqueue(ctypes.byref(self.c), _stream(stream)))
+
+    def capture(self, stream: torch.cuda.Stream):
+        h = ctypes.c_void_p()
+        L.check(L.lib().gs_graph_create(ctypes.byref(self.c), _stream(stream), ctypes.byref(h)))
+        self._graph = h
+
+    def replay(self, stream=None):
+        L.check(L.lib().gs_graph_launch(self._graph, _stream(stream)))
+
+    def close(self):
+        if self._graph is not None:
+            L.check(L.lib().gs_graph_destroy(self._graph))
+            self._graph = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- autograd
+
+class _Rasterize(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, pose_tangent, cams, plan,
+                sh_degree):
+        g = Gaussians(means.detach().contiguous(), log_scales.detach().contiguous(),
+                      quats.detach().contiguous(), opacity_logits.detach().contiguous(),
+                      sh.detach().contiguous(), sh_degree)
+        ws = plan.new_workspace(means.device)
+        preprocess(plan, ws, g, cams)
+        bin_sort(plan, ws)
+        fr = Frame(plan, means.device)
+        render_fwd(plan, ws, cams, fr)
+        flags = plan.flags_of(ws)
+        if flags[L.F_OVERFLOW]:
+            raise RuntimeError(
+                f"pair capacity {plan.pair_capacity} exceeded ({flags[L.F_PAIRS_WANTED]} needed)")
+        ctx.plan, ctx.ws, ctx.frame, ctx.g, ctx.cams = plan, ws, fr, g, cams
+        ctx.mark_non_differentiable(fr.T_final)
+        return fr.color, fr.depth, fr.T_final
+
+    @staticmethod
+    def backward(ctx, g_color, g_depth, g_T):
+        plan, g = ctx.plan, ctx.g
+        grads = g.zeros_like()
+        dpose = torch.zeros(plan.n_views, 6, dtype=torch.float32, device=g.means.device)
+        gc = torch.zeros_like(ctx.frame.color) if g_color is None else g_color.contiguous()
+        gd = None if g_depth is None else g_depth.contiguous()
+        render_bwd(plan, ctx.ws, g, ctx.cams, ctx.frame, grads, dL_dcolor=gc, dL_ddepth=gd,
+                   dL_dpose=dpose)
+        return (grads.means, grads.log_scales, grads.quats, grads.opacity_logits,
+                grads.sh.view_as(g.sh), dpose, None, None, None)
+
+
+def rasterize(means, log_scales, quats, opacity_logits, sh, cams: torch.Tensor,
+              view_wh: Sequence[Tuple[int, int]], sh_degree: int, pose_tangent=None,
+              tile=_DEFAULT_TILE, lds_batch: int = 256, pair_capacity: Optional[int] = None):
+    """Differentiable render of one or more views.
+
+    Returns (color [3*P], depth [P], T_final [P]) concatenated over views
+    (split with Plan.split_views).  Gradients flow to the five parameter
+    tensors and to ``pose_tangent`` ([V, 6] = (rho, phi), evaluated at zero:
+    a left perturbation R <- Exp(phi) R, t <- Exp(phi) t + rho of each view's
+    world->camera pose).  With pair_capacity None, the capacity is found by a
+    first binning pass (one host synchronisation).
+    """
+    n = int(means.shape[0])
+    if pose_tangent is None:
+        pose_tangent = torch.zeros(len(view_wh), 6, dtype=torch.float32, device=means.device)
+    if pair_capacity is None:
+        pair_capacity = required_pairs(means, log_scales, quats, opacity_logits, sh, cams,
+                                       view_wh, sh_degree, tile)
+    plan = Plan(n, sh_degree, view_wh, tile=tile, lds_batch=lds_batch,
+                pair_capacity=max(1, int(pair_capacity)))
+    return _Rasterize.apply(means, log_scales, quats, opacity_logits, sh, pose_tangent, cams,
+                            plan, sh_degree)
+
+
+def required_pairs(means, log_scales, quats, opacity_logits, sh, cams, view_wh, sh_degree,
+                   tile=_DEFAULT_TILE) -> int:
+    """Exact (Gaussian, tile) pair count of the current parameters."""
+    plan = Plan(int(means.shape[0]), sh_degree, view_wh, tile=tile, pair_capacity=1)
+    ws = plan.new_workspace(means.device)
+    g = Gaussians(means.detach().contiguous(), log_scales.detach().contiguous(),
+                  quats.detach().contiguous(), opacity_logits.detach().contiguous(),
+                  sh.detach().contiguous(), sh_degree)
+    preprocess(plan, ws, g, cams)
+    bin_sort(plan, ws)
+    return int(plan.flags_of(ws)[L.F_PAIRS_WANTED])

@@ -1,0 +1,375 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Forward colour and depth must match within 1e-5 relative (+1e-7 absolute);
+gradients within 1e-3 relative (+1e-3 of the tensor's rms) per element and
+1e-4 in norm.  Pixels where the oracle sees a discrete decision (alpha clamp,
+1/255 skip, 1e-4 stop) within a relative 1e-5 of its threshold are excluded
+and counted; Gaussians whose tile box covers such a pixel's tile are
+excluded from the gradient check.  Integer and index work (tile boxes, pair
+counts, the sorted pair list, `last`) must be bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2410_00486_amd as gsr
+from paper_2410_00486_amd import _lib as L
+from synth import scenes
+
+from gpu_common import (DEV, assert_forward_close, assert_grads_close, flagged_gaussians,
+                        grads_np, run_gpu, t32, view_images, workload)
+
+pytestmark = pytest.mark.gpu
+
+
+# ------------------------------------------------------------------ preprocess
+
+@pytest.mark.parametrize("cfg", [1, 3])
+def test_preprocess_records_match_oracle(cfg):
+    w = workload(cfg)
+    cam = w.cameras[0]
+    print(f"preprocess parity config {cfg}", flush=True)
+    it = run_gpu(w.scene, [cam])
+    plan, ws = it.plan, it.ws
+    n = w.scene.n
+    ref = oracle.preprocess(w.scene, cam)
+    tt = plan.region(ws, L.GS_WS_TILES_TOUCHED, torch.int32, n).cpu().numpy()
+    rec = plan.region(ws, L.GS_WS_RECORDS, torch.uint8, n * 64).cpu().numpy().reshape(n, 64)
+    rects = plan.region(ws, L.GS_WS_RECTS, torch.int16, 4 * n).cpu().numpy().reshape(n, 4).view(np.uint16)
+    vis = ref["status"] == 1
+    edge = ref["near_edge"] != 0
+    np.testing.assert_array_equal((tt > 0), vis)
+    np.testing.assert_array_equal(tt[~edge], ref["tiles_touched"][~edge])
+    np.testing.assert_array_equal(rects[vis & ~edge].astype(np.int32), ref["rect"][vis & ~edge])
+    d = rec[vis, :40].copy().view(np.float64).reshape(-1, 5)
+    f = rec[vis, 40:60].copy().view(np.float32).reshape(-1, 5)
+    np.testing.assert_allclose(d[:, 0:2], ref["mean2d"][vis], rtol=1e-12, atol=1e-9)
+    con = ref["conic"][vis]
+    np.testing.assert_allclose(d[:, 2], -0.5 * con[:, 0], rtol=1e-9)
+    np.testing.assert_allclose(d[:, 3], -con[:, 1], rtol=1e-9, atol=1e-12 * np.abs(con).max())
+    np.testing.assert_allclose(d[:, 4], -0.5 * con[:, 2], rtol=1e-9)
+    np.testing.assert_array_equal(f[:, 1], ref["depth32"][vis])
+    np.testing.assert_allclose(f[:, 0], ref["opacity"][vis], rtol=1.2e-7)
+    np.testing.assert_allclose(f[:, 2:5], ref["rgb"][vis], rtol=1.2e-7, atol=1e-12)
+    flags = plan.flags_of(ws)
+    assert flags[L.F_VISIBLE] == vis.sum() and flags[L.F_NONFINITE] == 0
+
+
+# ------------------------------------------------------------------ sort
+
+@pytest.mark.parametrize("n,bits", [(1, 40), (17, 38), (4096, 44), (4097, 44), (100_003, 48),
+                                    (1_000_000, 52), (65_536, 64)])
+def test_sort_pairs_bit_exact(n, bits):
+    keys, vals = scenes.random_keys(n, n, max(1, bits - 32))
+    if bits == 64:
+        keys ^= np.uint64(1) << np.uint64(63)
+    kt = torch.from_numpy(keys.view(np.int64).copy()).to(DEV)
+    vt = torch.from_numpy(vals.view(np.int32).copy()).to(DEV)
+    gsr.sort_pairs(kt, vt, bits)
+    torch.cuda.synchronize()
+    order = np.argsort(keys, kind="stable")
+    np.testing.assert_array_equal(kt.cpu().numpy().view(np.uint64), keys[order])
+    np.testing.assert_array_equal(vt.cpu().numpy().view(np.uint32), vals[order])
+
+
+@pytest.mark.parametrize("cfg,tile", [(1, (16, 16)), (1, (8, 8)), (3, (16, 8)), (2, (16, 16))])
+def test_bin_sort_matches_oracle(cfg, tile):
+    w = workload(cfg)
+    cam = w.cameras[0]
+    print(f"bin_sort parity config {cfg} tile {tile}", flush=True)
+    it = run_gpu(w.scene, [cam], tile=tile)
+    plan, ws = it.plan, it.ws
+    pre = oracle.preprocess(w.scene, cam, tile)
+    assert not (pre["near_edge"] != 0).any(), "a rect edge is ambiguous; pick another seed"
+    keys, vals, ranges = oracle.sort_pairs(pre, cam, tile)
+    fl = plan.flags_of(ws)
+    P = int(fl[L.F_PAIRS])
+    assert fl[L.F_OVERFLOW] == 0 and P == keys.shape[0]
+    gk = plan.region(ws, L.GS_WS_SORTED_KEYS, torch.int64, P).cpu().numpy().view(np.uint64)
+    gr = plan.region(ws, L.GS_WS_SORTED_RECS, torch.int32, P).cpu().numpy()
+    grg = plan.region(ws, L.GS_WS_RANGES, torch.int32, ranges.size).cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(gk, keys)
+    np.testing.assert_array_equal(gr, vals.astype(np.int32))
+    np.testing.assert_array_equal(grg, ranges)
+
+
+# ------------------------------------------------------------------ forward
+
+@pytest.mark.parametrize("cfg", [1, 3, 2])
+def test_forward_matches_oracle(cfg):
+    w = workload(cfg)
+    cam = w.cameras[0]
+    print(f"forward parity config {cfg}", flush=True)
+    it = run_gpu(w.scene, [cam])
+    col, dep, T, last = view_images(it, 0)
+    ref = oracle.render(w.scene, cam)
+    nflag = assert_forward_close(col, dep, ref)
+    ok = ref["flag"] == 0
+    np.testing.assert_array_equal(last[ok], ref["last"][ok])
+    # transmittance: relative error bounded by the conditioning of 1 - alpha
+    np.testing.assert_allclose(T[ok], ref["T_final"][ok], rtol=2e-4, atol=1e-7)
+    print(f"config {cfg}: {nflag} flagged pixels of {ok.size}")
+
+
+def test_forward_tile_shapes_identical():
+    w = workload(3)
+    cam = w.cameras[0]
+    outs = [view_images(run_gpu(w.scene, [cam], tile=t), 0) for t in [(16, 16), (16, 8), (8, 8)]]
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o[0], outs[0][0])
+        np.testing.assert_array_equal(o[1], outs[0][1])
+        np.testing.assert_array_equal(o[2], outs[0][2])
+
+
+# ------------------------------------------------------------------ backward
+
+def _bwd_case(cfg, tile=(16, 16), lds=256, pose=False):
+    w = workload(cfg)
+    cam = w.cameras[0]
+    gc, gd = scenes.linear_loss_weights(100 + cfg, [cam])
+    print(f"backward parity config {cfg} tile {tile} lds {lds}", flush=True)
+    it = run_gpu(w.scene, [cam], tile=tile, lds=lds, dL_dcolor=gc, dL_ddepth=gd, pose=pose)
+    ref = oracle.render(w.scene, cam, tile)
+    exclude = flagged_gaussians(ref, tile, cam)
+    grads, pose_ref = oracle.backward(w.scene, cam, gc[0], gd[0], tile)
+    return it, grads, pose_ref, exclude
+
+
+@pytest.mark.parametrize("cfg,tile,lds", [(1, (16, 16), 256), (1, (8, 8), 64), (1, (16, 8), 128),
+                                          (3, (16, 16), 256), (2, (16, 16), 128)])
+def test_backward_matches_oracle(cfg, tile, lds):
+    it, grads, _, exclude = _bwd_case(cfg, tile, lds)
+    visible = (oracle.preprocess(workload(cfg).scene, workload(cfg).cameras[0], tile)["status"] == 1).sum()
+    assert exclude.sum() < 0.15 * visible
+    rep = assert_grads_close(grads_np(it), grads, exclude)
+    print(f"config {cfg}: excluded {int(exclude.sum())} Gaussians; (max err/tol, rel norm) {rep}")
+
+
+def test_pose_gradient_matches_oracle_and_fd():
+    it, grads, pose_ref, exclude = _bwd_case(3, pose=True)
+    assert_grads_close(grads_np(it), grads, exclude)
+    got = it.dL_dpose.cpu().numpy().astype(np.float64)[0]
+    ref = pose_ref[0]
+    assert np.linalg.norm(got - ref) <= 1e-3 * np.linalg.norm(ref), (got, ref)
+    # FP32 directional finite difference of the GPU path itself
+    w = workload(3)
+    cam = w.cameras[0]
+    gc, gd = scenes.linear_loss_weights(103, [cam])
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal(6)
+    u /= np.linalg.norm(u)
+    h = 1e-3
+
+    def loss(xi):
+        c2 = scenes.perturb_camera(cam, xi)
+        r = run_gpu(w.scene, [c2])
+        col, dep, _, _ = view_images(r, 0)
+        return float(np.sum(gc[0] * col) + np.sum(gd[0] * dep))
+
+    fd = (loss(h * u) - loss(-h * u)) / (2 * h)
+    an = float(got @ u)
+    assert abs(fd - an) <= 2e-2 * max(abs(an), 1e-3 * np.linalg.norm(got)), (fd, an)
+
+
+def test_fused_l1_matches_oracle():
+    w = workload(2)
+    cam = w.cameras[0]
+    tgt = oracle.render(w.target_scene, cam)
+    trgb, tdep = tgt["color"].astype(np.float32), tgt["depth"].astype(np.float32)
+    it = run_gpu(w.scene, [cam], flags=L.GS_FUSED_L1, target_rgb=[trgb], target_depth=[tdep],
+                 lambda_depth=0.1)
+    ref = oracle.render(w.scene, cam)
+    loss, gC, gD = oracle.l1_loss_and_grads(ref["color"], ref["depth"], trgb, tdep, 0.1)
+    got_loss = float(it.frame.loss.cpu()[0])
+    assert abs(got_loss - loss) <= 1e-5 * abs(loss)
+    # pixels whose residual sign is not decided at FP32 accuracy are ambiguous
+    amb = (np.abs(ref["color"] - trgb) <= 1e-5 * np.abs(trgb) + 1e-6).any(0)
+    amb |= np.abs(ref["depth"] - tdep) <= 1e-5 * np.abs(tdep) + 1e-6
+    ref2 = dict(ref)
+    ref2["flag"] = ((ref["flag"] != 0) | amb).astype(np.int32)
+    exclude = flagged_gaussians(ref2, (16, 16), cam)
+    grads, _ = oracle.backward(w.scene, cam, gC, gD)
+    assert exclude.mean() < 0.05
+    assert_grads_close(grads_np(it), grads, exclude)
+
+
+# ------------------------------------------------------------------ Adam
+
+def test_adam_matches_oracle():
+    rng = np.random.default_rng(3)
+    n = 100_003
+    shapes = {"means": (n, 3), "log_scales": (n, 3), "quats": (n, 4), "opacity_logits": (n,),
+              "sh": (n, 16, 3)}
+    lrs = {"means": 1.6e-4, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
+    P = {k: rng.standard_normal(s) for k, s in shapes.items()}
+    mk = lambda d: gsr.Gaussians(*[t32(d[k]) for k in gsr.Gaussians.FIELDS], 3)
+    params, m, v = mk(P), mk({k: np.zeros(s) for k, s in shapes.items()}), mk({k: np.zeros(s) for k, s in shapes.items()})
+    grads = mk({k: rng.standard_normal(s) for k, s in shapes.items()})
+    groups = gsr.adam_groups(params, grads, m, v, lrs, opacity_reg=True)
+    ref = {k: (P[k].astype(np.float32).astype(np.float64), np.zeros(shapes[k]), np.zeros(shapes[k])) for k in shapes}
+    for step in (1, 2, 3):
+        gnp = {k: rng.standard_normal(shapes[k]).astype(np.float32) for k in shapes}
+        for k in shapes:
+            getattr(grads, k).copy_(t32(gnp[k]))
+        gsr.adam_step(groups, step, lambda_o=0.001, reg_count=n)
+        for k in shapes:
+            p0, m0, v0 = ref[k]
+            g = gnp[k].astype(np.float64)
+            if k == "opacity_logits":
+                g = g + oracle.opacity_reg_grad(p0, 0.001, n)
+            ref[k] = oracle.adam_step(p0, g, m0, v0, step, lrs[k])
+    torch.cuda.synchronize()
+    for k in shapes:
+        p, mm, vv = ref[k]
+        np.testing.assert_allclose(getattr(params, k).cpu().numpy(), p, rtol=2e-6, atol=1e-7)
+        np.testing.assert_allclose(getattr(m, k).cpu().numpy(), mm, rtol=1e-5, atol=1e-7)
+        np.testing.assert_allclose(getattr(v, k).cpu().numpy(), vv, rtol=1e-5, atol=1e-8)
+
+
+# ------------------------------------------------------------------ batching, graphs, modes
+
+def _multi_view_workload():
+    w = workload(4, n=120_000, n_views=4)
+    return w.scene, w.cameras
+
+
+def test_batched_equals_per_view():
+    scene, cams = _multi_view_workload()
+    gcs, gds = scenes.linear_loss_weights(44, cams)
+    batched = run_gpu(scene, cams, dL_dcolor=gcs, dL_ddepth=gds, pose=True)
+    gb = grads_np(batched)
+    acc = None
+    for v, cam in enumerate(cams):
+        single = run_gpu(scene, [cam], dL_dcolor=[gcs[v]], dL_ddepth=[gds[v]], pose=True)
+        for k in range(4):
+            np.testing.assert_array_equal(view_images(single, 0)[k], view_images(batched, v)[k])
+        np.testing.assert_allclose(single.dL_dpose.cpu().numpy()[0], batched.dL_dpose.cpu().numpy()[v],
+                                   rtol=1e-4, atol=1e-6 * np.abs(batched.dL_dpose.cpu().numpy()).max())
+        gv = grads_np(single)
+        acc = gv if acc is None else {k: acc[k] + gv[k] for k in acc}
+    for k in gb:
+        scale = np.abs(gb[k]).max()
+        np.testing.assert_allclose(gb[k], acc[k], rtol=1e-4, atol=1e-6 * scale)
+
+
+def test_batched_matches_oracle_multi_view():
+    scene, cams = _multi_view_workload()
+    gcs, gds = scenes.linear_loss_weights(45, cams)
+    it = run_gpu(scene, cams, dL_dcolor=gcs, dL_ddepth=gds, pose=True, flags=L.GS_PERSISTENT)
+    exclude = np.zeros(scene.n, bool)
+    for v, cam in enumerate(cams):
+        ref = oracle.render(scene, cam)
+        col, dep, _, _ = view_images(it, v)
+        assert_forward_close(col, dep, ref)
+        exclude |= flagged_gaussians(ref, (16, 16), cam)
+    grads, poses = oracle.backward(scene, list(cams), gcs, gds)
+    assert_grads_close(grads_np(it), grads, exclude)
+    got = it.dL_dpose.cpu().numpy()
+    for v in range(len(cams)):
+        assert np.linalg.norm(got[v] - poses[v]) <= 1e-3 * np.linalg.norm(poses[v])
+
+
+def test_persistent_equals_plain():
+    scene, cams = _multi_view_workload()
+    gcs, gds = scenes.linear_loss_weights(46, cams)
+    a = run_gpu(scene, cams, dL_dcolor=gcs, dL_ddepth=gds)
+    b = run_gpu(scene, cams, dL_dcolor=gcs, dL_ddepth=gds, flags=L.GS_PERSISTENT, chunk=4)
+    for v in range(len(cams)):
+        for k in range(4):
+            np.testing.assert_array_equal(view_images(a, v)[k], view_images(b, v)[k])
+    ga, gb = grads_np(a), grads_np(b)
+    for k in ga:
+        np.testing.assert_array_equal(ga[k], gb[k])
+
+
+def test_graph_replay_equals_eager():
+    w = workload(1)
+    cam = w.cameras[0]
+    lrs = {"means": 1e-3, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
+    tgt = t32(w.target_rgb[0].reshape(-1))
+
+    def make():
+        g = gsr.Gaussians.from_scene(w.scene, DEV)
+        plan = gsr.Plan(w.scene.n, 0, [(cam.width, cam.height)], flags=L.GS_FUSED_L1,
+                        pair_capacity=1 << 16)
+        return gsr.Iteration(plan, g, gsr.cameras_tensor([cam], DEV), target_rgb=tgt,
+                             adam_lrs=lrs, lambda_o=0.001)
+
+    eager, graphed = make(), make()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        graphed.capture(s)
+    for step in range(3):
+        eager.enqueue()
+        torch.cuda.synchronize()
+        _ = (eager.frame.color * 2).sum().item()      # unrelated eager work in between
+        with torch.cuda.stream(s):
+            graphed.replay(s)
+        s.synchronize()
+        for f in gsr.Gaussians.FIELDS:
+            assert torch.equal(getattr(eager.g, f), getattr(graphed.g, f)), (step, f)
+        assert torch.equal(eager.frame.color, graphed.frame.color)
+        assert torch.equal(eager.frame.loss, graphed.frame.loss)
+    assert int(graphed.step_dev.item()) == 3
+    graphed.close()
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_empty_scene_and_empty_view():
+    w = workload(1)
+    cam = w.cameras[0]
+    empty = w.scene.subset(np.arange(0))
+    it = run_gpu(empty, [cam], capacity=1)
+    col, dep, T, last = view_images(it, 0)
+    assert (col == 0).all() and (dep == 0).all() and (T == 1).all() and (last == 0).all()
+    # camera looking away from every Gaussian
+    back = scenes.Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy,
+                         np.diag([1.0, -1.0, -1.0]).astype(np.float32), np.zeros(3, np.float32),
+                         bg=(0.1, 0.2, 0.3))
+    gc, gd = scenes.linear_loss_weights(1, [back])
+    it = run_gpu(w.scene, [back], capacity=1, dL_dcolor=gc, dL_ddepth=gd)
+    col, _, _, _ = view_images(it, 0)
+    np.testing.assert_allclose(col[0], 0.1, rtol=0, atol=1e-7)
+    g = grads_np(it)
+    assert all((g[f] == 0).all() for f in g)
+
+
+def test_nonfinite_gaussians_are_culled_and_counted():
+    w = workload(1)
+    cam = w.cameras[0]
+    sc = w.scene.copy()
+    sc.means[5, 0] = np.nan
+    sc.quats[6] = 0.0
+    sc.sh[7, 0, 1] = np.inf
+    sc.opacity_logits[8] = -np.inf
+    it = run_gpu(sc, [cam])
+    assert it.plan.flags_of(it.ws)[L.F_NONFINITE] >= 2
+    keep = np.setdiff1d(np.arange(sc.n), [5, 6, 7, 8])
+    ref = run_gpu(w.scene.subset(keep), [cam])
+    np.testing.assert_array_equal(view_images(it, 0)[0], view_images(ref, 0)[0])
+
+
+def test_pair_capacity_overflow_is_flagged():
+    w = workload(1)
+    cam = w.cameras[0]
+    it = run_gpu(w.scene, [cam], capacity=100)
+    fl = it.plan.flags_of(it.ws)
+    assert fl[L.F_OVERFLOW] == 1 and fl[L.F_PAIRS_WANTED] > 100 and fl[L.F_PAIRS] == 0
+
+
+def test_ragged_view_and_large_gaussian_and_sh_degrees():
+    for deg in (1, 2):
+        w = scenes.tiny_scene(31 + deg, n=40, width=33, height=17, degree=deg, f=25.0)
+        sc = w.scene.copy()
+        sc.log_scales[0] = np.log(0.6)      # one Gaussian larger than the image
+        gc, gd = scenes.linear_loss_weights(9, w.cameras)
+        cam = w.cameras[0]
+        for tile in [(16, 16), (8, 8)]:
+            it = run_gpu(sc, [cam], tile=tile, dL_dcolor=gc, dL_ddepth=gd)
+            ref = oracle.render(sc, cam, tile)
+            col, dep, _, _ = view_images(it, 0)
+            assert_forward_close(col, dep, ref)
+            grads, _ = oracle.backward(sc, cam, gc[0], gd[0], tile)
+            assert_grads_close(grads_np(it), grads, flagged_gaussians(ref, tile, cam))
