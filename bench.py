@@ -49,9 +49,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--tile", default="16x16")
-    ap.add_argument("--lds-batch", type=int, default=256)
-    ap.add_argument("--persistent", action="store_true")
+    ap.add_argument("--tile", default=None, help="fix the tile shape (e.g. 16x16); default: autotune")
+    ap.add_argument("--lds-batch", type=int, default=None)
+    ap.add_argument("--chunk", type=int, default=None)
+    ap.add_argument("--persistent", type=int, default=None, choices=[0, 1])
     ap.add_argument("--graph-only", action="store_true",
                     help="only the graph-timed headline loop (for profiler runs)")
     args = ap.parse_args()
@@ -66,31 +67,43 @@ def main():
     from paper_2410_00486_amd import _lib as L
     from synth import scenes
 
+    from paper_2410_00486_amd import tune
+
     dev = torch.device("cuda:0")
-    tile = tuple(int(x) for x in args.tile.split("x"))
     t_setup = time.time()
     w = scenes.config2()
     cam = w.cameras[0]
     view_wh = [(cam.width, cam.height)]
     cams = gsr.cameras_tensor([cam], dev)
     params = gsr.Gaussians.from_scene(w.scene, dev)
-    # target: render of the perturbed parameters (untimed setup)
-    tg = gsr.Gaussians.from_scene(w.target_scene, dev)
-    tcap = gsr.required_pairs(*tg.tensors(), cams, view_wh, 3, tile)
-    tplan = gsr.Plan(w.scene.n, 3, view_wh, tile=tile, pair_capacity=int(tcap * 1.1) + 1024)
-    tws = tplan.new_workspace(dev)
-    tfr = gsr.Frame(tplan, dev)
-    gsr.preprocess(tplan, tws, tg, cams)
-    gsr.bin_sort(tplan, tws)
-    gsr.render_fwd(tplan, tws, cams, tfr)
-    target_rgb, target_depth = tfr.color.clone(), tfr.depth.clone()
-    del tws, tfr, tg
+    target_rgb, target_depth = render_target(gsr, w.target_scene, cams, view_wh, dev)
+
+    # ---- autotune tile shape / LDS batch / chunk / persistence (untimed)
+    table = []
+    fixed = args.tile is not None
+    tiles = [tuple(int(x) for x in args.tile.split("x"))] if fixed else tune.TILES
+    ldss = [args.lds_batch] if args.lds_batch else tune.LDS_BATCHES
+    pers_opts = [bool(args.persistent)] if args.persistent is not None else [False, True]
+    best = None
+    for pers in pers_opts:
+        chunks = [args.chunk] if args.chunk else ([1, 2, 4] if pers else [1])
+        b, tb = tune.autotune(params, cams, view_wh, target_rgb, target_depth, adam_lrs=LRS,
+                              persistent=pers, tiles=tiles, lds_batches=ldss, chunks=chunks,
+                              reps=10)
+        for r in tb:
+            r["persistent"] = pers
+        table += tb
+        b = dict(b, persistent=pers)
+        if best is None or b["ms"] < best["ms"]:
+            best = b
+    log(f"autotune best {best}")
+    tile = tuple(int(x) for x in best["tile"].split("x"))
 
     cap0 = gsr.required_pairs(*params.tensors(), cams, view_wh, 3, tile)
     cap = int(cap0 * 1.5) + 4096
-    flags = L.GS_FUSED_L1 | (L.GS_PERSISTENT if args.persistent else 0)
-    plan = gsr.Plan(w.scene.n, 3, view_wh, tile=tile, lds_batch=args.lds_batch, flags=flags,
-                    pair_capacity=cap, lambda_depth=0.1)
+    flags = L.GS_FUSED_L1 | (L.GS_PERSISTENT if best["persistent"] else 0)
+    plan = gsr.Plan(w.scene.n, 3, view_wh, tile=tile, lds_batch=best["lds_batch"],
+                    chunk=best["chunk"], flags=flags, pair_capacity=cap, lambda_depth=0.1)
     it = gsr.Iteration(plan, params, cams, target_rgb=target_rgb, target_depth=target_depth,
                        adam_lrs=LRS, lambda_o=0.0)
     stream = torch.cuda.Stream()
@@ -210,8 +223,9 @@ def main():
         "data": "synthetic (seeded indoor room, shaped like the paper's RGB-D sequences)",
         "config": {"workload": "config2: 1 view 1200x680 fx=fy=600, 300k Gaussians SH3, "
                                "L1 RGB + 0.1 L1 depth, Adam, HIP graph per iteration",
-                   "tile": f"{tile[0]}x{tile[1]}", "lds_batch": args.lds_batch,
-                   "persistent": bool(args.persistent)},
+                   "tile": best["tile"], "lds_batch": best["lds_batch"], "chunk": best["chunk"],
+                   "persistent": bool(best["persistent"])},
+        "autotune": sorted(table, key=lambda r: r["ms"])[:6],
         "plain_eager_iters_per_s": round(1e3 / ms_eager, 2),
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "counts": {"gaussians": N, "visible": V, "pairs": P, "pixels": npx,
@@ -226,19 +240,35 @@ def main():
     torch.cuda.synchronize()
 
     if not args.no_batched:
-        result["batched"] = bench_batched(args, dev, tile)
+        result["batched"] = bench_batched(args, dev)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(result))
 
 
-def bench_batched(args, dev, tile):
-    """8 keyframes of mixed resolution over a shared 500k pool: one persistent
-    graph for all views vs the plain form (standard grids, view by view)."""
+def render_target(gsr, scene, cams, view_wh, dev, tile=(16, 16)):
+    """Render the target images from (perturbed) parameters -- untimed setup."""
+    tg = gsr.Gaussians.from_scene(scene, dev)
+    tcap = gsr.required_pairs(*tg.tensors(), cams, view_wh, scene.sh_degree, tile)
+    tplan = gsr.Plan(scene.n, scene.sh_degree, view_wh, tile=tile,
+                     pair_capacity=int(tcap * 1.1) + 1024)
+    tws = tplan.new_workspace(dev)
+    tfr = gsr.Frame(tplan, dev)
+    gsr.preprocess(tplan, tws, tg, cams)
+    gsr.bin_sort(tplan, tws)
+    gsr.render_fwd(tplan, tws, cams, tfr)
+    return tfr.color.clone(), tfr.depth.clone()
+
+
+def bench_batched(args, dev):
+    """8 keyframes of mixed resolution over a shared 500k pool: one autotuned
+    persistent graph for all views vs the plain form (standard grids, view
+    by view, 16x16 tiles)."""
     import torch
 
     import paper_2410_00486_amd as gsr
     from paper_2410_00486_amd import _lib as L
+    from paper_2410_00486_amd import tune
     from synth import scenes
 
     w = scenes.config4()
@@ -246,20 +276,15 @@ def bench_batched(args, dev, tile):
     view_wh = [(c.width, c.height) for c in cams_l]
     cams = gsr.cameras_tensor(cams_l, dev)
     params = gsr.Gaussians.from_scene(w.scene, dev)
-    tg = gsr.Gaussians.from_scene(w.target_scene, dev)
-    tcap = gsr.required_pairs(*tg.tensors(), cams, view_wh, 3, tile)
-    tplan = gsr.Plan(w.scene.n, 3, view_wh, tile=tile, pair_capacity=int(tcap * 1.1) + 1024)
-    tws = tplan.new_workspace(dev)
-    tfr = gsr.Frame(tplan, dev)
-    gsr.preprocess(tplan, tws, tg, cams)
-    gsr.bin_sort(tplan, tws)
-    gsr.render_fwd(tplan, tws, cams, tfr)
-    target_rgb, target_depth = tfr.color.clone(), tfr.depth.clone()
-    del tws, tfr, tg
+    target_rgb, target_depth = render_target(gsr, w.target_scene, cams, view_wh, dev)
+    best, table = tune.autotune(params, cams, view_wh, target_rgb, target_depth, adam_lrs=LRS,
+                                persistent=True, chunks=[1, 2, 4, 8], reps=8)
+    log(f"batched autotune best {best}")
+    tile = tuple(int(x) for x in best["tile"].split("x"))
     cap0 = gsr.required_pairs(*params.tensors(), cams, view_wh, 3, tile)
     flags = L.GS_FUSED_L1 | L.GS_PERSISTENT
-    plan = gsr.Plan(w.scene.n, 3, view_wh, tile=tile, flags=flags, chunk=2,
-                    pair_capacity=int(cap0 * 1.5) + 4096)
+    plan = gsr.Plan(w.scene.n, 3, view_wh, tile=tile, flags=flags, chunk=best["chunk"],
+                    lds_batch=best["lds_batch"], pair_capacity=int(cap0 * 1.5) + 4096)
     it = gsr.Iteration(plan, params, cams, target_rgb=target_rgb, target_depth=target_depth,
                        adam_lrs=LRS)
     stream = torch.cuda.Stream()
@@ -276,18 +301,18 @@ def bench_batched(args, dev, tile):
     ms_b = (time.perf_counter() - t0) * 1e3 / args.steps
     fl = plan.flags_of(it.ws)
     assert fl[L.F_OVERFLOW] == 0
-    vis = int(fl[L.F_VISIBLE])
+    vis_total = int(fl[L.F_VISIBLE])
     groups = it._groups
     grads = it.grads
     it.close()
     del it
     # plain per-view form: one plan and workspace per view, gradients summed
     # into one buffer, then one Adam step
-    per = []
+    per, vis = [], []
     for v, c in enumerate(cams_l):
         cv = cams[v:v + 1].contiguous()
-        capv = gsr.required_pairs(*params.tensors(), cv, [view_wh[v]], 3, tile)
-        pv = gsr.Plan(w.scene.n, 3, [view_wh[v]], tile=tile,
+        capv = gsr.required_pairs(*params.tensors(), cv, [view_wh[v]], 3, (16, 16))
+        pv = gsr.Plan(w.scene.n, 3, [view_wh[v]], tile=(16, 16),
                       flags=L.GS_FUSED_L1 | L.GS_ACCUMULATE_GRADS,
                       pair_capacity=int(capv * 1.5) + 4096)
         off, npx = plan.pixel_offsets[v], view_wh[v][0] * view_wh[v][1]
@@ -310,6 +335,8 @@ def bench_batched(args, dev, tile):
         for _ in range(args.warmup):
             plain_iter()
     torch.cuda.synchronize()
+    for pv, ws, *_ in per:
+        vis.append(int(pv.flags_of(ws)[L.F_VISIBLE]))
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
         for _ in range(args.steps):
@@ -317,10 +344,12 @@ def bench_batched(args, dev, tile):
     torch.cuda.synchronize()
     ms_p = (time.perf_counter() - t0) * 1e3 / args.steps
     out = {"workload": "config4: 8 keyframes mixed {640x480,1200x680,320x240}, 500k SH3",
-           "views": view_wh, "visible_records": vis,
+           "views": view_wh, "visible_per_view": vis, "visible_total": vis_total,
            "batched_persistent_graph_iters_per_s": round(1e3 / ms_b, 2),
            "plain_per_view_iters_per_s": round(1e3 / ms_p, 2),
-           "speedup": round(ms_p / ms_b, 3)}
+           "speedup": round(ms_p / ms_b, 3),
+           "autotune_best": best,
+           "autotune_top": sorted(table, key=lambda r: r["ms"])[:5]}
     log(f"batched: {out}")
     return out
 

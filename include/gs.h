@@ -202,6 +202,19 @@ gs_status gs_render_bwd(const gs_plan* plan, const gs_gaussians* g, const float*
                         const float* target_rgb, const float* target_depth,
                         const gs_gaussian_grads* out, float* dL_dpose, void* stream);
 
+/* a4, full Eq. (9).  Rendered loss and its image gradients, per view:
+ *   L_v = (1 - lambda_ssim) mean|C - C*| + lambda_ssim (1 - SSIM(C, C*))
+ *         + lambda_depth mean|D - D*|          (lambda_depth from the plan)
+ * with the SSIM of 3DGS (per channel, 11x11 Gaussian window of sigma 1.5,
+ * zero padding, C1 = 0.01^2, C2 = 0.03^2, mean over pixels and channels;
+ * sign(0) = 0 in the L1 terms).  Writes dL_dcolor [3][H][W] and dL_ddepth
+ * [H][W] (device, concatenated over views) -- the explicit upstream
+ * gradients of gs_render_bwd -- and loss_per_view (nullable).
+ * target_depth is nullable (no depth term). */
+gs_status gs_render_loss(const gs_plan* plan, void* ws, const float* color, const float* depth,
+                         const float* target_rgb, const float* target_depth, double lambda_ssim,
+                         float* dL_dcolor, float* dL_ddepth, float* loss_per_view, void* stream);
+
 /* The two stages of gs_render_bwd as separate calls (same arguments, same
  * checks).  a5: gs_render_bwd_raster runs the per-pixel backward and leaves
  * one 10-float partial gradient (rgb, depth, opacity, conic a b c, mean x y)
@@ -277,6 +290,13 @@ typedef struct gs_iteration {
   int32_t* step_dev;
   double beta1, beta2, eps, lambda_o;
   int64_t reg_count;
+  /* lambda_ssim > 0: the loss of gs_render_loss (Eq. (9) with SSIM) is
+   * evaluated after the forward into loss_per_view, its image gradients into
+   * loss_grad_color / loss_grad_depth, which then drive the backward (the
+   * plan must not set GS_FUSED_L1).  0: fused L1 or explicit dL_dcolor. */
+  double lambda_ssim;
+  float* loss_grad_color;
+  float* loss_grad_depth;
 } gs_iteration;
 
 typedef struct gs_graph gs_graph;
@@ -285,6 +305,41 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream);
 gs_status gs_graph_create(const gs_iteration* it, void* stream, gs_graph** out);
 gs_status gs_graph_launch(gs_graph* graph, void* stream);
 gs_status gs_graph_destroy(gs_graph* graph);
+
+/* Autotuner timing core: replays `graph` warmup + reps times on `stream`
+ * and returns the mean milliseconds per replay of the timed reps, measured
+ * with HIP events on that stream.  Synchronises the stream (a measurement
+ * call, not for the iteration loop). */
+gs_status gs_graph_time(gs_graph* graph, void* stream, int32_t warmup, int32_t reps,
+                        float* ms_per_replay);
+
+/* Adaptive keyframe selection, host only (Sec. III-C-2, Eqs. (5)-(8)).
+ * A keyframe enters the pool with r0 remaining optimisations and loss +inf;
+ * gs_sched_select draws `batch` distinct keyframes uniformly among those
+ * with r > 0 -- uniforms[b] in [0, 1) picks position floor(u m) of the m
+ * eligible keyframes in index order -- and decrements their counts; when no
+ * keyframe is eligible it first resets every count by Eq. (8): 2 for the
+ * d_k = max(1, floor(k / d)) largest reported losses (ties to the lower
+ * index), 1 otherwise.  gs_sched_report stores a keyframe's latest loss.
+ * All storage is the caller's (r: int32[capacity], l: double[capacity]).
+ * batch = 1 is the paper's one-keyframe-per-iteration rule. */
+typedef struct gs_scheduler {
+  int32_t* r;
+  double* l;
+  int32_t capacity;
+  int32_t count;
+  int32_t r0;
+  int32_t d;
+  int64_t refills;
+} gs_scheduler;
+
+gs_status gs_sched_init(gs_scheduler* s, int32_t* r, double* l, int32_t capacity, int32_t r0,
+                        int32_t d);
+gs_status gs_sched_add_keyframe(gs_scheduler* s, int32_t* out_id);
+gs_status gs_sched_select(gs_scheduler* s, int32_t batch, const double* uniforms,
+                          int32_t* out_ids, int32_t* out_count);
+gs_status gs_sched_report(gs_scheduler* s, int32_t id, double loss);
+const char* gs_sched_last_error(void);
 
 const char* gs_status_string(gs_status s);
 const char* gs_last_error(void);

@@ -77,7 +77,14 @@ class GsIteration(ctypes.Structure):
                 ("dL_dcolor", vp), ("dL_ddepth", vp), ("grads", GsGaussianGrads),
                 ("dL_dpose", vp), ("adam_groups", ctypes.POINTER(GsParamGroup)),
                 ("n_adam_groups", i32), ("step_dev", vp), ("beta1", f64), ("beta2", f64),
-                ("eps", f64), ("lambda_o", f64), ("reg_count", i64)]
+                ("eps", f64), ("lambda_o", f64), ("reg_count", i64), ("lambda_ssim", f64),
+                ("loss_grad_color", vp), ("loss_grad_depth", vp)]
+
+
+class GsScheduler(ctypes.Structure):
+    _fields_ = [("r", ctypes.POINTER(i32)), ("l", ctypes.POINTER(ctypes.c_double)),
+                ("capacity", i32), ("count", i32), ("r0", i32), ("d", i32),
+                ("refills", i64)]
 
 
 # name -> (restype, argtypes)
@@ -95,6 +102,7 @@ SIGNATURES = {
     "gs_render_fwd": (i32, [ctypes.POINTER(GsPlan), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
     "gs_render_bwd": (i32, [ctypes.POINTER(GsPlan), ctypes.POINTER(GsGaussians), vp, vp, vp, vp,
                             vp, vp, vp, vp, vp, vp, ctypes.POINTER(GsGaussianGrads), vp, vp]),
+    "gs_render_loss": (i32, [ctypes.POINTER(GsPlan), vp, vp, vp, vp, vp, f64, vp, vp, vp, vp]),
     "gs_render_bwd_raster": (i32, [ctypes.POINTER(GsPlan), vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                    vp, vp]),
     "gs_project_bwd": (i32, [ctypes.POINTER(GsPlan), ctypes.POINTER(GsGaussians), vp, vp,
@@ -107,6 +115,14 @@ SIGNATURES = {
     "gs_graph_create": (i32, [ctypes.POINTER(GsIteration), vp, ctypes.POINTER(vp)]),
     "gs_graph_launch": (i32, [vp, vp]),
     "gs_graph_destroy": (i32, [vp]),
+    "gs_graph_time": (i32, [vp, vp, i32, i32, ctypes.POINTER(f32)]),
+    "gs_sched_init": (i32, [ctypes.POINTER(GsScheduler), ctypes.POINTER(i32),
+                            ctypes.POINTER(ctypes.c_double), i32, i32, i32]),
+    "gs_sched_add_keyframe": (i32, [ctypes.POINTER(GsScheduler), ctypes.POINTER(i32)]),
+    "gs_sched_select": (i32, [ctypes.POINTER(GsScheduler), i32, ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+    "gs_sched_report": (i32, [ctypes.POINTER(GsScheduler), i32, ctypes.c_double]),
+    "gs_sched_last_error": (ctypes.c_char_p, []),
     "gs_status_string": (ctypes.c_char_p, [i32]),
     "gs_last_error": (ctypes.c_char_p, []),
     "gs_version": (i32, []),

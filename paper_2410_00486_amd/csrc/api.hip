@@ -31,7 +31,6 @@ hipError_t launch_render_bwd(const Plan& P, void* ws, const float* cams, const f
                              const float* target_rgb, const float* target_depth, int fused,
                              const uint32_t* sorted_vals, const uint32_t* order, int32_t* queue,
                              int grid, hipStream_t s);
-size_t render_bwd_lds_bytes(const Plan& P);
 hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float* cams, void* ws,
                               const gs_gaussian_grads& out, float* dL_dpose, int accumulate,
                               hipStream_t s);
@@ -39,6 +38,12 @@ hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, dou
                        double beta2, double eps, double lambda_o, int64_t reg_count,
                        int32_t* step_dev, hipStream_t s);
 hipError_t launch_tile_order(const Plan& P, void* ws, hipStream_t s);
+int render_blocks_per_cu(const Plan& P, bool bwd);
+int64_t ssim_tiles(const Plan& P);
+hipError_t launch_render_loss(const Plan& P, void* ws, const float* color, const float* depth,
+                              const float* target_rgb, const float* target_depth,
+                              double lambda_ssim, float* dL_dcolor, float* dL_ddepth,
+                              float* loss_per_view, hipStream_t s);
 }  // namespace gs
 
 using namespace gs;
@@ -208,6 +213,8 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_pose_part = take((size_t)n_views * std::max<int64_t>(P->proj_blocks, 1) * 6 * 8);
   P->off_order = take(T * 4);
   P->off_order_tmp = take(T * (8 + 8 + 4 + 4) + 256);
+  P->off_ssim_maps = take((size_t)pix * 9 * 4);
+  P->off_ssim_part = take((size_t)ssim_tiles(*P) * 12 * 4);
   P->ws_size = o;
   P->magic = kPlanMagic;
   return GS_OK;
@@ -285,8 +292,7 @@ gs_status gs_bin_sort(const gs_plan* plan, void* ws, void* stream) {
 }
 
 static int persistent_grid(const Plan& P, bool bwd) {
-  (void)bwd;
-  const int per_cu = (P.cfg.tile_w * P.cfg.tile_h == 256) ? 4 : 8;
+  const int per_cu = render_blocks_per_cu(P, bwd);
   const int64_t items = (P.vt.total_tiles + P.cfg.chunk - 1) / P.cfg.chunk;
   return (int)std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)device_cus() * per_cu));
 }
@@ -380,6 +386,22 @@ gs_status gs_render_bwd(const gs_plan* plan, const gs_gaussians* g, const float*
   return gs_project_bwd(plan, g, cams_dev, ws, out, dL_dpose, stream);
 }
 
+gs_status gs_render_loss(const gs_plan* plan, void* ws, const float* color, const float* depth,
+                         const float* target_rgb, const float* target_depth, double lambda_ssim,
+                         float* dL_dcolor, float* dL_ddepth, float* loss_per_view, void* stream) {
+  gs_status st;
+  if ((st = check_plan(plan)) != GS_OK) return st;
+  const Plan& P = *plan_of(plan);
+  if ((st = check_ws(P, ws)) != GS_OK) return st;
+  if (!color || !depth || !target_rgb || !dL_dcolor || !dL_ddepth)
+    return fail(GS_ERR_INVALID_ARG, "color, depth, target_rgb, dL_dcolor and dL_ddepth must be non-null");
+  if (!(lambda_ssim >= 0.0 && lambda_ssim <= 1.0)) return fail(GS_ERR_INVALID_ARG, "lambda_ssim must be in [0, 1]");
+  return hip_check(launch_render_loss(P, ws, color, depth, target_rgb, target_depth, lambda_ssim,
+                                      dL_dcolor, dL_ddepth, loss_per_view,
+                                      static_cast<hipStream_t>(stream)),
+                   "gs_render_loss");
+}
+
 gs_status gs_adam_step(const gs_param_group* groups, int32_t n_groups, int32_t step,
                        double beta1, double beta2, double eps, double lambda_o,
                        int64_t reg_count, int32_t* step_dev, void* stream) {
@@ -445,16 +467,35 @@ gs_status gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_b
 
 gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
   if (!it) return fail(GS_ERR_INVALID_ARG, "iteration is null");
+  const bool ssim = it->lambda_ssim > 0.0;
+  if (ssim) {
+    if (!it->plan || check_plan(it->plan) != GS_OK) return fail(GS_ERR_INVALID_ARG, "bad plan");
+    if (plan_of(it->plan)->cfg.flags & GS_FUSED_L1)
+      return fail(GS_ERR_INVALID_ARG, "lambda_ssim > 0 takes explicit loss gradients: clear GS_FUSED_L1");
+    if (!it->target_rgb || !it->loss_grad_color || !it->loss_grad_depth)
+      return fail(GS_ERR_INVALID_ARG, "lambda_ssim > 0 needs target_rgb and loss gradient buffers");
+  }
   gs_status st = gs_preprocess(it->plan, &it->gaussians, it->cams_dev, it->ws, stream);
   if (st != GS_OK) return st;
   st = gs_bin_sort(it->plan, it->ws, stream);
   if (st != GS_OK) return st;
   st = gs_render_fwd(it->plan, it->ws, it->cams_dev, it->color, it->depth, it->T_final, it->last,
-                     it->target_rgb, it->target_depth, it->loss_per_view, stream);
+                     ssim ? nullptr : it->target_rgb, ssim ? nullptr : it->target_depth,
+                     ssim ? nullptr : it->loss_per_view, stream);
   if (st != GS_OK) return st;
+  const float* gC = it->dL_dcolor;
+  const float* gD = it->dL_ddepth;
+  if (ssim) {
+    st = gs_render_loss(it->plan, it->ws, it->color, it->depth, it->target_rgb, it->target_depth,
+                        it->lambda_ssim, it->loss_grad_color, it->loss_grad_depth,
+                        it->loss_per_view, stream);
+    if (st != GS_OK) return st;
+    gC = it->loss_grad_color;
+    gD = it->loss_grad_depth;
+  }
   st = gs_render_bwd(it->plan, &it->gaussians, it->cams_dev, it->ws, it->color, it->depth,
-                     it->T_final, it->last, it->dL_dcolor, it->dL_ddepth, it->target_rgb,
-                     it->target_depth, &it->grads, it->dL_dpose, stream);
+                     it->T_final, it->last, gC, gD, it->target_rgb, it->target_depth, &it->grads,
+                     it->dL_dpose, stream);
   if (st != GS_OK) return st;
   if (it->n_adam_groups > 0)
     st = gs_adam_step(it->adam_groups, it->n_adam_groups, 1, it->beta1, it->beta2, it->eps,
@@ -498,6 +539,28 @@ gs_status gs_graph_create(const gs_iteration* it, void* stream, gs_graph** out) 
 gs_status gs_graph_launch(gs_graph* graph, void* stream) {
   if (!graph) return fail(GS_ERR_INVALID_ARG, "graph is null");
   return hip_check(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
+}
+
+gs_status gs_graph_time(gs_graph* graph, void* stream, int32_t warmup, int32_t reps,
+                        float* ms_per_replay) {
+  if (!graph || !ms_per_replay || warmup < 0 || reps < 1)
+    return fail(GS_ERR_INVALID_ARG, "bad gs_graph_time arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (int i = 0; e == hipSuccess && i < warmup; ++i) e = hipGraphLaunch(graph->exec, s);
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  for (int i = 0; e == hipSuccess && i < reps; ++i) e = hipGraphLaunch(graph->exec, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_check(e, "gs_graph_time");
+  *ms_per_replay = ms / (float)reps;
+  return GS_OK;
 }
 
 gs_status gs_graph_destroy(gs_graph* graph) {

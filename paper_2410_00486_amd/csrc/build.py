@@ -7,7 +7,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
-SOURCES = ["api.hip", "preprocess.hip", "binsort.hip", "render.hip", "project_bwd.hip", "adam.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "binsort.hip", "render.hip", "project_bwd.hip", "adam.hip",
+           "loss.hip"]
 LIB = os.path.join(PKG, "libgs.so")
 BUILD = os.path.join(HERE, "_build")
 
@@ -19,9 +20,17 @@ FLAGS = [
 ]
 
 
+HOST_SOURCES = ["sched.cpp"]
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include")]
+
+
 def _compile(src, verbose):
-    obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(HERE, src), "-o", obj]
+    if src.endswith(".cpp"):
+        obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
+        cmd = ["g++"] + HOST_FLAGS + ["-c", os.path.join(HERE, src), "-o", obj]
+    else:
+        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+        cmd = [HIPCC] + FLAGS + ["-c", os.path.join(HERE, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -34,7 +43,7 @@ def _compile(src, verbose):
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        results = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        results = list(ex.map(lambda s: _compile(s, verbose), SOURCES + HOST_SOURCES))
     for _, w in results:
         if w and verbose:
             print(w)

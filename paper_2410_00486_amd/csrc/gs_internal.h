@@ -81,6 +81,7 @@ struct Plan {
   size_t off_keys0, off_keys1, off_vals0, off_vals1, off_pair_rec, off_sorted_rec;
   size_t off_hist, off_digit_tot, off_ranges, off_tile_last, off_tile_loss;
   size_t off_grad_pair, off_pose_part, off_order, off_order_tmp;
+  size_t off_ssim_maps, off_ssim_part;
   size_t ws_size;
 };
 static_assert(sizeof(Plan) <= sizeof(gs_plan), "plan does not fit gs_plan");

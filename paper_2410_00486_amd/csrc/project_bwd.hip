@@ -22,43 +22,62 @@ constexpr double kSH3c = 0.4570457994644658;
 constexpr double kSH3d = 0.3731763325901154;
 constexpr double kSH3e = 1.445305721320277;
 
-// SH basis values and gradients w.r.t. (x, y, z) as polynomials.
+// Real SH basis (orthonormal, Condon-Shortley phase) at unit direction (x,y,z).
 template <int DEG>
-__device__ __forceinline__ void sh_basis_grad(double x, double y, double z, double* Y,
-                                              double (*dY)[3]) {
+__device__ __forceinline__ void sh_basis(double x, double y, double z, double* Y) {
   Y[0] = kSH0;
-  dY[0][0] = dY[0][1] = dY[0][2] = 0.0;
-  if (DEG >= 1) {
-    Y[1] = -kSH1 * y; dY[1][0] = 0; dY[1][1] = -kSH1; dY[1][2] = 0;
-    Y[2] = kSH1 * z;  dY[2][0] = 0; dY[2][1] = 0;     dY[2][2] = kSH1;
-    Y[3] = -kSH1 * x; dY[3][0] = -kSH1; dY[3][1] = 0; dY[3][2] = 0;
-  }
+  if (DEG >= 1) { Y[1] = -kSH1 * y; Y[2] = kSH1 * z; Y[3] = -kSH1 * x; }
   if (DEG >= 2) {
     const double xx = x * x, yy = y * y, zz = z * z;
-    Y[4] = kSH2a * x * y;  dY[4][0] = kSH2a * y; dY[4][1] = kSH2a * x; dY[4][2] = 0;
-    Y[5] = -kSH2a * y * z; dY[5][0] = 0; dY[5][1] = -kSH2a * z; dY[5][2] = -kSH2a * y;
+    Y[4] = kSH2a * x * y;
+    Y[5] = -kSH2a * y * z;
     Y[6] = kSH2b * (2 * zz - xx - yy);
-    dY[6][0] = -2 * kSH2b * x; dY[6][1] = -2 * kSH2b * y; dY[6][2] = 4 * kSH2b * z;
-    Y[7] = -kSH2a * x * z; dY[7][0] = -kSH2a * z; dY[7][1] = 0; dY[7][2] = -kSH2a * x;
-    Y[8] = kSH2c * (xx - yy); dY[8][0] = 2 * kSH2c * x; dY[8][1] = -2 * kSH2c * y; dY[8][2] = 0;
+    Y[7] = -kSH2a * x * z;
+    Y[8] = kSH2c * (xx - yy);
     if (DEG >= 3) {
       Y[9] = -kSH3a * y * (3 * xx - yy);
-      dY[9][0] = -6 * kSH3a * x * y; dY[9][1] = -kSH3a * (3 * xx - 3 * yy); dY[9][2] = 0;
       Y[10] = kSH3b * x * y * z;
-      dY[10][0] = kSH3b * y * z; dY[10][1] = kSH3b * x * z; dY[10][2] = kSH3b * x * y;
       Y[11] = -kSH3c * y * (4 * zz - xx - yy);
-      dY[11][0] = 2 * kSH3c * x * y; dY[11][1] = -kSH3c * (4 * zz - xx - 3 * yy);
-      dY[11][2] = -8 * kSH3c * y * z;
       Y[12] = kSH3d * z * (2 * zz - 3 * xx - 3 * yy);
-      dY[12][0] = -6 * kSH3d * x * z; dY[12][1] = -6 * kSH3d * y * z;
-      dY[12][2] = kSH3d * (6 * zz - 3 * xx - 3 * yy);
       Y[13] = -kSH3c * x * (4 * zz - xx - yy);
-      dY[13][0] = -kSH3c * (4 * zz - 3 * xx - yy); dY[13][1] = 2 * kSH3c * x * y;
-      dY[13][2] = -8 * kSH3c * x * z;
       Y[14] = kSH3e * z * (xx - yy);
-      dY[14][0] = 2 * kSH3e * x * z; dY[14][1] = -2 * kSH3e * y * z; dY[14][2] = kSH3e * (xx - yy);
       Y[15] = -kSH3a * x * (xx - 3 * yy);
-      dY[15][0] = -kSH3a * (3 * xx - 3 * yy); dY[15][1] = 6 * kSH3a * x * y; dY[15][2] = 0;
+    }
+  }
+}
+
+// g += sum_k w_k grad Y_k(x, y, z), the basis treated as polynomials in x,y,z.
+template <int DEG>
+__device__ __forceinline__ void sh_dir_grad(double x, double y, double z, const double* w,
+                                            double& gx, double& gy, double& gz) {
+  if (DEG >= 1) {
+    gy += -kSH1 * w[1];
+    gz += kSH1 * w[2];
+    gx += -kSH1 * w[3];
+  }
+  if (DEG >= 2) {
+    gx += kSH2a * y * w[4];           gy += kSH2a * x * w[4];
+    gy += -kSH2a * z * w[5];          gz += -kSH2a * y * w[5];
+    gx += -2 * kSH2b * x * w[6];      gy += -2 * kSH2b * y * w[6];  gz += 4 * kSH2b * z * w[6];
+    gx += -kSH2a * z * w[7];          gz += -kSH2a * x * w[7];
+    gx += 2 * kSH2c * x * w[8];       gy += -2 * kSH2c * y * w[8];
+    if (DEG >= 3) {
+      const double xx = x * x, yy = y * y, zz = z * z;
+      gx += -6 * kSH3a * x * y * w[9];
+      gy += -kSH3a * (3 * xx - 3 * yy) * w[9];
+      gx += kSH3b * y * z * w[10];    gy += kSH3b * x * z * w[10];  gz += kSH3b * x * y * w[10];
+      gx += 2 * kSH3c * x * y * w[11];
+      gy += -kSH3c * (4 * zz - xx - 3 * yy) * w[11];
+      gz += -8 * kSH3c * y * z * w[11];
+      gx += -6 * kSH3d * x * z * w[12];
+      gy += -6 * kSH3d * y * z * w[12];
+      gz += kSH3d * (6 * zz - 3 * xx - 3 * yy) * w[12];
+      gx += -kSH3c * (4 * zz - 3 * xx - yy) * w[13];
+      gy += 2 * kSH3c * x * y * w[13];
+      gz += -8 * kSH3c * x * z * w[13];
+      gx += 2 * kSH3e * x * z * w[14]; gy += -2 * kSH3e * y * z * w[14]; gz += kSH3e * (xx - yy) * w[14];
+      gx += -kSH3a * (3 * xx - 3 * yy) * w[15];
+      gy += 6 * kSH3a * x * y * w[15];
     }
   }
 }
@@ -186,8 +205,8 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
       const double dv0 = p[0] - cxw, dv1 = p[1] - cyw, dv2 = p[2] - czw;
       const double dist = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
       const double d0 = dv0 / dist, d1 = dv1 / dist, d2 = dv2 / dist;
-      double Y[16], dY[16][3];
-      sh_basis_grad<DEG>(d0, d1, d2, Y, dY);
+      double Y[16];
+      sh_basis<DEG>(d0, d1, d2, Y);
       const float* shp = sh + i * (K * 3);
       float* gsh = g_sh + i * (K * 3);
       double raw[3] = {0.5, 0.5, 0.5};
@@ -195,18 +214,21 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
         for (int ch = 0; ch < 3; ++ch) raw[ch] += (double)shp[3 * k + ch] * Y[k];
       double gcr[3];
       for (int ch = 0; ch < 3; ++ch) gcr[ch] = raw[ch] < 0.0 ? 0.0 : g_rgb[ch];
-      double gd[3] = {0, 0, 0};
+      // per-basis weights w_k = sum_ch gcr_ch SH_k,ch and the SH gradients
+      double wk[16];
       const bool first = !sh_written && !accumulate;
+#pragma unroll
       for (int k = 0; k < K; ++k) {
+        wk[k] = 0.0;
+#pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-          const double coef = shp[3 * k + ch];
-          gd[0] += gcr[ch] * coef * dY[k][0];
-          gd[1] += gcr[ch] * coef * dY[k][1];
-          gd[2] += gcr[ch] * coef * dY[k][2];
+          wk[k] += gcr[ch] * (double)shp[3 * k + ch];
           const float add = (float)(Y[k] * gcr[ch]);
           gsh[3 * k + ch] = first ? add : gsh[3 * k + ch] + add;
         }
       }
+      double gd[3] = {0, 0, 0};
+      sh_dir_grad<DEG>(d0, d1, d2, wk, gd[0], gd[1], gd[2]);
       sh_written = true;
       const double dd = gd[0] * d0 + gd[1] * d1 + gd[2] * d2;
       const double gv[3] = {(gd[0] - dd * d0) / dist, (gd[1] - dd * d1) / dist, (gd[2] - dd * d2) / dist};

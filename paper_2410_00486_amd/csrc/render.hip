@@ -1,19 +1,23 @@
 // a3-a5: per-tile compositing (Eq. (1)) and its pixel-wise backward
-// (Eqs. (2)-(4)), one workgroup per tile, one lane per pixel.
+// (Eqs. (2)-(4)).  One wave64 per tile: a lane owns PPL = tile pixels / 64
+// pixels (2x2 quads on 16x16 tiles, horizontal pairs on 16x8, one pixel on
+// 8x8), so the per-Gaussian work that does not depend on the pixel -- the
+// LDS read of the record, the wavefront reduction of the backward -- is
+// shared by up to 256 pixels.  Single-wave workgroups need no workgroup
+// barriers beyond LDS reuse, and many of them fit a CU.
 //
 // Forward: records of the tile's depth-sorted list are staged in LDS in
-// batches; every lane walks the batch front to back.  A wavefront leaves the
-// batch loop as soon as the ballot of its unfinished lanes is empty, and the
-// workgroup stops staging batches once no lane of any wavefront is left.
+// batches; every lane walks the batch front to back for each of its pixels.
+// The wavefront leaves as soon as the ballot of lanes with an unfinished
+// pixel is empty.
 //
-// Backward: back to front from each tile's last used position.  Each lane
-// recomputes alpha with the same code as the forward (so every skip decision
-// is the forward's), undoes the transmittance by division starting from
-// T_final, and keeps the running sums of what lies behind.  The ten per-pair
-// partial gradients are summed across the wavefront (skipped when no lane
-// contributes), the wavefront sums are combined in LDS in a fixed order, and
-// each (tile, Gaussian) pair writes its own slot: no atomics, and the result
-// is deterministic.
+// Backward: back to front from the tile's last used position.  Each lane
+// recomputes alpha with the forward's code (so every skip decision is the
+// forward's), undoes the transmittance by division from T_final and keeps
+// the sums of what lies behind.  The ten per-pair partial gradients of a
+// Gaussian are summed over the lane's pixels, then over the wavefront with
+// DPP (skipped when no lane contributes), and written to the pair's own
+// slot: no atomics, deterministic.
 #include "gs_internal.h"
 
 namespace gs {
@@ -39,20 +43,53 @@ __device__ __forceinline__ bool eval_alpha(const Rec& r, double sx, double sy, d
   return a >= kAlphaMin;
 }
 
+// DPP move with zero fill where the lane has no source or its row is masked.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, true));
+}
+
+// Sum over the wavefront, result in lane 63: xor 1 and xor 2 within quads,
+// half-row and row mirrors (sums of 8 and 16), then row broadcasts of lanes
+// 15 and 31 into the upper rows.  Every lane must be active.
+__device__ __forceinline__ float wave_sum_to_last(float x) {
+  x += dpp<0xB1>(x);        // quad_perm [1,0,3,2]
+  x += dpp<0x4E>(x);        // quad_perm [2,3,0,1]
+  x += dpp<0x141>(x);       // row_half_mirror
+  x += dpp<0x140>(x);       // row_mirror
+  x += dpp<0x142, 0xA>(x);  // row_bcast:15 -> rows 1 and 3
+  x += dpp<0x143, 0xC>(x);  // row_bcast:31 -> rows 2 and 3
+  return x;
+}
+
+template <int TW, int TH>
+struct Tile {
+  static constexpr int NPX = TW * TH;
+  static constexpr int PPL = NPX / kWave;  // pixels per lane: 1, 2 or 4
+  static __device__ __forceinline__ int x(int l, int k) {
+    return PPL == 1 ? (l & 7) : 2 * (l & 7) + (k & 1);
+  }
+  static __device__ __forceinline__ int y(int l, int k) {
+    return PPL == 4 ? 2 * (l >> 3) + (k >> 1) : (l >> 3);
+  }
+};
+
 __device__ __forceinline__ int find_view(const ViewTable& vt, int gtile) {
   int v = 0;
   while (v + 1 < vt.n_views && gtile >= vt.v[v + 1].tile_off) ++v;
   return v;
 }
 
-__device__ __forceinline__ void stage_records(Rec* srec, const Rec* __restrict__ rec,
-                                              const uint32_t* __restrict__ sorted_rec,
-                                              uint32_t first, int count, int nthreads) {
-  for (int k = threadIdx.x; k < count; k += nthreads) {
+__device__ __forceinline__ void stage(Rec* srec, uint32_t* sval, const Rec* __restrict__ rec,
+                                      const uint32_t* __restrict__ sorted_rec,
+                                      const uint32_t* __restrict__ sorted_vals, uint32_t first,
+                                      int count, int lane) {
+  for (int k = lane; k < count; k += kWave) {
     const float4* src = reinterpret_cast<const float4*>(rec + sorted_rec[first + k]);
     float4* dst = reinterpret_cast<float4*>(srec + k);
     const float4 a0 = src[0], a1 = src[1], a2 = src[2], a3 = src[3];
     dst[0] = a0; dst[1] = a1; dst[2] = a2; dst[3] = a3;
+    if (sval) sval[k] = sorted_vals[first + k];
   }
 }
 
@@ -68,104 +105,110 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ rec,
                                          uint32_t* __restrict__ tile_last,
                                          const float* __restrict__ target_rgb,
                                          const float* __restrict__ target_depth,
-                                         float* __restrict__ tile_loss, Rec* srec,
-                                         uint32_t* sred, float* sloss) {
-  constexpr int NT = TW * TH;
-  constexpr int NW = NT / kWave;
+                                         float* __restrict__ tile_loss, Rec* srec) {
+  using TG = Tile<TW, TH>;
+  constexpr int PPL = TG::PPL;
   const int v = find_view(vt, gtile);
   const ViewInfo vi = vt.v[v];
   const int lt = gtile - vi.tile_off;
   const int tx0 = (lt % vi.tiles_x) * TW, ty0 = (lt / vi.tiles_x) * TH;
-  const int t = threadIdx.x;
-  const int px = tx0 + t % TW, py = ty0 + t / TW;
-  const bool inside = (px < vi.W) && (py < vi.H);
-  const double sx = px + 0.5, sy = py + 0.5;
+  const int lane = threadIdx.x;
   const uint32_t s = ranges[2 * (int64_t)gtile], e = ranges[2 * (int64_t)gtile + 1];
 
-  float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, D = 0.0f;
-  uint32_t lastpos = 0;
-  bool done = !inside;
+  double sx[PPL], sy[PPL];
+  float T[PPL], c0[PPL], c1[PPL], c2[PPL], D[PPL];
+  uint32_t lastpos[PPL];
+  bool done[PPL], inside[PPL];
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int px = tx0 + TG::x(lane, k), py = ty0 + TG::y(lane, k);
+    inside[k] = (px < vi.W) && (py < vi.H);
+    sx[k] = px + 0.5;
+    sy[k] = py + 0.5;
+    T[k] = 1.0f; c0[k] = c1[k] = c2[k] = D[k] = 0.0f;
+    lastpos[k] = 0;
+    done[k] = !inside[k];
+  }
+  auto active = [&]() {
+    bool a = false;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) a = a || !done[k];
+    return a;
+  };
   for (uint32_t b = s; b < e; b += (uint32_t)B) {
+    if (ballot64(active()) == 0) break;
     const int nb = (int)min((uint32_t)B, e - b);
-    if (__syncthreads_count(done ? 0 : 1) == 0) break;
-    stage_records(srec, rec, sorted_rec, b, nb, NT);
+    __syncthreads();
+    stage(srec, nullptr, rec, sorted_rec, nullptr, b, nb, lane);
     __syncthreads();
     for (int j = 0; j < nb; ++j) {
-      if (!done) {
-        const Rec& r = srec[j];
-        double dx, dy;
-        float G, oG, a;
-        if (eval_alpha(r, sx, sy, dx, dy, G, oG, a)) {
-          const float Tn = T * (1.0f - a);
-          if (Tn < kTMin) {
-            done = true;
-          } else {
-            const float w = a * T;
-            c0 = fmaf(r.r, w, c0);
-            c1 = fmaf(r.g, w, c1);
-            c2 = fmaf(r.b, w, c2);
-            D = fmaf(r.z, w, D);
-            T = Tn;
-            lastpos = b - s + (uint32_t)j + 1u;
+      const Rec& r = srec[j];
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) {
+        if (!done[k]) {
+          double dx, dy;
+          float G, oG, a;
+          if (eval_alpha(r, sx[k], sy[k], dx, dy, G, oG, a)) {
+            const float Tn = T[k] * (1.0f - a);
+            if (Tn < kTMin) {
+              done[k] = true;
+            } else {
+              const float w = a * T[k];
+              c0[k] = fmaf(r.r, w, c0[k]);
+              c1[k] = fmaf(r.g, w, c1[k]);
+              c2[k] = fmaf(r.b, w, c2[k]);
+              D[k] = fmaf(r.z, w, D[k]);
+              T[k] = Tn;
+              lastpos[k] = b - s + (uint32_t)j + 1u;
+            }
           }
         }
       }
-      if (ballot64(!done) == 0) break;
+      if (ballot64(active()) == 0) break;
     }
   }
   const float* cam = cams + (int64_t)v * GS_CAMERA_FLOATS;
+  const float bg0 = cam[17], bg1 = cam[18], bg2 = cam[19];
+  const int64_t npx = (int64_t)vi.W * vi.H;
   float lrgb = 0.0f, ld = 0.0f;
-  if (inside) {
-    const int64_t npx = (int64_t)vi.W * vi.H;
+  uint32_t lmax = 0;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    lmax = max(lmax, lastpos[k]);
+    if (!inside[k]) continue;
+    const int px = tx0 + TG::x(lane, k), py = ty0 + TG::y(lane, k);
     const int64_t pl = (int64_t)py * vi.W + px;
     const int64_t pix = (int64_t)vi.pix_off + pl;
     const int64_t cbase = 3 * (int64_t)vi.pix_off + pl;
-    const float o0 = fmaf(T, cam[17], c0), o1 = fmaf(T, cam[18], c1), o2 = fmaf(T, cam[19], c2);
+    const float o0 = fmaf(T[k], bg0, c0[k]), o1 = fmaf(T[k], bg1, c1[k]), o2 = fmaf(T[k], bg2, c2[k]);
     color[cbase] = o0;
     color[cbase + npx] = o1;
     color[cbase + 2 * npx] = o2;
-    depth[pix] = D;
-    T_final[pix] = T;
-    last[pix] = lastpos;
+    depth[pix] = D[k];
+    T_final[pix] = T[k];
+    last[pix] = lastpos[k];
     if (target_rgb) {
-      lrgb = fabsf(o0 - target_rgb[cbase]) + fabsf(o1 - target_rgb[cbase + npx]) +
-             fabsf(o2 - target_rgb[cbase + 2 * npx]);
-      if (target_depth) ld = fabsf(D - target_depth[pix]);
+      lrgb += fabsf(o0 - target_rgb[cbase]) + fabsf(o1 - target_rgb[cbase + npx]) +
+              fabsf(o2 - target_rgb[cbase + 2 * npx]);
+      if (target_depth) ld += fabsf(D[k] - target_depth[pix]);
     }
   }
-  // per-tile maximum of `last` (where the backward starts) and loss sums
-  const uint32_t m = wave_max(lastpos);
-  float sl0 = 0.0f, sl1 = 0.0f;
+  const uint32_t m = wave_max(lmax);
   if (target_rgb) {
-    sl0 = wave_sum(lrgb);
-    sl1 = wave_sum(ld);
+    lrgb = wave_sum_to_last(lrgb);
+    ld = wave_sum_to_last(ld);
   }
-  const int w = t / kWave;
-  if (lane_id() == 0) {
-    sred[w] = m;
-    sloss[2 * w] = sl0;
-    sloss[2 * w + 1] = sl1;
-  }
-  __syncthreads();
-  if (t == 0) {
-    uint32_t mm = 0;
-    float a0 = 0.0f, a1 = 0.0f;
-    for (int k = 0; k < NW; ++k) {
-      mm = max(mm, sred[k]);
-      a0 += sloss[2 * k];
-      a1 += sloss[2 * k + 1];
-    }
-    tile_last[gtile] = mm;
+  if (lane == kWave - 1) {
+    tile_last[gtile] = m;
     if (target_rgb) {
-      tile_loss[2 * (int64_t)gtile] = a0;
-      tile_loss[2 * (int64_t)gtile + 1] = a1;
+      tile_loss[2 * (int64_t)gtile] = lrgb;
+      tile_loss[2 * (int64_t)gtile + 1] = ld;
     }
   }
-  __syncthreads();
 }
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW* TH) k_render_fwd(
+__global__ void __launch_bounds__(kWave) k_render_fwd(
     const Rec* __restrict__ rec, const uint32_t* __restrict__ sorted_rec,
     const uint32_t* __restrict__ ranges, const float* __restrict__ cams, ViewTable vt, int B,
     float* __restrict__ color, float* __restrict__ depth, float* __restrict__ T_final,
@@ -175,29 +218,25 @@ __global__ void __launch_bounds__(TW* TH) k_render_fwd(
     int32_t* __restrict__ queue, int chunk) {
   extern __shared__ __align__(16) unsigned char smem[];
   Rec* srec = reinterpret_cast<Rec*>(smem);
-  __shared__ uint32_t sred[(TW * TH) / kWave];
-  __shared__ float sloss[2 * (TW * TH) / kWave];
-  __shared__ int swork;
   if (queue == nullptr) {
     const int g = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     fwd_tile<TW, TH>(g, rec, sorted_rec, ranges, cams, vt, B, color, depth, T_final, last,
-                     tile_last, target_rgb, target_depth, tile_loss, srec, sred, sloss);
+                     tile_last, target_rgb, target_depth, tile_loss, srec);
     return;
   }
   // persistent: pull chunks of `chunk` tiles until the queue is drained
   const int n_items = (vt.total_tiles + chunk - 1) / chunk;
   for (;;) {
-    if (threadIdx.x == 0) swork = atomicAdd(queue, 1);
-    __syncthreads();
-    const int item = swork;
-    __syncthreads();
+    int item = 0;
+    if (threadIdx.x == 0) item = atomicAdd(queue, 1);
+    item = __builtin_amdgcn_readfirstlane(item);
     if (item >= n_items) break;
     const int first = item * chunk;
     const int lastt = min(vt.total_tiles, first + chunk);
     for (int k = first; k < lastt; ++k) {
       const int g = order ? (int)order[k] : k;
       fwd_tile<TW, TH>(g, rec, sorted_rec, ranges, cams, vt, B, color, depth, T_final, last,
-                       tile_last, target_rgb, target_depth, tile_loss, srec, sred, sloss);
+                       tile_last, target_rgb, target_depth, tile_loss, srec);
     }
   }
 }
@@ -243,139 +282,138 @@ __device__ __forceinline__ void bwd_tile(
     const float* __restrict__ T_final, const uint32_t* __restrict__ last,
     const float* __restrict__ dL_dcolor, const float* __restrict__ dL_ddepth,
     const float* __restrict__ target_rgb, const float* __restrict__ target_depth, int fused,
-    float lambda_depth, float* __restrict__ grad_pair, Rec* srec, float* spart) {
-  constexpr int NT = TW * TH;
-  constexpr int NW = NT / kWave;
+    float lambda_depth, float* __restrict__ grad_pair, Rec* srec, uint32_t* sval) {
+  using TG = Tile<TW, TH>;
+  constexpr int PPL = TG::PPL;
   const int v = find_view(vt, gtile);
   const ViewInfo vi = vt.v[v];
   const int lt = gtile - vi.tile_off;
   const int tx0 = (lt % vi.tiles_x) * TW, ty0 = (lt / vi.tiles_x) * TH;
-  const int t = threadIdx.x;
-  const int w = t / kWave;
-  const int lane = lane_id();
-  const int px = tx0 + t % TW, py = ty0 + t / TW;
-  const bool inside = (px < vi.W) && (py < vi.H);
-  const double sx = px + 0.5, sy = py + 0.5;
+  const int lane = threadIdx.x;
   const uint32_t s = ranges[2 * (int64_t)gtile], e = ranges[2 * (int64_t)gtile + 1];
   const uint32_t tl = tile_last[gtile];
   const float* cam = cams + (int64_t)v * GS_CAMERA_FLOATS;
+  const float bg0 = cam[17], bg1 = cam[18], bg2 = cam[19];
 
   // pairs beyond the last used position get zero gradients
-  for (uint32_t k = tl + (uint32_t)t; k < e - s; k += NT) {
+  for (uint32_t k = tl + (uint32_t)lane; k < e - s; k += kWave) {
     float4* gp = reinterpret_cast<float4*>(grad_pair + (int64_t)sorted_vals[s + k] * kPairGrad);
     const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
     gp[0] = z; gp[1] = z; gp[2] = z;
   }
 
-  float T = 1.0f, gC0 = 0.0f, gC1 = 0.0f, gC2 = 0.0f, gD = 0.0f;
-  uint32_t L = 0;
-  if (inside) {
-    const int64_t npx = (int64_t)vi.W * vi.H;
-    const int64_t pl = (int64_t)py * vi.W + px;
-    const int64_t pix = (int64_t)vi.pix_off + pl;
-    const int64_t cbase = 3 * (int64_t)vi.pix_off + pl;
-    T = T_final[pix];
-    L = last[pix];
-    if (fused) {
-      const float inv3 = 1.0f / (3.0f * (float)npx);
-      const float c0 = color[cbase], c1 = color[cbase + npx], c2 = color[cbase + 2 * npx];
-      const float d0 = c0 - target_rgb[cbase], d1 = c1 - target_rgb[cbase + npx],
-                  d2 = c2 - target_rgb[cbase + 2 * npx];
-      gC0 = d0 > 0.0f ? inv3 : (d0 < 0.0f ? -inv3 : 0.0f);
-      gC1 = d1 > 0.0f ? inv3 : (d1 < 0.0f ? -inv3 : 0.0f);
-      gC2 = d2 > 0.0f ? inv3 : (d2 < 0.0f ? -inv3 : 0.0f);
-      if (target_depth) {
-        const float dd = depth[pix] - target_depth[pix];
-        const float sc = lambda_depth / (float)npx;
-        gD = dd > 0.0f ? sc : (dd < 0.0f ? -sc : 0.0f);
+  double sx[PPL], sy[PPL];
+  float T[PPL], gC0[PPL], gC1[PPL], gC2[PPL], gD[PPL], Sc0[PPL], Sc1[PPL], Sc2[PPL], Sd[PPL];
+  uint32_t L[PPL];
+  const int64_t npx = (int64_t)vi.W * vi.H;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int px = tx0 + TG::x(lane, k), py = ty0 + TG::y(lane, k);
+    sx[k] = px + 0.5;
+    sy[k] = py + 0.5;
+    T[k] = 1.0f; gC0[k] = gC1[k] = gC2[k] = gD[k] = 0.0f;
+    L[k] = 0;
+    if (px < vi.W && py < vi.H) {
+      const int64_t pl = (int64_t)py * vi.W + px;
+      const int64_t pix = (int64_t)vi.pix_off + pl;
+      const int64_t cbase = 3 * (int64_t)vi.pix_off + pl;
+      T[k] = T_final[pix];
+      L[k] = last[pix];
+      if (fused) {
+        const float inv3 = 1.0f / (3.0f * (float)npx);
+        const float d0 = color[cbase] - target_rgb[cbase];
+        const float d1 = color[cbase + npx] - target_rgb[cbase + npx];
+        const float d2 = color[cbase + 2 * npx] - target_rgb[cbase + 2 * npx];
+        gC0[k] = d0 > 0.0f ? inv3 : (d0 < 0.0f ? -inv3 : 0.0f);
+        gC1[k] = d1 > 0.0f ? inv3 : (d1 < 0.0f ? -inv3 : 0.0f);
+        gC2[k] = d2 > 0.0f ? inv3 : (d2 < 0.0f ? -inv3 : 0.0f);
+        if (target_depth) {
+          const float dd = depth[pix] - target_depth[pix];
+          const float sc = lambda_depth / (float)npx;
+          gD[k] = dd > 0.0f ? sc : (dd < 0.0f ? -sc : 0.0f);
+        }
+      } else {
+        gC0[k] = dL_dcolor[cbase];
+        gC1[k] = dL_dcolor[cbase + npx];
+        gC2[k] = dL_dcolor[cbase + 2 * npx];
+        gD[k] = dL_ddepth ? dL_ddepth[pix] : 0.0f;
       }
-    } else {
-      gC0 = dL_dcolor[cbase];
-      gC1 = dL_dcolor[cbase + npx];
-      gC2 = dL_dcolor[cbase + 2 * npx];
-      gD = dL_ddepth ? dL_ddepth[pix] : 0.0f;
     }
+    // behind-sums: background seen through T_final, nothing behind in depth
+    Sc0[k] = T[k] * bg0;
+    Sc1[k] = T[k] * bg1;
+    Sc2[k] = T[k] * bg2;
+    Sd[k] = 0.0f;
   }
-  // behind-sums: background seen through T_final, nothing behind in depth
-  float Sc0 = T * cam[17], Sc1 = T * cam[18], Sc2 = T * cam[19], Sd = 0.0f;
 
   for (int bend = (int)tl; bend > 0; bend -= B) {
     const int bstart = max(0, bend - B);
     const int nb = bend - bstart;
     __syncthreads();
-    stage_records(srec, rec, sorted_rec, s + (uint32_t)bstart, nb, NT);
-    for (int k = t; k < NW * nb * 10; k += NT) spart[k] = 0.0f;
+    stage(srec, sval, rec, sorted_rec, sorted_vals, s + (uint32_t)bstart, nb, lane);
     __syncthreads();
     for (int j = nb - 1; j >= 0; --j) {
       const uint32_t pos = (uint32_t)(bstart + j);
+      const Rec& r = srec[j];
       float g[10];
 #pragma unroll
       for (int f = 0; f < 10; ++f) g[f] = 0.0f;
       bool contrib = false;
-      if (pos < L) {
-        const Rec& r = srec[j];
-        double dx, dy;
-        float G, oG, a;
-        if (eval_alpha(r, sx, sy, dx, dy, G, oG, a)) {
-          contrib = true;
-          const float inv_om = __builtin_amdgcn_rcpf(1.0f - a);
-          const float Tk = T * inv_om;
-          const float wgt = a * Tk;
-          g[0] = wgt * gC0;
-          g[1] = wgt * gC1;
-          g[2] = wgt * gC2;
-          g[3] = wgt * gD;
-          const float front = gC0 * r.r + gC1 * r.g + gC2 * r.b + gD * r.z;
-          const float behind = gC0 * Sc0 + gC1 * Sc1 + gC2 * Sc2 + gD * Sd;
-          const float g_alpha = Tk * front - behind * inv_om;
-          Sc0 = fmaf(r.r, wgt, Sc0);
-          Sc1 = fmaf(r.g, wgt, Sc1);
-          Sc2 = fmaf(r.b, wgt, Sc2);
-          Sd = fmaf(r.z, wgt, Sd);
-          T = Tk;
-          if (oG <= kAlphaMax) {
-            const float gpow = a * g_alpha;
-            const float fx = (float)dx, fy = (float)dy;
-            const float ca = (float)(-2.0 * r.ca), cb = (float)(-r.cb), cc = (float)(-2.0 * r.cc);
-            g[4] = G * g_alpha;
-            g[5] = -0.5f * gpow * fx * fx;
-            g[6] = -gpow * fx * fy;
-            g[7] = -0.5f * gpow * fy * fy;
-            g[8] = -gpow * (ca * fx + cb * fy);
-            g[9] = -gpow * (cb * fx + cc * fy);
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) {
+        if (pos < L[k]) {
+          double dx, dy;
+          float G, oG, a;
+          if (eval_alpha(r, sx[k], sy[k], dx, dy, G, oG, a)) {
+            contrib = true;
+            const float inv_om = __builtin_amdgcn_rcpf(1.0f - a);
+            const float Tk = T[k] * inv_om;
+            const float wgt = a * Tk;
+            g[0] = fmaf(wgt, gC0[k], g[0]);
+            g[1] = fmaf(wgt, gC1[k], g[1]);
+            g[2] = fmaf(wgt, gC2[k], g[2]);
+            g[3] = fmaf(wgt, gD[k], g[3]);
+            const float front = gC0[k] * r.r + gC1[k] * r.g + gC2[k] * r.b + gD[k] * r.z;
+            const float behind = gC0[k] * Sc0[k] + gC1[k] * Sc1[k] + gC2[k] * Sc2[k] + gD[k] * Sd[k];
+            const float g_alpha = Tk * front - behind * inv_om;
+            Sc0[k] = fmaf(r.r, wgt, Sc0[k]);
+            Sc1[k] = fmaf(r.g, wgt, Sc1[k]);
+            Sc2[k] = fmaf(r.b, wgt, Sc2[k]);
+            Sd[k] = fmaf(r.z, wgt, Sd[k]);
+            T[k] = Tk;
+            if (oG <= kAlphaMax) {
+              const float gpow = a * g_alpha;
+              const float fx = (float)dx, fy = (float)dy;
+              const float ca = (float)(-2.0 * r.ca), cb = (float)(-r.cb), cc = (float)(-2.0 * r.cc);
+              g[4] = fmaf(G, g_alpha, g[4]);
+              g[5] -= 0.5f * gpow * fx * fx;
+              g[6] -= gpow * fx * fy;
+              g[7] -= 0.5f * gpow * fy * fy;
+              g[8] -= gpow * (ca * fx + cb * fy);
+              g[9] -= gpow * (cb * fx + cc * fy);
+            }
           }
         }
       }
+      float4* gp = reinterpret_cast<float4*>(grad_pair + (int64_t)sval[j] * kPairGrad);
       if (ballot64(contrib) != 0) {
 #pragma unroll
-        for (int f = 0; f < 10; ++f) g[f] = wave_sum(g[f]);
-        if (lane == 0) {
-#pragma unroll
-          for (int f = 0; f < 10; ++f) spart[(w * nb + j) * 10 + f] = g[f];
+        for (int f = 0; f < 10; ++f) g[f] = wave_sum_to_last(g[f]);
+        if (lane == kWave - 1) {
+          gp[0] = make_float4(g[0], g[1], g[2], g[3]);
+          gp[1] = make_float4(g[4], g[5], g[6], g[7]);
+          gp[2] = make_float4(g[8], g[9], 0.0f, 0.0f);
         }
+      } else if (lane == 0) {
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        gp[0] = z; gp[1] = z; gp[2] = z;
       }
     }
-    __syncthreads();
-    // combine wavefronts in a fixed order; one slot per (tile, Gaussian)
-    for (int k = t; k < nb; k += NT) {
-      float acc[10];
-#pragma unroll
-      for (int f = 0; f < 10; ++f) acc[f] = spart[k * 10 + f];
-      for (int ww = 1; ww < NW; ++ww)
-#pragma unroll
-        for (int f = 0; f < 10; ++f) acc[f] += spart[(ww * nb + k) * 10 + f];
-      float4* gp =
-          reinterpret_cast<float4*>(grad_pair + (int64_t)sorted_vals[s + bstart + k] * kPairGrad);
-      gp[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-      gp[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
-      gp[2] = make_float4(acc[8], acc[9], 0.0f, 0.0f);
-    }
   }
-  __syncthreads();
 }
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW* TH) k_render_bwd(
+__global__ void __launch_bounds__(kWave) k_render_bwd(
     const Rec* __restrict__ rec, const uint32_t* __restrict__ sorted_rec,
     const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ tile_last, const float* __restrict__ cams, ViewTable vt, int B,
@@ -387,21 +425,19 @@ __global__ void __launch_bounds__(TW* TH) k_render_bwd(
     int32_t* __restrict__ queue, int chunk) {
   extern __shared__ __align__(16) unsigned char smem[];
   Rec* srec = reinterpret_cast<Rec*>(smem);
-  float* spart = reinterpret_cast<float*>(smem + (size_t)B * sizeof(Rec));
-  __shared__ int swork;
+  uint32_t* sval = reinterpret_cast<uint32_t*>(smem + (size_t)B * sizeof(Rec));
   if (queue == nullptr) {
     const int g = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     bwd_tile<TW, TH>(g, rec, sorted_rec, sorted_vals, ranges, tile_last, cams, vt, B, color, depth,
                      T_final, last, dL_dcolor, dL_ddepth, target_rgb, target_depth, fused,
-                     lambda_depth, grad_pair, srec, spart);
+                     lambda_depth, grad_pair, srec, sval);
     return;
   }
   const int n_items = (vt.total_tiles + chunk - 1) / chunk;
   for (;;) {
-    if (threadIdx.x == 0) swork = atomicAdd(queue, 1);
-    __syncthreads();
-    const int item = swork;
-    __syncthreads();
+    int item = 0;
+    if (threadIdx.x == 0) item = atomicAdd(queue, 1);
+    item = __builtin_amdgcn_readfirstlane(item);
     if (item >= n_items) break;
     const int first = item * chunk;
     const int lastt = min(vt.total_tiles, first + chunk);
@@ -409,7 +445,7 @@ __global__ void __launch_bounds__(TW* TH) k_render_bwd(
       const int g = order ? (int)order[k] : k;
       bwd_tile<TW, TH>(g, rec, sorted_rec, sorted_vals, ranges, tile_last, cams, vt, B, color,
                        depth, T_final, last, dL_dcolor, dL_ddepth, target_rgb, target_depth,
-                       fused, lambda_depth, grad_pair, srec, spart);
+                       fused, lambda_depth, grad_pair, srec, sval);
     }
   }
 }
@@ -421,7 +457,7 @@ hipError_t fwd_launch(const Plan& P, void* ws, const float* cams, float* color, 
                       int grid, hipStream_t s) {
   const int B = P.cfg.lds_batch;
   const size_t lds = (size_t)B * sizeof(Rec);
-  hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3(grid), dim3(TW * TH), lds, s,
+  hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3(grid), dim3(kWave), lds, s,
                      ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_sorted_rec),
                      ws_at<uint32_t>(ws, P.off_ranges), cams, P.vt, B, color, depth, T_final,
                      last, ws_at<uint32_t>(ws, P.off_tile_last), target_rgb, target_depth,
@@ -435,10 +471,9 @@ hipError_t bwd_launch(const Plan& P, void* ws, const float* cams, const float* c
                       const float* dL_dcolor, const float* dL_ddepth, const float* target_rgb,
                       const float* target_depth, int fused, const uint32_t* sorted_vals,
                       const uint32_t* order, int32_t* queue, int grid, hipStream_t s) {
-  constexpr int NW = TW * TH / kWave;
   const int B = P.cfg.lds_batch;
-  const size_t lds = (size_t)B * sizeof(Rec) + (size_t)NW * B * 10 * sizeof(float);
-  hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(grid), dim3(TW * TH), lds, s,
+  const size_t lds = (size_t)B * (sizeof(Rec) + sizeof(uint32_t));
+  hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(grid), dim3(kWave), lds, s,
                      ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_sorted_rec), sorted_vals,
                      ws_at<uint32_t>(ws, P.off_ranges), ws_at<uint32_t>(ws, P.off_tile_last), cams,
                      P.vt, B, color, depth, T_final, last, dL_dcolor, dL_ddepth, target_rgb,
@@ -447,11 +482,24 @@ hipError_t bwd_launch(const Plan& P, void* ws, const float* cams, const float* c
   return hipGetLastError();
 }
 
+template <typename K>
+int occupancy(K kernel, size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, kWave, lds) != hipSuccess || n < 1)
+    n = 4;
+  return n;
+}
+
 }  // namespace
 
-size_t render_bwd_lds_bytes(const Plan& P) {
-  const int NW = P.cfg.tile_w * P.cfg.tile_h / kWave;
-  return (size_t)P.cfg.lds_batch * sizeof(Rec) + (size_t)NW * P.cfg.lds_batch * 10 * sizeof(float);
+// Resident single-wave workgroups per CU of the render kernel for this plan.
+int render_blocks_per_cu(const Plan& P, bool bwd) {
+  const int B = P.cfg.lds_batch;
+  const size_t lf = (size_t)B * sizeof(Rec), lb = (size_t)B * (sizeof(Rec) + sizeof(uint32_t));
+  const int tw = P.cfg.tile_w, th = P.cfg.tile_h;
+  if (tw == 16 && th == 16) return bwd ? occupancy(k_render_bwd<16, 16>, lb) : occupancy(k_render_fwd<16, 16>, lf);
+  if (tw == 16 && th == 8) return bwd ? occupancy(k_render_bwd<16, 8>, lb) : occupancy(k_render_fwd<16, 8>, lf);
+  return bwd ? occupancy(k_render_bwd<8, 8>, lb) : occupancy(k_render_fwd<8, 8>, lf);
 }
 
 hipError_t launch_render_fwd(const Plan& P, void* ws, const float* cams, float* color,

@@ -235,6 +235,25 @@ def render_bwd(plan: Plan, ws: torch.Tensor, g: Gaussians, cams: torch.Tensor, f
         _stream(stream)))
 
 
+def render_loss(plan: Plan, ws: torch.Tensor, fr: Frame, target_rgb, target_depth=None,
+                lambda_ssim: float = 0.2, dL_dcolor=None, dL_ddepth=None, stream=None):
+    """Eq. (9) loss per view (into fr.loss) and its image gradients."""
+    _check_ws(plan, ws)
+    P = plan.total_pixels
+    if dL_dcolor is None:
+        dL_dcolor = torch.empty(3 * P, dtype=torch.float32, device=ws.device)
+    if dL_ddepth is None:
+        dL_ddepth = torch.empty(P, dtype=torch.float32, device=ws.device)
+    for t, n, name in ((target_rgb, 3 * P, "target_rgb"), (target_depth, P, "target_depth"),
+                       (dL_dcolor, 3 * P, "dL_dcolor"), (dL_ddepth, P, "dL_ddepth")):
+        _check_img(t, n, name)
+    L.check(L.lib().gs_render_loss(ctypes.byref(plan.c), _ptr(ws), _ptr(fr.color), _ptr(fr.depth),
+                                   _ptr(target_rgb), _ptr(target_depth), float(lambda_ssim),
+                                   _ptr(dL_dcolor), _ptr(dL_ddepth), _ptr(fr.loss),
+                                   _stream(stream)))
+    return dL_dcolor, dL_ddepth
+
+
 def render_bwd_raster(plan: Plan, ws: torch.Tensor, cams: torch.Tensor, fr: Frame,
                       dL_dcolor=None, dL_ddepth=None, target_rgb=None, target_depth=None,
                       stream=None):
@@ -295,7 +314,8 @@ class Iteration:
 
     def __init__(self, plan: Plan, g: Gaussians, cams: torch.Tensor, target_rgb=None,
                  target_depth=None, dL_dcolor=None, dL_ddepth=None, pose_grad=False,
-                 adam_lrs: Optional[dict] = None, lambda_o: float = 0.0, device="cuda"):
+                 adam_lrs: Optional[dict] = None, lambda_o: float = 0.0, lambda_ssim: float = 0.0,
+                 device="cuda"):
         self.plan, self.g, self.cams = plan, g, cams
         _check_cams(plan, cams)
         if g.n != plan.n or g.sh_degree != plan.sh_degree:
@@ -338,6 +358,13 @@ class Iteration:
         it.step_dev = self.step_dev.data_ptr()
         it.beta1, it.beta2, it.eps, it.lambda_o = 0.9, 0.999, 1e-15, float(lambda_o)
         it.reg_count = g.n
+        self.loss_grad_color = self.loss_grad_depth = None
+        if lambda_ssim > 0.0:
+            self.loss_grad_color = torch.empty(3 * P, dtype=torch.float32, device=device)
+            self.loss_grad_depth = torch.empty(P, dtype=torch.float32, device=device)
+            it.lambda_ssim = float(lambda_ssim)
+            it.loss_grad_color = self.loss_grad_color.data_ptr()
+            it.loss_grad_depth = self.loss_grad_depth.data_ptr()
         self.c = it
 
     def enqueue(self, stream=None):
@@ -350,6 +377,13 @@ class Iteration:
 
     def replay(self, stream=None):
         L.check(L.lib().gs_graph_launch(self._graph, _stream(stream)))
+
+    def time_graph(self, stream: torch.cuda.Stream, warmup: int = 3, reps: int = 20) -> float:
+        """Mean ms per replay of the captured graph (HIP events, synchronises)."""
+        ms = ctypes.c_float()
+        L.check(L.lib().gs_graph_time(self._graph, _stream(stream), int(warmup), int(reps),
+                                      ctypes.byref(ms)))
+        return float(ms.value)
 
     def close(self):
         if self._graph is not None:

@@ -1,0 +1,67 @@
+"""GPU parity of the rendered loss of Eq. (9) (L1 + SSIM + depth L1) and of
+a whole iteration driven by it, against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import ssim as ossim
+import paper_2410_00486_amd as gsr
+from paper_2410_00486_amd import _lib as L
+from synth import scenes
+
+from gpu_common import DEV, assert_grads_close, flagged_gaussians, grads_np, t32, workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("views", [[(37, 29)], [(128, 96), (64, 40)], [(640, 480)]])
+def test_render_loss_matches_oracle(views):
+    rng = np.random.default_rng(len(views) * 100 + views[0][0])
+    plan = gsr.Plan(10, 0, views, pair_capacity=16)
+    ws = plan.new_workspace(DEV)
+    fr = gsr.Frame(plan, DEV)
+    cols, tgts, deps, tdeps = [], [], [], []
+    for (w, h) in views:
+        # smooth images with structure, plus noise
+        yy, xx = np.mgrid[0:h, 0:w]
+        base = 0.5 + 0.3 * np.sin(xx / 7.0)[None] * np.cos(yy / 5.0)[None]
+        cols.append((base + 0.1 * rng.standard_normal((3, h, w))).astype(np.float32))
+        tgts.append((base + 0.1 * rng.standard_normal((3, h, w))).astype(np.float32))
+        deps.append(rng.uniform(1, 3, (h, w)).astype(np.float32))
+        tdeps.append(rng.uniform(1, 3, (h, w)).astype(np.float32))
+    fr.color.copy_(t32(np.concatenate([c.reshape(-1) for c in cols])))
+    fr.depth.copy_(t32(np.concatenate([d.reshape(-1) for d in deps])))
+    trgb = t32(np.concatenate([c.reshape(-1) for c in tgts]))
+    tdep = t32(np.concatenate([d.reshape(-1) for d in tdeps]))
+    gC, gD = gsr.render_loss(plan, ws, fr, trgb, tdep, lambda_ssim=0.2)
+    torch.cuda.synchronize()
+    gCs, gDs = plan.split_views(gC, 3), plan.split_views(gD)
+    for v in range(len(views)):
+        loss, rC, rD = ossim.rendered_loss_and_grads(cols[v], deps[v], tgts[v], tdeps[v], 0.2, 0.1)
+        assert abs(float(fr.loss[v]) - loss) <= 1e-5 * abs(loss)
+        got = gCs[v].cpu().numpy().astype(np.float64)
+        rms = np.sqrt(np.mean(rC ** 2))
+        ok = np.abs(cols[v].astype(np.float64) - tgts[v]) > 1e-6
+        err = np.abs(got - rC)[ok]
+        assert (err <= 1e-3 * np.abs(rC[ok]) + 1e-3 * rms).all(), float((err / (1e-3 * np.abs(rC[ok]) + 1e-3 * rms)).max())
+        np.testing.assert_allclose(gDs[v].cpu().numpy().astype(np.float64), rD, rtol=1e-6, atol=0)
+
+
+def test_iteration_with_ssim_matches_oracle():
+    w = workload(1)
+    cam = w.cameras[0]
+    g = gsr.Gaussians.from_scene(w.scene, DEV)
+    cams = gsr.cameras_tensor([cam], DEV)
+    trgb = w.target_rgb[0]
+    plan = gsr.Plan(w.scene.n, 0, [(cam.width, cam.height)], pair_capacity=1 << 16)
+    it = gsr.Iteration(plan, g, cams, target_rgb=t32(trgb.reshape(-1)), lambda_ssim=0.2)
+    it.enqueue()
+    torch.cuda.synchronize()
+    ref = oracle.render(w.scene, cam)
+    loss, gC, gD = ossim.rendered_loss_and_grads(ref["color"], ref["depth"], trgb, None, 0.2, 0.0)
+    assert abs(float(it.frame.loss[0]) - loss) <= 1e-5 * loss
+    grads, _ = oracle.backward(w.scene, cam, gC, gD)
+    amb = (np.abs(ref["color"] - trgb) <= 1e-5).any(0)
+    ref2 = dict(ref, flag=((ref["flag"] != 0) | amb).astype(np.int32))
+    assert_grads_close(grads_np(it), grads, flagged_gaussians(ref2, (16, 16), cam))
