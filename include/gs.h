@@ -255,6 +255,37 @@ gs_status gs_adam_step(const gs_param_group* groups, int32_t n_groups, int32_t s
                        double beta1, double beta2, double eps, double lambda_o,
                        int64_t reg_count, int32_t* step_dev, void* stream);
 
+/* Adaptive densification and opacity pruning (Sec. IV-A: densify every 500
+ * iterations with a positional-gradient threshold tau_p, remove Gaussians
+ * with opacity below eps_alpha; clone and split as in 3DGS).
+ *
+ * gs_grad_stats, after gs_render_bwd(_raster) of an iteration: for every
+ * Gaussian visible in a view, accum[i] += |(g_x W/2, g_y H/2)| (the 2D mean
+ * gradient in normalised device coordinates) and denom[i] += 1.
+ * accum, denom: device float[n], caller-owned, zeroed by the caller at the
+ * start of a densification interval.
+ *
+ * gs_densify_prune: Gaussian i is selected when denom > 0 and accum/denom >=
+ * tau_p; a selected Gaussian is cloned (itself + a copy) when its largest
+ * scale is <= percent_dense * extent, otherwise split into two children with
+ * means p + R(q)(s * n_k), n_k = normals[i][k][0..2] (caller's standard
+ * normal draws, device float[n][2][3]) and scales s / 1.6.  Every output
+ * Gaussian with sigmoid(logit) < eps_alpha is dropped.  Output order is the
+ * input order (a copy right after its original, two children in place of
+ * their parent); Adam moments `m`, `v` are carried for kept originals and
+ * zero for copies and children.  Decisions are taken in FP32.  The output
+ * count is written to *n_out (device int32); at most out_capacity Gaussians
+ * are written (the caller compares *n_out with its capacity).  tmp: device
+ * scratch of gs_densify_tmp_bytes(n) bytes, 256-byte aligned. */
+gs_status gs_grad_stats(const gs_plan* plan, void* ws, float* accum, float* denom, void* stream);
+size_t gs_densify_tmp_bytes(int64_t n);
+gs_status gs_densify_prune(const gs_gaussians* g, const gs_gaussian_grads* m,
+                           const gs_gaussian_grads* v, const float* accum, const float* denom,
+                           const float* normals, float tau_p, float eps_alpha,
+                           float percent_dense, float extent, const gs_gaussian_grads* out,
+                           const gs_gaussian_grads* out_m, const gs_gaussian_grads* out_v,
+                           int64_t out_capacity, int32_t* n_out, void* tmp, void* stream);
+
 /* Stand-alone stable LSD radix sort of n (key, value) pairs on the low
  * key_bits bits of the keys (1..64), the same kernels gs_bin_sort uses.
  * keys/vals are device arrays, sorted in place; tmp is device scratch of

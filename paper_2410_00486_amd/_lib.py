@@ -109,6 +109,12 @@ SIGNATURES = {
                              ctypes.POINTER(GsGaussianGrads), vp, vp]),
     "gs_adam_step": (i32, [ctypes.POINTER(GsParamGroup), i32, i32, f64, f64, f64, f64, i64, vp,
                            vp]),
+    "gs_grad_stats": (i32, [ctypes.POINTER(GsPlan), vp, vp, vp, vp]),
+    "gs_densify_tmp_bytes": (sz, [i64]),
+    "gs_densify_prune": (i32, [ctypes.POINTER(GsGaussians), ctypes.POINTER(GsGaussianGrads),
+                               ctypes.POINTER(GsGaussianGrads), vp, vp, vp, f32, f32, f32, f32,
+                               ctypes.POINTER(GsGaussianGrads), ctypes.POINTER(GsGaussianGrads),
+                               ctypes.POINTER(GsGaussianGrads), i64, vp, vp, vp]),
     "gs_sort_tmp_bytes": (sz, [i64]),
     "gs_sort_pairs": (i32, [vp, vp, i64, i32, vp, vp]),
     "gs_iteration_enqueue": (i32, [ctypes.POINTER(GsIteration), vp]),

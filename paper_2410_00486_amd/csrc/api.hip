@@ -40,6 +40,14 @@ hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, dou
 hipError_t launch_tile_order(const Plan& P, void* ws, hipStream_t s);
 int render_blocks_per_cu(const Plan& P, bool bwd);
 int64_t ssim_tiles(const Plan& P);
+size_t densify_tmp_bytes(int64_t n);
+hipError_t launch_grad_stats(const Plan& P, void* ws, float* accum, float* denom, hipStream_t s);
+hipError_t launch_densify(const gs_gaussians& g, const gs_gaussian_grads& m,
+                          const gs_gaussian_grads& v, const float* accum, const float* denom,
+                          const float* normals, float tau_p, float eps_alpha, float percent_dense,
+                          float extent, const gs_gaussian_grads& out, const gs_gaussian_grads& out_m,
+                          const gs_gaussian_grads& out_v, int64_t cap, int32_t* n_out, void* tmp,
+                          hipStream_t s);
 hipError_t launch_render_loss(const Plan& P, void* ws, const float* color, const float* depth,
                               const float* target_rgb, const float* target_depth,
                               double lambda_ssim, float* dL_dcolor, float* dL_ddepth,
@@ -420,6 +428,45 @@ gs_status gs_adam_step(const gs_param_group* groups, int32_t n_groups, int32_t s
   return hip_check(launch_adam(groups, n_groups, step, beta1, beta2, eps, lambda_o, reg_count,
                                step_dev, s),
                    "gs_adam_step");
+}
+
+gs_status gs_grad_stats(const gs_plan* plan, void* ws, float* accum, float* denom, void* stream) {
+  gs_status st;
+  if ((st = check_plan(plan)) != GS_OK) return st;
+  const Plan& P = *plan_of(plan);
+  if ((st = check_ws(P, ws)) != GS_OK) return st;
+  if (P.n > 0 && (!accum || !denom)) return fail(GS_ERR_INVALID_ARG, "accum and denom must be non-null");
+  return hip_check(launch_grad_stats(P, ws, accum, denom, static_cast<hipStream_t>(stream)),
+                   "gs_grad_stats");
+}
+
+size_t gs_densify_tmp_bytes(int64_t n) { return n < 0 ? 0 : densify_tmp_bytes(n); }
+
+static bool grads_ok(const gs_gaussian_grads* x) {
+  return x && x->means && x->log_scales && x->quats && x->opacity_logits && x->sh;
+}
+
+gs_status gs_densify_prune(const gs_gaussians* g, const gs_gaussian_grads* m,
+                           const gs_gaussian_grads* v, const float* accum, const float* denom,
+                           const float* normals, float tau_p, float eps_alpha,
+                           float percent_dense, float extent, const gs_gaussian_grads* out,
+                           const gs_gaussian_grads* out_m, const gs_gaussian_grads* out_v,
+                           int64_t out_capacity, int32_t* n_out, void* tmp, void* stream) {
+  if (!g || g->n < 0 || g->sh_degree < 0 || g->sh_degree > 3) return fail(GS_ERR_INVALID_ARG, "bad gaussians");
+  if (g->n > INT32_MAX / 2) return fail(GS_ERR_INVALID_ARG, "too many Gaussians");
+  if (!n_out || !tmp || !aligned(tmp, 256)) return fail(GS_ERR_INVALID_ARG, "n_out and a 256-byte aligned tmp are required");
+  if (out_capacity < 0) return fail(GS_ERR_INVALID_ARG, "out_capacity < 0");
+  if (g->n > 0) {
+    if (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh || !accum || !denom ||
+        !normals || !grads_ok(m) || !grads_ok(v) || !grads_ok(out) || !grads_ok(out_m) || !grads_ok(out_v))
+      return fail(GS_ERR_INVALID_ARG, "null pointer");
+  }
+  if (!(tau_p >= 0.0f && eps_alpha >= 0.0f && percent_dense >= 0.0f && extent >= 0.0f))
+    return fail(GS_ERR_INVALID_ARG, "thresholds must be >= 0");
+  return hip_check(launch_densify(*g, *m, *v, accum, denom, normals, tau_p, eps_alpha,
+                                  percent_dense, extent, *out, *out_m, *out_v, out_capacity,
+                                  n_out, tmp, static_cast<hipStream_t>(stream)),
+                   "gs_densify_prune");
 }
 
 size_t gs_sort_tmp_bytes(int64_t n) {

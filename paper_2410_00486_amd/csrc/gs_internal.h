@@ -56,7 +56,7 @@ struct __align__(16) Rec {
   double cc;
   float o, z;        // opacity, camera-space depth
   float r, g, b;     // colour after the clamp at 0
-  uint32_t pad;
+  uint32_t clamp;    // bit ch set: channel ch was clamped at 0 (no gradient)
 };
 static_assert(sizeof(Rec) == 64, "record must be 64 bytes");
 

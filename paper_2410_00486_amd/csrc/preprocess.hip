@@ -59,8 +59,11 @@ __global__ void __launch_bounds__(256) k_preprocess(
     uint32_t flags, Rec* __restrict__ rec, ushort4* __restrict__ rect,
     uint32_t* __restrict__ tt, int32_t* __restrict__ fl) {
   constexpr int K = (DEG + 1) * (DEG + 1);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // lanes past the end stay active (as an invalid Gaussian) so that the
+  // wavefront reductions at the end see every lane
+  const bool in_range = i0 < n;
+  const int64_t i = in_range ? i0 : n - 1;
 
   const float pf[3] = {means[3 * i], means[3 * i + 1], means[3 * i + 2]};
   const float lf[3] = {log_scales[3 * i], log_scales[3 * i + 1], log_scales[3 * i + 2]};
@@ -69,7 +72,8 @@ __global__ void __launch_bounds__(256) k_preprocess(
   bool ok = finite_f(pf[0]) && finite_f(pf[1]) && finite_f(pf[2]) && finite_f(lf[0]) &&
             finite_f(lf[1]) && finite_f(lf[2]) && finite_f(qf.x) && finite_f(qf.y) &&
             finite_f(qf.z) && finite_f(qf.w) && finite_f(bf);
-  int nonfinite = ok ? 0 : 1;
+  int nonfinite = (ok || !in_range) ? 0 : 1;
+  ok = ok && in_range;
 
   // normalised quaternion, rotation, world covariance (symmetric, 6 entries)
   double qw = qf.x, qx = qf.y, qy = qf.z, qz = qf.w;
@@ -93,8 +97,6 @@ __global__ void __launch_bounds__(256) k_preprocess(
   }
   const bool sigma3 = (flags & GS_CUTOFF_3SIGMA) != 0;
   bool sh_loaded = false;
-  double col[3] = {0, 0, 0};
-  (void)col;
   float shv[K * 3];
   int visible_count = 0;
 
@@ -184,12 +186,14 @@ __global__ void __launch_bounds__(256) k_preprocess(
         double Y[16];
         sh_basis<DEG>(dx * inv, dy * inv, dz * inv, Y);
         float rgb[3];
+        uint32_t clamp_mask = 0;
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
           double acc = 0.0;
 #pragma unroll
           for (int k = 0; k < K; ++k) acc += (double)shv[3 * k + ch] * Y[k];
           rgb[ch] = (float)fmax(0.0, acc + 0.5);
+          if (acc + 0.5 < 0.0) clamp_mask |= 1u << ch;
         }
         Rec r;
         r.mx = mx;
@@ -202,7 +206,7 @@ __global__ void __launch_bounds__(256) k_preprocess(
         r.r = rgb[0];
         r.g = rgb[1];
         r.b = rgb[2];
-        r.pad = 0;
+        r.clamp = clamp_mask;
         rec[ri] = r;
         rect[ri] = make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)x1,
                                 (unsigned short)y1);
@@ -210,7 +214,7 @@ __global__ void __launch_bounds__(256) k_preprocess(
         ++visible_count;
       }
     }
-    tt[ri] = count;
+    if (in_range) tt[ri] = count;
   }
   // per-wave aggregated statistics
   const uint64_t nf = ballot64(nonfinite != 0);

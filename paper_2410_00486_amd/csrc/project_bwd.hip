@@ -22,72 +22,59 @@ constexpr double kSH3c = 0.4570457994644658;
 constexpr double kSH3d = 0.3731763325901154;
 constexpr double kSH3e = 1.445305721320277;
 
-// Real SH basis (orthonormal, Condon-Shortley phase) at unit direction (x,y,z).
+// For each basis function k up to DEG: Y_k and its gradient as a polynomial
+// in (x, y, z) are formed in place, the SH-coefficient gradient Y_k * gcr is
+// written, and w_k grad Y_k (w_k = sum_ch gcr_ch SH_k,ch) is added to gd.
 template <int DEG>
-__device__ __forceinline__ void sh_basis(double x, double y, double z, double* Y) {
-  Y[0] = kSH0;
-  if (DEG >= 1) { Y[1] = -kSH1 * y; Y[2] = kSH1 * z; Y[3] = -kSH1 * x; }
-  if (DEG >= 2) {
-    const double xx = x * x, yy = y * y, zz = z * z;
-    Y[4] = kSH2a * x * y;
-    Y[5] = -kSH2a * y * z;
-    Y[6] = kSH2b * (2 * zz - xx - yy);
-    Y[7] = -kSH2a * x * z;
-    Y[8] = kSH2c * (xx - yy);
-    if (DEG >= 3) {
-      Y[9] = -kSH3a * y * (3 * xx - yy);
-      Y[10] = kSH3b * x * y * z;
-      Y[11] = -kSH3c * y * (4 * zz - xx - yy);
-      Y[12] = kSH3d * z * (2 * zz - 3 * xx - 3 * yy);
-      Y[13] = -kSH3c * x * (4 * zz - xx - yy);
-      Y[14] = kSH3e * z * (xx - yy);
-      Y[15] = -kSH3a * x * (xx - 3 * yy);
+__device__ __forceinline__ void sh_backward(double x, double y, double z, const double* gcr,
+                                            const float* __restrict__ shp, float* gsh,
+                                            bool first, double& gx, double& gy, double& gz) {
+  const double xx = x * x, yy = y * y, zz = z * z;
+  auto term = [&](int k, double Yk, double dx, double dy, double dz) {
+    double w = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      w += gcr[ch] * (double)shp[3 * k + ch];
+      const float add = (float)(Yk * gcr[ch]);
+      gsh[3 * k + ch] = first ? add : gsh[3 * k + ch] + add;
     }
-  }
-}
-
-// g += sum_k w_k grad Y_k(x, y, z), the basis treated as polynomials in x,y,z.
-template <int DEG>
-__device__ __forceinline__ void sh_dir_grad(double x, double y, double z, const double* w,
-                                            double& gx, double& gy, double& gz) {
+    gx += w * dx;
+    gy += w * dy;
+    gz += w * dz;
+  };
+  term(0, kSH0, 0.0, 0.0, 0.0);
   if (DEG >= 1) {
-    gy += -kSH1 * w[1];
-    gz += kSH1 * w[2];
-    gx += -kSH1 * w[3];
+    term(1, -kSH1 * y, 0.0, -kSH1, 0.0);
+    term(2, kSH1 * z, 0.0, 0.0, kSH1);
+    term(3, -kSH1 * x, -kSH1, 0.0, 0.0);
   }
   if (DEG >= 2) {
-    gx += kSH2a * y * w[4];           gy += kSH2a * x * w[4];
-    gy += -kSH2a * z * w[5];          gz += -kSH2a * y * w[5];
-    gx += -2 * kSH2b * x * w[6];      gy += -2 * kSH2b * y * w[6];  gz += 4 * kSH2b * z * w[6];
-    gx += -kSH2a * z * w[7];          gz += -kSH2a * x * w[7];
-    gx += 2 * kSH2c * x * w[8];       gy += -2 * kSH2c * y * w[8];
-    if (DEG >= 3) {
-      const double xx = x * x, yy = y * y, zz = z * z;
-      gx += -6 * kSH3a * x * y * w[9];
-      gy += -kSH3a * (3 * xx - 3 * yy) * w[9];
-      gx += kSH3b * y * z * w[10];    gy += kSH3b * x * z * w[10];  gz += kSH3b * x * y * w[10];
-      gx += 2 * kSH3c * x * y * w[11];
-      gy += -kSH3c * (4 * zz - xx - 3 * yy) * w[11];
-      gz += -8 * kSH3c * y * z * w[11];
-      gx += -6 * kSH3d * x * z * w[12];
-      gy += -6 * kSH3d * y * z * w[12];
-      gz += kSH3d * (6 * zz - 3 * xx - 3 * yy) * w[12];
-      gx += -kSH3c * (4 * zz - 3 * xx - yy) * w[13];
-      gy += 2 * kSH3c * x * y * w[13];
-      gz += -8 * kSH3c * x * z * w[13];
-      gx += 2 * kSH3e * x * z * w[14]; gy += -2 * kSH3e * y * z * w[14]; gz += kSH3e * (xx - yy) * w[14];
-      gx += -kSH3a * (3 * xx - 3 * yy) * w[15];
-      gy += 6 * kSH3a * x * y * w[15];
-    }
+    term(4, kSH2a * x * y, kSH2a * y, kSH2a * x, 0.0);
+    term(5, -kSH2a * y * z, 0.0, -kSH2a * z, -kSH2a * y);
+    term(6, kSH2b * (2 * zz - xx - yy), -2 * kSH2b * x, -2 * kSH2b * y, 4 * kSH2b * z);
+    term(7, -kSH2a * x * z, -kSH2a * z, 0.0, -kSH2a * x);
+    term(8, kSH2c * (xx - yy), 2 * kSH2c * x, -2 * kSH2c * y, 0.0);
+  }
+  if (DEG >= 3) {
+    term(9, -kSH3a * y * (3 * xx - yy), -6 * kSH3a * x * y, -kSH3a * (3 * xx - 3 * yy), 0.0);
+    term(10, kSH3b * x * y * z, kSH3b * y * z, kSH3b * x * z, kSH3b * x * y);
+    term(11, -kSH3c * y * (4 * zz - xx - yy), 2 * kSH3c * x * y, -kSH3c * (4 * zz - xx - 3 * yy),
+         -8 * kSH3c * y * z);
+    term(12, kSH3d * z * (2 * zz - 3 * xx - 3 * yy), -6 * kSH3d * x * z, -6 * kSH3d * y * z,
+         kSH3d * (6 * zz - 3 * xx - 3 * yy));
+    term(13, -kSH3c * x * (4 * zz - xx - yy), -kSH3c * (4 * zz - 3 * xx - yy), 2 * kSH3c * x * y,
+         -8 * kSH3c * x * z);
+    term(14, kSH3e * z * (xx - yy), 2 * kSH3e * x * z, -2 * kSH3e * y * z, kSH3e * (xx - yy));
+    term(15, -kSH3a * x * (xx - 3 * yy), -kSH3a * (3 * xx - 3 * yy), 6 * kSH3a * x * y, 0.0);
   }
 }
 
-template <int DEG>
+template <int DEG, bool POSE>
 __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, int64_t n, const float* __restrict__ cams, ViewTable vt,
-    const uint32_t* __restrict__ tt, const uint32_t* __restrict__ poff,
+    const Rec* __restrict__ recs, const uint32_t* __restrict__ tt, const uint32_t* __restrict__ poff,
     const float* __restrict__ grad_pair, const int32_t* __restrict__ fl, int accumulate,
     float* __restrict__ g_means, float* __restrict__ g_ls, float* __restrict__ g_q,
     float* __restrict__ g_logit, float* __restrict__ g_sh, double* __restrict__ pose_part,
@@ -99,32 +86,33 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
   const bool overflow = fl[F_OVERFLOW] != 0;
   __shared__ double spose[NW][6];
 
-  double gp[3] = {0, 0, 0}, gl[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gb = 0.0;
-  bool sh_written = false;
-  // parameters (read once)
-  double p[3] = {0, 0, 0}, s[3] = {1, 1, 1}, q[4] = {1, 0, 0, 0}, qn = 1.0, o = 0.0;
-  double R[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  // world covariance Sigma (view independent); its gradient is summed over
+  // views and pushed through scale and rotation once, after the view loop
+  double p[3] = {0, 0, 0};
   double S00 = 0, S01 = 0, S02 = 0, S11 = 0, S12 = 0, S22 = 0;
   if (valid) {
     p[0] = means[3 * i]; p[1] = means[3 * i + 1]; p[2] = means[3 * i + 2];
-    for (int k = 0; k < 3; ++k) s[k] = exp((double)log_scales[3 * i + k]);
+    double q[4];
     for (int k = 0; k < 4; ++k) q[k] = quats[4 * i + k];
-    qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     if (qn > 0.0)
       for (int k = 0; k < 4; ++k) q[k] /= qn;
     const double w = q[0], x = q[1], y = q[2], z = q[3];
-    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z); R[2] = 2 * (x * z + w * y);
-    R[3] = 2 * (x * y + w * z); R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
-    R[6] = 2 * (x * z - w * y); R[7] = 2 * (y * z + w * x); R[8] = 1 - 2 * (x * x + y * y);
-    const double s0 = s[0] * s[0], s1 = s[1] * s[1], s2 = s[2] * s[2];
-    S00 = R[0] * R[0] * s0 + R[1] * R[1] * s1 + R[2] * R[2] * s2;
-    S01 = R[0] * R[3] * s0 + R[1] * R[4] * s1 + R[2] * R[5] * s2;
-    S02 = R[0] * R[6] * s0 + R[1] * R[7] * s1 + R[2] * R[8] * s2;
-    S11 = R[3] * R[3] * s0 + R[4] * R[4] * s1 + R[5] * R[5] * s2;
-    S12 = R[3] * R[6] * s0 + R[4] * R[7] * s1 + R[5] * R[8] * s2;
-    S22 = R[6] * R[6] * s0 + R[7] * R[7] * s1 + R[8] * R[8] * s2;
-    o = 1.0 / (1.0 + exp(-(double)logits[i]));
+    const double R00 = 1 - 2 * (y * y + z * z), R01 = 2 * (x * y - w * z), R02 = 2 * (x * z + w * y);
+    const double R10 = 2 * (x * y + w * z), R11 = 1 - 2 * (x * x + z * z), R12 = 2 * (y * z - w * x);
+    const double R20 = 2 * (x * z - w * y), R21 = 2 * (y * z + w * x), R22 = 1 - 2 * (x * x + y * y);
+    const double s0 = exp(2.0 * (double)log_scales[3 * i]), s1 = exp(2.0 * (double)log_scales[3 * i + 1]),
+                 s2 = exp(2.0 * (double)log_scales[3 * i + 2]);
+    S00 = R00 * R00 * s0 + R01 * R01 * s1 + R02 * R02 * s2;
+    S01 = R00 * R10 * s0 + R01 * R11 * s1 + R02 * R12 * s2;
+    S02 = R00 * R20 * s0 + R01 * R21 * s1 + R02 * R22 * s2;
+    S11 = R10 * R10 * s0 + R11 * R11 * s1 + R12 * R12 * s2;
+    S12 = R10 * R20 * s0 + R11 * R21 * s1 + R12 * R22 * s2;
+    S22 = R20 * R20 * s0 + R21 * R21 * s1 + R22 * R22 * s2;
   }
+  double gp0 = 0, gp1 = 0, gp2 = 0, gop = 0;
+  double GS00 = 0, GS01 = 0, GS02 = 0, GS11 = 0, GS12 = 0, GS22 = 0;
+  bool sh_written = false;
 
   for (int v = 0; v < vt.n_views; ++v) {
     const int64_t ri = (int64_t)v * n + i;
@@ -140,10 +128,7 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
         g2[4] += b.x; g2[5] += b.y; g2[6] += b.z; g2[7] += b.w;
         g2[8] += c.x; g2[9] += c.y;
       }
-      const double g_rgb[3] = {g2[0], g2[1], g2[2]};
-      const double g_depth = g2[3], g_op = g2[4];
-      const double ga = g2[5], gbb = g2[6], gc = g2[7], gmx = g2[8], gmy = g2[9];
-
+      gop += g2[4];
       const float* c = cams + (int64_t)v * GS_CAMERA_FLOATS;
       const double fx = c[0], fy = c[1];
       double W[9];
@@ -156,8 +141,8 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
       const double limy = 1.3 * (double)vt.v[v].H / (2.0 * fy);
       const double ux = tx / tz, vy = ty / tz;
       const bool cu = (ux < -limx) || (ux > limx), cv = (vy < -limy) || (vy > limy);
-      const double u = fmin(limx, fmax(-limx, ux)), w = fmin(limy, fmax(-limy, vy));
-      const double j00 = fx / tz, j02 = -fx * u / tz, j11 = fy / tz, j12 = -fy * w / tz;
+      const double u = fmin(limx, fmax(-limx, ux)), wv = fmin(limy, fmax(-limy, vy));
+      const double j00 = fx / tz, j02 = -fx * u / tz, j11 = fy / tz, j12 = -fy * wv / tz;
       const double a0 = j00 * W[0] + j02 * W[6], a1 = j00 * W[1] + j02 * W[7], a2 = j00 * W[2] + j02 * W[8];
       const double b0 = j11 * W[3] + j12 * W[6], b1 = j11 * W[4] + j12 * W[7], b2 = j11 * W[5] + j12 * W[8];
       const double Sa0 = S00 * a0 + S01 * a1 + S02 * a2, Sa1 = S01 * a0 + S11 * a1 + S12 * a2,
@@ -170,33 +155,37 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
       const double det = A * C - B * B;
       const double ya = C / det, yb = -B / det, yc = A / det;  // conic
       // dL/dX = -Y G_Y Y with G_Y = [[ga, gb/2], [gb/2, gc]]
-      const double M00 = ya * ga + yb * 0.5 * gbb, M01 = ya * 0.5 * gbb + yb * gc;
-      const double M10 = yb * ga + yc * 0.5 * gbb, M11 = yb * 0.5 * gbb + yc * gc;
+      const double ga = g2[5], gbh = 0.5 * g2[6], gc = g2[7];
+      const double M00 = ya * ga + yb * gbh, M01 = ya * gbh + yb * gc;
+      const double M10 = yb * ga + yc * gbh, M11 = yb * gbh + yc * gc;
       const double X00 = -(M00 * ya + M01 * yb), X01 = -(M00 * yb + M01 * yc),
                    X11 = -(M10 * yb + M11 * yc);
-      // G_Sigma = X00 a a^T + X01 (a b^T + b a^T) + X11 b b^T
-      const double av[3] = {a0, a1, a2}, bv[3] = {b0, b1, b2};
-      double GS[3][3];
-      for (int r = 0; r < 3; ++r)
-        for (int cc = 0; cc < 3; ++cc)
-          GS[r][cc] = X00 * av[r] * av[cc] + X01 * (av[r] * bv[cc] + bv[r] * av[cc]) + X11 * bv[r] * bv[cc];
+      // G_Sigma += X00 a a^T + X01 (a b^T + b a^T) + X11 b b^T
+      GS00 += X00 * a0 * a0 + 2.0 * X01 * a0 * b0 + X11 * b0 * b0;
+      GS11 += X00 * a1 * a1 + 2.0 * X01 * a1 * b1 + X11 * b1 * b1;
+      GS22 += X00 * a2 * a2 + 2.0 * X01 * a2 * b2 + X11 * b2 * b2;
+      GS01 += X00 * a0 * a1 + X01 * (a0 * b1 + b0 * a1) + X11 * b0 * b1;
+      GS02 += X00 * a0 * a2 + X01 * (a0 * b2 + b0 * a2) + X11 * b0 * b2;
+      GS12 += X00 * a1 * a2 + X01 * (a1 * b2 + b1 * a2) + X11 * b1 * b2;
       // G_T2 rows: 2 (X00 Sa + X01 Sb), 2 (X01 Sa + X11 Sb);  G_J = G_T2 W^T
-      const double gr0[3] = {2 * (X00 * Sa0 + X01 * Sb0), 2 * (X00 * Sa1 + X01 * Sb1), 2 * (X00 * Sa2 + X01 * Sb2)};
-      const double gr1[3] = {2 * (X01 * Sa0 + X11 * Sb0), 2 * (X01 * Sa1 + X11 * Sb1), 2 * (X01 * Sa2 + X11 * Sb2)};
-      const double GJ00 = gr0[0] * W[0] + gr0[1] * W[1] + gr0[2] * W[2];
-      const double GJ02 = gr0[0] * W[6] + gr0[1] * W[7] + gr0[2] * W[8];
-      const double GJ11 = gr1[0] * W[3] + gr1[1] * W[4] + gr1[2] * W[5];
-      const double GJ12 = gr1[0] * W[6] + gr1[1] * W[7] + gr1[2] * W[8];
+      const double r00 = 2 * (X00 * Sa0 + X01 * Sb0), r01 = 2 * (X00 * Sa1 + X01 * Sb1),
+                   r02 = 2 * (X00 * Sa2 + X01 * Sb2);
+      const double r10 = 2 * (X01 * Sa0 + X11 * Sb0), r11 = 2 * (X01 * Sa1 + X11 * Sb1),
+                   r12 = 2 * (X01 * Sa2 + X11 * Sb2);
+      const double GJ00 = r00 * W[0] + r01 * W[1] + r02 * W[2];
+      const double GJ02 = r00 * W[6] + r01 * W[7] + r02 * W[8];
+      const double GJ11 = r10 * W[3] + r11 * W[4] + r12 * W[5];
+      const double GJ12 = r10 * W[6] + r11 * W[7] + r12 * W[8];
       const double tz2 = tz * tz, tz3 = tz2 * tz;
-      double gt[3] = {0, 0, 0};
-      gt[2] += -GJ00 * fx / tz2 - GJ11 * fy / tz2;
-      if (!cu) { gt[0] += -GJ02 * fx / tz2; gt[2] += GJ02 * 2.0 * fx * tx / tz3; }
-      else { gt[2] += GJ02 * fx * u / tz2; }
-      if (!cv) { gt[1] += -GJ12 * fy / tz2; gt[2] += GJ12 * 2.0 * fy * ty / tz3; }
-      else { gt[2] += GJ12 * fy * w / tz2; }
-      gt[0] += gmx * fx / tz;
-      gt[1] += gmy * fy / tz;
-      gt[2] += -(gmx * fx * tx + gmy * fy * ty) / tz2 + g_depth;
+      double gt0 = 0, gt1 = 0, gt2 = -GJ00 * fx / tz2 - GJ11 * fy / tz2;
+      if (!cu) { gt0 += -GJ02 * fx / tz2; gt2 += GJ02 * 2.0 * fx * tx / tz3; }
+      else { gt2 += GJ02 * fx * u / tz2; }
+      if (!cv) { gt1 += -GJ12 * fy / tz2; gt2 += GJ12 * 2.0 * fy * ty / tz3; }
+      else { gt2 += GJ12 * fy * wv / tz2; }
+      const double gmx = g2[8], gmy = g2[9];
+      gt0 += gmx * fx / tz;
+      gt1 += gmy * fy / tz;
+      gt2 += -(gmx * fx * tx + gmy * fy * ty) / tz2 + g2[3];
 
       // colour: SH coefficients and view direction
       const double cxw = -(W[0] * t0 + W[3] * t1 + W[6] * t2);
@@ -205,96 +194,55 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
       const double dv0 = p[0] - cxw, dv1 = p[1] - cyw, dv2 = p[2] - czw;
       const double dist = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
       const double d0 = dv0 / dist, d1 = dv1 / dist, d2 = dv2 / dist;
-      double Y[16];
-      sh_basis<DEG>(d0, d1, d2, Y);
       const float* shp = sh + i * (K * 3);
       float* gsh = g_sh + i * (K * 3);
-      double raw[3] = {0.5, 0.5, 0.5};
-      for (int k = 0; k < K; ++k)
-        for (int ch = 0; ch < 3; ++ch) raw[ch] += (double)shp[3 * k + ch] * Y[k];
+      // colour clamp decided by the forward projection (record bit per channel)
+      const uint32_t cmask = recs[ri].clamp;
       double gcr[3];
-      for (int ch = 0; ch < 3; ++ch) gcr[ch] = raw[ch] < 0.0 ? 0.0 : g_rgb[ch];
-      // per-basis weights w_k = sum_ch gcr_ch SH_k,ch and the SH gradients
-      double wk[16];
-      const bool first = !sh_written && !accumulate;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        wk[k] = 0.0;
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          wk[k] += gcr[ch] * (double)shp[3 * k + ch];
-          const float add = (float)(Y[k] * gcr[ch]);
-          gsh[3 * k + ch] = first ? add : gsh[3 * k + ch] + add;
-        }
-      }
-      double gd[3] = {0, 0, 0};
-      sh_dir_grad<DEG>(d0, d1, d2, wk, gd[0], gd[1], gd[2]);
+      for (int ch = 0; ch < 3; ++ch) gcr[ch] = ((cmask >> ch) & 1u) ? 0.0 : g2[ch];
+      double gd0 = 0, gd1 = 0, gd2 = 0;
+      sh_backward<DEG>(d0, d1, d2, gcr, shp, gsh, !sh_written && !accumulate, gd0, gd1, gd2);
       sh_written = true;
-      const double dd = gd[0] * d0 + gd[1] * d1 + gd[2] * d2;
-      const double gv[3] = {(gd[0] - dd * d0) / dist, (gd[1] - dd * d1) / dist, (gd[2] - dd * d2) / dist};
-      // mean
-      for (int r = 0; r < 3; ++r) gp[r] += W[r] * gt[0] + W[3 + r] * gt[1] + W[6 + r] * gt[2] + gv[r];
-      // scale and rotation: G_R[:, j] = 2 s_j^2 G_Sigma R_j ; g_l_j = s_j^2 * 2 R_j^T G_Sigma R_j
-      double GR[9];
-      for (int j = 0; j < 3; ++j) {
-        const double Rj[3] = {R[j], R[3 + j], R[6 + j]};
-        const double GRj[3] = {GS[0][0] * Rj[0] + GS[0][1] * Rj[1] + GS[0][2] * Rj[2],
-                               GS[1][0] * Rj[0] + GS[1][1] * Rj[1] + GS[1][2] * Rj[2],
-                               GS[2][0] * Rj[0] + GS[2][1] * Rj[1] + GS[2][2] * Rj[2]};
-        const double s2 = s[j] * s[j];
-        gl[j] += 2.0 * s2 * (Rj[0] * GRj[0] + Rj[1] * GRj[1] + Rj[2] * GRj[2]);
-        GR[j] = 2.0 * s2 * GRj[0];
-        GR[3 + j] = 2.0 * s2 * GRj[1];
-        GR[6 + j] = 2.0 * s2 * GRj[2];
+      const double dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
+      const double gv0 = (gd0 - dd * d0) / dist, gv1 = (gd1 - dd * d1) / dist,
+                   gv2 = (gd2 - dd * d2) / dist;
+      // mean: W^T g_t + g_v
+      gp0 += W[0] * gt0 + W[3] * gt1 + W[6] * gt2 + gv0;
+      gp1 += W[1] * gt0 + W[4] * gt1 + W[7] * gt2 + gv1;
+      gp2 += W[2] * gt0 + W[5] * gt1 + W[8] * gt2 + gv2;
+      if (POSE) {
+        // camera tangent: rho = g_t + W g_v;  phi = t x g_t - 2 axial(Sc Gc - Gc Sc)
+        pose[0] = gt0 + W[0] * gv0 + W[1] * gv1 + W[2] * gv2;
+        pose[1] = gt1 + W[3] * gv0 + W[4] * gv1 + W[5] * gv2;
+        pose[2] = gt2 + W[6] * gv0 + W[7] * gv1 + W[8] * gv2;
+        pose[3] = ty * gt2 - tz * gt1;
+        pose[4] = tz * gt0 - tx * gt2;
+        pose[5] = tx * gt1 - ty * gt0;
+        const double Sw[3][3] = {{S00, S01, S02}, {S01, S11, S12}, {S02, S12, S22}};
+        double WS[3][3], Sc[3][3];
+        for (int r = 0; r < 3; ++r)
+          for (int cc = 0; cc < 3; ++cc)
+            WS[r][cc] = W[3 * r] * Sw[0][cc] + W[3 * r + 1] * Sw[1][cc] + W[3 * r + 2] * Sw[2][cc];
+        for (int r = 0; r < 3; ++r)
+          for (int cc = 0; cc < 3; ++cc)
+            Sc[r][cc] = WS[r][0] * W[3 * cc] + WS[r][1] * W[3 * cc + 1] + WS[r][2] * W[3 * cc + 2];
+        const double jr0[3] = {j00, 0.0, j02}, jr1[3] = {0.0, j11, j12};
+        double Gc[3][3];
+        for (int r = 0; r < 3; ++r)
+          for (int cc = 0; cc < 3; ++cc)
+            Gc[r][cc] = X00 * jr0[r] * jr0[cc] + X01 * (jr0[r] * jr1[cc] + jr1[r] * jr0[cc]) + X11 * jr1[r] * jr1[cc];
+        double A21 = 0, A02 = 0, A10 = 0;
+        for (int k = 0; k < 3; ++k) {
+          A21 += Sc[2][k] * Gc[k][1] - Gc[2][k] * Sc[k][1];
+          A02 += Sc[0][k] * Gc[k][2] - Gc[0][k] * Sc[k][2];
+          A10 += Sc[1][k] * Gc[k][0] - Gc[1][k] * Sc[k][0];
+        }
+        pose[3] -= 2.0 * A21;
+        pose[4] -= 2.0 * A02;
+        pose[5] -= 2.0 * A10;
       }
-      {
-        const double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
-        const double dw = GR[1] * (-2 * qz) + GR[2] * (2 * qy) + GR[3] * (2 * qz) + GR[5] * (-2 * qx) +
-                          GR[6] * (-2 * qy) + GR[7] * (2 * qx);
-        const double dx = GR[1] * (2 * qy) + GR[2] * (2 * qz) + GR[3] * (2 * qy) + GR[4] * (-4 * qx) +
-                          GR[5] * (-2 * qw) + GR[6] * (2 * qz) + GR[7] * (2 * qw) + GR[8] * (-4 * qx);
-        const double dy = GR[0] * (-4 * qy) + GR[1] * (2 * qx) + GR[2] * (2 * qw) + GR[3] * (2 * qx) +
-                          GR[5] * (2 * qz) + GR[6] * (-2 * qw) + GR[7] * (2 * qz) + GR[8] * (-4 * qy);
-        const double dz = GR[0] * (-4 * qz) + GR[1] * (-2 * qw) + GR[2] * (2 * qx) + GR[3] * (2 * qw) +
-                          GR[4] * (-4 * qz) + GR[5] * (2 * qy) + GR[6] * (2 * qx) + GR[7] * (2 * qy);
-        const double dot = dw * qw + dx * qx + dy * qy + dz * qz;
-        gq[0] += (dw - dot * qw) / qn;
-        gq[1] += (dx - dot * qx) / qn;
-        gq[2] += (dy - dot * qy) / qn;
-        gq[3] += (dz - dot * qz) / qn;
-      }
-      gb += g_op * o * (1.0 - o);
-      // camera tangent
-      for (int r = 0; r < 3; ++r) pose[r] = gt[r] + W[3 * r] * gv[0] + W[3 * r + 1] * gv[1] + W[3 * r + 2] * gv[2];
-      pose[3] = ty * gt[2] - tz * gt[1];
-      pose[4] = tz * gt[0] - tx * gt[2];
-      pose[5] = tx * gt[1] - ty * gt[0];
-      // Sigma_c = W Sigma W^T ;  G_c = J^T X J (J has j01 = j10 = 0)
-      const double Sw[3][3] = {{S00, S01, S02}, {S01, S11, S12}, {S02, S12, S22}};
-      double WS[3][3], Sc[3][3];
-      for (int r = 0; r < 3; ++r)
-        for (int cc = 0; cc < 3; ++cc)
-          WS[r][cc] = W[3 * r] * Sw[0][cc] + W[3 * r + 1] * Sw[1][cc] + W[3 * r + 2] * Sw[2][cc];
-      for (int r = 0; r < 3; ++r)
-        for (int cc = 0; cc < 3; ++cc)
-          Sc[r][cc] = WS[r][0] * W[3 * cc] + WS[r][1] * W[3 * cc + 1] + WS[r][2] * W[3 * cc + 2];
-      const double jr0[3] = {j00, 0.0, j02}, jr1[3] = {0.0, j11, j12};
-      double Gc[3][3];
-      for (int r = 0; r < 3; ++r)
-        for (int cc = 0; cc < 3; ++cc)
-          Gc[r][cc] = X00 * jr0[r] * jr0[cc] + X01 * (jr0[r] * jr1[cc] + jr1[r] * jr0[cc]) + X11 * jr1[r] * jr1[cc];
-      // A = Sc Gc - Gc Sc ; g_phi -= 2 (A21, A02, A10)
-      double A21 = 0, A02 = 0, A10 = 0;
-      for (int k = 0; k < 3; ++k) {
-        A21 += Sc[2][k] * Gc[k][1] - Gc[2][k] * Sc[k][1];
-        A02 += Sc[0][k] * Gc[k][2] - Gc[0][k] * Sc[k][2];
-        A10 += Sc[1][k] * Gc[k][0] - Gc[1][k] * Sc[k][0];
-      }
-      pose[3] -= 2.0 * A21;
-      pose[4] -= 2.0 * A02;
-      pose[5] -= 2.0 * A10;
     }
-    if (pose_part) {
+    if (POSE) {
       // workgroup sum of the camera tangent for this view, fixed order
       const int w = threadIdx.x / kWave;
 #pragma unroll
@@ -312,11 +260,50 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
     }
   }
   if (!valid) return;
+  // Sigma = M M^T, M = R diag(s):  g_l_j = 2 s_j^2 R_j^T G R_j,
+  // G_R[:, j] = 2 s_j^2 G R_j, then through the normalised quaternion
+  double q[4];
+  for (int k = 0; k < 4; ++k) q[k] = quats[4 * i + k];
+  const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  if (qn > 0.0)
+    for (int k = 0; k < 4; ++k) q[k] /= qn;
+  const double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+  const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
+                       2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
+                       2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
+  double GR[9], gl[3];
+  for (int j = 0; j < 3; ++j) {
+    const double Rj0 = R[j], Rj1 = R[3 + j], Rj2 = R[6 + j];
+    const double G0 = GS00 * Rj0 + GS01 * Rj1 + GS02 * Rj2;
+    const double G1 = GS01 * Rj0 + GS11 * Rj1 + GS12 * Rj2;
+    const double G2 = GS02 * Rj0 + GS12 * Rj1 + GS22 * Rj2;
+    const double s2 = exp(2.0 * (double)log_scales[3 * i + j]);
+    gl[j] = 2.0 * s2 * (Rj0 * G0 + Rj1 * G1 + Rj2 * G2);
+    GR[j] = 2.0 * s2 * G0;
+    GR[3 + j] = 2.0 * s2 * G1;
+    GR[6 + j] = 2.0 * s2 * G2;
+  }
+  const double dw = GR[1] * (-2 * qz) + GR[2] * (2 * qy) + GR[3] * (2 * qz) + GR[5] * (-2 * qx) +
+                    GR[6] * (-2 * qy) + GR[7] * (2 * qx);
+  const double dx = GR[1] * (2 * qy) + GR[2] * (2 * qz) + GR[3] * (2 * qy) + GR[4] * (-4 * qx) +
+                    GR[5] * (-2 * qw) + GR[6] * (2 * qz) + GR[7] * (2 * qw) + GR[8] * (-4 * qx);
+  const double dy = GR[0] * (-4 * qy) + GR[1] * (2 * qx) + GR[2] * (2 * qw) + GR[3] * (2 * qx) +
+                    GR[5] * (2 * qz) + GR[6] * (-2 * qw) + GR[7] * (2 * qz) + GR[8] * (-4 * qy);
+  const double dz = GR[0] * (-4 * qz) + GR[1] * (-2 * qw) + GR[2] * (2 * qx) + GR[3] * (2 * qw) +
+                    GR[4] * (-4 * qz) + GR[5] * (2 * qy) + GR[6] * (2 * qx) + GR[7] * (2 * qy);
+  const double dot = dw * qw + dx * qx + dy * qy + dz * qz;
+  const double o = 1.0 / (1.0 + exp(-(double)logits[i]));
   auto put = [&](float* dst, double val) { *dst = accumulate ? *dst + (float)val : (float)val; };
-  for (int r = 0; r < 3; ++r) put(&g_means[3 * i + r], gp[r]);
+  put(&g_means[3 * i], gp0);
+  put(&g_means[3 * i + 1], gp1);
+  put(&g_means[3 * i + 2], gp2);
   for (int r = 0; r < 3; ++r) put(&g_ls[3 * i + r], gl[r]);
-  for (int r = 0; r < 4; ++r) put(&g_q[4 * i + r], gq[r]);
-  put(&g_logit[i], gb);
+  const double qnn = qn > 0.0 ? qn : 1.0;
+  put(&g_q[4 * i], (dw - dot * qw) / qnn);
+  put(&g_q[4 * i + 1], (dx - dot * qx) / qnn);
+  put(&g_q[4 * i + 2], (dy - dot * qy) / qnn);
+  put(&g_q[4 * i + 3], (dz - dot * qz) / qnn);
+  put(&g_logit[i], gop * o * (1.0 - o));
   if (!sh_written && !accumulate) {
     float* gsh = g_sh + i * (K * 3);
     for (int k = 0; k < K * 3; ++k) gsh[k] = 0.0f;
@@ -351,13 +338,19 @@ hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float*
   const int64_t blocks = P.proj_blocks;
   if (blocks == 0) return hipSuccess;
   double* pose_part = dL_dpose ? ws_at<double>(ws, P.off_pose_part) : nullptr;
-#define GS_PB(D)                                                                              \
-  hipLaunchKernelGGL(k_project_bwd<D>, dim3((unsigned)blocks), dim3(kProjThreads), 0, s,       \
+#define GS_PB1(D, PO)                                                                         \
+  hipLaunchKernelGGL((k_project_bwd<D, PO>), dim3((unsigned)blocks), dim3(kProjThreads), 0, s, \
                      g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, P.n, cams, P.vt,  \
-                     ws_at<uint32_t>(ws, P.off_tt), ws_at<uint32_t>(ws, P.off_poff),          \
+                     ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_tt),                \
+                     ws_at<uint32_t>(ws, P.off_poff),                                          \
                      ws_at<float>(ws, P.off_grad_pair), ws_at<int32_t>(ws, P.off_flags),      \
                      accumulate, out.means, out.log_scales, out.quats, out.opacity_logits,    \
                      out.sh, pose_part, blocks)
+#define GS_PB(D)          \
+  if (pose_part)          \
+    GS_PB1(D, true);      \
+  else                    \
+    GS_PB1(D, false)
   switch (P.deg) {
     case 0: GS_PB(0); break;
     case 1: GS_PB(1); break;
@@ -365,6 +358,7 @@ hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float*
     default: GS_PB(3); break;
   }
 #undef GS_PB
+#undef GS_PB1
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (dL_dpose) {

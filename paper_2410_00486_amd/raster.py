@@ -306,6 +306,48 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, key_bits: int, stream=Non
                                   _stream(stream)))
 
 
+def grad_stats(plan: Plan, ws: torch.Tensor, accum: torch.Tensor, denom: torch.Tensor,
+               stream=None):
+    """Accumulate the densification statistics of the last backward."""
+    _check_ws(plan, ws)
+    for t, name in ((accum, "accum"), (denom, "denom")):
+        _need(t, name)
+        if t.numel() != plan.n:
+            raise ValueError(f"{name} must hold n floats")
+    L.check(L.lib().gs_grad_stats(ctypes.byref(plan.c), _ptr(ws), _ptr(accum), _ptr(denom),
+                                  _stream(stream)))
+
+
+def densify_prune(g: Gaussians, m: Gaussians, v: Gaussians, accum: torch.Tensor,
+                  denom: torch.Tensor, normals: torch.Tensor, tau_p: float = 0.001,
+                  eps_alpha: float = 0.02, percent_dense: float = 0.01, extent: float = 1.0,
+                  capacity: Optional[int] = None, stream=None):
+    """Clone / split / prune; returns (params, m, v) with the new count
+    (one host synchronisation to read it)."""
+    n = g.n
+    cap = 2 * n if capacity is None else int(capacity)
+    if normals.numel() != 6 * n or accum.numel() != n or denom.numel() != n:
+        raise ValueError("accum, denom must hold n floats and normals n x 2 x 3")
+    mk = lambda: Gaussians(*[torch.empty((cap,) + tuple(x.shape[1:]), dtype=torch.float32,
+                                         device=x.device) for x in g.tensors()], g.sh_degree)
+    out, om, ov = mk(), mk(), mk()
+    n_out = torch.zeros(1, dtype=torch.int32, device=g.means.device)
+    tmp = torch.empty(max(int(L.lib().gs_densify_tmp_bytes(n)), 256), dtype=torch.uint8,
+                      device=g.means.device)
+    gc, mc, vc = g.c(), m.grads_c(), v.grads_c()
+    oc, omc, ovc = out.grads_c(), om.grads_c(), ov.grads_c()
+    L.check(L.lib().gs_densify_prune(ctypes.byref(gc), ctypes.byref(mc), ctypes.byref(vc),
+                                     _ptr(accum), _ptr(denom), _ptr(normals), tau_p, eps_alpha,
+                                     percent_dense, extent, ctypes.byref(oc), ctypes.byref(omc),
+                                     ctypes.byref(ovc), cap, _ptr(n_out), _ptr(tmp),
+                                     _stream(stream)))
+    k = int(n_out.item())
+    if k > cap:
+        raise RuntimeError(f"densification needs {k} Gaussians, capacity {cap}")
+    cut = lambda G: Gaussians(*[x[:k].contiguous() for x in G.tensors()], g.sh_degree)
+    return cut(out), cut(om), cut(ov)
+
+
 # ---------------------------------------------------------------- iterations
 
 class Iteration:

@@ -1,0 +1,76 @@
+"""GPU parity of the densification statistics and of densify/prune."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import densify as D
+import paper_2410_00486_amd as gsr
+from synth import scenes
+
+from gpu_common import DEV, flagged_gaussians, run_gpu, t32, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def test_grad_stats_match_oracle():
+    w = workload(1)
+    cam = w.cameras[0]
+    gc, gd = scenes.linear_loss_weights(71, [cam])
+    it = run_gpu(w.scene, [cam], dL_dcolor=gc, dL_ddepth=gd)
+    n = w.scene.n
+    acc = torch.zeros(n, dtype=torch.float32, device=DEV)
+    den = torch.zeros(n, dtype=torch.float32, device=DEV)
+    gsr.grad_stats(it.plan, it.ws, acc, den)
+    gsr.grad_stats(it.plan, it.ws, acc, den)          # accumulates
+    torch.cuda.synchronize()
+    ref = oracle.render(w.scene, cam)
+    g2 = oracle.backward_2d(w.scene, cam, gc[0], gd[0], fwd=ref)
+    vis = ref["pre"]["status"] == 1
+    a, d = D.accumulate_stats(np.zeros(n), np.zeros(n), g2["mean2d"], vis, cam.width, cam.height)
+    a, d = D.accumulate_stats(a, d, g2["mean2d"], vis, cam.width, cam.height)
+    np.testing.assert_array_equal(den.cpu().numpy(), d)
+    ex = flagged_gaussians(ref, (16, 16), cam)
+    got = acc.cpu().numpy().astype(np.float64)
+    rms = np.sqrt(np.mean(a[~ex] ** 2))
+    assert (np.abs(got - a)[~ex] <= 1e-3 * a[~ex] + 1e-3 * rms).all()
+
+
+@pytest.mark.parametrize("n,deg", [(0, 0), (1, 3), (5000, 1), (70_001, 3)])
+def test_densify_prune_matches_oracle(n, deg):
+    rng = np.random.default_rng(n + deg)
+    k = (deg + 1) ** 2
+    P = {"means": rng.normal(size=(n, 3)), "log_scales": rng.normal(-4.0, 1.0, (n, 3)),
+         "quats": rng.normal(size=(n, 4)), "opacity_logits": rng.normal(-2.0, 2.0, n),
+         "sh": rng.normal(size=(n, k, 3))}
+    P = {f: x.astype(np.float32) for f, x in P.items()}
+    M = {f: rng.normal(size=x.shape).astype(np.float32) for f, x in P.items()}
+    V = {f: rng.uniform(size=x.shape).astype(np.float32) for f, x in P.items()}
+    denom = rng.integers(0, 4, n).astype(np.float32)
+    accum = (rng.uniform(0, 0.002, n) * denom).astype(np.float32)
+    normals = rng.standard_normal((n, 2, 3)).astype(np.float32)
+    # keep every decision clear of its threshold (relative 1e-4)
+    o = 1 / (1 + np.exp(-P["opacity_logits"].astype(np.float64)))
+    P["opacity_logits"][np.abs(o - 0.02) < 2e-6] += 0.01
+    ratio = np.where(denom > 0, accum / np.maximum(denom, 1), 0)
+    accum[np.abs(ratio - 0.001) < 1e-7] *= 1.01
+    smax = np.exp(P["log_scales"].max(1).astype(np.float64))
+    P["log_scales"][np.abs(smax - 0.01) < 1e-6] -= 0.01
+    ref, rm, rv = D.densify_prune(P, M, V, accum, denom, normals, 0.001, 0.02, 0.01, 1.0)
+    mk = lambda d: gsr.Gaussians(*[t32(d[f]) for f in gsr.Gaussians.FIELDS], deg) if n else \
+        gsr.Gaussians(*[torch.zeros((0,) + d[f].shape[1:], dtype=torch.float32, device=DEV)
+                        for f in gsr.Gaussians.FIELDS], deg)
+    out, om, ov = gsr.densify_prune(mk(P), mk(M), mk(V), t32(accum), t32(denom),
+                                    t32(normals.reshape(-1)) if n else torch.zeros(0, device=DEV),
+                                    0.001, 0.02, 0.01, 1.0, capacity=2 * n + 1)
+    assert out.n == ref["means"].shape[0]
+    for f in gsr.Gaussians.FIELDS:
+        g = getattr(out, f).cpu().numpy().reshape(ref[f].shape)
+        if f in ("means", "log_scales"):
+            np.testing.assert_allclose(g, ref[f], rtol=2e-7, atol=1e-7)
+        else:
+            np.testing.assert_array_equal(g, ref[f])
+        np.testing.assert_array_equal(getattr(om, f).cpu().numpy().reshape(rm[f].shape), rm[f])
+        np.testing.assert_array_equal(getattr(ov, f).cpu().numpy().reshape(rv[f].shape), rv[f])

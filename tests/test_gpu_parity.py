@@ -146,30 +146,28 @@ def test_backward_matches_oracle(cfg, tile, lds):
     print(f"config {cfg}: excluded {int(exclude.sum())} Gaussians; (max err/tol, rel norm) {rep}")
 
 
-def test_pose_gradient_matches_oracle_and_fd():
+def test_pose_gradient_matches_oracle():
+    """GPU camera tangent vs the oracle at 640x480 / 150k, and on the small
+    scene whose oracle tangent is checked against FP64 central differences
+    in the CPU pins (an FP32 finite difference of a 150k-Gaussian image is not
+    a valid check: the 1/255 skip and the 1e-4 stop make the loss jump)."""
     it, grads, pose_ref, exclude = _bwd_case(3, pose=True)
     assert_grads_close(grads_np(it), grads, exclude)
     got = it.dL_dpose.cpu().numpy().astype(np.float64)[0]
     ref = pose_ref[0]
     assert np.linalg.norm(got - ref) <= 1e-3 * np.linalg.norm(ref), (got, ref)
-    # FP32 directional finite difference of the GPU path itself
-    w = workload(3)
-    cam = w.cameras[0]
-    gc, gd = scenes.linear_loss_weights(103, [cam])
-    rng = np.random.default_rng(5)
-    u = rng.standard_normal(6)
-    u /= np.linalg.norm(u)
-    h = 1e-3
-
-    def loss(xi):
-        c2 = scenes.perturb_camera(cam, xi)
-        r = run_gpu(w.scene, [c2])
-        col, dep, _, _ = view_images(r, 0)
-        return float(np.sum(gc[0] * col) + np.sum(gd[0] * dep))
-
-    fd = (loss(h * u) - loss(-h * u)) / (2 * h)
-    an = float(got @ u)
-    assert abs(fd - an) <= 2e-2 * max(abs(an), 1e-3 * np.linalg.norm(got)), (fd, an)
+    # the FD-pinned small scene (same construction as the CPU pin)
+    w = scenes.tiny_scene(16, n=10, degree=3)
+    rng = np.random.default_rng(17)
+    R, t = scenes.random_pose(rng, 0.05, 0.05)
+    cam = scenes.Camera(32, 24, 30.0, 30.0, 16.0, 12.0, R.astype(np.float32), t.astype(np.float32))
+    gC, gD = scenes.linear_loss_weights(18, [cam])
+    gC, gD = [gC[0] * 100], [gD[0] * 100]
+    it2 = run_gpu(w.scene, [cam], dL_dcolor=gC, dL_ddepth=gD, pose=True)
+    grads2, pose2 = oracle.backward(w.scene, [cam], gC, gD)
+    got2 = it2.dL_dpose.cpu().numpy().astype(np.float64)[0]
+    assert np.linalg.norm(got2 - pose2[0]) <= 1e-3 * np.linalg.norm(pose2[0]), (got2, pose2[0])
+    assert_grads_close(grads_np(it2), grads2)
 
 
 def test_fused_l1_matches_oracle():
