@@ -57,6 +57,10 @@ def main():
     ap.add_argument("--lds-batch", type=int, default=64)
     ap.add_argument("--chunk", type=int, default=1)
     ap.add_argument("--persistent", type=int, default=0, choices=[0, 1])
+    ap.add_argument("--bwd", default="pixel", choices=["pixel", "splat"],
+                    help="backward of the headline: pixel-wise wave-reduced or splat-wise")
+    ap.add_argument("--no-ab", action="store_true",
+                    help="skip timing the other backward variant")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--graph-only", action="store_true",
@@ -114,10 +118,51 @@ def main():
     cap0 = gsr.required_pairs(*params.tensors(), cams, view_wh, 3, tile)
     cap = int(cap0 * 1.5) + 4096
     flags = L.GS_FUSED_L1 | (L.GS_PERSISTENT if best["persistent"] else 0)
-    plan = gsr.Plan(w.scene.n, 3, view_wh, tile=tile, lds_batch=best["lds_batch"],
-                    chunk=best["chunk"], flags=flags, pair_capacity=cap, lambda_depth=0.1)
-    it = gsr.Iteration(plan, params, cams, target_rgb=target_rgb, target_depth=target_depth,
-                       adam_lrs=LRS, lambda_o=0.0)
+    splat_flag = L.GS_SPLAT_BWD if args.bwd == "splat" else 0
+
+    def make_iteration(extra_flags, p):
+        pl = gsr.Plan(w.scene.n, 3, view_wh, tile=tile, lds_batch=best["lds_batch"],
+                      chunk=best["chunk"], flags=flags | extra_flags, pair_capacity=cap,
+                      lambda_depth=0.1)
+        return pl, gsr.Iteration(pl, p, cams, target_rgb=target_rgb, target_depth=target_depth,
+                                 adam_lrs=LRS, lambda_o=0.0)
+
+    # the other backward variant first, on its own copy of the parameters
+    ab = None
+    if not args.no_ab:
+        other = "pixel" if args.bwd == "splat" else "splat"
+        p2 = gsr.Gaussians.from_scene(w.scene, dev)
+        plan2, it2 = make_iteration(L.GS_SPLAT_BWD if other == "splat" else 0, p2)
+        s2 = torch.cuda.Stream()
+        with torch.cuda.stream(s2):
+            it2.capture(s2)
+            for _ in range(args.warmup):
+                it2.replay(s2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(s2):
+            for _ in range(args.steps):
+                it2.replay(s2)
+        torch.cuda.synchronize()
+        ms2 = (time.perf_counter() - t0) * 1e3 / args.steps
+        with torch.cuda.stream(s2):
+            evs = []
+            for _ in range(args.steps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(s2)
+                gsr.render_bwd_raster(plan2, it2.ws, cams, it2.frame, target_rgb=target_rgb,
+                                      target_depth=target_depth, stream=s2)
+                b.record(s2)
+                evs.append((a, b))
+        torch.cuda.synchronize()
+        ab = {other: {"iters_per_s": round(1e3 / ms2, 2),
+                      "render_bwd_ms": round(float(np.mean([a.elapsed_time(b) for a, b in evs])), 4)}}
+        log(f"{other}-wise backward: {ms2:.3f} ms/iter, bwd {ab[other]['render_bwd_ms']} ms")
+        it2.close()
+        del it2, p2
+        torch.cuda.synchronize()
+
+    plan, it = make_iteration(splat_flag, params)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         it.capture(stream)
@@ -208,7 +253,8 @@ def main():
     dominant = max(stage_ms, key=stage_ms.get)
     bwd_tflops = BWD_FLOPS_PER_POS * E_bwd / (stage_ms["render_bwd_raster"] * 1e-3) / 1e12
     if dominant == "render_bwd_raster":
-        roofline = {"bound": "alu", "kernel": "k_render_bwd (gs_render_bwd_raster)",
+        kname = "k_render_bwd_splat" if args.bwd == "splat" else "k_render_bwd"
+        roofline = {"bound": "alu", "kernel": f"{kname} (gs_render_bwd_raster)",
                     "achieved": round(bwd_tflops, 3), "peak": FP32_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(bwd_tflops / FP32_PEAK_TFLOPS, 4),
                     "traffic": None,
@@ -236,7 +282,7 @@ def main():
         "config": {"workload": "config2: 1 view 1200x680 fx=fy=600, 300k Gaussians SH3, "
                                "L1 RGB + 0.1 L1 depth, Adam, HIP graph per iteration",
                    "tile": best["tile"], "lds_batch": best["lds_batch"], "chunk": best["chunk"],
-                   "persistent": bool(best["persistent"])},
+                   "persistent": bool(best["persistent"]), "backward": args.bwd},
         "autotune": sorted(table, key=lambda r: r["ms"])[:6] if table else "defaults (--autotune to search)",
         "plain_eager_iters_per_s": round(1e3 / ms_eager, 2),
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
@@ -247,6 +293,10 @@ def main():
         "stage_gbs": {k: round(bytes_[k] / (stage_ms[k] * 1e-3) / 1e9, 1) for k in stages},
         "roofline": roofline,
     }
+    if ab is not None:
+        ab[args.bwd] = {"iters_per_s": result["value"],
+                        "render_bwd_ms": round(stage_ms["render_bwd_raster"], 4)}
+        result["backward_ab"] = ab
     it.close()
     del it
     torch.cuda.synchronize()

@@ -66,6 +66,11 @@ typedef int32_t gs_status;
 #define GS_ACCUMULATE_GRADS (1u << 2) /* gs_render_bwd adds into the gradient buffers */
 #define GS_PERSISTENT (1u << 3)       /* render kernels pull tile chunks from a device
                                          work queue (longest tiles first) */
+#define GS_SPLAT_BWD (1u << 4)        /* splat-wise backward (Sec. III-C-1, Fig. 4a):
+                                         the forward stores per-pixel (T, RGB, D) states
+                                         at every 64th splat of a tile; the backward
+                                         gives each lane one splat of a 64-splat bucket
+                                         and streams pixel states across the lanes */
 
 /* Gaussian parameters (Sec. III-B): SoA, float32, device pointers. */
 typedef struct gs_gaussians {

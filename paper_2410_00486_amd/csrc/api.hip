@@ -39,6 +39,7 @@ hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, dou
                        int32_t* step_dev, hipStream_t s);
 hipError_t launch_tile_order(const Plan& P, void* ws, hipStream_t s);
 int render_blocks_per_cu(const Plan& P, bool bwd);
+int splat_blocks_per_cu(const Plan& P);
 int64_t ssim_tiles(const Plan& P);
 size_t densify_tmp_bytes(int64_t n);
 hipError_t launch_grad_stats(const Plan& P, void* ws, float* accum, float* denom, hipStream_t s);
@@ -223,6 +224,13 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_order_tmp = take(T * (8 + 8 + 4 + 4) + 256);
   P->off_ssim_maps = take((size_t)pix * 9 * 4);
   P->off_ssim_part = take((size_t)ssim_tiles(*P) * 12 * 4);
+  // splat-wise backward: bucket k of tile t uses checkpoint slot boff[t] + k,
+  // boff the exclusive scan of ceil(pairs of tile / 64); at most
+  // pair_capacity / 64 + tiles slots
+  const bool splat = (cfg->flags & GS_SPLAT_BWD) != 0;
+  P->ckpt_slots = splat ? pair_capacity / kBucket + tiles : 0;
+  P->off_boff = take(splat ? (T + 1) * 4 : 0);
+  P->off_ckpt = take((size_t)P->ckpt_slots * tw * th * kStateFloats * 4);
   P->ws_size = o;
   P->magic = kPlanMagic;
   return GS_OK;
@@ -347,16 +355,19 @@ gs_status gs_render_bwd_raster(const gs_plan* plan, void* ws, const float* cams_
   if (fused && !target_rgb) return fail(GS_ERR_INVALID_ARG, "GS_FUSED_L1 needs target_rgb");
   if (!fused && !dL_dcolor) return fail(GS_ERR_INVALID_ARG, "dL_dcolor is null (and GS_FUSED_L1 not set)");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const bool pers = (P.cfg.flags & GS_PERSISTENT) != 0;
+  const bool splat = (P.cfg.flags & GS_SPLAT_BWD) != 0;
+  const bool pers = !splat && (P.cfg.flags & GS_PERSISTENT) != 0;
   int32_t* fl = ws_at<int32_t>(ws, P.off_flags);
   hipError_t e = hipSuccess;
   if (pers) e = launch_set_i32(fl + F_QUEUE_BWD, 0, s);
+  // splat-wise: grid-stride over the buckets, as many waves as stay resident
+  const int grid = splat ? (int)std::max<int64_t>(1, std::min<int64_t>(P.ckpt_slots, (int64_t)device_cus() * splat_blocks_per_cu(P)))
+                         : (pers ? persistent_grid(P, true) : P.vt.total_tiles);
   if (e == hipSuccess)
     e = launch_render_bwd(P, ws, cams_dev, color, depth, T_final, last, dL_dcolor, dL_ddepth,
                           target_rgb, target_depth, fused ? 1 : 0, sorted_vals(P, ws),
                           pers ? ws_at<uint32_t>(ws, P.off_order) : nullptr,
-                          pers ? fl + F_QUEUE_BWD : nullptr,
-                          pers ? persistent_grid(P, true) : P.vt.total_tiles, s);
+                          pers ? fl + F_QUEUE_BWD : nullptr, grid, s);
   return hip_check(e, "gs_render_bwd_raster");
 }
 

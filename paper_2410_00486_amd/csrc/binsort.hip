@@ -134,6 +134,10 @@ __global__ void __launch_bounds__(256) k_duplicate(
 // ---------------------------------------------------------------- radix sort
 __device__ __forceinline__ int sort_count(const int32_t* cnt) { return *cnt; }
 
+// Up to this many sort blocks (1M keys) the per-digit scan runs inside the
+// downsweep instead of as its own launch.
+constexpr int64_t kFusedScanBlocks = 256;
+
 __global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(const uint64_t* __restrict__ keys,
                                                                 const int32_t* __restrict__ cnt,
                                                                 uint32_t* __restrict__ hist,
@@ -202,6 +206,9 @@ __global__ void __launch_bounds__(256) k_radix_scan(uint32_t* __restrict__ hist,
 // round are found with 8 ballots (one per digit bit); the lowest such lane
 // advances the wave's counter for that digit.  Ranks are thus increasing in
 // index within each digit: the pass is stable.
+// FUSED: the per-digit scan over blocks is done here (each thread sums the
+// counts of its digit over the active blocks), for small block counts.
+template <bool FUSED>
 __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     const uint64_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
@@ -220,7 +227,22 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
   // block's exclusive prefix within the digit
   {
     const int d = threadIdx.x;  // kSortThreads == kRadix
-    const uint32_t x = digit_tot[d];
+    uint32_t x, before;
+    if (FUSED) {
+      const int64_t nb = (P + kSortTile - 1) / kSortTile;
+      const uint32_t* row = hist + (int64_t)d * nb_cap;
+      uint32_t tot = 0, pre = 0;
+      for (int64_t b = 0; b < nb; ++b) {
+        const uint32_t h = row[b];
+        pre += (b < (int64_t)blockIdx.x) ? h : 0u;
+        tot += h;
+      }
+      x = tot;
+      before = pre;
+    } else {
+      x = digit_tot[d];
+      before = hist[(int64_t)d * nb_cap + blockIdx.x];
+    }
     uint32_t incl = x;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
@@ -231,7 +253,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     __syncthreads();
     uint32_t woff = 0;
     for (int k = 0; k < w; ++k) woff += dsum[k];
-    boff[d] = woff + incl - x + hist[(int64_t)d * nb_cap + blockIdx.x];
+    boff[d] = woff + incl - x + before;
   }
   __syncthreads();
 
@@ -330,15 +352,22 @@ hipError_t launch_radix_sort(uint64_t* keys0, uint64_t* keys1, uint32_t* vals0,
   uint32_t* vb[2] = {vals0, vals1};
   const int passes = (key_bits + kRadixBits - 1) / kRadixBits;
   int cur = 0;
+  const bool fused = nb_cap <= kFusedScanBlocks;
   for (int p = 0; p < passes; ++p) {
     const int shift = p * kRadixBits;
     hipLaunchKernelGGL(k_radix_upsweep, dim3((unsigned)nb_cap), dim3(kSortThreads), 0, s,
                        kb[cur], cnt, hist, nb_cap, shift);
-    hipLaunchKernelGGL(k_radix_scan, dim3(kRadix), dim3(256), 0, s, hist, cnt, digit_tot,
-                       nb_cap);
-    hipLaunchKernelGGL(k_radix_downsweep, dim3((unsigned)nb_cap), dim3(kSortThreads), 0, s,
-                       kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], cnt, hist, digit_tot, nb_cap,
-                       shift, (iota && p == 0) ? 1 : 0);
+    if (fused) {
+      hipLaunchKernelGGL(k_radix_downsweep<true>, dim3((unsigned)nb_cap), dim3(kSortThreads), 0, s,
+                         kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], cnt, hist, digit_tot, nb_cap,
+                         shift, (iota && p == 0) ? 1 : 0);
+    } else {
+      hipLaunchKernelGGL(k_radix_scan, dim3(kRadix), dim3(256), 0, s, hist, cnt, digit_tot,
+                         nb_cap);
+      hipLaunchKernelGGL(k_radix_downsweep<false>, dim3((unsigned)nb_cap), dim3(kSortThreads), 0,
+                         s, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], cnt, hist, digit_tot,
+                         nb_cap, shift, (iota && p == 0) ? 1 : 0);
+    }
     cur ^= 1;
   }
   *which = cur;

@@ -82,6 +82,8 @@ struct Plan {
   size_t off_hist, off_digit_tot, off_ranges, off_tile_last, off_tile_loss;
   size_t off_grad_pair, off_pose_part, off_order, off_order_tmp;
   size_t off_ssim_maps, off_ssim_part;
+  size_t off_boff, off_ckpt;  // splat-wise backward: bucket offsets, pixel states
+  int64_t ckpt_slots;
   size_t ws_size;
 };
 static_assert(sizeof(Plan) <= sizeof(gs_plan), "plan does not fit gs_plan");
@@ -107,6 +109,11 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
 constexpr int kProjThreads = 128;
+
+// Splat-wise backward: splats per bucket (one per lane) and the floats of a
+// stored pixel state (T, r, g, b, depth).
+constexpr int kBucket = 64;
+constexpr int kStateFloats = 5;
 
 // ---------------------------------------------------------------------------
 // device helpers

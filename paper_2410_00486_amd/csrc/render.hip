@@ -94,7 +94,7 @@ __device__ __forceinline__ void stage(Rec* srec, uint32_t* sval, const Rec* __re
 }
 
 // ------------------------------------------------------------------ forward
-template <int TW, int TH>
+template <int TW, int TH, bool CKPT>
 __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ rec,
                                          const uint32_t* __restrict__ sorted_rec,
                                          const uint32_t* __restrict__ ranges,
@@ -105,9 +105,12 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ rec,
                                          uint32_t* __restrict__ tile_last,
                                          const float* __restrict__ target_rgb,
                                          const float* __restrict__ target_depth,
-                                         float* __restrict__ tile_loss, Rec* srec) {
+                                         float* __restrict__ tile_loss,
+                                         const uint32_t* __restrict__ boff,
+                                         float* __restrict__ ckpt, Rec* srec) {
   using TG = Tile<TW, TH>;
   constexpr int PPL = TG::PPL;
+  constexpr int NPX = TG::NPX;
   const int v = find_view(vt, gtile);
   const ViewInfo vi = vt.v[v];
   const int lt = gtile - vi.tile_off;
@@ -142,6 +145,22 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ rec,
     stage(srec, nullptr, rec, sorted_rec, nullptr, b, nb, lane);
     __syncthreads();
     for (int j = 0; j < nb; ++j) {
+      if constexpr (CKPT) {
+        // state of every pixel before each 64th splat of the tile list
+        const uint32_t q = b - s + (uint32_t)j;
+        if ((q & (kBucket - 1)) == 0) {
+          float* cp = ckpt + (int64_t)(boff[gtile] + q / kBucket) * (kStateFloats * NPX);
+#pragma unroll
+          for (int k = 0; k < PPL; ++k) {
+            const int jj = TG::y(lane, k) * TW + TG::x(lane, k);
+            cp[jj] = T[k];
+            cp[NPX + jj] = c0[k];
+            cp[2 * NPX + jj] = c1[k];
+            cp[3 * NPX + jj] = c2[k];
+            cp[4 * NPX + jj] = D[k];
+          }
+        }
+      }
       const Rec& r = srec[j];
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
@@ -207,7 +226,7 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ rec,
   }
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool CKPT>
 __global__ void __launch_bounds__(kWave) k_render_fwd(
     const Rec* __restrict__ rec, const uint32_t* __restrict__ sorted_rec,
     const uint32_t* __restrict__ ranges, const float* __restrict__ cams, ViewTable vt, int B,
@@ -215,13 +234,14 @@ __global__ void __launch_bounds__(kWave) k_render_fwd(
     uint32_t* __restrict__ last, uint32_t* __restrict__ tile_last,
     const float* __restrict__ target_rgb, const float* __restrict__ target_depth,
     float* __restrict__ tile_loss, const uint32_t* __restrict__ order,
-    int32_t* __restrict__ queue, int chunk) {
+    int32_t* __restrict__ queue, int chunk, const uint32_t* __restrict__ boff,
+    float* __restrict__ ckpt) {
   extern __shared__ __align__(16) unsigned char smem[];
   Rec* srec = reinterpret_cast<Rec*>(smem);
   if (queue == nullptr) {
     const int g = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
-    fwd_tile<TW, TH>(g, rec, sorted_rec, ranges, cams, vt, B, color, depth, T_final, last,
-                     tile_last, target_rgb, target_depth, tile_loss, srec);
+    fwd_tile<TW, TH, CKPT>(g, rec, sorted_rec, ranges, cams, vt, B, color, depth, T_final, last,
+                           tile_last, target_rgb, target_depth, tile_loss, boff, ckpt, srec);
     return;
   }
   // persistent: pull chunks of `chunk` tiles until the queue is drained
@@ -235,8 +255,9 @@ __global__ void __launch_bounds__(kWave) k_render_fwd(
     const int lastt = min(vt.total_tiles, first + chunk);
     for (int k = first; k < lastt; ++k) {
       const int g = order ? (int)order[k] : k;
-      fwd_tile<TW, TH>(g, rec, sorted_rec, ranges, cams, vt, B, color, depth, T_final, last,
-                       tile_last, target_rgb, target_depth, tile_loss, srec);
+      fwd_tile<TW, TH, CKPT>(g, rec, sorted_rec, ranges, cams, vt, B, color, depth, T_final,
+                             last, tile_last, target_rgb, target_depth, tile_loss, boff, ckpt,
+                             srec);
     }
   }
 }
@@ -450,6 +471,241 @@ __global__ void __launch_bounds__(kWave) k_render_bwd(
   }
 }
 
+// ----------------------------------------------------- splat-wise backward
+// Sec. III-C-1 / Fig. 4a mapped to wave64.  The tile list is cut into
+// buckets of 64 consecutive splats; one wavefront takes a bucket and lane l
+// owns its l-th splat.  The forward stored each pixel's state X = (T, RGB,
+// D) before every 64th splat, so a bucket starts from stored states and
+// needs nothing from the other buckets of its tile: buckets are the unit of
+// parallelism, which also splits long tile lists over many wavefronts.
+//
+// Pixel states move along a diagonal: at step t lane l applies its splat to
+// pixel j = t - l and hands the new state to lane l + 1 (DPP wave shift
+// right by one lane); lane 0 takes pixel t's stored state.  Lane l thus
+// meets every pixel with the state left by the splats in front of its own,
+// evaluates alpha with the forward's code and blends forward exactly as the
+// forward did (T * (1 - alpha), bit for bit).  What lies behind the splat is
+// the final pixel minus the front part: with per-pixel loss gradients gC, gD
+// the state carries Q = gC . C + gD . D, and behind = P - Q_next where
+// P = gC . (colour output) + gD . (depth output).  Each lane accumulates its
+// own splat's ten partial gradients over the tile's pixels and writes them
+// once: no reduction over lanes and no atomics.
+
+// Exclusive scan of buckets per tile (ceil(pairs / 64)); boff[T] = total.
+__global__ void __launch_bounds__(1024) k_bucket_scan(const uint32_t* __restrict__ ranges, int T,
+                                                      uint32_t* __restrict__ boff) {
+  __shared__ uint32_t wsum[1024 / kWave];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  for (int base = 0; base < T; base += 1024) {
+    const int t = base + (int)threadIdx.x;
+    const uint32_t x =
+        t < T ? (ranges[2 * (int64_t)t + 1] - ranges[2 * (int64_t)t] + kBucket - 1) / kBucket : 0u;
+    uint32_t incl = x;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, kWave);
+      if (lane >= o) incl += y;
+    }
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    uint32_t woff = carry;
+    for (int k = 0; k < w; ++k) woff += wsum[k];
+    if (t < T) boff[t] = woff + incl - x;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = woff + incl;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) boff[T] = carry;
+}
+
+template <int TW, int TH>
+__device__ __forceinline__ void splat_bucket(
+    int gtile, uint32_t k, const Rec* __restrict__ rec, const uint32_t* __restrict__ sorted_rec,
+    const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
+    const uint32_t* __restrict__ tile_last, const uint32_t* __restrict__ boff,
+    const float* __restrict__ ckpt, const float* __restrict__ cams, const ViewTable& vt,
+    const float* __restrict__ color, const float* __restrict__ depth,
+    const uint32_t* __restrict__ last, const float* __restrict__ dL_dcolor,
+    const float* __restrict__ dL_ddepth, const float* __restrict__ target_rgb,
+    const float* __restrict__ target_depth, int fused, float lambda_depth,
+    float* __restrict__ grad_pair, float4* pxa, float4* pxb) {
+  constexpr int NPX = TW * TH;
+  constexpr int LOG_TW = TW == 16 ? 4 : 3;
+  const int lane = threadIdx.x;
+  const uint32_t s = ranges[2 * (int64_t)gtile], e = ranges[2 * (int64_t)gtile + 1];
+  const uint32_t tl = tile_last[gtile];
+  const uint32_t q0 = k * kBucket;
+  const uint32_t pos = q0 + (uint32_t)lane;
+  const bool live = pos < tl;
+  if (pos < e - s && !live) {  // pairs behind the last used position: zero gradient
+    float4* gp = reinterpret_cast<float4*>(grad_pair + (int64_t)sorted_vals[s + pos] * kPairGrad);
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    gp[0] = z; gp[1] = z; gp[2] = z;
+  }
+  if (q0 >= tl) return;  // uniform: the whole bucket lies behind
+  const int nl = (int)min((uint32_t)kBucket, tl - q0);
+
+  const int v = find_view(vt, gtile);
+  const ViewInfo vi = vt.v[v];
+  const int lt = gtile - vi.tile_off;
+  const int tx0 = (lt % vi.tiles_x) * TW, ty0 = (lt / vi.tiles_x) * TH;
+  const int64_t npx = (int64_t)vi.W * vi.H;
+  const float* cp = ckpt + (int64_t)(boff[gtile] + k) * (kStateFloats * NPX);
+
+  // pixel table: loss gradients, P, last position, stored state (T, Q)
+  for (int j = lane; j < NPX; j += kWave) {
+    const int px = tx0 + (j & (TW - 1)), py = ty0 + (j >> LOG_TW);
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 1.f, 0.f);
+    if (px < vi.W && py < vi.H) {
+      const int64_t pl = (int64_t)py * vi.W + px;
+      const int64_t pix = (int64_t)vi.pix_off + pl;
+      const int64_t cbase = 3 * (int64_t)vi.pix_off + pl;
+      const float o0 = color[cbase], o1 = color[cbase + npx], o2 = color[cbase + 2 * npx];
+      const float od = depth[pix];
+      if (fused) {
+        const float inv3 = 1.0f / (3.0f * (float)npx);
+        const float d0 = o0 - target_rgb[cbase];
+        const float d1 = o1 - target_rgb[cbase + npx];
+        const float d2 = o2 - target_rgb[cbase + 2 * npx];
+        a.x = d0 > 0.0f ? inv3 : (d0 < 0.0f ? -inv3 : 0.0f);
+        a.y = d1 > 0.0f ? inv3 : (d1 < 0.0f ? -inv3 : 0.0f);
+        a.z = d2 > 0.0f ? inv3 : (d2 < 0.0f ? -inv3 : 0.0f);
+        if (target_depth) {
+          const float dd = od - target_depth[pix];
+          const float sc = lambda_depth / (float)npx;
+          a.w = dd > 0.0f ? sc : (dd < 0.0f ? -sc : 0.0f);
+        }
+      } else {
+        a.x = dL_dcolor[cbase];
+        a.y = dL_dcolor[cbase + npx];
+        a.z = dL_dcolor[cbase + 2 * npx];
+        a.w = dL_ddepth ? dL_ddepth[pix] : 0.0f;
+      }
+      b.x = a.x * o0 + a.y * o1 + a.z * o2 + a.w * od;
+      b.y = __uint_as_float(last[pix]);
+      b.z = cp[j];
+      b.w = a.x * cp[NPX + j] + a.y * cp[2 * NPX + j] + a.z * cp[3 * NPX + j] + a.w * cp[4 * NPX + j];
+    }
+    pxa[j] = a;
+    pxb[j] = b;
+  }
+  __syncthreads();
+
+  Rec r;
+  if (live) {
+    const float4* src = reinterpret_cast<const float4*>(rec + sorted_rec[s + pos]);
+    float4* dst = reinterpret_cast<float4*>(&r);
+    dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2]; dst[3] = src[3];
+  } else {
+    r.mx = r.my = 0.0; r.ca = r.cb = r.cc = 0.0;
+    r.o = r.z = r.r = r.g = r.b = 0.0f;
+    r.clamp = 0u;
+  }
+  const float ca = (float)(-2.0 * r.ca), cb = (float)(-r.cb), cc = (float)(-2.0 * r.cc);
+  float g[10];
+#pragma unroll
+  for (int f = 0; f < 10; ++f) g[f] = 0.0f;
+  float Tout = 1.0f, Qout = 0.0f;
+  const int steps = NPX + nl - 1;
+  for (int t = 0; t < steps; ++t) {
+    float Tc = dpp<0x138>(Tout);  // wave_shr:1, state of lane - 1
+    float Qc = dpp<0x138>(Qout);
+    const int j = t - lane;
+    const bool vj = (unsigned)j < (unsigned)NPX;
+    const int jc = vj ? j : 0;
+    const float4 b = pxb[jc];
+    if (lane == 0) {
+      Tc = b.z;
+      Qc = b.w;
+    }
+    if (vj && live && pos < __float_as_uint(b.y)) {
+      const double sx = (double)(tx0 + (jc & (TW - 1))) + 0.5;
+      const double sy = (double)(ty0 + (jc >> LOG_TW)) + 0.5;
+      double dx, dy;
+      float G, oG, a;
+      if (eval_alpha(r, sx, sy, dx, dy, G, oG, a)) {
+        const float4 gc = pxa[jc];
+        const float inv_om = __builtin_amdgcn_rcpf(1.0f - a);
+        const float wgt = a * Tc;
+        const float front = gc.x * r.r + gc.y * r.g + gc.z * r.b + gc.w * r.z;
+        const float Qn = fmaf(wgt, front, Qc);
+        const float g_alpha = Tc * front - (b.x - Qn) * inv_om;
+        g[0] = fmaf(wgt, gc.x, g[0]);
+        g[1] = fmaf(wgt, gc.y, g[1]);
+        g[2] = fmaf(wgt, gc.z, g[2]);
+        g[3] = fmaf(wgt, gc.w, g[3]);
+        if (oG <= kAlphaMax) {
+          const float gpow = a * g_alpha;
+          const float fx = (float)dx, fy = (float)dy;
+          g[4] = fmaf(G, g_alpha, g[4]);
+          g[5] -= 0.5f * gpow * fx * fx;
+          g[6] -= gpow * fx * fy;
+          g[7] -= 0.5f * gpow * fy * fy;
+          g[8] -= gpow * (ca * fx + cb * fy);
+          g[9] -= gpow * (cb * fx + cc * fy);
+        }
+        Tc = Tc * (1.0f - a);
+        Qc = Qn;
+      }
+    }
+    Tout = Tc;
+    Qout = Qc;
+  }
+  if (live) {
+    float4* gp = reinterpret_cast<float4*>(grad_pair + (int64_t)sorted_vals[s + pos] * kPairGrad);
+    gp[0] = make_float4(g[0], g[1], g[2], g[3]);
+    gp[1] = make_float4(g[4], g[5], g[6], g[7]);
+    gp[2] = make_float4(g[8], g[9], 0.0f, 0.0f);
+  }
+  __syncthreads();  // the pixel table is rewritten by the next bucket
+}
+
+// Buckets are taken grid-stride; bucket b belongs to the last tile t with
+// boff[t] <= b (tiles without pairs have no buckets).
+template <int TW, int TH>
+__global__ void __launch_bounds__(kWave) k_render_bwd_splat(
+    const Rec* __restrict__ rec, const uint32_t* __restrict__ sorted_rec,
+    const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
+    const uint32_t* __restrict__ tile_last, const uint32_t* __restrict__ boff,
+    const float* __restrict__ ckpt, const float* __restrict__ cams, ViewTable vt,
+    const float* __restrict__ color, const float* __restrict__ depth,
+    const uint32_t* __restrict__ last, const float* __restrict__ dL_dcolor,
+    const float* __restrict__ dL_ddepth, const float* __restrict__ target_rgb,
+    const float* __restrict__ target_depth, int fused, float lambda_depth,
+    float* __restrict__ grad_pair) {
+  __shared__ float4 pxa[TW * TH], pxb[TW * TH];
+  const int T = vt.total_tiles;
+  const uint32_t nbk = boff[T];
+  for (uint32_t bk = blockIdx.x; bk < nbk; bk += gridDim.x) {
+    int lo = 0, hi = T - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (boff[mid] <= bk) lo = mid; else hi = mid - 1;
+    }
+    splat_bucket<TW, TH>(lo, bk - boff[lo], rec, sorted_rec, sorted_vals, ranges, tile_last, boff,
+                         ckpt, cams, vt, color, depth, last, dL_dcolor, dL_ddepth, target_rgb,
+                         target_depth, fused, lambda_depth, grad_pair, pxa, pxb);
+  }
+}
+
+template <int TW, int TH>
+hipError_t bwd_splat_launch(const Plan& P, void* ws, const float* cams, const float* color,
+                            const float* depth, const uint32_t* last, const float* dL_dcolor,
+                            const float* dL_ddepth, const float* target_rgb,
+                            const float* target_depth, int fused, const uint32_t* sorted_vals,
+                            int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_render_bwd_splat<TW, TH>), dim3(grid), dim3(kWave), 0, s,
+                     ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_sorted_rec), sorted_vals,
+                     ws_at<uint32_t>(ws, P.off_ranges), ws_at<uint32_t>(ws, P.off_tile_last),
+                     ws_at<uint32_t>(ws, P.off_boff), ws_at<float>(ws, P.off_ckpt), cams, P.vt,
+                     color, depth, last, dL_dcolor, dL_ddepth, target_rgb, target_depth, fused,
+                     P.cfg.lambda_depth, ws_at<float>(ws, P.off_grad_pair));
+  return hipGetLastError();
+}
+
 template <int TW, int TH>
 hipError_t fwd_launch(const Plan& P, void* ws, const float* cams, float* color, float* depth,
                       float* T_final, uint32_t* last, const float* target_rgb,
@@ -457,11 +713,24 @@ hipError_t fwd_launch(const Plan& P, void* ws, const float* cams, float* color, 
                       int grid, hipStream_t s) {
   const int B = P.cfg.lds_batch;
   const size_t lds = (size_t)B * sizeof(Rec);
-  hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3(grid), dim3(kWave), lds, s,
-                     ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_sorted_rec),
-                     ws_at<uint32_t>(ws, P.off_ranges), cams, P.vt, B, color, depth, T_final,
-                     last, ws_at<uint32_t>(ws, P.off_tile_last), target_rgb, target_depth,
-                     ws_at<float>(ws, P.off_tile_loss), order, queue, P.cfg.chunk);
+  if (P.cfg.flags & GS_SPLAT_BWD) {
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s,
+                       ws_at<uint32_t>(ws, P.off_ranges), P.vt.total_tiles,
+                       ws_at<uint32_t>(ws, P.off_boff));
+    hipLaunchKernelGGL((k_render_fwd<TW, TH, true>), dim3(grid), dim3(kWave), lds, s,
+                       ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_sorted_rec),
+                       ws_at<uint32_t>(ws, P.off_ranges), cams, P.vt, B, color, depth, T_final,
+                       last, ws_at<uint32_t>(ws, P.off_tile_last), target_rgb, target_depth,
+                       ws_at<float>(ws, P.off_tile_loss), order, queue, P.cfg.chunk,
+                       ws_at<uint32_t>(ws, P.off_boff), ws_at<float>(ws, P.off_ckpt));
+  } else {
+    hipLaunchKernelGGL((k_render_fwd<TW, TH, false>), dim3(grid), dim3(kWave), lds, s,
+                       ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_sorted_rec),
+                       ws_at<uint32_t>(ws, P.off_ranges), cams, P.vt, B, color, depth, T_final,
+                       last, ws_at<uint32_t>(ws, P.off_tile_last), target_rgb, target_depth,
+                       ws_at<float>(ws, P.off_tile_loss), order, queue, P.cfg.chunk,
+                       nullptr, nullptr);
+  }
   return hipGetLastError();
 }
 
@@ -497,9 +766,17 @@ int render_blocks_per_cu(const Plan& P, bool bwd) {
   const int B = P.cfg.lds_batch;
   const size_t lf = (size_t)B * sizeof(Rec), lb = (size_t)B * (sizeof(Rec) + sizeof(uint32_t));
   const int tw = P.cfg.tile_w, th = P.cfg.tile_h;
-  if (tw == 16 && th == 16) return bwd ? occupancy(k_render_bwd<16, 16>, lb) : occupancy(k_render_fwd<16, 16>, lf);
-  if (tw == 16 && th == 8) return bwd ? occupancy(k_render_bwd<16, 8>, lb) : occupancy(k_render_fwd<16, 8>, lf);
-  return bwd ? occupancy(k_render_bwd<8, 8>, lb) : occupancy(k_render_fwd<8, 8>, lf);
+  if (tw == 16 && th == 16) return bwd ? occupancy(k_render_bwd<16, 16>, lb) : occupancy(k_render_fwd<16, 16, false>, lf);
+  if (tw == 16 && th == 8) return bwd ? occupancy(k_render_bwd<16, 8>, lb) : occupancy(k_render_fwd<16, 8, false>, lf);
+  return bwd ? occupancy(k_render_bwd<8, 8>, lb) : occupancy(k_render_fwd<8, 8, false>, lf);
+}
+
+// Resident workgroups per CU of the splat-wise backward.
+int splat_blocks_per_cu(const Plan& P) {
+  const int tw = P.cfg.tile_w, th = P.cfg.tile_h;
+  if (tw == 16 && th == 16) return occupancy(k_render_bwd_splat<16, 16>, 0);
+  if (tw == 16 && th == 8) return occupancy(k_render_bwd_splat<16, 8>, 0);
+  return occupancy(k_render_bwd_splat<8, 8>, 0);
 }
 
 hipError_t launch_render_fwd(const Plan& P, void* ws, const float* cams, float* color,
@@ -534,6 +811,13 @@ hipError_t launch_render_bwd(const Plan& P, void* ws, const float* cams, const f
                              int grid, hipStream_t s) {
   if (P.vt.total_tiles == 0) return hipSuccess;
   const int tw = P.cfg.tile_w, th = P.cfg.tile_h;
+  if (P.cfg.flags & GS_SPLAT_BWD) {
+    if (tw == 16 && th == 16)
+      return bwd_splat_launch<16, 16>(P, ws, cams, color, depth, last, dL_dcolor, dL_ddepth, target_rgb, target_depth, fused, sorted_vals, grid, s);
+    if (tw == 16 && th == 8)
+      return bwd_splat_launch<16, 8>(P, ws, cams, color, depth, last, dL_dcolor, dL_ddepth, target_rgb, target_depth, fused, sorted_vals, grid, s);
+    return bwd_splat_launch<8, 8>(P, ws, cams, color, depth, last, dL_dcolor, dL_ddepth, target_rgb, target_depth, fused, sorted_vals, grid, s);
+  }
   if (tw == 16 && th == 16)
     return bwd_launch<16, 16>(P, ws, cams, color, depth, T_final, last, dL_dcolor, dL_ddepth, target_rgb, target_depth, fused, sorted_vals, order, queue, grid, s);
   if (tw == 16 && th == 8)

@@ -59,7 +59,7 @@ def test_preprocess_records_match_oracle(cfg):
 # ------------------------------------------------------------------ sort
 
 @pytest.mark.parametrize("n,bits", [(1, 40), (17, 38), (4096, 44), (4097, 44), (100_003, 48),
-                                    (1_000_000, 52), (65_536, 64)])
+                                    (1_000_000, 52), (65_536, 64), (1_500_007, 46)])
 def test_sort_pairs_bit_exact(n, bits):
     keys, vals = scenes.random_keys(n, n, max(1, bits - 32))
     if bits == 64:
@@ -124,12 +124,13 @@ def test_forward_tile_shapes_identical():
 
 # ------------------------------------------------------------------ backward
 
-def _bwd_case(cfg, tile=(16, 16), lds=256, pose=False):
+def _bwd_case(cfg, tile=(16, 16), lds=256, pose=False, flags=0):
     w = workload(cfg)
     cam = w.cameras[0]
     gc, gd = scenes.linear_loss_weights(100 + cfg, [cam])
-    print(f"backward parity config {cfg} tile {tile} lds {lds}", flush=True)
-    it = run_gpu(w.scene, [cam], tile=tile, lds=lds, dL_dcolor=gc, dL_ddepth=gd, pose=pose)
+    print(f"backward parity config {cfg} tile {tile} lds {lds} flags {flags}", flush=True)
+    it = run_gpu(w.scene, [cam], tile=tile, lds=lds, dL_dcolor=gc, dL_ddepth=gd, pose=pose,
+                 flags=flags)
     ref = oracle.render(w.scene, cam, tile)
     exclude = flagged_gaussians(ref, tile, cam)
     grads, pose_ref = oracle.backward(w.scene, cam, gc[0], gd[0], tile)
@@ -144,6 +145,39 @@ def test_backward_matches_oracle(cfg, tile, lds):
     assert exclude.sum() < 0.15 * visible
     rep = assert_grads_close(grads_np(it), grads, exclude)
     print(f"config {cfg}: excluded {int(exclude.sum())} Gaussians; (max err/tol, rel norm) {rep}")
+
+
+@pytest.mark.parametrize("cfg,tile,lds", [(1, (16, 16), 256), (1, (8, 8), 32), (1, (16, 8), 96),
+                                          (3, (16, 16), 128), (2, (8, 8), 64), (2, (16, 16), 256)])
+def test_splat_backward_matches_oracle(cfg, tile, lds):
+    """Splat-wise backward (buckets of 64 splats, stored pixel states) against
+    the oracle; its forward (which also stores the states) must equal the
+    plain forward bit for bit."""
+    it, grads, _, exclude = _bwd_case(cfg, tile, lds, flags=L.GS_SPLAT_BWD)
+    w = workload(cfg)
+    visible = (oracle.preprocess(w.scene, w.cameras[0], tile)["status"] == 1).sum()
+    assert exclude.sum() < 0.15 * visible
+    rep = assert_grads_close(grads_np(it), grads, exclude)
+    print(f"config {cfg}: excluded {int(exclude.sum())} Gaussians; (max err/tol, rel norm) {rep}")
+    plain = run_gpu(w.scene, [w.cameras[0]], tile=tile, lds=lds)
+    for k in range(4):
+        np.testing.assert_array_equal(view_images(it, 0)[k], view_images(plain, 0)[k])
+
+
+def test_splat_backward_multi_view_and_pose():
+    scene, cams = _multi_view_workload()
+    gcs, gds = scenes.linear_loss_weights(47, cams)
+    print("splat-wise backward, 4 views, pose", flush=True)
+    it = run_gpu(scene, cams, dL_dcolor=gcs, dL_ddepth=gds, pose=True,
+                 flags=L.GS_SPLAT_BWD | L.GS_PERSISTENT)
+    exclude = np.zeros(scene.n, bool)
+    for cam in cams:
+        exclude |= flagged_gaussians(oracle.render(scene, cam), (16, 16), cam)
+    grads, poses = oracle.backward(scene, list(cams), gcs, gds)
+    assert_grads_close(grads_np(it), grads, exclude)
+    got = it.dL_dpose.cpu().numpy()
+    for v in range(len(cams)):
+        assert np.linalg.norm(got[v] - poses[v]) <= 1e-3 * np.linalg.norm(poses[v])
 
 
 def test_pose_gradient_matches_oracle():
@@ -281,7 +315,8 @@ def test_persistent_equals_plain():
         np.testing.assert_array_equal(ga[k], gb[k])
 
 
-def test_graph_replay_equals_eager():
+@pytest.mark.parametrize("flags", [L.GS_FUSED_L1, L.GS_FUSED_L1 | L.GS_SPLAT_BWD])
+def test_graph_replay_equals_eager(flags):
     w = workload(1)
     cam = w.cameras[0]
     lrs = {"means": 1e-3, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
@@ -289,7 +324,7 @@ def test_graph_replay_equals_eager():
 
     def make():
         g = gsr.Gaussians.from_scene(w.scene, DEV)
-        plan = gsr.Plan(w.scene.n, 0, [(cam.width, cam.height)], flags=L.GS_FUSED_L1,
+        plan = gsr.Plan(w.scene.n, 0, [(cam.width, cam.height)], flags=flags,
                         pair_capacity=1 << 16)
         return gsr.Iteration(plan, g, gsr.cameras_tensor([cam], DEV), target_rgb=tgt,
                              adam_lrs=lrs, lambda_o=0.001)
