@@ -19,6 +19,7 @@ hipError_t launch_radix_sort(uint64_t* keys0, uint64_t* keys1, uint32_t* vals0, 
                              const int32_t* cnt, uint32_t* hist, uint32_t* digit_tot,
                              int64_t nb_cap, int key_bits, bool iota, int* which, hipStream_t s);
 hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t s);
+hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s);
 uint32_t* sorted_vals(const Plan& P, void* ws);
 hipError_t launch_render_fwd(const Plan& P, void* ws, const float* cams, float* color,
                              float* depth, float* T_final, uint32_t* last,
@@ -186,13 +187,10 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   vt.total_tiles = (int32_t)tiles;
   vt.total_pix = pix;
   P->tile_bits = std::max(1, ceil_log2(tiles));
-  P->key_bits = 32 + P->tile_bits;
-  P->sort_passes = (P->key_bits + kRadixBits - 1) / kRadixBits;
   P->scan_blocks = (P->n_rec + kScanTile - 1) / kScanTile;
-  P->sort_blocks_cap = (pair_capacity + kSortTile - 1) / kSortTile;
+  P->tile_scan_blocks = (tiles + kScanTile - 1) / kScanTile;
   P->proj_blocks = (n + kProjThreads - 1) / kProjThreads;
   const int64_t order_blocks = (tiles + kSortTile - 1) / kSortTile;
-  const int64_t hist_blocks = std::max(P->sort_blocks_cap, order_blocks);
 
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -207,13 +205,15 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_tt = take(nrec * 4);
   P->off_poff = take(nrec * 4);
   P->off_scan = take((size_t)std::max<int64_t>(P->scan_blocks, 1) * 8);
-  P->off_keys0 = take(cap * 8);
-  P->off_keys1 = take(cap * 8);
-  P->off_vals0 = take(cap * 4);
-  P->off_vals1 = take(cap * 4);
+  P->off_tile_cnt = take(T * 4);
+  P->off_tile_start = take(T * 4);
+  P->off_tile_scan = take((size_t)std::max<int64_t>(P->tile_scan_blocks, 1) * 8);
+  P->off_keys = take(cap * 8);
+  P->off_scatter = take(cap * 8);
+  P->off_vals = take(cap * 4);
   P->off_pair_rec = take(cap * 4);
   P->off_sorted_rec = take(cap * 4);
-  P->off_hist = take((size_t)kRadix * hist_blocks * 4);
+  P->off_hist = take((size_t)kRadix * std::max<int64_t>(order_blocks, 1) * 4);
   P->off_digit_tot = take(kRadix * 4);
   P->off_ranges = take(T * 2 * 4);
   P->off_tile_last = take(T * 4);
@@ -261,14 +261,13 @@ int64_t gs_plan_total_tiles(const gs_plan* plan) {
 int64_t gs_plan_ws_offset(const gs_plan* plan, int32_t region) {
   if (check_plan(plan) != GS_OK) return -1;
   const Plan& P = *plan_of(plan);
-  const int passes = P.sort_passes;
   switch (region) {
     case GS_WS_RECORDS: return (int64_t)P.off_rec;
     case GS_WS_RECTS: return (int64_t)P.off_rect;
     case GS_WS_TILES_TOUCHED: return (int64_t)P.off_tt;
     case GS_WS_PAIR_OFFSETS: return (int64_t)P.off_poff;
-    case GS_WS_SORTED_KEYS: return (int64_t)((passes & 1) ? P.off_keys1 : P.off_keys0);
-    case GS_WS_SORTED_VALS: return (int64_t)((passes & 1) ? P.off_vals1 : P.off_vals0);
+    case GS_WS_SORTED_KEYS: return (int64_t)P.off_keys;
+    case GS_WS_SORTED_VALS: return (int64_t)P.off_vals;
     case GS_WS_SORTED_RECS: return (int64_t)P.off_sorted_rec;
     case GS_WS_RANGES: return (int64_t)P.off_ranges;
     default: return -1;
@@ -289,9 +288,9 @@ gs_status gs_preprocess(const gs_plan* plan, const gs_gaussians* g, const float*
   if ((st = check_gaussians(P, g)) != GS_OK) return st;
   if (!cams_dev) return fail(GS_ERR_INVALID_ARG, "cams_dev is null");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  int32_t* fl = ws_at<int32_t>(ws, P.off_flags);
-  // flags 0..3 are per-iteration: clear them with a kernel (graph-safe)
-  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(fl), 0u, 4, s);
+  // flags 0..3 and the per-tile pair counts are per-iteration: clear them
+  // with a kernel (graph-safe)
+  hipError_t e = launch_clear_counters(P, ws, s);
   if (e == hipSuccess) e = launch_preprocess(P, *g, cams_dev, ws, s);
   return hip_check(e, "gs_preprocess");
 }

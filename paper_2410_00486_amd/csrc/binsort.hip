@@ -1,17 +1,20 @@
 // a2: tile binning.  Pairs are the (Gaussian, tile) incidences of the exact
-// tile boxes; their keys are (global tile id << 32 | float32 bits of depth)
-// and their values the pair's index in generation order (Gaussian-major,
-// row-major tiles).  A stable LSD radix sort (8-bit digits, only the key
-// bits in use) therefore orders pairs by (tile, depth, Gaussian): the order
-// is unique and the result bit-exact.  Per-tile [start, end) ranges and the
-// record index of every sorted pair follow.
+// tile boxes, numbered in generation order (record-major, row-major tiles
+// within a box).  The order the renderer needs is (tile, depth, generation
+// index): unique, so the result is bit-exact whatever the schedule.
 //
-// Sort structure per digit pass (no spin-waits, no inter-block
-// dependencies inside a kernel): upsweep (per-block digit histogram),
-// per-digit scan over blocks, downsweep (stable in-block ranking with
-// wave64 ballots, scatter).  Pair counts live on the device, so the grid is
-// sized for the plan's capacity and blocks past the count exit at once; the
-// whole sequence is graph-capturable.
+// The projection counts pairs per tile as it computes the boxes.  Then:
+// exclusive scans of the per-record pair counts (generation offsets) and of
+// the per-tile counts (tile list starts), one scatter that puts every pair
+// into its tile's list at an atomically taken slot with the key
+// (depth bits << 32 | generation index), and a per-tile sort of those keys
+// (one wavefront per tile: a bitonic network in LDS for lists up to 2048,
+// an LSD radix sort through global memory beyond).  Five launches whatever
+// the pair count, no spin-waits; graph-capturable.
+//
+// The general stable LSD radix sort (8-bit digits, wave64 ballot ranking)
+// below serves the standalone key/value sort and the longest-first tile
+// order of the persistent render kernels.
 #include "gs_internal.h"
 
 namespace gs {
@@ -24,13 +27,22 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t cou
 
 __global__ void k_set_i32(int32_t* __restrict__ p, int32_t value) { *p = value; }
 
-// ---------------------------------------------------------------- record scan
-// Block-local exclusive scan of tiles_touched; block totals to scan_tmp.
+__global__ void k_fill2_u32(uint32_t* __restrict__ a, int64_t na, uint32_t* __restrict__ b,
+                            int64_t nb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < na) a[i] = 0u;
+  if (i < nb) b[i] = 0u;
+}
+
+// ---------------------------------------------------------------- scans
+// Block-local exclusive scan of u32 counts; block totals to block_tot.
 // Sums are 64-bit: a local offset is stored as u32, which is exact whenever
 // the total fits the pair capacity (< 2^31); otherwise the overflow flag
-// stops every consumer.
-__global__ void __launch_bounds__(kScanThreads) k_scan_local(const uint32_t* __restrict__ tt,
-                                                             uint32_t* __restrict__ poff,
+// stops every consumer.  ZERO: the counts are cleared after reading (the
+// tile counters become the scatter's cursors).
+template <bool ZERO>
+__global__ void __launch_bounds__(kScanThreads) k_scan_local(uint32_t* __restrict__ cnt,
+                                                             uint32_t* __restrict__ off,
                                                              uint64_t* __restrict__ block_tot,
                                                              int64_t n) {
   __shared__ uint64_t wsum[kScanThreads / kWave];
@@ -40,7 +52,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_local(const uint32_t* __r
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t idx = base + k;
-    v[k] = idx < n ? tt[idx] : 0u;
+    v[k] = idx < n ? cnt[idx] : 0u;
     s += v[k];
   }
   const int lane = lane_id(), w = threadIdx.x / kWave;
@@ -58,25 +70,25 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_local(const uint32_t* __r
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t idx = base + k;
-    if (idx < n) poff[idx] = (uint32_t)run;
+    if (idx < n) {
+      off[idx] = (uint32_t)run;
+      if (ZERO) cnt[idx] = 0u;
+    }
     run += v[k];
   }
   if (threadIdx.x == kScanThreads - 1) block_tot[blockIdx.x] = run;
 }
 
-// Exclusive scan of the block totals (one block), total pair count and the
-// capacity check.
-__global__ void __launch_bounds__(1024) k_scan_totals(uint64_t* __restrict__ block_tot,
-                                                      int64_t nblocks, int64_t cap,
-                                                      int32_t* __restrict__ fl) {
-  __shared__ uint64_t wsum[1024 / kWave];
-  __shared__ uint64_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
+// In-place exclusive scan of n u64 values by one 1024-thread block; returns
+// the total in every thread.
+__device__ uint64_t block_scan_u64(uint64_t* __restrict__ a, int64_t n, uint64_t* wsum,
+                                   uint64_t* carry) {
   const int lane = lane_id(), w = threadIdx.x / kWave;
-  for (int64_t base = 0; base < nblocks; base += 1024) {
+  if (threadIdx.x == 0) *carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < n; base += 1024) {
     const int64_t idx = base + threadIdx.x;
-    const uint64_t x = idx < nblocks ? block_tot[idx] : 0ull;
+    const uint64_t x = idx < n ? a[idx] : 0ull;
     uint64_t incl = x;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
@@ -85,50 +97,203 @@ __global__ void __launch_bounds__(1024) k_scan_totals(uint64_t* __restrict__ blo
     }
     if (lane == kWave - 1) wsum[w] = incl;
     __syncthreads();
-    uint64_t woff = carry;
+    uint64_t woff = *carry;
     for (int k = 0; k < w; ++k) woff += wsum[k];
-    if (idx < nblocks) block_tot[idx] = woff + incl - x;
+    if (idx < n) a[idx] = woff + incl - x;
     __syncthreads();
-    if (threadIdx.x == 1023) carry = woff + incl;
+    if (threadIdx.x == 1023) *carry = woff + incl;
     __syncthreads();
   }
+  return *carry;
+}
+
+// Exclusive scans of the record and tile block totals (one block); total
+// pair count and the capacity check.  Both scans count the same pairs; a
+// mismatch is reported as an overflow so that nothing is scattered.
+__global__ void __launch_bounds__(1024) k_scan_totals(uint64_t* __restrict__ rec_tot,
+                                                      int64_t n_rec_blocks,
+                                                      uint64_t* __restrict__ tile_tot,
+                                                      int64_t n_tile_blocks, int64_t cap,
+                                                      int32_t* __restrict__ fl) {
+  __shared__ uint64_t wsum[1024 / kWave];
+  __shared__ uint64_t carry;
+  const uint64_t total = block_scan_u64(rec_tot, n_rec_blocks, wsum, &carry);
+  const uint64_t total_t = block_scan_u64(tile_tot, n_tile_blocks, wsum, &carry);
   if (threadIdx.x == 0) {
-    const uint64_t total = carry;
-    const bool over = total > (uint64_t)cap;
+    const bool over = total > (uint64_t)cap || total != total_t;
     fl[F_OVERFLOW] = over ? 1 : 0;
     fl[F_PAIRS] = over ? 0 : (int32_t)total;
     fl[F_PAIRS_WANTED] = total > 0x7FFFFFFFull ? 0x7FFFFFFF : (int32_t)total;
   }
 }
 
-// ---------------------------------------------------------------- duplicate
-__global__ void __launch_bounds__(256) k_duplicate(
+// ---------------------------------------------------------------- scatter
+// Thread per record: generation offsets become absolute (poff), every pair
+// gets the next free slot of its tile's list with key (depth bits << 32 |
+// generation index), and pair -> record is recorded.
+__global__ void __launch_bounds__(256) k_scatter(
     const uint32_t* __restrict__ tt, uint32_t* __restrict__ poff,
-    const uint64_t* __restrict__ block_pre, const ushort4* __restrict__ rect,
+    const uint64_t* __restrict__ rec_pre, const ushort4* __restrict__ rect,
     const Rec* __restrict__ rec, int64_t n, int64_t n_rec, ViewTable vt,
-    const int32_t* __restrict__ fl, uint64_t* __restrict__ keys,
-    uint32_t* __restrict__ pair_rec) {
+    const int32_t* __restrict__ fl, const uint32_t* __restrict__ tstart,
+    const uint64_t* __restrict__ tile_pre, uint32_t* __restrict__ cursor,
+    uint64_t* __restrict__ skey, uint32_t* __restrict__ pair_rec) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_rec || fl[F_OVERFLOW]) return;
   const uint32_t c = tt[i];
   if (c == 0) return;
-  const uint64_t base64 = (uint64_t)poff[i] + block_pre[i / kScanTile];
-  if (base64 + c > (uint64_t)fl[F_PAIRS]) return;  // cannot happen without overflow
-  const uint32_t base = (uint32_t)base64;
-  poff[i] = base;
+  const uint64_t P = (uint64_t)fl[F_PAIRS];
+  const uint64_t base64 = (uint64_t)poff[i] + rec_pre[i / kScanTile];
+  if (base64 + c > P) return;  // cannot happen without overflow
+  uint32_t p = (uint32_t)base64;
+  poff[i] = p;
   const int v = (int)(i / n);
   const ushort4 r = rect[i];
-  const uint32_t dbits = __float_as_uint(rec[i].z);
+  const uint64_t dbits = (uint64_t)__float_as_uint(rec[i].z) << 32;
   const int tx = vt.v[v].tiles_x;
-  const uint32_t toff = (uint32_t)vt.v[v].tile_off;
-  uint32_t o = base;
+  const int toff = vt.v[v].tile_off;
   for (int y = r.y; y < r.w; ++y)
     for (int x = r.x; x < r.z; ++x) {
-      const uint64_t tile = (uint64_t)(toff + (uint32_t)(y * tx + x));
-      keys[o] = (tile << 32) | dbits;
-      pair_rec[o] = (uint32_t)i;
-      ++o;
+      const int t = toff + y * tx + x;
+      const uint64_t slot = (uint64_t)tstart[t] + tile_pre[t / kScanTile] + atomicAdd(&cursor[t], 1u);
+      if (slot < P) skey[slot] = dbits | p;
+      pair_rec[p] = (uint32_t)i;
+      ++p;
     }
+}
+
+// ---------------------------------------------------------------- tile sort
+// One wavefront per tile.  Output: sorted keys (tile << 32 | depth bits),
+// generation indices, record ids, and the tile's [start, end) range ((0, 0)
+// when empty).  Lists up to kTileSortLds keys: bitonic network in LDS.
+// Longer lists: LSD radix sort with 8-bit digits over the generation-index
+// bits in use and the 32 depth bits, ping-ponging between the scatter
+// buffer and the output buffer; each round of 64 keys is ranked with 8
+// ballots, so every pass is stable.
+__device__ void wave_radix_pass(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst,
+                                uint32_t n, int shift, uint32_t* hist) {
+  const int lane = threadIdx.x;
+  for (int d = lane; d < kRadix; d += kWave) hist[d] = 0u;
+  __syncthreads();
+  for (uint32_t k = lane; k < n; k += kWave)
+    atomicAdd(&hist[(uint32_t)(src[k] >> shift) & (kRadix - 1)], 1u);
+  __syncthreads();
+  // exclusive scan of the 256 bins: 4 per lane
+  uint32_t h[kRadix / kWave], sum = 0;
+#pragma unroll
+  for (int q = 0; q < kRadix / kWave; ++q) {
+    h[q] = hist[lane * (kRadix / kWave) + q];
+    sum += h[q];
+  }
+  uint32_t incl = sum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  uint32_t run = incl - sum;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kRadix / kWave; ++q) {
+    hist[lane * (kRadix / kWave) + q] = run;
+    run += h[q];
+  }
+  __syncthreads();
+  const uint64_t lt = lanemask_lt();
+  for (uint32_t b = 0; b < n; b += kWave) {
+    const uint32_t k = b + (uint32_t)lane;
+    const bool valid = k < n;
+    const uint64_t key = valid ? src[k] : 0ull;
+    const uint32_t d = (uint32_t)(key >> shift) & (kRadix - 1);
+    uint64_t peers = ballot64(valid);
+#pragma unroll
+    for (int bit = 0; bit < kRadixBits; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const uint64_t bb = ballot64(on);
+      peers &= on ? bb : ~bb;
+    }
+    uint32_t at = 0;
+    if (valid) at = hist[d];
+    const uint64_t below = peers & lt;
+    if (valid) dst[at + (uint32_t)__popcll(below)] = key;
+    __syncthreads();
+    if (valid && below == 0) hist[d] = at + (uint32_t)__popcll(peers);
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kWave) k_tile_sort(
+    const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ tstart,
+    const uint64_t* __restrict__ tile_pre, int T, const int32_t* __restrict__ fl,
+    uint64_t* __restrict__ skey, const uint32_t* __restrict__ pair_rec,
+    uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+    uint32_t* __restrict__ sorted_rec, uint32_t* __restrict__ ranges) {
+  __shared__ uint64_t sk[kTileSortLds];
+  const int t = blockIdx.x;
+  const int lane = threadIdx.x;
+  const uint64_t P = (uint64_t)fl[F_PAIRS];
+  const uint32_t n = fl[F_OVERFLOW] ? 0u : cnt[t];
+  const uint64_t start64 = (uint64_t)tstart[t] + tile_pre[t / kScanTile];
+  const bool ok = n > 0 && start64 + n <= P;
+  if (lane == 0) {
+    ranges[2 * (int64_t)t] = ok ? (uint32_t)start64 : 0u;
+    ranges[2 * (int64_t)t + 1] = ok ? (uint32_t)(start64 + n) : 0u;
+  }
+  if (!ok) return;
+  const uint32_t start = (uint32_t)start64;
+  const uint64_t tkey = (uint64_t)(uint32_t)t << 32;
+  if (n <= (uint32_t)kTileSortLds) {
+    uint32_t m = kWave;
+    while (m < n) m <<= 1;
+    for (uint32_t k = lane; k < m; k += kWave) sk[k] = k < n ? skey[start + k] : ~0ull;
+    __syncthreads();
+    for (uint32_t size = 2; size <= m; size <<= 1) {
+      for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+        for (uint32_t idx = lane; idx < m / 2; idx += kWave) {
+          const uint32_t a = 2 * idx - (idx & (stride - 1));
+          const uint32_t b = a + stride;
+          const uint64_t ka = sk[a], kb = sk[b];
+          const bool up = (a & size) == 0;
+          if ((ka > kb) == up) {
+            sk[a] = kb;
+            sk[b] = ka;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (uint32_t k = lane; k < n; k += kWave) {
+      const uint64_t key = sk[k];
+      const uint32_t g = (uint32_t)key;
+      keys_out[start + k] = tkey | (key >> 32);
+      vals_out[start + k] = g;
+      sorted_rec[start + k] = pair_rec[g];
+    }
+    return;
+  }
+  // long list: generation-index bits in use, then the 32 depth bits
+  uint32_t* hist = reinterpret_cast<uint32_t*>(sk);
+  const uint32_t pmax = (uint32_t)(P - 1);
+  const int gbits = pmax == 0 ? 1 : 32 - __clz((int)pmax);
+  const int gpasses = (gbits + kRadixBits - 1) / kRadixBits;
+  uint64_t* a = skey + start;
+  uint64_t* b = keys_out + start;
+  for (int q = 0; q < gpasses; ++q) {
+    wave_radix_pass(a, b, n, q * kRadixBits, hist);
+    uint64_t* tmp = a; a = b; b = tmp;
+  }
+  for (int q = 0; q < 32 / kRadixBits; ++q) {
+    wave_radix_pass(a, b, n, 32 + q * kRadixBits, hist);
+    uint64_t* tmp = a; a = b; b = tmp;
+  }
+  // the result is in `a`; the output is written element by element in place
+  for (uint32_t k = lane; k < n; k += kWave) {
+    const uint64_t key = a[k];
+    const uint32_t g = (uint32_t)key;
+    keys_out[start + k] = tkey | (key >> 32);
+    vals_out[start + k] = g;
+    sorted_rec[start + k] = pair_rec[g];
+  }
 }
 
 // ---------------------------------------------------------------- radix sort
@@ -304,22 +469,6 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
   }
 }
 
-// ---------------------------------------------------------------- ranges
-__global__ void __launch_bounds__(256) k_ranges(const uint64_t* __restrict__ keys,
-                                                const uint32_t* __restrict__ vals,
-                                                const uint32_t* __restrict__ pair_rec,
-                                                const int32_t* __restrict__ cnt,
-                                                uint32_t* __restrict__ ranges,
-                                                uint32_t* __restrict__ sorted_rec) {
-  const int P = sort_count(cnt);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P) return;
-  const uint32_t t = (uint32_t)(keys[i] >> 32);
-  if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[2 * (int64_t)t] = (uint32_t)i;
-  if (i == P - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
-  sorted_rec[i] = pair_rec[vals[i]];
-}
-
 // Work order of the persistent render kernels: tiles by descending pair
 // count (16-bit saturated), ties in tile order.
 __global__ void __launch_bounds__(256) k_order_keys(const uint32_t* __restrict__ ranges, int T,
@@ -379,44 +528,47 @@ hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s) {
+  // per-iteration flags 0..3 and the per-tile pair counters
+  const int64_t T = P.vt.total_tiles;
+  const int64_t m = T > 4 ? T : 4;
+  hipLaunchKernelGGL(k_fill2_u32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
+                     ws_at<uint32_t>(ws, P.off_flags), (int64_t)4,
+                     ws_at<uint32_t>(ws, P.off_tile_cnt), T);
+  return hipGetLastError();
+}
+
 hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
   int32_t* fl = ws_at<int32_t>(ws, P.off_flags);
   uint32_t* tt = ws_at<uint32_t>(ws, P.off_tt);
   uint32_t* poff = ws_at<uint32_t>(ws, P.off_poff);
-  uint64_t* btot = ws_at<uint64_t>(ws, P.off_scan);
-  uint64_t* keys0 = ws_at<uint64_t>(ws, P.off_keys0);
-  uint64_t* keys1 = ws_at<uint64_t>(ws, P.off_keys1);
-  uint32_t* vals0 = ws_at<uint32_t>(ws, P.off_vals0);
-  uint32_t* vals1 = ws_at<uint32_t>(ws, P.off_vals1);
+  uint64_t* rec_tot = ws_at<uint64_t>(ws, P.off_scan);
+  uint32_t* tcnt = ws_at<uint32_t>(ws, P.off_tile_cnt);
+  uint32_t* tstart = ws_at<uint32_t>(ws, P.off_tile_start);
+  uint64_t* tile_tot = ws_at<uint64_t>(ws, P.off_tile_scan);
+  const int T = P.vt.total_tiles;
+  const int64_t sb = P.scan_blocks, tb = P.tile_scan_blocks;
+  if (sb > 0)
+    hipLaunchKernelGGL(k_scan_local<false>, dim3((unsigned)sb), dim3(kScanThreads), 0, s, tt,
+                       poff, rec_tot, P.n_rec);
+  if (tb > 0)
+    hipLaunchKernelGGL(k_scan_local<true>, dim3((unsigned)tb), dim3(kScanThreads), 0, s, tcnt,
+                       tstart, tile_tot, (int64_t)T);
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, rec_tot, sb, tile_tot, tb,
+                     P.pair_cap, fl);
+  uint64_t* skey = ws_at<uint64_t>(ws, P.off_scatter);
   uint32_t* pair_rec = ws_at<uint32_t>(ws, P.off_pair_rec);
-  uint32_t* sorted_rec = ws_at<uint32_t>(ws, P.off_sorted_rec);
-  uint32_t* hist = ws_at<uint32_t>(ws, P.off_hist);
-  uint32_t* dtot = ws_at<uint32_t>(ws, P.off_digit_tot);
-  uint32_t* ranges = ws_at<uint32_t>(ws, P.off_ranges);
-  hipError_t e;
-  const int64_t sb = P.scan_blocks;
-  if (sb > 0) {
-    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)sb), dim3(kScanThreads), 0, s, tt, poff,
-                       btot, P.n_rec);
-  }
-  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, btot, sb, P.pair_cap, fl);
   if (P.n_rec > 0) {
     const int64_t blocks = (P.n_rec + 255) / 256;
-    hipLaunchKernelGGL(k_duplicate, dim3((unsigned)blocks), dim3(256), 0, s, tt, poff, btot,
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(256), 0, s, tt, poff, rec_tot,
                        ws_at<ushort4>(ws, P.off_rect), ws_at<Rec>(ws, P.off_rec), P.n, P.n_rec,
-                       P.vt, fl, keys0, pair_rec);
+                       P.vt, fl, tstart, tile_tot, tcnt, skey, pair_rec);
   }
-  int which = 0;
-  e = launch_radix_sort(keys0, keys1, vals0, vals1, fl + F_PAIRS, hist, dtot,
-                        P.sort_blocks_cap, P.key_bits, true, &which, s);
-  if (e != hipSuccess) return e;
-  e = launch_fill_u32(ranges, 0u, 2 * (int64_t)P.vt.total_tiles, s);
-  if (e != hipSuccess) return e;
-  const uint64_t* ks = which ? keys1 : keys0;
-  const uint32_t* vs = which ? vals1 : vals0;
-  const int64_t blocks = (P.pair_cap + 255) / 256;
-  hipLaunchKernelGGL(k_ranges, dim3((unsigned)blocks), dim3(256), 0, s, ks, vs, pair_rec,
-                     fl + F_PAIRS, ranges, sorted_rec);
+  if (T > 0)
+    hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)T), dim3(kWave), 0, s, tcnt, tstart, tile_tot,
+                       T, fl, skey, pair_rec, ws_at<uint64_t>(ws, P.off_keys),
+                       ws_at<uint32_t>(ws, P.off_vals), ws_at<uint32_t>(ws, P.off_sorted_rec),
+                       ws_at<uint32_t>(ws, P.off_ranges));
   return hipGetLastError();
 }
 
@@ -438,14 +590,7 @@ hipError_t launch_tile_order(const Plan& P, void* ws, hipStream_t s) {
                            ws_at<uint32_t>(ws, P.off_digit_tot), nb, 16, true, &which, s);
 }
 
-// Sorted pair values (original pair indices) after launch_bin_sort.
-uint32_t* sorted_vals(const Plan& P, void* ws) {
-  const int passes = (P.key_bits + kRadixBits - 1) / kRadixBits;
-  return ws_at<uint32_t>(ws, (passes & 1) ? P.off_vals1 : P.off_vals0);
-}
-uint64_t* sorted_keys(const Plan& P, void* ws) {
-  const int passes = (P.key_bits + kRadixBits - 1) / kRadixBits;
-  return ws_at<uint64_t>(ws, (passes & 1) ? P.off_keys1 : P.off_keys0);
-}
+// Sorted pair values (generation indices) after launch_bin_sort.
+uint32_t* sorted_vals(const Plan& P, void* ws) { return ws_at<uint32_t>(ws, P.off_vals); }
 
 }  // namespace gs

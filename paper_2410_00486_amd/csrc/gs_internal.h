@@ -71,14 +71,15 @@ struct Plan {
   int64_t n_rec;    // n_views * n
   int64_t pair_cap;
   gs_raster_cfg cfg;
-  int32_t tile_bits, key_bits, sort_passes, pad0;
-  int64_t scan_blocks;      // blocks of the record scan
-  int64_t sort_blocks_cap;  // radix-sort blocks at full capacity
-  int64_t proj_blocks;      // blocks of the projection backward
+  int32_t tile_bits, pad0;
+  int64_t scan_blocks;       // blocks of the record scan
+  int64_t tile_scan_blocks;  // blocks of the per-tile count scan
+  int64_t proj_blocks;       // blocks of the projection backward
   ViewTable vt;
   // workspace layout (byte offsets from the 256-aligned base)
   size_t off_flags, off_rec, off_rect, off_tt, off_poff, off_scan;
-  size_t off_keys0, off_keys1, off_vals0, off_vals1, off_pair_rec, off_sorted_rec;
+  size_t off_tile_cnt, off_tile_start, off_tile_scan;
+  size_t off_keys, off_scatter, off_vals, off_pair_rec, off_sorted_rec;
   size_t off_hist, off_digit_tot, off_ranges, off_tile_last, off_tile_loss;
   size_t off_grad_pair, off_pose_part, off_order, off_order_tmp;
   size_t off_ssim_maps, off_ssim_part;
@@ -95,6 +96,9 @@ template <typename T>
 inline T* ws_at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
+
+// Per-tile sort: lists up to this length are sorted in LDS by one wavefront.
+constexpr int kTileSortLds = 2048;
 
 // Radix sort geometry: 256 threads x 16 keys per block, 8-bit digits.
 constexpr int kSortThreads = 256;

@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(256) k_preprocess(
     const float* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, int64_t n, const float* __restrict__ cams, ViewTable vt,
     uint32_t flags, Rec* __restrict__ rec, ushort4* __restrict__ rect,
-    uint32_t* __restrict__ tt, int32_t* __restrict__ fl) {
+    uint32_t* __restrict__ tt, uint32_t* __restrict__ tile_cnt, int32_t* __restrict__ fl) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   // lanes past the end stay active (as an invalid Gaussian) so that the
@@ -212,6 +212,9 @@ __global__ void __launch_bounds__(256) k_preprocess(
                                 (unsigned short)y1);
         count = (uint32_t)((x1 - x0) * (y1 - y0));
         ++visible_count;
+        // pairs per tile, for the binning
+        for (int ty = y0; ty < y1; ++ty)
+          for (int tx = x0; tx < x1; ++tx) atomicAdd(&tile_cnt[vi.tile_off + ty * vi.tiles_x + tx], 1u);
       }
     }
     if (in_range) tt[ri] = count;
@@ -237,12 +240,13 @@ hipError_t launch_preprocess(const Plan& P, const gs_gaussians& g, const float* 
   Rec* rec = ws_at<Rec>(ws, P.off_rec);
   ushort4* rect = ws_at<ushort4>(ws, P.off_rect);
   uint32_t* tt = ws_at<uint32_t>(ws, P.off_tt);
+  uint32_t* tile_cnt = ws_at<uint32_t>(ws, P.off_tile_cnt);
   int32_t* fl = ws_at<int32_t>(ws, P.off_flags);
   const uint32_t flags = P.cfg.flags;
 #define GS_PRE(D)                                                                          \
   hipLaunchKernelGGL(k_preprocess<D>, dim3((unsigned)blocks), dim3(threads), 0, s, g.means, \
                      g.log_scales, g.quats, g.opacity_logits, g.sh, P.n, cams, P.vt, flags,  \
-                     rec, rect, tt, fl)
+                     rec, rect, tt, tile_cnt, fl)
   switch (P.deg) {
     case 0: GS_PRE(0); break;
     case 1: GS_PRE(1); break;

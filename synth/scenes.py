@@ -413,6 +413,26 @@ def tiny_scene(seed: int, n: int = 8, width: int = 32, height: int = 24,
     return Workload(f"tiny_{seed}", scene, [cam], None, None, 0.0)
 
 
+def crowded_scene(seed: int, n: int = 6000, width: int = 64, height: int = 48,
+                  degree: int = 1, f: float = 60.0) -> Workload:
+    """Many faint, small Gaussians stacked over a few tiles: per-tile lists of
+    thousands of pairs (long-list sorting, long compositing chains)."""
+    rng = np.random.default_rng(seed)
+    z = rng.uniform(2.0, 3.0, n)
+    # screen positions around pixel (21, 19), spread +-2.5 px
+    u = 21.0 + rng.uniform(-2.5, 2.5, n)
+    v = 19.0 + rng.uniform(-2.5, 2.5, n)
+    means = np.stack([(u - width / 2.0) * z / f, (v - height / 2.0) * z / f, z], 1)
+    log_scales = rng.normal(-4.2, 0.15, size=(n, 3))
+    quats = _random_quats(rng, n)
+    logits = rng.normal(-3.2, 0.2, size=n)
+    colour = rng.uniform(0.1, 0.9, size=(n, 3))
+    sh = _sh_coeffs(rng, n, degree, colour)
+    scene = Scene(_f32(means), _f32(log_scales), _f32(quats), _f32(logits), _f32(sh), degree)
+    cam = Camera(width, height, f, f, width / 2.0, height / 2.0, _f32(np.eye(3)), _f32(np.zeros(3)))
+    return Workload(f"crowded_{seed}", scene, [cam], None, None, 0.0)
+
+
 def random_pose(rng, scale_rot=0.2, scale_trans=0.3):
     """A random world->camera rigid transform near identity (for invariance tests)."""
     R = _so3(rng.normal(0.0, scale_rot, 3))

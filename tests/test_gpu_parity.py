@@ -94,6 +94,48 @@ def test_bin_sort_matches_oracle(cfg, tile):
     np.testing.assert_array_equal(grg, ranges)
 
 
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_bin_sort_long_tile_list(tile):
+    """6000 pairs in one tile: the per-tile sort's long-list path (radix
+    sort through global memory) against the oracle's order."""
+    w = scenes.crowded_scene(1)
+    cam = w.cameras[0]
+    print(f"bin_sort long list tile {tile}", flush=True)
+    it = run_gpu(w.scene, [cam], tile=tile)
+    plan, ws = it.plan, it.ws
+    pre = oracle.preprocess(w.scene, cam, tile)
+    assert not (pre["near_edge"] != 0).any()
+    keys, vals, ranges = oracle.sort_pairs(pre, cam, tile)
+    r = ranges.reshape(-1, 2).astype(np.int64)
+    assert (r[:, 1] - r[:, 0]).max() > 2048
+    fl = plan.flags_of(ws)
+    P = int(fl[L.F_PAIRS])
+    assert fl[L.F_OVERFLOW] == 0 and P == keys.shape[0]
+    gk = plan.region(ws, L.GS_WS_SORTED_KEYS, torch.int64, P).cpu().numpy().view(np.uint64)
+    gr = plan.region(ws, L.GS_WS_SORTED_RECS, torch.int32, P).cpu().numpy()
+    grg = plan.region(ws, L.GS_WS_RANGES, torch.int32, ranges.size).cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(gk, keys)
+    np.testing.assert_array_equal(gr, vals.astype(np.int32))
+    np.testing.assert_array_equal(grg, ranges)
+
+
+@pytest.mark.parametrize("flags", [0, L.GS_SPLAT_BWD])
+def test_long_tile_list_forward_backward(flags):
+    """Forward and both backward variants on a 6000-splat tile list."""
+    w = scenes.crowded_scene(2)
+    cam = w.cameras[0]
+    gc, gd = scenes.linear_loss_weights(7, [cam])
+    print(f"long list forward/backward flags {flags}", flush=True)
+    it = run_gpu(w.scene, [cam], lds=64, dL_dcolor=gc, dL_ddepth=gd, flags=flags)
+    ref = oracle.render(w.scene, cam)
+    col, dep, _, _ = view_images(it, 0)
+    assert_forward_close(col, dep, ref)
+    exclude = flagged_gaussians(ref, (16, 16), cam)
+    grads, _ = oracle.backward(w.scene, cam, gc[0], gd[0])
+    assert exclude.mean() < 0.05
+    assert_grads_close(grads_np(it), grads, exclude)
+
+
 # ------------------------------------------------------------------ forward
 
 @pytest.mark.parametrize("cfg", [1, 3, 2])
