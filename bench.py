@@ -240,10 +240,9 @@ def main():
     # ---- algorithmic bytes per stage: the compulsory HBM reads and writes of
     # each stage for the counted pairs P, visible records V, pixels and N
     N, K = w.scene.n, 16
-    passes = (32 + max(1, int(np.ceil(np.log2(max(plan.total_tiles, 2))))) + 7) // 8
     bytes_ = {
         "preprocess": 44 * N + 12 * K * V + 72 * V + 4 * N,
-        "bin_sort": 8 * N + 20 * V + 12 * P + passes * 32 * P + 20 * P,
+        "bin_sort": 16 * N + 12 * V + 40 * P + 20 * plan.total_tiles,
         "render_fwd": 68 * P + 40 * npx,
         "render_bwd_raster": 120 * P + 40 * npx,
         "project_bwd": 44 * N + 12 * K * V + 236 * N + 8 * N + 48 * P,

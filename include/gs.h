@@ -141,10 +141,12 @@ int32_t* gs_flags_ptr(const gs_plan* plan, void* ws);
  *   GS_WS_RECTS         [n_views*n] u16 x0, y0, x1, y1 (tile box, exclusive)
  *   GS_WS_TILES_TOUCHED [n_views*n] u32
  *   GS_WS_PAIR_OFFSETS  [n_views*n] u32, first pair of each visible record
- *   GS_WS_SORTED_KEYS   [P] u64 after gs_bin_sort
+ *   GS_WS_SORTED_KEYS   [P] u64 after gs_bin_sort: global tile id << 32 |
+ *                       float32 bits of depth
  *   GS_WS_SORTED_VALS   [P] u32 (pair index in generation order)
  *   GS_WS_SORTED_RECS   [P] u32 (record index v*n + i of each sorted pair)
- *   GS_WS_RANGES        [total_tiles][2] u32 */
+ *   GS_WS_RANGES        [total_tiles][2] u32 [start, end) of each tile's
+ *                       list, (0, 0) for a tile without pairs */
 #define GS_WS_RECORDS 0
 #define GS_WS_RECTS 1
 #define GS_WS_TILES_TOUCHED 2
@@ -166,12 +168,13 @@ int64_t gs_plan_ws_offset(const gs_plan* plan, int32_t region);
 gs_status gs_preprocess(const gs_plan* plan, const gs_gaussians* g, const float* cams_dev,
                         void* ws, void* stream);
 
-/* a2. Tile binning: exclusive scan of tiles touched, duplication of one
- * (global tile id << 32 | float32 bits of depth) key per (Gaussian, tile) in
- * Gaussian-major, row-major tile order, stable LSD radix sort over the key
- * bits in use, per-tile [start, end) ranges.  Ties in depth keep Gaussian
- * order, so the sorted list is unique and bit-exact.  Overflow of the plan's
- * pair capacity sets flag [0]. */
+/* a2. Tile binning (the per-tile depth-sorted lists of Sec. III-C-1).
+ * Pairs are the (record, tile) incidences of the tile boxes, numbered in
+ * generation order (record-major, row-major tiles).  Each tile's list is
+ * ordered by (float32 depth, generation index): ties in depth keep Gaussian
+ * order, so the lists are unique and bit-exact.  Needs the per-tile counts
+ * of the gs_preprocess call just before on the same workspace.  Overflow of
+ * the plan's pair capacity sets flag [0]. */
 gs_status gs_bin_sort(const gs_plan* plan, void* ws, void* stream);
 
 /* a3. Front-to-back compositing of Eq. (1) per pixel over its tile's sorted
@@ -188,11 +191,15 @@ gs_status gs_render_fwd(const gs_plan* plan, void* ws, const float* cams_dev, fl
                         float* depth, float* T_final, uint32_t* last, const float* target_rgb,
                         const float* target_depth, float* loss_per_view, void* stream);
 
-/* a4-a6. Backward of one iteration (Eqs. (2)-(4)).  Per pixel, back to front
- * from its last blended Gaussian, with the transmittance recomputed by
- * division from T_final; per-pair gradients are reduced across each
- * wavefront and tile, then per Gaussian in a fixed order (deterministic),
- * and carried through the projection to the parameters.  Upstream gradients
+/* a4-a6. Backward of one iteration (Eqs. (2)-(4)).  Default (pixel-wise):
+ * per pixel, back to front from its last blended Gaussian, with the
+ * transmittance recomputed by division from T_final; per-pair gradients are
+ * reduced across the tile's wavefront.  With GS_SPLAT_BWD (splat-wise,
+ * Sec. III-C-1): one lane per splat of a 64-splat bucket, pixel states
+ * resumed from those the forward stored and handed from lane to lane.
+ * Either way the per-pair gradients are then summed per Gaussian in a fixed
+ * order (deterministic) and carried through the projection to the
+ * parameters.  Upstream gradients
  * are dL_dcolor [3][H][W] and dL_ddepth [H][W] (nullable: zero), or, with
  * GS_FUSED_L1, those of the L1 loss of gs_render_fwd against target_rgb and
  * target_depth (sign(0) = 0).  `out` is overwritten (GS_ACCUMULATE_GRADS:
@@ -292,7 +299,8 @@ gs_status gs_densify_prune(const gs_gaussians* g, const gs_gaussian_grads* m,
                            int64_t out_capacity, int32_t* n_out, void* tmp, void* stream);
 
 /* Stand-alone stable LSD radix sort of n (key, value) pairs on the low
- * key_bits bits of the keys (1..64), the same kernels gs_bin_sort uses.
+ * key_bits bits of the keys (1..64), the kernels that order the tiles of
+ * the persistent render kernels.
  * keys/vals are device arrays, sorted in place; tmp is device scratch of
  * gs_sort_tmp_bytes(n) bytes. */
 size_t gs_sort_tmp_bytes(int64_t n);

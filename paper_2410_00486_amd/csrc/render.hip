@@ -62,6 +62,51 @@ __device__ __forceinline__ float wave_sum_to_last(float x) {
   return x;
 }
 
+// Sums of ten values over the wavefront, scattered: afterwards lane l of
+// the first row holds the total of value rs_index(l) (lanes whose index is
+// -1 hold nothing).  Four in-row halving steps -- each lane keeps half of
+// its values and adds the partner's copy of that half: row mirror (partner
+// differs in bit 3), half-row mirror (bit 2), quad reversal (bit 1), quad
+// swap (bit 0) -- then the row pairs (bit 4) and half-waves (bit 5) are
+// added with the gfx950 lane swaps.  37 VALU operations instead of the 60
+// of ten separate reductions.  Every lane must be active.
+__device__ __forceinline__ float sel(bool c, float a, float b) { return c ? a : b; }
+
+__device__ __forceinline__ float reduce_scatter10(const float* g) {
+  const int l = threadIdx.x & 15;
+  const bool b3 = l & 8, b2 = l & 4, b1 = l & 2, b0 = l & 1;
+  float h[6], u[4], w[2];
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+    h[k] = sel(b3, g[k + 5], g[k]) + dpp<0x140>(sel(b3, g[k], g[k + 5]));  // row_mirror
+  h[5] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    u[k] = sel(b2, h[k + 3], h[k]) + dpp<0x141>(sel(b2, h[k], h[k + 3]));  // row_half_mirror
+  u[3] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    w[k] = sel(b1, u[k + 2], u[k]) + dpp<0x1B>(sel(b1, u[k], u[k + 2]));  // quad [3,2,1,0]
+  float z = sel(b0, w[1], w[0]) + dpp<0xB1>(sel(b0, w[0], w[1]));         // quad [1,0,3,2]
+  const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(z), __float_as_uint(z),
+                                                    false, false);
+  z = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
+  const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(z), __float_as_uint(z),
+                                                    false, false);
+  return __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
+}
+
+// Which of the ten values reduce_scatter10 leaves in lane l (first 16 lanes
+// meaningful), -1 for none.
+__device__ __forceinline__ int rs_index(int lane) {
+  const int l = lane & 15;
+  const int j = ((l & 2) ? 2 : 0) + (l & 1);       // index among u
+  if (j >= 3) return -1;
+  const int hidx = ((l & 4) ? 3 : 0) + j;          // index among h
+  if (hidx >= 5) return -1;
+  return ((l & 8) ? 5 : 0) + hidx;
+}
+
 template <int TW, int TH>
 struct Tile {
   static constexpr int NPX = TW * TH;
@@ -323,6 +368,8 @@ __device__ __forceinline__ void bwd_tile(
     gp[0] = z; gp[1] = z; gp[2] = z;
   }
 
+  // lanes of the first row write the scattered sums of the ten partials
+  const int my_idx = lane < 16 ? rs_index(lane) : -1;
   double sx[PPL], sy[PPL];
   float T[PPL], gC0[PPL], gC1[PPL], gC2[PPL], gD[PPL], Sc0[PPL], Sc1[PPL], Sc2[PPL], Sd[PPL];
   uint32_t L[PPL];
@@ -416,16 +463,12 @@ __device__ __forceinline__ void bwd_tile(
           }
         }
       }
-      float4* gp = reinterpret_cast<float4*>(grad_pair + (int64_t)sval[j] * kPairGrad);
+      float* gpf = grad_pair + (int64_t)sval[j] * kPairGrad;
       if (ballot64(contrib) != 0) {
-#pragma unroll
-        for (int f = 0; f < 10; ++f) g[f] = wave_sum_to_last(g[f]);
-        if (lane == kWave - 1) {
-          gp[0] = make_float4(g[0], g[1], g[2], g[3]);
-          gp[1] = make_float4(g[4], g[5], g[6], g[7]);
-          gp[2] = make_float4(g[8], g[9], 0.0f, 0.0f);
-        }
+        const float z = reduce_scatter10(g);
+        if (my_idx >= 0) gpf[my_idx] = z;
       } else if (lane == 0) {
+        float4* gp = reinterpret_cast<float4*>(gpf);
         const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
         gp[0] = z; gp[1] = z; gp[2] = z;
       }
