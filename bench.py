@@ -57,7 +57,7 @@ def main():
     ap.add_argument("--lds-batch", type=int, default=64)
     ap.add_argument("--chunk", type=int, default=1)
     ap.add_argument("--persistent", type=int, default=0, choices=[0, 1])
-    ap.add_argument("--bwd", default="pixel", choices=["pixel", "splat"],
+    ap.add_argument("--bwd", default="splat", choices=["pixel", "splat"],
                     help="backward of the headline: pixel-wise wave-reduced or splat-wise")
     ap.add_argument("--no-ab", action="store_true",
                     help="skip timing the other backward variant")
@@ -113,6 +113,7 @@ def main():
             if best is None or b["ms"] < best["ms"]:
                 best = b
         log(f"autotune best {best}")
+        args.bwd = best["backward"]
     tile = tuple(int(x) for x in best["tile"].split("x"))
 
     cap0 = gsr.required_pairs(*params.tensors(), cams, view_wh, 3, tile)
@@ -343,7 +344,7 @@ def bench_batched(args, dev):
     log(f"batched autotune best {best}")
     tile = tuple(int(x) for x in best["tile"].split("x"))
     cap0 = gsr.required_pairs(*params.tensors(), cams, view_wh, 3, tile)
-    flags = L.GS_FUSED_L1 | L.GS_PERSISTENT
+    flags = L.GS_FUSED_L1 | L.GS_PERSISTENT | (L.GS_SPLAT_BWD if best["backward"] == "splat" else 0)
     plan = gsr.Plan(w.scene.n, 3, view_wh, tile=tile, flags=flags, chunk=best["chunk"],
                     lds_batch=best["lds_batch"], pair_capacity=int(cap0 * 1.5) + 4096)
     it = gsr.Iteration(plan, params, cams, target_rgb=target_rgb, target_depth=target_depth,

@@ -208,6 +208,7 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_tile_cnt = take(T * 4);
   P->off_tile_start = take(T * 4);
   P->off_tile_scan = take((size_t)std::max<int64_t>(P->tile_scan_blocks, 1) * 8);
+  P->off_long = take(T * 4);
   P->off_keys = take(cap * 8);
   P->off_scatter = take(cap * 8);
   P->off_vals = take(cap * 4);
@@ -229,6 +230,8 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   // pair_capacity / 64 + tiles slots
   const bool splat = (cfg->flags & GS_SPLAT_BWD) != 0;
   P->ckpt_slots = splat ? pair_capacity / kBucket + tiles : 0;
+  P->off_bucket_start = take(splat ? T * 4 : 0);
+  P->off_bucket_scan = take(splat ? (size_t)std::max<int64_t>(P->tile_scan_blocks, 1) * 8 : 0);
   P->off_boff = take(splat ? (T + 1) * 4 : 0);
   P->off_ckpt = take((size_t)P->ckpt_slots * tw * th * kStateFloats * 4);
   P->ws_size = o;

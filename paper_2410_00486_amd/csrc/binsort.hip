@@ -44,39 +44,57 @@ template <bool ZERO>
 __global__ void __launch_bounds__(kScanThreads) k_scan_local(uint32_t* __restrict__ cnt,
                                                              uint32_t* __restrict__ off,
                                                              uint64_t* __restrict__ block_tot,
-                                                             int64_t n) {
-  __shared__ uint64_t wsum[kScanThreads / kWave];
+                                                             int64_t n,
+                                                             uint32_t* __restrict__ boff,
+                                                             uint64_t* __restrict__ bblock_tot) {
+  __shared__ uint64_t wsum[kScanThreads / kWave], bsum[kScanThreads / kWave];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
-  uint64_t s = 0;
+  uint64_t s = 0, sb = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t idx = base + k;
     v[k] = idx < n ? cnt[idx] : 0u;
     s += v[k];
+    sb += (v[k] + kBucket - 1) / kBucket;
   }
   const int lane = lane_id(), w = threadIdx.x / kWave;
-  uint64_t incl = s;
+  uint64_t incl = s, bincl = sb;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
     const uint64_t y = __shfl_up(incl, o, kWave);
-    if (lane >= o) incl += y;
+    const uint64_t yb = __shfl_up(bincl, o, kWave);
+    if (lane >= o) {
+      incl += y;
+      bincl += yb;
+    }
   }
-  if (lane == kWave - 1) wsum[w] = incl;
+  if (lane == kWave - 1) {
+    wsum[w] = incl;
+    bsum[w] = bincl;
+  }
   __syncthreads();
-  uint64_t woff = 0;
-  for (int k = 0; k < w; ++k) woff += wsum[k];
-  uint64_t run = woff + incl - s;
+  uint64_t woff = 0, bwoff = 0;
+  for (int k = 0; k < w; ++k) {
+    woff += wsum[k];
+    bwoff += bsum[k];
+  }
+  uint64_t run = woff + incl - s, brun = bwoff + bincl - sb;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t idx = base + k;
     if (idx < n) {
       off[idx] = (uint32_t)run;
+      if (boff) boff[idx] = (uint32_t)brun;
       if (ZERO) cnt[idx] = 0u;
     }
     run += v[k];
+    brun += (v[k] + kBucket - 1) / kBucket;
   }
-  if (threadIdx.x == kScanThreads - 1) block_tot[blockIdx.x] = run;
+  if (threadIdx.x == kScanThreads - 1) {
+    block_tot[blockIdx.x] = run;
+    if (bblock_tot) bblock_tot[blockIdx.x] = brun;
+  }
 }
 
 // In-place exclusive scan of n u64 values by one 1024-thread block; returns
@@ -104,7 +122,9 @@ __device__ uint64_t block_scan_u64(uint64_t* __restrict__ a, int64_t n, uint64_t
     if (threadIdx.x == 1023) *carry = woff + incl;
     __syncthreads();
   }
-  return *carry;
+  const uint64_t total = *carry;
+  __syncthreads();  // every thread has read the total before a next call resets it
+  return total;
 }
 
 // Exclusive scans of the record and tile block totals (one block); total
@@ -113,12 +133,14 @@ __device__ uint64_t block_scan_u64(uint64_t* __restrict__ a, int64_t n, uint64_t
 __global__ void __launch_bounds__(1024) k_scan_totals(uint64_t* __restrict__ rec_tot,
                                                       int64_t n_rec_blocks,
                                                       uint64_t* __restrict__ tile_tot,
-                                                      int64_t n_tile_blocks, int64_t cap,
+                                                      int64_t n_tile_blocks,
+                                                      uint64_t* __restrict__ bucket_tot, int64_t cap,
                                                       int32_t* __restrict__ fl) {
   __shared__ uint64_t wsum[1024 / kWave];
   __shared__ uint64_t carry;
   const uint64_t total = block_scan_u64(rec_tot, n_rec_blocks, wsum, &carry);
   const uint64_t total_t = block_scan_u64(tile_tot, n_tile_blocks, wsum, &carry);
+  if (bucket_tot) block_scan_u64(bucket_tot, n_tile_blocks, wsum, &carry);
   if (threadIdx.x == 0) {
     const bool over = total > (uint64_t)cap || total != total_t;
     fl[F_OVERFLOW] = over ? 1 : 0;
@@ -128,9 +150,12 @@ __global__ void __launch_bounds__(1024) k_scan_totals(uint64_t* __restrict__ rec
 }
 
 // ---------------------------------------------------------------- scatter
-// Thread per record: generation offsets become absolute (poff), every pair
-// gets the next free slot of its tile's list with key (depth bits << 32 |
-// generation index), and pair -> record is recorded.
+// Generation offsets become absolute (poff), every pair gets the next free
+// slot of its tile's list with key (depth bits << 32 | generation index),
+// and pair -> record is recorded.  Each wavefront takes 64 consecutive
+// records and spreads their pairs evenly over its lanes (exclusive scan of
+// the pair counts, binary search of a pair's record in LDS), so a large
+// Gaussian does not serialise its tiles' slot claims on one lane.
 __global__ void __launch_bounds__(256) k_scatter(
     const uint32_t* __restrict__ tt, uint32_t* __restrict__ poff,
     const uint64_t* __restrict__ rec_pre, const ushort4* __restrict__ rect,
@@ -138,97 +163,136 @@ __global__ void __launch_bounds__(256) k_scatter(
     const int32_t* __restrict__ fl, const uint32_t* __restrict__ tstart,
     const uint64_t* __restrict__ tile_pre, uint32_t* __restrict__ cursor,
     uint64_t* __restrict__ skey, uint32_t* __restrict__ pair_rec) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_rec || fl[F_OVERFLOW]) return;
-  const uint32_t c = tt[i];
-  if (c == 0) return;
+  constexpr int NW = 256 / kWave;
+  __shared__ uint32_t s_pre[NW][kWave + 1];
+  __shared__ uint32_t s_p0[NW][kWave], s_dbits[NW][kWave], s_x0y0[NW][kWave];
+  __shared__ uint32_t s_wv[NW][kWave];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const uint64_t P = (uint64_t)fl[F_PAIRS];
-  const uint64_t base64 = (uint64_t)poff[i] + rec_pre[i / kScanTile];
-  if (base64 + c > P) return;  // cannot happen without overflow
-  uint32_t p = (uint32_t)base64;
-  poff[i] = p;
-  const int v = (int)(i / n);
-  const ushort4 r = rect[i];
-  const uint64_t dbits = (uint64_t)__float_as_uint(rec[i].z) << 32;
-  const int tx = vt.v[v].tiles_x;
-  const int toff = vt.v[v].tile_off;
-  for (int y = r.y; y < r.w; ++y)
-    for (int x = r.x; x < r.z; ++x) {
-      const int t = toff + y * tx + x;
-      const uint64_t slot = (uint64_t)tstart[t] + tile_pre[t / kScanTile] + atomicAdd(&cursor[t], 1u);
-      if (slot < P) skey[slot] = dbits | p;
-      pair_rec[p] = (uint32_t)i;
-      ++p;
+  const bool over = fl[F_OVERFLOW] != 0;
+  uint32_t c = (i < n_rec && !over) ? tt[i] : 0u;
+  uint32_t p0 = 0, dbits = 0, x0y0 = 0, wv = 0;
+  if (c > 0) {
+    const uint64_t base64 = (uint64_t)poff[i] + rec_pre[i / kScanTile];
+    if (base64 + c > P) {
+      c = 0;  // cannot happen without overflow
+    } else {
+      p0 = (uint32_t)base64;
+      poff[i] = p0;
+      const ushort4 r = rect[i];
+      dbits = __float_as_uint(rec[i].z);
+      x0y0 = (uint32_t)r.x | ((uint32_t)r.y << 16);
+      wv = (uint32_t)(r.z - r.x) | ((uint32_t)(i / n) << 16);
     }
-}
-
-// ---------------------------------------------------------------- tile sort
-// One wavefront per tile.  Output: sorted keys (tile << 32 | depth bits),
-// generation indices, record ids, and the tile's [start, end) range ((0, 0)
-// when empty).  Lists up to kTileSortLds keys: bitonic network in LDS.
-// Longer lists: LSD radix sort with 8-bit digits over the generation-index
-// bits in use and the 32 depth bits, ping-ponging between the scatter
-// buffer and the output buffer; each round of 64 keys is ranked with 8
-// ballots, so every pass is stable.
-__device__ void wave_radix_pass(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst,
-                                uint32_t n, int shift, uint32_t* hist) {
-  const int lane = threadIdx.x;
-  for (int d = lane; d < kRadix; d += kWave) hist[d] = 0u;
-  __syncthreads();
-  for (uint32_t k = lane; k < n; k += kWave)
-    atomicAdd(&hist[(uint32_t)(src[k] >> shift) & (kRadix - 1)], 1u);
-  __syncthreads();
-  // exclusive scan of the 256 bins: 4 per lane
-  uint32_t h[kRadix / kWave], sum = 0;
-#pragma unroll
-  for (int q = 0; q < kRadix / kWave; ++q) {
-    h[q] = hist[lane * (kRadix / kWave) + q];
-    sum += h[q];
   }
-  uint32_t incl = sum;
+  uint32_t incl = c;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
     const uint32_t y = __shfl_up(incl, o, kWave);
     if (lane >= o) incl += y;
   }
-  uint32_t run = incl - sum;
+  s_pre[w][lane] = incl - c;
+  if (lane == kWave - 1) s_pre[w][kWave] = incl;
+  s_p0[w][lane] = p0;
+  s_dbits[w][lane] = dbits;
+  s_x0y0[w][lane] = x0y0;
+  s_wv[w][lane] = wv;
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < kRadix / kWave; ++q) {
-    hist[lane * (kRadix / kWave) + q] = run;
-    run += h[q];
-  }
-  __syncthreads();
-  const uint64_t lt = lanemask_lt();
-  for (uint32_t b = 0; b < n; b += kWave) {
-    const uint32_t k = b + (uint32_t)lane;
-    const bool valid = k < n;
-    const uint64_t key = valid ? src[k] : 0ull;
-    const uint32_t d = (uint32_t)(key >> shift) & (kRadix - 1);
-    uint64_t peers = ballot64(valid);
-#pragma unroll
-    for (int bit = 0; bit < kRadixBits; ++bit) {
-      const bool on = (d >> bit) & 1u;
-      const uint64_t bb = ballot64(on);
-      peers &= on ? bb : ~bb;
+  const uint32_t total = s_pre[w][kWave];
+  const int64_t rec0 = (int64_t)blockIdx.x * 256 + (int64_t)w * kWave;
+  for (uint32_t q = (uint32_t)lane; q < total; q += kWave) {
+    // owner: the last record whose prefix is <= q (it has pairs)
+    int lo = 0, hi = kWave - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_pre[w][mid] <= q) lo = mid; else hi = mid - 1;
     }
-    uint32_t at = 0;
-    if (valid) at = hist[d];
-    const uint64_t below = peers & lt;
-    if (valid) dst[at + (uint32_t)__popcll(below)] = key;
+    const uint32_t k = q - s_pre[w][lo];
+    const uint32_t wvj = s_wv[w][lo], xy = s_x0y0[w][lo];
+    const uint32_t bw = wvj & 0xFFFFu;
+    const int v = (int)(wvj >> 16);
+    const int x = (int)(xy & 0xFFFFu) + (int)(k % bw);
+    const int y = (int)(xy >> 16) + (int)(k / bw);
+    const int t = vt.v[v].tile_off + y * vt.v[v].tiles_x + x;
+    const uint32_t p = s_p0[w][lo] + k;
+    const uint64_t slot = (uint64_t)tstart[t] + tile_pre[t / kScanTile] + atomicAdd(&cursor[t], 1u);
+    if (slot < P) skey[slot] = ((uint64_t)s_dbits[w][lo] << 32) | p;
+    pair_rec[p] = (uint32_t)(rec0 + lo);
+  }
+}
+
+// ---------------------------------------------------------------- tile sort
+// Output per tile: sorted keys (tile << 32 | depth bits), generation
+// indices, record ids, the [start, end) range ((0, 0) when empty) and, for
+// the splat-wise backward, the absolute bucket offset.  Keys are unique, so
+// any correct sort gives the same lists.  k_tile_sort (one wavefront per
+// tile) sorts lists up to 64 keys in registers (rank = number of smaller
+// keys) and up to kTileSortSmall keys with a bitonic network in LDS, and
+// queues longer lists; k_tile_sort_long (1024-thread blocks, grid-stride
+// over the queue) sorts them with the same network in LDS up to
+// kTileSortLong keys and in place in global memory beyond.
+//
+// The network keeps every merge ascending (the first compare of a merge
+// pairs i with its mirror in the block), so positions past the list end
+// act as +infinity and are never touched: no padding is written.
+constexpr uint32_t kTileSortSmall = 512;
+constexpr uint32_t kTileSortLong = 16384;
+constexpr int kLongThreads = 1024;
+
+struct TileSortOut {
+  uint64_t* keys;
+  uint32_t* vals;
+  uint32_t* sorted_rec;
+  const uint32_t* pair_rec;
+};
+
+__device__ __forceinline__ void emit_sorted(const TileSortOut& o, uint32_t pos, uint64_t tkey,
+                                            uint64_t key) {
+  const uint32_t g = (uint32_t)key;
+  o.keys[pos] = tkey | (key >> 32);
+  o.vals[pos] = g;
+  o.sorted_rec[pos] = o.pair_rec[g];
+}
+
+__device__ __forceinline__ void cmp_swap(uint64_t* k, uint32_t a, uint32_t b, uint32_t n) {
+  if (b >= n) return;
+  const uint64_t ka = k[a], kb = k[b];
+  if (ka > kb) {
+    k[a] = kb;
+    k[b] = ka;
+  }
+}
+
+// Sorts k[0, n) ascending (LDS or global memory) with nthreads threads of
+// the block; every thread of the block must call it.
+__device__ void bitonic_sort(uint64_t* k, uint32_t n, uint32_t tid, uint32_t nthreads) {
+  uint32_t m = 1;
+  while (m < n) m <<= 1;
+  for (uint32_t size = 2; size <= m; size <<= 1) {
+    const uint32_t half = size >> 1;
+    for (uint32_t idx = tid; idx < m / 2; idx += nthreads) {
+      const uint32_t blk = idx / half, off = idx % half;
+      cmp_swap(k, blk * size + off, blk * size + size - 1 - off, n);
+    }
     __syncthreads();
-    if (valid && below == 0) hist[d] = at + (uint32_t)__popcll(peers);
-    __syncthreads();
+    for (uint32_t stride = size >> 2; stride > 0; stride >>= 1) {
+      for (uint32_t idx = tid; idx < m / 2; idx += nthreads) {
+        const uint32_t a = 2 * idx - (idx & (stride - 1));
+        cmp_swap(k, a, a + stride, n);
+      }
+      __syncthreads();
+    }
   }
 }
 
 __global__ void __launch_bounds__(kWave) k_tile_sort(
     const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ tstart,
-    const uint64_t* __restrict__ tile_pre, int T, const int32_t* __restrict__ fl,
-    uint64_t* __restrict__ skey, const uint32_t* __restrict__ pair_rec,
-    uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
-    uint32_t* __restrict__ sorted_rec, uint32_t* __restrict__ ranges) {
-  __shared__ uint64_t sk[kTileSortLds];
+    const uint64_t* __restrict__ tile_pre, int T, int32_t* __restrict__ fl,
+    const uint64_t* __restrict__ skey, TileSortOut out, uint32_t* __restrict__ ranges,
+    uint32_t* __restrict__ long_list, const uint32_t* __restrict__ bstart,
+    const uint64_t* __restrict__ bucket_pre, uint32_t* __restrict__ boff) {
+  __shared__ uint64_t sk[kTileSortSmall];
   const int t = blockIdx.x;
   const int lane = threadIdx.x;
   const uint64_t P = (uint64_t)fl[F_PAIRS];
@@ -238,61 +302,56 @@ __global__ void __launch_bounds__(kWave) k_tile_sort(
   if (lane == 0) {
     ranges[2 * (int64_t)t] = ok ? (uint32_t)start64 : 0u;
     ranges[2 * (int64_t)t + 1] = ok ? (uint32_t)(start64 + n) : 0u;
+    if (boff) {
+      // buckets of 64 positions; a tile without a valid list has none
+      boff[t] = bstart[t] + (uint32_t)bucket_pre[t / kScanTile];
+      if (t == T - 1) boff[T] = boff[t] + (ok ? (n + kBucket - 1) / kBucket : 0u);
+    }
+    if (ok && n > kTileSortSmall) long_list[atomicAdd(&fl[F_LONG_TILES], 1)] = (uint32_t)t;
   }
-  if (!ok) return;
+  if (!ok || n > kTileSortSmall) return;
   const uint32_t start = (uint32_t)start64;
   const uint64_t tkey = (uint64_t)(uint32_t)t << 32;
-  if (n <= (uint32_t)kTileSortLds) {
-    uint32_t m = kWave;
-    while (m < n) m <<= 1;
-    for (uint32_t k = lane; k < m; k += kWave) sk[k] = k < n ? skey[start + k] : ~0ull;
-    __syncthreads();
-    for (uint32_t size = 2; size <= m; size <<= 1) {
-      for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-        for (uint32_t idx = lane; idx < m / 2; idx += kWave) {
-          const uint32_t a = 2 * idx - (idx & (stride - 1));
-          const uint32_t b = a + stride;
-          const uint64_t ka = sk[a], kb = sk[b];
-          const bool up = (a & size) == 0;
-          if ((ka > kb) == up) {
-            sk[a] = kb;
-            sk[b] = ka;
-          }
-        }
-        __syncthreads();
-      }
+  if (n <= (uint32_t)kWave) {
+    const bool has = (uint32_t)lane < n;
+    const uint64_t key = has ? skey[start + lane] : ~0ull;
+    uint32_t rank = 0;
+    for (uint32_t j = 0; j < n; ++j) {
+      const uint64_t kj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(key >> 32), j) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, j);
+      rank += kj < key ? 1u : 0u;
     }
-    for (uint32_t k = lane; k < n; k += kWave) {
-      const uint64_t key = sk[k];
-      const uint32_t g = (uint32_t)key;
-      keys_out[start + k] = tkey | (key >> 32);
-      vals_out[start + k] = g;
-      sorted_rec[start + k] = pair_rec[g];
-    }
+    if (has) emit_sorted(out, start + rank, tkey, key);
     return;
   }
-  // long list: generation-index bits in use, then the 32 depth bits
-  uint32_t* hist = reinterpret_cast<uint32_t*>(sk);
-  const uint32_t pmax = (uint32_t)(P - 1);
-  const int gbits = pmax == 0 ? 1 : 32 - __clz((int)pmax);
-  const int gpasses = (gbits + kRadixBits - 1) / kRadixBits;
-  uint64_t* a = skey + start;
-  uint64_t* b = keys_out + start;
-  for (int q = 0; q < gpasses; ++q) {
-    wave_radix_pass(a, b, n, q * kRadixBits, hist);
-    uint64_t* tmp = a; a = b; b = tmp;
-  }
-  for (int q = 0; q < 32 / kRadixBits; ++q) {
-    wave_radix_pass(a, b, n, 32 + q * kRadixBits, hist);
-    uint64_t* tmp = a; a = b; b = tmp;
-  }
-  // the result is in `a`; the output is written element by element in place
-  for (uint32_t k = lane; k < n; k += kWave) {
-    const uint64_t key = a[k];
-    const uint32_t g = (uint32_t)key;
-    keys_out[start + k] = tkey | (key >> 32);
-    vals_out[start + k] = g;
-    sorted_rec[start + k] = pair_rec[g];
+  for (uint32_t k = lane; k < n; k += kWave) sk[k] = skey[start + k];
+  __syncthreads();
+  bitonic_sort(sk, n, lane, kWave);
+  for (uint32_t k = lane; k < n; k += kWave) emit_sorted(out, start + k, tkey, sk[k]);
+}
+
+__global__ void __launch_bounds__(kLongThreads) k_tile_sort_long(
+    const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ tstart,
+    const uint64_t* __restrict__ tile_pre, const int32_t* __restrict__ fl,
+    const uint32_t* __restrict__ long_list, uint64_t* __restrict__ skey, TileSortOut out) {
+  __shared__ uint64_t sk[kTileSortLong];
+  const int n_long = fl[F_LONG_TILES];
+  for (int li = blockIdx.x; li < n_long; li += gridDim.x) {
+    const int t = (int)long_list[li];
+    const uint32_t n = cnt[t];
+    const uint32_t start = tstart[t] + (uint32_t)tile_pre[t / kScanTile];
+    const uint64_t tkey = (uint64_t)(uint32_t)t << 32;
+    if (n <= kTileSortLong) {
+      for (uint32_t k = threadIdx.x; k < n; k += kLongThreads) sk[k] = skey[start + k];
+      __syncthreads();
+      bitonic_sort(sk, n, threadIdx.x, kLongThreads);
+      for (uint32_t k = threadIdx.x; k < n; k += kLongThreads) emit_sorted(out, start + k, tkey, sk[k]);
+    } else {
+      bitonic_sort(skey + start, n, threadIdx.x, kLongThreads);
+      for (uint32_t k = threadIdx.x; k < n; k += kLongThreads)
+        emit_sorted(out, start + k, tkey, skey[start + k]);
+    }
+    __syncthreads();  // the LDS is reused by the next list
   }
 }
 
@@ -529,11 +588,11 @@ hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t s) {
 }
 
 hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s) {
-  // per-iteration flags 0..3 and the per-tile pair counters
+  // per-iteration flags 0..7 and the per-tile pair counters
   const int64_t T = P.vt.total_tiles;
   const int64_t m = T > 4 ? T : 4;
   hipLaunchKernelGGL(k_fill2_u32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
-                     ws_at<uint32_t>(ws, P.off_flags), (int64_t)4,
+                     ws_at<uint32_t>(ws, P.off_flags), (int64_t)8,
                      ws_at<uint32_t>(ws, P.off_tile_cnt), T);
   return hipGetLastError();
 }
@@ -546,16 +605,20 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
   uint32_t* tcnt = ws_at<uint32_t>(ws, P.off_tile_cnt);
   uint32_t* tstart = ws_at<uint32_t>(ws, P.off_tile_start);
   uint64_t* tile_tot = ws_at<uint64_t>(ws, P.off_tile_scan);
+  const bool splat = (P.cfg.flags & GS_SPLAT_BWD) != 0;
+  uint32_t* bstart = splat ? ws_at<uint32_t>(ws, P.off_bucket_start) : nullptr;
+  uint64_t* bucket_tot = splat ? ws_at<uint64_t>(ws, P.off_bucket_scan) : nullptr;
+  uint32_t* boff = splat ? ws_at<uint32_t>(ws, P.off_boff) : nullptr;
   const int T = P.vt.total_tiles;
   const int64_t sb = P.scan_blocks, tb = P.tile_scan_blocks;
   if (sb > 0)
     hipLaunchKernelGGL(k_scan_local<false>, dim3((unsigned)sb), dim3(kScanThreads), 0, s, tt,
-                       poff, rec_tot, P.n_rec);
+                       poff, rec_tot, P.n_rec, nullptr, nullptr);
   if (tb > 0)
     hipLaunchKernelGGL(k_scan_local<true>, dim3((unsigned)tb), dim3(kScanThreads), 0, s, tcnt,
-                       tstart, tile_tot, (int64_t)T);
+                       tstart, tile_tot, (int64_t)T, bstart, bucket_tot);
   hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, rec_tot, sb, tile_tot, tb,
-                     P.pair_cap, fl);
+                     bucket_tot, P.pair_cap, fl);
   uint64_t* skey = ws_at<uint64_t>(ws, P.off_scatter);
   uint32_t* pair_rec = ws_at<uint32_t>(ws, P.off_pair_rec);
   if (P.n_rec > 0) {
@@ -564,11 +627,17 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
                        ws_at<ushort4>(ws, P.off_rect), ws_at<Rec>(ws, P.off_rec), P.n, P.n_rec,
                        P.vt, fl, tstart, tile_tot, tcnt, skey, pair_rec);
   }
-  if (T > 0)
+  if (T > 0) {
+    TileSortOut out{ws_at<uint64_t>(ws, P.off_keys), ws_at<uint32_t>(ws, P.off_vals),
+                    ws_at<uint32_t>(ws, P.off_sorted_rec), pair_rec};
+    uint32_t* long_list = ws_at<uint32_t>(ws, P.off_long);
     hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)T), dim3(kWave), 0, s, tcnt, tstart, tile_tot,
-                       T, fl, skey, pair_rec, ws_at<uint64_t>(ws, P.off_keys),
-                       ws_at<uint32_t>(ws, P.off_vals), ws_at<uint32_t>(ws, P.off_sorted_rec),
-                       ws_at<uint32_t>(ws, P.off_ranges));
+                       T, fl, skey, out, ws_at<uint32_t>(ws, P.off_ranges), long_list, bstart,
+                       bucket_tot, boff);
+    const int long_grid = (int)std::min<int64_t>(T, 256);
+    hipLaunchKernelGGL(k_tile_sort_long, dim3((unsigned)long_grid), dim3(kLongThreads), 0, s,
+                       tcnt, tstart, tile_tot, fl, long_list, skey, out);
+  }
   return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ enum Flag : int {
   F_QUEUE_FWD = 4,
   F_QUEUE_BWD = 5,
   F_PAIRS_WANTED = 6,
+  F_LONG_TILES = 7,  // tiles whose lists go to the long-list sort
   F_COUNT = 16
 };
 
@@ -78,12 +79,13 @@ struct Plan {
   ViewTable vt;
   // workspace layout (byte offsets from the 256-aligned base)
   size_t off_flags, off_rec, off_rect, off_tt, off_poff, off_scan;
-  size_t off_tile_cnt, off_tile_start, off_tile_scan;
+  size_t off_tile_cnt, off_tile_start, off_tile_scan, off_long;
   size_t off_keys, off_scatter, off_vals, off_pair_rec, off_sorted_rec;
   size_t off_hist, off_digit_tot, off_ranges, off_tile_last, off_tile_loss;
   size_t off_grad_pair, off_pose_part, off_order, off_order_tmp;
   size_t off_ssim_maps, off_ssim_part;
-  size_t off_boff, off_ckpt;  // splat-wise backward: bucket offsets, pixel states
+  // splat-wise backward: bucket offsets (local, block sums, absolute), pixel states
+  size_t off_bucket_start, off_bucket_scan, off_boff, off_ckpt;
   int64_t ckpt_slots;
   size_t ws_size;
 };
@@ -96,9 +98,6 @@ template <typename T>
 inline T* ws_at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
-
-// Per-tile sort: lists up to this length are sorted in LDS by one wavefront.
-constexpr int kTileSortLds = 2048;
 
 // Radix sort geometry: 256 threads x 16 keys per block, 8-bit digits.
 constexpr int kSortThreads = 256;

@@ -308,18 +308,21 @@ __global__ void __launch_bounds__(kWave) k_render_fwd(
 }
 
 // Per-view L1 loss from the per-tile sums, in a fixed order.
-__global__ void __launch_bounds__(256) k_loss_reduce(const float* __restrict__ tile_loss,
-                                                     ViewTable vt, float lambda_depth,
-                                                     int has_depth, float* __restrict__ loss) {
+constexpr int kLossThreads = 1024;
+__global__ void __launch_bounds__(kLossThreads) k_loss_reduce(const float* __restrict__ tile_loss,
+                                                              ViewTable vt, float lambda_depth,
+                                                              int has_depth, float* __restrict__ loss) {
   const int v = blockIdx.x;
   const ViewInfo vi = vt.v[v];
   const int nt = vi.tiles_x * vi.tiles_y;
+  const float2* tl = reinterpret_cast<const float2*>(tile_loss) + vi.tile_off;
   double a = 0.0, b = 0.0;
-  for (int k = threadIdx.x; k < nt; k += 256) {
-    a += tile_loss[2 * (int64_t)(vi.tile_off + k)];
-    b += tile_loss[2 * (int64_t)(vi.tile_off + k) + 1];
+  for (int k = threadIdx.x; k < nt; k += kLossThreads) {
+    const float2 x = tl[k];
+    a += x.x;
+    b += x.y;
   }
-  __shared__ double sa[256 / kWave], sb[256 / kWave];
+  __shared__ double sa[kLossThreads / kWave], sb[kLossThreads / kWave];
   a = wave_sum(a);
   b = wave_sum(b);
   if (lane_id() == 0) {
@@ -329,7 +332,7 @@ __global__ void __launch_bounds__(256) k_loss_reduce(const float* __restrict__ t
   __syncthreads();
   if (threadIdx.x == 0) {
     double ta = 0.0, tb = 0.0;
-    for (int k = 0; k < 256 / kWave; ++k) {
+    for (int k = 0; k < kLossThreads / kWave; ++k) {
       ta += sa[k];
       tb += sb[k];
     }
@@ -534,36 +537,6 @@ __global__ void __launch_bounds__(kWave) k_render_bwd(
 // own splat's ten partial gradients over the tile's pixels and writes them
 // once: no reduction over lanes and no atomics.
 
-// Exclusive scan of buckets per tile (ceil(pairs / 64)); boff[T] = total.
-__global__ void __launch_bounds__(1024) k_bucket_scan(const uint32_t* __restrict__ ranges, int T,
-                                                      uint32_t* __restrict__ boff) {
-  __shared__ uint32_t wsum[1024 / kWave];
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  const int lane = lane_id(), w = threadIdx.x / kWave;
-  for (int base = 0; base < T; base += 1024) {
-    const int t = base + (int)threadIdx.x;
-    const uint32_t x =
-        t < T ? (ranges[2 * (int64_t)t + 1] - ranges[2 * (int64_t)t] + kBucket - 1) / kBucket : 0u;
-    uint32_t incl = x;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const uint32_t y = __shfl_up(incl, o, kWave);
-      if (lane >= o) incl += y;
-    }
-    if (lane == kWave - 1) wsum[w] = incl;
-    __syncthreads();
-    uint32_t woff = carry;
-    for (int k = 0; k < w; ++k) woff += wsum[k];
-    if (t < T) boff[t] = woff + incl - x;
-    __syncthreads();
-    if (threadIdx.x == 1023) carry = woff + incl;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) boff[T] = carry;
-}
-
 template <int TW, int TH>
 __device__ __forceinline__ void splat_bucket(
     int gtile, uint32_t k, const Rec* __restrict__ rec, const uint32_t* __restrict__ sorted_rec,
@@ -757,9 +730,6 @@ hipError_t fwd_launch(const Plan& P, void* ws, const float* cams, float* color, 
   const int B = P.cfg.lds_batch;
   const size_t lds = (size_t)B * sizeof(Rec);
   if (P.cfg.flags & GS_SPLAT_BWD) {
-    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s,
-                       ws_at<uint32_t>(ws, P.off_ranges), P.vt.total_tiles,
-                       ws_at<uint32_t>(ws, P.off_boff));
     hipLaunchKernelGGL((k_render_fwd<TW, TH, true>), dim3(grid), dim3(kWave), lds, s,
                        ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_sorted_rec),
                        ws_at<uint32_t>(ws, P.off_ranges), cams, P.vt, B, color, depth, T_final,
@@ -838,7 +808,7 @@ hipError_t launch_render_fwd(const Plan& P, void* ws, const float* cams, float* 
     e = fwd_launch<8, 8>(P, ws, cams, color, depth, T_final, last, target_rgb, target_depth, order, queue, grid, s);
   if (e != hipSuccess) return e;
   if (target_rgb && loss_per_view) {
-    hipLaunchKernelGGL(k_loss_reduce, dim3(P.vt.n_views), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_loss_reduce, dim3(P.vt.n_views), dim3(kLossThreads), 0, s,
                        ws_at<float>(ws, P.off_tile_loss), P.vt, P.cfg.lambda_depth,
                        target_depth ? 1 : 0, loss_per_view);
     e = hipGetLastError();

@@ -94,20 +94,22 @@ def test_bin_sort_matches_oracle(cfg, tile):
     np.testing.assert_array_equal(grg, ranges)
 
 
-@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
-def test_bin_sort_long_tile_list(tile):
-    """6000 pairs in one tile: the per-tile sort's long-list path (radix
-    sort through global memory) against the oracle's order."""
-    w = scenes.crowded_scene(1)
+@pytest.mark.parametrize("tile,n", [((16, 16), 6000), ((8, 8), 3000), ((8, 8), 300),
+                                    ((16, 16), 20000)])
+def test_bin_sort_long_tile_list(tile, n):
+    """n pairs in one tile: each path of the per-tile sort (300: bitonic in
+    one wavefront's LDS; 3000 and 6000: bitonic in a block's LDS; 20000:
+    bitonic in place in global memory) against the oracle's order."""
+    w = scenes.crowded_scene(1, n=n)
     cam = w.cameras[0]
-    print(f"bin_sort long list tile {tile}", flush=True)
+    print(f"bin_sort long list tile {tile} n {n}", flush=True)
     it = run_gpu(w.scene, [cam], tile=tile)
     plan, ws = it.plan, it.ws
     pre = oracle.preprocess(w.scene, cam, tile)
     assert not (pre["near_edge"] != 0).any()
     keys, vals, ranges = oracle.sort_pairs(pre, cam, tile)
     r = ranges.reshape(-1, 2).astype(np.int64)
-    assert (r[:, 1] - r[:, 0]).max() > 2048
+    assert (r[:, 1] - r[:, 0]).max() == n
     fl = plan.flags_of(ws)
     P = int(fl[L.F_PAIRS])
     assert fl[L.F_OVERFLOW] == 0 and P == keys.shape[0]
