@@ -364,10 +364,13 @@ def bench_batched(args, dev):
     fl = plan.flags_of(it.ws)
     assert fl[L.F_OVERFLOW] == 0
     vis_total = int(fl[L.F_VISIBLE])
-    groups = it._groups
     grads = it.grads
     it.close()
     del it
+    # the plain form starts from the same initial parameters
+    params = gsr.Gaussians.from_scene(w.scene, dev)
+    adam_m, adam_v = params.zeros_like(), params.zeros_like()
+    groups = gsr.adam_groups(params, grads, adam_m, adam_v, LRS)
     # plain per-view form: one plan and workspace per view, gradients summed
     # into one buffer, then one Adam step
     per, vis = [], []

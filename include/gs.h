@@ -129,7 +129,8 @@ int64_t gs_plan_total_tiles(const gs_plan* plan);
 /* Device pointer to the int32 flags inside `ws`:
  *   [0] pair-capacity overflow (0/1)   [1] Gaussians culled as non-finite
  *   [2] pair count P of the last gs_bin_sort (valid if [0] == 0)
- *   [3] summed visible (view, Gaussian) records of the last gs_preprocess
+ *   [3] visible (view, Gaussian) records (non-empty tile box) of the last
+ *       gs_preprocess, counted by the gs_bin_sort after it
  *   [6] pairs the last gs_bin_sort needed (saturated at 2^31-1) */
 int32_t* gs_flags_ptr(const gs_plan* plan, void* ws);
 

@@ -46,17 +46,21 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_local(uint32_t* __restric
                                                              uint64_t* __restrict__ block_tot,
                                                              int64_t n,
                                                              uint32_t* __restrict__ boff,
-                                                             uint64_t* __restrict__ bblock_tot) {
+                                                             uint64_t* __restrict__ bblock_tot,
+                                                             uint64_t* __restrict__ nz_tot) {
   __shared__ uint64_t wsum[kScanThreads / kWave], bsum[kScanThreads / kWave];
+  __shared__ uint32_t nzsum[kScanThreads / kWave];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
   uint64_t s = 0, sb = 0;
+  uint32_t nz = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t idx = base + k;
     v[k] = idx < n ? cnt[idx] : 0u;
     s += v[k];
     sb += (v[k] + kBucket - 1) / kBucket;
+    nz += v[k] > 0 ? 1u : 0u;
   }
   const int lane = lane_id(), w = threadIdx.x / kWave;
   uint64_t incl = s, bincl = sb;
@@ -72,6 +76,10 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_local(uint32_t* __restric
   if (lane == kWave - 1) {
     wsum[w] = incl;
     bsum[w] = bincl;
+  }
+  if (nz_tot) {
+    const uint32_t wnz = (uint32_t)wave_sum((double)nz);
+    if (lane == 0) nzsum[w] = wnz;
   }
   __syncthreads();
   uint64_t woff = 0, bwoff = 0;
@@ -94,6 +102,11 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_local(uint32_t* __restric
   if (threadIdx.x == kScanThreads - 1) {
     block_tot[blockIdx.x] = run;
     if (bblock_tot) bblock_tot[blockIdx.x] = brun;
+  }
+  if (nz_tot && threadIdx.x == 0) {
+    uint64_t t = 0;
+    for (int k = 0; k < kScanThreads / kWave; ++k) t += nzsum[k];
+    nz_tot[blockIdx.x] = t;
   }
 }
 
@@ -134,11 +147,13 @@ __global__ void __launch_bounds__(1024) k_scan_totals(uint64_t* __restrict__ rec
                                                       int64_t n_rec_blocks,
                                                       uint64_t* __restrict__ tile_tot,
                                                       int64_t n_tile_blocks,
-                                                      uint64_t* __restrict__ bucket_tot, int64_t cap,
+                                                      uint64_t* __restrict__ bucket_tot,
+                                                      uint64_t* __restrict__ vis_tot, int64_t cap,
                                                       int32_t* __restrict__ fl) {
   __shared__ uint64_t wsum[1024 / kWave];
   __shared__ uint64_t carry;
   const uint64_t total = block_scan_u64(rec_tot, n_rec_blocks, wsum, &carry);
+  const uint64_t visible = block_scan_u64(vis_tot, n_rec_blocks, wsum, &carry);
   const uint64_t total_t = block_scan_u64(tile_tot, n_tile_blocks, wsum, &carry);
   if (bucket_tot) block_scan_u64(bucket_tot, n_tile_blocks, wsum, &carry);
   if (threadIdx.x == 0) {
@@ -146,6 +161,7 @@ __global__ void __launch_bounds__(1024) k_scan_totals(uint64_t* __restrict__ rec
     fl[F_OVERFLOW] = over ? 1 : 0;
     fl[F_PAIRS] = over ? 0 : (int32_t)total;
     fl[F_PAIRS_WANTED] = total > 0x7FFFFFFFull ? 0x7FFFFFFF : (int32_t)total;
+    fl[F_VISIBLE] = (int32_t)visible;
   }
 }
 
@@ -602,6 +618,7 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
   uint32_t* tt = ws_at<uint32_t>(ws, P.off_tt);
   uint32_t* poff = ws_at<uint32_t>(ws, P.off_poff);
   uint64_t* rec_tot = ws_at<uint64_t>(ws, P.off_scan);
+  uint64_t* vis_tot = ws_at<uint64_t>(ws, P.off_vis_scan);
   uint32_t* tcnt = ws_at<uint32_t>(ws, P.off_tile_cnt);
   uint32_t* tstart = ws_at<uint32_t>(ws, P.off_tile_start);
   uint64_t* tile_tot = ws_at<uint64_t>(ws, P.off_tile_scan);
@@ -613,12 +630,12 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
   const int64_t sb = P.scan_blocks, tb = P.tile_scan_blocks;
   if (sb > 0)
     hipLaunchKernelGGL(k_scan_local<false>, dim3((unsigned)sb), dim3(kScanThreads), 0, s, tt,
-                       poff, rec_tot, P.n_rec, nullptr, nullptr);
+                       poff, rec_tot, P.n_rec, nullptr, nullptr, vis_tot);
   if (tb > 0)
     hipLaunchKernelGGL(k_scan_local<true>, dim3((unsigned)tb), dim3(kScanThreads), 0, s, tcnt,
-                       tstart, tile_tot, (int64_t)T, bstart, bucket_tot);
+                       tstart, tile_tot, (int64_t)T, bstart, bucket_tot, nullptr);
   hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, rec_tot, sb, tile_tot, tb,
-                     bucket_tot, P.pair_cap, fl);
+                     bucket_tot, vis_tot, P.pair_cap, fl);
   uint64_t* skey = ws_at<uint64_t>(ws, P.off_scatter);
   uint32_t* pair_rec = ws_at<uint32_t>(ws, P.off_pair_rec);
   if (P.n_rec > 0) {

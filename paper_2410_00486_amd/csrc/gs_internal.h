@@ -78,7 +78,7 @@ struct Plan {
   int64_t proj_blocks;       // blocks of the projection backward
   ViewTable vt;
   // workspace layout (byte offsets from the 256-aligned base)
-  size_t off_flags, off_rec, off_rect, off_tt, off_poff, off_scan;
+  size_t off_flags, off_rec, off_rect, off_tt, off_poff, off_scan, off_vis_scan;
   size_t off_tile_cnt, off_tile_start, off_tile_scan, off_long;
   size_t off_keys, off_scatter, off_vals, off_pair_rec, off_sorted_rec;
   size_t off_hist, off_digit_tot, off_ranges, off_tile_last, off_tile_loss;

@@ -98,7 +98,6 @@ __global__ void __launch_bounds__(256) k_preprocess(
   const bool sigma3 = (flags & GS_CUTOFF_3SIGMA) != 0;
   bool sh_loaded = false;
   float shv[K * 3];
-  int visible_count = 0;
 
   for (int v = 0; v < vt.n_views; ++v) {
     const ViewInfo vi = vt.v[v];
@@ -211,7 +210,6 @@ __global__ void __launch_bounds__(256) k_preprocess(
         rect[ri] = make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)x1,
                                 (unsigned short)y1);
         count = (uint32_t)((x1 - x0) * (y1 - y0));
-        ++visible_count;
         // pairs per tile, for the binning
         for (int ty = y0; ty < y1; ++ty)
           for (int tx = x0; tx < x1; ++tx) atomicAdd(&tile_cnt[vi.tile_off + ty * vi.tiles_x + tx], 1u);
@@ -219,15 +217,10 @@ __global__ void __launch_bounds__(256) k_preprocess(
     }
     if (in_range) tt[ri] = count;
   }
-  // per-wave aggregated statistics
+  // non-finite Gaussians are rare: one atomic per wave that has any (the
+  // visible-record count is taken by the binning's record scan)
   const uint64_t nf = ballot64(nonfinite != 0);
-  int vis_sum = visible_count;
-#pragma unroll
-  for (int o2 = 1; o2 < kWave; o2 <<= 1) vis_sum += __shfl_xor(vis_sum, o2, kWave);
-  if (lane_id() == 0) {
-    if (nf) atomicAdd(&fl[F_NONFINITE], (int)__popcll(nf));
-    if (vis_sum) atomicAdd(&fl[F_VISIBLE], vis_sum);
-  }
+  if (lane_id() == 0 && nf) atomicAdd(&fl[F_NONFINITE], (int)__popcll(nf));
 }
 
 }  // namespace
