@@ -162,6 +162,10 @@ __global__ void __launch_bounds__(1024) k_scan_totals(uint64_t* __restrict__ rec
     fl[F_PAIRS] = over ? 0 : (int32_t)total;
     fl[F_PAIRS_WANTED] = total > 0x7FFFFFFFull ? 0x7FFFFFFF : (int32_t)total;
     fl[F_VISIBLE] = (int32_t)visible;
+    // queue counters filled by the tile sort that follows
+    fl[F_LONG_TILES] = 0;
+    fl[F_BQ_FULL] = 0;
+    fl[F_BQ_HALF] = 0;
   }
 }
 
@@ -307,7 +311,8 @@ __global__ void __launch_bounds__(kWave) k_tile_sort(
     const uint64_t* __restrict__ tile_pre, int T, int32_t* __restrict__ fl,
     const uint64_t* __restrict__ skey, TileSortOut out, uint32_t* __restrict__ ranges,
     uint32_t* __restrict__ long_list, const uint32_t* __restrict__ bstart,
-    const uint64_t* __restrict__ bucket_pre, uint32_t* __restrict__ boff) {
+    const uint64_t* __restrict__ bucket_pre, uint32_t* __restrict__ boff,
+    uint2* __restrict__ bq, int64_t bq_stride) {
   __shared__ uint64_t sk[kTileSortSmall];
   const int t = blockIdx.x;
   const int lane = threadIdx.x;
@@ -324,6 +329,16 @@ __global__ void __launch_bounds__(kWave) k_tile_sort(
       if (t == T - 1) boff[T] = boff[t] + (ok ? (n + kBucket - 1) / kBucket : 0u);
     }
     if (ok && n > kTileSortSmall) long_list[atomicAdd(&fl[F_LONG_TILES], 1)] = (uint32_t)t;
+  }
+  if (boff && ok) {
+    // splat-wise work queues: buckets with more than 32 pairs, and the rest
+    const uint32_t nb = (n + kBucket - 1) / kBucket;
+    for (uint32_t k = lane; k < nb; k += kWave) {
+      const uint32_t c = min((uint32_t)kBucket, n - k * kBucket);
+      const int q = c > 32 ? 0 : 1;
+      const int at = atomicAdd(&fl[F_BQ_FULL + q], 1);
+      bq[q * bq_stride + at] = make_uint2((uint32_t)t, k);
+    }
   }
   if (!ok || n > kTileSortSmall) return;
   const uint32_t start = (uint32_t)start64;
@@ -604,11 +619,11 @@ hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t s) {
 }
 
 hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s) {
-  // per-iteration flags 0..7 and the per-tile pair counters
+  // per-iteration flags 0..9 and the per-tile pair counters
   const int64_t T = P.vt.total_tiles;
   const int64_t m = T > 4 ? T : 4;
   hipLaunchKernelGGL(k_fill2_u32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
-                     ws_at<uint32_t>(ws, P.off_flags), (int64_t)8,
+                     ws_at<uint32_t>(ws, P.off_flags), (int64_t)10,
                      ws_at<uint32_t>(ws, P.off_tile_cnt), T);
   return hipGetLastError();
 }
@@ -650,7 +665,8 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
     uint32_t* long_list = ws_at<uint32_t>(ws, P.off_long);
     hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)T), dim3(kWave), 0, s, tcnt, tstart, tile_tot,
                        T, fl, skey, out, ws_at<uint32_t>(ws, P.off_ranges), long_list, bstart,
-                       bucket_tot, boff);
+                       bucket_tot, boff, splat ? ws_at<uint2>(ws, P.off_bq) : nullptr,
+                       P.ckpt_slots);
     const int long_grid = (int)std::min<int64_t>(T, 256);
     hipLaunchKernelGGL(k_tile_sort_long, dim3((unsigned)long_grid), dim3(kLongThreads), 0, s,
                        tcnt, tstart, tile_tot, fl, long_list, skey, out);

@@ -26,6 +26,8 @@ enum Flag : int {
   F_QUEUE_BWD = 5,
   F_PAIRS_WANTED = 6,
   F_LONG_TILES = 7,  // tiles whose lists go to the long-list sort
+  F_BQ_FULL = 8,     // splat-wise buckets with more than 32 pairs
+  F_BQ_HALF = 9,     // splat-wise buckets with at most 32 pairs
   F_COUNT = 16
 };
 
@@ -85,7 +87,7 @@ struct Plan {
   size_t off_grad_pair, off_pose_part, off_order, off_order_tmp;
   size_t off_ssim_maps, off_ssim_part;
   // splat-wise backward: bucket offsets (local, block sums, absolute), pixel states
-  size_t off_bucket_start, off_bucket_scan, off_boff, off_ckpt;
+  size_t off_bucket_start, off_bucket_scan, off_boff, off_bq, off_ckpt;
   int64_t ckpt_slots;
   size_t ws_size;
 };

@@ -537,76 +537,100 @@ __global__ void __launch_bounds__(kWave) k_render_bwd(
 // own splat's ten partial gradients over the tile's pixels and writes them
 // once: no reduction over lanes and no atomics.
 
+// Buckets with at most 32 pairs share a wavefront: each 32-lane half runs
+// its own bucket (the lane starting a half takes stored states, like lane
+// 0), so the diagonal costs Pix_tile + 31 steps for two buckets.  The
+// binning queues buckets by size (more than 32 pairs / at most 32).
 template <int TW, int TH>
-__device__ __forceinline__ void splat_bucket(
-    int gtile, uint32_t k, const Rec* __restrict__ rec, const uint32_t* __restrict__ sorted_rec,
+__device__ __forceinline__ void splat_wave(
+    int seg_lanes, const uint2* __restrict__ queue, uint32_t q_first, uint32_t q_count,
+    const Rec* __restrict__ rec, const uint32_t* __restrict__ sorted_rec,
     const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ tile_last, const uint32_t* __restrict__ boff,
-    const float* __restrict__ ckpt, const float* __restrict__ cams, const ViewTable& vt,
-    const float* __restrict__ color, const float* __restrict__ depth,
-    const uint32_t* __restrict__ last, const float* __restrict__ dL_dcolor,
-    const float* __restrict__ dL_ddepth, const float* __restrict__ target_rgb,
-    const float* __restrict__ target_depth, int fused, float lambda_depth,
-    float* __restrict__ grad_pair, float4* pxa, float4* pxb) {
+    const float* __restrict__ ckpt, const ViewTable& vt, const float* __restrict__ color,
+    const float* __restrict__ depth, const uint32_t* __restrict__ last,
+    const float* __restrict__ dL_dcolor, const float* __restrict__ dL_ddepth,
+    const float* __restrict__ target_rgb, const float* __restrict__ target_depth, int fused,
+    float lambda_depth, float* __restrict__ grad_pair, float4* pxa, float4* pxb) {
   constexpr int NPX = TW * TH;
   constexpr int LOG_TW = TW == 16 ? 4 : 3;
   const int lane = threadIdx.x;
-  const uint32_t s = ranges[2 * (int64_t)gtile], e = ranges[2 * (int64_t)gtile + 1];
-  const uint32_t tl = tile_last[gtile];
+  const int lg = seg_lanes == 64 ? 6 : 5;
+  const int seg = lane >> lg, ls = lane & (seg_lanes - 1);
+  const uint32_t qi = q_first + (uint32_t)seg;
+  const bool has = qi < q_count;
+  const uint2 ent = has ? queue[qi] : make_uint2(0u, 0u);
+  const int gtile = (int)ent.x;
+  const uint32_t k = ent.y;
+  uint32_t s = 0, npairs = 0, tl = 0;
+  if (has) {
+    s = ranges[2 * (int64_t)gtile];
+    npairs = ranges[2 * (int64_t)gtile + 1] - s;
+    tl = tile_last[gtile];
+  }
   const uint32_t q0 = k * kBucket;
-  const uint32_t pos = q0 + (uint32_t)lane;
-  const bool live = pos < tl;
-  if (pos < e - s && !live) {  // pairs behind the last used position: zero gradient
+  const uint32_t pos = q0 + (uint32_t)ls;
+  const bool live = has && pos < tl;
+  if (has && pos < npairs && !live) {  // pairs behind the last used position: zero gradient
     float4* gp = reinterpret_cast<float4*>(grad_pair + (int64_t)sorted_vals[s + pos] * kPairGrad);
     const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
     gp[0] = z; gp[1] = z; gp[2] = z;
   }
-  if (q0 >= tl) return;  // uniform: the whole bucket lies behind
-  const int nl = (int)min((uint32_t)kBucket, tl - q0);
+  const bool active = has && q0 < tl;  // uniform over the segment
+  const int nl = active ? (int)min((uint32_t)seg_lanes, tl - q0) : 0;
+  // steps: the longest live bucket of the wave decides
+  int nl_max = nl;
+  if (seg_lanes == 32) nl_max = max(nl, __shfl_xor(nl, 32, kWave));
+  if (nl_max == 0) return;  // uniform
 
-  const int v = find_view(vt, gtile);
+  const int v = active ? find_view(vt, gtile) : 0;
   const ViewInfo vi = vt.v[v];
   const int lt = gtile - vi.tile_off;
   const int tx0 = (lt % vi.tiles_x) * TW, ty0 = (lt / vi.tiles_x) * TH;
   const int64_t npx = (int64_t)vi.W * vi.H;
-  const float* cp = ckpt + (int64_t)(boff[gtile] + k) * (kStateFloats * NPX);
+  float4* sa = pxa + seg * NPX;
+  float4* sb = pxb + seg * NPX;
 
-  // pixel table: loss gradients, P, last position, stored state (T, Q)
-  for (int j = lane; j < NPX; j += kWave) {
-    const int px = tx0 + (j & (TW - 1)), py = ty0 + (j >> LOG_TW);
-    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 1.f, 0.f);
-    if (px < vi.W && py < vi.H) {
-      const int64_t pl = (int64_t)py * vi.W + px;
-      const int64_t pix = (int64_t)vi.pix_off + pl;
-      const int64_t cbase = 3 * (int64_t)vi.pix_off + pl;
-      const float o0 = color[cbase], o1 = color[cbase + npx], o2 = color[cbase + 2 * npx];
-      const float od = depth[pix];
-      if (fused) {
-        const float inv3 = 1.0f / (3.0f * (float)npx);
-        const float d0 = o0 - target_rgb[cbase];
-        const float d1 = o1 - target_rgb[cbase + npx];
-        const float d2 = o2 - target_rgb[cbase + 2 * npx];
-        a.x = d0 > 0.0f ? inv3 : (d0 < 0.0f ? -inv3 : 0.0f);
-        a.y = d1 > 0.0f ? inv3 : (d1 < 0.0f ? -inv3 : 0.0f);
-        a.z = d2 > 0.0f ? inv3 : (d2 < 0.0f ? -inv3 : 0.0f);
-        if (target_depth) {
-          const float dd = od - target_depth[pix];
-          const float sc = lambda_depth / (float)npx;
-          a.w = dd > 0.0f ? sc : (dd < 0.0f ? -sc : 0.0f);
+  // pixel table of the segment's tile: loss gradients, P, last position,
+  // stored state (T, Q)
+  if (active) {
+    const float* cp = ckpt + (int64_t)(boff[gtile] + k) * (kStateFloats * NPX);
+    for (int j = ls; j < NPX; j += seg_lanes) {
+      const int px = tx0 + (j & (TW - 1)), py = ty0 + (j >> LOG_TW);
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 1.f, 0.f);
+      if (px < vi.W && py < vi.H) {
+        const int64_t pl = (int64_t)py * vi.W + px;
+        const int64_t pix = (int64_t)vi.pix_off + pl;
+        const int64_t cbase = 3 * (int64_t)vi.pix_off + pl;
+        const float o0 = color[cbase], o1 = color[cbase + npx], o2 = color[cbase + 2 * npx];
+        const float od = depth[pix];
+        if (fused) {
+          const float inv3 = 1.0f / (3.0f * (float)npx);
+          const float d0 = o0 - target_rgb[cbase];
+          const float d1 = o1 - target_rgb[cbase + npx];
+          const float d2 = o2 - target_rgb[cbase + 2 * npx];
+          a.x = d0 > 0.0f ? inv3 : (d0 < 0.0f ? -inv3 : 0.0f);
+          a.y = d1 > 0.0f ? inv3 : (d1 < 0.0f ? -inv3 : 0.0f);
+          a.z = d2 > 0.0f ? inv3 : (d2 < 0.0f ? -inv3 : 0.0f);
+          if (target_depth) {
+            const float dd = od - target_depth[pix];
+            const float sc = lambda_depth / (float)npx;
+            a.w = dd > 0.0f ? sc : (dd < 0.0f ? -sc : 0.0f);
+          }
+        } else {
+          a.x = dL_dcolor[cbase];
+          a.y = dL_dcolor[cbase + npx];
+          a.z = dL_dcolor[cbase + 2 * npx];
+          a.w = dL_ddepth ? dL_ddepth[pix] : 0.0f;
         }
-      } else {
-        a.x = dL_dcolor[cbase];
-        a.y = dL_dcolor[cbase + npx];
-        a.z = dL_dcolor[cbase + 2 * npx];
-        a.w = dL_ddepth ? dL_ddepth[pix] : 0.0f;
+        b.x = a.x * o0 + a.y * o1 + a.z * o2 + a.w * od;
+        b.y = __uint_as_float(last[pix]);
+        b.z = cp[j];
+        b.w = a.x * cp[NPX + j] + a.y * cp[2 * NPX + j] + a.z * cp[3 * NPX + j] + a.w * cp[4 * NPX + j];
       }
-      b.x = a.x * o0 + a.y * o1 + a.z * o2 + a.w * od;
-      b.y = __uint_as_float(last[pix]);
-      b.z = cp[j];
-      b.w = a.x * cp[NPX + j] + a.y * cp[2 * NPX + j] + a.z * cp[3 * NPX + j] + a.w * cp[4 * NPX + j];
+      sa[j] = a;
+      sb[j] = b;
     }
-    pxa[j] = a;
-    pxb[j] = b;
   }
   __syncthreads();
 
@@ -625,15 +649,15 @@ __device__ __forceinline__ void splat_bucket(
 #pragma unroll
   for (int f = 0; f < 10; ++f) g[f] = 0.0f;
   float Tout = 1.0f, Qout = 0.0f;
-  const int steps = NPX + nl - 1;
+  const int steps = NPX + nl_max - 1;
   for (int t = 0; t < steps; ++t) {
     float Tc = dpp<0x138>(Tout);  // wave_shr:1, state of lane - 1
     float Qc = dpp<0x138>(Qout);
-    const int j = t - lane;
+    const int j = t - ls;
     const bool vj = (unsigned)j < (unsigned)NPX;
     const int jc = vj ? j : 0;
-    const float4 b = pxb[jc];
-    if (lane == 0) {
+    const float4 b = sb[jc];
+    if (ls == 0) {
       Tc = b.z;
       Qc = b.w;
     }
@@ -643,8 +667,9 @@ __device__ __forceinline__ void splat_bucket(
       double dx, dy;
       float G, oG, a;
       if (eval_alpha(r, sx, sy, dx, dy, G, oG, a)) {
-        const float4 gc = pxa[jc];
-        const float inv_om = __builtin_amdgcn_rcpf(1.0f - a);
+        const float4 gc = sa[jc];
+        const float om = 1.0f - a;
+        const float inv_om = __builtin_amdgcn_rcpf(om);
         const float wgt = a * Tc;
         const float front = gc.x * r.r + gc.y * r.g + gc.z * r.b + gc.w * r.z;
         const float Qn = fmaf(wgt, front, Qc);
@@ -663,7 +688,7 @@ __device__ __forceinline__ void splat_bucket(
           g[8] -= gpow * (ca * fx + cb * fy);
           g[9] -= gpow * (cb * fx + cc * fy);
         }
-        Tc = Tc * (1.0f - a);
+        Tc = Tc * om;
         Qc = Qn;
       }
     }
@@ -676,34 +701,35 @@ __device__ __forceinline__ void splat_bucket(
     gp[1] = make_float4(g[4], g[5], g[6], g[7]);
     gp[2] = make_float4(g[8], g[9], 0.0f, 0.0f);
   }
-  __syncthreads();  // the pixel table is rewritten by the next bucket
+  __syncthreads();  // the pixel tables are rewritten by the next wave's work
 }
 
-// Buckets are taken grid-stride; bucket b belongs to the last tile t with
-// boff[t] <= b (tiles without pairs have no buckets).
+// Grid-stride over the work of the two queues: one bucket per wave from
+// the first, two per wave from the second.
 template <int TW, int TH>
 __global__ void __launch_bounds__(kWave) k_render_bwd_splat(
     const Rec* __restrict__ rec, const uint32_t* __restrict__ sorted_rec,
     const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ tile_last, const uint32_t* __restrict__ boff,
-    const float* __restrict__ ckpt, const float* __restrict__ cams, ViewTable vt,
-    const float* __restrict__ color, const float* __restrict__ depth,
-    const uint32_t* __restrict__ last, const float* __restrict__ dL_dcolor,
-    const float* __restrict__ dL_ddepth, const float* __restrict__ target_rgb,
-    const float* __restrict__ target_depth, int fused, float lambda_depth,
-    float* __restrict__ grad_pair) {
-  __shared__ float4 pxa[TW * TH], pxb[TW * TH];
-  const int T = vt.total_tiles;
-  const uint32_t nbk = boff[T];
-  for (uint32_t bk = blockIdx.x; bk < nbk; bk += gridDim.x) {
-    int lo = 0, hi = T - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (boff[mid] <= bk) lo = mid; else hi = mid - 1;
-    }
-    splat_bucket<TW, TH>(lo, bk - boff[lo], rec, sorted_rec, sorted_vals, ranges, tile_last, boff,
-                         ckpt, cams, vt, color, depth, last, dL_dcolor, dL_ddepth, target_rgb,
+    const float* __restrict__ ckpt, const uint2* __restrict__ bq, int64_t bq_stride,
+    const int32_t* __restrict__ fl, ViewTable vt, const float* __restrict__ color,
+    const float* __restrict__ depth, const uint32_t* __restrict__ last,
+    const float* __restrict__ dL_dcolor, const float* __restrict__ dL_ddepth,
+    const float* __restrict__ target_rgb, const float* __restrict__ target_depth, int fused,
+    float lambda_depth, float* __restrict__ grad_pair) {
+  __shared__ float4 pxa[2 * TW * TH], pxb[2 * TW * TH];
+  const uint32_t q_full = (uint32_t)fl[F_BQ_FULL], q_half = (uint32_t)fl[F_BQ_HALF];
+  const uint32_t w_full = q_full, w_half = (q_half + 1) / 2;
+  for (uint32_t wv = blockIdx.x; wv < w_full + w_half; wv += gridDim.x) {
+    if (wv < w_full)
+      splat_wave<TW, TH>(64, bq, wv, q_full, rec, sorted_rec, sorted_vals, ranges, tile_last,
+                         boff, ckpt, vt, color, depth, last, dL_dcolor, dL_ddepth, target_rgb,
                          target_depth, fused, lambda_depth, grad_pair, pxa, pxb);
+    else
+      splat_wave<TW, TH>(32, bq + bq_stride, 2 * (wv - w_full), q_half, rec, sorted_rec,
+                         sorted_vals, ranges, tile_last, boff, ckpt, vt, color, depth, last,
+                         dL_dcolor, dL_ddepth, target_rgb, target_depth, fused, lambda_depth,
+                         grad_pair, pxa, pxb);
   }
 }
 
@@ -713,12 +739,14 @@ hipError_t bwd_splat_launch(const Plan& P, void* ws, const float* cams, const fl
                             const float* dL_ddepth, const float* target_rgb,
                             const float* target_depth, int fused, const uint32_t* sorted_vals,
                             int grid, hipStream_t s) {
+  (void)cams;
   hipLaunchKernelGGL((k_render_bwd_splat<TW, TH>), dim3(grid), dim3(kWave), 0, s,
                      ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_sorted_rec), sorted_vals,
                      ws_at<uint32_t>(ws, P.off_ranges), ws_at<uint32_t>(ws, P.off_tile_last),
-                     ws_at<uint32_t>(ws, P.off_boff), ws_at<float>(ws, P.off_ckpt), cams, P.vt,
-                     color, depth, last, dL_dcolor, dL_ddepth, target_rgb, target_depth, fused,
-                     P.cfg.lambda_depth, ws_at<float>(ws, P.off_grad_pair));
+                     ws_at<uint32_t>(ws, P.off_boff), ws_at<float>(ws, P.off_ckpt),
+                     ws_at<uint2>(ws, P.off_bq), P.ckpt_slots, ws_at<int32_t>(ws, P.off_flags),
+                     P.vt, color, depth, last, dL_dcolor, dL_ddepth, target_rgb, target_depth,
+                     fused, P.cfg.lambda_depth, ws_at<float>(ws, P.off_grad_pair));
   return hipGetLastError();
 }
 
