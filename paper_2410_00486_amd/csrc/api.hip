@@ -206,6 +206,8 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_poff = take(nrec * 4);
   P->off_scan = take((size_t)std::max<int64_t>(P->scan_blocks, 1) * 8);
   P->off_vis_scan = take((size_t)std::max<int64_t>(P->scan_blocks, 1) * 8);
+  P->off_vpre = take(nrec * 4);
+  P->off_vis_list = take(nrec * 4);
   P->off_tile_cnt = take(T * 4);
   P->off_tile_start = take(T * 4);
   P->off_tile_scan = take((size_t)std::max<int64_t>(P->tile_scan_blocks, 1) * 8);

@@ -47,6 +47,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_local(uint32_t* __restric
                                                              int64_t n,
                                                              uint32_t* __restrict__ boff,
                                                              uint64_t* __restrict__ bblock_tot,
+                                                             uint32_t* __restrict__ nzoff,
                                                              uint64_t* __restrict__ nz_tot) {
   __shared__ uint64_t wsum[kScanThreads / kWave], bsum[kScanThreads / kWave];
   __shared__ uint32_t nzsum[kScanThreads / kWave];
@@ -77,16 +78,22 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_local(uint32_t* __restric
     wsum[w] = incl;
     bsum[w] = bincl;
   }
-  if (nz_tot) {
-    const uint32_t wnz = (uint32_t)wave_sum((double)nz);
-    if (lane == 0) nzsum[w] = wnz;
+  // nonzero entries: local exclusive prefix (the compact visible list)
+  uint32_t nzincl = nz;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t y = __shfl_up(nzincl, o, kWave);
+    if (lane >= o) nzincl += y;
   }
+  if (lane == kWave - 1) nzsum[w] = nzincl;
   __syncthreads();
   uint64_t woff = 0, bwoff = 0;
   for (int k = 0; k < w; ++k) {
     woff += wsum[k];
     bwoff += bsum[k];
   }
+  uint32_t nzrun = nzincl - nz;
+  for (int k = 0; k < w; ++k) nzrun += nzsum[k];
   uint64_t run = woff + incl - s, brun = bwoff + bincl - sb;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
@@ -94,10 +101,12 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_local(uint32_t* __restric
     if (idx < n) {
       off[idx] = (uint32_t)run;
       if (boff) boff[idx] = (uint32_t)brun;
+      if (nzoff) nzoff[idx] = nzrun;
       if (ZERO) cnt[idx] = 0u;
     }
     run += v[k];
     brun += (v[k] + kBucket - 1) / kBucket;
+    nzrun += v[k] > 0 ? 1u : 0u;
   }
   if (threadIdx.x == kScanThreads - 1) {
     block_tot[blockIdx.x] = run;
@@ -182,7 +191,9 @@ __global__ void __launch_bounds__(256) k_scatter(
     const Rec* __restrict__ rec, int64_t n, int64_t n_rec, ViewTable vt,
     const int32_t* __restrict__ fl, const uint32_t* __restrict__ tstart,
     const uint64_t* __restrict__ tile_pre, uint32_t* __restrict__ cursor,
-    uint64_t* __restrict__ skey, uint32_t* __restrict__ pair_rec) {
+    uint64_t* __restrict__ skey, uint32_t* __restrict__ pair_rec,
+    const uint32_t* __restrict__ vpre, const uint64_t* __restrict__ vis_pre,
+    uint32_t* __restrict__ vis_list) {
   constexpr int NW = 256 / kWave;
   __shared__ uint32_t s_pre[NW][kWave + 1];
   __shared__ uint32_t s_p0[NW][kWave], s_dbits[NW][kWave], s_x0y0[NW][kWave];
@@ -200,6 +211,7 @@ __global__ void __launch_bounds__(256) k_scatter(
     } else {
       p0 = (uint32_t)base64;
       poff[i] = p0;
+      vis_list[vpre[i] + vis_pre[i / kScanTile]] = (uint32_t)i;  // records in index order
       const ushort4 r = rect[i];
       dbits = __float_as_uint(rec[i].z);
       x0y0 = (uint32_t)r.x | ((uint32_t)r.y << 16);
@@ -645,10 +657,11 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
   const int64_t sb = P.scan_blocks, tb = P.tile_scan_blocks;
   if (sb > 0)
     hipLaunchKernelGGL(k_scan_local<false>, dim3((unsigned)sb), dim3(kScanThreads), 0, s, tt,
-                       poff, rec_tot, P.n_rec, nullptr, nullptr, vis_tot);
+                       poff, rec_tot, P.n_rec, nullptr, nullptr, ws_at<uint32_t>(ws, P.off_vpre),
+                       vis_tot);
   if (tb > 0)
     hipLaunchKernelGGL(k_scan_local<true>, dim3((unsigned)tb), dim3(kScanThreads), 0, s, tcnt,
-                       tstart, tile_tot, (int64_t)T, bstart, bucket_tot, nullptr);
+                       tstart, tile_tot, (int64_t)T, bstart, bucket_tot, nullptr, nullptr);
   hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, rec_tot, sb, tile_tot, tb,
                      bucket_tot, vis_tot, P.pair_cap, fl);
   uint64_t* skey = ws_at<uint64_t>(ws, P.off_scatter);
@@ -657,7 +670,9 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
     const int64_t blocks = (P.n_rec + 255) / 256;
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(256), 0, s, tt, poff, rec_tot,
                        ws_at<ushort4>(ws, P.off_rect), ws_at<Rec>(ws, P.off_rec), P.n, P.n_rec,
-                       P.vt, fl, tstart, tile_tot, tcnt, skey, pair_rec);
+                       P.vt, fl, tstart, tile_tot, tcnt, skey, pair_rec,
+                       ws_at<uint32_t>(ws, P.off_vpre), vis_tot,
+                       ws_at<uint32_t>(ws, P.off_vis_list));
   }
   if (T > 0) {
     TileSortOut out{ws_at<uint64_t>(ws, P.off_keys), ws_at<uint32_t>(ws, P.off_vals),

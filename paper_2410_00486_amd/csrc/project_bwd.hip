@@ -69,21 +69,34 @@ __device__ __forceinline__ void sh_backward(double x, double y, double z, const 
   }
 }
 
-template <int DEG, bool POSE>
+// COMPACT (one view): threads take the visible Gaussians from the list the
+// binning wrote, in index order, so that the long chain runs on full
+// wavefronts; the other Gaussians' gradients are zeroed beforehand.
+template <int DEG, bool POSE, bool COMPACT>
 __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, int64_t n, const float* __restrict__ cams, ViewTable vt,
     const Rec* __restrict__ recs, const uint32_t* __restrict__ tt, const uint32_t* __restrict__ poff,
-    const float* __restrict__ grad_pair, const int32_t* __restrict__ fl, int accumulate,
+    const float* __restrict__ grad_pair, const int32_t* __restrict__ fl,
+    const uint32_t* __restrict__ vis_list, int accumulate,
     float* __restrict__ g_means, float* __restrict__ g_ls, float* __restrict__ g_q,
     float* __restrict__ g_logit, float* __restrict__ g_sh, double* __restrict__ pose_part,
     int64_t pose_stride) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   constexpr int NW = kProjThreads / kWave;
-  const int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
-  const bool valid = i < n;
   const bool overflow = fl[F_OVERFLOW] != 0;
+  const int64_t t0 = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
+  bool valid;
+  int64_t i;
+  if (COMPACT) {
+    const int64_t nv = overflow ? 0 : (int64_t)fl[F_VISIBLE];
+    valid = t0 < nv;
+    i = valid ? (int64_t)vis_list[t0] : 0;
+  } else {
+    valid = t0 < n;
+    i = t0;
+  }
   __shared__ double spose[NW][6];
 
   // world covariance Sigma (view independent); its gradient is summed over
@@ -310,6 +323,28 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
   }
 }
 
+// Zero of the five gradient arrays (59 floats per Gaussian at degree 3).
+__global__ void __launch_bounds__(256) k_zero_grads(float* __restrict__ a, int64_t na,
+                                                    float* __restrict__ b, int64_t nb,
+                                                    float* __restrict__ c, int64_t nc,
+                                                    float* __restrict__ d, int64_t nd,
+                                                    float* __restrict__ e, int64_t ne) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < na + nb + nc + nd + ne;
+       k += stride) {
+    int64_t r = k;
+    if (r < na) { a[r] = 0.0f; continue; }
+    r -= na;
+    if (r < nb) { b[r] = 0.0f; continue; }
+    r -= nb;
+    if (r < nc) { c[r] = 0.0f; continue; }
+    r -= nc;
+    if (r < nd) { d[r] = 0.0f; continue; }
+    r -= nd;
+    e[r] = 0.0f;
+  }
+}
+
 // Per-view camera tangent from the workgroup partials, fixed order.
 __global__ void __launch_bounds__(256) k_pose_reduce(const double* __restrict__ pose_part,
                                                      int64_t nblocks, float* __restrict__ out) {
@@ -338,19 +373,33 @@ hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float*
   const int64_t blocks = P.proj_blocks;
   if (blocks == 0) return hipSuccess;
   double* pose_part = dL_dpose ? ws_at<double>(ws, P.off_pose_part) : nullptr;
-#define GS_PB1(D, PO)                                                                         \
-  hipLaunchKernelGGL((k_project_bwd<D, PO>), dim3((unsigned)blocks), dim3(kProjThreads), 0, s, \
-                     g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, P.n, cams, P.vt,  \
-                     ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_tt),                \
-                     ws_at<uint32_t>(ws, P.off_poff),                                          \
-                     ws_at<float>(ws, P.off_grad_pair), ws_at<int32_t>(ws, P.off_flags),      \
-                     accumulate, out.means, out.log_scales, out.quats, out.opacity_logits,    \
-                     out.sh, pose_part, blocks)
-#define GS_PB(D)          \
-  if (pose_part)          \
-    GS_PB1(D, true);      \
-  else                    \
-    GS_PB1(D, false)
+  const bool compact = P.vt.n_views == 1;
+  if (compact && !accumulate) {
+    const int64_t K3 = 3 * (int64_t)P.K;
+    hipLaunchKernelGGL(k_zero_grads, dim3(2048), dim3(256), 0, s, out.means, 3 * P.n,
+                       out.log_scales, 3 * P.n, out.quats, 4 * P.n, out.opacity_logits, P.n,
+                       out.sh, K3 * P.n);
+  }
+#define GS_PB1(D, PO, CO)                                                                         \
+  hipLaunchKernelGGL((k_project_bwd<D, PO, CO>), dim3((unsigned)blocks), dim3(kProjThreads), 0, s, \
+                     g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, P.n, cams, P.vt,      \
+                     ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_tt),                    \
+                     ws_at<uint32_t>(ws, P.off_poff),                                              \
+                     ws_at<float>(ws, P.off_grad_pair), ws_at<int32_t>(ws, P.off_flags),          \
+                     ws_at<uint32_t>(ws, P.off_vis_list), accumulate, out.means, out.log_scales,  \
+                     out.quats, out.opacity_logits, out.sh, pose_part, blocks)
+#define GS_PB(D)                \
+  if (pose_part) {              \
+    if (compact)                \
+      GS_PB1(D, true, true);    \
+    else                        \
+      GS_PB1(D, true, false);   \
+  } else {                      \
+    if (compact)                \
+      GS_PB1(D, false, true);   \
+    else                        \
+      GS_PB1(D, false, false);  \
+  }
   switch (P.deg) {
     case 0: GS_PB(0); break;
     case 1: GS_PB(1); break;
