@@ -3,7 +3,7 @@
 
 One step = one full mapping iteration of the CaRtGS back-end on the
 1200x680 indoor RGB-D view with 300k SH-3 Gaussians: per-Gaussian projection,
-tile binning + radix sort, forward compositing with the L1 photometric + 0.1
+tile binning, forward compositing with the L1 photometric + 0.1
 depth loss against a target, backward (raster + projection), Adam.  The
 timed form replays one captured HIP graph per step; the eager per-call form
 is timed beside it.  Also reported: per-stage times (HIP events on the
@@ -36,6 +36,37 @@ LRS = {"means": 1.6e-4, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-
 # 14, alpha gradient 3, behind-sum update 8, opacity/exponent gradient 2,
 # conic and mean gradients 13  -> 60 flops (exp and rcp counted as one each)
 BWD_FLOPS_PER_POS = 60
+# HBM counter summary of the headline iteration (rocprofv3 FETCH_SIZE /
+# WRITE_SIZE, scaled by a 1 GiB copy); used only while the kernel sources
+# still hash to the value recorded with the counters
+COUNTERS = os.path.join(ROOT, "profiles", "iteration_1200x680_300k_hbm_counters.txt")
+KERNEL_SOURCES = ["gs_internal.h", "api.hip", "preprocess.hip", "binsort.hip", "render.hip",
+                  "project_bwd.hip", "adam.hip", "loss.hip", "densify.hip"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2410_00486_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """Scaled HBM bytes per dispatch of `kernel` from the committed counter
+    summary, or None if there is none or the kernel sources changed since."""
+    if not os.path.exists(COUNTERS):
+        return None
+    text = open(COUNTERS).read().splitlines()
+    src = [ln.split(":", 1)[1].strip() for ln in text if ln.startswith("kernel source sha1:")]
+    if not src or src[0] != kernel_source_hash():
+        return None
+    for ln in text:
+        parts = ln.split()
+        if parts and parts[0] == kernel:
+            return float(parts[-1]) * 1e6
+    return None
 
 
 def log(msg):
@@ -61,6 +92,8 @@ def main():
                     help="backward of the headline: pixel-wise wave-reduced or splat-wise")
     ap.add_argument("--no-ab", action="store_true",
                     help="skip timing the other backward variant")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the SSIM-loss, densification and scheduler timings")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--graph-only", action="store_true",
@@ -254,10 +287,11 @@ def main():
     bwd_tflops = BWD_FLOPS_PER_POS * E_bwd / (stage_ms["render_bwd_raster"] * 1e-3) / 1e12
     if dominant == "render_bwd_raster":
         kname = "k_render_bwd_splat" if args.bwd == "splat" else "k_render_bwd"
+        tile_t = f"<{tile[0]},{tile[1]}>"
         roofline = {"bound": "alu", "kernel": f"{kname} (gs_render_bwd_raster)",
                     "achieved": round(bwd_tflops, 3), "peak": FP32_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(bwd_tflops / FP32_PEAK_TFLOPS, 4),
-                    "traffic": None,
+                    "traffic": measured_traffic(kname + tile_t),
                     "work": f"{BWD_FLOPS_PER_POS} flop x {E_bwd} pixel-Gaussian positions"}
     else:
         gbs = bytes_[dominant] / (stage_ms[dominant] * 1e-3) / 1e9
@@ -297,6 +331,9 @@ def main():
         ab[args.bwd] = {"iters_per_s": result["value"],
                         "render_bwd_ms": round(stage_ms["render_bwd_raster"], 4)}
         result["backward_ab"] = ab
+    if not args.no_extras:
+        result["extras"] = bench_extras(args, w, plan, it, params, cams, view_wh, target_rgb,
+                                        target_depth, stream)
     it.close()
     del it
     torch.cuda.synchronize()
@@ -306,6 +343,86 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(result))
+
+
+def bench_extras(args, w, plan, it, params, cams, view_wh, target_rgb, target_depth, stream):
+    """The other rows of the path on the same view: the full Eq. (9) loss
+    with SSIM (standalone and inside the graphed iteration), densification
+    statistics and clone/split/prune of the 300k pool, keyframe selection."""
+    import torch
+
+    import paper_2410_00486_amd as gsr
+    from paper_2410_00486_amd.sched import KeyframeScheduler
+
+    dev = params.means.device
+    out = {}
+
+    def ev_time(fn, reps):
+        evs = []
+        with torch.cuda.stream(stream):
+            for _ in range(2):
+                fn()
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                fn()
+                b.record(stream)
+                evs.append((a, b))
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+    npx = plan.total_pixels
+    dLc = torch.empty(3 * npx, dtype=torch.float32, device=dev)
+    dLd = torch.empty(npx, dtype=torch.float32, device=dev)
+    out["ssim_loss_ms"] = round(ev_time(lambda: gsr.render_loss(
+        plan, it.ws, it.frame, target_rgb, target_depth, 0.2, dLc, dLd, stream), 20), 4)
+    accum = torch.zeros(params.n, dtype=torch.float32, device=dev)
+    denom = torch.zeros(params.n, dtype=torch.float32, device=dev)
+    out["grad_stats_ms"] = round(ev_time(lambda: gsr.grad_stats(plan, it.ws, accum, denom,
+                                                                 stream), 20), 4)
+    # clone/split/prune on a copy of the pool with statistics of one view
+    p2 = gsr.Gaussians(*[t.clone() for t in params.tensors()], params.sh_degree)
+    m2, v2 = p2.zeros_like(), p2.zeros_like()
+    normals = torch.randn(params.n, 2, 3, generator=torch.Generator().manual_seed(5)).to(dev)
+    times = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = gsr.densify_prune(p2, m2, v2, accum, denom, normals, stream=stream)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    out["densify_prune_ms"] = round(float(np.median(times)), 4)
+    out["densify_prune_out"] = int(res[0].n)
+    # graphed iteration with the SSIM term (lambda_ssim 0.2): the loss
+    # gradients come from the loss kernels, so the plan drops the fused L1
+    from paper_2410_00486_amd import _lib as L
+    plan_s = plan.replace(flags=plan.flags & ~L.GS_FUSED_L1)
+    it2 = gsr.Iteration(plan_s, gsr.Gaussians(*[t.clone() for t in params.tensors()],
+                                            params.sh_degree), cams, target_rgb=target_rgb,
+                        target_depth=target_depth, adam_lrs=LRS, lambda_ssim=0.2)
+    with torch.cuda.stream(stream):
+        it2.capture(stream)
+        for _ in range(args.warmup):
+            it2.replay(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(args.steps):
+            it2.replay(stream)
+    torch.cuda.synchronize()
+    out["iters_per_s_with_ssim"] = round(args.steps / (time.perf_counter() - t0), 2)
+    it2.close()
+    # keyframe selection (host): 1000 keyframes, one selection
+    ks = KeyframeScheduler(capacity=4096)
+    for k in range(1000):
+        ks.add_keyframe()
+        ks.report(k, 1.0 / (1 + k))
+    t0 = time.perf_counter()
+    for _ in range(100):
+        ks.select([0.5] * 8)
+    out["scheduler_select_us"] = round((time.perf_counter() - t0) * 1e4, 2)
+    log(f"extras: {out}")
+    return out
 
 
 def render_target(gsr, scene, cams, view_wh, dev, tile=(16, 16)):

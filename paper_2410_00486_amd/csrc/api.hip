@@ -237,6 +237,10 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_bucket_scan = take(splat ? (size_t)std::max<int64_t>(P->tile_scan_blocks, 1) * 8 : 0);
   P->off_boff = take(splat ? (T + 1) * 4 : 0);
   P->off_bq = take((size_t)P->ckpt_slots * 2 * 8);  // two bucket queues of (tile, k)
+  P->off_full_start = take(splat ? T * 4 : 0);
+  P->off_full_scan = take(splat ? (size_t)std::max<int64_t>(P->tile_scan_blocks, 1) * 8 : 0);
+  P->off_half_start = take(splat ? T * 4 : 0);
+  P->off_half_scan = take(splat ? (size_t)std::max<int64_t>(P->tile_scan_blocks, 1) * 8 : 0);
   P->off_ckpt = take((size_t)P->ckpt_slots * tw * th * kStateFloats * 4);
   P->ws_size = o;
   P->magic = kPlanMagic;

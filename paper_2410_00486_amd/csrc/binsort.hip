@@ -35,87 +35,135 @@ __global__ void k_fill2_u32(uint32_t* __restrict__ a, int64_t na, uint32_t* __re
 }
 
 // ---------------------------------------------------------------- scans
-// Block-local exclusive scan of u32 counts; block totals to block_tot.
-// Sums are 64-bit: a local offset is stored as u32, which is exact whenever
-// the total fits the pair capacity (< 2^31); otherwise the overflow flag
-// stops every consumer.  ZERO: the counts are cleared after reading (the
-// tile counters become the scatter's cursors).
-template <bool ZERO>
-__global__ void __launch_bounds__(kScanThreads) k_scan_local(uint32_t* __restrict__ cnt,
-                                                             uint32_t* __restrict__ off,
-                                                             uint64_t* __restrict__ block_tot,
-                                                             int64_t n,
-                                                             uint32_t* __restrict__ boff,
-                                                             uint64_t* __restrict__ bblock_tot,
-                                                             uint32_t* __restrict__ nzoff,
-                                                             uint64_t* __restrict__ nz_tot) {
-  __shared__ uint64_t wsum[kScanThreads / kWave], bsum[kScanThreads / kWave];
-  __shared__ uint32_t nzsum[kScanThreads / kWave];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
-  uint64_t s = 0, sb = 0;
-  uint32_t nz = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t idx = base + k;
-    v[k] = idx < n ? cnt[idx] : 0u;
-    s += v[k];
-    sb += (v[k] + kBucket - 1) / kBucket;
-    nz += v[k] > 0 ? 1u : 0u;
-  }
+// Block-level exclusive scans of per-element counts (kScanThreads threads x
+// kScanItems consecutive elements).  Sums are 64-bit: a block-local offset
+// is stored as u32, which is exact whenever the total fits the pair
+// capacity (< 2^31); otherwise the overflow flag stops every consumer.
+
+// Exclusive start of this thread's items within the block for a thread sum
+// s; the block total goes to *total.  Every thread of the block must call.
+__device__ __forceinline__ uint64_t scan_start(uint64_t s, uint64_t* wsum, uint64_t* total) {
   const int lane = lane_id(), w = threadIdx.x / kWave;
-  uint64_t incl = s, bincl = sb;
+  uint64_t incl = s;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
     const uint64_t y = __shfl_up(incl, o, kWave);
-    const uint64_t yb = __shfl_up(bincl, o, kWave);
-    if (lane >= o) {
-      incl += y;
-      bincl += yb;
-    }
+    if (lane >= o) incl += y;
   }
-  if (lane == kWave - 1) {
-    wsum[w] = incl;
-    bsum[w] = bincl;
-  }
-  // nonzero entries: local exclusive prefix (the compact visible list)
-  uint32_t nzincl = nz;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const uint32_t y = __shfl_up(nzincl, o, kWave);
-    if (lane >= o) nzincl += y;
-  }
-  if (lane == kWave - 1) nzsum[w] = nzincl;
+  if (lane == kWave - 1) wsum[w] = incl;
   __syncthreads();
-  uint64_t woff = 0, bwoff = 0;
-  for (int k = 0; k < w; ++k) {
-    woff += wsum[k];
-    bwoff += bsum[k];
+  uint64_t woff = 0, tot = 0;
+  for (int k = 0; k < kScanThreads / kWave; ++k) {
+    woff += k < w ? wsum[k] : 0ull;
+    tot += wsum[k];
   }
-  uint32_t nzrun = nzincl - nz;
-  for (int k = 0; k < w; ++k) nzrun += nzsum[k];
-  uint64_t run = woff + incl - s, brun = bwoff + bincl - sb;
+  __syncthreads();  // wsum is reused by the next channel
+  *total = tot;
+  return woff + incl - s;
+}
+
+// Records: pair counts -> generation offsets (poff); visible (non-zero)
+// records -> position in the compact visible list (vpre).
+__global__ void __launch_bounds__(kScanThreads) k_scan_records(
+    const uint32_t* __restrict__ tt, uint32_t* __restrict__ poff, uint64_t* __restrict__ rec_tot,
+    uint32_t* __restrict__ vpre, uint64_t* __restrict__ vis_tot, int64_t n) {
+  __shared__ uint64_t wsum[kScanThreads / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint64_t sp = 0, sv = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = base + k;
+    v[k] = idx < n ? tt[idx] : 0u;
+    sp += v[k];
+    sv += v[k] > 0 ? 1u : 0u;
+  }
+  uint64_t tp, tv;
+  uint64_t rp = scan_start(sp, wsum, &tp);
+  uint64_t rv = scan_start(sv, wsum, &tv);
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t idx = base + k;
     if (idx < n) {
-      off[idx] = (uint32_t)run;
-      if (boff) boff[idx] = (uint32_t)brun;
-      if (nzoff) nzoff[idx] = nzrun;
-      if (ZERO) cnt[idx] = 0u;
+      poff[idx] = (uint32_t)rp;
+      vpre[idx] = (uint32_t)rv;
     }
-    run += v[k];
-    brun += (v[k] + kBucket - 1) / kBucket;
-    nzrun += v[k] > 0 ? 1u : 0u;
+    rp += v[k];
+    rv += v[k] > 0 ? 1u : 0u;
   }
-  if (threadIdx.x == kScanThreads - 1) {
-    block_tot[blockIdx.x] = run;
-    if (bblock_tot) bblock_tot[blockIdx.x] = brun;
+  if (threadIdx.x == 0) {
+    rec_tot[blockIdx.x] = tp;
+    vis_tot[blockIdx.x] = tv;
   }
-  if (nz_tot && threadIdx.x == 0) {
-    uint64_t t = 0;
-    for (int k = 0; k < kScanThreads / kWave; ++k) t += nzsum[k];
-    nz_tot[blockIdx.x] = t;
+}
+
+// Tiles: pair counts -> list starts (the counters are cleared and become
+// the scatter's cursors).  With the splat-wise backward also the starts of
+// each tile's buckets of 64 positions, and its positions in the two bucket
+// queues: buckets with more than 32 pairs (all but possibly the last) and
+// buckets with at most 32 (possibly the last).
+__device__ __forceinline__ void bucket_split(uint32_t c, uint32_t& nb, uint32_t& full,
+                                             uint32_t& half) {
+  nb = (c + kBucket - 1) / kBucket;
+  const uint32_t r = c - (nb > 0 ? (nb - 1) * kBucket : 0u);  // pairs of the last bucket
+  half = (c > 0 && r <= 32) ? 1u : 0u;
+  full = nb - half;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(
+    uint32_t* __restrict__ cnt, uint32_t* __restrict__ tstart, uint64_t* __restrict__ tile_tot,
+    int64_t n, uint32_t* __restrict__ bstart, uint64_t* __restrict__ bucket_tot,
+    uint32_t* __restrict__ fstart, uint64_t* __restrict__ full_tot,
+    uint32_t* __restrict__ hstart, uint64_t* __restrict__ half_tot) {
+  __shared__ uint64_t wsum[kScanThreads / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint64_t sp = 0, sb = 0, sf = 0, sh = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = base + k;
+    v[k] = idx < n ? cnt[idx] : 0u;
+    uint32_t nb, f, h;
+    bucket_split(v[k], nb, f, h);
+    sp += v[k];
+    sb += nb;
+    sf += f;
+    sh += h;
+  }
+  uint64_t tp, tb, tf, th;
+  uint64_t rp = scan_start(sp, wsum, &tp);
+  uint64_t rb = 0, rf = 0, rh = 0;
+  if (bstart) {  // uniform
+    rb = scan_start(sb, wsum, &tb);
+    rf = scan_start(sf, wsum, &tf);
+    rh = scan_start(sh, wsum, &th);
+  }
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = base + k;
+    uint32_t nb, f, h;
+    bucket_split(v[k], nb, f, h);
+    if (idx < n) {
+      tstart[idx] = (uint32_t)rp;
+      cnt[idx] = 0u;
+      if (bstart) {
+        bstart[idx] = (uint32_t)rb;
+        fstart[idx] = (uint32_t)rf;
+        hstart[idx] = (uint32_t)rh;
+      }
+    }
+    rp += v[k];
+    rb += nb;
+    rf += f;
+    rh += h;
+  }
+  if (threadIdx.x == 0) {
+    tile_tot[blockIdx.x] = tp;
+    if (bstart) {
+      bucket_tot[blockIdx.x] = tb;
+      full_tot[blockIdx.x] = tf;
+      half_tot[blockIdx.x] = th;
+    }
   }
 }
 
@@ -152,29 +200,33 @@ __device__ uint64_t block_scan_u64(uint64_t* __restrict__ a, int64_t n, uint64_t
 // Exclusive scans of the record and tile block totals (one block); total
 // pair count and the capacity check.  Both scans count the same pairs; a
 // mismatch is reported as an overflow so that nothing is scattered.
-__global__ void __launch_bounds__(1024) k_scan_totals(uint64_t* __restrict__ rec_tot,
-                                                      int64_t n_rec_blocks,
-                                                      uint64_t* __restrict__ tile_tot,
-                                                      int64_t n_tile_blocks,
-                                                      uint64_t* __restrict__ bucket_tot,
-                                                      uint64_t* __restrict__ vis_tot, int64_t cap,
-                                                      int32_t* __restrict__ fl) {
+__global__ void __launch_bounds__(1024) k_scan_totals(
+    uint64_t* __restrict__ rec_tot, uint64_t* __restrict__ vis_tot, int64_t n_rec_blocks,
+    uint64_t* __restrict__ tile_tot, uint64_t* __restrict__ bucket_tot,
+    uint64_t* __restrict__ full_tot, uint64_t* __restrict__ half_tot, int64_t n_tile_blocks,
+    int64_t cap, int32_t* __restrict__ fl) {
   __shared__ uint64_t wsum[1024 / kWave];
   __shared__ uint64_t carry;
   const uint64_t total = block_scan_u64(rec_tot, n_rec_blocks, wsum, &carry);
   const uint64_t visible = block_scan_u64(vis_tot, n_rec_blocks, wsum, &carry);
   const uint64_t total_t = block_scan_u64(tile_tot, n_tile_blocks, wsum, &carry);
-  if (bucket_tot) block_scan_u64(bucket_tot, n_tile_blocks, wsum, &carry);
+  uint64_t n_full = 0, n_half = 0;
+  if (bucket_tot) {
+    block_scan_u64(bucket_tot, n_tile_blocks, wsum, &carry);
+    n_full = block_scan_u64(full_tot, n_tile_blocks, wsum, &carry);
+    n_half = block_scan_u64(half_tot, n_tile_blocks, wsum, &carry);
+  }
   if (threadIdx.x == 0) {
     const bool over = total > (uint64_t)cap || total != total_t;
     fl[F_OVERFLOW] = over ? 1 : 0;
     fl[F_PAIRS] = over ? 0 : (int32_t)total;
     fl[F_PAIRS_WANTED] = total > 0x7FFFFFFFull ? 0x7FFFFFFF : (int32_t)total;
     fl[F_VISIBLE] = (int32_t)visible;
-    // queue counters filled by the tile sort that follows
+    // long lists are queued by the tile sort that follows; the bucket
+    // queues are filled there at the positions scanned here
     fl[F_LONG_TILES] = 0;
-    fl[F_BQ_FULL] = 0;
-    fl[F_BQ_HALF] = 0;
+    fl[F_BQ_FULL] = over ? 0 : (int32_t)n_full;
+    fl[F_BQ_HALF] = over ? 0 : (int32_t)n_half;
   }
 }
 
@@ -324,6 +376,8 @@ __global__ void __launch_bounds__(kWave) k_tile_sort(
     const uint64_t* __restrict__ skey, TileSortOut out, uint32_t* __restrict__ ranges,
     uint32_t* __restrict__ long_list, const uint32_t* __restrict__ bstart,
     const uint64_t* __restrict__ bucket_pre, uint32_t* __restrict__ boff,
+    const uint32_t* __restrict__ fstart, const uint64_t* __restrict__ full_pre,
+    const uint32_t* __restrict__ hstart, const uint64_t* __restrict__ half_pre,
     uint2* __restrict__ bq, int64_t bq_stride) {
   __shared__ uint64_t sk[kTileSortSmall];
   const int t = blockIdx.x;
@@ -343,14 +397,15 @@ __global__ void __launch_bounds__(kWave) k_tile_sort(
     if (ok && n > kTileSortSmall) long_list[atomicAdd(&fl[F_LONG_TILES], 1)] = (uint32_t)t;
   }
   if (boff && ok) {
-    // splat-wise work queues: buckets with more than 32 pairs, and the rest
-    const uint32_t nb = (n + kBucket - 1) / kBucket;
-    for (uint32_t k = lane; k < nb; k += kWave) {
-      const uint32_t c = min((uint32_t)kBucket, n - k * kBucket);
-      const int q = c > 32 ? 0 : 1;
-      const int at = atomicAdd(&fl[F_BQ_FULL + q], 1);
-      bq[q * bq_stride + at] = make_uint2((uint32_t)t, k);
-    }
+    // splat-wise work queues at the scanned positions: the tile's buckets
+    // 0 .. full-1 have more than 32 pairs; a last bucket with at most 32
+    // goes to the second queue
+    uint32_t nb, full, half;
+    bucket_split(n, nb, full, half);
+    const uint32_t f0 = fstart[t] + (uint32_t)full_pre[t / kScanTile];
+    for (uint32_t k = lane; k < full; k += kWave) bq[f0 + k] = make_uint2((uint32_t)t, k);
+    if (half && lane == 0)
+      bq[bq_stride + hstart[t] + (uint32_t)half_pre[t / kScanTile]] = make_uint2((uint32_t)t, nb - 1);
   }
   if (!ok || n > kTileSortSmall) return;
   const uint32_t start = (uint32_t)start64;
@@ -655,15 +710,19 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
   uint32_t* boff = splat ? ws_at<uint32_t>(ws, P.off_boff) : nullptr;
   const int T = P.vt.total_tiles;
   const int64_t sb = P.scan_blocks, tb = P.tile_scan_blocks;
+  uint32_t* fstart = splat ? ws_at<uint32_t>(ws, P.off_full_start) : nullptr;
+  uint64_t* full_tot = splat ? ws_at<uint64_t>(ws, P.off_full_scan) : nullptr;
+  uint32_t* hstart = splat ? ws_at<uint32_t>(ws, P.off_half_start) : nullptr;
+  uint64_t* half_tot = splat ? ws_at<uint64_t>(ws, P.off_half_scan) : nullptr;
   if (sb > 0)
-    hipLaunchKernelGGL(k_scan_local<false>, dim3((unsigned)sb), dim3(kScanThreads), 0, s, tt,
-                       poff, rec_tot, P.n_rec, nullptr, nullptr, ws_at<uint32_t>(ws, P.off_vpre),
-                       vis_tot);
+    hipLaunchKernelGGL(k_scan_records, dim3((unsigned)sb), dim3(kScanThreads), 0, s, tt, poff,
+                       rec_tot, ws_at<uint32_t>(ws, P.off_vpre), vis_tot, P.n_rec);
   if (tb > 0)
-    hipLaunchKernelGGL(k_scan_local<true>, dim3((unsigned)tb), dim3(kScanThreads), 0, s, tcnt,
-                       tstart, tile_tot, (int64_t)T, bstart, bucket_tot, nullptr, nullptr);
-  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, rec_tot, sb, tile_tot, tb,
-                     bucket_tot, vis_tot, P.pair_cap, fl);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tb), dim3(kScanThreads), 0, s, tcnt, tstart,
+                       tile_tot, (int64_t)T, bstart, bucket_tot, fstart, full_tot, hstart,
+                       half_tot);
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, rec_tot, vis_tot, sb, tile_tot,
+                     bucket_tot, full_tot, half_tot, tb, P.pair_cap, fl);
   uint64_t* skey = ws_at<uint64_t>(ws, P.off_scatter);
   uint32_t* pair_rec = ws_at<uint32_t>(ws, P.off_pair_rec);
   if (P.n_rec > 0) {
@@ -680,8 +739,8 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
     uint32_t* long_list = ws_at<uint32_t>(ws, P.off_long);
     hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)T), dim3(kWave), 0, s, tcnt, tstart, tile_tot,
                        T, fl, skey, out, ws_at<uint32_t>(ws, P.off_ranges), long_list, bstart,
-                       bucket_tot, boff, splat ? ws_at<uint2>(ws, P.off_bq) : nullptr,
-                       P.ckpt_slots);
+                       bucket_tot, boff, fstart, full_tot, hstart, half_tot,
+                       splat ? ws_at<uint2>(ws, P.off_bq) : nullptr, P.ckpt_slots);
     const int long_grid = (int)std::min<int64_t>(T, 256);
     hipLaunchKernelGGL(k_tile_sort_long, dim3((unsigned)long_grid), dim3(kLongThreads), 0, s,
                        tcnt, tstart, tile_tot, fl, long_list, skey, out);

@@ -89,6 +89,7 @@ struct Plan {
   size_t off_ssim_maps, off_ssim_part;
   // splat-wise backward: bucket offsets (local, block sums, absolute), pixel states
   size_t off_bucket_start, off_bucket_scan, off_boff, off_bq, off_ckpt;
+  size_t off_full_start, off_full_scan, off_half_start, off_half_scan;
   int64_t ckpt_slots;
   size_t ws_size;
 };

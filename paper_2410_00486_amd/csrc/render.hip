@@ -228,7 +228,9 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ rec,
           }
         }
       }
-      if (ballot64(active()) == 0) break;
+      // finished lanes skip the work, so the early exit is tested every
+      // fourth splat only
+      if ((j & 3) == 3 && ballot64(active()) == 0) break;
     }
   }
   const float* cam = cams + (int64_t)v * GS_CAMERA_FLOATS;
@@ -423,6 +425,7 @@ __device__ __forceinline__ void bwd_tile(
     __syncthreads();
     stage(srec, sval, rec, sorted_rec, sorted_vals, s + (uint32_t)bstart, nb, lane);
     __syncthreads();
+#pragma unroll 2
     for (int j = nb - 1; j >= 0; --j) {
       const uint32_t pos = (uint32_t)(bstart + j);
       const Rec& r = srec[j];
@@ -650,6 +653,7 @@ __device__ __forceinline__ void splat_wave(
   for (int f = 0; f < 10; ++f) g[f] = 0.0f;
   float Tout = 1.0f, Qout = 0.0f;
   const int steps = NPX + nl_max - 1;
+#pragma unroll 2
   for (int t = 0; t < steps; ++t) {
     float Tc = dpp<0x138>(Tout);  // wave_shr:1, state of lane - 1
     float Qc = dpp<0x138>(Qout);
