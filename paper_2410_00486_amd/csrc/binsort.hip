@@ -167,56 +167,68 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(
   }
 }
 
-// In-place exclusive scan of n u64 values by one 1024-thread block; returns
-// the total in every thread.
-__device__ uint64_t block_scan_u64(uint64_t* __restrict__ a, int64_t n, uint64_t* wsum,
-                                   uint64_t* carry) {
+// In-place exclusive scans of up to six u64 arrays at once by one
+// 1024-thread block (each array has its own length); totals to tot[].
+constexpr int kMaxChannels = 6;
+struct ScanChannels {
+  uint64_t* a[kMaxChannels];
+  int64_t n[kMaxChannels];
+  int count;
+};
+
+__device__ void block_scan_channels(const ScanChannels& ch, uint64_t* tot) {
+  __shared__ uint64_t wsum[kMaxChannels][1024 / kWave];
+  __shared__ uint64_t carry[kMaxChannels];
   const int lane = lane_id(), w = threadIdx.x / kWave;
-  if (threadIdx.x == 0) *carry = 0;
+  if (threadIdx.x < kMaxChannels) carry[threadIdx.x] = 0;
+  int64_t nmax = 0;
+  for (int c = 0; c < ch.count; ++c) nmax = ch.n[c] > nmax ? ch.n[c] : nmax;
   __syncthreads();
-  for (int64_t base = 0; base < n; base += 1024) {
+  for (int64_t base = 0; base < nmax; base += 1024) {
     const int64_t idx = base + threadIdx.x;
-    const uint64_t x = idx < n ? a[idx] : 0ull;
-    uint64_t incl = x;
+    uint64_t x[kMaxChannels], incl[kMaxChannels];
+#pragma unroll
+    for (int c = 0; c < kMaxChannels; ++c) {
+      x[c] = (c < ch.count && idx < ch.n[c]) ? ch.a[c][idx] : 0ull;
+      incl[c] = x[c];
+    }
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
-      const uint64_t y = __shfl_up(incl, o, kWave);
-      if (lane >= o) incl += y;
+#pragma unroll
+      for (int c = 0; c < kMaxChannels; ++c) {
+        const uint64_t y = __shfl_up(incl[c], o, kWave);
+        if (lane >= o) incl[c] += y;
+      }
     }
-    if (lane == kWave - 1) wsum[w] = incl;
+    if (lane == kWave - 1)
+      for (int c = 0; c < kMaxChannels; ++c) wsum[c][w] = incl[c];
     __syncthreads();
-    uint64_t woff = *carry;
-    for (int k = 0; k < w; ++k) woff += wsum[k];
-    if (idx < n) a[idx] = woff + incl - x;
+#pragma unroll
+    for (int c = 0; c < kMaxChannels; ++c) {
+      uint64_t woff = carry[c];
+      for (int k = 0; k < w; ++k) woff += wsum[c][k];
+      if (c < ch.count && idx < ch.n[c]) ch.a[c][idx] = woff + incl[c] - x[c];
+      if (threadIdx.x == 1023) incl[c] = woff + incl[c];  // running total
+    }
     __syncthreads();
-    if (threadIdx.x == 1023) *carry = woff + incl;
+    if (threadIdx.x == 1023)
+      for (int c = 0; c < kMaxChannels; ++c) carry[c] = incl[c];
     __syncthreads();
   }
-  const uint64_t total = *carry;
-  __syncthreads();  // every thread has read the total before a next call resets it
-  return total;
+  for (int c = 0; c < kMaxChannels; ++c) tot[c] = carry[c];
 }
 
-// Exclusive scans of the record and tile block totals (one block); total
-// pair count and the capacity check.  Both scans count the same pairs; a
-// mismatch is reported as an overflow so that nothing is scattered.
-__global__ void __launch_bounds__(1024) k_scan_totals(
-    uint64_t* __restrict__ rec_tot, uint64_t* __restrict__ vis_tot, int64_t n_rec_blocks,
-    uint64_t* __restrict__ tile_tot, uint64_t* __restrict__ bucket_tot,
-    uint64_t* __restrict__ full_tot, uint64_t* __restrict__ half_tot, int64_t n_tile_blocks,
-    int64_t cap, int32_t* __restrict__ fl) {
-  __shared__ uint64_t wsum[1024 / kWave];
-  __shared__ uint64_t carry;
-  const uint64_t total = block_scan_u64(rec_tot, n_rec_blocks, wsum, &carry);
-  const uint64_t visible = block_scan_u64(vis_tot, n_rec_blocks, wsum, &carry);
-  const uint64_t total_t = block_scan_u64(tile_tot, n_tile_blocks, wsum, &carry);
-  uint64_t n_full = 0, n_half = 0;
-  if (bucket_tot) {
-    block_scan_u64(bucket_tot, n_tile_blocks, wsum, &carry);
-    n_full = block_scan_u64(full_tot, n_tile_blocks, wsum, &carry);
-    n_half = block_scan_u64(half_tot, n_tile_blocks, wsum, &carry);
-  }
+// Exclusive scans of the block totals of the record scan (pairs, visible)
+// and of the tile scan (pairs, buckets, full and half buckets): one block.
+// Both pair totals count the same pairs; a mismatch is reported as an
+// overflow so that nothing is scattered.
+__global__ void __launch_bounds__(1024) k_scan_totals(ScanChannels ch, int64_t cap,
+                                                      int32_t* __restrict__ fl) {
+  uint64_t tot[kMaxChannels];
+  block_scan_channels(ch, tot);
   if (threadIdx.x == 0) {
+    const uint64_t total = tot[0], visible = tot[1], total_t = tot[2];
+    const uint64_t n_full = ch.count > 4 ? tot[4] : 0, n_half = ch.count > 5 ? tot[5] : 0;
     const bool over = total > (uint64_t)cap || total != total_t;
     fl[F_OVERFLOW] = over ? 1 : 0;
     fl[F_PAIRS] = over ? 0 : (int32_t)total;
@@ -721,8 +733,9 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tb), dim3(kScanThreads), 0, s, tcnt, tstart,
                        tile_tot, (int64_t)T, bstart, bucket_tot, fstart, full_tot, hstart,
                        half_tot);
-  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, rec_tot, vis_tot, sb, tile_tot,
-                     bucket_tot, full_tot, half_tot, tb, P.pair_cap, fl);
+  ScanChannels ch{{rec_tot, vis_tot, tile_tot, bucket_tot, full_tot, half_tot},
+                  {sb, sb, tb, tb, tb, tb}, splat ? 6 : 3};
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, ch, P.pair_cap, fl);
   uint64_t* skey = ws_at<uint64_t>(ws, P.off_scatter);
   uint32_t* pair_rec = ws_at<uint32_t>(ws, P.off_pair_rec);
   if (P.n_rec > 0) {

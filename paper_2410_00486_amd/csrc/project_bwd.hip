@@ -135,12 +135,26 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
       // fixed-order sum of this (view, Gaussian)'s pair partials
       double g2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       const float4* gpp = reinterpret_cast<const float4*>(grad_pair + (int64_t)poff[ri] * kPairGrad);
-      for (uint32_t k = 0; k < cnt; ++k) {
-        const float4 a = gpp[3 * k], b = gpp[3 * k + 1], c = gpp[3 * k + 2];
+      // loads of eight pairs are issued before their (in-order) additions,
+      // so a large Gaussian does not pay one memory round trip per tile
+      auto add = [&](const float4& a, const float4& b, const float4& c) {
         g2[0] += a.x; g2[1] += a.y; g2[2] += a.z; g2[3] += a.w;
         g2[4] += b.x; g2[5] += b.y; g2[6] += b.z; g2[7] += b.w;
         g2[8] += c.x; g2[9] += c.y;
+      };
+      uint32_t k = 0;
+      for (; k + 8 <= cnt; k += 8) {
+        float4 a[8], b[8], c[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          a[u] = gpp[3 * (k + u)];
+          b[u] = gpp[3 * (k + u) + 1];
+          c[u] = gpp[3 * (k + u) + 2];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) add(a[u], b[u], c[u]);
       }
+      for (; k < cnt; ++k) add(gpp[3 * k], gpp[3 * k + 1], gpp[3 * k + 2]);
       gop += g2[4];
       const float* c = cams + (int64_t)v * GS_CAMERA_FLOATS;
       const double fx = c[0], fy = c[1];

@@ -228,9 +228,7 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ rec,
           }
         }
       }
-      // finished lanes skip the work, so the early exit is tested every
-      // fourth splat only
-      if ((j & 3) == 3 && ballot64(active()) == 0) break;
+      if (ballot64(active()) == 0) break;
     }
   }
   const float* cam = cams + (int64_t)v * GS_CAMERA_FLOATS;
