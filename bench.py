@@ -388,7 +388,7 @@ def bench_extras(args, w, plan, it, params, cams, view_wh, target_rgb, target_de
     for _ in range(5):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = gsr.densify_prune(p2, m2, v2, accum, denom, normals, stream=stream)
+        res = gsr.densify_prune(p2, m2, v2, accum, denom, normals)  # reads its count
         torch.cuda.synchronize()
         times.append((time.perf_counter() - t0) * 1e3)
     out["densify_prune_ms"] = round(float(np.median(times)), 4)

@@ -64,8 +64,9 @@ typedef int32_t gs_status;
 #define GS_FUSED_L1 (1u << 1)         /* gs_render_bwd derives dL/dC, dL/dD from the L1
                                          loss against the targets instead of inputs */
 #define GS_ACCUMULATE_GRADS (1u << 2) /* gs_render_bwd adds into the gradient buffers */
-#define GS_PERSISTENT (1u << 3)       /* render kernels pull tile chunks from a device
-                                         work queue (longest tiles first) */
+#define GS_PERSISTENT (1u << 3)       /* render kernels are resident and walk the
+                                         tiles in chunks, longest tiles first, with a
+                                         static stride */
 #define GS_SPLAT_BWD (1u << 4)        /* splat-wise backward (Sec. III-C-1, Fig. 4a):
                                          the forward stores per-pixel (T, RGB, D) states
                                          at every 64th splat of a tile; the backward

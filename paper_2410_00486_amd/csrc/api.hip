@@ -337,7 +337,6 @@ gs_status gs_render_fwd(const gs_plan* plan, void* ws, const float* cams_dev, fl
   const bool pers = (P.cfg.flags & GS_PERSISTENT) != 0;
   int32_t* fl = ws_at<int32_t>(ws, P.off_flags);
   hipError_t e = hipSuccess;
-  if (pers) e = launch_set_i32(fl + F_QUEUE_FWD, 0, s);
   if (e == hipSuccess)
     e = launch_render_fwd(P, ws, cams_dev, color, depth, T_final, last, target_rgb, target_depth,
                           loss_per_view, pers ? ws_at<uint32_t>(ws, P.off_order) : nullptr,
@@ -369,7 +368,6 @@ gs_status gs_render_bwd_raster(const gs_plan* plan, void* ws, const float* cams_
   const bool pers = !splat && (P.cfg.flags & GS_PERSISTENT) != 0;
   int32_t* fl = ws_at<int32_t>(ws, P.off_flags);
   hipError_t e = hipSuccess;
-  if (pers) e = launch_set_i32(fl + F_QUEUE_BWD, 0, s);
   // splat-wise: grid-stride over the buckets, as many waves as stay resident
   const int grid = splat ? (int)std::max<int64_t>(1, std::min<int64_t>(P.ckpt_slots, (int64_t)device_cus() * splat_blocks_per_cu(P)))
                          : (pers ? persistent_grid(P, true) : P.vt.total_tiles);

@@ -64,11 +64,11 @@ __device__ __forceinline__ uint64_t scan_start(uint64_t s, uint64_t* wsum, uint6
 
 // Records: pair counts -> generation offsets (poff); visible (non-zero)
 // records -> position in the compact visible list (vpre).
-__global__ void __launch_bounds__(kScanThreads) k_scan_records(
-    const uint32_t* __restrict__ tt, uint32_t* __restrict__ poff, uint64_t* __restrict__ rec_tot,
-    uint32_t* __restrict__ vpre, uint64_t* __restrict__ vis_tot, int64_t n) {
-  __shared__ uint64_t wsum[kScanThreads / kWave];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+__device__ void scan_records(int64_t blk, const uint32_t* __restrict__ tt,
+                             uint32_t* __restrict__ poff, uint64_t* __restrict__ rec_tot,
+                             uint32_t* __restrict__ vpre, uint64_t* __restrict__ vis_tot,
+                             int64_t n, uint64_t* wsum) {
+  const int64_t base = blk * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
   uint64_t sp = 0, sv = 0;
 #pragma unroll
@@ -92,8 +92,8 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_records(
     rv += v[k] > 0 ? 1u : 0u;
   }
   if (threadIdx.x == 0) {
-    rec_tot[blockIdx.x] = tp;
-    vis_tot[blockIdx.x] = tv;
+    rec_tot[blk] = tp;
+    vis_tot[blk] = tv;
   }
 }
 
@@ -110,13 +110,27 @@ __device__ __forceinline__ void bucket_split(uint32_t c, uint32_t& nb, uint32_t&
   full = nb - half;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(
-    uint32_t* __restrict__ cnt, uint32_t* __restrict__ tstart, uint64_t* __restrict__ tile_tot,
-    int64_t n, uint32_t* __restrict__ bstart, uint64_t* __restrict__ bucket_tot,
-    uint32_t* __restrict__ fstart, uint64_t* __restrict__ full_tot,
-    uint32_t* __restrict__ hstart, uint64_t* __restrict__ half_tot) {
-  __shared__ uint64_t wsum[kScanThreads / kWave];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+struct TileScanArgs {
+  uint32_t* cnt;
+  uint32_t* tstart;
+  uint64_t* tile_tot;
+  int64_t n;
+  uint32_t* bstart;
+  uint64_t* bucket_tot;
+  uint32_t* fstart;
+  uint64_t* full_tot;
+  uint32_t* hstart;
+  uint64_t* half_tot;
+};
+
+__device__ void scan_tiles(int64_t blk, const TileScanArgs& A, uint64_t* wsum) {
+  uint32_t* __restrict__ cnt = A.cnt;
+  uint32_t* __restrict__ tstart = A.tstart;
+  uint32_t* __restrict__ bstart = A.bstart;
+  uint32_t* __restrict__ fstart = A.fstart;
+  uint32_t* __restrict__ hstart = A.hstart;
+  const int64_t n = A.n;
+  const int64_t base = blk * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
   uint64_t sp = 0, sb = 0, sf = 0, sh = 0;
 #pragma unroll
@@ -158,13 +172,25 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(
     rh += h;
   }
   if (threadIdx.x == 0) {
-    tile_tot[blockIdx.x] = tp;
+    A.tile_tot[blk] = tp;
     if (bstart) {
-      bucket_tot[blockIdx.x] = tb;
-      full_tot[blockIdx.x] = tf;
-      half_tot[blockIdx.x] = th;
+      A.bucket_tot[blk] = tb;
+      A.full_tot[blk] = tf;
+      A.half_tot[blk] = th;
     }
   }
+}
+
+// Record blocks first, then tile blocks: one launch for both scans.
+__global__ void __launch_bounds__(kScanThreads) k_scans(
+    const uint32_t* __restrict__ tt, uint32_t* __restrict__ poff, uint64_t* __restrict__ rec_tot,
+    uint32_t* __restrict__ vpre, uint64_t* __restrict__ vis_tot, int64_t n_rec,
+    int64_t rec_blocks, TileScanArgs tiles) {
+  __shared__ uint64_t wsum[kScanThreads / kWave];
+  if ((int64_t)blockIdx.x < rec_blocks)
+    scan_records(blockIdx.x, tt, poff, rec_tot, vpre, vis_tot, n_rec, wsum);
+  else
+    scan_tiles((int64_t)blockIdx.x - rec_blocks, tiles, wsum);
 }
 
 // In-place exclusive scans of up to six u64 arrays at once by one
@@ -726,13 +752,12 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
   uint64_t* full_tot = splat ? ws_at<uint64_t>(ws, P.off_full_scan) : nullptr;
   uint32_t* hstart = splat ? ws_at<uint32_t>(ws, P.off_half_start) : nullptr;
   uint64_t* half_tot = splat ? ws_at<uint64_t>(ws, P.off_half_scan) : nullptr;
-  if (sb > 0)
-    hipLaunchKernelGGL(k_scan_records, dim3((unsigned)sb), dim3(kScanThreads), 0, s, tt, poff,
-                       rec_tot, ws_at<uint32_t>(ws, P.off_vpre), vis_tot, P.n_rec);
-  if (tb > 0)
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tb), dim3(kScanThreads), 0, s, tcnt, tstart,
-                       tile_tot, (int64_t)T, bstart, bucket_tot, fstart, full_tot, hstart,
-                       half_tot);
+  if (sb + tb > 0) {
+    TileScanArgs ta{tcnt, tstart, tile_tot, (int64_t)T, bstart, bucket_tot, fstart, full_tot,
+                    hstart, half_tot};
+    hipLaunchKernelGGL(k_scans, dim3((unsigned)(sb + tb)), dim3(kScanThreads), 0, s, tt, poff,
+                       rec_tot, ws_at<uint32_t>(ws, P.off_vpre), vis_tot, P.n_rec, sb, ta);
+  }
   ScanChannels ch{{rec_tot, vis_tot, tile_tot, bucket_tot, full_tot, half_tot},
                   {sb, sb, tb, tb, tb, tb}, splat ? 6 : 3};
   hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, ch, P.pair_cap, fl);

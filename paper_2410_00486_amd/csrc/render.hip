@@ -289,13 +289,11 @@ __global__ void __launch_bounds__(kWave) k_render_fwd(
                            tile_last, target_rgb, target_depth, tile_loss, boff, ckpt, srec);
     return;
   }
-  // persistent: pull chunks of `chunk` tiles until the queue is drained
+  // persistent: chunks of `chunk` tiles of the work order, taken with a
+  // static stride (the order is longest first, so the first round takes the
+  // longest tiles; no shared counter)
   const int n_items = (vt.total_tiles + chunk - 1) / chunk;
-  for (;;) {
-    int item = 0;
-    if (threadIdx.x == 0) item = atomicAdd(queue, 1);
-    item = __builtin_amdgcn_readfirstlane(item);
-    if (item >= n_items) break;
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
     const int first = item * chunk;
     const int lastt = min(vt.total_tiles, first + chunk);
     for (int k = first; k < lastt; ++k) {
@@ -502,11 +500,7 @@ __global__ void __launch_bounds__(kWave) k_render_bwd(
     return;
   }
   const int n_items = (vt.total_tiles + chunk - 1) / chunk;
-  for (;;) {
-    int item = 0;
-    if (threadIdx.x == 0) item = atomicAdd(queue, 1);
-    item = __builtin_amdgcn_readfirstlane(item);
-    if (item >= n_items) break;
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
     const int first = item * chunk;
     const int lastt = min(vt.total_tiles, first + chunk);
     for (int k = first; k < lastt; ++k) {
