@@ -276,9 +276,9 @@ def main():
     N, K = w.scene.n, 16
     bytes_ = {
         "preprocess": 44 * N + 12 * K * V + 72 * V + 4 * N,
-        "bin_sort": 16 * N + 12 * V + 40 * P + 20 * plan.total_tiles,
-        "render_fwd": 68 * P + 40 * npx,
-        "render_bwd_raster": 120 * P + 40 * npx,
+        "bin_sort": 16 * N + 12 * V + 168 * P + 20 * plan.total_tiles,
+        "render_fwd": 64 * P + 40 * npx,
+        "render_bwd_raster": 116 * P + 40 * npx,
         "project_bwd": 44 * N + 12 * K * V + 236 * N + 8 * N + 48 * P,
         "adam": 28 * 59 * N,
     }

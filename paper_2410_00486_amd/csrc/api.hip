@@ -217,6 +217,7 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_vals = take(cap * 4);
   P->off_pair_rec = take(cap * 4);
   P->off_sorted_rec = take(cap * 4);
+  P->off_srec = take(cap * sizeof(Rec));
   P->off_hist = take((size_t)kRadix * std::max<int64_t>(order_blocks, 1) * 4);
   P->off_digit_tot = take(kRadix * 4);
   P->off_ranges = take(T * 2 * 4);

@@ -367,14 +367,21 @@ struct TileSortOut {
   uint32_t* vals;
   uint32_t* sorted_rec;
   const uint32_t* pair_rec;
+  const Rec* rec;
+  Rec* lrec;  // records in list order, read contiguously by the render kernels
 };
 
 __device__ __forceinline__ void emit_sorted(const TileSortOut& o, uint32_t pos, uint64_t tkey,
                                             uint64_t key) {
   const uint32_t g = (uint32_t)key;
+  const uint32_t r = o.pair_rec[g];
   o.keys[pos] = tkey | (key >> 32);
   o.vals[pos] = g;
-  o.sorted_rec[pos] = o.pair_rec[g];
+  o.sorted_rec[pos] = r;
+  const float4* src = reinterpret_cast<const float4*>(o.rec + r);
+  float4* dst = reinterpret_cast<float4*>(o.lrec + pos);
+  const float4 a0 = src[0], a1 = src[1], a2 = src[2], a3 = src[3];
+  dst[0] = a0; dst[1] = a1; dst[2] = a2; dst[3] = a3;
 }
 
 __device__ __forceinline__ void cmp_swap(uint64_t* k, uint32_t a, uint32_t b, uint32_t n) {
@@ -773,7 +780,8 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
   }
   if (T > 0) {
     TileSortOut out{ws_at<uint64_t>(ws, P.off_keys), ws_at<uint32_t>(ws, P.off_vals),
-                    ws_at<uint32_t>(ws, P.off_sorted_rec), pair_rec};
+                    ws_at<uint32_t>(ws, P.off_sorted_rec), pair_rec, ws_at<Rec>(ws, P.off_rec),
+                    ws_at<Rec>(ws, P.off_srec)};
     uint32_t* long_list = ws_at<uint32_t>(ws, P.off_long);
     hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)T), dim3(kWave), 0, s, tcnt, tstart, tile_tot,
                        T, fl, skey, out, ws_at<uint32_t>(ws, P.off_ranges), long_list, bstart,

@@ -125,12 +125,13 @@ __device__ __forceinline__ int find_view(const ViewTable& vt, int gtile) {
   return v;
 }
 
-__device__ __forceinline__ void stage(Rec* srec, uint32_t* sval, const Rec* __restrict__ rec,
-                                      const uint32_t* __restrict__ sorted_rec,
+// Records of a tile list are stored in list order (written by the
+// binning), so a batch is one contiguous, coalesced read.
+__device__ __forceinline__ void stage(Rec* srec, uint32_t* sval, const Rec* __restrict__ lrec,
                                       const uint32_t* __restrict__ sorted_vals, uint32_t first,
                                       int count, int lane) {
   for (int k = lane; k < count; k += kWave) {
-    const float4* src = reinterpret_cast<const float4*>(rec + sorted_rec[first + k]);
+    const float4* src = reinterpret_cast<const float4*>(lrec + first + k);
     float4* dst = reinterpret_cast<float4*>(srec + k);
     const float4 a0 = src[0], a1 = src[1], a2 = src[2], a3 = src[3];
     dst[0] = a0; dst[1] = a1; dst[2] = a2; dst[3] = a3;
@@ -140,8 +141,7 @@ __device__ __forceinline__ void stage(Rec* srec, uint32_t* sval, const Rec* __re
 
 // ------------------------------------------------------------------ forward
 template <int TW, int TH, bool CKPT>
-__device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ rec,
-                                         const uint32_t* __restrict__ sorted_rec,
+__device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec,
                                          const uint32_t* __restrict__ ranges,
                                          const float* __restrict__ cams, const ViewTable& vt,
                                          int B, float* __restrict__ color,
@@ -187,7 +187,7 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ rec,
     if (ballot64(active()) == 0) break;
     const int nb = (int)min((uint32_t)B, e - b);
     __syncthreads();
-    stage(srec, nullptr, rec, sorted_rec, nullptr, b, nb, lane);
+    stage(srec, nullptr, lrec, nullptr, b, nb, lane);
     __syncthreads();
     for (int j = 0; j < nb; ++j) {
       if constexpr (CKPT) {
@@ -273,7 +273,7 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ rec,
 
 template <int TW, int TH, bool CKPT>
 __global__ void __launch_bounds__(kWave) k_render_fwd(
-    const Rec* __restrict__ rec, const uint32_t* __restrict__ sorted_rec,
+    const Rec* __restrict__ lrec,
     const uint32_t* __restrict__ ranges, const float* __restrict__ cams, ViewTable vt, int B,
     float* __restrict__ color, float* __restrict__ depth, float* __restrict__ T_final,
     uint32_t* __restrict__ last, uint32_t* __restrict__ tile_last,
@@ -285,7 +285,7 @@ __global__ void __launch_bounds__(kWave) k_render_fwd(
   Rec* srec = reinterpret_cast<Rec*>(smem);
   if (queue == nullptr) {
     const int g = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
-    fwd_tile<TW, TH, CKPT>(g, rec, sorted_rec, ranges, cams, vt, B, color, depth, T_final, last,
+    fwd_tile<TW, TH, CKPT>(g, lrec, ranges, cams, vt, B, color, depth, T_final, last,
                            tile_last, target_rgb, target_depth, tile_loss, boff, ckpt, srec);
     return;
   }
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(kWave) k_render_fwd(
     const int lastt = min(vt.total_tiles, first + chunk);
     for (int k = first; k < lastt; ++k) {
       const int g = order ? (int)order[k] : k;
-      fwd_tile<TW, TH, CKPT>(g, rec, sorted_rec, ranges, cams, vt, B, color, depth, T_final,
+      fwd_tile<TW, TH, CKPT>(g, lrec, ranges, cams, vt, B, color, depth, T_final,
                              last, tile_last, target_rgb, target_depth, tile_loss, boff, ckpt,
                              srec);
     }
@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(kLossThreads) k_loss_reduce(const float* __res
 // ------------------------------------------------------------------ backward
 template <int TW, int TH>
 __device__ __forceinline__ void bwd_tile(
-    int gtile, const Rec* __restrict__ rec, const uint32_t* __restrict__ sorted_rec,
+    int gtile, const Rec* __restrict__ lrec,
     const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ tile_last, const float* __restrict__ cams, const ViewTable& vt,
     int B, const float* __restrict__ color, const float* __restrict__ depth,
@@ -419,7 +419,7 @@ __device__ __forceinline__ void bwd_tile(
     const int bstart = max(0, bend - B);
     const int nb = bend - bstart;
     __syncthreads();
-    stage(srec, sval, rec, sorted_rec, sorted_vals, s + (uint32_t)bstart, nb, lane);
+    stage(srec, sval, lrec, sorted_vals, s + (uint32_t)bstart, nb, lane);
     __syncthreads();
 #pragma unroll 2
     for (int j = nb - 1; j >= 0; --j) {
@@ -480,7 +480,7 @@ __device__ __forceinline__ void bwd_tile(
 
 template <int TW, int TH>
 __global__ void __launch_bounds__(kWave) k_render_bwd(
-    const Rec* __restrict__ rec, const uint32_t* __restrict__ sorted_rec,
+    const Rec* __restrict__ lrec,
     const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ tile_last, const float* __restrict__ cams, ViewTable vt, int B,
     const float* __restrict__ color, const float* __restrict__ depth,
@@ -494,7 +494,7 @@ __global__ void __launch_bounds__(kWave) k_render_bwd(
   uint32_t* sval = reinterpret_cast<uint32_t*>(smem + (size_t)B * sizeof(Rec));
   if (queue == nullptr) {
     const int g = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
-    bwd_tile<TW, TH>(g, rec, sorted_rec, sorted_vals, ranges, tile_last, cams, vt, B, color, depth,
+    bwd_tile<TW, TH>(g, lrec, sorted_vals, ranges, tile_last, cams, vt, B, color, depth,
                      T_final, last, dL_dcolor, dL_ddepth, target_rgb, target_depth, fused,
                      lambda_depth, grad_pair, srec, sval);
     return;
@@ -505,7 +505,7 @@ __global__ void __launch_bounds__(kWave) k_render_bwd(
     const int lastt = min(vt.total_tiles, first + chunk);
     for (int k = first; k < lastt; ++k) {
       const int g = order ? (int)order[k] : k;
-      bwd_tile<TW, TH>(g, rec, sorted_rec, sorted_vals, ranges, tile_last, cams, vt, B, color,
+      bwd_tile<TW, TH>(g, lrec, sorted_vals, ranges, tile_last, cams, vt, B, color,
                        depth, T_final, last, dL_dcolor, dL_ddepth, target_rgb, target_depth,
                        fused, lambda_depth, grad_pair, srec, sval);
     }
@@ -539,7 +539,7 @@ __global__ void __launch_bounds__(kWave) k_render_bwd(
 template <int TW, int TH>
 __device__ __forceinline__ void splat_wave(
     int seg_lanes, const uint2* __restrict__ queue, uint32_t q_first, uint32_t q_count,
-    const Rec* __restrict__ rec, const uint32_t* __restrict__ sorted_rec,
+    const Rec* __restrict__ lrec,
     const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ tile_last, const uint32_t* __restrict__ boff,
     const float* __restrict__ ckpt, const ViewTable& vt, const float* __restrict__ color,
@@ -631,7 +631,7 @@ __device__ __forceinline__ void splat_wave(
 
   Rec r;
   if (live) {
-    const float4* src = reinterpret_cast<const float4*>(rec + sorted_rec[s + pos]);
+    const float4* src = reinterpret_cast<const float4*>(lrec + s + pos);
     float4* dst = reinterpret_cast<float4*>(&r);
     dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2]; dst[3] = src[3];
   } else {
@@ -704,7 +704,7 @@ __device__ __forceinline__ void splat_wave(
 // the first, two per wave from the second.
 template <int TW, int TH>
 __global__ void __launch_bounds__(kWave) k_render_bwd_splat(
-    const Rec* __restrict__ rec, const uint32_t* __restrict__ sorted_rec,
+    const Rec* __restrict__ lrec,
     const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ tile_last, const uint32_t* __restrict__ boff,
     const float* __restrict__ ckpt, const uint2* __restrict__ bq, int64_t bq_stride,
@@ -718,11 +718,11 @@ __global__ void __launch_bounds__(kWave) k_render_bwd_splat(
   const uint32_t w_full = q_full, w_half = (q_half + 1) / 2;
   for (uint32_t wv = blockIdx.x; wv < w_full + w_half; wv += gridDim.x) {
     if (wv < w_full)
-      splat_wave<TW, TH>(64, bq, wv, q_full, rec, sorted_rec, sorted_vals, ranges, tile_last,
+      splat_wave<TW, TH>(64, bq, wv, q_full, lrec, sorted_vals, ranges, tile_last,
                          boff, ckpt, vt, color, depth, last, dL_dcolor, dL_ddepth, target_rgb,
                          target_depth, fused, lambda_depth, grad_pair, pxa, pxb);
     else
-      splat_wave<TW, TH>(32, bq + bq_stride, 2 * (wv - w_full), q_half, rec, sorted_rec,
+      splat_wave<TW, TH>(32, bq + bq_stride, 2 * (wv - w_full), q_half, lrec,
                          sorted_vals, ranges, tile_last, boff, ckpt, vt, color, depth, last,
                          dL_dcolor, dL_ddepth, target_rgb, target_depth, fused, lambda_depth,
                          grad_pair, pxa, pxb);
@@ -737,7 +737,7 @@ hipError_t bwd_splat_launch(const Plan& P, void* ws, const float* cams, const fl
                             int grid, hipStream_t s) {
   (void)cams;
   hipLaunchKernelGGL((k_render_bwd_splat<TW, TH>), dim3(grid), dim3(kWave), 0, s,
-                     ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_sorted_rec), sorted_vals,
+                     ws_at<Rec>(ws, P.off_srec), sorted_vals,
                      ws_at<uint32_t>(ws, P.off_ranges), ws_at<uint32_t>(ws, P.off_tile_last),
                      ws_at<uint32_t>(ws, P.off_boff), ws_at<float>(ws, P.off_ckpt),
                      ws_at<uint2>(ws, P.off_bq), P.ckpt_slots, ws_at<int32_t>(ws, P.off_flags),
@@ -755,14 +755,14 @@ hipError_t fwd_launch(const Plan& P, void* ws, const float* cams, float* color, 
   const size_t lds = (size_t)B * sizeof(Rec);
   if (P.cfg.flags & GS_SPLAT_BWD) {
     hipLaunchKernelGGL((k_render_fwd<TW, TH, true>), dim3(grid), dim3(kWave), lds, s,
-                       ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_sorted_rec),
+                       ws_at<Rec>(ws, P.off_srec),
                        ws_at<uint32_t>(ws, P.off_ranges), cams, P.vt, B, color, depth, T_final,
                        last, ws_at<uint32_t>(ws, P.off_tile_last), target_rgb, target_depth,
                        ws_at<float>(ws, P.off_tile_loss), order, queue, P.cfg.chunk,
                        ws_at<uint32_t>(ws, P.off_boff), ws_at<float>(ws, P.off_ckpt));
   } else {
     hipLaunchKernelGGL((k_render_fwd<TW, TH, false>), dim3(grid), dim3(kWave), lds, s,
-                       ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_sorted_rec),
+                       ws_at<Rec>(ws, P.off_srec),
                        ws_at<uint32_t>(ws, P.off_ranges), cams, P.vt, B, color, depth, T_final,
                        last, ws_at<uint32_t>(ws, P.off_tile_last), target_rgb, target_depth,
                        ws_at<float>(ws, P.off_tile_loss), order, queue, P.cfg.chunk,
@@ -780,7 +780,7 @@ hipError_t bwd_launch(const Plan& P, void* ws, const float* cams, const float* c
   const int B = P.cfg.lds_batch;
   const size_t lds = (size_t)B * (sizeof(Rec) + sizeof(uint32_t));
   hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(grid), dim3(kWave), lds, s,
-                     ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_sorted_rec), sorted_vals,
+                     ws_at<Rec>(ws, P.off_srec), sorted_vals,
                      ws_at<uint32_t>(ws, P.off_ranges), ws_at<uint32_t>(ws, P.off_tile_last), cams,
                      P.vt, B, color, depth, T_final, last, dL_dcolor, dL_ddepth, target_rgb,
                      target_depth, fused, P.cfg.lambda_depth,
