@@ -381,18 +381,31 @@ __global__ void __launch_bounds__(256) k_pose_reduce(const double* __restrict__ 
 
 }  // namespace
 
+// With one view the projection backward runs over the visible Gaussians
+// only, so the others' gradients must be zeroed first (unless accumulating).
+bool project_bwd_zeroes(const Plan& P, int accumulate) {
+  return P.vt.n_views == 1 && !accumulate && P.n > 0;
+}
+
+hipError_t launch_zero_grads(const Plan& P, const gs_gaussian_grads& out, hipStream_t s) {
+  const int64_t K3 = 3 * (int64_t)P.K;
+  hipLaunchKernelGGL(k_zero_grads, dim3(2048), dim3(256), 0, s, out.means, 3 * P.n,
+                     out.log_scales, 3 * P.n, out.quats, 4 * P.n, out.opacity_logits, P.n,
+                     out.sh, K3 * P.n);
+  return hipGetLastError();
+}
+
+// zeroed: the caller has already zeroed the gradients (see project_bwd_zeroes).
 hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float* cams, void* ws,
                               const gs_gaussian_grads& out, float* dL_dpose, int accumulate,
-                              hipStream_t s) {
+                              bool zeroed, hipStream_t s) {
   const int64_t blocks = P.proj_blocks;
   if (blocks == 0) return hipSuccess;
   double* pose_part = dL_dpose ? ws_at<double>(ws, P.off_pose_part) : nullptr;
   const bool compact = P.vt.n_views == 1;
-  if (compact && !accumulate) {
-    const int64_t K3 = 3 * (int64_t)P.K;
-    hipLaunchKernelGGL(k_zero_grads, dim3(2048), dim3(256), 0, s, out.means, 3 * P.n,
-                       out.log_scales, 3 * P.n, out.quats, 4 * P.n, out.opacity_logits, P.n,
-                       out.sh, K3 * P.n);
+  if (project_bwd_zeroes(P, accumulate) && !zeroed) {
+    const hipError_t e = launch_zero_grads(P, out, s);
+    if (e != hipSuccess) return e;
   }
 #define GS_PB1(D, PO, CO)                                                                         \
   hipLaunchKernelGGL((k_project_bwd<D, PO, CO>), dim3((unsigned)blocks), dim3(kProjThreads), 0, s, \

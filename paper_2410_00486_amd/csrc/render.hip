@@ -165,14 +165,25 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec
 
   double sx[PPL], sy[PPL];
   float T[PPL], c0[PPL], c1[PPL], c2[PPL], D[PPL];
+  float tr0[PPL], tr1[PPL], tr2[PPL], trd[PPL];  // loss targets, loaded up front
   uint32_t lastpos[PPL];
   bool done[PPL], inside[PPL];
+  const int64_t npx_v = (int64_t)vi.W * vi.H;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     const int px = tx0 + TG::x(lane, k), py = ty0 + TG::y(lane, k);
     inside[k] = (px < vi.W) && (py < vi.H);
     sx[k] = px + 0.5;
     sy[k] = py + 0.5;
+    tr0[k] = tr1[k] = tr2[k] = trd[k] = 0.0f;
+    if (target_rgb && inside[k]) {
+      const int64_t pl = (int64_t)py * vi.W + px;
+      const int64_t cbase = 3 * (int64_t)vi.pix_off + pl;
+      tr0[k] = target_rgb[cbase];
+      tr1[k] = target_rgb[cbase + npx_v];
+      tr2[k] = target_rgb[cbase + 2 * npx_v];
+      if (target_depth) trd[k] = target_depth[(int64_t)vi.pix_off + pl];
+    }
     T[k] = 1.0f; c0[k] = c1[k] = c2[k] = D[k] = 0.0f;
     lastpos[k] = 0;
     done[k] = !inside[k];
@@ -252,9 +263,8 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec
     T_final[pix] = T[k];
     last[pix] = lastpos[k];
     if (target_rgb) {
-      lrgb += fabsf(o0 - target_rgb[cbase]) + fabsf(o1 - target_rgb[cbase + npx]) +
-              fabsf(o2 - target_rgb[cbase + 2 * npx]);
-      if (target_depth) ld += fabsf(D[k] - target_depth[pix]);
+      lrgb += fabsf(o0 - tr0[k]) + fabsf(o1 - tr1[k]) + fabsf(o2 - tr2[k]);
+      if (target_depth) ld += fabsf(D[k] - trd[k]);
     }
   }
   const uint32_t m = wave_max(lmax);
@@ -369,8 +379,10 @@ __device__ __forceinline__ void bwd_tile(
     gp[0] = z; gp[1] = z; gp[2] = z;
   }
 
-  // lanes of the first row write the scattered sums of the ten partials
+  // lanes of the first row write the scattered sums of the ten partials;
+  // the conic and mean entries carry their sign and halves here
   const int my_idx = lane < 16 ? rs_index(lane) : -1;
+  const float my_scale = (my_idx == 5 || my_idx == 7) ? -0.5f : (my_idx >= 6 ? -1.0f : 1.0f);
   double sx[PPL], sy[PPL];
   float T[PPL], gC0[PPL], gC1[PPL], gC2[PPL], gD[PPL], Sc0[PPL], Sc1[PPL], Sc2[PPL], Sd[PPL];
   uint32_t L[PPL];
@@ -451,24 +463,27 @@ __device__ __forceinline__ void bwd_tile(
             Sc2[k] = fmaf(r.b, wgt, Sc2[k]);
             Sd[k] = fmaf(r.z, wgt, Sd[k]);
             T[k] = Tk;
-            if (oG <= kAlphaMax) {
-              const float gpow = a * g_alpha;
-              const float fx = (float)dx, fy = (float)dy;
-              const float ca = (float)(-2.0 * r.ca), cb = (float)(-r.cb), cc = (float)(-2.0 * r.cc);
-              g[4] = fmaf(G, g_alpha, g[4]);
-              g[5] -= 0.5f * gpow * fx * fx;
-              g[6] -= gpow * fx * fy;
-              g[7] -= 0.5f * gpow * fy * fy;
-              g[8] -= gpow * (ca * fx + cb * fy);
-              g[9] -= gpow * (cb * fx + cc * fy);
-            }
+            // unclamped alpha only (no gradient through the 0.99 clamp);
+            // the conic and mean partials are formed from t = gpow dx,
+            // u = gpow dy, their signs and halves applied after the sum
+            const bool open = oG <= kAlphaMax;
+            const float gpow = open ? a * g_alpha : 0.0f;
+            const float fx = (float)dx, fy = (float)dy;
+            const float ca = (float)(-2.0 * r.ca), cb = (float)(-r.cb), cc = (float)(-2.0 * r.cc);
+            const float t = gpow * fx, u = gpow * fy;
+            g[4] = fmaf(open ? G : 0.0f, g_alpha, g[4]);
+            g[5] = fmaf(t, fx, g[5]);
+            g[6] = fmaf(t, fy, g[6]);
+            g[7] = fmaf(u, fy, g[7]);
+            g[8] = fmaf(ca, t, fmaf(cb, u, g[8]));
+            g[9] = fmaf(cb, t, fmaf(cc, u, g[9]));
           }
         }
       }
       float* gpf = grad_pair + (int64_t)sval[j] * kPairGrad;
       if (ballot64(contrib) != 0) {
         const float z = reduce_scatter10(g);
-        if (my_idx >= 0) gpf[my_idx] = z;
+        if (my_idx >= 0) gpf[my_idx] = z * my_scale;
       } else if (lane == 0) {
         float4* gp = reinterpret_cast<float4*>(gpf);
         const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -546,7 +561,7 @@ __device__ __forceinline__ void splat_wave(
     const float* __restrict__ depth, const uint32_t* __restrict__ last,
     const float* __restrict__ dL_dcolor, const float* __restrict__ dL_ddepth,
     const float* __restrict__ target_rgb, const float* __restrict__ target_depth, int fused,
-    float lambda_depth, float* __restrict__ grad_pair, float4* pxa, float4* pxb) {
+    float lambda_depth, float* __restrict__ grad_pair, float4* pxa, float4* pxb, double2* pxc) {
   constexpr int NPX = TW * TH;
   constexpr int LOG_TW = TW == 16 ? 4 : 3;
   const int lane = threadIdx.x;
@@ -585,6 +600,7 @@ __device__ __forceinline__ void splat_wave(
   const int64_t npx = (int64_t)vi.W * vi.H;
   float4* sa = pxa + seg * NPX;
   float4* sb = pxb + seg * NPX;
+  double2* sc = pxc + seg * NPX;  // sample point of each pixel
 
   // pixel table of the segment's tile: loss gradients, P, last position,
   // stored state (T, Q)
@@ -625,6 +641,7 @@ __device__ __forceinline__ void splat_wave(
       }
       sa[j] = a;
       sb[j] = b;
+      sc[j] = make_double2((double)px + 0.5, (double)py + 0.5);
     }
   }
   __syncthreads();
@@ -658,11 +675,10 @@ __device__ __forceinline__ void splat_wave(
       Qc = b.w;
     }
     if (vj && live && pos < __float_as_uint(b.y)) {
-      const double sx = (double)(tx0 + (jc & (TW - 1))) + 0.5;
-      const double sy = (double)(ty0 + (jc >> LOG_TW)) + 0.5;
+      const double2 sxy = sc[jc];
       double dx, dy;
       float G, oG, a;
-      if (eval_alpha(r, sx, sy, dx, dy, G, oG, a)) {
+      if (eval_alpha(r, sxy.x, sxy.y, dx, dy, G, oG, a)) {
         const float4 gc = sa[jc];
         const float om = 1.0f - a;
         const float inv_om = __builtin_amdgcn_rcpf(om);
@@ -674,16 +690,18 @@ __device__ __forceinline__ void splat_wave(
         g[1] = fmaf(wgt, gc.y, g[1]);
         g[2] = fmaf(wgt, gc.z, g[2]);
         g[3] = fmaf(wgt, gc.w, g[3]);
-        if (oG <= kAlphaMax) {
-          const float gpow = a * g_alpha;
-          const float fx = (float)dx, fy = (float)dy;
-          g[4] = fmaf(G, g_alpha, g[4]);
-          g[5] -= 0.5f * gpow * fx * fx;
-          g[6] -= gpow * fx * fy;
-          g[7] -= 0.5f * gpow * fy * fy;
-          g[8] -= gpow * (ca * fx + cb * fy);
-          g[9] -= gpow * (cb * fx + cc * fy);
-        }
+        // moments of t = gpow dx, u = gpow dy; the conic and mean
+        // partials are formed from them once, after the pixels
+        const bool open = oG <= kAlphaMax;
+        const float gpow = open ? a * g_alpha : 0.0f;
+        const float fx = (float)dx, fy = (float)dy;
+        const float t = gpow * fx, u = gpow * fy;
+        g[4] = fmaf(open ? G : 0.0f, g_alpha, g[4]);
+        g[5] = fmaf(t, fx, g[5]);
+        g[6] = fmaf(t, fy, g[6]);
+        g[7] = fmaf(u, fy, g[7]);
+        g[8] += t;
+        g[9] += u;
         Tc = Tc * om;
         Qc = Qn;
       }
@@ -694,8 +712,8 @@ __device__ __forceinline__ void splat_wave(
   if (live) {
     float4* gp = reinterpret_cast<float4*>(grad_pair + (int64_t)sorted_vals[s + pos] * kPairGrad);
     gp[0] = make_float4(g[0], g[1], g[2], g[3]);
-    gp[1] = make_float4(g[4], g[5], g[6], g[7]);
-    gp[2] = make_float4(g[8], g[9], 0.0f, 0.0f);
+    gp[1] = make_float4(g[4], -0.5f * g[5], -g[6], -0.5f * g[7]);
+    gp[2] = make_float4(-(ca * g[8] + cb * g[9]), -(cb * g[8] + cc * g[9]), 0.0f, 0.0f);
   }
   __syncthreads();  // the pixel tables are rewritten by the next wave's work
 }
@@ -714,18 +732,19 @@ __global__ void __launch_bounds__(kWave) k_render_bwd_splat(
     const float* __restrict__ target_rgb, const float* __restrict__ target_depth, int fused,
     float lambda_depth, float* __restrict__ grad_pair) {
   __shared__ float4 pxa[2 * TW * TH], pxb[2 * TW * TH];
+  __shared__ double2 pxc[2 * TW * TH];
   const uint32_t q_full = (uint32_t)fl[F_BQ_FULL], q_half = (uint32_t)fl[F_BQ_HALF];
   const uint32_t w_full = q_full, w_half = (q_half + 1) / 2;
   for (uint32_t wv = blockIdx.x; wv < w_full + w_half; wv += gridDim.x) {
     if (wv < w_full)
       splat_wave<TW, TH>(64, bq, wv, q_full, lrec, sorted_vals, ranges, tile_last,
                          boff, ckpt, vt, color, depth, last, dL_dcolor, dL_ddepth, target_rgb,
-                         target_depth, fused, lambda_depth, grad_pair, pxa, pxb);
+                         target_depth, fused, lambda_depth, grad_pair, pxa, pxb, pxc);
     else
       splat_wave<TW, TH>(32, bq + bq_stride, 2 * (wv - w_full), q_half, lrec,
                          sorted_vals, ranges, tile_last, boff, ckpt, vt, color, depth, last,
                          dL_dcolor, dL_ddepth, target_rgb, target_depth, fused, lambda_depth,
-                         grad_pair, pxa, pxb);
+                         grad_pair, pxa, pxb, pxc);
   }
 }
 
