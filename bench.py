@@ -36,6 +36,9 @@ LRS = {"means": 1.6e-4, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-
 # 14, alpha gradient 3, behind-sum update 8, opacity/exponent gradient 2,
 # conic and mean gradients 13  -> 60 flops (exp and rcp counted as one each)
 BWD_FLOPS_PER_POS = 60
+# forward: alpha (quadratic form 9, exponent and clamp 4), transmittance 2,
+# weight and colour/depth blend 9, stop test 1 -> 25 flops per position
+FWD_FLOPS_PER_POS = 25
 # HBM counter summary of the headline iteration (rocprofv3 FETCH_SIZE /
 # WRITE_SIZE, scaled by a 1 GiB copy); used only while the kernel sources
 # still hash to the value recorded with the counters
@@ -284,20 +287,30 @@ def main():
     }
     total_bytes = sum(bytes_.values())
     dominant = max(stage_ms, key=stage_ms.get)
-    bwd_tflops = BWD_FLOPS_PER_POS * E_bwd / (stage_ms["render_bwd_raster"] * 1e-3) / 1e12
-    if dominant == "render_bwd_raster":
-        kname = "k_render_bwd_splat" if args.bwd == "splat" else "k_render_bwd"
-        tile_t = f"<{tile[0]},{tile[1]}>"
-        roofline = {"bound": "alu", "kernel": f"{kname} (gs_render_bwd_raster)",
-                    "achieved": round(bwd_tflops, 3), "peak": FP32_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(bwd_tflops / FP32_PEAK_TFLOPS, 4),
-                    "traffic": measured_traffic(kname + tile_t),
-                    "work": f"{BWD_FLOPS_PER_POS} flop x {E_bwd} pixel-Gaussian positions"}
+    tile_t = f"<{tile[0]},{tile[1]}>"
+
+    def alu_roofline(stage):
+        if stage == "render_bwd_raster":
+            kname = ("k_render_bwd_splat" if args.bwd == "splat" else "k_render_bwd") + tile_t
+            flops, api = BWD_FLOPS_PER_POS, "gs_render_bwd_raster"
+        else:
+            kname = "k_render_fwd" + tile_t[:-1] + ("," + "true>" if args.bwd == "splat" else ",false>")
+            flops, api = FWD_FLOPS_PER_POS, "gs_render_fwd"
+        tf = flops * E_bwd / (stage_ms[stage] * 1e-3) / 1e12
+        return {"bound": "alu", "kernel": f"{kname} ({api})", "achieved": round(tf, 3),
+                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / FP32_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(kname),
+                "work": f"{flops} flop x {E_bwd} pixel-Gaussian positions"}
+
+    if dominant in ("render_bwd_raster", "render_fwd"):
+        roofline = alu_roofline(dominant)
+        other = alu_roofline("render_fwd" if dominant == "render_bwd_raster" else "render_bwd_raster")
     else:
         gbs = bytes_[dominant] / (stage_ms[dominant] * 1e-3) / 1e9
         roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(gbs, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                     "traffic": None}
+        other = alu_roofline("render_bwd_raster")
     hbm_gbs = total_bytes / (ms_graph * 1e-3) / 1e9
 
     result = {
@@ -326,6 +339,7 @@ def main():
         "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
         "stage_gbs": {k: round(bytes_[k] / (stage_ms[k] * 1e-3) / 1e9, 1) for k in stages},
         "roofline": roofline,
+        "roofline_other_raster_kernel": other,
     }
     if ab is not None:
         ab[args.bwd] = {"iters_per_s": result["value"],

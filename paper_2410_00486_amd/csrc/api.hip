@@ -35,8 +35,6 @@ hipError_t launch_render_bwd(const Plan& P, void* ws, const float* cams, const f
 hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float* cams, void* ws,
                               const gs_gaussian_grads& out, float* dL_dpose, int accumulate,
                               bool zeroed, hipStream_t s);
-bool project_bwd_zeroes(const Plan& P, int accumulate);
-hipError_t launch_zero_grads(const Plan& P, const gs_gaussian_grads& out, hipStream_t s);
 hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, double beta1,
                        double beta2, double eps, double lambda_o, int64_t reg_count,
                        int32_t* step_dev, hipStream_t s);
@@ -534,30 +532,6 @@ gs_status gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_b
   return hip_check(e, "gs_sort_pairs");
 }
 
-// Per thread and device: a side stream (default priority) and the two
-// events of a fork and a join.  Per thread, so that iterations enqueued
-// concurrently from several threads never share an event.
-struct SideStream {
-  hipStream_t s = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
-  bool ok = false;
-};
-
-static SideStream* side_stream() {
-  constexpr int kMaxDevices = 64;
-  thread_local SideStream per_dev[kMaxDevices];
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
-  SideStream& x = per_dev[dev];
-  if (!x.ok) {
-    if (hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    if (hipEventCreateWithFlags(&x.fork, hipEventDisableTiming) != hipSuccess) return nullptr;
-    if (hipEventCreateWithFlags(&x.join, hipEventDisableTiming) != hipSuccess) return nullptr;
-    x.ok = true;
-  }
-  return &x;
-}
-
 gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
   if (!it) return fail(GS_ERR_INVALID_ARG, "iteration is null");
   const bool ssim = it->lambda_ssim > 0.0;
@@ -568,26 +542,7 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
     if (!it->target_rgb || !it->loss_grad_color || !it->loss_grad_depth)
       return fail(GS_ERR_INVALID_ARG, "lambda_ssim > 0 needs target_rgb and loss gradient buffers");
   }
-  if (!it->plan || check_plan(it->plan) != GS_OK) return fail(GS_ERR_INVALID_ARG, "bad plan");
-  const Plan& P = *plan_of(it->plan);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int acc = (P.cfg.flags & GS_ACCUMULATE_GRADS) ? 1 : 0;
-  // the gradient zeroing of the one-view projection backward depends on
-  // nothing before it: it runs on a side stream, joined before that kernel
-  // (a fork and a join node when captured)
-  SideStream* side = project_bwd_zeroes(P, acc) ? side_stream() : nullptr;
-  gs_status st;
-  if (side) {
-    const gs_gaussian_grads& g = it->grads;
-    if (!g.means || !g.log_scales || !g.quats || !g.opacity_logits || !g.sh)
-      return fail(GS_ERR_INVALID_ARG, "gradient output pointers must be non-null");
-    hipError_t e = hipEventRecord(side->fork, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
-    if (e == hipSuccess) e = launch_zero_grads(P, g, side->s);
-    if (e == hipSuccess) e = hipEventRecord(side->join, side->s);
-    if (e != hipSuccess) return hip_check(e, "gs_iteration_enqueue (gradient zeroing)");
-  }
-  st = gs_preprocess(it->plan, &it->gaussians, it->cams_dev, it->ws, stream);
+  gs_status st = gs_preprocess(it->plan, &it->gaussians, it->cams_dev, it->ws, stream);
   if (st != GS_OK) return st;
   st = gs_bin_sort(it->plan, it->ws, stream);
   if (st != GS_OK) return st;
@@ -605,22 +560,10 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
     gC = it->loss_grad_color;
     gD = it->loss_grad_depth;
   }
-  if (side) {
-    st = gs_render_bwd_raster(it->plan, it->ws, it->cams_dev, it->color, it->depth, it->T_final,
-                              it->last, gC, gD, it->target_rgb, it->target_depth, stream);
-    if (st != GS_OK) return st;
-    if ((st = check_gaussians(P, &it->gaussians)) != GS_OK) return st;
-    hipError_t e = hipStreamWaitEvent(s, side->join, 0);
-    if (e == hipSuccess)
-      e = launch_project_bwd(P, it->gaussians, it->cams_dev, it->ws, it->grads, it->dL_dpose,
-                             acc, true, s);
-    if (e != hipSuccess) return hip_check(e, "gs_iteration_enqueue (projection backward)");
-  } else {
-    st = gs_render_bwd(it->plan, &it->gaussians, it->cams_dev, it->ws, it->color, it->depth,
-                       it->T_final, it->last, gC, gD, it->target_rgb, it->target_depth,
-                       &it->grads, it->dL_dpose, stream);
-    if (st != GS_OK) return st;
-  }
+  st = gs_render_bwd(it->plan, &it->gaussians, it->cams_dev, it->ws, it->color, it->depth,
+                     it->T_final, it->last, gC, gD, it->target_rgb, it->target_depth, &it->grads,
+                     it->dL_dpose, stream);
+  if (st != GS_OK) return st;
   if (it->n_adam_groups > 0)
     st = gs_adam_step(it->adam_groups, it->n_adam_groups, 1, it->beta1, it->beta2, it->eps,
                       it->lambda_o, it->reg_count, it->step_dev, stream);

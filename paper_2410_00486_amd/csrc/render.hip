@@ -165,25 +165,15 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec
 
   double sx[PPL], sy[PPL];
   float T[PPL], c0[PPL], c1[PPL], c2[PPL], D[PPL];
-  float tr0[PPL], tr1[PPL], tr2[PPL], trd[PPL];  // loss targets, loaded up front
   uint32_t lastpos[PPL];
   bool done[PPL], inside[PPL];
-  const int64_t npx_v = (int64_t)vi.W * vi.H;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     const int px = tx0 + TG::x(lane, k), py = ty0 + TG::y(lane, k);
     inside[k] = (px < vi.W) && (py < vi.H);
     sx[k] = px + 0.5;
     sy[k] = py + 0.5;
-    tr0[k] = tr1[k] = tr2[k] = trd[k] = 0.0f;
-    if (target_rgb && inside[k]) {
-      const int64_t pl = (int64_t)py * vi.W + px;
-      const int64_t cbase = 3 * (int64_t)vi.pix_off + pl;
-      tr0[k] = target_rgb[cbase];
-      tr1[k] = target_rgb[cbase + npx_v];
-      tr2[k] = target_rgb[cbase + 2 * npx_v];
-      if (target_depth) trd[k] = target_depth[(int64_t)vi.pix_off + pl];
-    }
+
     T[k] = 1.0f; c0[k] = c1[k] = c2[k] = D[k] = 0.0f;
     lastpos[k] = 0;
     done[k] = !inside[k];
@@ -263,8 +253,9 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec
     T_final[pix] = T[k];
     last[pix] = lastpos[k];
     if (target_rgb) {
-      lrgb += fabsf(o0 - tr0[k]) + fabsf(o1 - tr1[k]) + fabsf(o2 - tr2[k]);
-      if (target_depth) ld += fabsf(D[k] - trd[k]);
+      lrgb += fabsf(o0 - target_rgb[cbase]) + fabsf(o1 - target_rgb[cbase + npx]) +
+              fabsf(o2 - target_rgb[cbase + 2 * npx]);
+      if (target_depth) ld += fabsf(D[k] - target_depth[pix]);
     }
   }
   const uint32_t m = wave_max(lmax);
