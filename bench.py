@@ -455,8 +455,8 @@ def render_target(gsr, scene, cams, view_wh, dev, tile=(16, 16)):
 
 def bench_batched(args, dev):
     """8 keyframes of mixed resolution over a shared 500k pool: one autotuned
-    persistent graph for all views vs the plain form (standard grids, view
-    by view, 16x16 tiles)."""
+    persistent graph for all views vs the same kernels and tile shape launched
+    view by view (one plan per view, gradients accumulated, one Adam step)."""
     import torch
 
     import paper_2410_00486_amd as gsr
@@ -507,9 +507,9 @@ def bench_batched(args, dev):
     per, vis = [], []
     for v, c in enumerate(cams_l):
         cv = cams[v:v + 1].contiguous()
-        capv = gsr.required_pairs(*params.tensors(), cv, [view_wh[v]], 3, (16, 16))
-        pv = gsr.Plan(w.scene.n, 3, [view_wh[v]], tile=(16, 16),
-                      flags=L.GS_FUSED_L1 | L.GS_ACCUMULATE_GRADS,
+        capv = gsr.required_pairs(*params.tensors(), cv, [view_wh[v]], 3, tile)
+        pv = gsr.Plan(w.scene.n, 3, [view_wh[v]], tile=tile, lds_batch=best["lds_batch"],
+                      flags=L.GS_FUSED_L1 | L.GS_ACCUMULATE_GRADS | (flags & L.GS_SPLAT_BWD),
                       pair_capacity=int(capv * 1.5) + 4096)
         off, npx = plan.pixel_offsets[v], view_wh[v][0] * view_wh[v][1]
         per.append((pv, pv.new_workspace(dev), cv, gsr.Frame(pv, dev),
