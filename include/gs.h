@@ -314,7 +314,11 @@ gs_status gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_b
  * gs_render_fwd, gs_render_bwd and (if n_adam_groups > 0) gs_adam_step on
  * `stream` and instantiates the graph.  Poses, parameters and targets live
  * in device memory, so replays see their current values.  Adam needs
- * step_dev (the device step counter) so replays advance the bias correction. */
+ * step_dev (the device step counter) so replays advance the bias correction.
+ * With one view, Adam groups and no GS_ACCUMULATE_GRADS, the gradient
+ * buffers are written for the Gaussians that have pairs only: Adam takes the
+ * others' gradients as zero, so their entries in `grads` are left as they
+ * were (the parameters and moments are those of a fully written gradient). */
 typedef struct gs_iteration {
   const gs_plan* plan;
   void* ws;

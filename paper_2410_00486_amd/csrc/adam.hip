@@ -19,6 +19,11 @@ struct AdamGroupArg {
   int64_t block0;  // first block of this group
   float lr;
   int32_t reg;
+  // optional: the gradient of element e is taken as zero unless
+  // vis[e / per] != 0 (Gaussians without pairs, whose entries the one-view
+  // projection backward leaves unwritten)
+  const uint32_t* vis;
+  int32_t per;
 };
 
 struct AdamArgs {
@@ -31,6 +36,7 @@ struct AdamArgs {
   float eps;
   float reg_scale;        // lambda_o / reg_count
   const int32_t* step_dev;
+  const int32_t* overflow;  // with vis: every gradient is zero after a pair overflow
 };
 
 namespace {
@@ -61,7 +67,18 @@ __global__ void __launch_bounds__(kAdamThreads) k_adam(AdamArgs a) {
                      (int64_t)threadIdx.x * kAdamVec;
   if (e0 + kAdamVec <= G.n) {
     float4 p = *reinterpret_cast<float4*>(G.p + e0);
-    const float4 g = *reinterpret_cast<const float4*>(G.g + e0);
+    float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (G.vis) {
+      const bool over = *a.overflow != 0;
+      const bool v0 = !over && G.vis[e0 / G.per] != 0, v1 = !over && G.vis[(e0 + 1) / G.per] != 0;
+      const bool v2 = !over && G.vis[(e0 + 2) / G.per] != 0, v3 = !over && G.vis[(e0 + 3) / G.per] != 0;
+      if (v0 || v1 || v2 || v3) {
+        const float4 gl = *reinterpret_cast<const float4*>(G.g + e0);
+        g = make_float4(v0 ? gl.x : 0.f, v1 ? gl.y : 0.f, v2 ? gl.z : 0.f, v3 ? gl.w : 0.f);
+      }
+    } else {
+      g = *reinterpret_cast<const float4*>(G.g + e0);
+    }
     float4 m = *reinterpret_cast<float4*>(G.m + e0);
     float4 v = *reinterpret_cast<float4*>(G.v + e0);
     adam_one(p.x, g.x, m.x, v.x, a, step_size, inv_bc2s, G.reg);
@@ -74,7 +91,8 @@ __global__ void __launch_bounds__(kAdamThreads) k_adam(AdamArgs a) {
   } else {
     for (int64_t e = e0; e < G.n; ++e) {
       float p = G.p[e], m = G.m[e], v = G.v[e];
-      adam_one(p, G.g[e], m, v, a, step_size, inv_bc2s, G.reg);
+      const bool live = !G.vis || (*a.overflow == 0 && G.vis[e / G.per] != 0);
+      adam_one(p, live ? G.g[e] : 0.0f, m, v, a, step_size, inv_bc2s, G.reg);
       G.p[e] = p;
       G.m[e] = m;
       G.v[e] = v;
@@ -90,16 +108,19 @@ int64_t adam_blocks(int64_t n) {
   return (n + kAdamThreads * kAdamVec - 1) / (kAdamThreads * kAdamVec);
 }
 
+// vis / per / overflow: optional per-group gradient masks (see AdamGroupArg).
 hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, double beta1,
                        double beta2, double eps, double lambda_o, int64_t reg_count,
-                       int32_t* step_dev, hipStream_t s) {
+                       int32_t* step_dev, hipStream_t s, const uint32_t* const* vis,
+                       const int32_t* per, const int32_t* overflow) {
   for (int base = 0; base < n_groups; base += kAdamMaxGroups) {
     AdamArgs a{};
     const int ng = n_groups - base < kAdamMaxGroups ? n_groups - base : kAdamMaxGroups;
     int64_t blocks = 0;
     for (int k = 0; k < ng; ++k) {
       const gs_param_group& G = groups[base + k];
-      a.grp[k] = AdamGroupArg{G.p, G.g, G.m, G.v, G.n, blocks, G.lr, G.opacity_reg};
+      a.grp[k] = AdamGroupArg{G.p, G.g, G.m, G.v, G.n, blocks, G.lr, G.opacity_reg,
+                              vis ? vis[base + k] : nullptr, per ? per[base + k] : 1};
       blocks += adam_blocks(G.n);
     }
     a.n_groups = ng;
@@ -115,6 +136,7 @@ hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, dou
     if (a.reg_scale == 0.0f)
       for (int k = 0; k < ng; ++k) a.grp[k].reg = 0;
     a.step_dev = step_dev;
+    a.overflow = overflow;
     if (blocks > 0) hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(kAdamThreads), 0, s, a);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

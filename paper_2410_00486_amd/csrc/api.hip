@@ -37,7 +37,8 @@ hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float*
                               bool zeroed, hipStream_t s);
 hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, double beta1,
                        double beta2, double eps, double lambda_o, int64_t reg_count,
-                       int32_t* step_dev, hipStream_t s);
+                       int32_t* step_dev, hipStream_t s, const uint32_t* const* vis = nullptr,
+                       const int32_t* per = nullptr, const int32_t* overflow = nullptr);
 hipError_t launch_tile_order(const Plan& P, void* ws, hipStream_t s);
 int render_blocks_per_cu(const Plan& P, bool bwd);
 int splat_blocks_per_cu(const Plan& P);
@@ -560,14 +561,62 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
     gC = it->loss_grad_color;
     gD = it->loss_grad_depth;
   }
-  st = gs_render_bwd(it->plan, &it->gaussians, it->cams_dev, it->ws, it->color, it->depth,
-                     it->T_final, it->last, gC, gD, it->target_rgb, it->target_depth, &it->grads,
-                     it->dL_dpose, stream);
+  // One view with Adam: the projection backward writes the gradients of the
+  // Gaussians with pairs only, and Adam takes the others as zero (no zero
+  // fill, no read).  The gradient buffers are left unspecified for those.
+  const Plan& P = *plan_of(it->plan);
+  const bool sparse = it->n_adam_groups > 0 && it->n_adam_groups <= 16 && P.vt.n_views == 1 &&
+                      !(P.cfg.flags & GS_ACCUMULATE_GRADS) && P.n > 0;
+  if (!sparse) {
+    st = gs_render_bwd(it->plan, &it->gaussians, it->cams_dev, it->ws, it->color, it->depth,
+                       it->T_final, it->last, gC, gD, it->target_rgb, it->target_depth,
+                       &it->grads, it->dL_dpose, stream);
+    if (st != GS_OK) return st;
+    if (it->n_adam_groups > 0)
+      st = gs_adam_step(it->adam_groups, it->n_adam_groups, 1, it->beta1, it->beta2, it->eps,
+                        it->lambda_o, it->reg_count, it->step_dev, stream);
+    return st;
+  }
+  st = gs_render_bwd_raster(it->plan, it->ws, it->cams_dev, it->color, it->depth, it->T_final,
+                            it->last, gC, gD, it->target_rgb, it->target_depth, stream);
   if (st != GS_OK) return st;
-  if (it->n_adam_groups > 0)
-    st = gs_adam_step(it->adam_groups, it->n_adam_groups, 1, it->beta1, it->beta2, it->eps,
-                      it->lambda_o, it->reg_count, it->step_dev, stream);
-  return st;
+  if ((st = check_gaussians(P, &it->gaussians)) != GS_OK) return st;
+  const gs_gaussian_grads& gr = it->grads;
+  if (!gr.means || !gr.log_scales || !gr.quats || !gr.opacity_logits || !gr.sh)
+    return fail(GS_ERR_INVALID_ARG, "gradient output pointers must be non-null");
+  // the Adam arguments are checked before anything of the backward is enqueued
+  if (!(it->beta1 >= 0.0 && it->beta1 < 1.0 && it->beta2 >= 0.0 && it->beta2 < 1.0 && it->eps >= 0.0))
+    return fail(GS_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+  for (int k = 0; k < it->n_adam_groups; ++k) {
+    const gs_param_group& G = it->adam_groups[k];
+    if (G.n > 0 && (!G.p || !G.g || !G.m || !G.v)) return fail(GS_ERR_INVALID_ARG, "group %d: null pointer", k);
+    if (!aligned(G.p, 16) || !aligned(G.g, 16) || !aligned(G.m, 16) || !aligned(G.v, 16))
+      return fail(GS_ERR_INVALID_ARG, "group %d: pointers must be 16-byte aligned", k);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_project_bwd(P, it->gaussians, it->cams_dev, it->ws, gr, it->dL_dpose, 0,
+                                    true, s);
+  if (e != hipSuccess) return hip_check(e, "gs_iteration_enqueue (projection backward)");
+  const uint32_t* vis[16];
+  int32_t per[16];
+  const uint32_t* tt = ws_at<uint32_t>(it->ws, P.off_tt);
+  for (int k = 0; k < it->n_adam_groups; ++k) {
+    const float* g = it->adam_groups[k].g;
+    vis[k] = tt;
+    if (g == gr.means || g == gr.log_scales) per[k] = 3;
+    else if (g == gr.quats) per[k] = 4;
+    else if (g == gr.opacity_logits) per[k] = 1;
+    else if (g == gr.sh) per[k] = 3 * P.K;
+    else per[k] = 0;
+    if (per[k] == 0 || it->adam_groups[k].n != (int64_t)per[k] * P.n) {
+      vis[k] = nullptr;  // not (all of) a gradient this iteration writes: read as is
+      per[k] = 1;
+    }
+  }
+  e = launch_adam(it->adam_groups, it->n_adam_groups, 1, it->beta1, it->beta2, it->eps,
+                  it->lambda_o, it->reg_count, it->step_dev, s, vis, per,
+                  ws_at<int32_t>(it->ws, P.off_flags) + F_OVERFLOW);
+  return hip_check(e, "gs_iteration_enqueue (Adam)");
 }
 
 struct gs_graph {

@@ -181,20 +181,8 @@ __device__ void scan_tiles(int64_t blk, const TileScanArgs& A, uint64_t* wsum) {
   }
 }
 
-// Record blocks first, then tile blocks: one launch for both scans.
-__global__ void __launch_bounds__(kScanThreads) k_scans(
-    const uint32_t* __restrict__ tt, uint32_t* __restrict__ poff, uint64_t* __restrict__ rec_tot,
-    uint32_t* __restrict__ vpre, uint64_t* __restrict__ vis_tot, int64_t n_rec,
-    int64_t rec_blocks, TileScanArgs tiles) {
-  __shared__ uint64_t wsum[kScanThreads / kWave];
-  if ((int64_t)blockIdx.x < rec_blocks)
-    scan_records(blockIdx.x, tt, poff, rec_tot, vpre, vis_tot, n_rec, wsum);
-  else
-    scan_tiles((int64_t)blockIdx.x - rec_blocks, tiles, wsum);
-}
-
-// In-place exclusive scans of up to six u64 arrays at once by one
-// 1024-thread block (each array has its own length); totals to tot[].
+// Block-total arrays of the scans (records: pairs, visible; tiles: pairs,
+// buckets, full and half buckets), scanned together by one block.
 constexpr int kMaxChannels = 6;
 struct ScanChannels {
   uint64_t* a[kMaxChannels];
@@ -202,15 +190,18 @@ struct ScanChannels {
   int count;
 };
 
+// In-place exclusive scans of up to six u64 arrays at once by one block of
+// NT threads (each array has its own length); totals to tot[].
+template <int NT>
 __device__ void block_scan_channels(const ScanChannels& ch, uint64_t* tot) {
-  __shared__ uint64_t wsum[kMaxChannels][1024 / kWave];
+  __shared__ uint64_t wsum[kMaxChannels][NT / kWave];
   __shared__ uint64_t carry[kMaxChannels];
   const int lane = lane_id(), w = threadIdx.x / kWave;
   if (threadIdx.x < kMaxChannels) carry[threadIdx.x] = 0;
   int64_t nmax = 0;
   for (int c = 0; c < ch.count; ++c) nmax = ch.n[c] > nmax ? ch.n[c] : nmax;
   __syncthreads();
-  for (int64_t base = 0; base < nmax; base += 1024) {
+  for (int64_t base = 0; base < nmax; base += NT) {
     const int64_t idx = base + threadIdx.x;
     uint64_t x[kMaxChannels], incl[kMaxChannels];
 #pragma unroll
@@ -234,39 +225,64 @@ __device__ void block_scan_channels(const ScanChannels& ch, uint64_t* tot) {
       uint64_t woff = carry[c];
       for (int k = 0; k < w; ++k) woff += wsum[c][k];
       if (c < ch.count && idx < ch.n[c]) ch.a[c][idx] = woff + incl[c] - x[c];
-      if (threadIdx.x == 1023) incl[c] = woff + incl[c];  // running total
+      if (threadIdx.x == NT - 1) incl[c] = woff + incl[c];  // running total
     }
     __syncthreads();
-    if (threadIdx.x == 1023)
+    if (threadIdx.x == NT - 1)
       for (int c = 0; c < kMaxChannels; ++c) carry[c] = incl[c];
     __syncthreads();
   }
   for (int c = 0; c < kMaxChannels; ++c) tot[c] = carry[c];
 }
 
-// Exclusive scans of the block totals of the record scan (pairs, visible)
-// and of the tile scan (pairs, buckets, full and half buckets): one block.
-// Both pair totals count the same pairs; a mismatch is reported as an
-// overflow so that nothing is scattered.
-__global__ void __launch_bounds__(1024) k_scan_totals(ScanChannels ch, int64_t cap,
-                                                      int32_t* __restrict__ fl) {
-  uint64_t tot[kMaxChannels];
-  block_scan_channels(ch, tot);
+// From the scanned totals: pair count, capacity check, visible count and
+// the sizes of the bucket queues.  Both pair totals count the same pairs; a
+// mismatch is reported as an overflow so that nothing is scattered.
+__device__ void set_scan_flags(const ScanChannels& ch, const uint64_t* tot, int64_t cap,
+                               int32_t* fl) {
+  const uint64_t total = tot[0], visible = tot[1], total_t = tot[2];
+  const uint64_t n_full = ch.count > 4 ? tot[4] : 0, n_half = ch.count > 5 ? tot[5] : 0;
+  const bool over = total > (uint64_t)cap || total != total_t;
+  fl[F_OVERFLOW] = over ? 1 : 0;
+  fl[F_PAIRS] = over ? 0 : (int32_t)total;
+  fl[F_PAIRS_WANTED] = total > 0x7FFFFFFFull ? 0x7FFFFFFF : (int32_t)total;
+  fl[F_VISIBLE] = (int32_t)visible;
+  // long lists are queued by the tile sort that follows; the bucket queues
+  // are filled there at the positions scanned here
+  fl[F_LONG_TILES] = 0;
+  fl[F_BQ_FULL] = over ? 0 : (int32_t)n_full;
+  fl[F_BQ_HALF] = over ? 0 : (int32_t)n_half;
+}
+
+// Record blocks first, then tile blocks: one launch for both scans.
+// The last block to finish (counted in a flag; each block publishes its
+// totals before it counts itself) scans the block totals of all channels.
+__global__ void __launch_bounds__(kScanThreads) k_scans(
+    const uint32_t* __restrict__ tt, uint32_t* __restrict__ poff, uint64_t* __restrict__ rec_tot,
+    uint32_t* __restrict__ vpre, uint64_t* __restrict__ vis_tot, int64_t n_rec,
+    int64_t rec_blocks, TileScanArgs tiles, ScanChannels ch, int64_t cap,
+    int32_t* __restrict__ fl) {
+  __shared__ uint64_t wsum[kScanThreads / kWave];
+  __shared__ int is_last;
+  if ((int64_t)blockIdx.x < rec_blocks)
+    scan_records(blockIdx.x, tt, poff, rec_tot, vpre, vis_tot, n_rec, wsum);
+  else
+    scan_tiles((int64_t)blockIdx.x - rec_blocks, tiles, wsum);
   if (threadIdx.x == 0) {
-    const uint64_t total = tot[0], visible = tot[1], total_t = tot[2];
-    const uint64_t n_full = ch.count > 4 ? tot[4] : 0, n_half = ch.count > 5 ? tot[5] : 0;
-    const bool over = total > (uint64_t)cap || total != total_t;
-    fl[F_OVERFLOW] = over ? 1 : 0;
-    fl[F_PAIRS] = over ? 0 : (int32_t)total;
-    fl[F_PAIRS_WANTED] = total > 0x7FFFFFFFull ? 0x7FFFFFFF : (int32_t)total;
-    fl[F_VISIBLE] = (int32_t)visible;
-    // long lists are queued by the tile sort that follows; the bucket
-    // queues are filled there at the positions scanned here
-    fl[F_LONG_TILES] = 0;
-    fl[F_BQ_FULL] = over ? 0 : (int32_t)n_full;
-    fl[F_BQ_HALF] = over ? 0 : (int32_t)n_half;
+    __threadfence();  // this block's totals before its count
+    is_last = atomicAdd(&fl[F_SCAN_DONE], 1) == (int)gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!is_last) return;  // uniform over the block
+  __threadfence();
+  uint64_t tot[kMaxChannels];
+  block_scan_channels<kScanThreads>(ch, tot);
+  if (threadIdx.x == 0) {
+    set_scan_flags(ch, tot, cap, fl);
+    fl[F_SCAN_DONE] = 0;  // ready for the next binning
   }
 }
+
 
 // ---------------------------------------------------------------- scatter
 // Generation offsets become absolute (poff), every pair gets the next free
@@ -731,11 +747,11 @@ hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t s) {
 }
 
 hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s) {
-  // per-iteration flags 0..9 and the per-tile pair counters
+  // per-iteration flags 0..10 and the per-tile pair counters
   const int64_t T = P.vt.total_tiles;
   const int64_t m = T > 4 ? T : 4;
   hipLaunchKernelGGL(k_fill2_u32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
-                     ws_at<uint32_t>(ws, P.off_flags), (int64_t)10,
+                     ws_at<uint32_t>(ws, P.off_flags), (int64_t)11,
                      ws_at<uint32_t>(ws, P.off_tile_cnt), T);
   return hipGetLastError();
 }
@@ -759,15 +775,14 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
   uint64_t* full_tot = splat ? ws_at<uint64_t>(ws, P.off_full_scan) : nullptr;
   uint32_t* hstart = splat ? ws_at<uint32_t>(ws, P.off_half_start) : nullptr;
   uint64_t* half_tot = splat ? ws_at<uint64_t>(ws, P.off_half_scan) : nullptr;
-  if (sb + tb > 0) {
-    TileScanArgs ta{tcnt, tstart, tile_tot, (int64_t)T, bstart, bucket_tot, fstart, full_tot,
-                    hstart, half_tot};
-    hipLaunchKernelGGL(k_scans, dim3((unsigned)(sb + tb)), dim3(kScanThreads), 0, s, tt, poff,
-                       rec_tot, ws_at<uint32_t>(ws, P.off_vpre), vis_tot, P.n_rec, sb, ta);
-  }
+  TileScanArgs ta{tcnt, tstart, tile_tot, (int64_t)T, bstart, bucket_tot, fstart, full_tot,
+                  hstart, half_tot};
   ScanChannels ch{{rec_tot, vis_tot, tile_tot, bucket_tot, full_tot, half_tot},
                   {sb, sb, tb, tb, tb, tb}, splat ? 6 : 3};
-  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, ch, P.pair_cap, fl);
+  // at least one block, so that the flags are always set
+  hipLaunchKernelGGL(k_scans, dim3((unsigned)std::max<int64_t>(sb + tb, 1)), dim3(kScanThreads), 0,
+                     s, tt, poff, rec_tot, ws_at<uint32_t>(ws, P.off_vpre), vis_tot, P.n_rec, sb,
+                     ta, ch, P.pair_cap, fl);
   uint64_t* skey = ws_at<uint64_t>(ws, P.off_scatter);
   uint32_t* pair_rec = ws_at<uint32_t>(ws, P.off_pair_rec);
   if (P.n_rec > 0) {

@@ -28,6 +28,7 @@ enum Flag : int {
   F_LONG_TILES = 7,  // tiles whose lists go to the long-list sort
   F_BQ_FULL = 8,     // splat-wise buckets with more than 32 pairs
   F_BQ_HALF = 9,     // splat-wise buckets with at most 32 pairs
+  F_SCAN_DONE = 10,  // blocks of the binning scans that have finished
   F_COUNT = 16
 };
 

@@ -392,6 +392,42 @@ def test_graph_replay_equals_eager(flags):
     graphed.close()
 
 
+@pytest.mark.parametrize("lambda_o", [0.0, 0.001])
+def test_iteration_sparse_adam_equals_separate_calls(lambda_o):
+    """One-view iteration with Adam (gradients of Gaussians without pairs are
+    not written; Adam takes them as zero) against the separate calls with
+    fully written gradients: parameters and moments bit for bit."""
+    w = workload(1)
+    cam = w.cameras[0]
+    lrs = {"means": 1e-3, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
+    tgt = t32(w.target_rgb[0].reshape(-1))
+    cams = gsr.cameras_tensor([cam], DEV)
+    plan = gsr.Plan(w.scene.n, 0, [(cam.width, cam.height)], flags=L.GS_FUSED_L1,
+                    pair_capacity=1 << 16)
+    g1 = gsr.Gaussians.from_scene(w.scene, DEV)
+    it = gsr.Iteration(plan, g1, cams, target_rgb=tgt, adam_lrs=lrs, lambda_o=lambda_o)
+    # stale, non-zero gradient buffers must not leak into the step
+    for x in it.grads.tensors():
+        x.fill_(7.0)
+    it.enqueue()
+    g2 = gsr.Gaussians.from_scene(w.scene, DEV)
+    ws = plan.new_workspace(DEV)
+    fr = gsr.Frame(plan, DEV)
+    grads, m, v = g2.zeros_like(), g2.zeros_like(), g2.zeros_like()
+    gsr.preprocess(plan, ws, g2, cams)
+    gsr.bin_sort(plan, ws)
+    gsr.render_fwd(plan, ws, cams, fr, tgt)
+    gsr.render_bwd(plan, ws, g2, cams, fr, grads, target_rgb=tgt)
+    groups = gsr.adam_groups(g2, grads, m, v, lrs, lambda_o != 0.0)
+    gsr.adam_step(groups, 1, lambda_o=lambda_o, reg_count=g2.n)
+    torch.cuda.synchronize()
+    assert int(plan.flags_of(it.ws)[L.F_VISIBLE]) < g1.n  # some Gaussians have no pairs
+    for f in gsr.Gaussians.FIELDS:
+        assert torch.equal(getattr(g1, f), getattr(g2, f)), f
+        assert torch.equal(getattr(it.m, f), getattr(m, f)), f
+        assert torch.equal(getattr(it.v, f), getattr(v, f)), f
+
+
 # ------------------------------------------------------------------ edge cases
 
 def test_empty_scene_and_empty_view():
