@@ -397,14 +397,17 @@ def test_iteration_sparse_adam_equals_separate_calls(lambda_o):
     """One-view iteration with Adam (gradients of Gaussians without pairs are
     not written; Adam takes them as zero) against the separate calls with
     fully written gradients: parameters and moments bit for bit."""
-    w = workload(1)
+    w = workload(3)  # 640x480 view of a 150k room: most Gaussians have no pairs
     cam = w.cameras[0]
     lrs = {"means": 1e-3, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
-    tgt = t32(w.target_rgb[0].reshape(-1))
+    rng = np.random.default_rng(9)
+    tgt = t32(rng.uniform(0.0, 1.0, (3, cam.height, cam.width)).reshape(-1))
     cams = gsr.cameras_tensor([cam], DEV)
-    plan = gsr.Plan(w.scene.n, 0, [(cam.width, cam.height)], flags=L.GS_FUSED_L1,
-                    pair_capacity=1 << 16)
     g1 = gsr.Gaussians.from_scene(w.scene, DEV)
+    cap = gsr.required_pairs(*g1.tensors(), cams, [(cam.width, cam.height)], w.scene.sh_degree,
+                             (16, 16)) + 7
+    plan = gsr.Plan(w.scene.n, w.scene.sh_degree, [(cam.width, cam.height)], flags=L.GS_FUSED_L1,
+                    pair_capacity=cap)
     it = gsr.Iteration(plan, g1, cams, target_rgb=tgt, adam_lrs=lrs, lambda_o=lambda_o)
     # stale, non-zero gradient buffers must not leak into the step
     for x in it.grads.tensors():
