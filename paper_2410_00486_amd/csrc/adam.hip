@@ -69,9 +69,26 @@ __global__ void __launch_bounds__(kAdamThreads) k_adam(AdamArgs a) {
     float4 p = *reinterpret_cast<float4*>(G.p + e0);
     float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
     if (G.vis) {
-      const bool over = *a.overflow != 0;
-      const bool v0 = !over && G.vis[e0 / G.per] != 0, v1 = !over && G.vis[(e0 + 1) / G.per] != 0;
-      const bool v2 = !over && G.vis[(e0 + 2) / G.per] != 0, v3 = !over && G.vis[(e0 + 3) / G.per] != 0;
+      // visibility of the four elements' Gaussians (e0 is a multiple of 4)
+      bool v0, v1, v2, v3;
+      if (*a.overflow != 0) {
+        v0 = v1 = v2 = v3 = false;
+      } else if (G.per == 1) {
+        const uint4 t = *reinterpret_cast<const uint4*>(G.vis + e0);
+        v0 = t.x != 0; v1 = t.y != 0; v2 = t.z != 0; v3 = t.w != 0;
+      } else if (G.per == 3) {
+        const int64_t q = e0 / 3;  // elements e0..e0+3 belong to q and q + 1
+        const int r = (int)(e0 - 3 * q);
+        const bool a0 = G.vis[q] != 0, a1 = G.vis[q + 1] != 0;
+        v0 = a0; v1 = r < 2 ? a0 : a1; v2 = r < 1 ? a0 : a1; v3 = a1;
+      } else if ((G.per & 3) == 0) {  // one Gaussian
+        v0 = v1 = v2 = v3 = G.vis[e0 / G.per] != 0;
+      } else {
+        v0 = G.vis[e0 / G.per] != 0;
+        v1 = G.vis[(e0 + 1) / G.per] != 0;
+        v2 = G.vis[(e0 + 2) / G.per] != 0;
+        v3 = G.vis[(e0 + 3) / G.per] != 0;
+      }
       if (v0 || v1 || v2 || v3) {
         const float4 gl = *reinterpret_cast<const float4*>(G.g + e0);
         g = make_float4(v0 ? gl.x : 0.f, v1 ? gl.y : 0.f, v2 ? gl.z : 0.f, v3 ? gl.w : 0.f);

@@ -392,28 +392,31 @@ def test_graph_replay_equals_eager(flags):
     graphed.close()
 
 
-@pytest.mark.parametrize("lambda_o", [0.0, 0.001])
-def test_iteration_sparse_adam_equals_separate_calls(lambda_o):
+@pytest.mark.parametrize("lambda_o,degree", [(0.0, 3), (0.001, 3), (0.0, 2), (0.0, 0)])
+def test_iteration_sparse_adam_equals_separate_calls(lambda_o, degree):
     """One-view iteration with Adam (gradients of Gaussians without pairs are
     not written; Adam takes them as zero) against the separate calls with
     fully written gradients: parameters and moments bit for bit."""
     w = workload(3)  # 640x480 view of a 150k room: most Gaussians have no pairs
     cam = w.cameras[0]
+    K = (degree + 1) ** 2
+    sc = w.scene
+    scene = scenes.Scene(sc.means, sc.log_scales, sc.quats, sc.opacity_logits,
+                         np.ascontiguousarray(sc.sh[:, :K]), degree)
     lrs = {"means": 1e-3, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
     rng = np.random.default_rng(9)
     tgt = t32(rng.uniform(0.0, 1.0, (3, cam.height, cam.width)).reshape(-1))
     cams = gsr.cameras_tensor([cam], DEV)
-    g1 = gsr.Gaussians.from_scene(w.scene, DEV)
-    cap = gsr.required_pairs(*g1.tensors(), cams, [(cam.width, cam.height)], w.scene.sh_degree,
-                             (16, 16)) + 7
-    plan = gsr.Plan(w.scene.n, w.scene.sh_degree, [(cam.width, cam.height)], flags=L.GS_FUSED_L1,
+    g1 = gsr.Gaussians.from_scene(scene, DEV)
+    cap = gsr.required_pairs(*g1.tensors(), cams, [(cam.width, cam.height)], degree, (16, 16)) + 7
+    plan = gsr.Plan(scene.n, degree, [(cam.width, cam.height)], flags=L.GS_FUSED_L1,
                     pair_capacity=cap)
     it = gsr.Iteration(plan, g1, cams, target_rgb=tgt, adam_lrs=lrs, lambda_o=lambda_o)
     # stale, non-zero gradient buffers must not leak into the step
     for x in it.grads.tensors():
         x.fill_(7.0)
     it.enqueue()
-    g2 = gsr.Gaussians.from_scene(w.scene, DEV)
+    g2 = gsr.Gaussians.from_scene(scene, DEV)
     ws = plan.new_workspace(DEV)
     fr = gsr.Frame(plan, DEV)
     grads, m, v = g2.zeros_like(), g2.zeros_like(), g2.zeros_like()
