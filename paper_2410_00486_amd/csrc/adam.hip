@@ -76,18 +76,20 @@ __global__ void __launch_bounds__(kAdamThreads) k_adam(AdamArgs a) {
       } else if (G.per == 1) {
         const uint4 t = *reinterpret_cast<const uint4*>(G.vis + e0);
         v0 = t.x != 0; v1 = t.y != 0; v2 = t.z != 0; v3 = t.w != 0;
-      } else if (G.per == 3) {
-        const int64_t q = e0 / 3;  // elements e0..e0+3 belong to q and q + 1
-        const int r = (int)(e0 - 3 * q);
-        const bool a0 = G.vis[q] != 0, a1 = G.vis[q + 1] != 0;
-        v0 = a0; v1 = r < 2 ? a0 : a1; v2 = r < 1 ? a0 : a1; v3 = a1;
-      } else if ((G.per & 3) == 0) {  // one Gaussian
-        v0 = v1 = v2 = v3 = G.vis[e0 / G.per] != 0;
       } else {
-        v0 = G.vis[e0 / G.per] != 0;
-        v1 = G.vis[(e0 + 1) / G.per] != 0;
-        v2 = G.vis[(e0 + 2) / G.per] != 0;
-        v3 = G.vis[(e0 + 3) / G.per] != 0;
+        // e0 = q0 per + r0; element e0 + i belongs to Gaussian q0 + (r0 + i) / per
+        const int64_t q0 = e0 / G.per;
+        const int r0 = (int)(e0 - q0 * G.per);
+        const int per = G.per;
+        auto vis_at = [&](int i) {
+          const int r = r0 + i;
+          const int64_t q = q0 + (r >= per ? 1 : 0) + (r >= 2 * per ? 1 : 0) + (r >= 3 * per ? 1 : 0);
+          return G.vis[q] != 0;
+        };
+        v0 = vis_at(0);
+        v1 = vis_at(1);
+        v2 = vis_at(2);
+        v3 = vis_at(3);
       }
       if (v0 || v1 || v2 || v3) {
         const float4 gl = *reinterpret_cast<const float4*>(G.g + e0);
