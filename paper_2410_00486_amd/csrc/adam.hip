@@ -78,7 +78,12 @@ __global__ void __launch_bounds__(kAdamThreads) k_adam(AdamArgs a) {
         v0 = t.x != 0; v1 = t.y != 0; v2 = t.z != 0; v3 = t.w != 0;
       } else {
         // e0 = q0 per + r0; element e0 + i belongs to Gaussian q0 + (r0 + i) / per
-        const int64_t q0 = e0 / G.per;
+        int64_t q0;
+        if (G.n <= 0xFFFFFFFFll) {  // uniform: 32-bit division
+          q0 = (int64_t)((uint32_t)e0 / (uint32_t)G.per);
+        } else {
+          q0 = e0 / G.per;
+        }
         const int r0 = (int)(e0 - q0 * G.per);
         const int per = G.per;
         auto vis_at = [&](int i) {
