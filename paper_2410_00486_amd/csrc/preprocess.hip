@@ -51,6 +51,14 @@ __device__ __forceinline__ void sh_basis(double x, double y, double z, double* Y
 
 __device__ __forceinline__ bool finite_f(float v) { return __builtin_isfinite(v); }
 
+// Orders this wavefront's LDS writes before its later reads (other
+// wavefronts of the block are not involved).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int DEG>
 __global__ void __launch_bounds__(256) k_preprocess(
     const float* __restrict__ means, const float* __restrict__ log_scales,
@@ -99,10 +107,11 @@ __global__ void __launch_bounds__(256) k_preprocess(
   bool sh_loaded = false;
   float shv[K * 3];
 
+  __shared__ uint32_t s_pre[256 / kWave][kWave], s_xy[256 / kWave][kWave], s_w[256 / kWave][kWave];
   for (int v = 0; v < vt.n_views; ++v) {
     const ViewInfo vi = vt.v[v];
     const int64_t ri = (int64_t)v * n + i;
-    uint32_t count = 0;
+    uint32_t count = 0, box_xy = 0, box_w = 0;
     if (ok) {
       const float* c = cams + (int64_t)v * GS_CAMERA_FLOATS;
       const double fx = c[0], fy = c[1], cx = c[2], cy = c[3];
@@ -210,12 +219,40 @@ __global__ void __launch_bounds__(256) k_preprocess(
         rect[ri] = make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)x1,
                                 (unsigned short)y1);
         count = (uint32_t)((x1 - x0) * (y1 - y0));
-        // pairs per tile, for the binning
-        for (int ty = y0; ty < y1; ++ty)
-          for (int tx = x0; tx < x1; ++tx) atomicAdd(&tile_cnt[vi.tile_off + ty * vi.tiles_x + tx], 1u);
+        box_xy = (uint32_t)x0 | ((uint32_t)y0 << 16);
+        box_w = (uint32_t)(x1 - x0);
       }
     }
     if (in_range) tt[ri] = count;
+    // pairs per tile, for the binning: the wavefront's pairs are spread over
+    // its lanes (a large Gaussian does not serialise its tiles on one lane)
+    {
+      const int lane = lane_id(), w = threadIdx.x / kWave;
+      uint32_t incl = count;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+      }
+      const uint32_t total = __shfl(incl, kWave - 1, kWave);
+      if (total > 0) {  // uniform over the wavefront
+        s_pre[w][lane] = incl - count;
+        s_xy[w][lane] = box_xy;
+        s_w[w][lane] = box_w;
+        wave_lds_sync();
+        for (uint32_t q = (uint32_t)lane; q < total; q += kWave) {
+          int lo = 0, hi = kWave - 1;  // owner: the last lane whose prefix is <= q
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_pre[w][mid] <= q) lo = mid; else hi = mid - 1;
+          }
+          const uint32_t k = q - s_pre[w][lo], bw = s_w[w][lo], xy = s_xy[w][lo];
+          const int tx = (int)(xy & 0xFFFFu) + (int)(k % bw), ty = (int)(xy >> 16) + (int)(k / bw);
+          atomicAdd(&tile_cnt[vi.tile_off + ty * vi.tiles_x + tx], 1u);
+        }
+        wave_lds_sync();  // before the next view rewrites the tables
+      }
+    }
   }
   // non-finite Gaussians are rare: one atomic per wave that has any (the
   // visible-record count is taken by the binning's record scan)

@@ -192,9 +192,10 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec
     __syncthreads();
     for (int j = 0; j < nb; ++j) {
       if constexpr (CKPT) {
-        // state of every pixel before each 64th splat of the tile list
+        // state of every pixel before each 64th splat of the tile list (the
+        // state before the first splat is the empty one and is not stored)
         const uint32_t q = b - s + (uint32_t)j;
-        if ((q & (kBucket - 1)) == 0) {
+        if (q != 0 && (q & (kBucket - 1)) == 0) {
           float* cp = ckpt + (int64_t)(boff[gtile] + q / kBucket) * (kStateFloats * NPX);
 #pragma unroll
           for (int k = 0; k < PPL; ++k) {
@@ -627,8 +628,10 @@ __device__ __forceinline__ void splat_wave(
         }
         b.x = a.x * o0 + a.y * o1 + a.z * o2 + a.w * od;
         b.y = __uint_as_float(last[pix]);
-        b.z = cp[j];
-        b.w = a.x * cp[NPX + j] + a.y * cp[2 * NPX + j] + a.z * cp[3 * NPX + j] + a.w * cp[4 * NPX + j];
+        if (k > 0) {  // the first bucket starts from T = 1 and nothing accumulated
+          b.z = cp[j];
+          b.w = a.x * cp[NPX + j] + a.y * cp[2 * NPX + j] + a.z * cp[3 * NPX + j] + a.w * cp[4 * NPX + j];
+        }
       }
       sa[j] = a;
       sb[j] = b;
