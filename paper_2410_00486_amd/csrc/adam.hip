@@ -66,7 +66,10 @@ __global__ void __launch_bounds__(kAdamThreads) k_adam(AdamArgs a) {
   const int64_t e0 = ((int64_t)blockIdx.x - G.block0) * (kAdamThreads * kAdamVec) +
                      (int64_t)threadIdx.x * kAdamVec;
   if (e0 + kAdamVec <= G.n) {
+    // p, m, v first: they do not wait for the visibility lookup
     float4 p = *reinterpret_cast<float4*>(G.p + e0);
+    float4 m = *reinterpret_cast<float4*>(G.m + e0);
+    float4 v = *reinterpret_cast<float4*>(G.v + e0);
     float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
     if (G.vis) {
       // visibility of the four elements' Gaussians (e0 is a multiple of 4)
@@ -103,8 +106,6 @@ __global__ void __launch_bounds__(kAdamThreads) k_adam(AdamArgs a) {
     } else {
       g = *reinterpret_cast<const float4*>(G.g + e0);
     }
-    float4 m = *reinterpret_cast<float4*>(G.m + e0);
-    float4 v = *reinterpret_cast<float4*>(G.v + e0);
     adam_one(p.x, g.x, m.x, v.x, a, step_size, inv_bc2s, G.reg);
     adam_one(p.y, g.y, m.y, v.y, a, step_size, inv_bc2s, G.reg);
     adam_one(p.z, g.z, m.z, v.z, a, step_size, inv_bc2s, G.reg);
