@@ -174,9 +174,10 @@ gs_status gs_preprocess(const gs_plan* plan, const gs_gaussians* g, const float*
  * Pairs are the (record, tile) incidences of the tile boxes, numbered in
  * generation order (record-major, row-major tiles).  Each tile's list is
  * ordered by (float32 depth, generation index): ties in depth keep Gaussian
- * order, so the lists are unique and bit-exact.  Needs the per-tile counts
- * of the gs_preprocess call just before on the same workspace.  Overflow of
- * the plan's pair capacity sets flag [0]. */
+ * order, so the lists are unique and bit-exact.  Needs the per-tile and
+ * per-chunk (64 Gaussians of a view) pair counts of the gs_preprocess call
+ * just before on the same workspace.  Overflow of the plan's pair capacity
+ * sets flag [0]. */
 gs_status gs_bin_sort(const gs_plan* plan, void* ws, void* stream);
 
 /* a3. Front-to-back compositing of Eq. (1) per pixel over its tile's sorted

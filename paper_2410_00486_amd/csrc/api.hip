@@ -188,8 +188,8 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   vt.total_tiles = (int32_t)tiles;
   vt.total_pix = pix;
   P->tile_bits = std::max(1, ceil_log2(tiles));
-  P->scan_blocks = (P->n_rec + kScanTile - 1) / kScanTile;
-  P->tile_scan_blocks = (tiles + kScanTile - 1) / kScanTile;
+  P->chunks_per_view = (n + kWave - 1) / kWave;
+  P->n_chunks = (int64_t)n_views * P->chunks_per_view;
   P->proj_blocks = (n + kProjThreads - 1) / kProjThreads;
   const int64_t order_blocks = (tiles + kSortTile - 1) / kSortTile;
 
@@ -205,13 +205,11 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_rect = take(nrec * 8);
   P->off_tt = take(nrec * 4);
   P->off_poff = take(nrec * 4);
-  P->off_scan = take((size_t)std::max<int64_t>(P->scan_blocks, 1) * 8);
-  P->off_vis_scan = take((size_t)std::max<int64_t>(P->scan_blocks, 1) * 8);
-  P->off_vpre = take(nrec * 4);
+  P->off_chunk_cnt = take((size_t)P->n_chunks * 8);
+  P->off_chunk_pre = take((size_t)P->n_chunks * 8);
   P->off_vis_list = take(nrec * 4);
   P->off_tile_cnt = take(T * 4);
   P->off_tile_start = take(T * 4);
-  P->off_tile_scan = take((size_t)std::max<int64_t>(P->tile_scan_blocks, 1) * 8);
   P->off_long = take(T * 4);
   P->off_keys = take(cap * 8);
   P->off_scatter = take(cap * 8);
@@ -235,14 +233,10 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   // pair_capacity / 64 + tiles slots
   const bool splat = (cfg->flags & GS_SPLAT_BWD) != 0;
   P->ckpt_slots = splat ? pair_capacity / kBucket + tiles : 0;
-  P->off_bucket_start = take(splat ? T * 4 : 0);
-  P->off_bucket_scan = take(splat ? (size_t)std::max<int64_t>(P->tile_scan_blocks, 1) * 8 : 0);
   P->off_boff = take(splat ? (T + 1) * 4 : 0);
   P->off_bq = take((size_t)P->ckpt_slots * 2 * 8);  // two bucket queues of (tile, k)
   P->off_full_start = take(splat ? T * 4 : 0);
-  P->off_full_scan = take(splat ? (size_t)std::max<int64_t>(P->tile_scan_blocks, 1) * 8 : 0);
   P->off_half_start = take(splat ? T * 4 : 0);
-  P->off_half_scan = take(splat ? (size_t)std::max<int64_t>(P->tile_scan_blocks, 1) * 8 : 0);
   P->off_ckpt = take((size_t)P->ckpt_slots * tw * th * kStateFloats * 4);
   P->ws_size = o;
   P->magic = kPlanMagic;

@@ -3,14 +3,16 @@
 // within a box).  The order the renderer needs is (tile, depth, generation
 // index): unique, so the result is bit-exact whatever the schedule.
 //
-// The projection counts pairs per tile as it computes the boxes.  Then:
-// exclusive scans of the per-record pair counts (generation offsets) and of
-// the per-tile counts (tile list starts), one scatter that puts every pair
-// into its tile's list at an atomically taken slot with the key
-// (depth bits << 32 | generation index), and a per-tile sort of those keys
-// (one wavefront per tile: a bitonic network in LDS for lists up to 2048,
-// an LSD radix sort through global memory beyond).  Five launches whatever
-// the pair count, no spin-waits; graph-capturable.
+// The projection counts pairs per tile and per chunk of 64 Gaussians as it
+// computes the boxes.  Then: one block scans the chunk counts (generation
+// offsets, visible-list positions) and the tile counts (list starts, bucket
+// offsets and queue positions); one scatter puts every pair into its tile's
+// list at an atomically taken slot with the key (depth bits << 32 |
+// generation index); a per-tile sort orders those keys (one wavefront per
+// tile: ranks in registers up to 64 keys, a bitonic network in LDS up to
+// 512; longer lists go to 1024-thread blocks, in LDS up to 16384 keys and in
+// global memory beyond).  Four launches whatever the pair count, no
+// spin-waits; graph-capturable.
 //
 // The general stable LSD radix sort (8-bit digits, wave64 ballot ranking)
 // below serves the standalone key/value sort and the longest-first tile
@@ -35,73 +37,29 @@ __global__ void k_fill2_u32(uint32_t* __restrict__ a, int64_t na, uint32_t* __re
 }
 
 // ---------------------------------------------------------------- scans
-// Block-level exclusive scans of per-element counts (kScanThreads threads x
-// kScanItems consecutive elements).  Sums are 64-bit: a block-local offset
-// is stored as u32, which is exact whenever the total fits the pair
-// capacity (< 2^31); otherwise the overflow flag stops every consumer.
+// The projection writes, for every chunk of 64 Gaussians of a view (one
+// wavefront), its pair count and its number of visible records; and the
+// pair count of every tile.  One block scans both: chunks -> generation
+// offset and visible-list position of the chunk's first record; tiles ->
+// list start, bucket offset and positions in the two splat-wise bucket
+// queues.  One block needs no inter-block handshake (a grid-wide fence
+// costs more than the scan itself at these sizes), and the results are
+// absolute, so the consumers add nothing.
+//
+// Offsets are stored as u32, exact whenever the pair total fits the pair
+// capacity (< 2^31); otherwise the overflow flag stops every consumer.  The
+// running sums are 64-bit.
 
-// Exclusive start of this thread's items within the block for a thread sum
-// s; the block total goes to *total.  Every thread of the block must call.
-__device__ __forceinline__ uint64_t scan_start(uint64_t s, uint64_t* wsum, uint64_t* total) {
-  const int lane = lane_id(), w = threadIdx.x / kWave;
-  uint64_t incl = s;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const uint64_t y = __shfl_up(incl, o, kWave);
-    if (lane >= o) incl += y;
-  }
-  if (lane == kWave - 1) wsum[w] = incl;
-  __syncthreads();
-  uint64_t woff = 0, tot = 0;
-  for (int k = 0; k < kScanThreads / kWave; ++k) {
-    woff += k < w ? wsum[k] : 0ull;
-    tot += wsum[k];
-  }
-  __syncthreads();  // wsum is reused by the next channel
-  *total = tot;
-  return woff + incl - s;
-}
+constexpr int kScanBlock = 1024;  // threads of the scan block
+constexpr int kScanVec = 2;       // uint4 loads per thread and array in a round
+// A round: 4 * kScanVec consecutive tiles and 2 * kScanVec consecutive
+// chunks per thread, loaded and stored as uint4.
+constexpr int64_t kTileRound = (int64_t)kScanBlock * 4 * kScanVec;
+constexpr int64_t kChunkRound = (int64_t)kScanBlock * 2 * kScanVec;
 
-// Records: pair counts -> generation offsets (poff); visible (non-zero)
-// records -> position in the compact visible list (vpre).
-__device__ void scan_records(int64_t blk, const uint32_t* __restrict__ tt,
-                             uint32_t* __restrict__ poff, uint64_t* __restrict__ rec_tot,
-                             uint32_t* __restrict__ vpre, uint64_t* __restrict__ vis_tot,
-                             int64_t n, uint64_t* wsum) {
-  const int64_t base = blk * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
-  uint64_t sp = 0, sv = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t idx = base + k;
-    v[k] = idx < n ? tt[idx] : 0u;
-    sp += v[k];
-    sv += v[k] > 0 ? 1u : 0u;
-  }
-  uint64_t tp, tv;
-  uint64_t rp = scan_start(sp, wsum, &tp);
-  uint64_t rv = scan_start(sv, wsum, &tv);
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t idx = base + k;
-    if (idx < n) {
-      poff[idx] = (uint32_t)rp;
-      vpre[idx] = (uint32_t)rv;
-    }
-    rp += v[k];
-    rv += v[k] > 0 ? 1u : 0u;
-  }
-  if (threadIdx.x == 0) {
-    rec_tot[blk] = tp;
-    vis_tot[blk] = tv;
-  }
-}
-
-// Tiles: pair counts -> list starts (the counters are cleared and become
-// the scatter's cursors).  With the splat-wise backward also the starts of
-// each tile's buckets of 64 positions, and its positions in the two bucket
-// queues: buckets with more than 32 pairs (all but possibly the last) and
-// buckets with at most 32 (possibly the last).
+// Splits a tile of c pairs into buckets of 64 positions: all but possibly
+// the last hold more than 32 pairs (full); a last bucket with at most 32
+// pairs is a half bucket.
 __device__ __forceinline__ void bucket_split(uint32_t c, uint32_t& nb, uint32_t& full,
                                              uint32_t& half) {
   nb = (c + kBucket - 1) / kBucket;
@@ -110,253 +68,309 @@ __device__ __forceinline__ void bucket_split(uint32_t c, uint32_t& nb, uint32_t&
   full = nb - half;
 }
 
-struct TileScanArgs {
-  uint32_t* cnt;
-  uint32_t* tstart;
-  uint64_t* tile_tot;
-  int64_t n;
-  uint32_t* bstart;
-  uint64_t* bucket_tot;
-  uint32_t* fstart;
-  uint64_t* full_tot;
-  uint32_t* hstart;
-  uint64_t* half_tot;
+struct ScanArgs {
+  const uint2* chunk_cnt;  // (pairs, visible records) per chunk
+  uint2* chunk_pre;        // (generation offset, visible-list position) per chunk
+  int64_t n_chunks;
+  uint32_t* cnt;           // pairs per tile; cleared here (the scatter's cursors)
+  uint32_t* tstart;        // list start per tile
+  int64_t n_tiles;
+  uint32_t* boff;          // splat-wise only (else null): bucket offset per tile, [T] = total
+  uint32_t* fstart;        // position of the tile's first full bucket in queue 0
+  uint32_t* hstart;        // position of the tile's half bucket in queue 1
 };
 
-__device__ void scan_tiles(int64_t blk, const TileScanArgs& A, uint64_t* wsum) {
-  uint32_t* __restrict__ cnt = A.cnt;
-  uint32_t* __restrict__ tstart = A.tstart;
-  uint32_t* __restrict__ bstart = A.bstart;
-  uint32_t* __restrict__ fstart = A.fstart;
-  uint32_t* __restrict__ hstart = A.hstart;
-  const int64_t n = A.n;
-  const int64_t base = blk * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
-  uint64_t sp = 0, sb = 0, sf = 0, sh = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t idx = base + k;
-    v[k] = idx < n ? cnt[idx] : 0u;
-    uint32_t nb, f, h;
-    bucket_split(v[k], nb, f, h);
-    sp += v[k];
-    sb += nb;
-    sf += f;
-    sh += h;
-  }
-  uint64_t tp, tb, tf, th;
-  uint64_t rp = scan_start(sp, wsum, &tp);
-  uint64_t rb = 0, rf = 0, rh = 0;
-  if (bstart) {  // uniform
-    rb = scan_start(sb, wsum, &tb);
-    rf = scan_start(sf, wsum, &tf);
-    rh = scan_start(sh, wsum, &th);
-  }
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t idx = base + k;
-    uint32_t nb, f, h;
-    bucket_split(v[k], nb, f, h);
-    if (idx < n) {
-      tstart[idx] = (uint32_t)rp;
-      cnt[idx] = 0u;
-      if (bstart) {
-        bstart[idx] = (uint32_t)rb;
-        fstart[idx] = (uint32_t)rf;
-        hstart[idx] = (uint32_t)rh;
-      }
-    }
-    rp += v[k];
-    rb += nb;
-    rf += f;
-    rh += h;
-  }
-  if (threadIdx.x == 0) {
-    A.tile_tot[blk] = tp;
-    if (bstart) {
-      A.bucket_tot[blk] = tb;
-      A.full_tot[blk] = tf;
-      A.half_tot[blk] = th;
-    }
+// Inclusive wavefront scans with DPP (full-rate VALU, no LDS traffic): row
+// shifts by 1, 2, 4, 8 within each 16-lane row, then the last lane of row 0
+// and 2 into rows 1 and 3 (row_bcast:15) and of row 1 into rows 2 and 3
+// (row_bcast:31).  Lanes shifted in from outside a row add 0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xF, false);
+}
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t x) {
+  const uint32_t lo = dpp_u32<CTRL, ROW_MASK>((uint32_t)x);
+  const uint32_t hi = dpp_u32<CTRL, ROW_MASK>((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+template <typename U, int STEP>
+__device__ __forceinline__ U dpp_step(U x) {
+  if constexpr (sizeof(U) == 8) {
+    if constexpr (STEP == 0) return dpp_u64<0x111>(x);
+    else if constexpr (STEP == 1) return dpp_u64<0x112>(x);
+    else if constexpr (STEP == 2) return dpp_u64<0x114>(x);
+    else if constexpr (STEP == 3) return dpp_u64<0x118>(x);
+    else if constexpr (STEP == 4) return dpp_u64<0x142, 0xA>(x);
+    else return dpp_u64<0x143, 0xC>(x);
+  } else {
+    if constexpr (STEP == 0) return dpp_u32<0x111>(x);
+    else if constexpr (STEP == 1) return dpp_u32<0x112>(x);
+    else if constexpr (STEP == 2) return dpp_u32<0x114>(x);
+    else if constexpr (STEP == 3) return dpp_u32<0x118>(x);
+    else if constexpr (STEP == 4) return dpp_u32<0x142, 0xA>(x);
+    else return dpp_u32<0x143, 0xC>(x);
   }
 }
 
-// Block-total arrays of the scans (records: pairs, visible; tiles: pairs,
-// buckets, full and half buckets), scanned together by one block.
-constexpr int kMaxChannels = 6;
-struct ScanChannels {
-  uint64_t* a[kMaxChannels];
-  int64_t n[kMaxChannels];
-  int count;
-};
+// Inclusive scan over the first 16 lanes (STEPS = 4) or the whole
+// wavefront (STEPS = 6).
+template <int STEPS, typename U>
+__device__ __forceinline__ U scan_dpp(U x) {
+  x += dpp_step<U, 0>(x);
+  x += dpp_step<U, 1>(x);
+  x += dpp_step<U, 2>(x);
+  x += dpp_step<U, 3>(x);
+  if constexpr (STEPS > 4) {
+    x += dpp_step<U, 4>(x);
+    x += dpp_step<U, 5>(x);
+  }
+  return x;
+}
 
-// In-place exclusive scans of up to six u64 arrays at once by one block of
-// NT threads (each array has its own length); totals to tot[].
-template <int NT>
-__device__ void block_scan_channels(const ScanChannels& ch, uint64_t* tot) {
-  __shared__ uint64_t wsum[kMaxChannels][NT / kWave];
-  __shared__ uint64_t carry[kMaxChannels];
+// Block-wide exclusive scan of N64 64-bit and N32 32-bit per-thread sums
+// (replaced by the thread's start); the carries (uniform) are added and
+// advanced by the block totals.  The 64-bit channels count pairs (their
+// totals decide the overflow); the 32-bit ones are exact whenever those fit
+// the pair capacity.  w64 / w32 hold (NW + 1) entries per channel.  Every
+// thread of the block must call.
+template <int N64, int N32>
+__device__ __forceinline__ void block_exscan(uint64_t (&s64)[N64], uint32_t (&s32)[N32],
+                                             uint64_t (&c64)[N64], uint32_t (&c32)[N32],
+                                             uint64_t* w64, uint32_t* w32) {
+  constexpr int NW = kScanBlock / kWave;
+  static_assert(NW == 16, "the wave sums are scanned within one 16-lane row");
   const int lane = lane_id(), w = threadIdx.x / kWave;
-  if (threadIdx.x < kMaxChannels) carry[threadIdx.x] = 0;
-  int64_t nmax = 0;
-  for (int c = 0; c < ch.count; ++c) nmax = ch.n[c] > nmax ? ch.n[c] : nmax;
-  __syncthreads();
-  for (int64_t base = 0; base < nmax; base += NT) {
-    const int64_t idx = base + threadIdx.x;
-    uint64_t x[kMaxChannels], incl[kMaxChannels];
+  uint64_t i64[N64];
+  uint32_t i32[N32];
 #pragma unroll
-    for (int c = 0; c < kMaxChannels; ++c) {
-      x[c] = (c < ch.count && idx < ch.n[c]) ? ch.a[c][idx] : 0ull;
-      incl[c] = x[c];
-    }
+  for (int c = 0; c < N64; ++c) i64[c] = scan_dpp<6>(s64[c]);
 #pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
+  for (int c = 0; c < N32; ++c) i32[c] = scan_dpp<6>(s32[c]);
+  if (lane == kWave - 1) {
 #pragma unroll
-      for (int c = 0; c < kMaxChannels; ++c) {
-        const uint64_t y = __shfl_up(incl[c], o, kWave);
-        if (lane >= o) incl[c] += y;
-      }
-    }
-    if (lane == kWave - 1)
-      for (int c = 0; c < kMaxChannels; ++c) wsum[c][w] = incl[c];
-    __syncthreads();
+    for (int c = 0; c < N64; ++c) w64[c * (NW + 1) + w] = i64[c];
 #pragma unroll
-    for (int c = 0; c < kMaxChannels; ++c) {
-      uint64_t woff = carry[c];
-      for (int k = 0; k < w; ++k) woff += wsum[c][k];
-      if (c < ch.count && idx < ch.n[c]) ch.a[c][idx] = woff + incl[c] - x[c];
-      if (threadIdx.x == NT - 1) incl[c] = woff + incl[c];  // running total
-    }
-    __syncthreads();
-    if (threadIdx.x == NT - 1)
-      for (int c = 0; c < kMaxChannels; ++c) carry[c] = incl[c];
-    __syncthreads();
+    for (int c = 0; c < N32; ++c) w32[c * (NW + 1) + w] = i32[c];
   }
-  for (int c = 0; c < kMaxChannels; ++c) tot[c] = carry[c];
+  __syncthreads();
+  if (w == 0) {
+    // lanes 0..15 of wave 0 scan the wave sums: exclusive offsets (plus the
+    // carry) at [0, NW), the new carry at [NW]
+#pragma unroll
+    for (int c = 0; c < N64; ++c) {
+      const uint64_t x = lane < NW ? w64[c * (NW + 1) + lane] : 0ull;
+      const uint64_t j = scan_dpp<4>(x);
+      if (lane < NW) w64[c * (NW + 1) + lane] = c64[c] + j - x;
+      if (lane == NW - 1) w64[c * (NW + 1) + NW] = c64[c] + j;
+    }
+#pragma unroll
+    for (int c = 0; c < N32; ++c) {
+      const uint32_t x = lane < NW ? w32[c * (NW + 1) + lane] : 0u;
+      const uint32_t j = scan_dpp<4>(x);
+      if (lane < NW) w32[c * (NW + 1) + lane] = c32[c] + j - x;
+      if (lane == NW - 1) w32[c * (NW + 1) + NW] = c32[c] + j;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < N64; ++c) {
+    s64[c] = w64[c * (NW + 1) + w] + i64[c] - s64[c];
+    c64[c] = w64[c * (NW + 1) + NW];
+  }
+#pragma unroll
+  for (int c = 0; c < N32; ++c) {
+    s32[c] = w32[c * (NW + 1) + w] + i32[c] - s32[c];
+    c32[c] = w32[c * (NW + 1) + NW];
+  }
+  __syncthreads();  // the wave sums are rewritten by the next round
 }
 
-// From the scanned totals: pair count, capacity check, visible count and
-// the sizes of the bucket queues.  Both pair totals count the same pairs; a
-// mismatch is reported as an overflow so that nothing is scattered.
-__device__ void set_scan_flags(const ScanChannels& ch, const uint64_t* tot, int64_t cap,
-                               int32_t* fl) {
-  const uint64_t total = tot[0], visible = tot[1], total_t = tot[2];
-  const uint64_t n_full = ch.count > 4 ? tot[4] : 0, n_half = ch.count > 5 ? tot[5] : 0;
-  const bool over = total > (uint64_t)cap || total != total_t;
+// Four consecutive u32 from a[i], zeros past n (a is 16-byte aligned, i a
+// multiple of 4).
+__device__ __forceinline__ uint4 load4(const uint32_t* __restrict__ a, int64_t i, int64_t n) {
+  if (i + 4 <= n) return *reinterpret_cast<const uint4*>(a + i);
+  uint4 x = make_uint4(0u, 0u, 0u, 0u);
+  if (i < n) x.x = a[i];
+  if (i + 1 < n) x.y = a[i + 1];
+  if (i + 2 < n) x.z = a[i + 2];
+  return x;
+}
+
+__device__ __forceinline__ void store4(uint32_t* __restrict__ a, int64_t i, int64_t n, uint4 x) {
+  if (i + 4 <= n) {
+    *reinterpret_cast<uint4*>(a + i) = x;
+    return;
+  }
+  if (i < n) a[i] = x.x;
+  if (i + 1 < n) a[i + 1] = x.y;
+  if (i + 2 < n) a[i + 2] = x.z;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scans(ScanArgs A, int64_t cap,
+                                                      int32_t* __restrict__ fl) {
+  constexpr int NW = kScanBlock / kWave;
+  constexpr int NT = 4 * kScanVec, NC = 2 * kScanVec;  // tiles, chunks per thread and round
+  // channels: 64-bit tile pairs, chunk pairs; 32-bit buckets, half buckets,
+  // visible records (full buckets = buckets - half buckets)
+  __shared__ uint64_t w64[2 * (NW + 1)];
+  __shared__ uint32_t w32[3 * (NW + 1)];
+  uint64_t c64[2] = {0, 0};
+  uint32_t c32[3] = {0, 0, 0};
+  const int64_t T = A.n_tiles, C = A.n_chunks;
+  const int64_t rt = (T + kTileRound - 1) / kTileRound, rc = (C + kChunkRound - 1) / kChunkRound;
+  const int64_t rounds = rt > rc ? rt : rc;
+  const uint32_t* chunk_in = reinterpret_cast<const uint32_t*>(A.chunk_cnt);
+  uint32_t* chunk_out = reinterpret_cast<uint32_t*>(A.chunk_pre);
+  for (int64_t r = 0; r < rounds; ++r) {
+    const int64_t it = r * kTileRound + (int64_t)NT * threadIdx.x;
+    const int64_t ic = r * kChunkRound + (int64_t)NC * threadIdx.x;
+    uint32_t tc[NT], cp[NC], cv[NC];
+#pragma unroll
+    for (int k = 0; k < kScanVec; ++k) {
+      const uint4 x = load4(A.cnt, it + 4 * k, T);
+      tc[4 * k] = x.x; tc[4 * k + 1] = x.y; tc[4 * k + 2] = x.z; tc[4 * k + 3] = x.w;
+      const uint4 y = load4(chunk_in, 2 * (ic + 2 * k), 2 * C);
+      cp[2 * k] = y.x; cv[2 * k] = y.y; cp[2 * k + 1] = y.z; cv[2 * k + 1] = y.w;
+    }
+    uint32_t nb[NT], h[NT];
+    uint64_t s64[2] = {0, 0};
+    uint32_t s32[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      uint32_t f;
+      bucket_split(tc[k], nb[k], f, h[k]);
+      s64[0] += tc[k];
+      s32[0] += nb[k];
+      s32[1] += h[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      s64[1] += cp[k];
+      s32[2] += cv[k];
+    }
+    block_exscan<2, 3>(s64, s32, c64, c32, w64, w32);
+#pragma unroll
+    for (int k = 0; k < kScanVec; ++k) {
+      uint32_t ts[4], bs[4], hs[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        ts[e] = (uint32_t)s64[0];
+        bs[e] = s32[0];
+        hs[e] = s32[1];
+        s64[0] += tc[4 * k + e];
+        s32[0] += nb[4 * k + e];
+        s32[1] += h[4 * k + e];
+      }
+      store4(A.tstart, it + 4 * k, T, make_uint4(ts[0], ts[1], ts[2], ts[3]));
+      store4(A.cnt, it + 4 * k, T, make_uint4(0u, 0u, 0u, 0u));
+      if (A.boff) {
+        store4(A.boff, it + 4 * k, T, make_uint4(bs[0], bs[1], bs[2], bs[3]));
+        store4(A.fstart, it + 4 * k, T,
+               make_uint4(bs[0] - hs[0], bs[1] - hs[1], bs[2] - hs[2], bs[3] - hs[3]));
+        store4(A.hstart, it + 4 * k, T, make_uint4(hs[0], hs[1], hs[2], hs[3]));
+      }
+      const uint32_t p0 = (uint32_t)s64[1], v0 = s32[2];
+      const uint32_t p1 = p0 + cp[2 * k], v1 = v0 + cv[2 * k];
+      store4(chunk_out, 2 * (ic + 2 * k), 2 * C, make_uint4(p0, v0, p1, v1));
+      s64[1] = p1 + cp[2 * k + 1];
+      s32[2] = v1 + cv[2 * k + 1];
+    }
+  }
+  if (threadIdx.x != 0) return;
+  // Both pair totals count the same pairs; a mismatch is reported as an
+  // overflow so that nothing is scattered.
+  const uint64_t tile_pairs = c64[0], chunk_pairs = c64[1];
+  const bool over = tile_pairs > (uint64_t)cap || tile_pairs != chunk_pairs;
   fl[F_OVERFLOW] = over ? 1 : 0;
-  fl[F_PAIRS] = over ? 0 : (int32_t)total;
-  fl[F_PAIRS_WANTED] = total > 0x7FFFFFFFull ? 0x7FFFFFFF : (int32_t)total;
-  fl[F_VISIBLE] = (int32_t)visible;
+  fl[F_PAIRS] = over ? 0 : (int32_t)tile_pairs;
+  fl[F_PAIRS_WANTED] = tile_pairs > 0x7FFFFFFFull ? 0x7FFFFFFF : (int32_t)tile_pairs;
+  fl[F_VISIBLE] = (int32_t)c32[2];
   // long lists are queued by the tile sort that follows; the bucket queues
   // are filled there at the positions scanned here
   fl[F_LONG_TILES] = 0;
-  fl[F_BQ_FULL] = over ? 0 : (int32_t)n_full;
-  fl[F_BQ_HALF] = over ? 0 : (int32_t)n_half;
-}
-
-// Record blocks first, then tile blocks: one launch for both scans.
-// The last block to finish (counted in a flag; each block publishes its
-// totals before it counts itself) scans the block totals of all channels.
-__global__ void __launch_bounds__(kScanThreads) k_scans(
-    const uint32_t* __restrict__ tt, uint32_t* __restrict__ poff, uint64_t* __restrict__ rec_tot,
-    uint32_t* __restrict__ vpre, uint64_t* __restrict__ vis_tot, int64_t n_rec,
-    int64_t rec_blocks, TileScanArgs tiles, ScanChannels ch, int64_t cap,
-    int32_t* __restrict__ fl) {
-  __shared__ uint64_t wsum[kScanThreads / kWave];
-  __shared__ int is_last;
-  if ((int64_t)blockIdx.x < rec_blocks)
-    scan_records(blockIdx.x, tt, poff, rec_tot, vpre, vis_tot, n_rec, wsum);
-  else
-    scan_tiles((int64_t)blockIdx.x - rec_blocks, tiles, wsum);
-  if (threadIdx.x == 0) {
-    __threadfence();  // this block's totals before its count
-    is_last = atomicAdd(&fl[F_SCAN_DONE], 1) == (int)gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!is_last) return;  // uniform over the block
-  __threadfence();
-  uint64_t tot[kMaxChannels];
-  block_scan_channels<kScanThreads>(ch, tot);
-  if (threadIdx.x == 0) {
-    set_scan_flags(ch, tot, cap, fl);
-    fl[F_SCAN_DONE] = 0;  // ready for the next binning
-  }
+  const bool splat = A.boff != nullptr;
+  fl[F_BQ_FULL] = (over || !splat) ? 0 : (int32_t)(c32[0] - c32[1]);
+  fl[F_BQ_HALF] = (over || !splat) ? 0 : (int32_t)c32[1];
+  if (splat) A.boff[T] = c32[0];
 }
 
 
 // ---------------------------------------------------------------- scatter
-// Generation offsets become absolute (poff), every pair gets the next free
-// slot of its tile's list with key (depth bits << 32 | generation index),
-// and pair -> record is recorded.  Each wavefront takes 64 consecutive
-// records and spreads their pairs evenly over its lanes (exclusive scan of
-// the pair counts, binary search of a pair's record in LDS), so a large
-// Gaussian does not serialise its tiles' slot claims on one lane.
+// One wavefront per chunk (64 Gaussians of one view, the projection's
+// wavefront): the generation offsets of its records become absolute (poff),
+// its visible records are listed in index order, and every pair gets the
+// next free slot of its tile's list with key (depth bits << 32 | generation
+// index); pair -> record is recorded.  The chunk's pairs are spread evenly
+// over the lanes (exclusive scan of the pair counts, binary search of a
+// pair's record in LDS), so a large Gaussian does not serialise its tiles'
+// slot claims on one lane.
 __global__ void __launch_bounds__(256) k_scatter(
     const uint32_t* __restrict__ tt, uint32_t* __restrict__ poff,
-    const uint64_t* __restrict__ rec_pre, const ushort4* __restrict__ rect,
-    const Rec* __restrict__ rec, int64_t n, int64_t n_rec, ViewTable vt,
+    const uint2* __restrict__ chunk_pre, int64_t chunks_per_view, int64_t n_chunks,
+    const ushort4* __restrict__ rect, const Rec* __restrict__ rec, int64_t n, ViewTable vt,
     const int32_t* __restrict__ fl, const uint32_t* __restrict__ tstart,
-    const uint64_t* __restrict__ tile_pre, uint32_t* __restrict__ cursor,
-    uint64_t* __restrict__ skey, uint32_t* __restrict__ pair_rec,
-    const uint32_t* __restrict__ vpre, const uint64_t* __restrict__ vis_pre,
+    uint32_t* __restrict__ cursor, uint64_t* __restrict__ skey, uint32_t* __restrict__ pair_rec,
     uint32_t* __restrict__ vis_list) {
   constexpr int NW = 256 / kWave;
-  __shared__ uint32_t s_pre[NW][kWave + 1];
+  __shared__ uint32_t s_pre[NW][kWave];
   __shared__ uint32_t s_p0[NW][kWave], s_dbits[NW][kWave], s_x0y0[NW][kWave];
-  __shared__ uint32_t s_wv[NW][kWave];
-  const int w = threadIdx.x / kWave, lane = lane_id();
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  __shared__ uint32_t s_tile0[NW][kWave];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = lane_id();
+  const int64_t gw = (int64_t)blockIdx.x * NW + w;  // chunk
+  if (gw >= n_chunks) return;                       // whole wavefront; no block barrier below
+  const int v = (int)(gw / chunks_per_view);
+  const int64_t gi = (gw - (int64_t)v * chunks_per_view) * kWave + lane;  // Gaussian
+  const int64_t ri = (int64_t)v * n + gi;                                 // record
   const uint64_t P = (uint64_t)fl[F_PAIRS];
   const bool over = fl[F_OVERFLOW] != 0;
-  uint32_t c = (i < n_rec && !over) ? tt[i] : 0u;
-  uint32_t p0 = 0, dbits = 0, x0y0 = 0, wv = 0;
-  if (c > 0) {
-    const uint64_t base64 = (uint64_t)poff[i] + rec_pre[i / kScanTile];
-    if (base64 + c > P) {
-      c = 0;  // cannot happen without overflow
-    } else {
-      p0 = (uint32_t)base64;
-      poff[i] = p0;
-      vis_list[vpre[i] + vis_pre[i / kScanTile]] = (uint32_t)i;  // records in index order
-      const ushort4 r = rect[i];
-      dbits = __float_as_uint(rec[i].z);
-      x0y0 = (uint32_t)r.x | ((uint32_t)r.y << 16);
-      wv = (uint32_t)(r.z - r.x) | ((uint32_t)(i / n) << 16);
-    }
-  }
+  uint32_t c = (gi < n && !over) ? tt[ri] : 0u;
   uint32_t incl = c;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
     const uint32_t y = __shfl_up(incl, o, kWave);
     if (lane >= o) incl += y;
   }
+  const uint32_t total = __shfl(incl, kWave - 1, kWave);
+  const uint2 cp = chunk_pre[gw];
+  const uint64_t base64 = (uint64_t)cp.x + (incl - c);
+  if ((uint64_t)cp.x + total > P) return;  // cannot happen without overflow (uniform)
+  const uint64_t vmask = ballot64(c > 0);
+  uint32_t p0 = 0, dbits = 0, x0y0 = 0, tile0 = 0;
+  if (c > 0) {
+    p0 = (uint32_t)base64;
+    poff[ri] = p0;
+    vis_list[cp.y + (uint32_t)__popcll(vmask & lanemask_lt())] = (uint32_t)ri;
+    const ushort4 r = rect[ri];
+    dbits = __float_as_uint(rec[ri].z);
+    x0y0 = (uint32_t)r.x | ((uint32_t)r.y << 16);
+    tile0 = (uint32_t)(r.z - r.x);  // box width in tiles
+  }
+  if (total == 0) return;
   s_pre[w][lane] = incl - c;
-  if (lane == kWave - 1) s_pre[w][kWave] = incl;
   s_p0[w][lane] = p0;
   s_dbits[w][lane] = dbits;
   s_x0y0[w][lane] = x0y0;
-  s_wv[w][lane] = wv;
-  __syncthreads();
-  const uint32_t total = s_pre[w][kWave];
-  const int64_t rec0 = (int64_t)blockIdx.x * 256 + (int64_t)w * kWave;
+  s_tile0[w][lane] = tile0;
+  wave_lds_sync();
+  const ViewInfo vi = vt.v[v];
+  const uint32_t rec0 = (uint32_t)(ri - lane);
   for (uint32_t q = (uint32_t)lane; q < total; q += kWave) {
-    // owner: the last record whose prefix is <= q (it has pairs)
+    // owner: the last lane whose prefix is <= q (it has pairs)
     int lo = 0, hi = kWave - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (s_pre[w][mid] <= q) lo = mid; else hi = mid - 1;
     }
     const uint32_t k = q - s_pre[w][lo];
-    const uint32_t wvj = s_wv[w][lo], xy = s_x0y0[w][lo];
-    const uint32_t bw = wvj & 0xFFFFu;
-    const int v = (int)(wvj >> 16);
+    const uint32_t bw = s_tile0[w][lo], xy = s_x0y0[w][lo];
     const int x = (int)(xy & 0xFFFFu) + (int)(k % bw);
     const int y = (int)(xy >> 16) + (int)(k / bw);
-    const int t = vt.v[v].tile_off + y * vt.v[v].tiles_x + x;
+    const int t = vi.tile_off + y * vi.tiles_x + x;
     const uint32_t p = s_p0[w][lo] + k;
-    const uint64_t slot = (uint64_t)tstart[t] + tile_pre[t / kScanTile] + atomicAdd(&cursor[t], 1u);
+    const uint64_t slot = (uint64_t)tstart[t] + atomicAdd(&cursor[t], 1u);
     if (slot < P) skey[slot] = ((uint64_t)s_dbits[w][lo] << 32) | p;
-    pair_rec[p] = (uint32_t)(rec0 + lo);
+    pair_rec[p] = rec0 + (uint32_t)lo;
   }
 }
 
@@ -432,41 +446,32 @@ __device__ void bitonic_sort(uint64_t* k, uint32_t n, uint32_t tid, uint32_t nth
 }
 
 __global__ void __launch_bounds__(kWave) k_tile_sort(
-    const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ tstart,
-    const uint64_t* __restrict__ tile_pre, int T, int32_t* __restrict__ fl,
-    const uint64_t* __restrict__ skey, TileSortOut out, uint32_t* __restrict__ ranges,
-    uint32_t* __restrict__ long_list, const uint32_t* __restrict__ bstart,
-    const uint64_t* __restrict__ bucket_pre, uint32_t* __restrict__ boff,
-    const uint32_t* __restrict__ fstart, const uint64_t* __restrict__ full_pre,
-    const uint32_t* __restrict__ hstart, const uint64_t* __restrict__ half_pre,
+    const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ tstart, int T,
+    int32_t* __restrict__ fl, const uint64_t* __restrict__ skey, TileSortOut out,
+    uint32_t* __restrict__ ranges, uint32_t* __restrict__ long_list,
+    const uint32_t* __restrict__ fstart, const uint32_t* __restrict__ hstart,
     uint2* __restrict__ bq, int64_t bq_stride) {
   __shared__ uint64_t sk[kTileSortSmall];
   const int t = blockIdx.x;
   const int lane = threadIdx.x;
   const uint64_t P = (uint64_t)fl[F_PAIRS];
   const uint32_t n = fl[F_OVERFLOW] ? 0u : cnt[t];
-  const uint64_t start64 = (uint64_t)tstart[t] + tile_pre[t / kScanTile];
+  const uint64_t start64 = tstart[t];
   const bool ok = n > 0 && start64 + n <= P;
   if (lane == 0) {
     ranges[2 * (int64_t)t] = ok ? (uint32_t)start64 : 0u;
     ranges[2 * (int64_t)t + 1] = ok ? (uint32_t)(start64 + n) : 0u;
-    if (boff) {
-      // buckets of 64 positions; a tile without a valid list has none
-      boff[t] = bstart[t] + (uint32_t)bucket_pre[t / kScanTile];
-      if (t == T - 1) boff[T] = boff[t] + (ok ? (n + kBucket - 1) / kBucket : 0u);
-    }
     if (ok && n > kTileSortSmall) long_list[atomicAdd(&fl[F_LONG_TILES], 1)] = (uint32_t)t;
   }
-  if (boff && ok) {
+  if (bq && ok) {
     // splat-wise work queues at the scanned positions: the tile's buckets
     // 0 .. full-1 have more than 32 pairs; a last bucket with at most 32
     // goes to the second queue
     uint32_t nb, full, half;
     bucket_split(n, nb, full, half);
-    const uint32_t f0 = fstart[t] + (uint32_t)full_pre[t / kScanTile];
+    const uint32_t f0 = fstart[t];
     for (uint32_t k = lane; k < full; k += kWave) bq[f0 + k] = make_uint2((uint32_t)t, k);
-    if (half && lane == 0)
-      bq[bq_stride + hstart[t] + (uint32_t)half_pre[t / kScanTile]] = make_uint2((uint32_t)t, nb - 1);
+    if (half && lane == 0) bq[bq_stride + hstart[t]] = make_uint2((uint32_t)t, nb - 1);
   }
   if (!ok || n > kTileSortSmall) return;
   const uint32_t start = (uint32_t)start64;
@@ -491,14 +496,14 @@ __global__ void __launch_bounds__(kWave) k_tile_sort(
 
 __global__ void __launch_bounds__(kLongThreads) k_tile_sort_long(
     const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ tstart,
-    const uint64_t* __restrict__ tile_pre, const int32_t* __restrict__ fl,
-    const uint32_t* __restrict__ long_list, uint64_t* __restrict__ skey, TileSortOut out) {
+    const int32_t* __restrict__ fl, const uint32_t* __restrict__ long_list,
+    uint64_t* __restrict__ skey, TileSortOut out) {
   __shared__ uint64_t sk[kTileSortLong];
   const int n_long = fl[F_LONG_TILES];
   for (int li = blockIdx.x; li < n_long; li += gridDim.x) {
     const int t = (int)long_list[li];
     const uint32_t n = cnt[t];
-    const uint32_t start = tstart[t] + (uint32_t)tile_pre[t / kScanTile];
+    const uint32_t start = tstart[t];
     const uint64_t tkey = (uint64_t)(uint32_t)t << 32;
     if (n <= kTileSortLong) {
       for (uint32_t k = threadIdx.x; k < n; k += kLongThreads) sk[k] = skey[start + k];
@@ -760,37 +765,25 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
   int32_t* fl = ws_at<int32_t>(ws, P.off_flags);
   uint32_t* tt = ws_at<uint32_t>(ws, P.off_tt);
   uint32_t* poff = ws_at<uint32_t>(ws, P.off_poff);
-  uint64_t* rec_tot = ws_at<uint64_t>(ws, P.off_scan);
-  uint64_t* vis_tot = ws_at<uint64_t>(ws, P.off_vis_scan);
   uint32_t* tcnt = ws_at<uint32_t>(ws, P.off_tile_cnt);
   uint32_t* tstart = ws_at<uint32_t>(ws, P.off_tile_start);
-  uint64_t* tile_tot = ws_at<uint64_t>(ws, P.off_tile_scan);
   const bool splat = (P.cfg.flags & GS_SPLAT_BWD) != 0;
-  uint32_t* bstart = splat ? ws_at<uint32_t>(ws, P.off_bucket_start) : nullptr;
-  uint64_t* bucket_tot = splat ? ws_at<uint64_t>(ws, P.off_bucket_scan) : nullptr;
-  uint32_t* boff = splat ? ws_at<uint32_t>(ws, P.off_boff) : nullptr;
   const int T = P.vt.total_tiles;
-  const int64_t sb = P.scan_blocks, tb = P.tile_scan_blocks;
   uint32_t* fstart = splat ? ws_at<uint32_t>(ws, P.off_full_start) : nullptr;
-  uint64_t* full_tot = splat ? ws_at<uint64_t>(ws, P.off_full_scan) : nullptr;
   uint32_t* hstart = splat ? ws_at<uint32_t>(ws, P.off_half_start) : nullptr;
-  uint64_t* half_tot = splat ? ws_at<uint64_t>(ws, P.off_half_scan) : nullptr;
-  TileScanArgs ta{tcnt, tstart, tile_tot, (int64_t)T, bstart, bucket_tot, fstart, full_tot,
-                  hstart, half_tot};
-  ScanChannels ch{{rec_tot, vis_tot, tile_tot, bucket_tot, full_tot, half_tot},
-                  {sb, sb, tb, tb, tb, tb}, splat ? 6 : 3};
-  // at least one block, so that the flags are always set
-  hipLaunchKernelGGL(k_scans, dim3((unsigned)std::max<int64_t>(sb + tb, 1)), dim3(kScanThreads), 0,
-                     s, tt, poff, rec_tot, ws_at<uint32_t>(ws, P.off_vpre), vis_tot, P.n_rec, sb,
-                     ta, ch, P.pair_cap, fl);
+  const uint2* chunk_cnt = ws_at<uint2>(ws, P.off_chunk_cnt);
+  uint2* chunk_pre = ws_at<uint2>(ws, P.off_chunk_pre);
+  ScanArgs sa{chunk_cnt, chunk_pre, P.n_chunks, tcnt, tstart, (int64_t)T,
+              splat ? ws_at<uint32_t>(ws, P.off_boff) : nullptr, fstart, hstart};
+  // always launched, so that the flags are always set
+  hipLaunchKernelGGL(k_scans, dim3(1), dim3(kScanBlock), 0, s, sa, P.pair_cap, fl);
   uint64_t* skey = ws_at<uint64_t>(ws, P.off_scatter);
   uint32_t* pair_rec = ws_at<uint32_t>(ws, P.off_pair_rec);
-  if (P.n_rec > 0) {
-    const int64_t blocks = (P.n_rec + 255) / 256;
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(256), 0, s, tt, poff, rec_tot,
-                       ws_at<ushort4>(ws, P.off_rect), ws_at<Rec>(ws, P.off_rec), P.n, P.n_rec,
-                       P.vt, fl, tstart, tile_tot, tcnt, skey, pair_rec,
-                       ws_at<uint32_t>(ws, P.off_vpre), vis_tot,
+  if (P.n_chunks > 0) {
+    const int64_t blocks = (P.n_chunks + 3) / 4;
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(256), 0, s, tt, poff, chunk_pre,
+                       P.chunks_per_view, P.n_chunks, ws_at<ushort4>(ws, P.off_rect),
+                       ws_at<Rec>(ws, P.off_rec), P.n, P.vt, fl, tstart, tcnt, skey, pair_rec,
                        ws_at<uint32_t>(ws, P.off_vis_list));
   }
   if (T > 0) {
@@ -798,13 +791,12 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
                     ws_at<uint32_t>(ws, P.off_sorted_rec), pair_rec, ws_at<Rec>(ws, P.off_rec),
                     ws_at<Rec>(ws, P.off_srec)};
     uint32_t* long_list = ws_at<uint32_t>(ws, P.off_long);
-    hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)T), dim3(kWave), 0, s, tcnt, tstart, tile_tot,
-                       T, fl, skey, out, ws_at<uint32_t>(ws, P.off_ranges), long_list, bstart,
-                       bucket_tot, boff, fstart, full_tot, hstart, half_tot,
+    hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)T), dim3(kWave), 0, s, tcnt, tstart, T, fl, skey,
+                       out, ws_at<uint32_t>(ws, P.off_ranges), long_list, fstart, hstart,
                        splat ? ws_at<uint2>(ws, P.off_bq) : nullptr, P.ckpt_slots);
     const int long_grid = (int)std::min<int64_t>(T, 256);
     hipLaunchKernelGGL(k_tile_sort_long, dim3((unsigned)long_grid), dim3(kLongThreads), 0, s,
-                       tcnt, tstart, tile_tot, fl, long_list, skey, out);
+                       tcnt, tstart, fl, long_list, skey, out);
   }
   return hipGetLastError();
 }

@@ -28,7 +28,6 @@ enum Flag : int {
   F_LONG_TILES = 7,  // tiles whose lists go to the long-list sort
   F_BQ_FULL = 8,     // splat-wise buckets with more than 32 pairs
   F_BQ_HALF = 9,     // splat-wise buckets with at most 32 pairs
-  F_SCAN_DONE = 10,  // blocks of the binning scans that have finished
   F_COUNT = 16
 };
 
@@ -76,21 +75,22 @@ struct Plan {
   int64_t pair_cap;
   gs_raster_cfg cfg;
   int32_t tile_bits, pad0;
-  int64_t scan_blocks;       // blocks of the record scan
-  int64_t tile_scan_blocks;  // blocks of the per-tile count scan
+  int64_t chunks_per_view;   // chunks of 64 Gaussians per view (one wavefront each)
+  int64_t n_chunks;          // n_views * chunks_per_view
   int64_t proj_blocks;       // blocks of the projection backward
   ViewTable vt;
   // workspace layout (byte offsets from the 256-aligned base)
-  size_t off_flags, off_rec, off_rect, off_tt, off_poff, off_scan, off_vis_scan;
-  size_t off_vpre, off_vis_list;  // visible records: local prefix, list in index order
-  size_t off_tile_cnt, off_tile_start, off_tile_scan, off_long;
+  size_t off_flags, off_rec, off_rect, off_tt, off_poff;
+  size_t off_chunk_cnt, off_chunk_pre;  // per chunk: (pairs, visible) counts and offsets
+  size_t off_vis_list;                  // visible records in index order
+  size_t off_tile_cnt, off_tile_start, off_long;
   size_t off_keys, off_scatter, off_vals, off_pair_rec, off_sorted_rec, off_srec;
   size_t off_hist, off_digit_tot, off_ranges, off_tile_last, off_tile_loss;
   size_t off_grad_pair, off_pose_part, off_order, off_order_tmp;
   size_t off_ssim_maps, off_ssim_part;
-  // splat-wise backward: bucket offsets (local, block sums, absolute), pixel states
-  size_t off_bucket_start, off_bucket_scan, off_boff, off_bq, off_ckpt;
-  size_t off_full_start, off_full_scan, off_half_start, off_half_scan;
+  // splat-wise backward: bucket offsets, bucket queues and their per-tile
+  // positions, pixel states
+  size_t off_boff, off_bq, off_ckpt, off_full_start, off_half_start;
   int64_t ckpt_slots;
   size_t ws_size;
 };
@@ -111,11 +111,6 @@ constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
-// Record scan geometry.
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kScanThreads * kScanItems;
-
 constexpr int kProjThreads = 128;
 
 // Splat-wise backward: splats per bucket (one per lane) and the floats of a
@@ -135,6 +130,14 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 }
 
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+// Orders a wavefront's LDS writes before its own later LDS reads (the lanes
+// of one wavefront, no block barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Wave64 sum with the result valid in every lane: butterfly over xor
 // distances 1..32.  Lanes that are inactive must hold 0.

@@ -51,13 +51,6 @@ __device__ __forceinline__ void sh_basis(double x, double y, double z, double* Y
 
 __device__ __forceinline__ bool finite_f(float v) { return __builtin_isfinite(v); }
 
-// Orders this wavefront's LDS writes before its later reads (other
-// wavefronts of the block are not involved).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <int DEG>
 __global__ void __launch_bounds__(256) k_preprocess(
@@ -65,7 +58,8 @@ __global__ void __launch_bounds__(256) k_preprocess(
     const float* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, int64_t n, const float* __restrict__ cams, ViewTable vt,
     uint32_t flags, Rec* __restrict__ rec, ushort4* __restrict__ rect,
-    uint32_t* __restrict__ tt, uint32_t* __restrict__ tile_cnt, int32_t* __restrict__ fl) {
+    uint32_t* __restrict__ tt, uint32_t* __restrict__ tile_cnt, uint2* __restrict__ chunk_cnt,
+    int64_t chunks_per_view, int32_t* __restrict__ fl) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   // lanes past the end stay active (as an invalid Gaussian) so that the
@@ -225,7 +219,10 @@ __global__ void __launch_bounds__(256) k_preprocess(
     }
     if (in_range) tt[ri] = count;
     // pairs per tile, for the binning: the wavefront's pairs are spread over
-    // its lanes (a large Gaussian does not serialise its tiles on one lane)
+    // its lanes (a large Gaussian does not serialise its tiles on one lane).
+    // The wavefront's 64 Gaussians are one chunk of the binning's record
+    // scan: its pair count (at most 64 x 2^22 tiles of a 16384^2 view in
+    // 8x8 tiles, so u32) and its number of visible records.
     {
       const int lane = lane_id(), w = threadIdx.x / kWave;
       uint32_t incl = count;
@@ -235,6 +232,10 @@ __global__ void __launch_bounds__(256) k_preprocess(
         if (lane >= o) incl += y;
       }
       const uint32_t total = __shfl(incl, kWave - 1, kWave);
+      const uint32_t n_vis = (uint32_t)__popcll(ballot64(count > 0));
+      const int64_t chunk = (int64_t)blockIdx.x * (256 / kWave) + w;
+      if (lane == 0 && chunk < chunks_per_view)
+        chunk_cnt[(int64_t)v * chunks_per_view + chunk] = make_uint2(total, n_vis);
       if (total > 0) {  // uniform over the wavefront
         s_pre[w][lane] = incl - count;
         s_xy[w][lane] = box_xy;
@@ -271,12 +272,13 @@ hipError_t launch_preprocess(const Plan& P, const gs_gaussians& g, const float* 
   ushort4* rect = ws_at<ushort4>(ws, P.off_rect);
   uint32_t* tt = ws_at<uint32_t>(ws, P.off_tt);
   uint32_t* tile_cnt = ws_at<uint32_t>(ws, P.off_tile_cnt);
+  uint2* chunk_cnt = ws_at<uint2>(ws, P.off_chunk_cnt);
   int32_t* fl = ws_at<int32_t>(ws, P.off_flags);
   const uint32_t flags = P.cfg.flags;
 #define GS_PRE(D)                                                                          \
   hipLaunchKernelGGL(k_preprocess<D>, dim3((unsigned)blocks), dim3(threads), 0, s, g.means, \
                      g.log_scales, g.quats, g.opacity_logits, g.sh, P.n, cams, P.vt, flags,  \
-                     rec, rect, tt, tile_cnt, fl)
+                     rec, rect, tt, tile_cnt, chunk_cnt, P.chunks_per_view, fl)
   switch (P.deg) {
     case 0: GS_PRE(0); break;
     case 1: GS_PRE(1); break;
