@@ -36,7 +36,15 @@ struct AdamArgs {
   float eps;
   float reg_scale;        // lambda_o / reg_count
   const int32_t* step_dev;
+  int32_t step_taken;       // the iteration advanced *step_dev already: t = *step_dev
   const int32_t* overflow;  // with vis: every gradient is zero after a pair overflow
+  // optional: block 0 also reduces the forward's per-tile L1 partials of a
+  // one-view iteration into *loss (the loss needs nothing after the forward)
+  const float2* tile_loss;
+  int32_t loss_tiles, loss_has_depth;
+  double loss_pixels;
+  float lambda_depth;
+  float* loss;
 };
 
 namespace {
@@ -58,7 +66,10 @@ __global__ void __launch_bounds__(kAdamThreads) k_adam(AdamArgs a) {
   int gi = 0;
   while (gi + 1 < a.n_groups && (int64_t)blockIdx.x >= a.grp[gi + 1].block0) ++gi;
   const AdamGroupArg G = a.grp[gi];
-  const int step = a.step_dev ? (*a.step_dev + 1) : a.step;
+  if (a.loss && blockIdx.x == 0)
+    loss_reduce_view<kAdamThreads>(a.tile_loss, a.loss_tiles, a.loss_pixels, a.lambda_depth,
+                                   a.loss_has_depth, a.loss);
+  const int step = a.step_dev ? (*a.step_dev + (a.step_taken ? 0 : 1)) : a.step;
   const double bc1 = 1.0 - pow(a.beta1d, (double)step);
   const double bc2 = 1.0 - pow(a.beta2d, (double)step);
   const float step_size = (float)((double)G.lr / bc1);
@@ -134,10 +145,12 @@ int64_t adam_blocks(int64_t n) {
 }
 
 // vis / per / overflow: optional per-group gradient masks (see AdamGroupArg).
+// fold (optional): the iteration advanced step_dev already, and/or the
+// forward's loss reduction rides on block 0.
 hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, double beta1,
                        double beta2, double eps, double lambda_o, int64_t reg_count,
                        int32_t* step_dev, hipStream_t s, const uint32_t* const* vis,
-                       const int32_t* per, const int32_t* overflow) {
+                       const int32_t* per, const int32_t* overflow, const AdamFold* fold) {
   for (int base = 0; base < n_groups; base += kAdamMaxGroups) {
     AdamArgs a{};
     const int ng = n_groups - base < kAdamMaxGroups ? n_groups - base : kAdamMaxGroups;
@@ -161,12 +174,21 @@ hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, dou
     if (a.reg_scale == 0.0f)
       for (int k = 0; k < ng; ++k) a.grp[k].reg = 0;
     a.step_dev = step_dev;
+    a.step_taken = (fold && fold->step_taken) ? 1 : 0;
     a.overflow = overflow;
+    if (fold && fold->loss && base == 0) {
+      a.tile_loss = fold->tile_loss;
+      a.loss_tiles = fold->loss_tiles;
+      a.loss_has_depth = fold->loss_has_depth;
+      a.loss_pixels = fold->loss_pixels;
+      a.lambda_depth = fold->lambda_depth;
+      a.loss = fold->loss;
+    }
     if (blocks > 0) hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(kAdamThreads), 0, s, a);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (step_dev) {
+  if (step_dev && !(fold && fold->step_taken)) {
     hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(1), 0, s, step_dev);
     return hipGetLastError();
   }

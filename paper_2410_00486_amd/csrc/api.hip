@@ -19,7 +19,7 @@ hipError_t launch_radix_sort(uint64_t* keys0, uint64_t* keys1, uint32_t* vals0, 
                              const int32_t* cnt, uint32_t* hist, uint32_t* digit_tot,
                              int64_t nb_cap, int key_bits, bool iota, int* which, hipStream_t s);
 hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t s);
-hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s);
+hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s, int32_t* step = nullptr);
 uint32_t* sorted_vals(const Plan& P, void* ws);
 hipError_t launch_render_fwd(const Plan& P, void* ws, const float* cams, float* color,
                              float* depth, float* T_final, uint32_t* last,
@@ -38,7 +38,8 @@ hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float*
 hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, double beta1,
                        double beta2, double eps, double lambda_o, int64_t reg_count,
                        int32_t* step_dev, hipStream_t s, const uint32_t* const* vis = nullptr,
-                       const int32_t* per = nullptr, const int32_t* overflow = nullptr);
+                       const int32_t* per = nullptr, const int32_t* overflow = nullptr,
+                       const AdamFold* fold = nullptr);
 hipError_t launch_tile_order(const Plan& P, void* ws, hipStream_t s);
 int render_blocks_per_cu(const Plan& P, bool bwd);
 int splat_blocks_per_cu(const Plan& P);
@@ -286,20 +287,27 @@ int32_t* gs_flags_ptr(const gs_plan* plan, void* ws) {
   return ws_at<int32_t>(ws, plan_of(plan)->off_flags);
 }
 
-gs_status gs_preprocess(const gs_plan* plan, const gs_gaussians* g, const float* cams_dev,
-                        void* ws, void* stream) {
+// Preprocess with an optional device step counter to advance in the same
+// launch as the counter clear (used by the whole-iteration enqueue).
+static gs_status preprocess_enqueue(const gs_plan* plan, const gs_gaussians* g,
+                                    const float* cams_dev, void* ws, hipStream_t s,
+                                    int32_t* step_advance) {
   gs_status st;
   if ((st = check_plan(plan)) != GS_OK) return st;
   const Plan& P = *plan_of(plan);
   if ((st = check_ws(P, ws)) != GS_OK) return st;
   if ((st = check_gaussians(P, g)) != GS_OK) return st;
   if (!cams_dev) return fail(GS_ERR_INVALID_ARG, "cams_dev is null");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  // flags 0..3 and the per-tile pair counts are per-iteration: clear them
-  // with a kernel (graph-safe)
-  hipError_t e = launch_clear_counters(P, ws, s);
+  // the per-iteration flags and the per-tile pair counts are cleared by a
+  // kernel (graph-safe)
+  hipError_t e = launch_clear_counters(P, ws, s, step_advance);
   if (e == hipSuccess) e = launch_preprocess(P, *g, cams_dev, ws, s);
   return hip_check(e, "gs_preprocess");
+}
+
+gs_status gs_preprocess(const gs_plan* plan, const gs_gaussians* g, const float* cams_dev,
+                        void* ws, void* stream) {
+  return preprocess_enqueue(plan, g, cams_dev, ws, static_cast<hipStream_t>(stream), nullptr);
 }
 
 gs_status gs_bin_sort(const gs_plan* plan, void* ws, void* stream) {
@@ -529,22 +537,106 @@ gs_status gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_b
 
 gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
   if (!it) return fail(GS_ERR_INVALID_ARG, "iteration is null");
+  if (!it->plan || check_plan(it->plan) != GS_OK) return fail(GS_ERR_INVALID_ARG, "bad plan");
+  const Plan& P = *plan_of(it->plan);
   const bool ssim = it->lambda_ssim > 0.0;
   if (ssim) {
-    if (!it->plan || check_plan(it->plan) != GS_OK) return fail(GS_ERR_INVALID_ARG, "bad plan");
-    if (plan_of(it->plan)->cfg.flags & GS_FUSED_L1)
+    if (!(it->lambda_ssim <= 1.0)) return fail(GS_ERR_INVALID_ARG, "lambda_ssim must be in [0, 1]");
+    if (P.cfg.flags & GS_FUSED_L1)
       return fail(GS_ERR_INVALID_ARG, "lambda_ssim > 0 takes explicit loss gradients: clear GS_FUSED_L1");
     if (!it->target_rgb || !it->loss_grad_color || !it->loss_grad_depth)
       return fail(GS_ERR_INVALID_ARG, "lambda_ssim > 0 needs target_rgb and loss gradient buffers");
   }
-  gs_status st = gs_preprocess(it->plan, &it->gaussians, it->cams_dev, it->ws, stream);
+  // One view with Adam: the projection backward writes the gradients of the
+  // Gaussians with pairs only, and Adam takes the others as zero (no zero
+  // fill, no read).  The gradient buffers are left unspecified for those.
+  const bool sparse = it->n_adam_groups > 0 && it->n_adam_groups <= 16 && P.vt.n_views == 1 &&
+                      !(P.cfg.flags & GS_ACCUMULATE_GRADS) && P.n > 0;
+  if (!sparse) {
+    gs_status st = gs_preprocess(it->plan, &it->gaussians, it->cams_dev, it->ws, stream);
+    if (st != GS_OK) return st;
+    st = gs_bin_sort(it->plan, it->ws, stream);
+    if (st != GS_OK) return st;
+    st = gs_render_fwd(it->plan, it->ws, it->cams_dev, it->color, it->depth, it->T_final, it->last,
+                       ssim ? nullptr : it->target_rgb, ssim ? nullptr : it->target_depth,
+                       ssim ? nullptr : it->loss_per_view, stream);
+    if (st != GS_OK) return st;
+    const float* gC = it->dL_dcolor;
+    const float* gD = it->dL_ddepth;
+    if (ssim) {
+      st = gs_render_loss(it->plan, it->ws, it->color, it->depth, it->target_rgb, it->target_depth,
+                          it->lambda_ssim, it->loss_grad_color, it->loss_grad_depth,
+                          it->loss_per_view, stream);
+      if (st != GS_OK) return st;
+      gC = it->loss_grad_color;
+      gD = it->loss_grad_depth;
+    }
+    st = gs_render_bwd(it->plan, &it->gaussians, it->cams_dev, it->ws, it->color, it->depth,
+                       it->T_final, it->last, gC, gD, it->target_rgb, it->target_depth,
+                       &it->grads, it->dL_dpose, stream);
+    if (st != GS_OK) return st;
+    if (it->n_adam_groups > 0)
+      st = gs_adam_step(it->adam_groups, it->n_adam_groups, 1, it->beta1, it->beta2, it->eps,
+                        it->lambda_o, it->reg_count, it->step_dev, stream);
+    return st;
+  }
+
+  // Sparse path: everything is checked before anything is enqueued.
+  gs_status st;
+  if ((st = check_ws(P, it->ws)) != GS_OK) return st;
+  if ((st = check_gaussians(P, &it->gaussians)) != GS_OK) return st;
+  if (!it->cams_dev) return fail(GS_ERR_INVALID_ARG, "cams_dev is null");
+  if (!it->color || !it->depth || !it->T_final || !it->last)
+    return fail(GS_ERR_INVALID_ARG, "output image pointer is null");
+  if (!ssim && it->target_rgb && !it->loss_per_view)
+    return fail(GS_ERR_INVALID_ARG, "target_rgb given without loss_per_view");
+  const bool fused = (P.cfg.flags & GS_FUSED_L1) != 0;
+  if (!ssim && fused && !it->target_rgb) return fail(GS_ERR_INVALID_ARG, "GS_FUSED_L1 needs target_rgb");
+  if (!ssim && !fused && !it->dL_dcolor)
+    return fail(GS_ERR_INVALID_ARG, "dL_dcolor is null (and GS_FUSED_L1 not set)");
+  const gs_gaussian_grads& gr = it->grads;
+  if (!gr.means || !gr.log_scales || !gr.quats || !gr.opacity_logits || !gr.sh)
+    return fail(GS_ERR_INVALID_ARG, "gradient output pointers must be non-null");
+  if (!(it->beta1 >= 0.0 && it->beta1 < 1.0 && it->beta2 >= 0.0 && it->beta2 < 1.0 && it->eps >= 0.0))
+    return fail(GS_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+  int64_t adam_elems = 0;
+  for (int k = 0; k < it->n_adam_groups; ++k) {
+    const gs_param_group& G = it->adam_groups[k];
+    if (G.n < 0) return fail(GS_ERR_INVALID_ARG, "group %d: negative size", k);
+    if (G.n > 0 && (!G.p || !G.g || !G.m || !G.v)) return fail(GS_ERR_INVALID_ARG, "group %d: null pointer", k);
+    if (!aligned(G.p, 16) || !aligned(G.g, 16) || !aligned(G.m, 16) || !aligned(G.v, 16))
+      return fail(GS_ERR_INVALID_ARG, "group %d: pointers must be 16-byte aligned", k);
+    adam_elems += G.n;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // The Adam step counter is advanced by the first launch of the iteration
+  // and the one-view loss reduction rides on the Adam launch: two launches
+  // fewer per iteration, same values.
+  AdamFold fold{};
+  fold.step_taken = it->step_dev != nullptr;
+  const bool fold_loss = !ssim && it->target_rgb && adam_elems > 0;
+  if (fold_loss) {
+    const ViewInfo& vi = P.vt.v[0];
+    fold.tile_loss = ws_at<float2>(it->ws, P.off_tile_loss) + vi.tile_off;
+    fold.loss_tiles = vi.tiles_x * vi.tiles_y;
+    fold.loss_has_depth = it->target_depth ? 1 : 0;
+    fold.loss_pixels = (double)vi.W * vi.H;
+    fold.lambda_depth = P.cfg.lambda_depth;
+    fold.loss = it->loss_per_view;
+  }
+  st = preprocess_enqueue(it->plan, &it->gaussians, it->cams_dev, it->ws, s, it->step_dev);
   if (st != GS_OK) return st;
   st = gs_bin_sort(it->plan, it->ws, stream);
   if (st != GS_OK) return st;
-  st = gs_render_fwd(it->plan, it->ws, it->cams_dev, it->color, it->depth, it->T_final, it->last,
-                     ssim ? nullptr : it->target_rgb, ssim ? nullptr : it->target_depth,
-                     ssim ? nullptr : it->loss_per_view, stream);
-  if (st != GS_OK) return st;
+  const bool pers = (P.cfg.flags & GS_PERSISTENT) != 0;
+  int32_t* fl = ws_at<int32_t>(it->ws, P.off_flags);
+  hipError_t e = launch_render_fwd(
+      P, it->ws, it->cams_dev, it->color, it->depth, it->T_final, it->last,
+      ssim ? nullptr : it->target_rgb, ssim ? nullptr : it->target_depth,
+      (ssim || fold_loss) ? nullptr : it->loss_per_view,
+      pers ? ws_at<uint32_t>(it->ws, P.off_order) : nullptr, pers ? fl + F_QUEUE_FWD : nullptr,
+      pers ? persistent_grid(P, false) : P.vt.total_tiles, s);
+  if (e != hipSuccess) return hip_check(e, "gs_iteration_enqueue (forward)");
   const float* gC = it->dL_dcolor;
   const float* gD = it->dL_ddepth;
   if (ssim) {
@@ -555,41 +647,10 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
     gC = it->loss_grad_color;
     gD = it->loss_grad_depth;
   }
-  // One view with Adam: the projection backward writes the gradients of the
-  // Gaussians with pairs only, and Adam takes the others as zero (no zero
-  // fill, no read).  The gradient buffers are left unspecified for those.
-  const Plan& P = *plan_of(it->plan);
-  const bool sparse = it->n_adam_groups > 0 && it->n_adam_groups <= 16 && P.vt.n_views == 1 &&
-                      !(P.cfg.flags & GS_ACCUMULATE_GRADS) && P.n > 0;
-  if (!sparse) {
-    st = gs_render_bwd(it->plan, &it->gaussians, it->cams_dev, it->ws, it->color, it->depth,
-                       it->T_final, it->last, gC, gD, it->target_rgb, it->target_depth,
-                       &it->grads, it->dL_dpose, stream);
-    if (st != GS_OK) return st;
-    if (it->n_adam_groups > 0)
-      st = gs_adam_step(it->adam_groups, it->n_adam_groups, 1, it->beta1, it->beta2, it->eps,
-                        it->lambda_o, it->reg_count, it->step_dev, stream);
-    return st;
-  }
   st = gs_render_bwd_raster(it->plan, it->ws, it->cams_dev, it->color, it->depth, it->T_final,
                             it->last, gC, gD, it->target_rgb, it->target_depth, stream);
   if (st != GS_OK) return st;
-  if ((st = check_gaussians(P, &it->gaussians)) != GS_OK) return st;
-  const gs_gaussian_grads& gr = it->grads;
-  if (!gr.means || !gr.log_scales || !gr.quats || !gr.opacity_logits || !gr.sh)
-    return fail(GS_ERR_INVALID_ARG, "gradient output pointers must be non-null");
-  // the Adam arguments are checked before anything of the backward is enqueued
-  if (!(it->beta1 >= 0.0 && it->beta1 < 1.0 && it->beta2 >= 0.0 && it->beta2 < 1.0 && it->eps >= 0.0))
-    return fail(GS_ERR_INVALID_ARG, "bad Adam hyper-parameters");
-  for (int k = 0; k < it->n_adam_groups; ++k) {
-    const gs_param_group& G = it->adam_groups[k];
-    if (G.n > 0 && (!G.p || !G.g || !G.m || !G.v)) return fail(GS_ERR_INVALID_ARG, "group %d: null pointer", k);
-    if (!aligned(G.p, 16) || !aligned(G.g, 16) || !aligned(G.m, 16) || !aligned(G.v, 16))
-      return fail(GS_ERR_INVALID_ARG, "group %d: pointers must be 16-byte aligned", k);
-  }
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_project_bwd(P, it->gaussians, it->cams_dev, it->ws, gr, it->dL_dpose, 0,
-                                    true, s);
+  e = launch_project_bwd(P, it->gaussians, it->cams_dev, it->ws, gr, it->dL_dpose, 0, true, s);
   if (e != hipSuccess) return hip_check(e, "gs_iteration_enqueue (projection backward)");
   const uint32_t* vis[16];
   int32_t per[16];
@@ -609,7 +670,7 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
   }
   e = launch_adam(it->adam_groups, it->n_adam_groups, 1, it->beta1, it->beta2, it->eps,
                   it->lambda_o, it->reg_count, it->step_dev, s, vis, per,
-                  ws_at<int32_t>(it->ws, P.off_flags) + F_OVERFLOW);
+                  ws_at<int32_t>(it->ws, P.off_flags) + F_OVERFLOW, &fold);
   return hip_check(e, "gs_iteration_enqueue (Adam)");
 }
 

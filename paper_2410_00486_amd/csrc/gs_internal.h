@@ -162,6 +162,59 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t x) {
   return x;
 }
 
+// L1 loss of one view from its per-tile partials (float2: colour sum, depth
+// sum): mean|C - C*| + lambda_depth mean|D - D*|.  The summation order is
+// that of 1024 threads (thread t sums tiles t, t + 1024, ... in FP64; wave
+// butterflies; the 16 wave sums in order), whatever the block size NT (a
+// multiple of 64 dividing 1024), so every caller gets the same bits.  Every
+// thread of the block must call; thread 0 writes *loss.
+constexpr int kLossVirtual = 1024;
+template <int NT>
+__device__ __forceinline__ void loss_reduce_view(const float2* __restrict__ tl, int nt, double npx,
+                                                 float lambda_depth, int has_depth,
+                                                 float* __restrict__ loss) {
+  static_assert(NT % kWave == 0 && kLossVirtual % NT == 0, "block size");
+  constexpr int J = kLossVirtual / NT, VW = kLossVirtual / kWave;
+  __shared__ double sa[VW], sb[VW];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int vt = j * NT + (int)threadIdx.x;  // virtual thread
+    double a = 0.0, b = 0.0;
+    for (int k = vt; k < nt; k += kLossVirtual) {
+      const float2 x = tl[k];
+      a += x.x;
+      b += x.y;
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane_id() == 0) {
+      sa[vt / kWave] = a;
+      sb[vt / kWave] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tb = 0.0;
+    for (int k = 0; k < VW; ++k) {
+      ta += sa[k];
+      tb += sb[k];
+    }
+    *loss = (float)(ta / (3.0 * npx) + (has_depth ? lambda_depth * tb / npx : 0.0));
+  }
+}
+
+// Work of a whole iteration that rides on the Adam launch: the step counter
+// advanced at the iteration's start (Adam then reads t = *step_dev), and the
+// reduction of a one-view forward's per-tile L1 partials into *loss.
+struct AdamFold {
+  bool step_taken;
+  const float2* tile_loss;
+  int32_t loss_tiles, loss_has_depth;
+  double loss_pixels;
+  float lambda_depth;
+  float* loss;
+};
+
 // Host-side launch helpers (defined in the .hip files).
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 

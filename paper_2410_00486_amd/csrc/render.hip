@@ -308,37 +308,15 @@ __global__ void __launch_bounds__(kWave) k_render_fwd(
 }
 
 // Per-view L1 loss from the per-tile sums, in a fixed order.
-constexpr int kLossThreads = 1024;
+constexpr int kLossThreads = kLossVirtual;
 __global__ void __launch_bounds__(kLossThreads) k_loss_reduce(const float* __restrict__ tile_loss,
                                                               ViewTable vt, float lambda_depth,
                                                               int has_depth, float* __restrict__ loss) {
   const int v = blockIdx.x;
   const ViewInfo vi = vt.v[v];
-  const int nt = vi.tiles_x * vi.tiles_y;
-  const float2* tl = reinterpret_cast<const float2*>(tile_loss) + vi.tile_off;
-  double a = 0.0, b = 0.0;
-  for (int k = threadIdx.x; k < nt; k += kLossThreads) {
-    const float2 x = tl[k];
-    a += x.x;
-    b += x.y;
-  }
-  __shared__ double sa[kLossThreads / kWave], sb[kLossThreads / kWave];
-  a = wave_sum(a);
-  b = wave_sum(b);
-  if (lane_id() == 0) {
-    sa[threadIdx.x / kWave] = a;
-    sb[threadIdx.x / kWave] = b;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double ta = 0.0, tb = 0.0;
-    for (int k = 0; k < kLossThreads / kWave; ++k) {
-      ta += sa[k];
-      tb += sb[k];
-    }
-    const double npx = (double)vi.W * vi.H;
-    loss[v] = (float)(ta / (3.0 * npx) + (has_depth ? lambda_depth * tb / npx : 0.0));
-  }
+  loss_reduce_view<kLossThreads>(reinterpret_cast<const float2*>(tile_loss) + vi.tile_off,
+                                 vi.tiles_x * vi.tiles_y, (double)vi.W * vi.H, lambda_depth,
+                                 has_depth, loss + v);
 }
 
 // ------------------------------------------------------------------ backward

@@ -432,6 +432,13 @@ def test_iteration_sparse_adam_equals_separate_calls(lambda_o, degree):
         assert torch.equal(getattr(g1, f), getattr(g2, f)), f
         assert torch.equal(getattr(it.m, f), getattr(m, f)), f
         assert torch.equal(getattr(it.v, f), getattr(v, f)), f
+    # the iteration reduces the loss inside its Adam launch and advances the
+    # step counter in its first launch: same loss bits, one step per call
+    assert torch.equal(it.frame.loss, fr.loss)
+    assert int(it.step_dev.item()) == 1
+    it.enqueue()
+    torch.cuda.synchronize()
+    assert int(it.step_dev.item()) == 2
 
 
 # ------------------------------------------------------------------ edge cases
