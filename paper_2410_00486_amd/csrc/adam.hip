@@ -36,7 +36,7 @@ struct AdamArgs {
   float eps;
   float reg_scale;        // lambda_o / reg_count
   const int32_t* step_dev;
-  int32_t step_taken;       // the iteration advanced *step_dev already: t = *step_dev
+  const double* bias;       // the iteration advanced *step_dev already: bias corrections
   const int32_t* overflow;  // with vis: every gradient is zero after a pair overflow
   // optional: block 0 also reduces the forward's per-tile L1 partials of a
   // one-view iteration into *loss (the loss needs nothing after the forward)
@@ -69,9 +69,15 @@ __global__ void __launch_bounds__(kAdamThreads) k_adam(AdamArgs a) {
   if (a.loss && blockIdx.x == 0)
     loss_reduce_view<kAdamThreads>(a.tile_loss, a.loss_tiles, a.loss_pixels, a.lambda_depth,
                                    a.loss_has_depth, a.loss);
-  const int step = a.step_dev ? (*a.step_dev + (a.step_taken ? 0 : 1)) : a.step;
-  const double bc1 = 1.0 - pow(a.beta1d, (double)step);
-  const double bc2 = 1.0 - pow(a.beta2d, (double)step);
+  double bc1, bc2;
+  if (a.bias) {
+    bc1 = a.bias[0];
+    bc2 = a.bias[1];
+  } else {
+    const int step = a.step_dev ? (*a.step_dev + 1) : a.step;
+    bc1 = 1.0 - pow(a.beta1d, (double)step);
+    bc2 = 1.0 - pow(a.beta2d, (double)step);
+  }
   const float step_size = (float)((double)G.lr / bc1);
   const float inv_bc2s = (float)(1.0 / sqrt(bc2));
   const int64_t e0 = ((int64_t)blockIdx.x - G.block0) * (kAdamThreads * kAdamVec) +
@@ -174,7 +180,7 @@ hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, dou
     if (a.reg_scale == 0.0f)
       for (int k = 0; k < ng; ++k) a.grp[k].reg = 0;
     a.step_dev = step_dev;
-    a.step_taken = (fold && fold->step_taken) ? 1 : 0;
+    a.bias = (fold && fold->step_taken) ? fold->bias : nullptr;
     a.overflow = overflow;
     if (fold && fold->loss && base == 0) {
       a.tile_loss = fold->tile_loss;

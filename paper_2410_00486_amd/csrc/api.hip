@@ -19,7 +19,8 @@ hipError_t launch_radix_sort(uint64_t* keys0, uint64_t* keys1, uint32_t* vals0, 
                              const int32_t* cnt, uint32_t* hist, uint32_t* digit_tot,
                              int64_t nb_cap, int key_bits, bool iota, int* which, hipStream_t s);
 hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t s);
-hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s, int32_t* step = nullptr);
+hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s,
+                                 const StepAdvance* step = nullptr);
 uint32_t* sorted_vals(const Plan& P, void* ws);
 hipError_t launch_render_fwd(const Plan& P, void* ws, const float* cams, float* color,
                              float* depth, float* T_final, uint32_t* last,
@@ -291,7 +292,7 @@ int32_t* gs_flags_ptr(const gs_plan* plan, void* ws) {
 // launch as the counter clear (used by the whole-iteration enqueue).
 static gs_status preprocess_enqueue(const gs_plan* plan, const gs_gaussians* g,
                                     const float* cams_dev, void* ws, hipStream_t s,
-                                    int32_t* step_advance) {
+                                    const StepAdvance* step_advance) {
   gs_status st;
   if ((st = check_plan(plan)) != GS_OK) return st;
   const Plan& P = *plan_of(plan);
@@ -614,6 +615,9 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
   // fewer per iteration, same values.
   AdamFold fold{};
   fold.step_taken = it->step_dev != nullptr;
+  double* bias = reinterpret_cast<double*>(ws_at<char>(it->ws, P.off_flags) + kBiasOffset);
+  fold.bias = bias;
+  const StepAdvance adv{it->step_dev, it->beta1, it->beta2, bias};
   const bool fold_loss = !ssim && it->target_rgb && adam_elems > 0;
   if (fold_loss) {
     const ViewInfo& vi = P.vt.v[0];
@@ -624,7 +628,8 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
     fold.lambda_depth = P.cfg.lambda_depth;
     fold.loss = it->loss_per_view;
   }
-  st = preprocess_enqueue(it->plan, &it->gaussians, it->cams_dev, it->ws, s, it->step_dev);
+  st = preprocess_enqueue(it->plan, &it->gaussians, it->cams_dev, it->ws, s,
+                          it->step_dev ? &adv : nullptr);
   if (st != GS_OK) return st;
   st = gs_bin_sort(it->plan, it->ws, stream);
   if (st != GS_OK) return st;

@@ -30,13 +30,19 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t cou
 __global__ void k_set_i32(int32_t* __restrict__ p, int32_t value) { *p = value; }
 
 // Clears a[0, na) and b[0, nb); with a step counter, also advances it (the
-// Adam step of a whole iteration, taken at its start).
+// Adam step of a whole iteration, taken at its start) and stores the bias
+// corrections 1 - beta1^t, 1 - beta2^t of the new step t for the Adam launch.
 __global__ void k_fill2_u32(uint32_t* __restrict__ a, int64_t na, uint32_t* __restrict__ b,
-                            int64_t nb, int32_t* __restrict__ step) {
+                            int64_t nb, StepAdvance st) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < na) a[i] = 0u;
   if (i < nb) b[i] = 0u;
-  if (step && i == 0) *step += 1;
+  if (st.step && i == 0) {
+    const int32_t t = *st.step + 1;
+    *st.step = t;
+    st.bias[0] = 1.0 - pow(st.beta1, (double)t);
+    st.bias[1] = 1.0 - pow(st.beta2, (double)t);
+  }
 }
 
 // ---------------------------------------------------------------- scans
@@ -754,13 +760,14 @@ hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s, int32_t* step) {
+hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s, const StepAdvance* step) {
   // per-iteration flags 0..10 and the per-tile pair counters
   const int64_t T = P.vt.total_tiles;
   const int64_t m = T > 4 ? T : 4;
   hipLaunchKernelGGL(k_fill2_u32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
                      ws_at<uint32_t>(ws, P.off_flags), (int64_t)11,
-                     ws_at<uint32_t>(ws, P.off_tile_cnt), T, step);
+                     ws_at<uint32_t>(ws, P.off_tile_cnt), T,
+                     step ? *step : StepAdvance{nullptr, 0.0, 0.0, nullptr});
   return hipGetLastError();
 }
 

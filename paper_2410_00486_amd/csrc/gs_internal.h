@@ -203,11 +203,24 @@ __device__ __forceinline__ void loss_reduce_view(const float2* __restrict__ tl, 
   }
 }
 
+// The Adam step counter advanced by the first launch of an iteration, with
+// the bias corrections of the new step stored at `bias` (two doubles inside
+// the workspace's flag block, at kBiasOffset).
+struct StepAdvance {
+  int32_t* step;
+  double beta1, beta2;
+  double* bias;
+};
+constexpr size_t kBiasOffset = 128;  // bytes from the flags (F_COUNT int32 before it)
+static_assert(kBiasOffset >= F_COUNT * 4 && kBiasOffset + 16 <= F_COUNT * 16, "flag block");
+
 // Work of a whole iteration that rides on the Adam launch: the step counter
-// advanced at the iteration's start (Adam then reads t = *step_dev), and the
-// reduction of a one-view forward's per-tile L1 partials into *loss.
+// advanced at the iteration's start (Adam then reads the bias corrections
+// stored then), and the reduction of a one-view forward's per-tile L1
+// partials into *loss.
 struct AdamFold {
   bool step_taken;
+  const double* bias;
   const float2* tile_loss;
   int32_t loss_tiles, loss_has_depth;
   double loss_pixels;
