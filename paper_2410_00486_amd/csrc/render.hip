@@ -184,19 +184,22 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec
     for (int k = 0; k < PPL; ++k) a = a || !done[k];
     return a;
   };
-  for (uint32_t b = s; b < e; b += (uint32_t)B) {
+  bool more = true;
+  for (uint32_t b = s; more && b < e; b += (uint32_t)B) {
     if (ballot64(active()) == 0) break;
     const int nb = (int)min((uint32_t)B, e - b);
     __syncthreads();
     stage(srec, nullptr, lrec, nullptr, b, nb, lane);
     __syncthreads();
-    for (int j = 0; j < nb; ++j) {
+    // segments between the 64-position bucket boundaries of the list, so
+    // that the pixel states are stored outside the per-splat loop
+    for (int j = 0; more && j < nb;) {
+      const uint32_t q0 = b - s + (uint32_t)j;
       if constexpr (CKPT) {
         // state of every pixel before each 64th splat of the tile list (the
         // state before the first splat is the empty one and is not stored)
-        const uint32_t q = b - s + (uint32_t)j;
-        if (q != 0 && (q & (kBucket - 1)) == 0) {
-          float* cp = ckpt + (int64_t)(boff[gtile] + q / kBucket) * (kStateFloats * NPX);
+        if (q0 != 0 && (q0 & (kBucket - 1)) == 0) {
+          float* cp = ckpt + (int64_t)(boff[gtile] + q0 / kBucket) * (kStateFloats * NPX);
 #pragma unroll
           for (int k = 0; k < PPL; ++k) {
             const int jj = TG::y(lane, k) * TW + TG::x(lane, k);
@@ -208,29 +211,57 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec
           }
         }
       }
-      const Rec& r = srec[j];
+      const int jend = min(nb, j + (int)(kBucket - (q0 & (kBucket - 1))));
+      for (; j < jend; j += 2) {
+        // two records at once (whole records, broadcast LDS reads): their
+        // alphas are independent, only the blends are ordered.  Every
+        // decision of eval_alpha is a select: no divergent branches.
+        const bool has1 = j + 1 < jend;
+        const Rec r0 = srec[j];
+        const Rec r1 = srec[has1 ? j + 1 : j];
+        const uint32_t pos0 = b - s + (uint32_t)j + 1u;
 #pragma unroll
-      for (int k = 0; k < PPL; ++k) {
-        if (!done[k]) {
-          double dx, dy;
-          float G, oG, a;
-          if (eval_alpha(r, sx[k], sy[k], dx, dy, G, oG, a)) {
-            const float Tn = T[k] * (1.0f - a);
-            if (Tn < kTMin) {
-              done[k] = true;
-            } else {
-              const float w = a * T[k];
-              c0[k] = fmaf(r.r, w, c0[k]);
-              c1[k] = fmaf(r.g, w, c1[k]);
-              c2[k] = fmaf(r.b, w, c2[k]);
-              D[k] = fmaf(r.z, w, D[k]);
-              T[k] = Tn;
-              lastpos[k] = b - s + (uint32_t)j + 1u;
-            }
+        for (int k = 0; k < PPL; ++k) {
+          const double dx0 = r0.mx - sx[k], dy0 = r0.my - sy[k];
+          const double dx1 = r1.mx - sx[k], dy1 = r1.my - sy[k];
+          const double pw0 = fma(dx0, fma(r0.ca, dx0, r0.cb * dy0), (r0.cc * dy0) * dy0);
+          const double pw1 = fma(dx1, fma(r1.ca, dx1, r1.cb * dy1), (r1.cc * dy1) * dy1);
+          const float a0 = fminf(kAlphaMax, r0.o * __builtin_amdgcn_exp2f((float)(pw0 * kLog2e)));
+          const float a1 = fminf(kAlphaMax, r1.o * __builtin_amdgcn_exp2f((float)(pw1 * kLog2e)));
+          {
+            const bool hit = !done[k] && !(pw0 > 0.0) && a0 >= kAlphaMin;
+            const float Tn = T[k] * (1.0f - a0);
+            const bool stop = Tn < kTMin;
+            const bool blend = hit && !stop;
+            const float w = a0 * T[k];
+            c0[k] = blend ? fmaf(r0.r, w, c0[k]) : c0[k];
+            c1[k] = blend ? fmaf(r0.g, w, c1[k]) : c1[k];
+            c2[k] = blend ? fmaf(r0.b, w, c2[k]) : c2[k];
+            D[k] = blend ? fmaf(r0.z, w, D[k]) : D[k];
+            T[k] = blend ? Tn : T[k];
+            lastpos[k] = blend ? pos0 : lastpos[k];
+            done[k] = done[k] || (hit && stop);
+          }
+          {
+            const bool hit = has1 && !done[k] && !(pw1 > 0.0) && a1 >= kAlphaMin;
+            const float Tn = T[k] * (1.0f - a1);
+            const bool stop = Tn < kTMin;
+            const bool blend = hit && !stop;
+            const float w = a1 * T[k];
+            c0[k] = blend ? fmaf(r1.r, w, c0[k]) : c0[k];
+            c1[k] = blend ? fmaf(r1.g, w, c1[k]) : c1[k];
+            c2[k] = blend ? fmaf(r1.b, w, c2[k]) : c2[k];
+            D[k] = blend ? fmaf(r1.z, w, D[k]) : D[k];
+            T[k] = blend ? Tn : T[k];
+            lastpos[k] = blend ? pos0 + 1u : lastpos[k];
+            done[k] = done[k] || (hit && stop);
           }
         }
+        if (ballot64(active()) == 0) {
+          more = false;
+          break;
+        }
       }
-      if (ballot64(active()) == 0) break;
     }
   }
   const float* cam = cams + (int64_t)v * GS_CAMERA_FLOATS;
