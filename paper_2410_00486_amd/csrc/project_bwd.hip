@@ -24,19 +24,20 @@ constexpr double kSH3e = 1.445305721320277;
 
 // For each basis function k up to DEG: Y_k and its gradient as a polynomial
 // in (x, y, z) are formed in place, the SH-coefficient gradient Y_k * gcr is
-// written, and w_k grad Y_k (w_k = sum_ch gcr_ch SH_k,ch) is added to gd.
+// added to gsh[], and w_k grad Y_k (w_k = sum_ch gcr_ch SH_k,ch) to gd.  The
+// coefficients shv[] and gradients gsh[] are registers: the caller loads
+// and stores them in batches, so no memory round trip sits in the chain.
 template <int DEG>
 __device__ __forceinline__ void sh_backward(double x, double y, double z, const double* gcr,
-                                            const float* __restrict__ shp, float* gsh,
-                                            bool first, double& gx, double& gy, double& gz) {
+                                            const float* shv, float* gsh, double& gx,
+                                            double& gy, double& gz) {
   const double xx = x * x, yy = y * y, zz = z * z;
   auto term = [&](int k, double Yk, double dx, double dy, double dz) {
     double w = 0.0;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-      w += gcr[ch] * (double)shp[3 * k + ch];
-      const float add = (float)(Yk * gcr[ch]);
-      gsh[3 * k + ch] = first ? add : gsh[3 * k + ch] + add;
+      w += gcr[ch] * (double)shv[3 * k + ch];
+      gsh[3 * k + ch] += (float)(Yk * gcr[ch]);
     }
     gx += w * dx;
     gy += w * dy;
@@ -99,14 +100,23 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
   }
   __shared__ double spose[NW][6];
 
+  // Every per-Gaussian input is loaded at once, unconditionally (row 0 for
+  // an idle thread; n > 0 whenever the kernel runs), so that the loads issue
+  // together instead of one round trip each along the chain.
+  const int64_t ic = valid ? i : 0;
+  const float mf0 = means[3 * ic], mf1 = means[3 * ic + 1], mf2 = means[3 * ic + 2];
+  const float qf0 = quats[4 * ic], qf1 = quats[4 * ic + 1], qf2 = quats[4 * ic + 2],
+              qf3 = quats[4 * ic + 3];
+  const float lf0 = log_scales[3 * ic], lf1 = log_scales[3 * ic + 1], lf2 = log_scales[3 * ic + 2];
+  const float logit = logits[ic];
+
   // world covariance Sigma (view independent); its gradient is summed over
   // views and pushed through scale and rotation once, after the view loop
   double p[3] = {0, 0, 0};
   double S00 = 0, S01 = 0, S02 = 0, S11 = 0, S12 = 0, S22 = 0;
   if (valid) {
-    p[0] = means[3 * i]; p[1] = means[3 * i + 1]; p[2] = means[3 * i + 2];
-    double q[4];
-    for (int k = 0; k < 4; ++k) q[k] = quats[4 * i + k];
+    p[0] = mf0; p[1] = mf1; p[2] = mf2;
+    double q[4] = {qf0, qf1, qf2, qf3};
     const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     if (qn > 0.0)
       for (int k = 0; k < 4; ++k) q[k] /= qn;
@@ -114,8 +124,7 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
     const double R00 = 1 - 2 * (y * y + z * z), R01 = 2 * (x * y - w * z), R02 = 2 * (x * z + w * y);
     const double R10 = 2 * (x * y + w * z), R11 = 1 - 2 * (x * x + z * z), R12 = 2 * (y * z - w * x);
     const double R20 = 2 * (x * z - w * y), R21 = 2 * (y * z + w * x), R22 = 1 - 2 * (x * x + y * y);
-    const double s0 = exp(2.0 * (double)log_scales[3 * i]), s1 = exp(2.0 * (double)log_scales[3 * i + 1]),
-                 s2 = exp(2.0 * (double)log_scales[3 * i + 2]);
+    const double s0 = exp(2.0 * (double)lf0), s1 = exp(2.0 * (double)lf1), s2 = exp(2.0 * (double)lf2);
     S00 = R00 * R00 * s0 + R01 * R01 * s1 + R02 * R02 * s2;
     S01 = R00 * R10 * s0 + R01 * R11 * s1 + R02 * R12 * s2;
     S02 = R00 * R20 * s0 + R01 * R21 * s1 + R02 * R22 * s2;
@@ -125,16 +134,27 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
   }
   double gp0 = 0, gp1 = 0, gp2 = 0, gop = 0;
   double GS00 = 0, GS01 = 0, GS02 = 0, GS11 = 0, GS12 = 0, GS22 = 0;
+  // SH coefficients and their gradient in registers for the whole view loop
+  // (loaded unconditionally, row 0 for an idle thread, so that the loads
+  // issue together; n > 0 whenever the kernel runs)
+  float shv[K * 3], gsh[K * 3];
+  const float* shrow = sh + ic * (K * 3);
+#pragma unroll
+  for (int k = 0; k < K * 3; ++k) {
+    shv[k] = shrow[k];
+    gsh[k] = 0.0f;
+  }
   bool sh_written = false;
 
   for (int v = 0; v < vt.n_views; ++v) {
-    const int64_t ri = (int64_t)v * n + i;
-    const uint32_t cnt = (valid && !overflow) ? tt[ri] : 0u;
+    const int64_t ri = (int64_t)v * n + ic;
+    const uint32_t tt_v = tt[ri], poff_v = poff[ri], cmask = recs[ri].clamp;
+    const uint32_t cnt = (valid && !overflow) ? tt_v : 0u;
     double pose[6] = {0, 0, 0, 0, 0, 0};
     if (cnt > 0) {
       // fixed-order sum of this (view, Gaussian)'s pair partials
       double g2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-      const float4* gpp = reinterpret_cast<const float4*>(grad_pair + (int64_t)poff[ri] * kPairGrad);
+      const float4* gpp = reinterpret_cast<const float4*>(grad_pair + (int64_t)poff_v * kPairGrad);
       // loads of eight pairs are issued before their (in-order) additions,
       // so a large Gaussian does not pay one memory round trip per tile
       auto add = [&](const float4& a, const float4& b, const float4& c) {
@@ -221,14 +241,11 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
       const double dv0 = p[0] - cxw, dv1 = p[1] - cyw, dv2 = p[2] - czw;
       const double dist = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
       const double d0 = dv0 / dist, d1 = dv1 / dist, d2 = dv2 / dist;
-      const float* shp = sh + i * (K * 3);
-      float* gsh = g_sh + i * (K * 3);
       // colour clamp decided by the forward projection (record bit per channel)
-      const uint32_t cmask = recs[ri].clamp;
       double gcr[3];
       for (int ch = 0; ch < 3; ++ch) gcr[ch] = ((cmask >> ch) & 1u) ? 0.0 : g2[ch];
       double gd0 = 0, gd1 = 0, gd2 = 0;
-      sh_backward<DEG>(d0, d1, d2, gcr, shp, gsh, !sh_written && !accumulate, gd0, gd1, gd2);
+      sh_backward<DEG>(d0, d1, d2, gcr, shv, gsh, gd0, gd1, gd2);
       sh_written = true;
       const double dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
       const double gv0 = (gd0 - dd * d0) / dist, gv1 = (gd1 - dd * d1) / dist,
@@ -289,8 +306,7 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
   if (!valid) return;
   // Sigma = M M^T, M = R diag(s):  g_l_j = 2 s_j^2 R_j^T G R_j,
   // G_R[:, j] = 2 s_j^2 G R_j, then through the normalised quaternion
-  double q[4];
-  for (int k = 0; k < 4; ++k) q[k] = quats[4 * i + k];
+  double q[4] = {qf0, qf1, qf2, qf3};
   const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
   if (qn > 0.0)
     for (int k = 0; k < 4; ++k) q[k] /= qn;
@@ -304,7 +320,7 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
     const double G0 = GS00 * Rj0 + GS01 * Rj1 + GS02 * Rj2;
     const double G1 = GS01 * Rj0 + GS11 * Rj1 + GS12 * Rj2;
     const double G2 = GS02 * Rj0 + GS12 * Rj1 + GS22 * Rj2;
-    const double s2 = exp(2.0 * (double)log_scales[3 * i + j]);
+    const double s2 = exp(2.0 * (double)(j == 0 ? lf0 : (j == 1 ? lf1 : lf2)));
     gl[j] = 2.0 * s2 * (Rj0 * G0 + Rj1 * G1 + Rj2 * G2);
     GR[j] = 2.0 * s2 * G0;
     GR[3 + j] = 2.0 * s2 * G1;
@@ -319,7 +335,7 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
   const double dz = GR[0] * (-4 * qz) + GR[1] * (-2 * qw) + GR[2] * (2 * qx) + GR[3] * (2 * qw) +
                     GR[4] * (-4 * qz) + GR[5] * (2 * qy) + GR[6] * (2 * qx) + GR[7] * (2 * qy);
   const double dot = dw * qw + dx * qx + dy * qy + dz * qz;
-  const double o = 1.0 / (1.0 + exp(-(double)logits[i]));
+  const double o = 1.0 / (1.0 + exp(-(double)logit));
   auto put = [&](float* dst, double val) { *dst = accumulate ? *dst + (float)val : (float)val; };
   put(&g_means[3 * i], gp0);
   put(&g_means[3 * i + 1], gp1);
@@ -331,10 +347,20 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
   put(&g_q[4 * i + 2], (dy - dot * qy) / qnn);
   put(&g_q[4 * i + 3], (dz - dot * qz) / qnn);
   put(&g_logit[i], gop * o * (1.0 - o));
-  if (!sh_written && !accumulate) {
-    float* gsh = g_sh + i * (K * 3);
-    for (int k = 0; k < K * 3; ++k) gsh[k] = 0.0f;
+  // SH gradients: sums over the views in registers, one batch of stores
+  // (zeros for a Gaussian without pairs)
+  float* gdst = g_sh + i * (K * 3);
+  if (accumulate) {
+    float old[K * 3];
+#pragma unroll
+    for (int k = 0; k < K * 3; ++k) old[k] = gdst[k];
+#pragma unroll
+    for (int k = 0; k < K * 3; ++k) gdst[k] = old[k] + gsh[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < K * 3; ++k) gdst[k] = gsh[k];
   }
+  (void)sh_written;
 }
 
 // Zero of the five gradient arrays (59 floats per Gaussian at degree 3).
