@@ -65,8 +65,9 @@ typedef int32_t gs_status;
                                          loss against the targets instead of inputs */
 #define GS_ACCUMULATE_GRADS (1u << 2) /* gs_render_bwd adds into the gradient buffers */
 #define GS_PERSISTENT (1u << 3)       /* render kernels are resident and walk the
-                                         tiles in chunks, longest tiles first, with a
-                                         static stride */
+                                         tiles in chunks with a static stride (in
+                                         either mode tiles with long lists run
+                                         first, the order gs_bin_sort writes) */
 #define GS_SPLAT_BWD (1u << 4)        /* splat-wise backward (Sec. III-C-1, Fig. 4a):
                                          the forward stores per-pixel (T, RGB, D) states
                                          at every 64th splat of a tile; the backward
@@ -176,8 +177,10 @@ gs_status gs_preprocess(const gs_plan* plan, const gs_gaussians* g, const float*
  * ordered by (float32 depth, generation index): ties in depth keep Gaussian
  * order, so the lists are unique and bit-exact.  Needs the per-tile and
  * per-chunk (64 Gaussians of a view) pair counts of the gs_preprocess call
- * just before on the same workspace.  Overflow of the plan's pair capacity
- * sets flag [0]. */
+ * just before on the same workspace.  Also writes the render kernels' work
+ * order: tiles with at least 32 pairs first, in tile order, then the others
+ * in reverse tile order (results do not depend on the order).
+ * Overflow of the plan's pair capacity sets flag [0]. */
 gs_status gs_bin_sort(const gs_plan* plan, void* ws, void* stream);
 
 /* a3. Front-to-back compositing of Eq. (1) per pixel over its tile's sorted
@@ -302,8 +305,7 @@ gs_status gs_densify_prune(const gs_gaussians* g, const gs_gaussian_grads* m,
                            int64_t out_capacity, int32_t* n_out, void* tmp, void* stream);
 
 /* Stand-alone stable LSD radix sort of n (key, value) pairs on the low
- * key_bits bits of the keys (1..64), the kernels that order the tiles of
- * the persistent render kernels.
+ * key_bits bits of the keys (1..64).
  * keys/vals are device arrays, sorted in place; tmp is device scratch of
  * gs_sort_tmp_bytes(n) bytes. */
 size_t gs_sort_tmp_bytes(int64_t n);

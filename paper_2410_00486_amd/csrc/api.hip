@@ -41,7 +41,6 @@ hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, dou
                        int32_t* step_dev, hipStream_t s, const uint32_t* const* vis = nullptr,
                        const int32_t* per = nullptr, const int32_t* overflow = nullptr,
                        const AdamFold* fold = nullptr);
-hipError_t launch_tile_order(const Plan& P, void* ws, hipStream_t s);
 int render_blocks_per_cu(const Plan& P, bool bwd);
 int splat_blocks_per_cu(const Plan& P);
 int64_t ssim_tiles(const Plan& P);
@@ -193,7 +192,6 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->chunks_per_view = (n + kWave - 1) / kWave;
   P->n_chunks = (int64_t)n_views * P->chunks_per_view;
   P->proj_blocks = (n + kProjThreads - 1) / kProjThreads;
-  const int64_t order_blocks = (tiles + kSortTile - 1) / kSortTile;
 
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -219,15 +217,12 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_pair_rec = take(cap * 4);
   P->off_sorted_rec = take(cap * 4);
   P->off_srec = take(cap * sizeof(Rec));
-  P->off_hist = take((size_t)kRadix * std::max<int64_t>(order_blocks, 1) * 4);
-  P->off_digit_tot = take(kRadix * 4);
   P->off_ranges = take(T * 2 * 4);
   P->off_tile_last = take(T * 4);
   P->off_tile_loss = take(T * 2 * 4);
   P->off_grad_pair = take(cap * kPairGrad * 4);
   P->off_pose_part = take((size_t)n_views * std::max<int64_t>(P->proj_blocks, 1) * 6 * 8);
   P->off_order = take(T * 4);
-  P->off_order_tmp = take(T * (8 + 8 + 4 + 4) + 256);
   P->off_ssim_maps = take((size_t)pix * 9 * 4);
   P->off_ssim_part = take((size_t)ssim_tiles(*P) * 12 * 4);
   // splat-wise backward: bucket k of tile t uses checkpoint slot boff[t] + k,
@@ -318,7 +313,6 @@ gs_status gs_bin_sort(const gs_plan* plan, void* ws, void* stream) {
   if ((st = check_ws(P, ws)) != GS_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = launch_bin_sort(P, ws, s);
-  if (e == hipSuccess && (P.cfg.flags & GS_PERSISTENT)) e = launch_tile_order(P, ws, s);
   return hip_check(e, "gs_bin_sort");
 }
 
@@ -344,7 +338,7 @@ gs_status gs_render_fwd(const gs_plan* plan, void* ws, const float* cams_dev, fl
   hipError_t e = hipSuccess;
   if (e == hipSuccess)
     e = launch_render_fwd(P, ws, cams_dev, color, depth, T_final, last, target_rgb, target_depth,
-                          loss_per_view, pers ? ws_at<uint32_t>(ws, P.off_order) : nullptr,
+                          loss_per_view, ws_at<uint32_t>(ws, P.off_order),
                           pers ? fl + F_QUEUE_FWD : nullptr,
                           pers ? persistent_grid(P, false) : P.vt.total_tiles, s);
   return hip_check(e, "gs_render_fwd");
@@ -379,7 +373,7 @@ gs_status gs_render_bwd_raster(const gs_plan* plan, void* ws, const float* cams_
   if (e == hipSuccess)
     e = launch_render_bwd(P, ws, cams_dev, color, depth, T_final, last, dL_dcolor, dL_ddepth,
                           target_rgb, target_depth, fused ? 1 : 0, sorted_vals(P, ws),
-                          pers ? ws_at<uint32_t>(ws, P.off_order) : nullptr,
+                          ws_at<uint32_t>(ws, P.off_order),
                           pers ? fl + F_QUEUE_BWD : nullptr, grid, s);
   return hip_check(e, "gs_render_bwd_raster");
 }
@@ -639,7 +633,7 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
       P, it->ws, it->cams_dev, it->color, it->depth, it->T_final, it->last,
       ssim ? nullptr : it->target_rgb, ssim ? nullptr : it->target_depth,
       (ssim || fold_loss) ? nullptr : it->loss_per_view,
-      pers ? ws_at<uint32_t>(it->ws, P.off_order) : nullptr, pers ? fl + F_QUEUE_FWD : nullptr,
+      ws_at<uint32_t>(it->ws, P.off_order), pers ? fl + F_QUEUE_FWD : nullptr,
       pers ? persistent_grid(P, false) : P.vt.total_tiles, s);
   if (e != hipSuccess) return hip_check(e, "gs_iteration_enqueue (forward)");
   const float* gC = it->dL_dcolor;

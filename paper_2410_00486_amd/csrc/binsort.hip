@@ -14,9 +14,10 @@
 // global memory beyond).  Four launches whatever the pair count, no
 // spin-waits; graph-capturable.
 //
-// The general stable LSD radix sort (8-bit digits, wave64 ballot ranking)
-// below serves the standalone key/value sort and the longest-first tile
-// order of the persistent render kernels.
+// The scan block also writes the work order of the render kernels: tiles
+// with long lists first.  The general stable LSD
+// radix sort (8-bit digits, wave64 ballot ranking) below serves the
+// standalone key/value sort.
 #include "gs_internal.h"
 
 namespace gs {
@@ -87,7 +88,14 @@ struct ScanArgs {
   uint32_t* boff;          // splat-wise only (else null): bucket offset per tile, [T] = total
   uint32_t* fstart;        // position of the tile's first full bucket in queue 0
   uint32_t* hstart;        // position of the tile's half bucket in queue 1
+  uint32_t* order;         // work order of the render kernels, longest tiles first
 };
+
+// Work order of the render kernels: tiles with at least kLongTile pairs
+// first (in tile order), then the others (in reverse tile order), so that
+// the long lists start in the first round of the dispatch and the tail is
+// made of short ones.  Both positions come out of the scan.
+constexpr uint32_t kLongTile = 32;
 
 // Inclusive wavefront scans with DPP (full-rate VALU, no LDS traffic): row
 // shifts by 1, 2, 4, 8 within each 16-lane row, then the last lane of row 0
@@ -221,11 +229,11 @@ __global__ void __launch_bounds__(kScanBlock) k_scans(ScanArgs A, int64_t cap,
   constexpr int NW = kScanBlock / kWave;
   constexpr int NT = 4 * kScanVec, NC = 2 * kScanVec;  // tiles, chunks per thread and round
   // channels: 64-bit tile pairs, chunk pairs; 32-bit buckets, half buckets,
-  // visible records (full buckets = buckets - half buckets)
+  // visible records (full buckets = buckets - half buckets), long tiles
   __shared__ uint64_t w64[2 * (NW + 1)];
-  __shared__ uint32_t w32[3 * (NW + 1)];
+  __shared__ uint32_t w32[4 * (NW + 1)];
   uint64_t c64[2] = {0, 0};
-  uint32_t c32[3] = {0, 0, 0};
+  uint32_t c32[4] = {0, 0, 0, 0};
   const int64_t T = A.n_tiles, C = A.n_chunks;
   const int64_t rt = (T + kTileRound - 1) / kTileRound, rc = (C + kChunkRound - 1) / kChunkRound;
   const int64_t rounds = rt > rc ? rt : rc;
@@ -244,7 +252,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scans(ScanArgs A, int64_t cap,
     }
     uint32_t nb[NT], h[NT];
     uint64_t s64[2] = {0, 0};
-    uint32_t s32[3] = {0, 0, 0};
+    uint32_t s32[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
       uint32_t f;
@@ -252,24 +260,32 @@ __global__ void __launch_bounds__(kScanBlock) k_scans(ScanArgs A, int64_t cap,
       s64[0] += tc[k];
       s32[0] += nb[k];
       s32[1] += h[k];
+      s32[3] += tc[k] >= kLongTile ? 1u : 0u;
     }
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       s64[1] += cp[k];
       s32[2] += cv[k];
     }
-    block_exscan<2, 3>(s64, s32, c64, c32, w64, w32);
+    block_exscan<2, 4>(s64, s32, c64, c32, w64, w32);
 #pragma unroll
     for (int k = 0; k < kScanVec; ++k) {
       uint32_t ts[4], bs[4], hs[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
+        const int64_t t = it + 4 * k + e;
+        const uint32_t c = tc[4 * k + e];
+        // work order: long tiles from the front, the others from the back
+        // (both positions follow from the long tiles before t)
+        if (t < T)
+          A.order[c >= kLongTile ? s32[3] : (uint32_t)(T - 1 - (t - s32[3]))] = (uint32_t)t;
         ts[e] = (uint32_t)s64[0];
         bs[e] = s32[0];
         hs[e] = s32[1];
-        s64[0] += tc[4 * k + e];
+        s64[0] += c;
         s32[0] += nb[4 * k + e];
         s32[1] += h[4 * k + e];
+        s32[3] += c >= kLongTile ? 1u : 0u;
       }
       store4(A.tstart, it + 4 * k, T, make_uint4(ts[0], ts[1], ts[2], ts[3]));
       store4(A.cnt, it + 4 * k, T, make_uint4(0u, 0u, 0u, 0u));
@@ -701,18 +717,6 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
   }
 }
 
-// Work order of the persistent render kernels: tiles by descending pair
-// count (16-bit saturated), ties in tile order.
-__global__ void __launch_bounds__(256) k_order_keys(const uint32_t* __restrict__ ranges, int T,
-                                                    uint64_t* __restrict__ keys,
-                                                    int32_t* __restrict__ cnt) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0) *cnt = T;
-  if (t >= T) return;
-  const uint32_t c = ranges[2 * (int64_t)t + 1] - ranges[2 * (int64_t)t];
-  keys[t] = (uint64_t)(0xFFFFu - (c > 0xFFFFu ? 0xFFFFu : c));
-}
-
 }  // namespace
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) {
@@ -784,7 +788,8 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
   const uint2* chunk_cnt = ws_at<uint2>(ws, P.off_chunk_cnt);
   uint2* chunk_pre = ws_at<uint2>(ws, P.off_chunk_pre);
   ScanArgs sa{chunk_cnt, chunk_pre, P.n_chunks, tcnt, tstart, (int64_t)T,
-              splat ? ws_at<uint32_t>(ws, P.off_boff) : nullptr, fstart, hstart};
+              splat ? ws_at<uint32_t>(ws, P.off_boff) : nullptr, fstart, hstart,
+              ws_at<uint32_t>(ws, P.off_order)};
   // always launched, so that the flags are always set
   hipLaunchKernelGGL(k_scans, dim3(1), dim3(kScanBlock), 0, s, sa, P.pair_cap, fl);
   uint64_t* skey = ws_at<uint64_t>(ws, P.off_scatter);
@@ -809,24 +814,6 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
                        tcnt, tstart, fl, long_list, skey, out);
   }
   return hipGetLastError();
-}
-
-hipError_t launch_tile_order(const Plan& P, void* ws, hipStream_t s) {
-  const int T = P.vt.total_tiles;
-  if (T == 0) return hipSuccess;
-  char* tmp = ws_at<char>(ws, P.off_order_tmp);
-  uint64_t* ka = reinterpret_cast<uint64_t*>(tmp);
-  uint64_t* kb = ka + T;
-  uint32_t* vb = reinterpret_cast<uint32_t*>(kb + T);
-  int32_t* cnt = reinterpret_cast<int32_t*>(vb + T);
-  uint32_t* order = ws_at<uint32_t>(ws, P.off_order);
-  hipLaunchKernelGGL(k_order_keys, dim3((T + 255) / 256), dim3(256), 0, s,
-                     ws_at<uint32_t>(ws, P.off_ranges), T, ka, cnt);
-  int which = 0;
-  const int64_t nb = (T + kSortTile - 1) / kSortTile;
-  // 16 key bits: two passes, the result lands back in (ka, order)
-  return launch_radix_sort(ka, kb, order, vb, cnt, ws_at<uint32_t>(ws, P.off_hist),
-                           ws_at<uint32_t>(ws, P.off_digit_tot), nb, 16, true, &which, s);
 }
 
 // Sorted pair values (generation indices) after launch_bin_sort.

@@ -85,8 +85,8 @@ struct Plan {
   size_t off_vis_list;                  // visible records in index order
   size_t off_tile_cnt, off_tile_start, off_long;
   size_t off_keys, off_scatter, off_vals, off_pair_rec, off_sorted_rec, off_srec;
-  size_t off_hist, off_digit_tot, off_ranges, off_tile_last, off_tile_loss;
-  size_t off_grad_pair, off_pose_part, off_order, off_order_tmp;
+  size_t off_ranges, off_tile_last, off_tile_loss;
+  size_t off_grad_pair, off_pose_part, off_order;
   size_t off_ssim_maps, off_ssim_part;
   // splat-wise backward: bucket offsets, bucket queues and their per-tile
   // positions, pixel states
