@@ -36,7 +36,10 @@ struct AdamArgs {
   float eps;
   float reg_scale;        // lambda_o / reg_count
   const int32_t* step_dev;
-  const double* bias;       // the iteration advanced *step_dev already: bias corrections
+  // the iteration advanced *step_dev already and stored the factors of the
+  // step; group k of this launch is group group0 + k there
+  const AdamStepFactors* factors;
+  int32_t group0;
   const int32_t* overflow;  // with vis: every gradient is zero after a pair overflow
   // optional: block 0 also reduces the forward's per-tile L1 partials of a
   // one-view iteration into *loss (the loss needs nothing after the forward)
@@ -69,19 +72,26 @@ __global__ void __launch_bounds__(kAdamThreads) k_adam(AdamArgs a) {
   if (a.loss && blockIdx.x == 0)
     loss_reduce_view<kAdamThreads>(a.tile_loss, a.loss_tiles, a.loss_pixels, a.lambda_depth,
                                    a.loss_has_depth, a.loss);
-  double bc1, bc2;
-  if (a.bias) {
-    bc1 = a.bias[0];
-    bc2 = a.bias[1];
+  float step_size, inv_bc2s;
+  int step;
+  if (a.factors) {
+    step = a.factors->step;
+    step_size = a.factors->step_size[a.group0 + gi];
+    inv_bc2s = a.factors->inv_bc2s;
   } else {
-    const int step = a.step_dev ? (*a.step_dev + 1) : a.step;
-    bc1 = 1.0 - pow(a.beta1d, (double)step);
-    bc2 = 1.0 - pow(a.beta2d, (double)step);
+    step = a.step_dev ? (*a.step_dev + 1) : a.step;
+    const double bc1 = 1.0 - pow(a.beta1d, (double)step);
+    const double bc2 = 1.0 - pow(a.beta2d, (double)step);
+    step_size = (float)((double)G.lr / bc1);
+    inv_bc2s = (float)(1.0 / sqrt(bc2));
   }
-  const float step_size = (float)((double)G.lr / bc1);
-  const float inv_bc2s = (float)(1.0 / sqrt(bc2));
-  const int64_t e0 = ((int64_t)blockIdx.x - G.block0) * (kAdamThreads * kAdamVec) +
-                     (int64_t)threadIdx.x * kAdamVec;
+  // Odd steps walk the group's blocks backwards: the part of the state
+  // touched last by the previous step is still in the last-level cache when
+  // this one starts.  The order does not change any value.
+  const int64_t gblocks = (G.n + kAdamThreads * kAdamVec - 1) / (kAdamThreads * kAdamVec);
+  const int64_t lb = (int64_t)blockIdx.x - G.block0;
+  const int64_t wb = (step & 1) ? gblocks - 1 - lb : lb;
+  const int64_t e0 = wb * (kAdamThreads * kAdamVec) + (int64_t)threadIdx.x * kAdamVec;
   if (e0 + kAdamVec <= G.n) {
     // p, m, v first: they do not wait for the visibility lookup
     float4 p = *reinterpret_cast<float4*>(G.p + e0);
@@ -180,7 +190,8 @@ hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, dou
     if (a.reg_scale == 0.0f)
       for (int k = 0; k < ng; ++k) a.grp[k].reg = 0;
     a.step_dev = step_dev;
-    a.bias = (fold && fold->step_taken) ? fold->bias : nullptr;
+    a.factors = (fold && fold->step_taken) ? fold->factors : nullptr;
+    a.group0 = base;
     a.overflow = overflow;
     if (fold && fold->loss && base == 0) {
       a.tile_loss = fold->tile_loss;

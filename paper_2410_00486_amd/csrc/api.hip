@@ -545,7 +545,7 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
   // One view with Adam: the projection backward writes the gradients of the
   // Gaussians with pairs only, and Adam takes the others as zero (no zero
   // fill, no read).  The gradient buffers are left unspecified for those.
-  const bool sparse = it->n_adam_groups > 0 && it->n_adam_groups <= 16 && P.vt.n_views == 1 &&
+  const bool sparse = it->n_adam_groups > 0 && it->n_adam_groups <= kAdamFoldGroups && P.vt.n_views == 1 &&
                       !(P.cfg.flags & GS_ACCUMULATE_GRADS) && P.n > 0;
   if (!sparse) {
     gs_status st = gs_preprocess(it->plan, &it->gaussians, it->cams_dev, it->ws, stream);
@@ -609,9 +609,16 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
   // fewer per iteration, same values.
   AdamFold fold{};
   fold.step_taken = it->step_dev != nullptr;
-  double* bias = reinterpret_cast<double*>(ws_at<char>(it->ws, P.off_flags) + kBiasOffset);
-  fold.bias = bias;
-  const StepAdvance adv{it->step_dev, it->beta1, it->beta2, bias};
+  AdamStepFactors* factors =
+      reinterpret_cast<AdamStepFactors*>(ws_at<char>(it->ws, P.off_flags) + kBiasOffset);
+  fold.factors = factors;
+  StepAdvance adv{};
+  adv.step = it->step_dev;
+  adv.beta1 = it->beta1;
+  adv.beta2 = it->beta2;
+  adv.out = factors;
+  adv.n_groups = it->n_adam_groups;
+  for (int k = 0; k < it->n_adam_groups; ++k) adv.lr[k] = it->adam_groups[k].lr;
   const bool fold_loss = !ssim && it->target_rgb && adam_elems > 0;
   if (fold_loss) {
     const ViewInfo& vi = P.vt.v[0];

@@ -31,8 +31,8 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t cou
 __global__ void k_set_i32(int32_t* __restrict__ p, int32_t value) { *p = value; }
 
 // Clears a[0, na) and b[0, nb); with a step counter, also advances it (the
-// Adam step of a whole iteration, taken at its start) and stores the bias
-// corrections 1 - beta1^t, 1 - beta2^t of the new step t for the Adam launch.
+// Adam step of a whole iteration, taken at its start) and stores the
+// step-dependent Adam factors of the new step t for the Adam launch.
 __global__ void k_fill2_u32(uint32_t* __restrict__ a, int64_t na, uint32_t* __restrict__ b,
                             int64_t nb, StepAdvance st) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -41,8 +41,14 @@ __global__ void k_fill2_u32(uint32_t* __restrict__ a, int64_t na, uint32_t* __re
   if (st.step && i == 0) {
     const int32_t t = *st.step + 1;
     *st.step = t;
-    st.bias[0] = 1.0 - pow(st.beta1, (double)t);
-    st.bias[1] = 1.0 - pow(st.beta2, (double)t);
+    AdamStepFactors* f = st.out;
+    const double bc1 = 1.0 - pow(st.beta1, (double)t);
+    const double bc2 = 1.0 - pow(st.beta2, (double)t);
+    f->bc1 = bc1;
+    f->bc2 = bc2;
+    f->inv_bc2s = (float)(1.0 / sqrt(bc2));
+    f->step = t;
+    for (int g = 0; g < st.n_groups; ++g) f->step_size[g] = (float)((double)st.lr[g] / bc1);
   }
 }
 
@@ -771,7 +777,7 @@ hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s, const S
   hipLaunchKernelGGL(k_fill2_u32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
                      ws_at<uint32_t>(ws, P.off_flags), (int64_t)11,
                      ws_at<uint32_t>(ws, P.off_tile_cnt), T,
-                     step ? *step : StepAdvance{nullptr, 0.0, 0.0, nullptr});
+                     step ? *step : StepAdvance{});
   return hipGetLastError();
 }
 

@@ -203,24 +203,36 @@ __device__ __forceinline__ void loss_reduce_view(const float2* __restrict__ tl, 
   }
 }
 
-// The Adam step counter advanced by the first launch of an iteration, with
-// the bias corrections of the new step stored at `bias` (two doubles inside
-// the workspace's flag block, at kBiasOffset).
+// Step-dependent Adam factors of an iteration, computed once by its first
+// launch (which also advances the device step counter): the bias
+// corrections 1 - beta^t, 1/sqrt(1 - beta2^t) and lr_g / (1 - beta1^t) per
+// parameter group, with the formulas the Adam kernel uses otherwise, so the
+// values are the same bits.  Lives in the workspace's flag block.
+constexpr int kAdamFoldGroups = 16;
+struct AdamStepFactors {
+  double bc1, bc2;
+  float inv_bc2s;
+  int32_t step;
+  float step_size[kAdamFoldGroups];
+};
 struct StepAdvance {
   int32_t* step;
   double beta1, beta2;
-  double* bias;
+  AdamStepFactors* out;
+  int32_t n_groups;
+  float lr[kAdamFoldGroups];
 };
 constexpr size_t kBiasOffset = 128;  // bytes from the flags (F_COUNT int32 before it)
-static_assert(kBiasOffset >= F_COUNT * 4 && kBiasOffset + 16 <= F_COUNT * 16, "flag block");
+static_assert(kBiasOffset >= F_COUNT * 4 && kBiasOffset + sizeof(AdamStepFactors) <= F_COUNT * 16,
+              "flag block");
 
 // Work of a whole iteration that rides on the Adam launch: the step counter
-// advanced at the iteration's start (Adam then reads the bias corrections
-// stored then), and the reduction of a one-view forward's per-tile L1
-// partials into *loss.
+// advanced at the iteration's start (Adam then reads the factors stored
+// then), and the reduction of a one-view forward's per-tile L1 partials into
+// *loss.
 struct AdamFold {
   bool step_taken;
-  const double* bias;
+  const AdamStepFactors* factors;
   const float2* tile_loss;
   int32_t loss_tiles, loss_has_depth;
   double loss_pixels;
