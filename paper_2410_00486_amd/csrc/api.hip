@@ -9,12 +9,13 @@
 #include <string>
 #include <vector>
 
-#include "gs_internal.h"
+#include "tilesort.h"
 
 namespace gs {
 hipError_t launch_preprocess(const Plan& P, const gs_gaussians& g, const float* cams, void* ws,
                              hipStream_t s);
-hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s);
+hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_short_sorts = false);
+TileSortArgs tile_sort_args(const Plan& P, void* ws);
 hipError_t launch_radix_sort(uint64_t* keys0, uint64_t* keys1, uint32_t* vals0, uint32_t* vals1,
                              const int32_t* cnt, uint32_t* hist, uint32_t* digit_tot,
                              int64_t nb_cap, int key_bits, bool iota, int* which, hipStream_t s);
@@ -26,7 +27,7 @@ hipError_t launch_render_fwd(const Plan& P, void* ws, const float* cams, float* 
                              float* depth, float* T_final, uint32_t* last,
                              const float* target_rgb, const float* target_depth,
                              float* loss_per_view, const uint32_t* order, int32_t* queue,
-                             int grid, hipStream_t s);
+                             int grid, hipStream_t s, const TileSortArgs& sort = TileSortArgs{});
 hipError_t launch_render_bwd(const Plan& P, void* ws, const float* cams, const float* color,
                              const float* depth, const float* T_final, const uint32_t* last,
                              const float* dL_dcolor, const float* dL_ddepth,
@@ -632,16 +633,19 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
   st = preprocess_enqueue(it->plan, &it->gaussians, it->cams_dev, it->ws, s,
                           it->step_dev ? &adv : nullptr);
   if (st != GS_OK) return st;
-  st = gs_bin_sort(it->plan, it->ws, stream);
-  if (st != GS_OK) return st;
+  // the binning leaves the short lists to the forward, which sorts each
+  // tile's list right before compositing it (one launch fewer; the sort's
+  // memory latency hides behind other wavefronts' compositing)
+  hipError_t e = launch_bin_sort(P, it->ws, s, true);
+  if (e != hipSuccess) return hip_check(e, "gs_iteration_enqueue (binning)");
   const bool pers = (P.cfg.flags & GS_PERSISTENT) != 0;
   int32_t* fl = ws_at<int32_t>(it->ws, P.off_flags);
-  hipError_t e = launch_render_fwd(
+  e = launch_render_fwd(
       P, it->ws, it->cams_dev, it->color, it->depth, it->T_final, it->last,
       ssim ? nullptr : it->target_rgb, ssim ? nullptr : it->target_depth,
       (ssim || fold_loss) ? nullptr : it->loss_per_view,
       ws_at<uint32_t>(it->ws, P.off_order), pers ? fl + F_QUEUE_FWD : nullptr,
-      pers ? persistent_grid(P, false) : P.vt.total_tiles, s);
+      pers ? persistent_grid(P, false) : P.vt.total_tiles, s, tile_sort_args(P, it->ws));
   if (e != hipSuccess) return hip_check(e, "gs_iteration_enqueue (forward)");
   const float* gC = it->dL_dcolor;
   const float* gD = it->dL_ddepth;

@@ -18,7 +18,7 @@
 // with long lists first.  The general stable LSD
 // radix sort (8-bit digits, wave64 ballot ranking) below serves the
 // standalone key/value sort.
-#include "gs_internal.h"
+#include "tilesort.h"
 
 namespace gs {
 namespace {
@@ -73,17 +73,6 @@ constexpr int kScanVec = 2;       // uint4 loads per thread and array in a round
 constexpr int64_t kTileRound = (int64_t)kScanBlock * 4 * kScanVec;
 constexpr int64_t kChunkRound = (int64_t)kScanBlock * 2 * kScanVec;
 
-// Splits a tile of c pairs into buckets of 64 positions: all but possibly
-// the last hold more than 32 pairs (full); a last bucket with at most 32
-// pairs is a half bucket.
-__device__ __forceinline__ void bucket_split(uint32_t c, uint32_t& nb, uint32_t& full,
-                                             uint32_t& half) {
-  nb = (c + kBucket - 1) / kBucket;
-  const uint32_t r = c - (nb > 0 ? (nb - 1) * kBucket : 0u);  // pairs of the last bucket
-  half = (c > 0 && r <= 32) ? 1u : 0u;
-  full = nb - half;
-}
-
 struct ScanArgs {
   const uint2* chunk_cnt;  // (pairs, visible records) per chunk
   uint2* chunk_pre;        // (generation offset, visible-list position) per chunk
@@ -95,6 +84,7 @@ struct ScanArgs {
   uint32_t* fstart;        // position of the tile's first full bucket in queue 0
   uint32_t* hstart;        // position of the tile's half bucket in queue 1
   uint32_t* order;         // work order of the render kernels, longest tiles first
+  uint32_t* long_list;     // tiles whose lists go to the long-list sort
 };
 
 // Work order of the render kernels: tiles with at least kLongTile pairs
@@ -238,6 +228,9 @@ __global__ void __launch_bounds__(kScanBlock) k_scans(ScanArgs A, int64_t cap,
   // visible records (full buckets = buckets - half buckets), long tiles
   __shared__ uint64_t w64[2 * (NW + 1)];
   __shared__ uint32_t w32[4 * (NW + 1)];
+  __shared__ uint32_t n_long;
+  if (threadIdx.x == 0) n_long = 0u;
+  __syncthreads();
   uint64_t c64[2] = {0, 0};
   uint32_t c32[4] = {0, 0, 0, 0};
   const int64_t T = A.n_tiles, C = A.n_chunks;
@@ -285,6 +278,8 @@ __global__ void __launch_bounds__(kScanBlock) k_scans(ScanArgs A, int64_t cap,
         // (both positions follow from the long tiles before t)
         if (t < T)
           A.order[c >= kLongTile ? s32[3] : (uint32_t)(T - 1 - (t - s32[3]))] = (uint32_t)t;
+        // lists too long for one wavefront (rare): listed for the long-list sort
+        if (t < T && c > kTileSortSmall) A.long_list[atomicAdd(&n_long, 1u)] = (uint32_t)t;
         ts[e] = (uint32_t)s64[0];
         bs[e] = s32[0];
         hs[e] = s32[1];
@@ -308,6 +303,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scans(ScanArgs A, int64_t cap,
       s32[2] = v1 + cv[2 * k + 1];
     }
   }
+  __syncthreads();  // n_long complete
   if (threadIdx.x != 0) return;
   // Both pair totals count the same pairs; a mismatch is reported as an
   // overflow so that nothing is scattered.
@@ -317,9 +313,9 @@ __global__ void __launch_bounds__(kScanBlock) k_scans(ScanArgs A, int64_t cap,
   fl[F_PAIRS] = over ? 0 : (int32_t)tile_pairs;
   fl[F_PAIRS_WANTED] = tile_pairs > 0x7FFFFFFFull ? 0x7FFFFFFF : (int32_t)tile_pairs;
   fl[F_VISIBLE] = (int32_t)c32[2];
-  // long lists are queued by the tile sort that follows; the bucket queues
-  // are filled there at the positions scanned here
-  fl[F_LONG_TILES] = 0;
+  // the bucket queues are filled by the tile sort at the positions scanned
+  // here; the long lists are sorted by their own kernel (none on overflow)
+  fl[F_LONG_TILES] = (int32_t)n_long;
   const bool splat = A.boff != nullptr;
   fl[F_BQ_FULL] = (over || !splat) ? 0 : (int32_t)(c32[0] - c32[1]);
   fl[F_BQ_HALF] = (over || !splat) ? 0 : (int32_t)c32[1];
@@ -406,123 +402,11 @@ __global__ void __launch_bounds__(256) k_scatter(
 }
 
 // ---------------------------------------------------------------- tile sort
-// Output per tile: sorted keys (tile << 32 | depth bits), generation
-// indices, record ids, the [start, end) range ((0, 0) when empty) and, for
-// the splat-wise backward, the absolute bucket offset.  Keys are unique, so
-// any correct sort gives the same lists.  k_tile_sort (one wavefront per
-// tile) sorts lists up to 64 keys in registers (rank = number of smaller
-// keys) and up to kTileSortSmall keys with a bitonic network in LDS, and
-// queues longer lists; k_tile_sort_long (1024-thread blocks, grid-stride
-// over the queue) sorts them with the same network in LDS up to
-// kTileSortLong keys and in place in global memory beyond.
-//
-// The network keeps every merge ascending (the first compare of a merge
-// pairs i with its mirror in the block), so positions past the list end
-// act as +infinity and are never touched: no padding is written.
-constexpr uint32_t kTileSortSmall = 512;
-constexpr uint32_t kTileSortLong = 16384;
-constexpr int kLongThreads = 1024;
+// (per-tile sort helpers in tilesort.h)
 
-struct TileSortOut {
-  uint64_t* keys;
-  uint32_t* vals;
-  uint32_t* sorted_rec;
-  const uint32_t* pair_rec;
-  const Rec* rec;
-  Rec* lrec;  // records in list order, read contiguously by the render kernels
-};
-
-__device__ __forceinline__ void emit_sorted(const TileSortOut& o, uint32_t pos, uint64_t tkey,
-                                            uint64_t key) {
-  const uint32_t g = (uint32_t)key;
-  const uint32_t r = o.pair_rec[g];
-  o.keys[pos] = tkey | (key >> 32);
-  o.vals[pos] = g;
-  o.sorted_rec[pos] = r;
-  const float4* src = reinterpret_cast<const float4*>(o.rec + r);
-  float4* dst = reinterpret_cast<float4*>(o.lrec + pos);
-  const float4 a0 = src[0], a1 = src[1], a2 = src[2], a3 = src[3];
-  dst[0] = a0; dst[1] = a1; dst[2] = a2; dst[3] = a3;
-}
-
-__device__ __forceinline__ void cmp_swap(uint64_t* k, uint32_t a, uint32_t b, uint32_t n) {
-  if (b >= n) return;
-  const uint64_t ka = k[a], kb = k[b];
-  if (ka > kb) {
-    k[a] = kb;
-    k[b] = ka;
-  }
-}
-
-// Sorts k[0, n) ascending (LDS or global memory) with nthreads threads of
-// the block; every thread of the block must call it.
-__device__ void bitonic_sort(uint64_t* k, uint32_t n, uint32_t tid, uint32_t nthreads) {
-  uint32_t m = 1;
-  while (m < n) m <<= 1;
-  for (uint32_t size = 2; size <= m; size <<= 1) {
-    const uint32_t half = size >> 1;
-    for (uint32_t idx = tid; idx < m / 2; idx += nthreads) {
-      const uint32_t blk = idx / half, off = idx % half;
-      cmp_swap(k, blk * size + off, blk * size + size - 1 - off, n);
-    }
-    __syncthreads();
-    for (uint32_t stride = size >> 2; stride > 0; stride >>= 1) {
-      for (uint32_t idx = tid; idx < m / 2; idx += nthreads) {
-        const uint32_t a = 2 * idx - (idx & (stride - 1));
-        cmp_swap(k, a, a + stride, n);
-      }
-      __syncthreads();
-    }
-  }
-}
-
-__global__ void __launch_bounds__(kWave) k_tile_sort(
-    const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ tstart, int T,
-    int32_t* __restrict__ fl, const uint64_t* __restrict__ skey, TileSortOut out,
-    uint32_t* __restrict__ ranges, uint32_t* __restrict__ long_list,
-    const uint32_t* __restrict__ fstart, const uint32_t* __restrict__ hstart,
-    uint2* __restrict__ bq, int64_t bq_stride) {
+__global__ void __launch_bounds__(kWave) k_tile_sort(TileSortArgs A) {
   __shared__ uint64_t sk[kTileSortSmall];
-  const int t = blockIdx.x;
-  const int lane = threadIdx.x;
-  const uint64_t P = (uint64_t)fl[F_PAIRS];
-  const uint32_t n = fl[F_OVERFLOW] ? 0u : cnt[t];
-  const uint64_t start64 = tstart[t];
-  const bool ok = n > 0 && start64 + n <= P;
-  if (lane == 0) {
-    ranges[2 * (int64_t)t] = ok ? (uint32_t)start64 : 0u;
-    ranges[2 * (int64_t)t + 1] = ok ? (uint32_t)(start64 + n) : 0u;
-    if (ok && n > kTileSortSmall) long_list[atomicAdd(&fl[F_LONG_TILES], 1)] = (uint32_t)t;
-  }
-  if (bq && ok) {
-    // splat-wise work queues at the scanned positions: the tile's buckets
-    // 0 .. full-1 have more than 32 pairs; a last bucket with at most 32
-    // goes to the second queue
-    uint32_t nb, full, half;
-    bucket_split(n, nb, full, half);
-    const uint32_t f0 = fstart[t];
-    for (uint32_t k = lane; k < full; k += kWave) bq[f0 + k] = make_uint2((uint32_t)t, k);
-    if (half && lane == 0) bq[bq_stride + hstart[t]] = make_uint2((uint32_t)t, nb - 1);
-  }
-  if (!ok || n > kTileSortSmall) return;
-  const uint32_t start = (uint32_t)start64;
-  const uint64_t tkey = (uint64_t)(uint32_t)t << 32;
-  if (n <= (uint32_t)kWave) {
-    const bool has = (uint32_t)lane < n;
-    const uint64_t key = has ? skey[start + lane] : ~0ull;
-    uint32_t rank = 0;
-    for (uint32_t j = 0; j < n; ++j) {
-      const uint64_t kj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(key >> 32), j) << 32) |
-                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, j);
-      rank += kj < key ? 1u : 0u;
-    }
-    if (has) emit_sorted(out, start + rank, tkey, key);
-    return;
-  }
-  for (uint32_t k = lane; k < n; k += kWave) sk[k] = skey[start + k];
-  __syncthreads();
-  bitonic_sort(sk, n, lane, kWave);
-  for (uint32_t k = lane; k < n; k += kWave) emit_sorted(out, start + k, tkey, sk[k]);
+  (void)sort_tile_wave(A, blockIdx.x, threadIdx.x, sk);
 }
 
 __global__ void __launch_bounds__(kLongThreads) k_tile_sort_long(
@@ -530,7 +414,7 @@ __global__ void __launch_bounds__(kLongThreads) k_tile_sort_long(
     const int32_t* __restrict__ fl, const uint32_t* __restrict__ long_list,
     uint64_t* __restrict__ skey, TileSortOut out) {
   __shared__ uint64_t sk[kTileSortLong];
-  const int n_long = fl[F_LONG_TILES];
+  const int n_long = fl[F_OVERFLOW] ? 0 : fl[F_LONG_TILES];
   for (int li = blockIdx.x; li < n_long; li += gridDim.x) {
     const int t = (int)long_list[li];
     const uint32_t n = cnt[t];
@@ -781,7 +665,30 @@ hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s, const S
   return hipGetLastError();
 }
 
-hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
+// Arguments of the per-tile sort (k_tile_sort, or the forward of a whole
+// iteration, which sorts its tiles itself).
+TileSortArgs tile_sort_args(const Plan& P, void* ws) {
+  const bool splat = (P.cfg.flags & GS_SPLAT_BWD) != 0;
+  TileSortArgs A{};
+  A.cnt = ws_at<uint32_t>(ws, P.off_tile_cnt);
+  A.tstart = ws_at<uint32_t>(ws, P.off_tile_start);
+  A.fl = ws_at<int32_t>(ws, P.off_flags);
+  A.skey = ws_at<uint64_t>(ws, P.off_scatter);
+  A.out = TileSortOut{ws_at<uint64_t>(ws, P.off_keys), ws_at<uint32_t>(ws, P.off_vals),
+                      ws_at<uint32_t>(ws, P.off_sorted_rec), ws_at<uint32_t>(ws, P.off_pair_rec),
+                      ws_at<Rec>(ws, P.off_rec), ws_at<Rec>(ws, P.off_srec)};
+  A.ranges = ws_at<uint32_t>(ws, P.off_ranges);
+  A.fstart = splat ? ws_at<uint32_t>(ws, P.off_full_start) : nullptr;
+  A.hstart = splat ? ws_at<uint32_t>(ws, P.off_half_start) : nullptr;
+  A.bq = splat ? ws_at<uint2>(ws, P.off_bq) : nullptr;
+  A.bq_stride = P.ckpt_slots;
+  return A;
+}
+
+// defer_short_sorts: the lists of at most kTileSortSmall pairs are left to
+// the forward (a whole iteration), which sorts each tile before compositing
+// it; the long lists are sorted here in either case.
+hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_short_sorts) {
   int32_t* fl = ws_at<int32_t>(ws, P.off_flags);
   uint32_t* tt = ws_at<uint32_t>(ws, P.off_tt);
   uint32_t* poff = ws_at<uint32_t>(ws, P.off_poff);
@@ -793,9 +700,10 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
   uint32_t* hstart = splat ? ws_at<uint32_t>(ws, P.off_half_start) : nullptr;
   const uint2* chunk_cnt = ws_at<uint2>(ws, P.off_chunk_cnt);
   uint2* chunk_pre = ws_at<uint2>(ws, P.off_chunk_pre);
+  uint32_t* long_list = ws_at<uint32_t>(ws, P.off_long);
   ScanArgs sa{chunk_cnt, chunk_pre, P.n_chunks, tcnt, tstart, (int64_t)T,
               splat ? ws_at<uint32_t>(ws, P.off_boff) : nullptr, fstart, hstart,
-              ws_at<uint32_t>(ws, P.off_order)};
+              ws_at<uint32_t>(ws, P.off_order), long_list};
   // always launched, so that the flags are always set
   hipLaunchKernelGGL(k_scans, dim3(1), dim3(kScanBlock), 0, s, sa, P.pair_cap, fl);
   uint64_t* skey = ws_at<uint64_t>(ws, P.off_scatter);
@@ -808,16 +716,11 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s) {
                        ws_at<uint32_t>(ws, P.off_vis_list));
   }
   if (T > 0) {
-    TileSortOut out{ws_at<uint64_t>(ws, P.off_keys), ws_at<uint32_t>(ws, P.off_vals),
-                    ws_at<uint32_t>(ws, P.off_sorted_rec), pair_rec, ws_at<Rec>(ws, P.off_rec),
-                    ws_at<Rec>(ws, P.off_srec)};
-    uint32_t* long_list = ws_at<uint32_t>(ws, P.off_long);
-    hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)T), dim3(kWave), 0, s, tcnt, tstart, T, fl, skey,
-                       out, ws_at<uint32_t>(ws, P.off_ranges), long_list, fstart, hstart,
-                       splat ? ws_at<uint2>(ws, P.off_bq) : nullptr, P.ckpt_slots);
+    const TileSortArgs A = tile_sort_args(P, ws);
+    if (!defer_short_sorts) hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)T), dim3(kWave), 0, s, A);
     const int long_grid = (int)std::min<int64_t>(T, 256);
     hipLaunchKernelGGL(k_tile_sort_long, dim3((unsigned)long_grid), dim3(kLongThreads), 0, s,
-                       tcnt, tstart, fl, long_list, skey, out);
+                       tcnt, tstart, fl, long_list, skey, A.out);
   }
   return hipGetLastError();
 }

@@ -18,7 +18,7 @@
 // Gaussian are summed over the lane's pixels, then over the wavefront with
 // DPP (skipped when no lane contributes), and written to the pair's own
 // slot: no atomics, deterministic.
-#include "gs_internal.h"
+#include "tilesort.h"
 
 namespace gs {
 namespace {
@@ -126,15 +126,29 @@ __device__ __forceinline__ int find_view(const ViewTable& vt, int gtile) {
 }
 
 // Records of a tile list are stored in list order (written by the
-// binning), so a batch is one contiguous, coalesced read.
+// binning), so a batch is one contiguous, coalesced read.  fresh: the
+// records were written by this wavefront in this kernel, so they are read
+// at device scope, past the vector L1 (which may hold an older copy of the
+// line, loaded for a neighbouring tile).
 __device__ __forceinline__ void stage(Rec* srec, uint32_t* sval, const Rec* __restrict__ lrec,
                                       const uint32_t* __restrict__ sorted_vals, uint32_t first,
-                                      int count, int lane) {
+                                      int count, int lane, bool fresh = false) {
   for (int k = lane; k < count; k += kWave) {
-    const float4* src = reinterpret_cast<const float4*>(lrec + first + k);
-    float4* dst = reinterpret_cast<float4*>(srec + k);
-    const float4 a0 = src[0], a1 = src[1], a2 = src[2], a3 = src[3];
-    dst[0] = a0; dst[1] = a1; dst[2] = a2; dst[3] = a3;
+    uint64_t* dst = reinterpret_cast<uint64_t*>(srec + k);
+    if (fresh) {
+      const uint64_t* src = reinterpret_cast<const uint64_t*>(lrec + first + k);
+      uint64_t w[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        w[q] = __hip_atomic_load(src + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) dst[q] = w[q];
+    } else {
+      const float4* src = reinterpret_cast<const float4*>(lrec + first + k);
+      float4* d4 = reinterpret_cast<float4*>(dst);
+      const float4 a0 = src[0], a1 = src[1], a2 = src[2], a3 = src[3];
+      d4[0] = a0; d4[1] = a1; d4[2] = a2; d4[3] = a3;
+    }
     if (sval) sval[k] = sorted_vals[first + k];
   }
 }
@@ -152,7 +166,8 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec
                                          const float* __restrict__ target_depth,
                                          float* __restrict__ tile_loss,
                                          const uint32_t* __restrict__ boff,
-                                         float* __restrict__ ckpt, Rec* srec) {
+                                         float* __restrict__ ckpt, Rec* srec,
+                                         const TileList* known = nullptr) {
   using TG = Tile<TW, TH>;
   constexpr int PPL = TG::PPL;
   constexpr int NPX = TG::NPX;
@@ -161,7 +176,11 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec
   const int lt = gtile - vi.tile_off;
   const int tx0 = (lt % vi.tiles_x) * TW, ty0 = (lt / vi.tiles_x) * TH;
   const int lane = threadIdx.x;
-  const uint32_t s = ranges[2 * (int64_t)gtile], e = ranges[2 * (int64_t)gtile + 1];
+  // the list: from the binning's ranges, or from this wavefront's own sort
+  // (range in registers, records possibly staged already)
+  const uint32_t s = known ? known->start : ranges[2 * (int64_t)gtile];
+  const uint32_t e = known ? known->end : ranges[2 * (int64_t)gtile + 1];
+  const bool fresh = known && known->fresh, staged = known && known->staged;
 
   double sx[PPL], sy[PPL];
   float T[PPL], c0[PPL], c1[PPL], c2[PPL], D[PPL];
@@ -188,9 +207,11 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec
   for (uint32_t b = s; more && b < e; b += (uint32_t)B) {
     if (ballot64(active()) == 0) break;
     const int nb = (int)min((uint32_t)B, e - b);
-    __syncthreads();
-    stage(srec, nullptr, lrec, nullptr, b, nb, lane);
-    __syncthreads();
+    if (!(staged && b == s)) {  // a staged list fits the first batch
+      __syncthreads();
+      stage(srec, nullptr, lrec, nullptr, b, nb, lane, fresh);
+      __syncthreads();
+    }
     // segments between the 64-position bucket boundaries of the list, so
     // that the pixel states are stored outside the per-splat loop
     for (int j = 0; more && j < nb;) {
@@ -313,13 +334,29 @@ __global__ void __launch_bounds__(kWave) k_render_fwd(
     const float* __restrict__ target_rgb, const float* __restrict__ target_depth,
     float* __restrict__ tile_loss, const uint32_t* __restrict__ order,
     int32_t* __restrict__ queue, int chunk, const uint32_t* __restrict__ boff,
-    float* __restrict__ ckpt) {
+    float* __restrict__ ckpt, TileSortArgs sort) {
   extern __shared__ __align__(16) unsigned char smem[];
   Rec* srec = reinterpret_cast<Rec*>(smem);
-  if (queue == nullptr) {
-    const int g = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
+  // With sort.cnt set (a whole iteration), the wavefront first sorts its
+  // tile's list (lists of at most kTileSortSmall pairs; longer ones are
+  // sorted already), in the same LDS; the barrier makes the sorted records
+  // and the range visible to every lane before the compositing reads them.
+  auto tile = [&](int g) {
+    if (sort.cnt) {
+      // a list of at most min(64, B) pairs is staged by the sort itself
+      const TileList L = sort_tile_wave(sort, g, (int)threadIdx.x,
+                                        reinterpret_cast<uint64_t*>(smem), srec, B);
+      __syncthreads();
+      fwd_tile<TW, TH, CKPT>(g, lrec, ranges, cams, vt, B, color, depth, T_final, last,
+                             tile_last, target_rgb, target_depth, tile_loss, boff, ckpt, srec,
+                             &L);
+      return;
+    }
     fwd_tile<TW, TH, CKPT>(g, lrec, ranges, cams, vt, B, color, depth, T_final, last,
                            tile_last, target_rgb, target_depth, tile_loss, boff, ckpt, srec);
+  };
+  if (queue == nullptr) {
+    tile(order ? (int)order[blockIdx.x] : (int)blockIdx.x);
     return;
   }
   // persistent: chunks of `chunk` tiles of the work order, taken with a
@@ -330,10 +367,8 @@ __global__ void __launch_bounds__(kWave) k_render_fwd(
     const int first = item * chunk;
     const int lastt = min(vt.total_tiles, first + chunk);
     for (int k = first; k < lastt; ++k) {
-      const int g = order ? (int)order[k] : k;
-      fwd_tile<TW, TH, CKPT>(g, lrec, ranges, cams, vt, B, color, depth, T_final,
-                             last, tile_last, target_rgb, target_depth, tile_loss, boff, ckpt,
-                             srec);
+      __syncthreads();  // the LDS of the previous tile is reused
+      tile(order ? (int)order[k] : k);
     }
   }
 }
@@ -772,23 +807,24 @@ template <int TW, int TH>
 hipError_t fwd_launch(const Plan& P, void* ws, const float* cams, float* color, float* depth,
                       float* T_final, uint32_t* last, const float* target_rgb,
                       const float* target_depth, const uint32_t* order, int32_t* queue,
-                      int grid, hipStream_t s) {
+                      int grid, const TileSortArgs& sort, hipStream_t s) {
   const int B = P.cfg.lds_batch;
-  const size_t lds = (size_t)B * sizeof(Rec);
+  const size_t lds = std::max((size_t)B * sizeof(Rec),
+                              sort.cnt ? (size_t)kTileSortSmall * sizeof(uint64_t) : (size_t)0);
   if (P.cfg.flags & GS_SPLAT_BWD) {
     hipLaunchKernelGGL((k_render_fwd<TW, TH, true>), dim3(grid), dim3(kWave), lds, s,
                        ws_at<Rec>(ws, P.off_srec),
                        ws_at<uint32_t>(ws, P.off_ranges), cams, P.vt, B, color, depth, T_final,
                        last, ws_at<uint32_t>(ws, P.off_tile_last), target_rgb, target_depth,
                        ws_at<float>(ws, P.off_tile_loss), order, queue, P.cfg.chunk,
-                       ws_at<uint32_t>(ws, P.off_boff), ws_at<float>(ws, P.off_ckpt));
+                       ws_at<uint32_t>(ws, P.off_boff), ws_at<float>(ws, P.off_ckpt), sort);
   } else {
     hipLaunchKernelGGL((k_render_fwd<TW, TH, false>), dim3(grid), dim3(kWave), lds, s,
                        ws_at<Rec>(ws, P.off_srec),
                        ws_at<uint32_t>(ws, P.off_ranges), cams, P.vt, B, color, depth, T_final,
                        last, ws_at<uint32_t>(ws, P.off_tile_last), target_rgb, target_depth,
                        ws_at<float>(ws, P.off_tile_loss), order, queue, P.cfg.chunk,
-                       nullptr, nullptr);
+                       nullptr, nullptr, sort);
   }
   return hipGetLastError();
 }
@@ -838,20 +874,22 @@ int splat_blocks_per_cu(const Plan& P) {
   return occupancy(k_render_bwd_splat<8, 8>, 0);
 }
 
+// sort (optional, cnt non-null): the forward sorts each tile's short list
+// itself (a whole iteration whose binning deferred those sorts).
 hipError_t launch_render_fwd(const Plan& P, void* ws, const float* cams, float* color,
                              float* depth, float* T_final, uint32_t* last,
                              const float* target_rgb, const float* target_depth,
                              float* loss_per_view, const uint32_t* order, int32_t* queue,
-                             int grid, hipStream_t s) {
+                             int grid, hipStream_t s, const TileSortArgs& sort) {
   if (P.vt.total_tiles == 0) return hipSuccess;
   hipError_t e;
   const int tw = P.cfg.tile_w, th = P.cfg.tile_h;
   if (tw == 16 && th == 16)
-    e = fwd_launch<16, 16>(P, ws, cams, color, depth, T_final, last, target_rgb, target_depth, order, queue, grid, s);
+    e = fwd_launch<16, 16>(P, ws, cams, color, depth, T_final, last, target_rgb, target_depth, order, queue, grid, sort, s);
   else if (tw == 16 && th == 8)
-    e = fwd_launch<16, 8>(P, ws, cams, color, depth, T_final, last, target_rgb, target_depth, order, queue, grid, s);
+    e = fwd_launch<16, 8>(P, ws, cams, color, depth, T_final, last, target_rgb, target_depth, order, queue, grid, sort, s);
   else
-    e = fwd_launch<8, 8>(P, ws, cams, color, depth, T_final, last, target_rgb, target_depth, order, queue, grid, s);
+    e = fwd_launch<8, 8>(P, ws, cams, color, depth, T_final, last, target_rgb, target_depth, order, queue, grid, sort, s);
   if (e != hipSuccess) return e;
   if (target_rgb && loss_per_view) {
     hipLaunchKernelGGL(k_loss_reduce, dim3(P.vt.n_views), dim3(kLossThreads), 0, s,

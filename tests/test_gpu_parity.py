@@ -441,6 +441,93 @@ def test_iteration_sparse_adam_equals_separate_calls(lambda_o, degree):
     assert int(it.step_dev.item()) == 2
 
 
+@pytest.mark.parametrize("n,extra", [(300, 0), (3000, 0), (300, L.GS_SPLAT_BWD), (3000, L.GS_SPLAT_BWD)])
+def test_iteration_sorting_in_forward_equals_separate_calls(n, extra):
+    """A whole iteration lets the forward sort each tile's list (up to 512
+    pairs; longer lists by the long-list kernel before it).  Against the
+    separate calls, whose binning sorts every list itself: the sorted lists,
+    the images, the loss and the Adam step bit for bit, on a view with lists
+    of n pairs over a few tiles and short lists elsewhere."""
+    w = scenes.crowded_scene(3, n=n)
+    cam = w.cameras[0]
+    sc = w.scene
+    print(f"iteration sorting in forward n {n} flags {extra}", flush=True)
+    lrs = {"means": 1e-3, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
+    rng = np.random.default_rng(11)
+    tgt = t32(rng.uniform(0.0, 1.0, (3, cam.height, cam.width)).reshape(-1))
+    cams = gsr.cameras_tensor([cam], DEV)
+    g1 = gsr.Gaussians.from_scene(sc, DEV)
+    cap = gsr.required_pairs(*g1.tensors(), cams, [(cam.width, cam.height)], sc.sh_degree, (16, 16)) + 7
+    plan = gsr.Plan(sc.n, sc.sh_degree, [(cam.width, cam.height)], flags=L.GS_FUSED_L1 | extra,
+                    pair_capacity=cap)
+    it = gsr.Iteration(plan, g1, cams, target_rgb=tgt, adam_lrs=lrs)
+    it.enqueue()
+    g2 = gsr.Gaussians.from_scene(sc, DEV)
+    ws = plan.new_workspace(DEV)
+    fr = gsr.Frame(plan, DEV)
+    grads, m, v = g2.zeros_like(), g2.zeros_like(), g2.zeros_like()
+    gsr.preprocess(plan, ws, g2, cams)
+    gsr.bin_sort(plan, ws)
+    gsr.render_fwd(plan, ws, cams, fr, tgt)
+    gsr.render_bwd(plan, ws, g2, cams, fr, grads, target_rgb=tgt)
+    gsr.adam_step(gsr.adam_groups(g2, grads, m, v, lrs, False), 1)
+    torch.cuda.synchronize()
+    fl = plan.flags_of(ws)
+    P = int(fl[L.F_PAIRS])
+    assert fl[L.F_OVERFLOW] == 0 and int(plan.flags_of(it.ws)[L.F_PAIRS]) == P
+    T = plan.total_tiles
+    rg = plan.region(ws, L.GS_WS_RANGES, torch.int32, 2 * T).cpu().numpy().reshape(T, 2)
+    assert (rg[:, 1] - rg[:, 0]).max() == n  # the crowded tiles hold n pairs
+    for region, dt, cnt in ((L.GS_WS_SORTED_KEYS, torch.int64, P), (L.GS_WS_SORTED_VALS, torch.int32, P),
+                            (L.GS_WS_SORTED_RECS, torch.int32, P), (L.GS_WS_RANGES, torch.int32, 2 * T)):
+        assert torch.equal(plan.region(it.ws, region, dt, cnt), plan.region(ws, region, dt, cnt)), region
+    for a, b in ((it.frame.color, fr.color), (it.frame.depth, fr.depth), (it.frame.T_final, fr.T_final),
+                 (it.frame.last, fr.last), (it.frame.loss, fr.loss)):
+        assert torch.equal(a, b)
+    for f in gsr.Gaussians.FIELDS:
+        assert torch.equal(getattr(g1, f), getattr(g2, f)), f
+        assert torch.equal(getattr(it.m, f), getattr(m, f)), f
+        assert torch.equal(getattr(it.v, f), getattr(v, f)), f
+
+
+@pytest.mark.parametrize("extra", [L.GS_SPLAT_BWD, 0])
+def test_iteration_equals_separate_calls_full_view(extra):
+    """The 1200x680 / 300k view (12,750 tiles): one whole iteration, whose
+    forward sorts each tile and composites it from what that wavefront just
+    wrote, against the separate calls: sorted lists and every image bit for
+    bit.  (Many neighbouring tiles per CU: a read of the fresh records through
+    a stale cached line would show here.)"""
+    w = scenes.config2()
+    cam = w.cameras[0]
+    view_wh = [(cam.width, cam.height)]
+    cams = gsr.cameras_tensor([cam], DEV)
+    g1 = gsr.Gaussians.from_scene(w.scene, DEV)
+    rng = np.random.default_rng(5)
+    tgt = t32(rng.uniform(0.0, 1.0, (3, cam.height, cam.width)).reshape(-1))
+    print(f"full-view iteration against separate calls, flags {extra}", flush=True)
+    cap = int(gsr.required_pairs(*g1.tensors(), cams, view_wh, 3, (8, 8)) * 1.2) + 4096
+    plan = gsr.Plan(w.scene.n, 3, view_wh, tile=(8, 8), lds_batch=64, flags=L.GS_FUSED_L1 | extra,
+                    pair_capacity=cap)
+    lrs = {"means": 1e-3, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
+    it = gsr.Iteration(plan, g1, cams, target_rgb=tgt, adam_lrs=lrs)
+    it.enqueue()
+    g2 = gsr.Gaussians.from_scene(w.scene, DEV)
+    ws = plan.new_workspace(DEV)
+    fr = gsr.Frame(plan, DEV)
+    gsr.preprocess(plan, ws, g2, cams)
+    gsr.bin_sort(plan, ws)
+    gsr.render_fwd(plan, ws, cams, fr, tgt)
+    torch.cuda.synchronize()
+    P = int(plan.flags_of(ws)[L.F_PAIRS])
+    T = plan.total_tiles
+    for region, dt, cnt in ((L.GS_WS_SORTED_KEYS, torch.int64, P), (L.GS_WS_SORTED_VALS, torch.int32, P),
+                            (L.GS_WS_SORTED_RECS, torch.int32, P), (L.GS_WS_RANGES, torch.int32, 2 * T)):
+        assert torch.equal(plan.region(it.ws, region, dt, cnt), plan.region(ws, region, dt, cnt)), region
+    for a, b in ((it.frame.color, fr.color), (it.frame.depth, fr.depth), (it.frame.T_final, fr.T_final),
+                 (it.frame.last, fr.last), (it.frame.loss, fr.loss)):
+        assert int((a != b).sum().item()) == 0
+
+
 # ------------------------------------------------------------------ edge cases
 
 def test_empty_scene_and_empty_view():
