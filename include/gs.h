@@ -120,7 +120,13 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
                        const int32_t* view_wh, const gs_raster_cfg* cfg,
                        int64_t pair_capacity);
 
-/* Bytes of device workspace the plan needs (256-byte aligned base). */
+/* Bytes of device workspace the plan needs (256-byte aligned base).  A new
+ * workspace must be zero-filled once before its first use: a whole
+ * iteration (gs_iteration_enqueue, graph replays) does not clear its
+ * per-tile pair counters, relying on the binning of the previous iteration
+ * or gs_bin_sort having left them zero.  gs_preprocess called on its own
+ * clears them; calling it and then a whole iteration without gs_bin_sort in
+ * between makes that iteration report a pair overflow (flag [0]). */
 size_t gs_workspace_size(const gs_plan* plan);
 
 /* Queries: total pixels over views, pixel offset of a view, total tiles. */
@@ -130,6 +136,7 @@ int64_t gs_plan_total_tiles(const gs_plan* plan);
 
 /* Device pointer to the int32 flags inside `ws`:
  *   [0] pair-capacity overflow (0/1)   [1] Gaussians culled as non-finite
+ *       by the last gs_preprocess (published by the gs_bin_sort after it)
  *   [2] pair count P of the last gs_bin_sort (valid if [0] == 0)
  *   [3] visible (view, Gaussian) records (non-empty tile box) of the last
  *       gs_preprocess, counted by the gs_bin_sort after it

@@ -13,15 +13,14 @@
 
 namespace gs {
 hipError_t launch_preprocess(const Plan& P, const gs_gaussians& g, const float* cams, void* ws,
-                             hipStream_t s);
+                             hipStream_t s, const StepAdvance* step = nullptr);
 hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_short_sorts = false);
 TileSortArgs tile_sort_args(const Plan& P, void* ws);
 hipError_t launch_radix_sort(uint64_t* keys0, uint64_t* keys1, uint32_t* vals0, uint32_t* vals1,
                              const int32_t* cnt, uint32_t* hist, uint32_t* digit_tot,
                              int64_t nb_cap, int key_bits, bool iota, int* which, hipStream_t s);
 hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t s);
-hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s,
-                                 const StepAdvance* step = nullptr);
+hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s);
 uint32_t* sorted_vals(const Plan& P, void* ws);
 hipError_t launch_render_fwd(const Plan& P, void* ws, const float* cams, float* color,
                              float* depth, float* T_final, uint32_t* last,
@@ -284,27 +283,27 @@ int32_t* gs_flags_ptr(const gs_plan* plan, void* ws) {
   return ws_at<int32_t>(ws, plan_of(plan)->off_flags);
 }
 
-// Preprocess with an optional device step counter to advance in the same
-// launch as the counter clear (used by the whole-iteration enqueue).
+// Preprocess.  clear: the per-iteration flags and the per-tile pair
+// counters are zeroed by a kernel first (graph-safe); a whole iteration
+// skips it, the binning of the previous one having left them zero.
+// step_advance (optional): the projection also advances the Adam step.
 static gs_status preprocess_enqueue(const gs_plan* plan, const gs_gaussians* g,
                                     const float* cams_dev, void* ws, hipStream_t s,
-                                    const StepAdvance* step_advance) {
+                                    const StepAdvance* step_advance, bool clear) {
   gs_status st;
   if ((st = check_plan(plan)) != GS_OK) return st;
   const Plan& P = *plan_of(plan);
   if ((st = check_ws(P, ws)) != GS_OK) return st;
   if ((st = check_gaussians(P, g)) != GS_OK) return st;
   if (!cams_dev) return fail(GS_ERR_INVALID_ARG, "cams_dev is null");
-  // the per-iteration flags and the per-tile pair counts are cleared by a
-  // kernel (graph-safe)
-  hipError_t e = launch_clear_counters(P, ws, s, step_advance);
-  if (e == hipSuccess) e = launch_preprocess(P, *g, cams_dev, ws, s);
+  hipError_t e = clear ? launch_clear_counters(P, ws, s) : hipSuccess;
+  if (e == hipSuccess) e = launch_preprocess(P, *g, cams_dev, ws, s, step_advance);
   return hip_check(e, "gs_preprocess");
 }
 
 gs_status gs_preprocess(const gs_plan* plan, const gs_gaussians* g, const float* cams_dev,
                         void* ws, void* stream) {
-  return preprocess_enqueue(plan, g, cams_dev, ws, static_cast<hipStream_t>(stream), nullptr);
+  return preprocess_enqueue(plan, g, cams_dev, ws, static_cast<hipStream_t>(stream), nullptr, true);
 }
 
 gs_status gs_bin_sort(const gs_plan* plan, void* ws, void* stream) {
@@ -630,13 +629,17 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
     fold.lambda_depth = P.cfg.lambda_depth;
     fold.loss = it->loss_per_view;
   }
+  // no clearing launch: the counters were left zero by the last binning on
+  // this workspace (or the workspace is fresh, zero-filled)
   st = preprocess_enqueue(it->plan, &it->gaussians, it->cams_dev, it->ws, s,
-                          it->step_dev ? &adv : nullptr);
+                          it->step_dev ? &adv : nullptr, false);
   if (st != GS_OK) return st;
   // the binning leaves the short lists to the forward, which sorts each
   // tile's list right before compositing it (one launch fewer; the sort's
   // memory latency hides behind other wavefronts' compositing)
   hipError_t e = launch_bin_sort(P, it->ws, s, true);
+  TileSortArgs fwd_sort = tile_sort_args(P, it->ws);
+  fwd_sort.long_after = false;  // the long lists were sorted by the binning
   if (e != hipSuccess) return hip_check(e, "gs_iteration_enqueue (binning)");
   const bool pers = (P.cfg.flags & GS_PERSISTENT) != 0;
   int32_t* fl = ws_at<int32_t>(it->ws, P.off_flags);
@@ -645,7 +648,7 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
       ssim ? nullptr : it->target_rgb, ssim ? nullptr : it->target_depth,
       (ssim || fold_loss) ? nullptr : it->loss_per_view,
       ws_at<uint32_t>(it->ws, P.off_order), pers ? fl + F_QUEUE_FWD : nullptr,
-      pers ? persistent_grid(P, false) : P.vt.total_tiles, s, tile_sort_args(P, it->ws));
+      pers ? persistent_grid(P, false) : P.vt.total_tiles, s, fwd_sort);
   if (e != hipSuccess) return hip_check(e, "gs_iteration_enqueue (forward)");
   const float* gC = it->dL_dcolor;
   const float* gD = it->dL_ddepth;

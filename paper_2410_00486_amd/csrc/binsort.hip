@@ -30,26 +30,12 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t cou
 
 __global__ void k_set_i32(int32_t* __restrict__ p, int32_t value) { *p = value; }
 
-// Clears a[0, na) and b[0, nb); with a step counter, also advances it (the
-// Adam step of a whole iteration, taken at its start) and stores the
-// step-dependent Adam factors of the new step t for the Adam launch.
+// Clears a[0, na) and b[0, nb).
 __global__ void k_fill2_u32(uint32_t* __restrict__ a, int64_t na, uint32_t* __restrict__ b,
-                            int64_t nb, StepAdvance st) {
+                            int64_t nb) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < na) a[i] = 0u;
   if (i < nb) b[i] = 0u;
-  if (st.step && i == 0) {
-    const int32_t t = *st.step + 1;
-    *st.step = t;
-    AdamStepFactors* f = st.out;
-    const double bc1 = 1.0 - pow(st.beta1, (double)t);
-    const double bc2 = 1.0 - pow(st.beta2, (double)t);
-    f->bc1 = bc1;
-    f->bc2 = bc2;
-    f->inv_bc2s = (float)(1.0 / sqrt(bc2));
-    f->step = t;
-    for (int g = 0; g < st.n_groups; ++g) f->step_size[g] = (float)((double)st.lr[g] / bc1);
-  }
 }
 
 // ---------------------------------------------------------------- scans
@@ -313,6 +299,8 @@ __global__ void __launch_bounds__(kScanBlock) k_scans(ScanArgs A, int64_t cap,
   fl[F_PAIRS] = over ? 0 : (int32_t)tile_pairs;
   fl[F_PAIRS_WANTED] = tile_pairs > 0x7FFFFFFFull ? 0x7FFFFFFF : (int32_t)tile_pairs;
   fl[F_VISIBLE] = (int32_t)c32[2];
+  fl[F_NONFINITE] = fl[F_NF_ACC];  // counted by the projection
+  fl[F_NF_ACC] = 0;
   // the bucket queues are filled by the tile sort at the positions scanned
   // here; the long lists are sorted by their own kernel (none on overflow)
   fl[F_LONG_TILES] = (int32_t)n_long;
@@ -410,9 +398,9 @@ __global__ void __launch_bounds__(kWave) k_tile_sort(TileSortArgs A) {
 }
 
 __global__ void __launch_bounds__(kLongThreads) k_tile_sort_long(
-    const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ tstart,
+    uint32_t* __restrict__ cnt, const uint32_t* __restrict__ tstart,
     const int32_t* __restrict__ fl, const uint32_t* __restrict__ long_list,
-    uint64_t* __restrict__ skey, TileSortOut out) {
+    uint64_t* __restrict__ skey, TileSortOut out, int clear) {
   __shared__ uint64_t sk[kTileSortLong];
   const int n_long = fl[F_OVERFLOW] ? 0 : fl[F_LONG_TILES];
   for (int li = blockIdx.x; li < n_long; li += gridDim.x) {
@@ -431,6 +419,8 @@ __global__ void __launch_bounds__(kLongThreads) k_tile_sort_long(
         emit_sorted(out, start + k, tkey, skey[start + k]);
     }
     __syncthreads();  // the LDS is reused by the next list
+    // counter consumed (when the per-tile pass ran before this kernel)
+    if (clear && threadIdx.x == 0) cnt[t] = 0u;
   }
 }
 
@@ -654,14 +644,13 @@ hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s, const StepAdvance* step) {
+hipError_t launch_clear_counters(const Plan& P, void* ws, hipStream_t s) {
   // per-iteration flags 0..10 and the per-tile pair counters
   const int64_t T = P.vt.total_tiles;
   const int64_t m = T > 4 ? T : 4;
   hipLaunchKernelGGL(k_fill2_u32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
-                     ws_at<uint32_t>(ws, P.off_flags), (int64_t)11,
-                     ws_at<uint32_t>(ws, P.off_tile_cnt), T,
-                     step ? *step : StepAdvance{});
+                     ws_at<uint32_t>(ws, P.off_flags), (int64_t)(F_NF_ACC + 1),
+                     ws_at<uint32_t>(ws, P.off_tile_cnt), T);
   return hipGetLastError();
 }
 
@@ -682,6 +671,7 @@ TileSortArgs tile_sort_args(const Plan& P, void* ws) {
   A.hstart = splat ? ws_at<uint32_t>(ws, P.off_half_start) : nullptr;
   A.bq = splat ? ws_at<uint2>(ws, P.off_bq) : nullptr;
   A.bq_stride = P.ckpt_slots;
+  A.long_after = true;
   return A;
 }
 
@@ -716,11 +706,14 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_sh
                        ws_at<uint32_t>(ws, P.off_vis_list));
   }
   if (T > 0) {
+    // the per-tile pass (here, or the forward's when deferred) and the
+    // long-list kernel each zero the counters they consume, so that every
+    // counter is zero again after the binning of an iteration
     const TileSortArgs A = tile_sort_args(P, ws);
     if (!defer_short_sorts) hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)T), dim3(kWave), 0, s, A);
     const int long_grid = (int)std::min<int64_t>(T, 256);
     hipLaunchKernelGGL(k_tile_sort_long, dim3((unsigned)long_grid), dim3(kLongThreads), 0, s,
-                       tcnt, tstart, fl, long_list, skey, A.out);
+                       tcnt, tstart, fl, long_list, skey, A.out, defer_short_sorts ? 0 : 1);
   }
   return hipGetLastError();
 }

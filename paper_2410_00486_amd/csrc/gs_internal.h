@@ -28,6 +28,8 @@ enum Flag : int {
   F_LONG_TILES = 7,  // tiles whose lists go to the long-list sort
   F_BQ_FULL = 8,     // splat-wise buckets with more than 32 pairs
   F_BQ_HALF = 9,     // splat-wise buckets with at most 32 pairs
+  F_NF_ACC = 10,     // non-finite Gaussians counted by the projection, published
+                     // in F_NONFINITE (and cleared) by the binning scan
   F_COUNT = 16
 };
 
@@ -222,6 +224,20 @@ struct StepAdvance {
   int32_t n_groups;
   float lr[kAdamFoldGroups];
 };
+// One thread: advances the step counter and stores the factors of the new
+// step t.
+__device__ inline void advance_step(const StepAdvance& st) {
+  const int32_t t = *st.step + 1;
+  *st.step = t;
+  AdamStepFactors* f = st.out;
+  const double bc1 = 1.0 - pow(st.beta1, (double)t);
+  const double bc2 = 1.0 - pow(st.beta2, (double)t);
+  f->bc1 = bc1;
+  f->bc2 = bc2;
+  f->inv_bc2s = (float)(1.0 / sqrt(bc2));
+  f->step = t;
+  for (int g = 0; g < st.n_groups; ++g) f->step_size[g] = (float)((double)st.lr[g] / bc1);
+}
 constexpr size_t kBiasOffset = 128;  // bytes from the flags (F_COUNT int32 before it)
 static_assert(kBiasOffset >= F_COUNT * 4 && kBiasOffset + sizeof(AdamStepFactors) <= F_COUNT * 16,
               "flag block");

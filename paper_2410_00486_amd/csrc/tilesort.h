@@ -98,7 +98,7 @@ __device__ inline void bitonic_sort(uint64_t* k, uint32_t n, uint32_t tid, uint3
 
 // Everything a wavefront needs to sort one tile's list.
 struct TileSortArgs {
-  const uint32_t* cnt;     // pairs per tile (the scatter's cursors)
+  uint32_t* cnt;           // pairs per tile (the scatter's cursors); cleared after use
   const uint32_t* tstart;  // list start per tile
   const int32_t* fl;
   const uint64_t* skey;    // scattered keys (depth bits << 32 | generation index)
@@ -108,6 +108,9 @@ struct TileSortArgs {
   const uint32_t* hstart;
   uint2* bq;
   int64_t bq_stride;
+  // the long-list kernel runs after this one (it then clears the counters of
+  // the long lists itself) rather than before
+  bool long_after;
 };
 
 // What a wavefront that sorted a tile knows about its list: the range
@@ -129,12 +132,16 @@ struct TileList {
 __device__ inline TileList sort_tile_wave(const TileSortArgs& A, int t, int lane, uint64_t* sk,
                                           Rec* stage = nullptr, int stage_cap = 0) {
   const uint64_t P = (uint64_t)A.fl[F_PAIRS];
-  const uint32_t n = A.fl[F_OVERFLOW] ? 0u : A.cnt[t];
+  const uint32_t c = A.cnt[t];
+  const uint32_t n = A.fl[F_OVERFLOW] ? 0u : c;
   const uint64_t start64 = A.tstart[t];
   const bool ok = n > 0 && start64 + n <= P;
   if (lane == 0) {
     A.ranges[2 * (int64_t)t] = ok ? (uint32_t)start64 : 0u;
     A.ranges[2 * (int64_t)t + 1] = ok ? (uint32_t)(start64 + n) : 0u;
+    // the counter is consumed: zero again for the next projection (a long
+    // list's counter is still read by a long-list kernel that runs after)
+    if (!(A.long_after && c > kTileSortSmall)) A.cnt[t] = 0u;
   }
   if (A.bq && ok) {
     // splat-wise work queues at the scanned positions: the tile's buckets

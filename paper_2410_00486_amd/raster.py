@@ -73,7 +73,9 @@ class Plan:
         return int(L.lib().gs_plan_ws_offset(ctypes.byref(self.c), region))
 
     def new_workspace(self, device="cuda") -> torch.Tensor:
-        ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        # zero-filled: a whole iteration relies on the per-tile counters being
+        # zero before its first projection (later binnings leave them so)
+        ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=device)
         if ws.data_ptr() % 256:
             raise RuntimeError("workspace allocation is not 256-byte aligned")
         return ws
