@@ -6,6 +6,8 @@
 // covariance (scale, rotation), the SH colour and the view direction, and
 // the opacity sigmoid.  Camera tangents (rho, phi) for a left perturbation of
 // each pose are reduced per workgroup (fixed order) and then per view.
+#include <type_traits>
+
 #include "gs_internal.h"
 
 namespace gs {
@@ -73,7 +75,12 @@ __device__ __forceinline__ void sh_backward(double x, double y, double z, const 
 // COMPACT (one view): threads take the visible Gaussians from the list the
 // binning wrote, in index order, so that the long chain runs on full
 // wavefronts; the other Gaussians' gradients are zeroed beforehand.
-template <int DEG, bool POSE, bool COMPACT>
+// SPLIT (no pose gradient): the two wavefronts of a workgroup take the same
+// 64 Gaussians, one the projection chain (mean, scale, rotation, opacity),
+// the other the colour chain (SH coefficients and the view-direction part of
+// the mean gradient, handed over in LDS after the views), so the two halves
+// of each Gaussian's chain run side by side, each with its own registers.
+template <int DEG, bool POSE, bool COMPACT, bool SPLIT>
 __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
@@ -84,10 +91,15 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
     float* __restrict__ g_means, float* __restrict__ g_ls, float* __restrict__ g_q,
     float* __restrict__ g_logit, float* __restrict__ g_sh, double* __restrict__ pose_part,
     int64_t pose_stride) {
+  static_assert(!(SPLIT && POSE), "the camera tangent needs both halves in one thread");
   constexpr int K = (DEG + 1) * (DEG + 1);
   constexpr int NW = kProjThreads / kWave;
   const bool overflow = fl[F_OVERFLOW] != 0;
-  const int64_t t0 = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
+  const int lane = lane_id();
+  // wavefront role (SPLIT): 0 projection chain, 1 colour chain
+  const int role = SPLIT ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)) : 0;
+  const int64_t t0 = SPLIT ? (int64_t)blockIdx.x * kWave + lane
+                           : (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
   bool valid;
   int64_t i;
   if (COMPACT) {
@@ -99,268 +111,312 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
     i = t0;
   }
   __shared__ double spose[NW][6];
+  __shared__ double sgv[3][kWave];
 
   // Every per-Gaussian input is loaded at once, unconditionally (row 0 for
   // an idle thread; n > 0 whenever the kernel runs), so that the loads issue
   // together instead of one round trip each along the chain.
   const int64_t ic = valid ? i : 0;
-  const float mf0 = means[3 * ic], mf1 = means[3 * ic + 1], mf2 = means[3 * ic + 2];
-  const float qf0 = quats[4 * ic], qf1 = quats[4 * ic + 1], qf2 = quats[4 * ic + 2],
-              qf3 = quats[4 * ic + 3];
-  const float lf0 = log_scales[3 * ic], lf1 = log_scales[3 * ic + 1], lf2 = log_scales[3 * ic + 2];
-  const float logit = logits[ic];
 
-  // world covariance Sigma (view independent); its gradient is summed over
-  // views and pushed through scale and rotation once, after the view loop
-  double p[3] = {0, 0, 0};
-  double S00 = 0, S01 = 0, S02 = 0, S11 = 0, S12 = 0, S22 = 0;
-  if (valid) {
-    p[0] = mf0; p[1] = mf1; p[2] = mf2;
+  // DP: projection chain, DS: colour chain (both without SPLIT)
+  auto run = [&](auto dp_tag, auto ds_tag) {
+    constexpr bool DP = decltype(dp_tag)::value, DS = decltype(ds_tag)::value;
+    const float mf0 = means[3 * ic], mf1 = means[3 * ic + 1], mf2 = means[3 * ic + 2];
+    float qf0 = 0, qf1 = 0, qf2 = 0, qf3 = 0, lf0 = 0, lf1 = 0, lf2 = 0, logit = 0;
+    if (DP) {
+      qf0 = quats[4 * ic]; qf1 = quats[4 * ic + 1]; qf2 = quats[4 * ic + 2]; qf3 = quats[4 * ic + 3];
+      lf0 = log_scales[3 * ic]; lf1 = log_scales[3 * ic + 1]; lf2 = log_scales[3 * ic + 2];
+      logit = logits[ic];
+    }
+    // SH coefficients and their gradient in registers for the whole view
+    // loop, loaded the same way
+    constexpr int KS = DS ? K * 3 : 1;
+    float shv[KS], gsh[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      shv[k] = DS ? sh[ic * (K * 3) + k] : 0.0f;
+      gsh[k] = 0.0f;
+    }
+
+    // world covariance Sigma (view independent); its gradient is summed over
+    // views and pushed through scale and rotation once, after the view loop
+    double p[3] = {0, 0, 0};
+    double S00 = 0, S01 = 0, S02 = 0, S11 = 0, S12 = 0, S22 = 0;
+    if (valid) {
+      p[0] = mf0; p[1] = mf1; p[2] = mf2;
+    }
+    if (DP && valid) {
+      double q[4] = {qf0, qf1, qf2, qf3};
+      const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+      if (qn > 0.0)
+        for (int k = 0; k < 4; ++k) q[k] /= qn;
+      const double w = q[0], x = q[1], y = q[2], z = q[3];
+      const double R00 = 1 - 2 * (y * y + z * z), R01 = 2 * (x * y - w * z), R02 = 2 * (x * z + w * y);
+      const double R10 = 2 * (x * y + w * z), R11 = 1 - 2 * (x * x + z * z), R12 = 2 * (y * z - w * x);
+      const double R20 = 2 * (x * z - w * y), R21 = 2 * (y * z + w * x), R22 = 1 - 2 * (x * x + y * y);
+      const double s0 = exp(2.0 * (double)lf0), s1 = exp(2.0 * (double)lf1), s2 = exp(2.0 * (double)lf2);
+      S00 = R00 * R00 * s0 + R01 * R01 * s1 + R02 * R02 * s2;
+      S01 = R00 * R10 * s0 + R01 * R11 * s1 + R02 * R12 * s2;
+      S02 = R00 * R20 * s0 + R01 * R21 * s1 + R02 * R22 * s2;
+      S11 = R10 * R10 * s0 + R11 * R11 * s1 + R12 * R12 * s2;
+      S12 = R10 * R20 * s0 + R11 * R21 * s1 + R12 * R22 * s2;
+      S22 = R20 * R20 * s0 + R21 * R21 * s1 + R22 * R22 * s2;
+    }
+    double gp0 = 0, gp1 = 0, gp2 = 0, gop = 0;
+    double GS00 = 0, GS01 = 0, GS02 = 0, GS11 = 0, GS12 = 0, GS22 = 0;
+
+    for (int v = 0; v < vt.n_views; ++v) {
+      const int64_t ri = (int64_t)v * n + ic;
+      const uint32_t tt_v = tt[ri], poff_v = poff[ri];
+      const uint32_t cmask = DS ? recs[ri].clamp : 0u;
+      const uint32_t cnt = (valid && !overflow) ? tt_v : 0u;
+      double pose[6] = {0, 0, 0, 0, 0, 0};
+      if (cnt > 0) {
+        // fixed-order sum of this (view, Gaussian)'s pair partials (the
+        // colour chain needs the first three, the projection chain the rest)
+        double g2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        const float4* gpp = reinterpret_cast<const float4*>(grad_pair + (int64_t)poff_v * kPairGrad);
+        auto add = [&](const float4& a, const float4& b, const float4& c) {
+          if (DS) { g2[0] += a.x; g2[1] += a.y; g2[2] += a.z; }
+          if (DP) {
+            g2[3] += a.w;
+            g2[4] += b.x; g2[5] += b.y; g2[6] += b.z; g2[7] += b.w;
+            g2[8] += c.x; g2[9] += c.y;
+          }
+        };
+        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        // loads of eight pairs are issued before their (in-order) additions,
+        // so a large Gaussian does not pay one memory round trip per tile
+        uint32_t k = 0;
+        for (; k + 8 <= cnt; k += 8) {
+          float4 a[8], b[8], c[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            a[u] = gpp[3 * (k + u)];
+            b[u] = DP ? gpp[3 * (k + u) + 1] : z4;
+            c[u] = DP ? gpp[3 * (k + u) + 2] : z4;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) add(a[u], b[u], c[u]);
+        }
+        for (; k < cnt; ++k) add(gpp[3 * k], DP ? gpp[3 * k + 1] : z4, DP ? gpp[3 * k + 2] : z4);
+        gop += g2[4];
+        const float* c = cams + (int64_t)v * GS_CAMERA_FLOATS;
+        const double fx = c[0], fy = c[1];
+        double W[9];
+        for (int k = 0; k < 9; ++k) W[k] = c[4 + k];
+        const double t0 = c[13], t1 = c[14], t2 = c[15];
+        const double tx = W[0] * p[0] + W[1] * p[1] + W[2] * p[2] + t0;
+        const double ty = W[3] * p[0] + W[4] * p[1] + W[5] * p[2] + t1;
+        const double tz = W[6] * p[0] + W[7] * p[1] + W[8] * p[2] + t2;
+        double gt0 = 0, gt1 = 0, gt2 = 0;
+        double j00 = 0, j02 = 0, j11 = 0, j12 = 0, X00 = 0, X01 = 0, X11 = 0;
+        if (DP) {
+          const double limx = 1.3 * (double)vt.v[v].W / (2.0 * fx);
+          const double limy = 1.3 * (double)vt.v[v].H / (2.0 * fy);
+          const double ux = tx / tz, vy = ty / tz;
+          const bool cu = (ux < -limx) || (ux > limx), cv = (vy < -limy) || (vy > limy);
+          const double u = fmin(limx, fmax(-limx, ux)), wv = fmin(limy, fmax(-limy, vy));
+          j00 = fx / tz; j02 = -fx * u / tz; j11 = fy / tz; j12 = -fy * wv / tz;
+          const double a0 = j00 * W[0] + j02 * W[6], a1 = j00 * W[1] + j02 * W[7], a2 = j00 * W[2] + j02 * W[8];
+          const double b0 = j11 * W[3] + j12 * W[6], b1 = j11 * W[4] + j12 * W[7], b2 = j11 * W[5] + j12 * W[8];
+          const double Sa0 = S00 * a0 + S01 * a1 + S02 * a2, Sa1 = S01 * a0 + S11 * a1 + S12 * a2,
+                       Sa2 = S02 * a0 + S12 * a1 + S22 * a2;
+          const double Sb0 = S00 * b0 + S01 * b1 + S02 * b2, Sb1 = S01 * b0 + S11 * b1 + S12 * b2,
+                       Sb2 = S02 * b0 + S12 * b1 + S22 * b2;
+          const double A = a0 * Sa0 + a1 * Sa1 + a2 * Sa2 + 0.3;
+          const double B = 0.5 * ((a0 * Sb0 + a1 * Sb1 + a2 * Sb2) + (b0 * Sa0 + b1 * Sa1 + b2 * Sa2));
+          const double C = b0 * Sb0 + b1 * Sb1 + b2 * Sb2 + 0.3;
+          const double det = A * C - B * B;
+          const double ya = C / det, yb = -B / det, yc = A / det;  // conic
+          // dL/dX = -Y G_Y Y with G_Y = [[ga, gb/2], [gb/2, gc]]
+          const double ga = g2[5], gbh = 0.5 * g2[6], gc = g2[7];
+          const double M00 = ya * ga + yb * gbh, M01 = ya * gbh + yb * gc;
+          const double M10 = yb * ga + yc * gbh, M11 = yb * gbh + yc * gc;
+          X00 = -(M00 * ya + M01 * yb);
+          X01 = -(M00 * yb + M01 * yc);
+          X11 = -(M10 * yb + M11 * yc);
+          // G_Sigma += X00 a a^T + X01 (a b^T + b a^T) + X11 b b^T
+          GS00 += X00 * a0 * a0 + 2.0 * X01 * a0 * b0 + X11 * b0 * b0;
+          GS11 += X00 * a1 * a1 + 2.0 * X01 * a1 * b1 + X11 * b1 * b1;
+          GS22 += X00 * a2 * a2 + 2.0 * X01 * a2 * b2 + X11 * b2 * b2;
+          GS01 += X00 * a0 * a1 + X01 * (a0 * b1 + b0 * a1) + X11 * b0 * b1;
+          GS02 += X00 * a0 * a2 + X01 * (a0 * b2 + b0 * a2) + X11 * b0 * b2;
+          GS12 += X00 * a1 * a2 + X01 * (a1 * b2 + b1 * a2) + X11 * b1 * b2;
+          // G_T2 rows: 2 (X00 Sa + X01 Sb), 2 (X01 Sa + X11 Sb);  G_J = G_T2 W^T
+          const double r00 = 2 * (X00 * Sa0 + X01 * Sb0), r01 = 2 * (X00 * Sa1 + X01 * Sb1),
+                       r02 = 2 * (X00 * Sa2 + X01 * Sb2);
+          const double r10 = 2 * (X01 * Sa0 + X11 * Sb0), r11 = 2 * (X01 * Sa1 + X11 * Sb1),
+                       r12 = 2 * (X01 * Sa2 + X11 * Sb2);
+          const double GJ00 = r00 * W[0] + r01 * W[1] + r02 * W[2];
+          const double GJ02 = r00 * W[6] + r01 * W[7] + r02 * W[8];
+          const double GJ11 = r10 * W[3] + r11 * W[4] + r12 * W[5];
+          const double GJ12 = r10 * W[6] + r11 * W[7] + r12 * W[8];
+          const double tz2 = tz * tz, tz3 = tz2 * tz;
+          gt2 = -GJ00 * fx / tz2 - GJ11 * fy / tz2;
+          if (!cu) { gt0 += -GJ02 * fx / tz2; gt2 += GJ02 * 2.0 * fx * tx / tz3; }
+          else { gt2 += GJ02 * fx * u / tz2; }
+          if (!cv) { gt1 += -GJ12 * fy / tz2; gt2 += GJ12 * 2.0 * fy * ty / tz3; }
+          else { gt2 += GJ12 * fy * wv / tz2; }
+          const double gmx = g2[8], gmy = g2[9];
+          gt0 += gmx * fx / tz;
+          gt1 += gmy * fy / tz;
+          gt2 += -(gmx * fx * tx + gmy * fy * ty) / tz2 + g2[3];
+        }
+
+        double gv0 = 0, gv1 = 0, gv2 = 0;
+        if (DS) {
+          // colour: SH coefficients and view direction
+          const double cxw = -(W[0] * t0 + W[3] * t1 + W[6] * t2);
+          const double cyw = -(W[1] * t0 + W[4] * t1 + W[7] * t2);
+          const double czw = -(W[2] * t0 + W[5] * t1 + W[8] * t2);
+          const double dv0 = p[0] - cxw, dv1 = p[1] - cyw, dv2 = p[2] - czw;
+          const double dist = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
+          const double d0 = dv0 / dist, d1 = dv1 / dist, d2 = dv2 / dist;
+          // colour clamp decided by the forward projection (record bit per channel)
+          double gcr[3];
+          for (int ch = 0; ch < 3; ++ch) gcr[ch] = ((cmask >> ch) & 1u) ? 0.0 : g2[ch];
+          double gd0 = 0, gd1 = 0, gd2 = 0;
+          sh_backward<DEG>(d0, d1, d2, gcr, shv, gsh, gd0, gd1, gd2);
+          const double dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
+          gv0 = (gd0 - dd * d0) / dist;
+          gv1 = (gd1 - dd * d1) / dist;
+          gv2 = (gd2 - dd * d2) / dist;
+        }
+        // mean: W^T g_t + g_v (the colour wavefront of SPLIT sums g_v alone)
+        gp0 += W[0] * gt0 + W[3] * gt1 + W[6] * gt2 + gv0;
+        gp1 += W[1] * gt0 + W[4] * gt1 + W[7] * gt2 + gv1;
+        gp2 += W[2] * gt0 + W[5] * gt1 + W[8] * gt2 + gv2;
+        if (POSE) {
+          // camera tangent: rho = g_t + W g_v;  phi = t x g_t - 2 axial(Sc Gc - Gc Sc)
+          pose[0] = gt0 + W[0] * gv0 + W[1] * gv1 + W[2] * gv2;
+          pose[1] = gt1 + W[3] * gv0 + W[4] * gv1 + W[5] * gv2;
+          pose[2] = gt2 + W[6] * gv0 + W[7] * gv1 + W[8] * gv2;
+          pose[3] = ty * gt2 - tz * gt1;
+          pose[4] = tz * gt0 - tx * gt2;
+          pose[5] = tx * gt1 - ty * gt0;
+          const double Sw[3][3] = {{S00, S01, S02}, {S01, S11, S12}, {S02, S12, S22}};
+          double WS[3][3], Sc[3][3];
+          for (int r = 0; r < 3; ++r)
+            for (int cc = 0; cc < 3; ++cc)
+              WS[r][cc] = W[3 * r] * Sw[0][cc] + W[3 * r + 1] * Sw[1][cc] + W[3 * r + 2] * Sw[2][cc];
+          for (int r = 0; r < 3; ++r)
+            for (int cc = 0; cc < 3; ++cc)
+              Sc[r][cc] = WS[r][0] * W[3 * cc] + WS[r][1] * W[3 * cc + 1] + WS[r][2] * W[3 * cc + 2];
+          const double jr0[3] = {j00, 0.0, j02}, jr1[3] = {0.0, j11, j12};
+          double Gc[3][3];
+          for (int r = 0; r < 3; ++r)
+            for (int cc = 0; cc < 3; ++cc)
+              Gc[r][cc] = X00 * jr0[r] * jr0[cc] + X01 * (jr0[r] * jr1[cc] + jr1[r] * jr0[cc]) + X11 * jr1[r] * jr1[cc];
+          double A21 = 0, A02 = 0, A10 = 0;
+          for (int k = 0; k < 3; ++k) {
+            A21 += Sc[2][k] * Gc[k][1] - Gc[2][k] * Sc[k][1];
+            A02 += Sc[0][k] * Gc[k][2] - Gc[0][k] * Sc[k][2];
+            A10 += Sc[1][k] * Gc[k][0] - Gc[1][k] * Sc[k][0];
+          }
+          pose[3] -= 2.0 * A21;
+          pose[4] -= 2.0 * A02;
+          pose[5] -= 2.0 * A10;
+        }
+      }
+      if (POSE) {
+        // workgroup sum of the camera tangent for this view, fixed order
+        const int w = threadIdx.x / kWave;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const double sum = wave_sum(pose[k]);
+          if (lane == 0) spose[w][k] = sum;
+        }
+        __syncthreads();
+        if (threadIdx.x < 6) {
+          double acc = 0.0;
+          for (int ww = 0; ww < NW; ++ww) acc += spose[ww][threadIdx.x];
+          pose_part[((int64_t)v * pose_stride + blockIdx.x) * 6 + threadIdx.x] = acc;
+        }
+        __syncthreads();
+      }
+    }
+
+    if (DS && valid) {
+      // SH gradients: sums over the views in registers, one batch of stores
+      // (zeros for a Gaussian without pairs)
+      float* gdst = g_sh + i * (K * 3);
+      if (accumulate) {
+        float old[KS];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) old[k] = gdst[k];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) gdst[k] = old[k] + gsh[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < KS; ++k) gdst[k] = gsh[k];
+      }
+    }
+    if (SPLIT) {
+      // hand-over of the view-direction part of the mean gradient: one
+      // barrier in each wavefront's path
+      if (!DP) {
+        sgv[0][lane] = gp0;
+        sgv[1][lane] = gp1;
+        sgv[2][lane] = gp2;
+        __syncthreads();
+        return;
+      }
+      __syncthreads();
+      gp0 += sgv[0][lane];
+      gp1 += sgv[1][lane];
+      gp2 += sgv[2][lane];
+    }
+    if (!DP || !valid) return;
+    // Sigma = M M^T, M = R diag(s):  g_l_j = 2 s_j^2 R_j^T G R_j,
+    // G_R[:, j] = 2 s_j^2 G R_j, then through the normalised quaternion
     double q[4] = {qf0, qf1, qf2, qf3};
     const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     if (qn > 0.0)
       for (int k = 0; k < 4; ++k) q[k] /= qn;
-    const double w = q[0], x = q[1], y = q[2], z = q[3];
-    const double R00 = 1 - 2 * (y * y + z * z), R01 = 2 * (x * y - w * z), R02 = 2 * (x * z + w * y);
-    const double R10 = 2 * (x * y + w * z), R11 = 1 - 2 * (x * x + z * z), R12 = 2 * (y * z - w * x);
-    const double R20 = 2 * (x * z - w * y), R21 = 2 * (y * z + w * x), R22 = 1 - 2 * (x * x + y * y);
-    const double s0 = exp(2.0 * (double)lf0), s1 = exp(2.0 * (double)lf1), s2 = exp(2.0 * (double)lf2);
-    S00 = R00 * R00 * s0 + R01 * R01 * s1 + R02 * R02 * s2;
-    S01 = R00 * R10 * s0 + R01 * R11 * s1 + R02 * R12 * s2;
-    S02 = R00 * R20 * s0 + R01 * R21 * s1 + R02 * R22 * s2;
-    S11 = R10 * R10 * s0 + R11 * R11 * s1 + R12 * R12 * s2;
-    S12 = R10 * R20 * s0 + R11 * R21 * s1 + R12 * R22 * s2;
-    S22 = R20 * R20 * s0 + R21 * R21 * s1 + R22 * R22 * s2;
-  }
-  double gp0 = 0, gp1 = 0, gp2 = 0, gop = 0;
-  double GS00 = 0, GS01 = 0, GS02 = 0, GS11 = 0, GS12 = 0, GS22 = 0;
-  // SH coefficients and their gradient in registers for the whole view loop
-  // (loaded unconditionally, row 0 for an idle thread, so that the loads
-  // issue together; n > 0 whenever the kernel runs)
-  float shv[K * 3], gsh[K * 3];
-  const float* shrow = sh + ic * (K * 3);
-#pragma unroll
-  for (int k = 0; k < K * 3; ++k) {
-    shv[k] = shrow[k];
-    gsh[k] = 0.0f;
-  }
-  bool sh_written = false;
-
-  for (int v = 0; v < vt.n_views; ++v) {
-    const int64_t ri = (int64_t)v * n + ic;
-    const uint32_t tt_v = tt[ri], poff_v = poff[ri], cmask = recs[ri].clamp;
-    const uint32_t cnt = (valid && !overflow) ? tt_v : 0u;
-    double pose[6] = {0, 0, 0, 0, 0, 0};
-    if (cnt > 0) {
-      // fixed-order sum of this (view, Gaussian)'s pair partials
-      double g2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-      const float4* gpp = reinterpret_cast<const float4*>(grad_pair + (int64_t)poff_v * kPairGrad);
-      // loads of eight pairs are issued before their (in-order) additions,
-      // so a large Gaussian does not pay one memory round trip per tile
-      auto add = [&](const float4& a, const float4& b, const float4& c) {
-        g2[0] += a.x; g2[1] += a.y; g2[2] += a.z; g2[3] += a.w;
-        g2[4] += b.x; g2[5] += b.y; g2[6] += b.z; g2[7] += b.w;
-        g2[8] += c.x; g2[9] += c.y;
-      };
-      uint32_t k = 0;
-      for (; k + 8 <= cnt; k += 8) {
-        float4 a[8], b[8], c[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          a[u] = gpp[3 * (k + u)];
-          b[u] = gpp[3 * (k + u) + 1];
-          c[u] = gpp[3 * (k + u) + 2];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) add(a[u], b[u], c[u]);
-      }
-      for (; k < cnt; ++k) add(gpp[3 * k], gpp[3 * k + 1], gpp[3 * k + 2]);
-      gop += g2[4];
-      const float* c = cams + (int64_t)v * GS_CAMERA_FLOATS;
-      const double fx = c[0], fy = c[1];
-      double W[9];
-      for (int k = 0; k < 9; ++k) W[k] = c[4 + k];
-      const double t0 = c[13], t1 = c[14], t2 = c[15];
-      const double tx = W[0] * p[0] + W[1] * p[1] + W[2] * p[2] + t0;
-      const double ty = W[3] * p[0] + W[4] * p[1] + W[5] * p[2] + t1;
-      const double tz = W[6] * p[0] + W[7] * p[1] + W[8] * p[2] + t2;
-      const double limx = 1.3 * (double)vt.v[v].W / (2.0 * fx);
-      const double limy = 1.3 * (double)vt.v[v].H / (2.0 * fy);
-      const double ux = tx / tz, vy = ty / tz;
-      const bool cu = (ux < -limx) || (ux > limx), cv = (vy < -limy) || (vy > limy);
-      const double u = fmin(limx, fmax(-limx, ux)), wv = fmin(limy, fmax(-limy, vy));
-      const double j00 = fx / tz, j02 = -fx * u / tz, j11 = fy / tz, j12 = -fy * wv / tz;
-      const double a0 = j00 * W[0] + j02 * W[6], a1 = j00 * W[1] + j02 * W[7], a2 = j00 * W[2] + j02 * W[8];
-      const double b0 = j11 * W[3] + j12 * W[6], b1 = j11 * W[4] + j12 * W[7], b2 = j11 * W[5] + j12 * W[8];
-      const double Sa0 = S00 * a0 + S01 * a1 + S02 * a2, Sa1 = S01 * a0 + S11 * a1 + S12 * a2,
-                   Sa2 = S02 * a0 + S12 * a1 + S22 * a2;
-      const double Sb0 = S00 * b0 + S01 * b1 + S02 * b2, Sb1 = S01 * b0 + S11 * b1 + S12 * b2,
-                   Sb2 = S02 * b0 + S12 * b1 + S22 * b2;
-      const double A = a0 * Sa0 + a1 * Sa1 + a2 * Sa2 + 0.3;
-      const double B = 0.5 * ((a0 * Sb0 + a1 * Sb1 + a2 * Sb2) + (b0 * Sa0 + b1 * Sa1 + b2 * Sa2));
-      const double C = b0 * Sb0 + b1 * Sb1 + b2 * Sb2 + 0.3;
-      const double det = A * C - B * B;
-      const double ya = C / det, yb = -B / det, yc = A / det;  // conic
-      // dL/dX = -Y G_Y Y with G_Y = [[ga, gb/2], [gb/2, gc]]
-      const double ga = g2[5], gbh = 0.5 * g2[6], gc = g2[7];
-      const double M00 = ya * ga + yb * gbh, M01 = ya * gbh + yb * gc;
-      const double M10 = yb * ga + yc * gbh, M11 = yb * gbh + yc * gc;
-      const double X00 = -(M00 * ya + M01 * yb), X01 = -(M00 * yb + M01 * yc),
-                   X11 = -(M10 * yb + M11 * yc);
-      // G_Sigma += X00 a a^T + X01 (a b^T + b a^T) + X11 b b^T
-      GS00 += X00 * a0 * a0 + 2.0 * X01 * a0 * b0 + X11 * b0 * b0;
-      GS11 += X00 * a1 * a1 + 2.0 * X01 * a1 * b1 + X11 * b1 * b1;
-      GS22 += X00 * a2 * a2 + 2.0 * X01 * a2 * b2 + X11 * b2 * b2;
-      GS01 += X00 * a0 * a1 + X01 * (a0 * b1 + b0 * a1) + X11 * b0 * b1;
-      GS02 += X00 * a0 * a2 + X01 * (a0 * b2 + b0 * a2) + X11 * b0 * b2;
-      GS12 += X00 * a1 * a2 + X01 * (a1 * b2 + b1 * a2) + X11 * b1 * b2;
-      // G_T2 rows: 2 (X00 Sa + X01 Sb), 2 (X01 Sa + X11 Sb);  G_J = G_T2 W^T
-      const double r00 = 2 * (X00 * Sa0 + X01 * Sb0), r01 = 2 * (X00 * Sa1 + X01 * Sb1),
-                   r02 = 2 * (X00 * Sa2 + X01 * Sb2);
-      const double r10 = 2 * (X01 * Sa0 + X11 * Sb0), r11 = 2 * (X01 * Sa1 + X11 * Sb1),
-                   r12 = 2 * (X01 * Sa2 + X11 * Sb2);
-      const double GJ00 = r00 * W[0] + r01 * W[1] + r02 * W[2];
-      const double GJ02 = r00 * W[6] + r01 * W[7] + r02 * W[8];
-      const double GJ11 = r10 * W[3] + r11 * W[4] + r12 * W[5];
-      const double GJ12 = r10 * W[6] + r11 * W[7] + r12 * W[8];
-      const double tz2 = tz * tz, tz3 = tz2 * tz;
-      double gt0 = 0, gt1 = 0, gt2 = -GJ00 * fx / tz2 - GJ11 * fy / tz2;
-      if (!cu) { gt0 += -GJ02 * fx / tz2; gt2 += GJ02 * 2.0 * fx * tx / tz3; }
-      else { gt2 += GJ02 * fx * u / tz2; }
-      if (!cv) { gt1 += -GJ12 * fy / tz2; gt2 += GJ12 * 2.0 * fy * ty / tz3; }
-      else { gt2 += GJ12 * fy * wv / tz2; }
-      const double gmx = g2[8], gmy = g2[9];
-      gt0 += gmx * fx / tz;
-      gt1 += gmy * fy / tz;
-      gt2 += -(gmx * fx * tx + gmy * fy * ty) / tz2 + g2[3];
-
-      // colour: SH coefficients and view direction
-      const double cxw = -(W[0] * t0 + W[3] * t1 + W[6] * t2);
-      const double cyw = -(W[1] * t0 + W[4] * t1 + W[7] * t2);
-      const double czw = -(W[2] * t0 + W[5] * t1 + W[8] * t2);
-      const double dv0 = p[0] - cxw, dv1 = p[1] - cyw, dv2 = p[2] - czw;
-      const double dist = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
-      const double d0 = dv0 / dist, d1 = dv1 / dist, d2 = dv2 / dist;
-      // colour clamp decided by the forward projection (record bit per channel)
-      double gcr[3];
-      for (int ch = 0; ch < 3; ++ch) gcr[ch] = ((cmask >> ch) & 1u) ? 0.0 : g2[ch];
-      double gd0 = 0, gd1 = 0, gd2 = 0;
-      sh_backward<DEG>(d0, d1, d2, gcr, shv, gsh, gd0, gd1, gd2);
-      sh_written = true;
-      const double dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
-      const double gv0 = (gd0 - dd * d0) / dist, gv1 = (gd1 - dd * d1) / dist,
-                   gv2 = (gd2 - dd * d2) / dist;
-      // mean: W^T g_t + g_v
-      gp0 += W[0] * gt0 + W[3] * gt1 + W[6] * gt2 + gv0;
-      gp1 += W[1] * gt0 + W[4] * gt1 + W[7] * gt2 + gv1;
-      gp2 += W[2] * gt0 + W[5] * gt1 + W[8] * gt2 + gv2;
-      if (POSE) {
-        // camera tangent: rho = g_t + W g_v;  phi = t x g_t - 2 axial(Sc Gc - Gc Sc)
-        pose[0] = gt0 + W[0] * gv0 + W[1] * gv1 + W[2] * gv2;
-        pose[1] = gt1 + W[3] * gv0 + W[4] * gv1 + W[5] * gv2;
-        pose[2] = gt2 + W[6] * gv0 + W[7] * gv1 + W[8] * gv2;
-        pose[3] = ty * gt2 - tz * gt1;
-        pose[4] = tz * gt0 - tx * gt2;
-        pose[5] = tx * gt1 - ty * gt0;
-        const double Sw[3][3] = {{S00, S01, S02}, {S01, S11, S12}, {S02, S12, S22}};
-        double WS[3][3], Sc[3][3];
-        for (int r = 0; r < 3; ++r)
-          for (int cc = 0; cc < 3; ++cc)
-            WS[r][cc] = W[3 * r] * Sw[0][cc] + W[3 * r + 1] * Sw[1][cc] + W[3 * r + 2] * Sw[2][cc];
-        for (int r = 0; r < 3; ++r)
-          for (int cc = 0; cc < 3; ++cc)
-            Sc[r][cc] = WS[r][0] * W[3 * cc] + WS[r][1] * W[3 * cc + 1] + WS[r][2] * W[3 * cc + 2];
-        const double jr0[3] = {j00, 0.0, j02}, jr1[3] = {0.0, j11, j12};
-        double Gc[3][3];
-        for (int r = 0; r < 3; ++r)
-          for (int cc = 0; cc < 3; ++cc)
-            Gc[r][cc] = X00 * jr0[r] * jr0[cc] + X01 * (jr0[r] * jr1[cc] + jr1[r] * jr0[cc]) + X11 * jr1[r] * jr1[cc];
-        double A21 = 0, A02 = 0, A10 = 0;
-        for (int k = 0; k < 3; ++k) {
-          A21 += Sc[2][k] * Gc[k][1] - Gc[2][k] * Sc[k][1];
-          A02 += Sc[0][k] * Gc[k][2] - Gc[0][k] * Sc[k][2];
-          A10 += Sc[1][k] * Gc[k][0] - Gc[1][k] * Sc[k][0];
-        }
-        pose[3] -= 2.0 * A21;
-        pose[4] -= 2.0 * A02;
-        pose[5] -= 2.0 * A10;
-      }
+    const double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+    const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
+                         2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
+                         2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
+    double GR[9], gl[3];
+    for (int j = 0; j < 3; ++j) {
+      const double Rj0 = R[j], Rj1 = R[3 + j], Rj2 = R[6 + j];
+      const double G0 = GS00 * Rj0 + GS01 * Rj1 + GS02 * Rj2;
+      const double G1 = GS01 * Rj0 + GS11 * Rj1 + GS12 * Rj2;
+      const double G2 = GS02 * Rj0 + GS12 * Rj1 + GS22 * Rj2;
+      const double s2 = exp(2.0 * (double)(j == 0 ? lf0 : (j == 1 ? lf1 : lf2)));
+      gl[j] = 2.0 * s2 * (Rj0 * G0 + Rj1 * G1 + Rj2 * G2);
+      GR[j] = 2.0 * s2 * G0;
+      GR[3 + j] = 2.0 * s2 * G1;
+      GR[6 + j] = 2.0 * s2 * G2;
     }
-    if (POSE) {
-      // workgroup sum of the camera tangent for this view, fixed order
-      const int w = threadIdx.x / kWave;
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const double sum = wave_sum(pose[k]);
-        if (lane_id() == 0) spose[w][k] = sum;
-      }
-      __syncthreads();
-      if (threadIdx.x < 6) {
-        double acc = 0.0;
-        for (int ww = 0; ww < NW; ++ww) acc += spose[ww][threadIdx.x];
-        pose_part[((int64_t)v * pose_stride + blockIdx.x) * 6 + threadIdx.x] = acc;
-      }
-      __syncthreads();
-    }
-  }
-  if (!valid) return;
-  // Sigma = M M^T, M = R diag(s):  g_l_j = 2 s_j^2 R_j^T G R_j,
-  // G_R[:, j] = 2 s_j^2 G R_j, then through the normalised quaternion
-  double q[4] = {qf0, qf1, qf2, qf3};
-  const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-  if (qn > 0.0)
-    for (int k = 0; k < 4; ++k) q[k] /= qn;
-  const double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
-  const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
-                       2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
-                       2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
-  double GR[9], gl[3];
-  for (int j = 0; j < 3; ++j) {
-    const double Rj0 = R[j], Rj1 = R[3 + j], Rj2 = R[6 + j];
-    const double G0 = GS00 * Rj0 + GS01 * Rj1 + GS02 * Rj2;
-    const double G1 = GS01 * Rj0 + GS11 * Rj1 + GS12 * Rj2;
-    const double G2 = GS02 * Rj0 + GS12 * Rj1 + GS22 * Rj2;
-    const double s2 = exp(2.0 * (double)(j == 0 ? lf0 : (j == 1 ? lf1 : lf2)));
-    gl[j] = 2.0 * s2 * (Rj0 * G0 + Rj1 * G1 + Rj2 * G2);
-    GR[j] = 2.0 * s2 * G0;
-    GR[3 + j] = 2.0 * s2 * G1;
-    GR[6 + j] = 2.0 * s2 * G2;
-  }
-  const double dw = GR[1] * (-2 * qz) + GR[2] * (2 * qy) + GR[3] * (2 * qz) + GR[5] * (-2 * qx) +
-                    GR[6] * (-2 * qy) + GR[7] * (2 * qx);
-  const double dx = GR[1] * (2 * qy) + GR[2] * (2 * qz) + GR[3] * (2 * qy) + GR[4] * (-4 * qx) +
-                    GR[5] * (-2 * qw) + GR[6] * (2 * qz) + GR[7] * (2 * qw) + GR[8] * (-4 * qx);
-  const double dy = GR[0] * (-4 * qy) + GR[1] * (2 * qx) + GR[2] * (2 * qw) + GR[3] * (2 * qx) +
-                    GR[5] * (2 * qz) + GR[6] * (-2 * qw) + GR[7] * (2 * qz) + GR[8] * (-4 * qy);
-  const double dz = GR[0] * (-4 * qz) + GR[1] * (-2 * qw) + GR[2] * (2 * qx) + GR[3] * (2 * qw) +
-                    GR[4] * (-4 * qz) + GR[5] * (2 * qy) + GR[6] * (2 * qx) + GR[7] * (2 * qy);
-  const double dot = dw * qw + dx * qx + dy * qy + dz * qz;
-  const double o = 1.0 / (1.0 + exp(-(double)logit));
-  auto put = [&](float* dst, double val) { *dst = accumulate ? *dst + (float)val : (float)val; };
-  put(&g_means[3 * i], gp0);
-  put(&g_means[3 * i + 1], gp1);
-  put(&g_means[3 * i + 2], gp2);
-  for (int r = 0; r < 3; ++r) put(&g_ls[3 * i + r], gl[r]);
-  const double qnn = qn > 0.0 ? qn : 1.0;
-  put(&g_q[4 * i], (dw - dot * qw) / qnn);
-  put(&g_q[4 * i + 1], (dx - dot * qx) / qnn);
-  put(&g_q[4 * i + 2], (dy - dot * qy) / qnn);
-  put(&g_q[4 * i + 3], (dz - dot * qz) / qnn);
-  put(&g_logit[i], gop * o * (1.0 - o));
-  // SH gradients: sums over the views in registers, one batch of stores
-  // (zeros for a Gaussian without pairs)
-  float* gdst = g_sh + i * (K * 3);
-  if (accumulate) {
-    float old[K * 3];
-#pragma unroll
-    for (int k = 0; k < K * 3; ++k) old[k] = gdst[k];
-#pragma unroll
-    for (int k = 0; k < K * 3; ++k) gdst[k] = old[k] + gsh[k];
-  } else {
-#pragma unroll
-    for (int k = 0; k < K * 3; ++k) gdst[k] = gsh[k];
-  }
-  (void)sh_written;
+    const double dw = GR[1] * (-2 * qz) + GR[2] * (2 * qy) + GR[3] * (2 * qz) + GR[5] * (-2 * qx) +
+                      GR[6] * (-2 * qy) + GR[7] * (2 * qx);
+    const double dx = GR[1] * (2 * qy) + GR[2] * (2 * qz) + GR[3] * (2 * qy) + GR[4] * (-4 * qx) +
+                      GR[5] * (-2 * qw) + GR[6] * (2 * qz) + GR[7] * (2 * qw) + GR[8] * (-4 * qx);
+    const double dy = GR[0] * (-4 * qy) + GR[1] * (2 * qx) + GR[2] * (2 * qw) + GR[3] * (2 * qx) +
+                      GR[5] * (2 * qz) + GR[6] * (-2 * qw) + GR[7] * (2 * qz) + GR[8] * (-4 * qy);
+    const double dz = GR[0] * (-4 * qz) + GR[1] * (-2 * qw) + GR[2] * (2 * qx) + GR[3] * (2 * qw) +
+                      GR[4] * (-4 * qz) + GR[5] * (2 * qy) + GR[6] * (2 * qx) + GR[7] * (2 * qy);
+    const double dot = dw * qw + dx * qx + dy * qy + dz * qz;
+    const double o = 1.0 / (1.0 + exp(-(double)logit));
+    auto put = [&](float* dst, double val) { *dst = accumulate ? *dst + (float)val : (float)val; };
+    put(&g_means[3 * i], gp0);
+    put(&g_means[3 * i + 1], gp1);
+    put(&g_means[3 * i + 2], gp2);
+    for (int r = 0; r < 3; ++r) put(&g_ls[3 * i + r], gl[r]);
+    const double qnn = qn > 0.0 ? qn : 1.0;
+    put(&g_q[4 * i], (dw - dot * qw) / qnn);
+    put(&g_q[4 * i + 1], (dx - dot * qx) / qnn);
+    put(&g_q[4 * i + 2], (dy - dot * qy) / qnn);
+    put(&g_q[4 * i + 3], (dz - dot * qz) / qnn);
+    put(&g_logit[i], gop * o * (1.0 - o));
+  };
+  using T = std::true_type;
+  using F = std::false_type;
+  if (!SPLIT) run(T{}, T{});
+  else if (role == 0) run(T{}, F{});
+  else run(F{}, T{});
 }
 
 // Zero of the five gradient arrays (59 floats per Gaussian at degree 3).
@@ -427,6 +483,8 @@ hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float*
                               bool zeroed, hipStream_t s) {
   const int64_t blocks = P.proj_blocks;
   if (blocks == 0) return hipSuccess;
+  // SPLIT workgroups (no camera tangent) take 64 Gaussians each
+  const int64_t split_blocks = (P.n + kWave - 1) / kWave;
   double* pose_part = dL_dpose ? ws_at<double>(ws, P.off_pose_part) : nullptr;
   const bool compact = P.vt.n_views == 1;
   if (project_bwd_zeroes(P, accumulate) && !zeroed) {
@@ -434,7 +492,8 @@ hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float*
     if (e != hipSuccess) return e;
   }
 #define GS_PB1(D, PO, CO)                                                                         \
-  hipLaunchKernelGGL((k_project_bwd<D, PO, CO>), dim3((unsigned)blocks), dim3(kProjThreads), 0, s, \
+  hipLaunchKernelGGL((k_project_bwd<D, PO, CO, !PO>), dim3((unsigned)(PO ? blocks : split_blocks)), \
+                     dim3(kProjThreads), 0, s,                                                      \
                      g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, P.n, cams, P.vt,      \
                      ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_tt),                    \
                      ws_at<uint32_t>(ws, P.off_poff),                                              \
