@@ -571,25 +571,70 @@ __global__ void __launch_bounds__(kWave) k_render_bwd(
 // needs nothing from the other buckets of its tile: buckets are the unit of
 // parallelism, which also splits long tile lists over many wavefronts.
 //
-// Pixel states move along a diagonal: at step t lane l applies its splat to
-// pixel j = t - l and hands the new state to lane l + 1 (DPP wave shift
-// right by one lane); lane 0 takes pixel t's stored state.  Lane l thus
-// meets every pixel with the state left by the splats in front of its own,
-// evaluates alpha with the forward's code and blends forward exactly as the
-// forward did (T * (1 - alpha), bit for bit).  What lies behind the splat is
-// the final pixel minus the front part: with per-pixel loss gradients gC, gD
-// the state carries Q = gC . C + gD . D, and behind = P - Q_next where
-// P = gC . (colour output) + gD . (depth output).  Each lane accumulates its
-// own splat's ten partial gradients over the tile's pixels and writes them
-// once: no reduction over lanes and no atomics.
-
+// All lanes of a segment take the same pixel at each step.  Lane l
+// evaluates its splat's alpha with the forward's code (the same bits, so
+// the same skip decisions; the forward's stop rule is its stored last
+// position).  What lies in front of lane l's splat at the pixel is the
+// segment's stored state advanced over the blended splats of lanes < l: the
+// transmittance is T_in times an exclusive prefix product of (1 - alpha), and
+// the front part of the loss-weighted output Q = gC . C + gD . D an
+// inclusive prefix sum of alpha T gC . c, both taken across the lanes with
+// DPP.  What lies behind the splat is the final pixel minus the front part,
+// P - Q with P = gC . (colour output) + gD . (depth output).  A bucket thus
+// costs one step per pixel, with no pipeline to fill or drain.  Each lane
+// accumulates its own splat's ten partial gradients over the tile's pixels
+// and writes them once: no reduction over lanes and no atomics.
+//
 // Buckets with at most 32 pairs share a wavefront: each 32-lane half runs
-// its own bucket (the lane starting a half takes stored states, like lane
-// 0), so the diagonal costs Pix_tile + 31 steps for two buckets.  The
-// binning queues buckets by size (more than 32 pairs / at most 32).
-template <int TW, int TH>
+// its own bucket (the scans stop at the half), two buckets per NPX steps.
+// The binning queues buckets by size (more than 32 pairs / at most 32).
+
+// DPP move in which a lane without a source (or in a masked row) gets `old`.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp_or(float old, float x) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), CTRL, ROW_MASK, 0xF, false));
+}
+
+// Inclusive product / sum over segments of SEG (64 or 32) lanes, in place:
+// steps in rows of 16 (row_shr 1, 2, 4, 8), then the ends of rows 0 and 2
+// into rows 1 and 3 (row_bcast:15), and for 64 lanes the end of row 1 into
+// rows 2 and 3 (row_bcast:31).  Each step is one DPP multiply or add whose
+// lanes without a source (or outside the row mask) are not written, i.e.
+// keep their value; each is preceded by the two wait states a DPP read of a
+// VGPR written by the previous VALU instruction needs.
+#define GS_DPP_STEP(OP, CTRL) "s_nop 1\n\t" OP " %0, %0, %0 " CTRL " bank_mask:0xf\n\t"
+#define GS_SEG_SCAN32(OP)                              \
+  GS_DPP_STEP(OP, "row_shr:1 row_mask:0xf")            \
+  GS_DPP_STEP(OP, "row_shr:2 row_mask:0xf")            \
+  GS_DPP_STEP(OP, "row_shr:4 row_mask:0xf")            \
+  GS_DPP_STEP(OP, "row_shr:8 row_mask:0xf")            \
+  GS_DPP_STEP(OP, "row_bcast:15 row_mask:0xa")
+template <int SEG>
+__device__ __forceinline__ float seg_scan_mul(float x) {
+  // (the trailing wait states cover a DPP read of the result right after)
+  if (SEG == 64)
+    asm volatile(GS_SEG_SCAN32("v_mul_f32_dpp") GS_DPP_STEP("v_mul_f32_dpp", "row_bcast:31 row_mask:0xc")
+                 "s_nop 1" : "+v"(x));
+  else
+    asm volatile(GS_SEG_SCAN32("v_mul_f32_dpp") "s_nop 1" : "+v"(x));
+  return x;
+}
+template <int SEG>
+__device__ __forceinline__ float seg_scan_add(float x) {
+  if (SEG == 64)
+    asm volatile(GS_SEG_SCAN32("v_add_f32_dpp") GS_DPP_STEP("v_add_f32_dpp", "row_bcast:31 row_mask:0xc")
+                 : "+v"(x));
+  else
+    asm volatile(GS_SEG_SCAN32("v_add_f32_dpp") : "+v"(x));
+  return x;
+}
+#undef GS_SEG_SCAN32
+#undef GS_DPP_STEP
+
+template <int TW, int TH, int SEG>
 __device__ __forceinline__ void splat_wave(
-    int seg_lanes, const uint2* __restrict__ queue, uint32_t q_first, uint32_t q_count,
+    const uint2* __restrict__ queue, uint32_t q_first, uint32_t q_count,
     const Rec* __restrict__ lrec,
     const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ tile_last, const uint32_t* __restrict__ boff,
@@ -598,11 +643,11 @@ __device__ __forceinline__ void splat_wave(
     const float* __restrict__ dL_dcolor, const float* __restrict__ dL_ddepth,
     const float* __restrict__ target_rgb, const float* __restrict__ target_depth, int fused,
     float lambda_depth, float* __restrict__ grad_pair, float4* pxa, float4* pxb, double2* pxc) {
+  static_assert(SEG == 64 || SEG == 32, "segment of 64 or 32 lanes");
   constexpr int NPX = TW * TH;
   constexpr int LOG_TW = TW == 16 ? 4 : 3;
   const int lane = threadIdx.x;
-  const int lg = seg_lanes == 64 ? 6 : 5;
-  const int seg = lane >> lg, ls = lane & (seg_lanes - 1);
+  const int seg = SEG == 64 ? 0 : lane >> 5, ls = lane & (SEG - 1);
   const uint32_t qi = q_first + (uint32_t)seg;
   const bool has = qi < q_count;
   const uint2 ent = has ? queue[qi] : make_uint2(0u, 0u);
@@ -623,11 +668,7 @@ __device__ __forceinline__ void splat_wave(
     gp[0] = z; gp[1] = z; gp[2] = z;
   }
   const bool active = has && q0 < tl;  // uniform over the segment
-  const int nl = active ? (int)min((uint32_t)seg_lanes, tl - q0) : 0;
-  // steps: the longest live bucket of the wave decides
-  int nl_max = nl;
-  if (seg_lanes == 32) nl_max = max(nl, __shfl_xor(nl, 32, kWave));
-  if (nl_max == 0) return;  // uniform
+  if (ballot64(active) == 0) return;   // uniform
 
   const int v = active ? find_view(vt, gtile) : 0;
   const ViewInfo vi = vt.v[v];
@@ -639,48 +680,46 @@ __device__ __forceinline__ void splat_wave(
   double2* sc = pxc + seg * NPX;  // sample point of each pixel
 
   // pixel table of the segment's tile: loss gradients, P, last position,
-  // stored state (T, Q)
-  if (active) {
-    const float* cp = ckpt + (int64_t)(boff[gtile] + k) * (kStateFloats * NPX);
-    for (int j = ls; j < NPX; j += seg_lanes) {
-      const int px = tx0 + (j & (TW - 1)), py = ty0 + (j >> LOG_TW);
-      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 1.f, 0.f);
-      if (px < vi.W && py < vi.H) {
-        const int64_t pl = (int64_t)py * vi.W + px;
-        const int64_t pix = (int64_t)vi.pix_off + pl;
-        const int64_t cbase = 3 * (int64_t)vi.pix_off + pl;
-        const float o0 = color[cbase], o1 = color[cbase + npx], o2 = color[cbase + 2 * npx];
-        const float od = depth[pix];
-        if (fused) {
-          const float inv3 = 1.0f / (3.0f * (float)npx);
-          const float d0 = o0 - target_rgb[cbase];
-          const float d1 = o1 - target_rgb[cbase + npx];
-          const float d2 = o2 - target_rgb[cbase + 2 * npx];
-          a.x = d0 > 0.0f ? inv3 : (d0 < 0.0f ? -inv3 : 0.0f);
-          a.y = d1 > 0.0f ? inv3 : (d1 < 0.0f ? -inv3 : 0.0f);
-          a.z = d2 > 0.0f ? inv3 : (d2 < 0.0f ? -inv3 : 0.0f);
-          if (target_depth) {
-            const float dd = od - target_depth[pix];
-            const float sc = lambda_depth / (float)npx;
-            a.w = dd > 0.0f ? sc : (dd < 0.0f ? -sc : 0.0f);
-          }
-        } else {
-          a.x = dL_dcolor[cbase];
-          a.y = dL_dcolor[cbase + npx];
-          a.z = dL_dcolor[cbase + 2 * npx];
-          a.w = dL_ddepth ? dL_ddepth[pix] : 0.0f;
+  // stored state (T, Q); an inactive segment gets last = 0 (nothing blended)
+  for (int j = ls; j < NPX; j += SEG) {
+    const int px = tx0 + (j & (TW - 1)), py = ty0 + (j >> LOG_TW);
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 1.f, 0.f);
+    if (active && px < vi.W && py < vi.H) {
+      const float* cp = ckpt + (int64_t)(boff[gtile] + k) * (kStateFloats * NPX);
+      const int64_t pl = (int64_t)py * vi.W + px;
+      const int64_t pix = (int64_t)vi.pix_off + pl;
+      const int64_t cbase = 3 * (int64_t)vi.pix_off + pl;
+      const float o0 = color[cbase], o1 = color[cbase + npx], o2 = color[cbase + 2 * npx];
+      const float od = depth[pix];
+      if (fused) {
+        const float inv3 = 1.0f / (3.0f * (float)npx);
+        const float d0 = o0 - target_rgb[cbase];
+        const float d1 = o1 - target_rgb[cbase + npx];
+        const float d2 = o2 - target_rgb[cbase + 2 * npx];
+        a.x = d0 > 0.0f ? inv3 : (d0 < 0.0f ? -inv3 : 0.0f);
+        a.y = d1 > 0.0f ? inv3 : (d1 < 0.0f ? -inv3 : 0.0f);
+        a.z = d2 > 0.0f ? inv3 : (d2 < 0.0f ? -inv3 : 0.0f);
+        if (target_depth) {
+          const float dd = od - target_depth[pix];
+          const float sc = lambda_depth / (float)npx;
+          a.w = dd > 0.0f ? sc : (dd < 0.0f ? -sc : 0.0f);
         }
-        b.x = a.x * o0 + a.y * o1 + a.z * o2 + a.w * od;
-        b.y = __uint_as_float(last[pix]);
-        if (k > 0) {  // the first bucket starts from T = 1 and nothing accumulated
-          b.z = cp[j];
-          b.w = a.x * cp[NPX + j] + a.y * cp[2 * NPX + j] + a.z * cp[3 * NPX + j] + a.w * cp[4 * NPX + j];
-        }
+      } else {
+        a.x = dL_dcolor[cbase];
+        a.y = dL_dcolor[cbase + npx];
+        a.z = dL_dcolor[cbase + 2 * npx];
+        a.w = dL_ddepth ? dL_ddepth[pix] : 0.0f;
       }
-      sa[j] = a;
-      sb[j] = b;
-      sc[j] = make_double2((double)px + 0.5, (double)py + 0.5);
+      b.x = a.x * o0 + a.y * o1 + a.z * o2 + a.w * od;
+      b.y = __uint_as_float(last[pix]);
+      if (k > 0) {  // the first bucket starts from T = 1 and nothing accumulated
+        b.z = cp[j];
+        b.w = a.x * cp[NPX + j] + a.y * cp[2 * NPX + j] + a.z * cp[3 * NPX + j] + a.w * cp[4 * NPX + j];
+      }
     }
+    sa[j] = a;
+    sb[j] = b;
+    sc[j] = make_double2((double)px + 0.5, (double)py + 0.5);
   }
   __syncthreads();
 
@@ -698,54 +737,44 @@ __device__ __forceinline__ void splat_wave(
   float g[10];
 #pragma unroll
   for (int f = 0; f < 10; ++f) g[f] = 0.0f;
-  float Tout = 1.0f, Qout = 0.0f;
-  const int steps = NPX + nl_max - 1;
 #pragma unroll 2
-  for (int t = 0; t < steps; ++t) {
-    float Tc = dpp<0x138>(Tout);  // wave_shr:1, state of lane - 1
-    float Qc = dpp<0x138>(Qout);
-    const int j = t - ls;
-    const bool vj = (unsigned)j < (unsigned)NPX;
-    const int jc = vj ? j : 0;
-    const float4 b = sb[jc];
-    if (ls == 0) {
-      Tc = b.z;
-      Qc = b.w;
-    }
-    if (vj && live && pos < __float_as_uint(b.y)) {
-      const double2 sxy = sc[jc];
-      double dx, dy;
-      float G, oG, a;
-      if (eval_alpha(r, sxy.x, sxy.y, dx, dy, G, oG, a)) {
-        const float4 gc = sa[jc];
-        const float om = 1.0f - a;
-        const float inv_om = __builtin_amdgcn_rcpf(om);
-        const float wgt = a * Tc;
-        const float front = gc.x * r.r + gc.y * r.g + gc.z * r.b + gc.w * r.z;
-        const float Qn = fmaf(wgt, front, Qc);
-        const float g_alpha = Tc * front - (b.x - Qn) * inv_om;
-        g[0] = fmaf(wgt, gc.x, g[0]);
-        g[1] = fmaf(wgt, gc.y, g[1]);
-        g[2] = fmaf(wgt, gc.z, g[2]);
-        g[3] = fmaf(wgt, gc.w, g[3]);
-        // moments of t = gpow dx, u = gpow dy; the conic and mean
-        // partials are formed from them once, after the pixels
-        const bool open = oG <= kAlphaMax;
-        const float gpow = open ? a * g_alpha : 0.0f;
-        const float fx = (float)dx, fy = (float)dy;
-        const float t = gpow * fx, u = gpow * fy;
-        g[4] = fmaf(open ? G : 0.0f, g_alpha, g[4]);
-        g[5] = fmaf(t, fx, g[5]);
-        g[6] = fmaf(t, fy, g[6]);
-        g[7] = fmaf(u, fy, g[7]);
-        g[8] += t;
-        g[9] += u;
-        Tc = Tc * om;
-        Qc = Qn;
-      }
-    }
-    Tout = Tc;
-    Qout = Qc;
+  for (int j = 0; j < NPX; ++j) {
+    const float4 b = sb[j];  // P, last, T_in, Q_in of the segment's pixel j
+    const double2 sxy = sc[j];
+    // alpha as in the forward (same bits)
+    const double dx = r.mx - sxy.x, dy = r.my - sxy.y;
+    const double pw = fma(dx, fma(r.ca, dx, r.cb * dy), (r.cc * dy) * dy);
+    const float G = __builtin_amdgcn_exp2f((float)(pw * kLog2e));
+    const float oG = r.o * G;
+    const float a = fminf(kAlphaMax, oG);
+    const bool hit = live && pos < __float_as_uint(b.y) && !(pw > 0.0) && a >= kAlphaMin;
+    if (__builtin_amdgcn_ballot_w64(hit) == 0) continue;  // no splat of the wavefront is blended here
+    const float4 gc = sa[j];
+    const float om = 1.0f - a;
+    // transmittance in front of the splat
+    const float Tf = b.z * dpp_or<0x138>(1.0f, seg_scan_mul<SEG>(hit ? om : 1.0f));
+    const float Tl = (SEG == 32 && ls == 0) ? b.z : Tf;  // wave_shr crosses the halves
+    const float wgt = hit ? a * Tl : 0.0f;
+    const float front = fmaf(gc.w, r.z, fmaf(gc.z, r.b, fmaf(gc.y, r.g, gc.x * r.r)));
+    const float Qn = b.w + seg_scan_add<SEG>(wgt * front);  // front part after the splat
+    const float inv_om = __builtin_amdgcn_rcpf(om);
+    const float g_alpha = fmaf(-(b.x - Qn), inv_om, Tl * front);
+    g[0] = fmaf(wgt, gc.x, g[0]);
+    g[1] = fmaf(wgt, gc.y, g[1]);
+    g[2] = fmaf(wgt, gc.z, g[2]);
+    g[3] = fmaf(wgt, gc.w, g[3]);
+    // moments of t = gpow dx, u = gpow dy; the conic and mean partials are
+    // formed from them once, after the pixels
+    const bool open = hit && oG <= kAlphaMax;
+    const float gpow = open ? a * g_alpha : 0.0f;
+    const float fx = (float)dx, fy = (float)dy;
+    const float t = gpow * fx, u = gpow * fy;
+    g[4] = fmaf(open ? G : 0.0f, g_alpha, g[4]);
+    g[5] = fmaf(t, fx, g[5]);
+    g[6] = fmaf(t, fy, g[6]);
+    g[7] = fmaf(u, fy, g[7]);
+    g[8] += t;
+    g[9] += u;
   }
   if (live) {
     float4* gp = reinterpret_cast<float4*>(grad_pair + (int64_t)sorted_vals[s + pos] * kPairGrad);
@@ -775,11 +804,11 @@ __global__ void __launch_bounds__(kWave) k_render_bwd_splat(
   const uint32_t w_full = q_full, w_half = (q_half + 1) / 2;
   for (uint32_t wv = blockIdx.x; wv < w_full + w_half; wv += gridDim.x) {
     if (wv < w_full)
-      splat_wave<TW, TH>(64, bq, wv, q_full, lrec, sorted_vals, ranges, tile_last,
-                         boff, ckpt, vt, color, depth, last, dL_dcolor, dL_ddepth, target_rgb,
-                         target_depth, fused, lambda_depth, grad_pair, pxa, pxb, pxc);
+      splat_wave<TW, TH, 64>(bq, wv, q_full, lrec, sorted_vals, ranges, tile_last,
+                             boff, ckpt, vt, color, depth, last, dL_dcolor, dL_ddepth, target_rgb,
+                             target_depth, fused, lambda_depth, grad_pair, pxa, pxb, pxc);
     else
-      splat_wave<TW, TH>(32, bq + bq_stride, 2 * (wv - w_full), q_half, lrec,
+      splat_wave<TW, TH, 32>(bq + bq_stride, 2 * (wv - w_full), q_half, lrec,
                          sorted_vals, ranges, tile_last, boff, ckpt, vt, color, depth, last,
                          dL_dcolor, dL_ddepth, target_rgb, target_depth, fused, lambda_depth,
                          grad_pair, pxa, pxb, pxc);
