@@ -254,7 +254,13 @@ def main():
             mark()
             gsr.project_bwd(plan, it.ws, params, cams, it.grads, stream=stream)
             mark()
-            gsr.adam_step(groups, 1, step_dev=it.step_dev, stream=stream)
+            if record:
+                # one kernel between the marks: an explicit step launches
+                # k_adam alone (with the device counter a one-thread launch
+                # that advances it follows)
+                gsr.adam_step(groups, 1, stream=stream)
+            else:
+                gsr.adam_step(groups, 1, step_dev=it.step_dev, stream=stream)
             mark()
             return marks
 
@@ -307,9 +313,14 @@ def main():
         other = alu_roofline("render_fwd" if dominant == "render_bwd_raster" else "render_bwd_raster")
     else:
         gbs = bytes_[dominant] / (stage_ms[dominant] * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(gbs, 1),
+        kname = {"adam": "k_adam", "project_bwd": "k_project_bwd<3,false,true,true>",
+                 "preprocess": "k_preprocess<3>"}.get(dominant)
+        api = {"adam": "gs_adam_step", "project_bwd": "gs_project_bwd",
+               "preprocess": "gs_preprocess"}.get(dominant, dominant)
+        roofline = {"bound": "hbm", "kernel": f"{kname or dominant} ({api})", "achieved": round(gbs, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                    "traffic": None}
+                    "traffic": measured_traffic(kname) if kname else None,
+                    "work": f"{bytes_[dominant]} algorithmic bytes per launch"}
         other = alu_roofline("render_bwd_raster")
     hbm_gbs = total_bytes / (ms_graph * 1e-3) / 1e9
 
