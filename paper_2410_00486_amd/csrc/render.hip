@@ -181,6 +181,9 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec
   const uint32_t s = known ? known->start : ranges[2 * (int64_t)gtile];
   const uint32_t e = known ? known->end : ranges[2 * (int64_t)gtile + 1];
   const bool fresh = known && known->fresh, staged = known && known->staged;
+  // the long lists start first (work order) and end last: their wavefronts
+  // take precedence at instruction issue over the short tiles sharing a SIMD
+  if (e - s >= (uint32_t)kWave) __builtin_amdgcn_s_setprio(2);
 
   double sx[PPL], sy[PPL];
   float T[PPL], c0[PPL], c1[PPL], c2[PPL], D[PPL];
@@ -207,7 +210,7 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec
   for (uint32_t b = s; more && b < e; b += (uint32_t)B) {
     if (ballot64(active()) == 0) break;
     const int nb = (int)min((uint32_t)B, e - b);
-    if (!(staged && b == s)) {  // a staged list fits the first batch
+    if (!(staged && b == s)) {  // the sort staged the first batch
       __syncthreads();
       stage(srec, nullptr, lrec, nullptr, b, nb, lane, fresh);
       __syncthreads();
@@ -343,7 +346,7 @@ __global__ void __launch_bounds__(kWave) k_render_fwd(
   // and the range visible to every lane before the compositing reads them.
   auto tile = [&](int g) {
     if (sort.cnt) {
-      // a list of at most min(64, B) pairs is staged by the sort itself
+      // the list's first B records are staged by the sort itself
       const TileList L = sort_tile_wave(sort, g, (int)threadIdx.x,
                                         reinterpret_cast<uint64_t*>(smem), srec, B);
       __syncthreads();

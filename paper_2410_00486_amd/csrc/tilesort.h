@@ -10,7 +10,11 @@
 // number of smaller keys) and up to kTileSortSmall keys with a bitonic
 // network in LDS; longer lists (listed by the binning scan) go to 1024-thread
 // blocks, with the same network in LDS up to kTileSortLong keys and in place
-// in global memory beyond.
+// in global memory beyond.  The limit is low on purpose: inside a whole
+// iteration the wavefront that sorts a list also composites it, and a
+// long list sorted there would hold back the end of the forward (its
+// wavefront starts first but finishes last), while the binning sorts the
+// few long lists in parallel before the forward starts.
 //
 // The network keeps every merge ascending (the first compare of a merge
 // pairs i with its mirror in the block), so positions past the list end act
@@ -21,7 +25,7 @@
 
 namespace gs {
 
-constexpr uint32_t kTileSortSmall = 512;
+constexpr uint32_t kTileSortSmall = 128;
 constexpr uint32_t kTileSortLong = 16384;
 constexpr int kLongThreads = 1024;
 
@@ -116,8 +120,8 @@ struct TileSortArgs {
 // What a wavefront that sorted a tile knows about its list: the range
 // ((0, 0) when empty), whether this wavefront wrote the sorted records (then
 // a read of them inside the same kernel must not be served by the vector L1,
-// which may hold an older copy of the line), and whether they are also in
-// the staging LDS already (a list of at most 64 pairs).
+// which may hold an older copy of the line), and whether its first
+// stage_cap records are also in the staging LDS already.
 struct TileList {
   uint32_t start, end;
   bool fresh, staged;
@@ -127,8 +131,9 @@ struct TileList {
 // queue entries of tile t, then, for a list of at most kTileSortSmall pairs,
 // the sort and the sorted outputs.  sk: kTileSortSmall keys of LDS.
 // Longer lists are left to the long-list kernel.  stage (optional, at least
-// stage_cap records of LDS, may alias sk): a list of at most
-// min(64, stage_cap) pairs also lands there in list order.
+// stage_cap records of LDS, may alias sk): the list's first stage_cap
+// records also land there in list order (all of a list of at most 64 pairs
+// only if it fits).
 __device__ inline TileList sort_tile_wave(const TileSortArgs& A, int t, int lane, uint64_t* sk,
                                           Rec* stage = nullptr, int stage_cap = 0) {
   const uint64_t P = (uint64_t)A.fl[F_PAIRS];
@@ -174,7 +179,39 @@ __device__ inline TileList sort_tile_wave(const TileSortArgs& A, int t, int lane
   for (uint32_t k = lane; k < n; k += kWave) sk[k] = A.skey[start + k];
   __syncthreads();
   bitonic_sort(sk, n, lane, kWave);
-  for (uint32_t k = lane; k < n; k += kWave) emit_sorted(A.out, start + k, tkey, sk[k]);
+  // The lane's sorted keys are written out and their record ids looked up
+  // all at once (one memory round trip for all of them instead of one per
+  // position); the ids then wait in the keys' LDS for the record gathers.
+  constexpr int KMAX = kTileSortSmall / kWave;
+  const TileSortOut& o = A.out;
+  uint32_t r[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    const uint32_t k = (uint32_t)lane + (uint32_t)q * kWave;
+    r[q] = 0u;
+    if (k < n) {
+      const uint64_t key = sk[k];
+      const uint32_t g = (uint32_t)key;
+      o.keys[start + k] = tkey | (key >> 32);
+      o.vals[start + k] = g;
+      r[q] = o.pair_rec[g];
+    }
+  }
+  __syncthreads();  // every key has been read
+  uint32_t* sr = reinterpret_cast<uint32_t*>(sk);
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    const uint32_t k = (uint32_t)lane + (uint32_t)q * kWave;
+    if (k < n) sr[k] = r[q];
+  }
+  for (uint32_t k = lane; k < n; k += kWave) {  // this lane's own positions
+    const uint32_t rk = sr[k];
+    o.sorted_rec[start + k] = rk;
+    const float4* src = reinterpret_cast<const float4*>(o.rec + rk);
+    float4* dst = reinterpret_cast<float4*>(o.lrec + start + k);
+    const float4 a0 = src[0], a1 = src[1], a2 = src[2], a3 = src[3];
+    dst[0] = a0; dst[1] = a1; dst[2] = a2; dst[3] = a3;
+  }
   return L;
 }
 
