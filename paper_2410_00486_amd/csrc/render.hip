@@ -751,7 +751,7 @@ __device__ __forceinline__ void splat_wave(
     const float oG = r.o * G;
     const float a = fminf(kAlphaMax, oG);
     const bool hit = live && pos < __float_as_uint(b.y) && !(pw > 0.0) && a >= kAlphaMin;
-    if (__builtin_amdgcn_ballot_w64(hit) == 0) continue;  // no splat of the wavefront is blended here
+    // (no early exit when no lane is blended at this pixel: rare, and its test costs two VALU per step)
     const float4 gc = sa[j];
     const float om = 1.0f - a;
     // transmittance in front of the splat
