@@ -339,25 +339,26 @@ __global__ void __launch_bounds__(256) k_scatter(
   const int64_t ri = (int64_t)v * n + gi;                                 // record
   const uint64_t P = (uint64_t)fl[F_PAIRS];
   const bool over = fl[F_OVERFLOW] != 0;
-  uint32_t c = (gi < n && !over) ? tt[ri] : 0u;
-  uint32_t incl = c;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const uint32_t y = __shfl_up(incl, o, kWave);
-    if (lane >= o) incl += y;
-  }
-  const uint32_t total = __shfl(incl, kWave - 1, kWave);
+  const uint32_t c = (gi < n && !over) ? tt[ri] : 0u;
   const uint2 cp = chunk_pre[gw];
+  // the record's tile box and depth are fetched before the scan of the
+  // counts, which then runs while they are in flight (DPP, no LDS)
+  ushort4 r = make_ushort4(0, 0, 0, 0);
+  uint32_t dbits = 0;
+  if (c > 0) {
+    r = rect[ri];
+    dbits = __float_as_uint(rec[ri].z);
+  }
+  const uint32_t incl = scan_dpp<6>(c);
+  const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
   const uint64_t base64 = (uint64_t)cp.x + (incl - c);
   if ((uint64_t)cp.x + total > P) return;  // cannot happen without overflow (uniform)
   const uint64_t vmask = ballot64(c > 0);
-  uint32_t p0 = 0, dbits = 0, x0y0 = 0, tile0 = 0;
+  uint32_t p0 = 0, x0y0 = 0, tile0 = 0;
   if (c > 0) {
     p0 = (uint32_t)base64;
     poff[ri] = p0;
     vis_list[cp.y + (uint32_t)__popcll(vmask & lanemask_lt())] = (uint32_t)ri;
-    const ushort4 r = rect[ri];
-    dbits = __float_as_uint(rec[ri].z);
     x0y0 = (uint32_t)r.x | ((uint32_t)r.y << 16);
     tile0 = (uint32_t)(r.z - r.x);  // box width in tiles
   }
