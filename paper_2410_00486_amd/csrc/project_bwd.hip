@@ -4,8 +4,11 @@
 // recomputes the view's projection in FP64 and applies the chain rule
 // through conic -> EWA covariance -> Jacobian -> camera-space mean, the 3D
 // covariance (scale, rotation), the SH colour and the view direction, and
-// the opacity sigmoid.  Camera tangents (rho, phi) for a left perturbation of
-// each pose are reduced per workgroup (fixed order) and then per view.
+// the opacity sigmoid.  Without a camera tangent two threads (in two
+// wavefronts of one workgroup) share a Gaussian, one for the projection
+// chain and one for the colour chain.  Camera tangents (rho, phi) for a left
+// perturbation of each pose are reduced per workgroup (fixed order) and then
+// per view.
 #include <type_traits>
 
 #include "gs_internal.h"

@@ -1,5 +1,5 @@
-// a3-a5: per-tile compositing (Eq. (1)) and its pixel-wise backward
-// (Eqs. (2)-(4)).  One wave64 per tile: a lane owns PPL = tile pixels / 64
+// a3-a5: per-tile compositing (Eq. (1)), its pixel-wise backward
+// (Eqs. (2)-(4)) and the splat-wise backward (Sec. III-C-1, below).  One wave64 per tile: a lane owns PPL = tile pixels / 64
 // pixels (2x2 quads on 16x16 tiles, horizontal pairs on 16x8, one pixel on
 // 8x8), so the per-Gaussian work that does not depend on the pixel -- the
 // LDS read of the record, the wavefront reduction of the backward -- is
