@@ -210,7 +210,7 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_vis_list = take(nrec * 4);
   P->off_tile_cnt = take(T * 4);
   P->off_tile_start = take(T * 4);
-  P->off_long = take(T * 4);
+  P->off_long = take(T * 16);  // (tile, list start, pairs, -) per long list
   P->off_keys = take(cap * 8);
   P->off_scatter = take(cap * 8);
   P->off_vals = take(cap * 4);

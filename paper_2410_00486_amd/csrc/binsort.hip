@@ -70,7 +70,7 @@ struct ScanArgs {
   uint32_t* fstart;        // position of the tile's first full bucket in queue 0
   uint32_t* hstart;        // position of the tile's half bucket in queue 1
   uint32_t* order;         // work order of the render kernels, longest tiles first
-  uint32_t* long_list;     // tiles whose lists go to the long-list sort
+  uint4* long_list;        // (tile, list start, pairs, -) of the lists for the long-list sort
 };
 
 // Work order of the render kernels: tiles with at least kLongTile pairs
@@ -265,7 +265,8 @@ __global__ void __launch_bounds__(kScanBlock) k_scans(ScanArgs A, int64_t cap,
         if (t < T)
           A.order[c >= kLongTile ? s32[3] : (uint32_t)(T - 1 - (t - s32[3]))] = (uint32_t)t;
         // lists too long for one wavefront (rare): listed for the long-list sort
-        if (t < T && c > kTileSortSmall) A.long_list[atomicAdd(&n_long, 1u)] = (uint32_t)t;
+        if (t < T && c > kTileSortSmall)
+          A.long_list[atomicAdd(&n_long, 1u)] = make_uint4((uint32_t)t, (uint32_t)s64[0], c, 0u);
         ts[e] = (uint32_t)s64[0];
         bs[e] = s32[0];
         hs[e] = s32[1];
@@ -399,15 +400,14 @@ __global__ void __launch_bounds__(kWave) k_tile_sort(TileSortArgs A) {
 }
 
 __global__ void __launch_bounds__(kLongThreads) k_tile_sort_long(
-    uint32_t* __restrict__ cnt, const uint32_t* __restrict__ tstart,
-    const int32_t* __restrict__ fl, const uint32_t* __restrict__ long_list,
+    uint32_t* __restrict__ cnt, const int32_t* __restrict__ fl, const uint4* __restrict__ long_list,
     uint64_t* __restrict__ skey, TileSortOut out, int clear) {
   __shared__ uint64_t sk[kTileSortLong];
   const int n_long = fl[F_OVERFLOW] ? 0 : fl[F_LONG_TILES];
   for (int li = blockIdx.x; li < n_long; li += gridDim.x) {
-    const int t = (int)long_list[li];
-    const uint32_t n = cnt[t];
-    const uint32_t start = tstart[t];
+    const uint4 e = long_list[li];  // the scan recorded the list's start and length
+    const int t = (int)e.x;
+    const uint32_t start = e.y, n = e.z;
     const uint64_t tkey = (uint64_t)(uint32_t)t << 32;
     if (n <= kTileSortLong) {
       for (uint32_t k = threadIdx.x; k < n; k += kLongThreads) sk[k] = skey[start + k];
@@ -691,7 +691,7 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_sh
   uint32_t* hstart = splat ? ws_at<uint32_t>(ws, P.off_half_start) : nullptr;
   const uint2* chunk_cnt = ws_at<uint2>(ws, P.off_chunk_cnt);
   uint2* chunk_pre = ws_at<uint2>(ws, P.off_chunk_pre);
-  uint32_t* long_list = ws_at<uint32_t>(ws, P.off_long);
+  uint4* long_list = ws_at<uint4>(ws, P.off_long);
   ScanArgs sa{chunk_cnt, chunk_pre, P.n_chunks, tcnt, tstart, (int64_t)T,
               splat ? ws_at<uint32_t>(ws, P.off_boff) : nullptr, fstart, hstart,
               ws_at<uint32_t>(ws, P.off_order), long_list};
@@ -714,7 +714,7 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_sh
     if (!defer_short_sorts) hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)T), dim3(kWave), 0, s, A);
     const int long_grid = (int)std::min<int64_t>(T, 256);
     hipLaunchKernelGGL(k_tile_sort_long, dim3((unsigned)long_grid), dim3(kLongThreads), 0, s,
-                       tcnt, tstart, fl, long_list, skey, A.out, defer_short_sorts ? 0 : 1);
+                       tcnt, fl, long_list, skey, A.out, defer_short_sorts ? 0 : 1);
   }
   return hipGetLastError();
 }
