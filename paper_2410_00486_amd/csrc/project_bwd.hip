@@ -83,8 +83,13 @@ __device__ __forceinline__ void sh_backward(double x, double y, double z, const 
 // the other the colour chain (SH coefficients and the view-direction part of
 // the mean gradient, handed over in LDS after the views), so the two halves
 // of each Gaussian's chain run side by side, each with its own registers.
+// With one view (COMPACT) two more wavefronts join them for the sums of the
+// pair partials: wavefront w sums the w-th quarter of each Gaussian's pairs
+// (in pair order) into LDS and the chains add the four quarters in order, so
+// a Gaussian with many pairs waits for a quarter of the memory round trips.
+constexpr int kSumWaves = 4;
 template <int DEG, bool POSE, bool COMPACT, bool SPLIT>
-__global__ void __launch_bounds__(kProjThreads) k_project_bwd(
+__global__ void __launch_bounds__((SPLIT && COMPACT) ? kSumWaves * kWave : kProjThreads) k_project_bwd(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, int64_t n, const float* __restrict__ cams, ViewTable vt,
@@ -115,6 +120,45 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
   }
   __shared__ double spose[NW][6];
   __shared__ double sgv[3][kWave];
+  constexpr bool COOP = SPLIT && COMPACT;
+  // COOP: the pair sums of the four quarters (ten partials each)
+  __shared__ double ssum[COOP ? kSumWaves : 1][COOP ? 10 : 1][kWave];
+  if constexpr (COOP) {
+    const int w = role;  // every wavefront sums a quarter first
+    const int64_t ig = valid ? i : 0;
+    const uint32_t cnt = (valid && !overflow) ? tt[ig] : 0u;  // one view: record = Gaussian
+    const uint32_t lo = (uint32_t)(((uint64_t)cnt * (uint32_t)w) / kSumWaves);
+    const uint32_t hi = (uint32_t)(((uint64_t)cnt * (uint32_t)(w + 1)) / kSumWaves);
+    double s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (hi > lo) {
+      const float4* gpp = reinterpret_cast<const float4*>(grad_pair + (int64_t)poff[ig] * kPairGrad);
+      auto add = [&](const float4& a, const float4& b, const float4& c) {
+        s[0] += a.x; s[1] += a.y; s[2] += a.z; s[3] += a.w;
+        s[4] += b.x; s[5] += b.y; s[6] += b.z; s[7] += b.w;
+        s[8] += c.x; s[9] += c.y;
+      };
+      uint32_t k = lo;
+      for (; k + 8 <= hi; k += 8) {
+        float4 a[8], b[8], c[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          a[u] = gpp[3 * (k + u)];
+          b[u] = gpp[3 * (k + u) + 1];
+          c[u] = gpp[3 * (k + u) + 2];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) add(a[u], b[u], c[u]);
+      }
+      for (; k < hi; ++k) add(gpp[3 * k], gpp[3 * k + 1], gpp[3 * k + 2]);
+    }
+#pragma unroll
+    for (int c = 0; c < 10; ++c) ssum[w][c][lane] = s[c];
+    __syncthreads();
+    if (w >= 2) {  // helpers: only the hand-over barrier of the chains is left
+      __syncthreads();
+      return;
+    }
+  }
 
   // Every per-Gaussian input is loaded at once, unconditionally (row 0 for
   // an idle thread; n > 0 whenever the kernel runs), so that the loads issue
@@ -178,31 +222,38 @@ __global__ void __launch_bounds__(kProjThreads) k_project_bwd(
         // fixed-order sum of this (view, Gaussian)'s pair partials (the
         // colour chain needs the first three, the projection chain the rest)
         double g2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-        const float4* gpp = reinterpret_cast<const float4*>(grad_pair + (int64_t)poff_v * kPairGrad);
-        auto add = [&](const float4& a, const float4& b, const float4& c) {
-          if (DS) { g2[0] += a.x; g2[1] += a.y; g2[2] += a.z; }
-          if (DP) {
-            g2[3] += a.w;
-            g2[4] += b.x; g2[5] += b.y; g2[6] += b.z; g2[7] += b.w;
-            g2[8] += c.x; g2[9] += c.y;
-          }
-        };
-        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-        // loads of eight pairs are issued before their (in-order) additions,
-        // so a large Gaussian does not pay one memory round trip per tile
-        uint32_t k = 0;
-        for (; k + 8 <= cnt; k += 8) {
-          float4 a[8], b[8], c[8];
+        if constexpr (COOP) {
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            a[u] = gpp[3 * (k + u)];
-            b[u] = DP ? gpp[3 * (k + u) + 1] : z4;
-            c[u] = DP ? gpp[3 * (k + u) + 2] : z4;
-          }
+          for (int c = 0; c < 10; ++c)
+            if ((DS && c < 3) || (DP && c >= 3))
+              g2[c] = ((ssum[0][c][lane] + ssum[1][c][lane]) + ssum[2][c][lane]) + ssum[3][c][lane];
+        } else {
+          const float4* gpp = reinterpret_cast<const float4*>(grad_pair + (int64_t)poff_v * kPairGrad);
+          auto add = [&](const float4& a, const float4& b, const float4& c) {
+            if (DS) { g2[0] += a.x; g2[1] += a.y; g2[2] += a.z; }
+            if (DP) {
+              g2[3] += a.w;
+              g2[4] += b.x; g2[5] += b.y; g2[6] += b.z; g2[7] += b.w;
+              g2[8] += c.x; g2[9] += c.y;
+            }
+          };
+          const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+          // loads of eight pairs are issued before their (in-order) additions,
+          // so a large Gaussian does not pay one memory round trip per tile
+          uint32_t k = 0;
+          for (; k + 8 <= cnt; k += 8) {
+            float4 a[8], b[8], c[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) add(a[u], b[u], c[u]);
+            for (int u = 0; u < 8; ++u) {
+              a[u] = gpp[3 * (k + u)];
+              b[u] = DP ? gpp[3 * (k + u) + 1] : z4;
+              c[u] = DP ? gpp[3 * (k + u) + 2] : z4;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) add(a[u], b[u], c[u]);
+          }
+          for (; k < cnt; ++k) add(gpp[3 * k], DP ? gpp[3 * k + 1] : z4, DP ? gpp[3 * k + 2] : z4);
         }
-        for (; k < cnt; ++k) add(gpp[3 * k], DP ? gpp[3 * k + 1] : z4, DP ? gpp[3 * k + 2] : z4);
         gop += g2[4];
         const float* c = cams + (int64_t)v * GS_CAMERA_FLOATS;
         const double fx = c[0], fy = c[1];
@@ -496,7 +547,7 @@ hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float*
   }
 #define GS_PB1(D, PO, CO)                                                                         \
   hipLaunchKernelGGL((k_project_bwd<D, PO, CO, !PO>), dim3((unsigned)(PO ? blocks : split_blocks)), \
-                     dim3(kProjThreads), 0, s,                                                      \
+                     dim3((CO && !PO) ? kSumWaves * kWave : kProjThreads), 0, s,                    \
                      g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, P.n, cams, P.vt,      \
                      ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_tt),                    \
                      ws_at<uint32_t>(ws, P.off_poff),                                              \
