@@ -86,7 +86,10 @@ __global__ void __launch_bounds__(256) k_preprocess(
   double S00 = 0, S01 = 0, S02 = 0, S11 = 0, S12 = 0, S22 = 0, o = 0;
   const double p[3] = {pf[0], pf[1], pf[2]};
   if (ok) {
-    qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+    // FP64 quotients by a shared denominator as products with its reciprocal
+    // (within an ulp of FP64: far below anything the float outputs resolve)
+    const double iqn = 1.0 / qn;
+    qw *= iqn; qx *= iqn; qy *= iqn; qz *= iqn;
     const double R00 = 1 - 2 * (qy * qy + qz * qz), R01 = 2 * (qx * qy - qw * qz), R02 = 2 * (qx * qz + qw * qy);
     const double R10 = 2 * (qx * qy + qw * qz), R11 = 1 - 2 * (qx * qx + qz * qz), R12 = 2 * (qy * qz - qw * qx);
     const double R20 = 2 * (qx * qz - qw * qy), R21 = 2 * (qy * qz + qw * qx), R22 = 1 - 2 * (qx * qx + qy * qy);
@@ -120,14 +123,15 @@ __global__ void __launch_bounds__(256) k_preprocess(
       bool vis = tz > near_z;
       double mx = 0, my = 0, A = 0, B = 0, C = 0, det = 0;
       if (vis) {
-        mx = fx * tx / tz + cx;
-        my = fy * ty / tz + cy;
+        const double itz = 1.0 / tz;
+        mx = fx * tx * itz + cx;
+        my = fy * ty * itz + cy;
         const double limx = 1.3 * (double)vi.W / (2.0 * fx);
         const double limy = 1.3 * (double)vi.H / (2.0 * fy);
-        const double u = fmin(limx, fmax(-limx, tx / tz));
-        const double w = fmin(limy, fmax(-limy, ty / tz));
+        const double u = fmin(limx, fmax(-limx, tx * itz));
+        const double w = fmin(limy, fmax(-limy, ty * itz));
         // rows of T2 = J W
-        const double j00 = fx / tz, j02 = -fx * u / tz, j11 = fy / tz, j12 = -fy * w / tz;
+        const double j00 = fx * itz, j02 = -fx * u * itz, j11 = fy * itz, j12 = -fy * w * itz;
         const double a0 = j00 * W0 + j02 * W6, a1 = j00 * W1 + j02 * W7, a2 = j00 * W2 + j02 * W8;
         const double b0 = j11 * W3 + j12 * W6, b1 = j11 * W4 + j12 * W7, b2 = j11 * W5 + j12 * W8;
         // Sigma a, Sigma b
@@ -158,10 +162,12 @@ __global__ void __launch_bounds__(256) k_preprocess(
         hx = hx * (1.0 + 1e-4) + 1e-3;
         hy = hy * (1.0 + 1e-4) + 1e-3;
         const double tw = vt.tw, th = vt.th;
-        x0 = (int)fmax(0.0, fmin((double)vi.tiles_x, floor((mx - hx) / tw)));
-        y0 = (int)fmax(0.0, fmin((double)vi.tiles_y, floor((my - hy) / th)));
-        x1 = (int)fmax(0.0, fmin((double)vi.tiles_x, floor((mx + hx) / tw) + 1.0));
-        y1 = (int)fmax(0.0, fmin((double)vi.tiles_y, floor((my + hy) / th) + 1.0));
+        // tile sides are powers of two: the products are the exact quotients
+        const double itw = 1.0 / tw, ith = 1.0 / th;
+        x0 = (int)fmax(0.0, fmin((double)vi.tiles_x, floor((mx - hx) * itw)));
+        y0 = (int)fmax(0.0, fmin((double)vi.tiles_y, floor((my - hy) * ith)));
+        x1 = (int)fmax(0.0, fmin((double)vi.tiles_x, floor((mx + hx) * itw) + 1.0));
+        y1 = (int)fmax(0.0, fmin((double)vi.tiles_y, floor((my + hy) * ith) + 1.0));
         vis = (x1 > x0) && (y1 > y0);
       }
       if (vis && !sh_loaded) {
@@ -202,9 +208,10 @@ __global__ void __launch_bounds__(256) k_preprocess(
         Rec r;
         r.mx = mx;
         r.my = my;
-        r.ca = -0.5 * (C / det);
-        r.cb = B / det;
-        r.cc = -0.5 * (A / det);
+        const double idet = 1.0 / det;
+        r.ca = -0.5 * (C * idet);
+        r.cb = B * idet;
+        r.cc = -0.5 * (A * idet);
         r.o = (float)o;
         r.z = (float)tz;
         r.r = rgb[0];
