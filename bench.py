@@ -126,7 +126,7 @@ def main():
                           "launches": 5}))
         return
     t_setup = time.time()
-    w = scenes.config2()
+    w = scenes.room_1200x680()
     cam = w.cameras[0]
     view_wh = [(cam.width, cam.height)]
     cams = gsr.cameras_tensor([cam], dev)
@@ -337,7 +337,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 (quadratic form and projection in f64)",
         "data": "synthetic (seeded indoor room, shaped like the paper's RGB-D sequences)",
-        "config": {"workload": "config2: 1 view 1200x680 fx=fy=600, 300k Gaussians SH3, "
+        "config": {"workload": "room_1200x680: 1 view 1200x680 fx=fy=600, 300k Gaussians SH3, "
                                "L1 RGB + 0.1 L1 depth, Adam, HIP graph per iteration",
                    "tile": best["tile"], "lds_batch": best["lds_batch"], "chunk": best["chunk"],
                    "persistent": bool(best["persistent"]), "backward": args.bwd},
@@ -475,7 +475,7 @@ def bench_batched(args, dev):
     from paper_2410_00486_amd import tune
     from synth import scenes
 
-    w = scenes.config4()
+    w = scenes.keyframes8_mixed()
     cams_l = w.cameras
     view_wh = [(c.width, c.height) for c in cams_l]
     cams = gsr.cameras_tensor(cams_l, dev)
@@ -550,7 +550,7 @@ def bench_batched(args, dev):
             plain_iter()
     torch.cuda.synchronize()
     ms_p = (time.perf_counter() - t0) * 1e3 / args.steps
-    out = {"workload": "config4: 8 keyframes mixed {640x480,1200x680,320x240}, 500k SH3",
+    out = {"workload": "keyframes8_mixed: 8 keyframes mixed {640x480,1200x680,320x240}, 500k SH3",
            "views": view_wh, "visible_per_view": vis, "visible_total": vis_total,
            "batched_persistent_graph_iters_per_s": round(1e3 / ms_b, 2),
            "plain_per_view_iters_per_s": round(1e3 / ms_p, 2),

@@ -9,14 +9,14 @@ parameters the GPU optimises); the oracle upcasts the same arrays to float64.
 Workloads (sizes and distributions follow the indoor RGB-D mapping setting of
 CaRtGS, Sec. IV-A; the datasets themselves are not used or reproduced):
 
-* ``config1`` -- 128x96 pinhole, 2,000 Gaussians in a slab in front of an
+* ``slab_128x96`` -- 128x96 pinhole, 2,000 Gaussians in a slab in front of an
   identity camera, SH degree 0, random target image.
-* ``config2`` -- 1200x680 view inside a 6x5x3 m box room with 20 boxes,
+* ``room_1200x680`` -- 1200x680 view inside a 6x5x3 m box room with 20 boxes,
   300k Gaussians seeded on the surfaces, SH degree 3.
-* ``config3`` -- 640x480 view of a 150k-Gaussian room, pose perturbed from
+* ``room_640x480_pose`` -- 640x480 view of a 150k-Gaussian room, pose perturbed from
   the ground truth for the camera-gradient check.
-* ``config4`` -- 8 keyframes of mixed resolution over a shared 500k pool.
-* ``config5`` -- 16 keyframes at 1200x680 over a 2M-Gaussian four-room
+* ``keyframes8_mixed`` -- 8 keyframes of mixed resolution over a shared 500k pool.
+* ``keyframes16_1200x680`` -- 16 keyframes at 1200x680 over a 2M-Gaussian four-room
   layout with 30% near-transparent Gaussians.
 
 Conventions: world z is up; cameras look along their +z axis with +x right
@@ -267,7 +267,7 @@ def _inside_room_camera(rng, width, height, f, x0=0.0, y0=0.0):
 # workloads
 # ----------------------------------------------------------------------------
 
-def config1(seed: int = 1001, n: int = 2000) -> Workload:
+def slab_128x96(seed: int = 1001, n: int = 2000) -> Workload:
     """128x96, fx=fy=100, identity pose, N Gaussians in x,y in [-1,1], z in [2,4]."""
     rng = np.random.default_rng(seed)
     means = np.stack([rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(2, 4, n)], 1)
@@ -279,18 +279,18 @@ def config1(seed: int = 1001, n: int = 2000) -> Workload:
     scene = Scene(_f32(means), _f32(log_scales), _f32(quats), _f32(logits), _f32(sh), 0)
     cam = Camera(128, 96, 100.0, 100.0, 64.0, 48.0, _f32(np.eye(3)), _f32(np.zeros(3)))
     target = _f32(rng.uniform(0.0, 1.0, size=(3, 96, 128)))
-    return Workload("config1_128x96_2k_sh0", scene, [cam], [target], None, 0.0,
+    return Workload("slab_128x96_2k_sh0", scene, [cam], [target], None, 0.0,
                     notes="L1 RGB against a uniform random target")
 
 
-def config2(seed: int = 1002, n: int = 300_000, width: int = 1200, height: int = 680,
+def room_1200x680(seed: int = 1002, n: int = 300_000, width: int = 1200, height: int = 680,
             f: float = 600.0) -> Workload:
     rng = np.random.default_rng(seed)
     faces = _room_faces(0.0, 0.0) + _box_faces(rng, 0.0, 0.0, 20)
     scene = _room_gaussians(rng, n, faces, -4.5, 0.4, 3)
     cam = _inside_room_camera(rng, width, height, f)
     target_scene = _perturbed(rng, scene)
-    return Workload("config2_1200x680_300k_sh3", scene, [cam], None, None, 0.1,
+    return Workload("room_1200x680_300k_sh3", scene, [cam], None, None, 0.1,
                     target_scene=target_scene,
                     notes="L1 RGB + 0.1 L1 depth against a render of perturbed params")
 
@@ -309,14 +309,14 @@ def perturb_camera(cam: Camera, xi) -> Camera:
     return dataclasses.replace(cam, R=_f32(R), t=_f32(t))
 
 
-def config3(seed: int = 1003, n: int = 150_000) -> Workload:
+def room_640x480_pose(seed: int = 1003, n: int = 150_000) -> Workload:
     rng = np.random.default_rng(seed)
     faces = _room_faces(0.0, 0.0) + _box_faces(rng, 0.0, 0.0, 20)
     scene = _room_gaussians(rng, n, faces, -4.5, 0.4, 3)
     gt = _inside_room_camera(rng, 640, 480, 525.0)
     xi = np.concatenate([rng.normal(0.0, 0.02, 3), rng.normal(0.0, 0.01, 3)])
     cam = perturb_camera(gt, xi)
-    return Workload("config3_640x480_150k_sh3_pose", scene, [cam], None, None, 0.1,
+    return Workload("room_640x480_150k_sh3_pose", scene, [cam], None, None, 0.1,
                     target_scene=scene, gt_cameras=[gt], pose_perturbation=xi[None, :],
                     notes="target rendered at the ground-truth pose")
 
@@ -353,7 +353,7 @@ def _overview_camera(rng, width, height, f, x0, y0, size=(6.0, 5.0, 3.0)):
 _RESOLUTIONS = [(640, 480), (1200, 680), (320, 240)]
 
 
-def config4(seed: int = 1004, n: int = 500_000, n_views: int = 8) -> Workload:
+def keyframes8_mixed(seed: int = 1004, n: int = 500_000, n_views: int = 8) -> Workload:
     """8 keyframes, mixed resolution, alternating close-up / overview poses."""
     rng = np.random.default_rng(seed)
     faces = _room_faces(0.0, 0.0) + _box_faces(rng, 0.0, 0.0, 20)
@@ -366,12 +366,12 @@ def config4(seed: int = 1004, n: int = 500_000, n_views: int = 8) -> Workload:
         else:
             cams.append(_overview_camera(rng, w, h, w / 2.0, 0.0, 0.0))
     target_scene = _perturbed(rng, scene)
-    return Workload("config4_8views_mixed_500k_sh3", scene, cams, None, None, 0.1,
+    return Workload("keyframes8_mixed_500k_sh3", scene, cams, None, None, 0.1,
                     target_scene=target_scene,
                     notes="batched keyframes; targets are renders of perturbed params")
 
 
-def config5(seed: int = 1005, n: int = 2_000_000, n_views: int = 16) -> Workload:
+def keyframes16_1200x680(seed: int = 1005, n: int = 2_000_000, n_views: int = 16) -> Workload:
     """Four 6x5x3 rooms in a 2x2 layout with 1 m doorways, 16 views."""
     rng = np.random.default_rng(seed)
     faces, holes = [], []
@@ -391,7 +391,7 @@ def config5(seed: int = 1005, n: int = 2_000_000, n_views: int = 16) -> Workload
         x0, y0 = 6.0 * (room & 1), 5.0 * (room >> 1)
         cams.append(_inside_room_camera(rng, 1200, 680, 600.0, x0, y0))
     target_scene = _perturbed(rng, scene)
-    return Workload("config5_16x1200x680_2M_sh3", scene, cams, None, None, 0.1,
+    return Workload("keyframes16_1200x680_2M_sh3", scene, cams, None, None, 0.1,
                     target_scene=target_scene,
                     notes="large scene; forward + backward + Adam per iteration")
 
@@ -470,4 +470,4 @@ def random_keys(seed: int, n: int, tile_bits: int, tie_fraction: float = 0.05):
     return keys, vals
 
 
-CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
+WORKLOADS = {1: slab_128x96, 2: room_1200x680, 3: room_640x480_pose, 4: keyframes8_mixed, 5: keyframes16_1200x680}

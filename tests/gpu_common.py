@@ -20,7 +20,7 @@ GRAD_RTOL, GRAD_ATOL_RMS, GRAD_NORM = 1e-3, 1e-3, 1e-4
 
 @functools.lru_cache(maxsize=None)
 def workload(cfg: int, **kw):
-    return scenes.CONFIGS[cfg](**kw)
+    return scenes.WORKLOADS[cfg](**kw)
 
 
 def t32(a):

@@ -29,7 +29,7 @@ pytestmark = pytest.mark.gpu
 def test_preprocess_records_match_oracle(cfg):
     w = workload(cfg)
     cam = w.cameras[0]
-    print(f"preprocess parity config {cfg}", flush=True)
+    print(f"preprocess parity workload {cfg}", flush=True)
     it = run_gpu(w.scene, [cam])
     plan, ws = it.plan, it.ws
     n = w.scene.n
@@ -77,7 +77,7 @@ def test_sort_pairs_bit_exact(n, bits):
 def test_bin_sort_matches_oracle(cfg, tile):
     w = workload(cfg)
     cam = w.cameras[0]
-    print(f"bin_sort parity config {cfg} tile {tile}", flush=True)
+    print(f"bin_sort parity workload {cfg} tile {tile}", flush=True)
     it = run_gpu(w.scene, [cam], tile=tile)
     plan, ws = it.plan, it.ws
     pre = oracle.preprocess(w.scene, cam, tile)
@@ -144,7 +144,7 @@ def test_long_tile_list_forward_backward(flags):
 def test_forward_matches_oracle(cfg):
     w = workload(cfg)
     cam = w.cameras[0]
-    print(f"forward parity config {cfg}", flush=True)
+    print(f"forward parity workload {cfg}", flush=True)
     it = run_gpu(w.scene, [cam])
     col, dep, T, last = view_images(it, 0)
     ref = oracle.render(w.scene, cam)
@@ -153,7 +153,7 @@ def test_forward_matches_oracle(cfg):
     np.testing.assert_array_equal(last[ok], ref["last"][ok])
     # transmittance: relative error bounded by the conditioning of 1 - alpha
     np.testing.assert_allclose(T[ok], ref["T_final"][ok], rtol=2e-4, atol=1e-7)
-    print(f"config {cfg}: {nflag} flagged pixels of {ok.size}")
+    print(f"workload {cfg}: {nflag} flagged pixels of {ok.size}")
 
 
 def test_forward_tile_shapes_identical():
@@ -172,7 +172,7 @@ def _bwd_case(cfg, tile=(16, 16), lds=256, pose=False, flags=0):
     w = workload(cfg)
     cam = w.cameras[0]
     gc, gd = scenes.linear_loss_weights(100 + cfg, [cam])
-    print(f"backward parity config {cfg} tile {tile} lds {lds} flags {flags}", flush=True)
+    print(f"backward parity workload {cfg} tile {tile} lds {lds} flags {flags}", flush=True)
     it = run_gpu(w.scene, [cam], tile=tile, lds=lds, dL_dcolor=gc, dL_ddepth=gd, pose=pose,
                  flags=flags)
     ref = oracle.render(w.scene, cam, tile)
@@ -188,7 +188,7 @@ def test_backward_matches_oracle(cfg, tile, lds):
     visible = (oracle.preprocess(workload(cfg).scene, workload(cfg).cameras[0], tile)["status"] == 1).sum()
     assert exclude.sum() < 0.15 * visible
     rep = assert_grads_close(grads_np(it), grads, exclude)
-    print(f"config {cfg}: excluded {int(exclude.sum())} Gaussians; (max err/tol, rel norm) {rep}")
+    print(f"workload {cfg}: excluded {int(exclude.sum())} Gaussians; (max err/tol, rel norm) {rep}")
 
 
 @pytest.mark.parametrize("cfg,tile,lds", [(1, (16, 16), 256), (1, (8, 8), 32), (1, (16, 8), 96),
@@ -202,7 +202,7 @@ def test_splat_backward_matches_oracle(cfg, tile, lds):
     visible = (oracle.preprocess(w.scene, w.cameras[0], tile)["status"] == 1).sum()
     assert exclude.sum() < 0.15 * visible
     rep = assert_grads_close(grads_np(it), grads, exclude)
-    print(f"config {cfg}: excluded {int(exclude.sum())} Gaussians; (max err/tol, rel norm) {rep}")
+    print(f"workload {cfg}: excluded {int(exclude.sum())} Gaussians; (max err/tol, rel norm) {rep}")
     plain = run_gpu(w.scene, [w.cameras[0]], tile=tile, lds=lds)
     for k in range(4):
         np.testing.assert_array_equal(view_images(it, 0)[k], view_images(plain, 0)[k])
@@ -497,7 +497,7 @@ def test_iteration_equals_separate_calls_full_view(extra):
     wrote, against the separate calls: sorted lists and every image bit for
     bit.  (Many neighbouring tiles per CU: a read of the fresh records through
     a stale cached line would show here.)"""
-    w = scenes.config2()
+    w = scenes.room_1200x680()
     cam = w.cameras[0]
     view_wh = [(cam.width, cam.height)]
     cams = gsr.cameras_tensor([cam], DEV)

@@ -293,7 +293,7 @@ def test_stop_rule_closed_form():
 def test_weights_telescope_to_one():
     """With every colour 1 and a black background, C = sum_k a_k T_k, so
     C + T_final = 1 exactly (up to rounding) at every pixel."""
-    w = scenes.config1(seed=77, n=600)
+    w = scenes.slab_128x96(seed=77, n=600)
     sc = w.scene.copy()
     sc.sh = np.tile(_dc_for_colour([1.0, 1.0, 1.0]), (sc.n, 1))[:, None, :]
     out = oracle.render(sc, w.cameras[0])
@@ -326,7 +326,7 @@ def _quat_mul(a, b):
 
 
 def test_rigid_motion_invariance():
-    w = scenes.config1(seed=5, n=400)
+    w = scenes.slab_128x96(seed=5, n=400)
     sc = w.scene.copy()
     sc = _scene(sc.means, sc.log_scales, sc.quats, sc.opacity_logits, sc.sh)
     cam = _cam(128, 96, 100.0)
@@ -347,7 +347,7 @@ def test_rigid_motion_invariance():
 
 
 def test_quaternion_sign_and_isotropic_invariance():
-    w = scenes.config1(seed=8, n=300)
+    w = scenes.slab_128x96(seed=8, n=300)
     sc = _scene(w.scene.means, w.scene.log_scales, w.scene.quats, w.scene.opacity_logits, w.scene.sh)
     cam = _cam(128, 96, 100.0)
     base = oracle.render(sc, cam)
@@ -363,7 +363,7 @@ def test_quaternion_sign_and_isotropic_invariance():
 
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (16, 8)])
 def test_tiled_equals_untiled(tile):
-    w = scenes.config1(seed=9, n=800)
+    w = scenes.slab_128x96(seed=9, n=800)
     cam = w.cameras[0]
     tiled = oracle.render(w.scene, cam, tile)
     brute = oracle.render_untiled(w.scene, cam)
@@ -373,7 +373,7 @@ def test_tiled_equals_untiled(tile):
 
 
 def test_sort_matches_lexsort():
-    w = scenes.config1(seed=10, n=1500)
+    w = scenes.slab_128x96(seed=10, n=1500)
     cam = w.cameras[0]
     pre = oracle.preprocess(w.scene, cam)
     keys, vals, ranges = oracle.sort_pairs(pre, cam)
@@ -502,7 +502,7 @@ def test_pose_gradient_matches_finite_differences():
 def test_pose_translation_equals_summed_mean_gradient():
     """Translating the camera by rho equals moving every mean by W^T rho, so
     g_rho = W sum_i g_p,i."""
-    w = scenes.config1(seed=19, n=500)
+    w = scenes.slab_128x96(seed=19, n=500)
     rng = np.random.default_rng(20)
     R, t = scenes.random_pose(rng, 0.1, 0.1)
     cam = dataclasses.replace(w.cameras[0], R=R, t=t)
