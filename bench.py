@@ -99,6 +99,10 @@ def main():
                     help="skip the SSIM-loss, densification and scheduler timings")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the 8-keyframe batched vs per-view comparison, with the "
+                         "--tile/--lds-batch/--chunk configuration unless --autotune "
+                         "(for profiler runs)")
     ap.add_argument("--graph-only", action="store_true",
                     help="only the graph-timed headline loop (for profiler runs)")
     args = ap.parse_args()
@@ -124,6 +128,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
                           "launches": 5}))
+        return
+    if args.batched_only:
+        print(json.dumps(bench_batched(args, dev, search=args.autotune)))
         return
     t_setup = time.time()
     w = scenes.room_1200x680()
@@ -464,10 +471,12 @@ def render_target(gsr, scene, cams, view_wh, dev, tile=(16, 16)):
     return tfr.color.clone(), tfr.depth.clone()
 
 
-def bench_batched(args, dev):
+def bench_batched(args, dev, search: bool = True):
     """8 keyframes of mixed resolution over a shared 500k pool: one autotuned
     persistent graph for all views vs the same kernels and tile shape launched
-    view by view (one plan per view, gradients accumulated, one Adam step)."""
+    view by view (one plan per view, gradients accumulated, one Adam step).
+    Without `search` the configuration comes from --tile, --lds-batch,
+    --chunk and --bwd instead of the autotuner."""
     import torch
 
     import paper_2410_00486_amd as gsr
@@ -481,8 +490,13 @@ def bench_batched(args, dev):
     cams = gsr.cameras_tensor(cams_l, dev)
     params = gsr.Gaussians.from_scene(w.scene, dev)
     target_rgb, target_depth = render_target(gsr, w.target_scene, cams, view_wh, dev)
-    best, table = tune.autotune(params, cams, view_wh, target_rgb, target_depth, adam_lrs=LRS,
-                                persistent=True, chunks=[1, 2, 4, 8], reps=8)
+    if search:
+        best, table = tune.autotune(params, cams, view_wh, target_rgb, target_depth, adam_lrs=LRS,
+                                    persistent=True, chunks=[1, 2, 4, 8], reps=8)
+    else:
+        best = {"tile": args.tile, "lds_batch": args.lds_batch, "chunk": args.chunk,
+                "backward": args.bwd}
+        table = []
     log(f"batched autotune best {best}")
     tile = tuple(int(x) for x in best["tile"].split("x"))
     cap0 = gsr.required_pairs(*params.tensors(), cams, view_wh, 3, tile)
@@ -555,7 +569,7 @@ def bench_batched(args, dev):
            "batched_persistent_graph_iters_per_s": round(1e3 / ms_b, 2),
            "plain_per_view_iters_per_s": round(1e3 / ms_p, 2),
            "speedup": round(ms_p / ms_b, 3),
-           "autotune_best": best,
+           ("autotune_best" if search else "config"): best,
            "autotune_top": sorted(table, key=lambda r: r["ms"])[:5]}
     log(f"batched: {out}")
     return out
