@@ -712,7 +712,7 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_sh
     // counter is zero again after the binning of an iteration
     const TileSortArgs A = tile_sort_args(P, ws);
     if (!defer_short_sorts) hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)T), dim3(kWave), 0, s, A);
-    const int long_grid = (int)std::min<int64_t>(T, 256);
+    const int long_grid = (int)std::min<int64_t>(T, 512);  // two blocks per CU
     hipLaunchKernelGGL(k_tile_sort_long, dim3((unsigned)long_grid), dim3(kLongThreads), 0, s,
                        tcnt, fl, long_list, skey, A.out, defer_short_sorts ? 0 : 1);
   }

@@ -14,7 +14,10 @@
 // iteration the wavefront that sorts a list also composites it, and a
 // long list sorted there would hold back the end of the forward (its
 // wavefront starts first but finishes last), while the binning sorts the
-// few long lists in parallel before the forward starts.
+// few long lists in parallel before the forward starts.  The block's LDS
+// holds kTileSortLong keys (64 KB), so that two blocks share a CU and one
+// block's barrier waits overlap the other's compares: views with thousands
+// of pairs per tile send almost every list here.
 //
 // The network keeps every merge ascending (the first compare of a merge
 // pairs i with its mirror in the block), so positions past the list end act
@@ -26,7 +29,7 @@
 namespace gs {
 
 constexpr uint32_t kTileSortSmall = 128;
-constexpr uint32_t kTileSortLong = 16384;
+constexpr uint32_t kTileSortLong = 8192;
 constexpr int kLongThreads = 1024;
 
 // Splits a tile of c pairs into buckets of 64 positions: all but possibly

@@ -98,7 +98,7 @@ def test_bin_sort_matches_oracle(cfg, tile):
                                     ((16, 16), 20000)])
 def test_bin_sort_long_tile_list(tile, n):
     """n pairs in one tile: each path of the per-tile sort (300: bitonic in
-    one wavefront's LDS; 3000 and 6000: bitonic in a block's LDS; 20000:
+    one wavefront's LDS; 3000 and 6000: bitonic in a block's LDS (up to 8192); 20000:
     bitonic in place in global memory) against the oracle's order."""
     w = scenes.crowded_scene(1, n=n)
     cam = w.cameras[0]
