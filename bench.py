@@ -284,7 +284,15 @@ def main():
     for marks in all_marks:
         for k, s in enumerate(stages):
             ev[s].append(marks[k].elapsed_time(marks[k + 1]))
-    stage_ms = {s: float(np.mean(v)) for s, v in ev.items()}
+    def trimmed_mean(v, frac=0.1):
+        # mean of the launches between the 10th and 90th percentile: a host
+        # stall between two event marks (tens of ms, once in a run) would
+        # otherwise dominate the mean of a 50 us stage
+        a = np.sort(np.asarray(v, dtype=np.float64))
+        k = int(len(a) * frac)
+        return float(a[k:len(a) - k].mean()) if len(a) > 2 * k else float(a.mean())
+
+    stage_ms = {s: trimmed_mean(v) for s, v in ev.items()}
     log("stages (ms): " + ", ".join(f"{k}={v:.4f}" for k, v in stage_ms.items()))
 
     # ---- algorithmic bytes per stage: the compulsory HBM reads and writes of
