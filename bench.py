@@ -103,6 +103,8 @@ def main():
                     help="only the 8-keyframe batched vs per-view comparison, with the "
                          "--tile/--lds-batch/--chunk configuration unless --autotune "
                          "(for profiler runs)")
+    ap.add_argument("--batched-workload", default="keyframes8_mixed",
+                    choices=["keyframes8_mixed", "keyframes16_1200x680"])
     ap.add_argument("--graph-only", action="store_true",
                     help="only the graph-timed headline loop (for profiler runs)")
     args = ap.parse_args()
@@ -130,7 +132,8 @@ def main():
                           "launches": 5}))
         return
     if args.batched_only:
-        print(json.dumps(bench_batched(args, dev, search=args.autotune)))
+        print(json.dumps(bench_batched(args, dev, search=args.autotune,
+                                       workload=args.batched_workload)))
         return
     t_setup = time.time()
     w = scenes.room_1200x680()
@@ -479,7 +482,7 @@ def render_target(gsr, scene, cams, view_wh, dev, tile=(16, 16)):
     return tfr.color.clone(), tfr.depth.clone()
 
 
-def bench_batched(args, dev, search: bool = True):
+def bench_batched(args, dev, search: bool = True, workload: str = "keyframes8_mixed"):
     """8 keyframes of mixed resolution over a shared 500k pool: one autotuned
     persistent graph for all views vs the same kernels and tile shape launched
     view by view (one plan per view, gradients accumulated, one Adam step).
@@ -492,7 +495,7 @@ def bench_batched(args, dev, search: bool = True):
     from paper_2410_00486_amd import tune
     from synth import scenes
 
-    w = scenes.keyframes8_mixed()
+    w = getattr(scenes, workload)()
     cams_l = w.cameras
     view_wh = [(c.width, c.height) for c in cams_l]
     cams = gsr.cameras_tensor(cams_l, dev)
@@ -572,7 +575,7 @@ def bench_batched(args, dev, search: bool = True):
             plain_iter()
     torch.cuda.synchronize()
     ms_p = (time.perf_counter() - t0) * 1e3 / args.steps
-    out = {"workload": "keyframes8_mixed: 8 keyframes mixed {640x480,1200x680,320x240}, 500k SH3",
+    out = {"workload": w.name,
            "views": view_wh, "visible_per_view": vis, "visible_total": vis_total,
            "batched_persistent_graph_iters_per_s": round(1e3 / ms_b, 2),
            "plain_per_view_iters_per_s": round(1e3 / ms_p, 2),

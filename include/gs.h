@@ -22,7 +22,9 @@
  *     int32 flags inside the workspace (gs_flags_ptr): pair-capacity overflow
  *     and the count of Gaussians culled for non-finite parameters.  After an
  *     overflow, the downstream kernels of that iteration see zero pairs and
- *     their outputs are invalid; the caller re-plans with a larger capacity.
+ *     their outputs are invalid; the Adam step of a whole iteration
+ *     (gs_iteration_enqueue, graph replays) then changes no parameter, moment
+ *     or step counter.  The caller re-plans with a larger capacity.
  *   - Ownership: every buffer is owned by the caller.  Calls never allocate
  *     device memory, never free it and never synchronise with the host.
  *     Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
@@ -280,6 +282,32 @@ gs_status gs_adam_step(const gs_param_group* groups, int32_t n_groups, int32_t s
                        double beta1, double beta2, double eps, double lambda_o,
                        int64_t reg_count, int32_t* step_dev, void* stream);
 
+/* Camera-pose tangent of the autograd path (the camera gradient of the
+ * render, Sec. III-B; the mapping back-end refines keyframe poses with the
+ * map).  gs_render_bwd's dL_dpose is the gradient w.r.t. a left perturbation
+ * delta = (rho, phi) of each view's world->camera pose at zero.  A caller
+ * that optimises a tangent xi renders with the retracted pose and pulls the
+ * gradient back to xi:
+ *
+ * gs_pose_retract: for each view v, cams_out[v] = cams_in[v] with
+ *   R' = Exp(phi) R,  t' = Exp(phi) t + rho      (xi[v] = (rho, phi))
+ * Exp is the SO(3) exponential (Rodrigues); computed in FP64 from the
+ * float32 inputs and rounded once to float32; the other record fields are
+ * copied.  cams_in, cams_out: device [n_views][GS_CAMERA_FLOATS] (may be the
+ * same buffer); xi: device float [n_views][6].
+ *
+ * gs_pose_tangent_vjp: given dL_ddelta [n_views][6] at the retracted pose,
+ * writes dL_dxi [n_views][6]:
+ *   dL/drho = g_rho,   dL/dphi = J(phi)^T (g_phi - rho x g_rho)
+ * with J the left Jacobian of SO(3) (Exp(phi + dphi) = Exp(J dphi) Exp(phi)
+ * to first order).  At xi = 0 it is the identity.  Device buffers; dL_dxi
+ * may alias dL_ddelta.
+ * Errors: GS_ERR_INVALID_ARG (null pointer, n_views not in 1..GS_MAX_VIEWS). */
+gs_status gs_pose_retract(const float* cams_in, const float* xi, float* cams_out,
+                          int32_t n_views, void* stream);
+gs_status gs_pose_tangent_vjp(const float* xi, const float* dL_ddelta, float* dL_dxi,
+                              int32_t n_views, void* stream);
+
 /* Adaptive densification and opacity pruning (Sec. IV-A: densify every 500
  * iterations with a positional-gradient threshold tau_p, remove Gaussians
  * with opacity below eps_alpha; clone and split as in 3DGS).
@@ -319,12 +347,17 @@ size_t gs_sort_tmp_bytes(int64_t n);
 gs_status gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits,
                         void* tmp, void* stream);
 
-/* a8. Whole-iteration hipGraph.  The descriptor names every buffer of one
- * mapping iteration; gs_graph_create captures gs_preprocess, gs_bin_sort,
- * gs_render_fwd, gs_render_bwd and (if n_adam_groups > 0) gs_adam_step on
- * `stream` and instantiates the graph.  Poses, parameters and targets live
- * in device memory, so replays see their current values.  Adam needs
- * step_dev (the device step counter) so replays advance the bias correction.
+/* a8. Whole-iteration hipGraph.  The mapping back-end re-optimises keyframes
+ * of a growing pool again and again (Sec. III-C-2, Eqs. (5)-(8)); the paper
+ * takes one keyframe per iteration, this form takes a batch of keyframes of
+ * any resolutions over one shared Gaussian pool per iteration.  The
+ * descriptor names every buffer of one mapping iteration; gs_graph_create
+ * captures gs_preprocess, gs_bin_sort, gs_render_fwd, gs_render_bwd and (if
+ * n_adam_groups > 0) gs_adam_step on `stream` and instantiates the graph.
+ * Poses, parameters and targets live in device memory, so replays see their
+ * current values.  An iteration with Adam needs step_dev (the device step
+ * counter, advanced once per iteration unless the pairs overflow);
+ * gs_iteration_enqueue and gs_graph_create reject a null one.
  * With one view, Adam groups and no GS_ACCUMULATE_GRADS, the gradient
  * buffers are written for the Gaussians that have pairs only: Adam takes the
  * others' gradients as zero, so their entries in `grads` are left as they

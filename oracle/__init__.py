@@ -50,13 +50,17 @@ def lib():
         L.ora_sort_pairs.argtypes = [_I64, _i32, _i32, _fp, _I, _I, _u64, _u32, _u32]
         L.ora_sort_pairs.restype = _I64
         L.ora_render_fwd.argtypes = [_I, _I, _I, _I, _dp, _dp, _dp, _dp, _dp, _u32, _u32, _dp,
-                                     _dp, _dp, _dp, _i32, _i32]
+                                     _dp, _dp, _dp, _i32, _i32, _I]
         L.ora_render_fwd.restype = None
+        L.ora_flag_decisions.argtypes = [_I, _I, _I, _I, _dp, _dp, _dp, _dp, _dp, _u32, _u32,
+                                         _dp, _I64, _i32, _i32, _i32]
+        L.ora_flag_decisions.restype = _I64
         L.ora_render_untiled.argtypes = [_I, _I, _I64, _i32, _dp, _dp, _dp, _dp, _dp, _fp, _dp,
                                          _dp, _dp, _dp, _i32]
         L.ora_render_untiled.restype = None
         L.ora_render_bwd.argtypes = [_I, _I, _I, _I, _I64, _I64, _dp, _dp, _dp, _dp, _dp, _u32,
-                                     _u32, _dp, _dp, ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp]
+                                     _u32, _dp, _dp, ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp,
+                                     _I]
         L.ora_render_bwd.restype = None
         L.ora_project_bwd.argtypes = [_I64, _I, _dp, _dp, _dp, _dp, _dp, _dp, _I, _I, _I, _I, _I,
                                       _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
@@ -130,10 +134,12 @@ def sort_pairs(pre, cam, tile=(16, 16)):
     return keys[:P], vals[:P], ranges
 
 
-def render(scene, cam, tile=(16, 16), cutoff="exact", pre=None):
+def render(scene, cam, tile=(16, 16), cutoff="exact", pre=None, flip_band=False):
     """Tiled forward render of one view.  Returns a dict with color [3,H,W],
     depth, T_final, last, flag (pixels near a discrete decision), and the
-    preprocess / sort products."""
+    preprocess / sort products.  flip_band: every decision within a relative
+    1e-5 of its threshold takes the other branch (for the tests' sensitivity
+    of a result to those decisions)."""
     if pre is None:
         pre = preprocess(scene, cam, tile, cutoff)
     keys, vals, ranges = sort_pairs(pre, cam, tile)
@@ -142,9 +148,28 @@ def render(scene, cam, tile=(16, 16), cutoff="exact", pre=None):
     last = np.zeros((H, W), np.int32); flag = np.zeros((H, W), np.int32)
     lib().ora_render_fwd(W, H, tile[0], tile[1], pre["mean2d"], pre["conic"], pre["opacity"],
                          pre["rgb"], pre["depth"], np.ascontiguousarray(vals), ranges,
-                         _c64(cam.bg), color, depth, T, last, flag)
+                         _c64(cam.bg), color, depth, T, last, flag, 1 if flip_band else 0)
     return dict(color=color, depth=depth, T_final=T, last=last, flag=flag, pre=pre,
-                keys=keys, vals=vals, ranges=ranges)
+                keys=keys, vals=vals, ranges=ranges, flip_band=flip_band)
+
+
+def flag_decisions(fwd, cam, tile=(16, 16)):
+    """Decisions of ``fwd`` (a result of render) taken within a relative 1e-5
+    of their thresholds.  Returns int arrays (pixel, gaussian, kind): kind 1
+    the 0.99 clamp, 2 the 1/255 skip, 4 the 1e-4 stop (the Gaussian whose
+    decision it is), 8 a Gaussian blended at a pixel that has such a
+    decision."""
+    pre = fwd["pre"]
+    args = (cam.width, cam.height, tile[0], tile[1], pre["mean2d"], pre["conic"],
+            pre["opacity"], pre["rgb"], pre["depth"], np.ascontiguousarray(fwd["vals"]),
+            fwd["ranges"], _c64(cam.bg))
+    cap = 1 << 16
+    while True:
+        pix, g, kind = (np.zeros(cap, np.int32) for _ in range(3))
+        total = lib().ora_flag_decisions(*args, cap, pix, g, kind)
+        if total <= cap:
+            return pix[:total], g[:total], kind[:total]
+        cap = int(total)
 
 
 def render_untiled(scene, cam, pre=None):
@@ -160,10 +185,13 @@ def render_untiled(scene, cam, pre=None):
     return dict(color=color, depth=depth, T_final=T, n_blended=nb)
 
 
-def backward_2d(scene, cam, dL_dcolor, dL_ddepth=None, tile=(16, 16), cutoff="exact", fwd=None):
-    """Per-Gaussian 2D gradients of one view (mean2d, conic, opacity, rgb, depth)."""
+def backward_2d(scene, cam, dL_dcolor, dL_ddepth=None, tile=(16, 16), cutoff="exact", fwd=None,
+                flip_band=False):
+    """Per-Gaussian 2D gradients of one view (mean2d, conic, opacity, rgb, depth).
+    flip_band as in render (taken from ``fwd`` when given)."""
     if fwd is None:
-        fwd = render(scene, cam, tile, cutoff)
+        fwd = render(scene, cam, tile, cutoff, flip_band=flip_band)
+    flip_band = fwd.get("flip_band", False)
     pre = fwd["pre"]
     n = scene.n
     H, W = cam.height, cam.width
@@ -175,7 +203,8 @@ def backward_2d(scene, cam, dL_dcolor, dL_ddepth=None, tile=(16, 16), cutoff="ex
                          np.ascontiguousarray(fwd["vals"]), fwd["ranges"], _c64(cam.bg),
                          _c64(dL_dcolor).reshape(3 * H * W),
                          None if gd is None else gd.ctypes.data_as(ctypes.c_void_p),
-                         g["mean2d"], g["conic"], g["opacity"], g["rgb"], g["depth"])
+                         g["mean2d"], g["conic"], g["opacity"], g["rgb"], g["depth"],
+                         1 if flip_band else 0)
     if gd is not None:
         g["_keep"] = gd
     return g
@@ -201,7 +230,8 @@ def project_backward(scene, cam, g2d, tile=(16, 16), cutoff="exact", accum=None)
     return accum, pose
 
 
-def backward(scene, cams, dL_dcolor, dL_ddepth=None, tile=(16, 16), cutoff="exact"):
+def backward(scene, cams, dL_dcolor, dL_ddepth=None, tile=(16, 16), cutoff="exact",
+             flip_band=False):
     """Full backward over one or more views: parameter gradients summed over
     views, and one camera-tangent gradient per view."""
     if not isinstance(cams, (list, tuple)):
@@ -210,10 +240,67 @@ def backward(scene, cams, dL_dcolor, dL_ddepth=None, tile=(16, 16), cutoff="exac
         dL_ddepth = [None] * len(cams)
     accum, poses = None, []
     for cam, gc, gd in zip(cams, dL_dcolor, dL_ddepth):
-        g2d = backward_2d(scene, cam, gc, gd, tile, cutoff)
+        g2d = backward_2d(scene, cam, gc, gd, tile, cutoff, flip_band=flip_band)
         accum, pose = project_backward(scene, cam, g2d, tile, cutoff, accum)
         poses.append(pose)
     return accum, np.stack(poses)
+
+
+def _hat(v):
+    x, y, z = (float(a) for a in v)
+    return np.array([[0.0, -z, y], [z, 0.0, -x], [-y, x, 0.0]])
+
+
+def so3_exp(phi):
+    """Rotation matrix of the rotation vector phi (scipy's rotvec map)."""
+    from scipy.spatial.transform import Rotation
+    return Rotation.from_rotvec(np.asarray(phi, np.float64)).as_matrix()
+
+
+def so3_left_jacobian(phi, terms=40):
+    """Left Jacobian of SO(3) from its defining power series
+    J(phi) = sum_k [phi]x^k / (k+1)!  (so that Exp(phi + d) = Exp(J d) Exp(phi)
+    to first order in d)."""
+    K = _hat(phi)
+    J = np.zeros((3, 3))
+    P = np.eye(3)
+    fact = 1.0
+    for k in range(terms):
+        fact *= (k + 1)
+        J += P / fact
+        P = P @ K
+    return J
+
+
+def retract_camera(cam, xi, round32=True):
+    """The camera at the pose R' = Exp(phi) R, t' = Exp(phi) t + rho, xi =
+    (rho, phi): the left perturbation the camera gradient is taken for.
+    round32: store R', t' as float32, the type of the device camera record."""
+    import dataclasses
+    xi = np.asarray(xi, np.float64)
+    E = so3_exp(xi[3:6])
+    R = E @ np.asarray(cam.R, np.float64)
+    t = E @ np.asarray(cam.t, np.float64) + xi[0:3]
+    if round32:
+        R, t = R.astype(np.float32), t.astype(np.float32)
+    return dataclasses.replace(cam, R=R, t=t)
+
+
+def pose_tangent_vjp(xi, g_delta):
+    """dL/dxi of L(retract(xi)) from g_delta = dL/ddelta, the gradient of a
+    left perturbation at the retracted pose: with Exp(phi + dphi) =
+    Exp(J dphi) Exp(phi), a step dxi is the perturbation delta = (drho +
+    rho x (J dphi), J dphi), so dL/drho = g_rho, dL/dphi = J^T (g_phi - rho x
+    g_rho)."""
+    xi = np.asarray(xi, np.float64).reshape(-1, 6)
+    g = np.asarray(g_delta, np.float64).reshape(-1, 6)
+    out = np.zeros_like(g)
+    for v in range(xi.shape[0]):
+        rho, phi = xi[v, :3], xi[v, 3:]
+        J = so3_left_jacobian(phi)
+        out[v, :3] = g[v, :3]
+        out[v, 3:] = J.T @ (g[v, 3:] - np.cross(rho, g[v, :3]))
+    return out
 
 
 def linear_loss(fwd_list, dL_dcolor, dL_ddepth=None):

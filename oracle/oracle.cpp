@@ -428,13 +428,26 @@ struct Blend {
   bool clamped;
 };
 
+// Kinds of a decision taken within the band of its threshold (reported by
+// ora_flag_decisions): the 0.99 clamp, the 1/255 skip, the 1e-4 stop.
+enum { kDecClamp = 1, kDecSkip = 2, kDecStop = 4 };
+
 int composite_pixel(double sx, double sy, const uint32_t* list, int64_t count,
                     const double* mean2d, const double* conic, const double* opacity,
                     const double* rgb, const double* depth, const double* bg,
                     double out_c[3], double* out_d, double* out_T, int* out_last,
-                    std::vector<Blend>* rec) {
+                    std::vector<Blend>* rec,
+                    std::vector<std::pair<int, int>>* decisions = nullptr,
+                    bool flip_band = false) {
   double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
   int last = 0, flag = 0;
+  // near(): the decision is within the band; with flip_band the other branch
+  // is taken (what a computation within rounding of the threshold may do)
+  auto near = [&](int i, int kind) {
+    flag = 1;
+    if (decisions) decisions->push_back({i, kind});
+    return flip_band;
+  };
   for (int64_t j = 0; j < count; ++j) {
     const int i = (int)list[j];
     const double dx = mean2d[2 * i] - sx, dy = mean2d[2 * i + 1] - sy;
@@ -443,14 +456,14 @@ int composite_pixel(double sx, double sy, const uint32_t* list, int64_t count,
     if (power > 0.0) continue;
     const double G = std::exp(power);
     const double oG = opacity[i] * G;
-    if (std::fabs(oG - kAlphaMax) <= kBand * kAlphaMax) flag = 1;
-    const bool clamped = oG > kAlphaMax;
+    bool flip = std::fabs(oG - kAlphaMax) <= kBand * kAlphaMax && near(i, kDecClamp);
+    const bool clamped = (oG > kAlphaMax) != flip;
     const double alpha = clamped ? kAlphaMax : oG;
-    if (std::fabs(alpha - kAlphaMin) <= kBand * kAlphaMin) flag = 1;
-    if (alpha < kAlphaMin) continue;
+    flip = std::fabs(alpha - kAlphaMin) <= kBand * kAlphaMin && near(i, kDecSkip);
+    if ((alpha < kAlphaMin) != flip) continue;
     const double Tn = T * (1.0 - alpha);
-    if (std::fabs(Tn - kTransmittanceMin) <= kBand * kTransmittanceMin) flag = 1;
-    if (Tn < kTransmittanceMin) break;
+    flip = std::fabs(Tn - kTransmittanceMin) <= kBand * kTransmittanceMin && near(i, kDecStop);
+    if ((Tn < kTransmittanceMin) != flip) break;
     if (rec) rec->push_back({i, (int)j, alpha, T, G, dx, dy, clamped});
     for (int ch = 0; ch < 3; ++ch) C[ch] += rgb[3 * i + ch] * alpha * T;
     D += depth[i] * alpha * T;
@@ -476,7 +489,7 @@ void ora_render_fwd(int width, int height, int tw, int th,
                     const double* rgb, const double* depth, const uint32_t* vals,
                     const uint32_t* ranges, const double* bg,
                     double* color, double* out_depth, double* T_final, int32_t* last,
-                    int32_t* flag) {
+                    int32_t* flag, int flip_band) {
   const int tiles_x = (width + tw - 1) / tw;
   const int64_t npx = (int64_t)width * height;
 #pragma omp parallel for schedule(dynamic, 64)
@@ -487,12 +500,52 @@ void ora_render_fwd(int width, int height, int tw, int th,
     double c[3], d, T;
     int l;
     flag[p] = composite_pixel(px + 0.5, py + 0.5, vals + s, (int64_t)e - s, mean2d, conic,
-                              opacity, rgb, depth, bg, c, &d, &T, &l, nullptr);
+                              opacity, rgb, depth, bg, c, &d, &T, &l, nullptr, nullptr,
+                              flip_band != 0);
     for (int ch = 0; ch < 3; ++ch) color[ch * npx + p] = c[ch];
     out_depth[p] = d;
     T_final[p] = T;
     last[p] = l;
   }
+}
+
+// Decisions within the band of their thresholds, for the parity tests'
+// exclusions (no arithmetic beyond the forward's own).  For every pixel with
+// at least one such decision: one (pixel, Gaussian, kind) triple per
+// decision (kind kDecClamp / kDecSkip / kDecStop), then one (pixel,
+// Gaussian, 8) triple per Gaussian blended at that pixel.  Writes at most
+// cap triples; returns the number there are.
+int64_t ora_flag_decisions(int width, int height, int tw, int th, const double* mean2d,
+                           const double* conic, const double* opacity, const double* rgb,
+                           const double* depth, const uint32_t* vals, const uint32_t* ranges,
+                           const double* bg, int64_t cap, int32_t* out_pix, int32_t* out_gauss,
+                           int32_t* out_kind) {
+  const int tiles_x = (width + tw - 1) / tw;
+  const int64_t npx = (int64_t)width * height;
+  int64_t total = 0;
+  for (int64_t p = 0; p < npx; ++p) {
+    const int px = (int)(p % width), py = (int)(p / width);
+    const int tile = (py / th) * tiles_x + (px / tw);
+    const uint32_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
+    double c[3], d, T;
+    int l;
+    std::vector<Blend> rec;
+    std::vector<std::pair<int, int>> dec;
+    composite_pixel(px + 0.5, py + 0.5, vals + s, (int64_t)e - s, mean2d, conic, opacity, rgb,
+                    depth, bg, c, &d, &T, &l, &rec, &dec);
+    if (dec.empty()) continue;
+    auto put = [&](int g, int kind) {
+      if (total < cap) {
+        out_pix[total] = (int32_t)p;
+        out_gauss[total] = g;
+        out_kind[total] = kind;
+      }
+      ++total;
+    };
+    for (const auto& x : dec) put(x.first, x.second);
+    for (const Blend& b : rec) put(b.idx, 8);
+  }
+  return total;
 }
 
 // Untiled brute force: every visible Gaussian, ordered by (float32 depth,
@@ -534,7 +587,7 @@ void ora_render_bwd(int width, int height, int tw, int th, int64_t n, int64_t n_
                     const double* rgb, const double* depth, const uint32_t* vals,
                     const uint32_t* ranges, const double* bg, const double* dL_dcolor,
                     const double* dL_ddepth, double* g_mean2d, double* g_conic,
-                    double* g_opacity, double* g_rgb, double* g_depth) {
+                    double* g_opacity, double* g_rgb, double* g_depth, int flip_band) {
   const int tiles_x = (width + tw - 1) / tw;
   const int tiles_y = (height + th - 1) / th;
   const int64_t npx = (int64_t)width * height;
@@ -552,7 +605,7 @@ void ora_render_bwd(int width, int height, int tw, int th, int64_t n, int64_t n_
         double c[3], d, Tf;
         int l;
         composite_pixel(px + 0.5, py + 0.5, vals + s, (int64_t)e - s, mean2d, conic, opacity,
-                        rgb, depth, bg, c, &d, &Tf, &l, &rec);
+                        rgb, depth, bg, c, &d, &Tf, &l, &rec, nullptr, flip_band != 0);
         const double gC[3] = {dL_dcolor[p], dL_dcolor[npx + p], dL_dcolor[2 * npx + p]};
         const double gD = dL_ddepth ? dL_ddepth[p] : 0.0;
         double Sc[3] = {Tf * bg[0], Tf * bg[1], Tf * bg[2]};

@@ -110,6 +110,8 @@ SIGNATURES = {
                              ctypes.POINTER(GsGaussianGrads), vp, vp]),
     "gs_adam_step": (i32, [ctypes.POINTER(GsParamGroup), i32, i32, f64, f64, f64, f64, i64, vp,
                            vp]),
+    "gs_pose_retract": (i32, [vp, vp, vp, i32, vp]),
+    "gs_pose_tangent_vjp": (i32, [vp, vp, vp, i32, vp]),
     "gs_grad_stats": (i32, [ctypes.POINTER(GsPlan), vp, vp, vp, vp]),
     "gs_densify_tmp_bytes": (sz, [i64]),
     "gs_densify_prune": (i32, [ctypes.POINTER(GsGaussians), ctypes.POINTER(GsGaussianGrads),

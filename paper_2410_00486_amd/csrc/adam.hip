@@ -40,7 +40,7 @@ struct AdamArgs {
   // step; group k of this launch is group group0 + k there
   const AdamStepFactors* factors;
   int32_t group0;
-  const int32_t* overflow;  // with vis: every gradient is zero after a pair overflow
+  const int32_t* overflow;  // optional: a nonzero flag turns the launch into a no-op
   // optional: block 0 also reduces the forward's per-tile L1 partials of a
   // one-view iteration into *loss (the loss needs nothing after the forward)
   const float2* tile_loss;
@@ -72,6 +72,10 @@ __global__ void __launch_bounds__(kAdamThreads) k_adam(AdamArgs a) {
   if (a.loss && blockIdx.x == 0)
     loss_reduce_view<kAdamThreads>(a.tile_loss, a.loss_tiles, a.loss_pixels, a.lambda_depth,
                                    a.loss_has_depth, a.loss);
+  // the iteration's binning overflowed: its gradients are invalid, and the
+  // parameters and moments are left as they are (the step counter was not
+  // advanced either)
+  if (a.overflow && *a.overflow != 0) return;
   float step_size, inv_bc2s;
   int step;
   if (a.factors) {
@@ -101,9 +105,7 @@ __global__ void __launch_bounds__(kAdamThreads) k_adam(AdamArgs a) {
     if (G.vis) {
       // visibility of the four elements' Gaussians (e0 is a multiple of 4)
       bool v0, v1, v2, v3;
-      if (*a.overflow != 0) {
-        v0 = v1 = v2 = v3 = false;
-      } else if (G.per == 1) {
+      if (G.per == 1) {
         const uint4 t = *reinterpret_cast<const uint4*>(G.vis + e0);
         v0 = t.x != 0; v1 = t.y != 0; v2 = t.z != 0; v3 = t.w != 0;
       } else {
@@ -143,7 +145,7 @@ __global__ void __launch_bounds__(kAdamThreads) k_adam(AdamArgs a) {
   } else {
     for (int64_t e = e0; e < G.n; ++e) {
       float p = G.p[e], m = G.m[e], v = G.v[e];
-      const bool live = !G.vis || (*a.overflow == 0 && G.vis[e / G.per] != 0);
+      const bool live = !G.vis || G.vis[e / G.per] != 0;
       adam_one(p, live ? G.g[e] : 0.0f, m, v, a, step_size, inv_bc2s, G.reg);
       G.p[e] = p;
       G.m[e] = m;
@@ -152,7 +154,9 @@ __global__ void __launch_bounds__(kAdamThreads) k_adam(AdamArgs a) {
   }
 }
 
-__global__ void k_step_advance(int32_t* step_dev) { *step_dev += 1; }
+__global__ void k_step_advance(int32_t* step_dev, const int32_t* overflow) {
+  if (!overflow || *overflow == 0) *step_dev += 1;
+}
 
 }  // namespace
 
@@ -160,7 +164,9 @@ int64_t adam_blocks(int64_t n) {
   return (n + kAdamThreads * kAdamVec - 1) / (kAdamThreads * kAdamVec);
 }
 
-// vis / per / overflow: optional per-group gradient masks (see AdamGroupArg).
+// vis / per: optional per-group gradient masks (see AdamGroupArg).
+// overflow (optional): the pair-overflow flag of the iteration; when set on
+// the device, the launch changes no parameter, moment or step counter.
 // fold (optional): the iteration advanced step_dev already, and/or the
 // forward's loss reduction rides on block 0.
 hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, double beta1,
@@ -206,7 +212,7 @@ hipError_t launch_adam(const gs_param_group* groups, int n_groups, int step, dou
     if (e != hipSuccess) return e;
   }
   if (step_dev && !(fold && fold->step_taken)) {
-    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(1), 0, s, step_dev);
+    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(1), 0, s, step_dev, overflow);
     return hipGetLastError();
   }
   return hipSuccess;

@@ -13,8 +13,9 @@
 
 namespace gs {
 hipError_t launch_preprocess(const Plan& P, const gs_gaussians& g, const float* cams, void* ws,
-                             hipStream_t s, const StepAdvance* step = nullptr);
-hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_short_sorts = false);
+                             hipStream_t s);
+hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_short_sorts = false,
+                           const StepAdvance* step = nullptr);
 TileSortArgs tile_sort_args(const Plan& P, void* ws);
 hipError_t launch_radix_sort(uint64_t* keys0, uint64_t* keys1, uint32_t* vals0, uint32_t* vals1,
                              const int32_t* cnt, uint32_t* hist, uint32_t* digit_tot,
@@ -52,6 +53,10 @@ hipError_t launch_densify(const gs_gaussians& g, const gs_gaussian_grads& m,
                           float extent, const gs_gaussian_grads& out, const gs_gaussian_grads& out_m,
                           const gs_gaussian_grads& out_v, int64_t cap, int32_t* n_out, void* tmp,
                           hipStream_t s);
+hipError_t launch_pose_retract(const float* cams_in, const float* xi, float* cams_out,
+                               int n_views, hipStream_t s);
+hipError_t launch_pose_vjp(const float* xi, const float* g_delta, float* g_xi, int n_views,
+                           hipStream_t s);
 hipError_t launch_render_loss(const Plan& P, void* ws, const float* color, const float* depth,
                               const float* target_rgb, const float* target_depth,
                               double lambda_ssim, float* dL_dcolor, float* dL_ddepth,
@@ -286,10 +291,8 @@ int32_t* gs_flags_ptr(const gs_plan* plan, void* ws) {
 // Preprocess.  clear: the per-iteration flags and the per-tile pair
 // counters are zeroed by a kernel first (graph-safe); a whole iteration
 // skips it, the binning of the previous one having left them zero.
-// step_advance (optional): the projection also advances the Adam step.
 static gs_status preprocess_enqueue(const gs_plan* plan, const gs_gaussians* g,
-                                    const float* cams_dev, void* ws, hipStream_t s,
-                                    const StepAdvance* step_advance, bool clear) {
+                                    const float* cams_dev, void* ws, hipStream_t s, bool clear) {
   gs_status st;
   if ((st = check_plan(plan)) != GS_OK) return st;
   const Plan& P = *plan_of(plan);
@@ -297,13 +300,13 @@ static gs_status preprocess_enqueue(const gs_plan* plan, const gs_gaussians* g,
   if ((st = check_gaussians(P, g)) != GS_OK) return st;
   if (!cams_dev) return fail(GS_ERR_INVALID_ARG, "cams_dev is null");
   hipError_t e = clear ? launch_clear_counters(P, ws, s) : hipSuccess;
-  if (e == hipSuccess) e = launch_preprocess(P, *g, cams_dev, ws, s, step_advance);
+  if (e == hipSuccess) e = launch_preprocess(P, *g, cams_dev, ws, s);
   return hip_check(e, "gs_preprocess");
 }
 
 gs_status gs_preprocess(const gs_plan* plan, const gs_gaussians* g, const float* cams_dev,
                         void* ws, void* stream) {
-  return preprocess_enqueue(plan, g, cams_dev, ws, static_cast<hipStream_t>(stream), nullptr, true);
+  return preprocess_enqueue(plan, g, cams_dev, ws, static_cast<hipStream_t>(stream), true);
 }
 
 gs_status gs_bin_sort(const gs_plan* plan, void* ws, void* stream) {
@@ -428,9 +431,8 @@ gs_status gs_render_loss(const gs_plan* plan, void* ws, const float* color, cons
                    "gs_render_loss");
 }
 
-gs_status gs_adam_step(const gs_param_group* groups, int32_t n_groups, int32_t step,
-                       double beta1, double beta2, double eps, double lambda_o,
-                       int64_t reg_count, int32_t* step_dev, void* stream) {
+static gs_status check_adam(const gs_param_group* groups, int32_t n_groups, int32_t step,
+                            double beta1, double beta2, double eps, const int32_t* step_dev) {
   if (n_groups < 0 || (n_groups > 0 && !groups)) return fail(GS_ERR_INVALID_ARG, "bad group array");
   if (!step_dev && step < 1) return fail(GS_ERR_INVALID_ARG, "step must be >= 1");
   if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps >= 0.0))
@@ -442,10 +444,35 @@ gs_status gs_adam_step(const gs_param_group* groups, int32_t n_groups, int32_t s
     if (!aligned(G.p, 16) || !aligned(G.g, 16) || !aligned(G.m, 16) || !aligned(G.v, 16))
       return fail(GS_ERR_INVALID_ARG, "group %d: pointers must be 16-byte aligned", k);
   }
+  return GS_OK;
+}
+
+gs_status gs_adam_step(const gs_param_group* groups, int32_t n_groups, int32_t step,
+                       double beta1, double beta2, double eps, double lambda_o,
+                       int64_t reg_count, int32_t* step_dev, void* stream) {
+  gs_status st = check_adam(groups, n_groups, step, beta1, beta2, eps, step_dev);
+  if (st != GS_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   return hip_check(launch_adam(groups, n_groups, step, beta1, beta2, eps, lambda_o, reg_count,
                                step_dev, s),
                    "gs_adam_step");
+}
+
+gs_status gs_pose_retract(const float* cams_in, const float* xi, float* cams_out,
+                          int32_t n_views, void* stream) {
+  if (n_views < 1 || n_views > GS_MAX_VIEWS) return fail(GS_ERR_INVALID_ARG, "n_views must be 1..%d", GS_MAX_VIEWS);
+  if (!cams_in || !xi || !cams_out) return fail(GS_ERR_INVALID_ARG, "null pointer");
+  return hip_check(launch_pose_retract(cams_in, xi, cams_out, n_views,
+                                       static_cast<hipStream_t>(stream)),
+                   "gs_pose_retract");
+}
+
+gs_status gs_pose_tangent_vjp(const float* xi, const float* dL_ddelta, float* dL_dxi,
+                              int32_t n_views, void* stream) {
+  if (n_views < 1 || n_views > GS_MAX_VIEWS) return fail(GS_ERR_INVALID_ARG, "n_views must be 1..%d", GS_MAX_VIEWS);
+  if (!xi || !dL_ddelta || !dL_dxi) return fail(GS_ERR_INVALID_ARG, "null pointer");
+  return hip_check(launch_pose_vjp(xi, dL_ddelta, dL_dxi, n_views, static_cast<hipStream_t>(stream)),
+                   "gs_pose_tangent_vjp");
 }
 
 gs_status gs_grad_stats(const gs_plan* plan, void* ws, float* accum, float* denom, void* stream) {
@@ -533,6 +560,10 @@ gs_status gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_b
 gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
   if (!it) return fail(GS_ERR_INVALID_ARG, "iteration is null");
   if (!it->plan || check_plan(it->plan) != GS_OK) return fail(GS_ERR_INVALID_ARG, "bad plan");
+  if (it->n_adam_groups < 0 || (it->n_adam_groups > 0 && !it->adam_groups))
+    return fail(GS_ERR_INVALID_ARG, "bad Adam group array");
+  if (it->n_adam_groups > 0 && !it->step_dev)
+    return fail(GS_ERR_INVALID_ARG, "an iteration with Adam needs step_dev (the device step counter)");
   const Plan& P = *plan_of(it->plan);
   const bool ssim = it->lambda_ssim > 0.0;
   if (ssim) {
@@ -570,9 +601,18 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
                        it->T_final, it->last, gC, gD, it->target_rgb, it->target_depth,
                        &it->grads, it->dL_dpose, stream);
     if (st != GS_OK) return st;
-    if (it->n_adam_groups > 0)
-      st = gs_adam_step(it->adam_groups, it->n_adam_groups, 1, it->beta1, it->beta2, it->eps,
-                        it->lambda_o, it->reg_count, it->step_dev, stream);
+    if (it->n_adam_groups > 0) {
+      // the Adam launch (and the step advance after it) do nothing when the
+      // binning of this iteration overflowed
+      st = check_adam(it->adam_groups, it->n_adam_groups, 1, it->beta1, it->beta2, it->eps,
+                      it->step_dev);
+      if (st != GS_OK) return st;
+      st = hip_check(launch_adam(it->adam_groups, it->n_adam_groups, 1, it->beta1, it->beta2,
+                                 it->eps, it->lambda_o, it->reg_count, it->step_dev,
+                                 static_cast<hipStream_t>(stream), nullptr, nullptr,
+                                 ws_at<int32_t>(it->ws, P.off_flags) + F_OVERFLOW),
+                     "gs_iteration_enqueue (Adam)");
+    }
     return st;
   }
 
@@ -604,7 +644,7 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
     adam_elems += G.n;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // The Adam step counter is advanced by the first launch of the iteration
+  // The Adam step counter is advanced by the binning scan of the iteration
   // and the one-view loss reduction rides on the Adam launch: two launches
   // fewer per iteration, same values.
   AdamFold fold{};
@@ -631,13 +671,13 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
   }
   // no clearing launch: the counters were left zero by the last binning on
   // this workspace (or the workspace is fresh, zero-filled)
-  st = preprocess_enqueue(it->plan, &it->gaussians, it->cams_dev, it->ws, s,
-                          it->step_dev ? &adv : nullptr, false);
+  st = preprocess_enqueue(it->plan, &it->gaussians, it->cams_dev, it->ws, s, false);
   if (st != GS_OK) return st;
   // the binning leaves the short lists to the forward, which sorts each
   // tile's list right before compositing it (one launch fewer; the sort's
-  // memory latency hides behind other wavefronts' compositing)
-  hipError_t e = launch_bin_sort(P, it->ws, s, true);
+  // memory latency hides behind other wavefronts' compositing); its scan
+  // advances the Adam step unless the pairs overflow
+  hipError_t e = launch_bin_sort(P, it->ws, s, true, it->step_dev ? &adv : nullptr);
   TileSortArgs fwd_sort = tile_sort_args(P, it->ws);
   fwd_sort.long_after = false;  // the long lists were sorted by the binning
   if (e != hipSuccess) return hip_check(e, "gs_iteration_enqueue (binning)");

@@ -207,7 +207,7 @@ __device__ __forceinline__ void store4(uint32_t* __restrict__ a, int64_t i, int6
 }
 
 __global__ void __launch_bounds__(kScanBlock) k_scans(ScanArgs A, int64_t cap,
-                                                      int32_t* __restrict__ fl) {
+                                                      int32_t* __restrict__ fl, StepAdvance st) {
   constexpr int NW = kScanBlock / kWave;
   constexpr int NT = 4 * kScanVec, NC = 2 * kScanVec;  // tiles, chunks per thread and round
   // channels: 64-bit tile pairs, chunk pairs; 32-bit buckets, half buckets,
@@ -309,6 +309,10 @@ __global__ void __launch_bounds__(kScanBlock) k_scans(ScanArgs A, int64_t cap,
   fl[F_BQ_FULL] = (over || !splat) ? 0 : (int32_t)(c32[0] - c32[1]);
   fl[F_BQ_HALF] = (over || !splat) ? 0 : (int32_t)c32[1];
   if (splat) A.boff[T] = c32[0];
+  // a whole iteration with Adam advances its step here, once the pairs are
+  // known to fit: after an overflow the iteration's Adam launch changes
+  // nothing, and neither does the step counter
+  if (st.step && !over) advance_step(st);
 }
 
 
@@ -679,7 +683,8 @@ TileSortArgs tile_sort_args(const Plan& P, void* ws) {
 // defer_short_sorts: the lists of at most kTileSortSmall pairs are left to
 // the forward (a whole iteration), which sorts each tile before compositing
 // it; the long lists are sorted here in either case.
-hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_short_sorts) {
+hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_short_sorts,
+                           const StepAdvance* step) {
   int32_t* fl = ws_at<int32_t>(ws, P.off_flags);
   uint32_t* tt = ws_at<uint32_t>(ws, P.off_tt);
   uint32_t* poff = ws_at<uint32_t>(ws, P.off_poff);
@@ -696,7 +701,8 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_sh
               splat ? ws_at<uint32_t>(ws, P.off_boff) : nullptr, fstart, hstart,
               ws_at<uint32_t>(ws, P.off_order), long_list};
   // always launched, so that the flags are always set
-  hipLaunchKernelGGL(k_scans, dim3(1), dim3(kScanBlock), 0, s, sa, P.pair_cap, fl);
+  hipLaunchKernelGGL(k_scans, dim3(1), dim3(kScanBlock), 0, s, sa, P.pair_cap, fl,
+                     step ? *step : StepAdvance{});
   uint64_t* skey = ws_at<uint64_t>(ws, P.off_scatter);
   uint32_t* pair_rec = ws_at<uint32_t>(ws, P.off_pair_rec);
   if (P.n_chunks > 0) {

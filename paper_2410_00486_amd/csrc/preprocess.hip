@@ -59,9 +59,7 @@ __global__ void __launch_bounds__(256) k_preprocess(
     const float* __restrict__ sh, int64_t n, const float* __restrict__ cams, ViewTable vt,
     uint32_t flags, Rec* __restrict__ rec, ushort4* __restrict__ rect,
     uint32_t* __restrict__ tt, uint32_t* __restrict__ tile_cnt, uint2* __restrict__ chunk_cnt,
-    int64_t chunks_per_view, int32_t* __restrict__ fl, StepAdvance st) {
-  // a whole iteration advances its Adam step here (one thread)
-  if (st.step && blockIdx.x == 0 && threadIdx.x == 0) advance_step(st);
+    int64_t chunks_per_view, int32_t* __restrict__ fl) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   // lanes past the end stay active (as an invalid Gaussian) so that the
@@ -274,7 +272,7 @@ __global__ void __launch_bounds__(256) k_preprocess(
 }  // namespace
 
 hipError_t launch_preprocess(const Plan& P, const gs_gaussians& g, const float* cams,
-                             void* ws, hipStream_t s, const StepAdvance* step) {
+                             void* ws, hipStream_t s) {
   const int threads = 256;
   const int64_t blocks = (P.n + threads - 1) / threads;
   if (blocks == 0) return hipSuccess;
@@ -288,8 +286,7 @@ hipError_t launch_preprocess(const Plan& P, const gs_gaussians& g, const float* 
 #define GS_PRE(D)                                                                          \
   hipLaunchKernelGGL(k_preprocess<D>, dim3((unsigned)blocks), dim3(threads), 0, s, g.means, \
                      g.log_scales, g.quats, g.opacity_logits, g.sh, P.n, cams, P.vt, flags,  \
-                     rec, rect, tt, tile_cnt, chunk_cnt, P.chunks_per_view, fl,               \
-                     step ? *step : StepAdvance{})
+                     rec, rect, tt, tile_cnt, chunk_cnt, P.chunks_per_view, fl)
   switch (P.deg) {
     case 0: GS_PRE(0); break;
     case 1: GS_PRE(1); break;

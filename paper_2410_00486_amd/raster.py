@@ -443,37 +443,157 @@ class Iteration:
 
 # ---------------------------------------------------------------- autograd
 
+def pose_retract(cams: torch.Tensor, xi: torch.Tensor, out: Optional[torch.Tensor] = None,
+                 stream=None) -> torch.Tensor:
+    """Cameras at the poses R' = Exp(phi) R, t' = Exp(phi) t + rho for
+    xi = [V, 6] (rho, phi) (gs_pose_retract)."""
+    V = cams.numel() // L.GS_CAMERA_FLOATS
+    _need(cams, "cams")
+    _need(xi, "pose_tangent")
+    if xi.numel() != 6 * V:
+        raise ValueError("pose_tangent must hold n_views x 6 floats")
+    out = torch.empty_like(cams) if out is None else out
+    L.check(L.lib().gs_pose_retract(_ptr(cams), _ptr(xi), _ptr(out), V, _stream(stream)))
+    return out
+
+
+def pose_tangent_vjp(xi: torch.Tensor, g_delta: torch.Tensor, out: Optional[torch.Tensor] = None,
+                     stream=None) -> torch.Tensor:
+    """dL/dxi from the camera gradient at the retracted pose (gs_pose_tangent_vjp)."""
+    _need(xi, "pose_tangent")
+    _need(g_delta, "dL_ddelta")
+    V = xi.numel() // 6
+    out = torch.empty_like(g_delta) if out is None else out
+    L.check(L.lib().gs_pose_tangent_vjp(_ptr(xi), _ptr(g_delta), _ptr(out), V, _stream(stream)))
+    return out
+
+
+class Rasterizer:
+    """Differentiable render of a fixed set of views (sizes, SH degree, tile
+    configuration), reusable across calls: the plan is kept while the
+    Gaussian count stays the same, and workspaces are pooled -- a forward
+    takes one (allocating a zero-filled one only when none is free) and its
+    backward returns it, so steady-state calls allocate nothing beyond
+    torch's caching allocator.
+
+    The pair capacity grows on demand: each forward reads the device flags
+    once (one host synchronisation, the overflow check) and, if the pairs
+    did not fit, re-plans with 25 % headroom and renders again.  With
+    check_overflow=False there is no synchronisation; the caller then reads
+    ``overflowed()`` after its own synchronisation.
+    """
+
+    def __init__(self, view_wh: Sequence[Tuple[int, int]], sh_degree: int, tile=_DEFAULT_TILE,
+                 lds_batch: int = 256, flags: int = 0, pair_capacity: int = 1 << 16,
+                 check_overflow: bool = True):
+        self.view_wh = [(int(w), int(h)) for (w, h) in view_wh]
+        self.sh_degree = int(sh_degree)
+        self.tile, self.lds_batch = tuple(tile), int(lds_batch)
+        self.flags = int(flags) & ~(L.GS_FUSED_L1 | L.GS_ACCUMULATE_GRADS)
+        self.capacity = max(1, int(pair_capacity))
+        self.check_overflow = check_overflow
+        self.plan: Optional[Plan] = None
+        self._free: List[torch.Tensor] = []
+        self._last_ws: Optional[torch.Tensor] = None
+
+    @property
+    def n_views(self):
+        return len(self.view_wh)
+
+    def _plan_for(self, n: int) -> Plan:
+        if self.plan is None or self.plan.n != n or self.plan.pair_capacity != self.capacity:
+            self.plan = Plan(n, self.sh_degree, self.view_wh, tile=self.tile,
+                             lds_batch=self.lds_batch, flags=self.flags,
+                             pair_capacity=self.capacity)
+            self._free = []   # workspaces of another layout
+        return self.plan
+
+    def acquire(self, device) -> torch.Tensor:
+        plan = self.plan
+        while self._free:
+            ws = self._free.pop()
+            if ws.numel() >= plan.ws_bytes and ws.device == torch.device(device):
+                return ws
+        return plan.new_workspace(device)
+
+    def release(self, plan: Plan, ws: torch.Tensor):
+        if plan is self.plan:
+            self._free.append(ws)
+
+    def overflowed(self) -> bool:
+        """Whether the last forward's pairs exceeded the capacity (reads the
+        device flags: synchronises)."""
+        if self._last_ws is None:
+            return False
+        return bool(self.plan.flags_of(self._last_ws)[L.F_OVERFLOW])
+
+    def forward_buffers(self, g: "Gaussians", cams: torch.Tensor):
+        """Preprocess, binning and forward into fresh output buffers; returns
+        (plan, ws, frame).  Retries once with a larger capacity on overflow."""
+        for attempt in range(2):
+            plan = self._plan_for(g.n)
+            ws = self.acquire(g.means.device)
+            preprocess(plan, ws, g, cams)
+            bin_sort(plan, ws)
+            fr = Frame(plan, g.means.device)
+            render_fwd(plan, ws, cams, fr)
+            self._last_ws = ws
+            if not self.check_overflow:
+                return plan, ws, fr
+            fl = plan.flags_of(ws)
+            if not fl[L.F_OVERFLOW]:
+                return plan, ws, fr
+            self.release(plan, ws)
+            self.capacity = int(fl[L.F_PAIRS_WANTED] * 1.25) + 1024
+            if self.capacity > 0x7FFFFFFF:
+                break
+        raise RuntimeError(f"pair capacity exceeded ({int(fl[L.F_PAIRS_WANTED])} pairs needed)")
+
+    def __call__(self, means, log_scales, quats, opacity_logits, sh, cams: torch.Tensor,
+                 pose_tangent: Optional[torch.Tensor] = None):
+        return _Rasterize.apply(means, log_scales, quats, opacity_logits, sh, pose_tangent,
+                                cams, self)
+
+
 class _Rasterize(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, means, log_scales, quats, opacity_logits, sh, pose_tangent, cams, plan,
-                sh_degree):
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, pose_tangent, cams, rz):
         g = Gaussians(means.detach().contiguous(), log_scales.detach().contiguous(),
                       quats.detach().contiguous(), opacity_logits.detach().contiguous(),
-                      sh.detach().contiguous(), sh_degree)
-        ws = plan.new_workspace(means.device)
-        preprocess(plan, ws, g, cams)
-        bin_sort(plan, ws)
-        fr = Frame(plan, means.device)
-        render_fwd(plan, ws, cams, fr)
-        flags = plan.flags_of(ws)
-        if flags[L.F_OVERFLOW]:
-            raise RuntimeError(
-                f"pair capacity {plan.pair_capacity} exceeded ({flags[L.F_PAIRS_WANTED]} needed)")
-        ctx.plan, ctx.ws, ctx.frame, ctx.g, ctx.cams = plan, ws, fr, g, cams
+                      sh.detach().contiguous(), rz.sh_degree)
+        _need(cams, "cams")
+        xi = None
+        if pose_tangent is not None:
+            xi = pose_tangent.detach().contiguous()
+            cams = pose_retract(cams, xi)
+        plan, ws, fr = rz.forward_buffers(g, cams)
+        if any(ctx.needs_input_grad):
+            ctx.rz, ctx.plan, ctx.ws, ctx.frame, ctx.g, ctx.cams, ctx.xi = (
+                rz, plan, ws, fr, g, cams, xi)
+        else:
+            rz.release(plan, ws)
         ctx.mark_non_differentiable(fr.T_final)
         return fr.color, fr.depth, fr.T_final
 
     @staticmethod
     def backward(ctx, g_color, g_depth, g_T):
         plan, g = ctx.plan, ctx.g
-        grads = g.zeros_like()
-        dpose = torch.zeros(plan.n_views, 6, dtype=torch.float32, device=g.means.device)
+        dev = g.means.device
+        grads = Gaussians(*[torch.empty_like(x) for x in g.tensors()], g.sh_degree)
+        want_pose = ctx.xi is not None and ctx.needs_input_grad[5]
+        dpose = torch.empty(plan.n_views, 6, dtype=torch.float32, device=dev) if want_pose else None
         gc = torch.zeros_like(ctx.frame.color) if g_color is None else g_color.contiguous()
         gd = None if g_depth is None else g_depth.contiguous()
         render_bwd(plan, ctx.ws, g, ctx.cams, ctx.frame, grads, dL_dcolor=gc, dL_ddepth=gd,
                    dL_dpose=dpose)
+        ctx.rz.release(plan, ctx.ws)
+        ctx.ws = None
+        dxi = pose_tangent_vjp(ctx.xi, dpose) if want_pose else None
         return (grads.means, grads.log_scales, grads.quats, grads.opacity_logits,
-                grads.sh.view_as(g.sh), dpose, None, None, None)
+                grads.sh.view_as(g.sh), dxi, None, None)
+
+
+_RASTERIZERS = {}
 
 
 def rasterize(means, log_scales, quats, opacity_logits, sh, cams: torch.Tensor,
@@ -483,21 +603,22 @@ def rasterize(means, log_scales, quats, opacity_logits, sh, cams: torch.Tensor,
 
     Returns (color [3*P], depth [P], T_final [P]) concatenated over views
     (split with Plan.split_views).  Gradients flow to the five parameter
-    tensors and to ``pose_tangent`` ([V, 6] = (rho, phi), evaluated at zero:
-    a left perturbation R <- Exp(phi) R, t <- Exp(phi) t + rho of each view's
-    world->camera pose).  With pair_capacity None, the capacity is found by a
-    first binning pass (one host synchronisation).
+    tensors and to ``pose_tangent`` ([V, 6] = (rho, phi)): the views are
+    rendered at R' = Exp(phi) R, t' = Exp(phi) t + rho (gs_pose_retract),
+    and dL/dxi is the camera gradient pulled back through that map
+    (gs_pose_tangent_vjp; at xi = 0 it is the camera gradient itself).
+    Plans and workspaces are cached per (view sizes, degree, tile, LDS
+    batch); the pair capacity grows on demand (see Rasterizer).
     """
-    n = int(means.shape[0])
-    if pose_tangent is None:
-        pose_tangent = torch.zeros(len(view_wh), 6, dtype=torch.float32, device=means.device)
-    if pair_capacity is None:
-        pair_capacity = required_pairs(means, log_scales, quats, opacity_logits, sh, cams,
-                                       view_wh, sh_degree, tile)
-    plan = Plan(n, sh_degree, view_wh, tile=tile, lds_batch=lds_batch,
-                pair_capacity=max(1, int(pair_capacity)))
-    return _Rasterize.apply(means, log_scales, quats, opacity_logits, sh, pose_tangent, cams,
-                            plan, sh_degree)
+    key = (tuple((int(w), int(h)) for (w, h) in view_wh), int(sh_degree), tuple(tile),
+           int(lds_batch), str(means.device))
+    rz = _RASTERIZERS.get(key)
+    if rz is None:
+        rz = Rasterizer(view_wh, sh_degree, tile=tile, lds_batch=lds_batch)
+        _RASTERIZERS[key] = rz
+    if pair_capacity is not None and int(pair_capacity) > rz.capacity:
+        rz.capacity = int(pair_capacity)
+    return rz(means, log_scales, quats, opacity_logits, sh, cams, pose_tangent)
 
 
 def required_pairs(means, log_scales, quats, opacity_logits, sh, cams, view_wh, sh_degree,

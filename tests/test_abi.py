@@ -96,6 +96,20 @@ def test_entry_points_reject_bad_arguments_without_gpu():
     assert lib.gs_adam_step(grp, 1, 1, 0.9, 0.999, 1e-15, 0.0, 0, None, None) == L.GS_ERR_INVALID_ARG
     assert lib.gs_adam_step(grp, 1, 0, 0.9, 0.999, 1e-15, 0.0, 0, None, None) == L.GS_ERR_INVALID_ARG
     assert lib.gs_graph_create(None, None, None) == L.GS_ERR_INVALID_ARG
+    # an iteration with Adam groups but no device step counter
+    it = L.GsIteration()
+    it.plan = ctypes.pointer(p)
+    it.ws = 256
+    it.adam_groups = ctypes.cast(grp, ctypes.POINTER(L.GsParamGroup))
+    it.n_adam_groups = 1
+    it.step_dev = None
+    assert lib.gs_iteration_enqueue(ctypes.byref(it), None) == L.GS_ERR_INVALID_ARG
+    assert b"step_dev" in lib.gs_last_error()
+    # pose retraction and its tangent pull-back: null buffers, view count
+    assert lib.gs_pose_retract(None, 16, 16, 1, None) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_pose_retract(16, 16, 16, 0, None) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_pose_tangent_vjp(16, None, 16, 1, None) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_pose_tangent_vjp(16, 16, 16, L.GS_MAX_VIEWS + 1, None) == L.GS_ERR_INVALID_ARG
     assert lib.gs_status_string(L.GS_ERR_HIP) == b"GS_ERR_HIP"
 
 

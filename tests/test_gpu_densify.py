@@ -10,7 +10,7 @@ from oracle import densify as D
 import paper_2410_00486_amd as gsr
 from synth import scenes
 
-from gpu_common import DEV, flagged_gaussians, run_gpu, t32, workload
+from gpu_common import DEV, run_gpu, t32, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -32,10 +32,19 @@ def test_grad_stats_match_oracle():
     a, d = D.accumulate_stats(np.zeros(n), np.zeros(n), g2["mean2d"], vis, cam.width, cam.height)
     a, d = D.accumulate_stats(a, d, g2["mean2d"], vis, cam.width, cam.height)
     np.testing.assert_array_equal(den.cpu().numpy(), d)
-    ex = flagged_gaussians(ref, (16, 16), cam)
+    # excluded: Gaussians with a near-threshold decision of their own, and
+    # those whose statistic moves by more than a quarter of the tolerance
+    # when every near-threshold decision takes the other branch
+    g2f = oracle.backward_2d(w.scene, cam, gc[0], gd[0], fwd=oracle.render(w.scene, cam, flip_band=True))
+    af, _ = D.accumulate_stats(np.zeros(n), np.zeros(n), g2f["mean2d"], vis, cam.width, cam.height)
+    rms = np.sqrt(np.mean(a ** 2))
+    tol = 1e-3 * a + 1e-3 * rms
+    ex = np.abs(2 * af - a) > 0.25 * tol
+    _, gi, kind = oracle.flag_decisions(ref, cam)
+    ex[gi[kind < 8]] = True
+    assert ex.sum() <= max(2, 0.01 * vis.sum())
     got = acc.cpu().numpy().astype(np.float64)
-    rms = np.sqrt(np.mean(a[~ex] ** 2))
-    assert (np.abs(got - a)[~ex] <= 1e-3 * a[~ex] + 1e-3 * rms).all()
+    assert (np.abs(got - a)[~ex] <= tol[~ex]).all()
 
 
 @pytest.mark.parametrize("n,deg", [(0, 0), (1, 3), (5000, 1), (70_001, 3)])

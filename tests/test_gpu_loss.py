@@ -10,7 +10,8 @@ import paper_2410_00486_amd as gsr
 from paper_2410_00486_amd import _lib as L
 from synth import scenes
 
-from gpu_common import DEV, assert_grads_close, flagged_gaussians, grads_np, t32, workload
+from gpu_common import (DEV, assert_grads_close, grads_np, oracle_reference, t32,
+                        visible_count, workload)
 
 pytestmark = pytest.mark.gpu
 
@@ -61,7 +62,10 @@ def test_iteration_with_ssim_matches_oracle():
     ref = oracle.render(w.scene, cam)
     loss, gC, gD = ossim.rendered_loss_and_grads(ref["color"], ref["depth"], trgb, None, 0.2, 0.0)
     assert abs(float(it.frame.loss[0]) - loss) <= 1e-5 * loss
-    grads, _ = oracle.backward(w.scene, cam, gC, gD)
-    amb = (np.abs(ref["color"] - trgb) <= 1e-5).any(0)
-    ref2 = dict(ref, flag=((ref["flag"] != 0) | amb).astype(np.int32))
-    assert_grads_close(grads_np(it), grads, flagged_gaussians(ref2, (16, 16), cam))
+    # residual signs not decided at FP32 accuracy: the other sign is as valid
+    amb = np.abs(ref["color"] - trgb) <= 1e-5
+    col_alt = np.where(amb, 2.0 * trgb - ref["color"], ref["color"])
+    _, gC_alt, gD_alt = ossim.rendered_loss_and_grads(col_alt, ref["depth"], trgb, None, 0.2, 0.0)
+    grads, _, exclude, _ = oracle_reference(w.scene, [cam], [gC], [gD], alt_gcs=[gC_alt],
+                                            alt_gds=[gD_alt])
+    assert_grads_close(grads_np(it), grads, exclude, visible=visible_count(w.scene, [cam]))

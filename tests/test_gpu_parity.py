@@ -4,8 +4,10 @@ Forward colour and depth must match within 1e-5 relative (+1e-7 absolute);
 gradients within 1e-3 relative (+1e-3 of the tensor's rms) per element and
 1e-4 in norm.  Pixels where the oracle sees a discrete decision (alpha clamp,
 1/255 skip, 1e-4 stop) within a relative 1e-5 of its threshold are excluded
-and counted; Gaussians whose tile box covers such a pixel's tile are
-excluded from the gradient check.  Integer and index work (tile boxes, pair
+and counted; Gaussians whose own decision is that close, or whose oracle
+gradient moves by more than a quarter of its tolerance when those decisions
+take the other branch, are excluded from the gradient check (fewer than 1 %
+of the visible ones).  Integer and index work (tile boxes, pair
 counts, the sorted pair list, `last`) must be bit-exact.
 """
 import numpy as np
@@ -17,8 +19,9 @@ import paper_2410_00486_amd as gsr
 from paper_2410_00486_amd import _lib as L
 from synth import scenes
 
-from gpu_common import (DEV, assert_forward_close, assert_grads_close, flagged_gaussians,
-                        grads_np, run_gpu, t32, view_images, workload)
+from gpu_common import (DEV, assert_forward_close, assert_grads_close, assert_pose_close,
+                        grads_np, oracle_reference, run_gpu, t32, view_images, visible_count,
+                        workload)
 
 pytestmark = pytest.mark.gpu
 
@@ -132,10 +135,8 @@ def test_long_tile_list_forward_backward(flags):
     ref = oracle.render(w.scene, cam)
     col, dep, _, _ = view_images(it, 0)
     assert_forward_close(col, dep, ref)
-    exclude = flagged_gaussians(ref, (16, 16), cam)
-    grads, _ = oracle.backward(w.scene, cam, gc[0], gd[0])
-    assert exclude.mean() < 0.05
-    assert_grads_close(grads_np(it), grads, exclude)
+    grads, _, exclude, _ = oracle_reference(w.scene, [cam], gc, gd)
+    assert_grads_close(grads_np(it), grads, exclude, visible=visible_count(w.scene, [cam]))
 
 
 # ------------------------------------------------------------------ forward
@@ -175,19 +176,16 @@ def _bwd_case(cfg, tile=(16, 16), lds=256, pose=False, flags=0):
     print(f"backward parity workload {cfg} tile {tile} lds {lds} flags {flags}", flush=True)
     it = run_gpu(w.scene, [cam], tile=tile, lds=lds, dL_dcolor=gc, dL_ddepth=gd, pose=pose,
                  flags=flags)
-    ref = oracle.render(w.scene, cam, tile)
-    exclude = flagged_gaussians(ref, tile, cam)
-    grads, pose_ref = oracle.backward(w.scene, cam, gc[0], gd[0], tile)
-    return it, grads, pose_ref, exclude
+    grads, pose_ref, exclude, pose_flip = oracle_reference(w.scene, [cam], gc, gd, tile)
+    return it, grads, (pose_ref, pose_flip), exclude
 
 
 @pytest.mark.parametrize("cfg,tile,lds", [(1, (16, 16), 256), (1, (8, 8), 64), (1, (16, 8), 128),
                                           (3, (16, 16), 256), (2, (16, 16), 128)])
 def test_backward_matches_oracle(cfg, tile, lds):
     it, grads, _, exclude = _bwd_case(cfg, tile, lds)
-    visible = (oracle.preprocess(workload(cfg).scene, workload(cfg).cameras[0], tile)["status"] == 1).sum()
-    assert exclude.sum() < 0.15 * visible
-    rep = assert_grads_close(grads_np(it), grads, exclude)
+    visible = visible_count(workload(cfg).scene, workload(cfg).cameras[:1], tile)
+    rep = assert_grads_close(grads_np(it), grads, exclude, visible=visible)
     print(f"workload {cfg}: excluded {int(exclude.sum())} Gaussians; (max err/tol, rel norm) {rep}")
 
 
@@ -199,9 +197,8 @@ def test_splat_backward_matches_oracle(cfg, tile, lds):
     plain forward bit for bit."""
     it, grads, _, exclude = _bwd_case(cfg, tile, lds, flags=L.GS_SPLAT_BWD)
     w = workload(cfg)
-    visible = (oracle.preprocess(w.scene, w.cameras[0], tile)["status"] == 1).sum()
-    assert exclude.sum() < 0.15 * visible
-    rep = assert_grads_close(grads_np(it), grads, exclude)
+    visible = visible_count(w.scene, w.cameras[:1], tile)
+    rep = assert_grads_close(grads_np(it), grads, exclude, visible=visible)
     print(f"workload {cfg}: excluded {int(exclude.sum())} Gaussians; (max err/tol, rel norm) {rep}")
     plain = run_gpu(w.scene, [w.cameras[0]], tile=tile, lds=lds)
     for k in range(4):
@@ -214,14 +211,9 @@ def test_splat_backward_multi_view_and_pose():
     print("splat-wise backward, 4 views, pose", flush=True)
     it = run_gpu(scene, cams, dL_dcolor=gcs, dL_ddepth=gds, pose=True,
                  flags=L.GS_SPLAT_BWD | L.GS_PERSISTENT)
-    exclude = np.zeros(scene.n, bool)
-    for cam in cams:
-        exclude |= flagged_gaussians(oracle.render(scene, cam), (16, 16), cam)
-    grads, poses = oracle.backward(scene, list(cams), gcs, gds)
-    assert_grads_close(grads_np(it), grads, exclude)
-    got = it.dL_dpose.cpu().numpy()
-    for v in range(len(cams)):
-        assert np.linalg.norm(got[v] - poses[v]) <= 1e-3 * np.linalg.norm(poses[v])
+    grads, poses, exclude, poses_f = oracle_reference(scene, cams, gcs, gds)
+    assert_grads_close(grads_np(it), grads, exclude, visible=visible_count(scene, cams))
+    assert_pose_close(it.dL_dpose.cpu().numpy(), poses, poses_f)
 
 
 def test_pose_gradient_matches_oracle():
@@ -229,11 +221,10 @@ def test_pose_gradient_matches_oracle():
     scene whose oracle tangent is checked against FP64 central differences
     in the CPU pins (an FP32 finite difference of a 150k-Gaussian image is not
     a valid check: the 1/255 skip and the 1e-4 stop make the loss jump)."""
-    it, grads, pose_ref, exclude = _bwd_case(3, pose=True)
-    assert_grads_close(grads_np(it), grads, exclude)
-    got = it.dL_dpose.cpu().numpy().astype(np.float64)[0]
-    ref = pose_ref[0]
-    assert np.linalg.norm(got - ref) <= 1e-3 * np.linalg.norm(ref), (got, ref)
+    it, grads, (pose_ref, pose_flip), exclude = _bwd_case(3, pose=True)
+    assert_grads_close(grads_np(it), grads, exclude,
+                       visible=visible_count(workload(3).scene, workload(3).cameras))
+    assert_pose_close(it.dL_dpose.cpu().numpy(), pose_ref, pose_flip)
     # the FD-pinned small scene (same construction as the CPU pin)
     w = scenes.tiny_scene(16, n=10, degree=3)
     rng = np.random.default_rng(17)
@@ -259,15 +250,15 @@ def test_fused_l1_matches_oracle():
     loss, gC, gD = oracle.l1_loss_and_grads(ref["color"], ref["depth"], trgb, tdep, 0.1)
     got_loss = float(it.frame.loss.cpu()[0])
     assert abs(got_loss - loss) <= 1e-5 * abs(loss)
-    # pixels whose residual sign is not decided at FP32 accuracy are ambiguous
-    amb = (np.abs(ref["color"] - trgb) <= 1e-5 * np.abs(trgb) + 1e-6).any(0)
-    amb |= np.abs(ref["depth"] - tdep) <= 1e-5 * np.abs(tdep) + 1e-6
-    ref2 = dict(ref)
-    ref2["flag"] = ((ref["flag"] != 0) | amb).astype(np.int32)
-    exclude = flagged_gaussians(ref2, (16, 16), cam)
-    grads, _ = oracle.backward(w.scene, cam, gC, gD)
-    assert exclude.mean() < 0.05
-    assert_grads_close(grads_np(it), grads, exclude)
+    # residual signs not decided at FP32 accuracy: the other sign is as valid
+    ambc = np.abs(ref["color"] - trgb) <= 1e-5 * np.abs(trgb) + 1e-6
+    ambd = np.abs(ref["depth"] - tdep) <= 1e-5 * np.abs(tdep) + 1e-6
+    col_alt = np.where(ambc, 2.0 * trgb - ref["color"], ref["color"])
+    dep_alt = np.where(ambd, 2.0 * tdep - ref["depth"], ref["depth"])
+    _, gC_alt, gD_alt = oracle.l1_loss_and_grads(col_alt, dep_alt, trgb, tdep, 0.1)
+    grads, _, exclude, _ = oracle_reference(w.scene, [cam], [gC], [gD], alt_gcs=[gC_alt],
+                                            alt_gds=[gD_alt])
+    assert_grads_close(grads_np(it), grads, exclude, visible=visible_count(w.scene, [cam]))
 
 
 # ------------------------------------------------------------------ Adam
@@ -333,17 +324,13 @@ def test_batched_matches_oracle_multi_view():
     scene, cams = _multi_view_workload()
     gcs, gds = scenes.linear_loss_weights(45, cams)
     it = run_gpu(scene, cams, dL_dcolor=gcs, dL_ddepth=gds, pose=True, flags=L.GS_PERSISTENT)
-    exclude = np.zeros(scene.n, bool)
     for v, cam in enumerate(cams):
         ref = oracle.render(scene, cam)
         col, dep, _, _ = view_images(it, v)
         assert_forward_close(col, dep, ref)
-        exclude |= flagged_gaussians(ref, (16, 16), cam)
-    grads, poses = oracle.backward(scene, list(cams), gcs, gds)
-    assert_grads_close(grads_np(it), grads, exclude)
-    got = it.dL_dpose.cpu().numpy()
-    for v in range(len(cams)):
-        assert np.linalg.norm(got[v] - poses[v]) <= 1e-3 * np.linalg.norm(poses[v])
+    grads, poses, exclude, poses_f = oracle_reference(scene, cams, gcs, gds)
+    assert_grads_close(grads_np(it), grads, exclude, visible=visible_count(scene, cams))
+    assert_pose_close(it.dL_dpose.cpu().numpy(), poses, poses_f)
 
 
 def test_persistent_equals_plain():
@@ -572,6 +559,48 @@ def test_pair_capacity_overflow_is_flagged():
     assert fl[L.F_OVERFLOW] == 1 and fl[L.F_PAIRS_WANTED] > 100 and fl[L.F_PAIRS] == 0
 
 
+@pytest.mark.parametrize("views,graph", [(1, False), (1, True), (2, False), (2, True)])
+def test_overflow_iteration_leaves_optimizer_state_unchanged(views, graph):
+    """A whole iteration whose pairs overflow the plan's capacity: its Adam
+    step changes no parameter, moment or step counter (one view: the sparse
+    in-iteration Adam; two views: the plain one), eagerly and as graph
+    replays."""
+    w = workload(1)
+    cams = [w.cameras[0]] * views
+    wh = [(c.width, c.height) for c in cams]
+    lrs = {"means": 1e-3, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
+    tgt = t32(np.concatenate([w.target_rgb[0].reshape(-1)] * views))
+    g = gsr.Gaussians.from_scene(w.scene, DEV)
+    plan = gsr.Plan(w.scene.n, 0, wh, flags=L.GS_FUSED_L1, pair_capacity=100)
+    it = gsr.Iteration(plan, g, gsr.cameras_tensor(cams, DEV), target_rgb=tgt, adam_lrs=lrs,
+                       lambda_o=0.001)
+    for k, x in enumerate(it.m.tensors()):
+        x.fill_(0.25 * (k + 1))
+    for k, x in enumerate(it.v.tensors()):
+        x.fill_(0.01 * (k + 1))
+    it.step_dev.fill_(5)
+    before = [x.clone() for x in g.tensors() + it.m.tensors() + it.v.tensors()]
+    s = torch.cuda.Stream()
+    if graph:
+        with torch.cuda.stream(s):
+            it.capture(s)
+    for rep in range(2):
+        if graph:
+            with torch.cuda.stream(s):
+                it.replay(s)
+            s.synchronize()
+        else:
+            it.enqueue()
+        torch.cuda.synchronize()
+        fl = plan.flags_of(it.ws)
+        assert fl[L.F_OVERFLOW] == 1 and fl[L.F_PAIRS_WANTED] > 100
+        after = g.tensors() + it.m.tensors() + it.v.tensors()
+        for a, b in zip(before, after):
+            assert torch.equal(a, b), rep
+        assert int(it.step_dev.item()) == 5
+    it.close()
+
+
 def test_ragged_view_and_large_gaussian_and_sh_degrees():
     for deg in (1, 2):
         w = scenes.tiny_scene(31 + deg, n=40, width=33, height=17, degree=deg, f=25.0)
@@ -584,5 +613,5 @@ def test_ragged_view_and_large_gaussian_and_sh_degrees():
             ref = oracle.render(sc, cam, tile)
             col, dep, _, _ = view_images(it, 0)
             assert_forward_close(col, dep, ref)
-            grads, _ = oracle.backward(sc, cam, gc[0], gd[0], tile)
-            assert_grads_close(grads_np(it), grads, flagged_gaussians(ref, tile, cam))
+            grads, _, exclude, _ = oracle_reference(sc, [cam], gc, gd, tile)
+            assert_grads_close(grads_np(it), grads, exclude)

@@ -1,0 +1,168 @@
+"""Parity at the full sizes of the batched workloads, in the configuration
+the benchmark times (8x8 tiles, 64-record LDS batches, persistent render
+kernels, splat-wise backward):
+
+* the 8 keyframes of mixed resolution over a shared 500k-Gaussian pool
+  (visible counts from about 2k to 390k per view, tile lists of up to ~6k
+  pairs): every view's image, sorted pair lists, the summed gradients and
+  the camera tangents against the oracle; batched == per view;
+* the 16 views at 1200x680 over the 2M-Gaussian four-room pool (30 % of the
+  opacities below 0.05, up to ~1.4M visible and 4.2M pairs in one view):
+  batched == per view over all 16 views, two views against the oracle, and
+  the whole iteration with Adam as a graph replay against the same calls
+  enqueued eagerly.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2410_00486_amd as gsr
+from paper_2410_00486_amd import _lib as L
+from synth import scenes
+
+from gpu_common import (DEV, assert_forward_close, assert_grads_close, assert_pose_close,
+                        assert_sorted_lists_match_oracle, grads_np, oracle_reference, run_gpu,
+                        t32, view_images, visible_count, workload)
+
+pytestmark = pytest.mark.gpu
+
+TILE = (8, 8)
+BENCH_FLAGS = L.GS_PERSISTENT | L.GS_SPLAT_BWD
+LRS = {"means": 1.6e-4, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
+
+
+def _batched(scene, cams, seed, flags=BENCH_FLAGS):
+    gcs, gds = scenes.linear_loss_weights(seed, cams)
+    it = run_gpu(scene, cams, tile=TILE, lds=64, chunk=1, dL_dcolor=gcs, dL_ddepth=gds,
+                 pose=True, flags=flags)
+    return it, gcs, gds
+
+
+def _batched_equals_per_view(scene, cams, it, gcs, gds):
+    """Every view alone (its own plan) renders the same image bits as the
+    batched launch; the per-view gradients sum to the batched ones."""
+    acc = [torch.zeros(x.shape, dtype=torch.float64, device=DEV) for x in it.grads.tensors()]
+    batched_pose = it.dL_dpose.cpu().numpy()
+    for v, cam in enumerate(cams):
+        print(f"  view {v} alone", flush=True)
+        single = run_gpu(scene, [cam], tile=TILE, lds=64, chunk=1, dL_dcolor=[gcs[v]],
+                         dL_ddepth=[gds[v]], pose=True, flags=BENCH_FLAGS)
+        for k in range(4):
+            np.testing.assert_array_equal(view_images(single, 0)[k], view_images(it, v)[k])
+        np.testing.assert_allclose(single.dL_dpose.cpu().numpy()[0], batched_pose[v], rtol=1e-4,
+                                   atol=1e-6 * np.abs(batched_pose).max())
+        for a, x in zip(acc, single.grads.tensors()):
+            a += x.double()
+        del single
+    for f, a, b in zip(gsr.Gaussians.FIELDS, acc, it.grads.tensors()):
+        scale = float(a.abs().max())
+        err = (b.double() - a).abs()
+        assert bool((err <= 1e-4 * a.abs() + 1e-6 * scale).all()), (f, float(err.max()), scale)
+
+
+def test_keyframes8_full_matches_oracle():
+    w = workload(4)
+    cams = w.cameras
+    print("8 keyframes, 500k pool: batched launch against the oracle", flush=True)
+    it, gcs, gds = _batched(w.scene, cams, 400)
+    assert_sorted_lists_match_oracle(it, w.scene, cams, TILE, range(len(cams)))
+    for v, cam in enumerate(cams):
+        ref = oracle.render(w.scene, cam, TILE)
+        col, dep, _, last = view_images(it, v)
+        assert_forward_close(col, dep, ref)
+        ok = ref["flag"] == 0
+        np.testing.assert_array_equal(last[ok], ref["last"][ok])
+    grads, poses, exclude, poses_f = oracle_reference(w.scene, cams, gcs, gds, TILE)
+    rep = assert_grads_close(grads_np(it), grads, exclude,
+                             visible=visible_count(w.scene, cams, TILE))
+    print(f"excluded {int(exclude.sum())}; (max err/tol, rel norm) {rep}")
+    assert_pose_close(it.dL_dpose.cpu().numpy(), poses, poses_f)
+
+
+def test_keyframes8_full_batched_equals_per_view():
+    w = workload(4)
+    print("8 keyframes, 500k pool: batched == per view", flush=True)
+    it, gcs, gds = _batched(w.scene, w.cameras, 401)
+    _batched_equals_per_view(w.scene, w.cameras, it, gcs, gds)
+
+
+def test_keyframes16_batched_equals_per_view():
+    w = workload(5)
+    print("16 views 1200x680, 2M pool: batched == per view", flush=True)
+    it, gcs, gds = _batched(w.scene, w.cameras, 500)
+    fl = it.plan.flags_of(it.ws)
+    print(f"pairs {int(fl[L.F_PAIRS])}, visible records {int(fl[L.F_VISIBLE])}")
+    _batched_equals_per_view(w.scene, w.cameras, it, gcs, gds)
+
+
+def test_keyframes16_two_views_match_oracle():
+    """Two full-size views of the 2M pool (the densest and a sparse one)
+    batched: images, lists, gradients and camera tangents against the
+    oracle."""
+    w = workload(5)
+    cams = [w.cameras[8], w.cameras[9]]
+    print("16 views 1200x680, 2M pool: views 8 and 9 against the oracle", flush=True)
+    it, gcs, gds = _batched(w.scene, cams, 501)
+    assert_sorted_lists_match_oracle(it, w.scene, cams, TILE, range(2))
+    for v, cam in enumerate(cams):
+        ref = oracle.render(w.scene, cam, TILE)
+        col, dep, _, last = view_images(it, v)
+        assert_forward_close(col, dep, ref)
+        ok = ref["flag"] == 0
+        np.testing.assert_array_equal(last[ok], ref["last"][ok])
+    grads, poses, exclude, poses_f = oracle_reference(w.scene, cams, gcs, gds, TILE)
+    rep = assert_grads_close(grads_np(it), grads, exclude,
+                             visible=visible_count(w.scene, cams, TILE))
+    print(f"excluded {int(exclude.sum())}; (max err/tol, rel norm) {rep}")
+    assert_pose_close(it.dL_dpose.cpu().numpy(), poses, poses_f)
+
+
+def test_keyframes16_graph_with_adam_equals_eager():
+    """The full 16-view iteration with the fused L1 loss against rendered
+    targets and Adam, captured once and replayed, against the same iteration
+    enqueued eagerly: parameters, moments, images and losses bit for bit over
+    two steps."""
+    w = workload(5)
+    cams = w.cameras
+    wh = [(c.width, c.height) for c in cams]
+    ct = gsr.cameras_tensor(cams, DEV)
+    tg = gsr.Gaussians.from_scene(w.target_scene, DEV)
+    cap = gsr.required_pairs(*tg.tensors(), ct, wh, 3, TILE)
+    tplan = gsr.Plan(w.scene.n, 3, wh, tile=TILE, lds_batch=64, pair_capacity=cap + 4096)
+    tws = tplan.new_workspace(DEV)
+    tfr = gsr.Frame(tplan, DEV)
+    gsr.preprocess(tplan, tws, tg, ct)
+    gsr.bin_sort(tplan, tws)
+    gsr.render_fwd(tplan, tws, ct, tfr)
+    trgb, tdep = tfr.color.clone(), tfr.depth.clone()
+    del tws, tfr, tg
+
+    def make():
+        g = gsr.Gaussians.from_scene(w.scene, DEV)
+        cap = int(gsr.required_pairs(*g.tensors(), ct, wh, 3, TILE) * 1.3) + 4096
+        plan = gsr.Plan(w.scene.n, 3, wh, tile=TILE, lds_batch=64, chunk=1,
+                        flags=L.GS_FUSED_L1 | BENCH_FLAGS, pair_capacity=cap)
+        return gsr.Iteration(plan, g, ct, target_rgb=trgb, target_depth=tdep, adam_lrs=LRS)
+
+    print("16 views 1200x680, 2M pool: graph with Adam == eager", flush=True)
+    eager, graphed = make(), make()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        graphed.capture(s)
+    for step in range(2):
+        eager.enqueue()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            graphed.replay(s)
+        s.synchronize()
+        assert graphed.plan.flags_of(graphed.ws)[L.F_OVERFLOW] == 0
+        for f in gsr.Gaussians.FIELDS:
+            assert torch.equal(getattr(eager.g, f), getattr(graphed.g, f)), (step, f)
+            assert torch.equal(getattr(eager.m, f), getattr(graphed.m, f)), (step, f)
+            assert torch.equal(getattr(eager.v, f), getattr(graphed.v, f)), (step, f)
+        assert torch.equal(eager.frame.color, graphed.frame.color)
+        assert torch.equal(eager.frame.loss, graphed.frame.loss)
+        assert bool(torch.isfinite(graphed.frame.loss).all())
+    assert int(graphed.step_dev.item()) == 2
+    graphed.close()

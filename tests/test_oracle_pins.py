@@ -499,6 +499,53 @@ def test_pose_gradient_matches_finite_differences():
         assert abs(fd - pose[k]) <= 1e-6 * abs(pose[k]) + 1e-7 * np.abs(pose).max(), (k, fd, pose[k])
 
 
+def test_pose_tangent_away_from_zero_matches_finite_differences():
+    """The gradient of the tangent xi at xi != 0 (the autograd path renders at
+    the retracted pose R' = Exp(phi) R, t' = Exp(phi) t + rho): the camera
+    gradient at the retracted pose pulled back through the SO(3) left
+    Jacobian, against FP64 central differences of the loss over xi (the
+    rotation from scipy's rotvec map)."""
+    w = scenes.tiny_scene(16, n=10, degree=3)
+    sc = _as64(w.scene)
+    rng = np.random.default_rng(17)
+    R, t = scenes.random_pose(rng, 0.05, 0.05)
+    cam = _cam(32, 24, 30.0, R=R, t=t)
+    gC, gD = scenes.linear_loss_weights(18, [cam])
+    gC, gD = [gC[0] * 100], [gD[0] * 100]
+    xi = np.array([0.03, -0.02, 0.025, 0.04, -0.05, 0.03])
+    cx = oracle.retract_camera(cam, xi, round32=False)
+    _, g_delta = oracle.backward(sc, [cx], gC, gD)
+    g_xi = oracle.pose_tangent_vjp(xi, g_delta)[0]
+    assert np.linalg.norm(g_xi[3:] - g_delta[0, 3:]) > 1e-3 * np.linalg.norm(g_xi)  # not the identity here
+    for k in range(6):
+        h = 1e-6
+        vals = []
+        for sgn in (1, -1):
+            x2 = xi.copy()
+            x2[k] += sgn * h
+            f = oracle.render(sc, oracle.retract_camera(cam, x2, round32=False))
+            vals.append(oracle.linear_loss([f], gC, gD))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g_xi[k]) <= 1e-6 * abs(g_xi[k]) + 1e-7 * np.abs(g_xi).max(), (k, fd, g_xi[k])
+
+
+def test_so3_left_jacobian_series():
+    """J from its power series against the closed form I + (1-cos)/th^2 K +
+    (th - sin)/th^3 K^2 and against Exp(phi + eps e_k) Exp(phi)^T = Exp(eps J e_k)."""
+    phi = np.array([0.3, -0.7, 0.4])
+    th = np.linalg.norm(phi)
+    K = np.array([[0, -phi[2], phi[1]], [phi[2], 0, -phi[0]], [-phi[1], phi[0], 0]])
+    closed = np.eye(3) + (1 - math.cos(th)) / th ** 2 * K + (th - math.sin(th)) / th ** 3 * K @ K
+    J = oracle.so3_left_jacobian(phi)
+    np.testing.assert_allclose(J, closed, atol=1e-14)
+    for k in range(3):
+        e = np.zeros(3); e[k] = 1e-6
+        D = Rotation.from_matrix(oracle.so3_exp(phi + e) @ oracle.so3_exp(phi).T).as_rotvec()
+        Dm = Rotation.from_matrix(oracle.so3_exp(phi - e) @ oracle.so3_exp(phi).T).as_rotvec()
+        np.testing.assert_allclose((D - Dm) / 2e-6, J[:, k], atol=1e-8)
+    assert np.allclose(oracle.so3_left_jacobian(np.zeros(3)), np.eye(3))
+
+
 def test_pose_translation_equals_summed_mean_gradient():
     """Translating the camera by rho equals moving every mean by W^T rho, so
     g_rho = W sum_i g_p,i."""
