@@ -1,18 +1,27 @@
 #!/usr/bin/env python3
 """Mapping-iteration benchmark of the gfx950 differentiable 3DGS rasterizer.
 
-One step = one full mapping iteration of the CaRtGS back-end on the
-1200x680 indoor RGB-D view with 300k SH-3 Gaussians: per-Gaussian projection,
-tile binning, forward compositing with the L1 photometric + 0.1
-depth loss against a target, backward (raster + projection), Adam.  The
-timed form replays one captured HIP graph per step; the eager per-call form
-is timed beside it.  Also reported: per-stage times (HIP events on the
-launch stream), the dominant kernel against its roofline, algorithmic HBM
-bytes per iteration, batched (8 keyframes, one persistent graph) vs plain
-per-view iterations on the mixed-resolution keyframe workload, and the FP64
-oracle timed on the host cores.
+One step = one full mapping iteration over a batch of keyframes sharing one
+Gaussian pool: per-Gaussian projection, tile binning, forward compositing
+with the L1 RGB + 0.1 L1 depth loss against rendered targets, backward
+(raster + projection) and Adam.  The headline workload is the large-scene
+batch: 16 views at 1200x680 over a 2M-Gaussian four-room pool (SH degree 3,
+30 % of the opacities below 0.05).  Two forms of the same iteration are
+timed in one process:
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+* batched: one persistent whole-iteration HIP graph for all 16 views;
+* per view: the same kernels launched view by view (one plan per view,
+  gradients accumulated, one Adam step), stream-ordered, no graph.
+
+`value` is the batched form's iterations/s (median of the trials, HIP
+events around `--steps` graph replays on the launch stream, after
+`--warmup` replays).  Also reported: views/s, the per-launch durations of
+the batched iteration (HIP events between its launches, eagerly enqueued),
+the dominant kernel against its roofline, the same comparison on the
+8-keyframe mixed-resolution workload, the single-view workloads, and the
+FP64 oracle timed on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--trials T]
 """
 import argparse
 import json
@@ -39,12 +48,28 @@ BWD_FLOPS_PER_POS = 60
 # forward: alpha (quadratic form 9, exponent and clamp 4), transmittance 2,
 # weight and colour/depth blend 9, stop test 1 -> 25 flops per position
 FWD_FLOPS_PER_POS = 25
-# HBM counter summary of the headline iteration (rocprofv3 FETCH_SIZE /
-# WRITE_SIZE, scaled by a 1 GiB copy); used only while the kernel sources
-# still hash to the value recorded with the counters
-COUNTERS = os.path.join(ROOT, "profiles", "iteration_1200x680_300k_hbm_counters.txt")
-KERNEL_SOURCES = ["gs_internal.h", "api.hip", "preprocess.hip", "binsort.hip", "render.hip",
-                  "project_bwd.hip", "adam.hip", "loss.hip", "densify.hip"]
+# span of gs_iteration_time_marks -> the kernel(s) it holds
+SPAN_KERNELS = {
+    "preprocess": "k_preprocess<3>",
+    "bin_scan": "k_scans",
+    "bin_scatter": "k_scatter",
+    "bin_short_sort": "k_tile_sort",
+    "bin_long_sort": "k_tile_sort_long",
+    "forward": "k_render_fwd",
+    "loss": "(SSIM loss kernels)",
+    "raster_bwd": "k_render_bwd_splat",
+    "project_bwd": "k_project_bwd",
+    "adam": "k_adam",
+}
+# HBM counter summaries (rocprofv3 FETCH_SIZE / WRITE_SIZE per dispatch,
+# scaled by a 1 GiB copy), used only while the kernel sources still hash to
+# the value recorded with the counters
+COUNTER_FILES = {
+    "keyframes16_1200x680": os.path.join(ROOT, "profiles", "batched_16views_2M_hbm_counters.txt"),
+    "room_1200x680": os.path.join(ROOT, "profiles", "iteration_1200x680_300k_hbm_counters.txt"),
+}
+KERNEL_SOURCES = ["gs_internal.h", "tilesort.h", "api.hip", "preprocess.hip", "binsort.hip",
+                  "render.hip", "project_bwd.hip", "adam.hip", "loss.hip", "densify.hip"]
 
 
 def kernel_source_hash() -> str:
@@ -56,12 +81,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(workload: str, kernel: str):
     """Scaled HBM bytes per dispatch of `kernel` from the committed counter
-    summary, or None if there is none or the kernel sources changed since."""
-    if not os.path.exists(COUNTERS):
+    summary of `workload`, or None if there is none or the kernel sources
+    changed since the counters were taken."""
+    path = COUNTER_FILES.get(workload)
+    if not path or not os.path.exists(path):
         return None
-    text = open(COUNTERS).read().splitlines()
+    text = open(path).read().splitlines()
     src = [ln.split(":", 1)[1].strip() for ln in text if ln.startswith("kernel source sha1:")]
     if not src or src[0] != kernel_source_hash():
         return None
@@ -76,400 +103,18 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
-    # defaults: the configuration the autotuner selects for this workload on
-    # MI355X (8x8 tiles, 64-record LDS batches, plain grid); --autotune reruns
-    # the search over tile shape x LDS batch x chunk x persistence
-    ap.add_argument("--autotune", action="store_true")
-    ap.add_argument("--tile", default="8x8")
-    ap.add_argument("--lds-batch", type=int, default=64)
-    ap.add_argument("--chunk", type=int, default=1)
-    ap.add_argument("--persistent", type=int, default=0, choices=[0, 1])
-    ap.add_argument("--bwd", default="splat", choices=["pixel", "splat"],
-                    help="backward of the headline: pixel-wise wave-reduced or splat-wise")
-    ap.add_argument("--no-ab", action="store_true",
-                    help="skip timing the other backward variant")
-    ap.add_argument("--no-extras", action="store_true",
-                    help="skip the SSIM-loss, densification and scheduler timings")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="run only a 1 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--batched-only", action="store_true",
-                    help="only the 8-keyframe batched vs per-view comparison, with the "
-                         "--tile/--lds-batch/--chunk configuration unless --autotune "
-                         "(for profiler runs)")
-    ap.add_argument("--batched-workload", default="keyframes8_mixed",
-                    choices=["keyframes8_mixed", "keyframes16_1200x680"])
-    ap.add_argument("--graph-only", action="store_true",
-                    help="only the graph-timed headline loop (for profiler runs)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the "
-              "keyframes over several GPUs is a documented design, not built", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-
-    import paper_2410_00486_amd as gsr
-    from paper_2410_00486_amd import _lib as L
-    from synth import scenes
-
-    from paper_2410_00486_amd import tune
-
-    dev = torch.device("cuda:0")
-    if args.calibrate_copy:
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
-                          "launches": 5}))
-        return
-    if args.batched_only:
-        print(json.dumps(bench_batched(args, dev, search=args.autotune,
-                                       workload=args.batched_workload)))
-        return
-    t_setup = time.time()
-    w = scenes.room_1200x680()
-    cam = w.cameras[0]
-    view_wh = [(cam.width, cam.height)]
-    cams = gsr.cameras_tensor([cam], dev)
-    params = gsr.Gaussians.from_scene(w.scene, dev)
-    target_rgb, target_depth = render_target(gsr, w.target_scene, cams, view_wh, dev)
-
-    # ---- autotune tile shape / LDS batch / chunk / persistence (untimed)
-    table = []
-    best = {"tile": args.tile, "lds_batch": args.lds_batch, "chunk": args.chunk,
-            "persistent": bool(args.persistent), "ms": None}
-    if args.autotune:
-        best = None
-        for pers in (False, True):
-            b, tb = tune.autotune(params, cams, view_wh, target_rgb, target_depth, adam_lrs=LRS,
-                                  persistent=pers, chunks=[1, 2, 4] if pers else [1], reps=10)
-            for r in tb:
-                r["persistent"] = pers
-            table += tb
-            b = dict(b, persistent=pers)
-            if best is None or b["ms"] < best["ms"]:
-                best = b
-        log(f"autotune best {best}")
-        args.bwd = best["backward"]
-    tile = tuple(int(x) for x in best["tile"].split("x"))
-
-    cap0 = gsr.required_pairs(*params.tensors(), cams, view_wh, 3, tile)
-    cap = int(cap0 * 1.5) + 4096
-    flags = L.GS_FUSED_L1 | (L.GS_PERSISTENT if best["persistent"] else 0)
-    splat_flag = L.GS_SPLAT_BWD if args.bwd == "splat" else 0
-
-    def make_iteration(extra_flags, p):
-        pl = gsr.Plan(w.scene.n, 3, view_wh, tile=tile, lds_batch=best["lds_batch"],
-                      chunk=best["chunk"], flags=flags | extra_flags, pair_capacity=cap,
-                      lambda_depth=0.1)
-        return pl, gsr.Iteration(pl, p, cams, target_rgb=target_rgb, target_depth=target_depth,
-                                 adam_lrs=LRS, lambda_o=0.0)
-
-    # the other backward variant first, on its own copy of the parameters
-    ab = None
-    if not args.no_ab:
-        other = "pixel" if args.bwd == "splat" else "splat"
-        p2 = gsr.Gaussians.from_scene(w.scene, dev)
-        plan2, it2 = make_iteration(L.GS_SPLAT_BWD if other == "splat" else 0, p2)
-        s2 = torch.cuda.Stream()
-        with torch.cuda.stream(s2):
-            it2.capture(s2)
-            for _ in range(args.warmup):
-                it2.replay(s2)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        with torch.cuda.stream(s2):
-            for _ in range(args.steps):
-                it2.replay(s2)
-        torch.cuda.synchronize()
-        ms2 = (time.perf_counter() - t0) * 1e3 / args.steps
-        with torch.cuda.stream(s2):
-            evs = []
-            for _ in range(args.steps):
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record(s2)
-                gsr.render_bwd_raster(plan2, it2.ws, cams, it2.frame, target_rgb=target_rgb,
-                                      target_depth=target_depth, stream=s2)
-                b.record(s2)
-                evs.append((a, b))
-        torch.cuda.synchronize()
-        ab = {other: {"iters_per_s": round(1e3 / ms2, 2),
-                      "render_bwd_ms": round(float(np.mean([a.elapsed_time(b) for a, b in evs])), 4)}}
-        log(f"{other}-wise backward: {ms2:.3f} ms/iter, bwd {ab[other]['render_bwd_ms']} ms")
-        it2.close()
-        del it2, p2
-        torch.cuda.synchronize()
-
-    plan, it = make_iteration(splat_flag, params)
-    stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        it.capture(stream)
-    torch.cuda.synchronize()
-    log(f"setup {time.time() - t_setup:.1f}s: N={w.scene.n} pairs~{cap0} cap={cap}")
-
-    # ---- headline: graph replay, one mapping iteration per step
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            it.replay(stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        for _ in range(args.steps):
-            it.replay(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_graph = (t1 - t0) * 1e3 / args.steps
-    fl = plan.flags_of(it.ws)
-    if fl[L.F_OVERFLOW]:
-        raise SystemExit(f"pair capacity overflow ({fl[L.F_PAIRS_WANTED]} > {cap})")
-    log(f"graph: {ms_graph:.3f} ms/iter, loss {float(it.frame.loss[0]):.5f}")
-    if args.graph_only:
-        print(json.dumps({"ms_per_step_graph": ms_graph}))
-        return
-
-    # ---- eager per-call form, per-stage HIP events on the launch stream
-    P = int(fl[L.F_PAIRS])
-    V = int(fl[L.F_VISIBLE])
-    E_bwd = int(it.frame.last.to(torch.int64).sum().item())
-    npx = plan.total_pixels
-    stages = ["preprocess", "bin_sort", "render_fwd", "render_bwd_raster", "project_bwd", "adam"]
-    ev = {s: [] for s in stages}
-    groups = it._groups
-    with torch.cuda.stream(stream):
-        def eager_iter(record):
-            marks = []
-            def mark():
-                if record:
-                    e = torch.cuda.Event(enable_timing=True)
-                    e.record(stream)
-                    marks.append(e)
-            mark()
-            gsr.preprocess(plan, it.ws, params, cams, stream)
-            mark()
-            gsr.bin_sort(plan, it.ws, stream)
-            mark()
-            gsr.render_fwd(plan, it.ws, cams, it.frame, target_rgb, target_depth, stream)
-            mark()
-            gsr.render_bwd_raster(plan, it.ws, cams, it.frame, target_rgb=target_rgb,
-                                  target_depth=target_depth, stream=stream)
-            mark()
-            gsr.project_bwd(plan, it.ws, params, cams, it.grads, stream=stream)
-            mark()
-            if record:
-                # one kernel between the marks: an explicit step launches
-                # k_adam alone (with the device counter a one-thread launch
-                # that advances it follows)
-                gsr.adam_step(groups, 1, stream=stream)
-            else:
-                gsr.adam_step(groups, 1, step_dev=it.step_dev, stream=stream)
-            mark()
-            return marks
-
-        for _ in range(args.warmup):
-            eager_iter(False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            eager_iter(False)
-        torch.cuda.synchronize()
-        ms_eager = (time.perf_counter() - t0) * 1e3 / args.steps
-        all_marks = [eager_iter(True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    for marks in all_marks:
-        for k, s in enumerate(stages):
-            ev[s].append(marks[k].elapsed_time(marks[k + 1]))
-    def trimmed_mean(v, frac=0.1):
-        # mean of the launches between the 10th and 90th percentile: a host
-        # stall between two event marks (tens of ms, once in a run) would
-        # otherwise dominate the mean of a 50 us stage
-        a = np.sort(np.asarray(v, dtype=np.float64))
-        k = int(len(a) * frac)
-        return float(a[k:len(a) - k].mean()) if len(a) > 2 * k else float(a.mean())
-
-    stage_ms = {s: trimmed_mean(v) for s, v in ev.items()}
-    log("stages (ms): " + ", ".join(f"{k}={v:.4f}" for k, v in stage_ms.items()))
-
-    # ---- algorithmic bytes per stage: the compulsory HBM reads and writes of
-    # each stage for the counted pairs P, visible records V, pixels and N
-    N, K = w.scene.n, 16
-    bytes_ = {
-        "preprocess": 44 * N + 12 * K * V + 72 * V + 4 * N,
-        "bin_sort": 16 * N + 12 * V + 168 * P + 20 * plan.total_tiles,
-        "render_fwd": 64 * P + 40 * npx,
-        "render_bwd_raster": 116 * P + 40 * npx,
-        "project_bwd": 44 * N + 12 * K * V + 236 * N + 8 * N + 48 * P,
-        "adam": 28 * 59 * N,
-    }
-    total_bytes = sum(bytes_.values())
-    dominant = max(stage_ms, key=stage_ms.get)
-    tile_t = f"<{tile[0]},{tile[1]}>"
-
-    def alu_roofline(stage):
-        if stage == "render_bwd_raster":
-            kname = ("k_render_bwd_splat" if args.bwd == "splat" else "k_render_bwd") + tile_t
-            flops, api = BWD_FLOPS_PER_POS, "gs_render_bwd_raster"
-        else:
-            kname = "k_render_fwd" + tile_t[:-1] + ("," + "true>" if args.bwd == "splat" else ",false>")
-            flops, api = FWD_FLOPS_PER_POS, "gs_render_fwd"
-        tf = flops * E_bwd / (stage_ms[stage] * 1e-3) / 1e12
-        return {"bound": "alu", "kernel": f"{kname} ({api})", "achieved": round(tf, 3),
-                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / FP32_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(kname),
-                "work": f"{flops} flop x {E_bwd} pixel-Gaussian positions"}
-
-    if dominant in ("render_bwd_raster", "render_fwd"):
-        roofline = alu_roofline(dominant)
-        other = alu_roofline("render_fwd" if dominant == "render_bwd_raster" else "render_bwd_raster")
-    else:
-        gbs = bytes_[dominant] / (stage_ms[dominant] * 1e-3) / 1e9
-        kname = {"adam": "k_adam", "project_bwd": "k_project_bwd<3,false,true,true>",
-                 "preprocess": "k_preprocess<3>"}.get(dominant)
-        api = {"adam": "gs_adam_step", "project_bwd": "gs_project_bwd",
-               "preprocess": "gs_preprocess"}.get(dominant, dominant)
-        roofline = {"bound": "hbm", "kernel": f"{kname or dominant} ({api})", "achieved": round(gbs, 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(kname) if kname else None,
-                    "work": f"{bytes_[dominant]} algorithmic bytes per launch"}
-        other = alu_roofline("render_bwd_raster")
-    hbm_gbs = total_bytes / (ms_graph * 1e-3) / 1e9
-
-    result = {
-        "metric": METRIC,
-        "value": round(1e3 / ms_graph, 2),
-        "unit": "iters/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_graph, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32 (quadratic form and projection in f64)",
-        "data": "synthetic (seeded indoor room, shaped like the paper's RGB-D sequences)",
-        "config": {"workload": "room_1200x680: 1 view 1200x680 fx=fy=600, 300k Gaussians SH3, "
-                               "L1 RGB + 0.1 L1 depth, Adam, HIP graph per iteration",
-                   "tile": best["tile"], "lds_batch": best["lds_batch"], "chunk": best["chunk"],
-                   "persistent": bool(best["persistent"]), "backward": args.bwd},
-        "autotune": sorted(table, key=lambda r: r["ms"])[:6] if table else "defaults (--autotune to search)",
-        "plain_eager_iters_per_s": round(1e3 / ms_eager, 2),
-        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "counts": {"gaussians": N, "visible": V, "pairs": P, "pixels": npx,
-                   "bwd_positions": E_bwd},
-        "hbm_gbs_algorithmic": round(hbm_gbs, 1),
-        "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
-        "stage_gbs": {k: round(bytes_[k] / (stage_ms[k] * 1e-3) / 1e9, 1) for k in stages},
-        "roofline": roofline,
-        "roofline_other_raster_kernel": other,
-    }
-    if ab is not None:
-        ab[args.bwd] = {"iters_per_s": result["value"],
-                        "render_bwd_ms": round(stage_ms["render_bwd_raster"], 4)}
-        result["backward_ab"] = ab
-    if not args.no_extras:
-        result["extras"] = bench_extras(args, w, plan, it, params, cams, view_wh, target_rgb,
-                                        target_depth, stream)
-    it.close()
-    del it
-    torch.cuda.synchronize()
-
-    if not args.no_batched:
-        result["batched"] = bench_batched(args, dev)
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(w)
-    print(json.dumps(result))
+def trimmed_mean(v, frac=0.1):
+    # mean between the 10th and 90th percentile: one host stall between two
+    # event marks (tens of ms, once in a run) cannot dominate a short span
+    a = np.sort(np.asarray(v, dtype=np.float64))
+    k = int(len(a) * frac)
+    return float(a[k:len(a) - k].mean()) if len(a) > 2 * k else float(a.mean())
 
 
-def bench_extras(args, w, plan, it, params, cams, view_wh, target_rgb, target_depth, stream):
-    """The other rows of the path on the same view: the full Eq. (9) loss
-    with SSIM (standalone and inside the graphed iteration), densification
-    statistics and clone/split/prune of the 300k pool, keyframe selection."""
-    import torch
-
-    import paper_2410_00486_amd as gsr
-    from paper_2410_00486_amd.sched import KeyframeScheduler
-
-    dev = params.means.device
-    out = {}
-
-    def ev_time(fn, reps):
-        evs = []
-        with torch.cuda.stream(stream):
-            for _ in range(2):
-                fn()
-            for _ in range(reps):
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-                fn()
-                b.record(stream)
-                evs.append((a, b))
-        torch.cuda.synchronize()
-        return float(np.mean([a.elapsed_time(b) for a, b in evs]))
-
-    npx = plan.total_pixels
-    dLc = torch.empty(3 * npx, dtype=torch.float32, device=dev)
-    dLd = torch.empty(npx, dtype=torch.float32, device=dev)
-    out["ssim_loss_ms"] = round(ev_time(lambda: gsr.render_loss(
-        plan, it.ws, it.frame, target_rgb, target_depth, 0.2, dLc, dLd, stream), 20), 4)
-    accum = torch.zeros(params.n, dtype=torch.float32, device=dev)
-    denom = torch.zeros(params.n, dtype=torch.float32, device=dev)
-    out["grad_stats_ms"] = round(ev_time(lambda: gsr.grad_stats(plan, it.ws, accum, denom,
-                                                                 stream), 20), 4)
-    # clone/split/prune on a copy of the pool with statistics of one view
-    p2 = gsr.Gaussians(*[t.clone() for t in params.tensors()], params.sh_degree)
-    m2, v2 = p2.zeros_like(), p2.zeros_like()
-    normals = torch.randn(params.n, 2, 3, generator=torch.Generator().manual_seed(5)).to(dev)
-    times = []
-    for _ in range(5):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = gsr.densify_prune(p2, m2, v2, accum, denom, normals)  # reads its count
-        torch.cuda.synchronize()
-        times.append((time.perf_counter() - t0) * 1e3)
-    out["densify_prune_ms"] = round(float(np.median(times)), 4)
-    out["densify_prune_out"] = int(res[0].n)
-    # graphed iteration with the SSIM term (lambda_ssim 0.2): the loss
-    # gradients come from the loss kernels, so the plan drops the fused L1
-    from paper_2410_00486_amd import _lib as L
-    plan_s = plan.replace(flags=plan.flags & ~L.GS_FUSED_L1)
-    it2 = gsr.Iteration(plan_s, gsr.Gaussians(*[t.clone() for t in params.tensors()],
-                                            params.sh_degree), cams, target_rgb=target_rgb,
-                        target_depth=target_depth, adam_lrs=LRS, lambda_ssim=0.2)
-    with torch.cuda.stream(stream):
-        it2.capture(stream)
-        for _ in range(args.warmup):
-            it2.replay(stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        for _ in range(args.steps):
-            it2.replay(stream)
-    torch.cuda.synchronize()
-    out["iters_per_s_with_ssim"] = round(args.steps / (time.perf_counter() - t0), 2)
-    it2.close()
-    # keyframe selection (host): 1000 keyframes, one selection
-    ks = KeyframeScheduler(capacity=4096)
-    for k in range(1000):
-        ks.add_keyframe()
-        ks.report(k, 1.0 / (1 + k))
-    t0 = time.perf_counter()
-    for _ in range(100):
-        ks.select([0.5] * 8)
-    out["scheduler_select_us"] = round((time.perf_counter() - t0) * 1e4, 2)
-    log(f"extras: {out}")
-    return out
-
+# ---------------------------------------------------------------- set-up
 
 def render_target(gsr, scene, cams, view_wh, dev, tile=(16, 16)):
-    """Render the target images from (perturbed) parameters -- untimed setup."""
+    """Render target images from (perturbed) parameters -- untimed set-up."""
     tg = gsr.Gaussians.from_scene(scene, dev)
     tcap = gsr.required_pairs(*tg.tensors(), cams, view_wh, scene.sh_degree, tile)
     tplan = gsr.Plan(scene.n, scene.sh_degree, view_wh, tile=tile,
@@ -479,83 +124,140 @@ def render_target(gsr, scene, cams, view_wh, dev, tile=(16, 16)):
     gsr.preprocess(tplan, tws, tg, cams)
     gsr.bin_sort(tplan, tws)
     gsr.render_fwd(tplan, tws, cams, tfr)
-    return tfr.color.clone(), tfr.depth.clone()
+    out = tfr.color.clone(), tfr.depth.clone()
+    del tws, tfr, tg
+    return out
 
 
-def bench_batched(args, dev, search: bool = True, workload: str = "keyframes8_mixed"):
-    """8 keyframes of mixed resolution over a shared 500k pool: one autotuned
-    persistent graph for all views vs the same kernels and tile shape launched
-    view by view (one plan per view, gradients accumulated, one Adam step).
-    Without `search` the configuration comes from --tile, --lds-batch,
-    --chunk and --bwd instead of the autotuner."""
+def load_workload(name, dev):
+    """Scene, cameras and targets of a named workload (GPU-rendered targets
+    from the perturbed scene, or the drawn target of the small slab)."""
+    import torch
+
+    import paper_2410_00486_amd as gsr
+    from synth import scenes
+    w = getattr(scenes, name)()
+    cams_l = w.cameras
+    view_wh = [(c.width, c.height) for c in cams_l]
+    cams = gsr.cameras_tensor(cams_l, dev)
+    if w.target_scene is not None:
+        trgb, tdep = render_target(gsr, w.target_scene, cams, view_wh, dev)
+    elif w.gt_cameras is not None:
+        trgb, tdep = render_target(gsr, w.scene, gsr.cameras_tensor(w.gt_cameras, dev), view_wh,
+                                   dev)
+    else:
+        trgb = torch.from_numpy(np.concatenate([t.reshape(-1) for t in w.target_rgb])
+                                .astype(np.float32)).to(dev)
+        tdep = None
+    return w, view_wh, cams, trgb, tdep
+
+
+def time_replays(fn, stream, warmup, steps, trials):
+    """ms per call of fn() (which enqueues on `stream`): `warmup` untimed
+    calls, then `trials` runs of `steps` calls, each bracketed by HIP events
+    on the stream; returns the list of per-trial ms per call."""
+    import torch
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(trials):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            a.record(stream)
+            for _ in range(steps):
+                fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        out.append(a.elapsed_time(b) / steps)
+    return out
+
+
+# ---------------------------------------------------------------- batched vs per view
+
+def bench_batched(args, dev, workload, search=False, marks=True):
+    """One persistent whole-iteration graph for all views vs the same kernels
+    and tile shape launched view by view (one plan per view, gradients
+    accumulated, one Adam step).  With `search` the configuration comes from
+    the autotuner, otherwise from --tile/--lds-batch/--chunk/--bwd."""
     import torch
 
     import paper_2410_00486_amd as gsr
     from paper_2410_00486_amd import _lib as L
     from paper_2410_00486_amd import tune
-    from synth import scenes
 
-    w = getattr(scenes, workload)()
+    t_setup = time.time()
+    w, view_wh, cams, target_rgb, target_depth = load_workload(workload, dev)
     cams_l = w.cameras
-    view_wh = [(c.width, c.height) for c in cams_l]
-    cams = gsr.cameras_tensor(cams_l, dev)
     params = gsr.Gaussians.from_scene(w.scene, dev)
-    target_rgb, target_depth = render_target(gsr, w.target_scene, cams, view_wh, dev)
+    table = []
     if search:
         best, table = tune.autotune(params, cams, view_wh, target_rgb, target_depth, adam_lrs=LRS,
-                                    persistent=True, chunks=[1, 2, 4, 8], reps=8)
+                                    persistent=True, tiles=[(8, 8), (16, 8), (16, 16)],
+                                    lds_batches=[64, 128], chunks=[1, 2], backwards=["splat"],
+                                    reps=4)
     else:
         best = {"tile": args.tile, "lds_batch": args.lds_batch, "chunk": args.chunk,
                 "backward": args.bwd}
-        table = []
-    log(f"batched autotune best {best}")
     tile = tuple(int(x) for x in best["tile"].split("x"))
     cap0 = gsr.required_pairs(*params.tensors(), cams, view_wh, 3, tile)
     flags = L.GS_FUSED_L1 | L.GS_PERSISTENT | (L.GS_SPLAT_BWD if best["backward"] == "splat" else 0)
     plan = gsr.Plan(w.scene.n, 3, view_wh, tile=tile, flags=flags, chunk=best["chunk"],
-                    lds_batch=best["lds_batch"], pair_capacity=int(cap0 * 1.5) + 4096)
+                    lds_batch=best["lds_batch"], pair_capacity=int(cap0 * 1.3) + 4096)
     it = gsr.Iteration(plan, params, cams, target_rgb=target_rgb, target_depth=target_depth,
                        adam_lrs=LRS)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         it.capture(stream)
-        for _ in range(args.warmup):
-            it.replay(stream)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        for _ in range(args.steps):
-            it.replay(stream)
-    torch.cuda.synchronize()
-    ms_b = (time.perf_counter() - t0) * 1e3 / args.steps
+    log(f"{workload}: set-up {time.time() - t_setup:.1f}s, N={w.scene.n}, pairs~{cap0}, {best}")
+    trials_b = time_replays(lambda: it.replay(stream), stream, args.warmup, args.steps,
+                            args.trials)
+    ms_b = float(np.median(trials_b))
     fl = plan.flags_of(it.ws)
-    assert fl[L.F_OVERFLOW] == 0
-    vis_total = int(fl[L.F_VISIBLE])
-    grads = it.grads
+    if fl[L.F_OVERFLOW]:
+        raise SystemExit(f"{workload}: pair capacity overflow")
+    counts = {"gaussians": w.scene.n, "views": len(cams_l), "visible_records": int(fl[L.F_VISIBLE]),
+              "pairs": int(fl[L.F_PAIRS]), "pixels": plan.total_pixels,
+              "bwd_positions": int(it.frame.last.to(torch.int64).sum().item())}
+    log(f"{workload}: batched graph {ms_b:.3f} ms/iter (trials {[round(x, 3) for x in trials_b]}), "
+        f"counts {counts}")
+    spans = None
+    if marks:
+        # the same iteration enqueued eagerly with HIP events between its
+        # launches (per-launch durations of the batched kernels)
+        with torch.cuda.stream(stream):
+            per = it.time_marks(stream, warmup=2, reps=max(10, args.steps))
+        spans = {k: trimmed_mean(per[:, j]) for j, k in enumerate(gsr.Iteration.MARKS)}
+        log(f"{workload}: spans (ms) " + ", ".join(f"{k}={v:.4f}" for k, v in spans.items()))
     it.close()
+    grads = it.grads
     del it
     # the plain form starts from the same initial parameters
     params = gsr.Gaussians.from_scene(w.scene, dev)
     adam_m, adam_v = params.zeros_like(), params.zeros_like()
     groups = gsr.adam_groups(params, grads, adam_m, adam_v, LRS)
-    # plain per-view form: one plan and workspace per view, gradients summed
-    # into one buffer, then one Adam step
-    per, vis = [], []
+    per_view = []
     for v, c in enumerate(cams_l):
         cv = cams[v:v + 1].contiguous()
         capv = gsr.required_pairs(*params.tensors(), cv, [view_wh[v]], 3, tile)
         pv = gsr.Plan(w.scene.n, 3, [view_wh[v]], tile=tile, lds_batch=best["lds_batch"],
                       flags=L.GS_FUSED_L1 | L.GS_ACCUMULATE_GRADS | (flags & L.GS_SPLAT_BWD),
-                      pair_capacity=int(capv * 1.5) + 4096)
+                      pair_capacity=int(capv * 1.3) + 4096)
         off, npx = plan.pixel_offsets[v], view_wh[v][0] * view_wh[v][1]
-        per.append((pv, pv.new_workspace(dev), cv, gsr.Frame(pv, dev),
-                    target_rgb[3 * off:3 * (off + npx)], target_depth[off:off + npx]))
+        per_view.append((pv, pv.new_workspace(dev), cv, gsr.Frame(pv, dev),
+                         target_rgb[3 * off:3 * (off + npx)],
+                         None if target_depth is None else target_depth[off:off + npx]))
     step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
 
     def plain_iter():
         for x in grads.tensors():
             x.zero_()
-        for pv, ws, cv, fr, trgb, tdep in per:
+        for pv, ws, cv, fr, trgb, tdep in per_view:
             gsr.preprocess(pv, ws, params, cv, stream)
             gsr.bin_sort(pv, ws, stream)
             gsr.render_fwd(pv, ws, cv, fr, trgb, tdep, stream)
@@ -563,56 +265,312 @@ def bench_batched(args, dev, search: bool = True, workload: str = "keyframes8_mi
                            stream=stream)
         gsr.adam_step(groups, 1, step_dev=step_dev, stream=stream)
 
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            plain_iter()
+    trials_p = time_replays(plain_iter, stream, args.warmup, args.steps, args.trials)
+    ms_p = float(np.median(trials_p))
+    vis = [int(pv.flags_of(ws)[L.F_VISIBLE]) for pv, ws, *_ in per_view]
+    over = [int(pv.flags_of(ws)[L.F_OVERFLOW]) for pv, ws, *_ in per_view]
+    if any(over):
+        raise SystemExit(f"{workload}: per-view pair capacity overflow")
+    log(f"{workload}: per view {ms_p:.3f} ms/iter (trials {[round(x, 3) for x in trials_p]})")
+    del per_view
     torch.cuda.synchronize()
-    for pv, ws, *_ in per:
-        vis.append(int(pv.flags_of(ws)[L.F_VISIBLE]))
-    t0 = time.perf_counter()
+    return {"workload": w.name, "scene": w, "plan": plan, "tile": tile, "config": best,
+            "autotune_top": sorted(table, key=lambda r: r["ms"])[:5] if table else None,
+            "views": view_wh, "visible_per_view": vis, "counts": counts,
+            "ms_batched": ms_b, "ms_batched_trials": trials_b,
+            "ms_per_view": ms_p, "ms_per_view_trials": trials_p, "spans": spans}
+
+
+def stage_bytes(c, K=16):
+    """Algorithmic (compulsory) HBM bytes of each span of one iteration for
+    N Gaussians, V visible records, P pairs and the image pixels: parameter
+    and record reads, list and image writes, each once."""
+    N, V, P, npx = c["gaussians"], c["visible_records"], c["pairs"], c["pixels"]
+    views = c.get("views", 1)
+    return {
+        "preprocess": 44 * N * views + 12 * K * V + 72 * V + 4 * N * views,
+        "bin_scan": 16 * N * views // 64 + 12 * 4 * c.get("tiles", 0),
+        "bin_scatter": 12 * P + 16 * V,
+        "bin_short_sort": 24 * P,
+        "bin_long_sort": 24 * P,
+        "forward": 64 * P + 40 * npx,
+        "raster_bwd": 116 * P + 40 * npx,
+        "project_bwd": 44 * N + 12 * K * V + 236 * N + 8 * N + 48 * P,
+        "adam": 28 * 59 * N,
+    }
+
+
+def roofline_of(span, ms, c, workload, tile):
+    """Roofline entry of the kernel that a span of the iteration holds."""
+    kname = SPAN_KERNELS.get(span, span)
+    if span in ("forward", "raster_bwd"):
+        flops = FWD_FLOPS_PER_POS if span == "forward" else BWD_FLOPS_PER_POS
+        tf = flops * c["bwd_positions"] / (ms * 1e-3) / 1e12
+        full = f"{kname}<{tile[0]},{tile[1]}" + (",true>" if span == "forward" else ">")
+        return {"bound": "alu", "kernel": full, "achieved": round(tf, 3),
+                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tf / FP32_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(workload, full),
+                "work": f"{flops} flop x {c['bwd_positions']} pixel-Gaussian positions per launch",
+                "launch_ms": round(ms, 4)}
+    b = stage_bytes(c)[span]
+    gbs = b / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kname, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(workload, kname),
+            "work": f"{b} algorithmic bytes per launch", "launch_ms": round(ms, 4)}
+
+
+# ---------------------------------------------------------------- single views
+
+def bench_single(args, dev, workload, pose=False):
+    """One-view mapping iteration (fused L1, Adam) as a graph replay and as
+    eager calls."""
+    import torch
+
+    import paper_2410_00486_amd as gsr
+    from paper_2410_00486_amd import _lib as L
+    w, view_wh, cams, trgb, tdep = load_workload(workload, dev)
+    params = gsr.Gaussians.from_scene(w.scene, dev)
+    tile = tuple(int(x) for x in args.tile.split("x"))
+    cap = int(gsr.required_pairs(*params.tensors(), cams, view_wh, w.scene.sh_degree, tile)
+              * 1.5) + 4096
+    flags = L.GS_FUSED_L1 | (L.GS_SPLAT_BWD if args.bwd == "splat" else 0)
+    plan = gsr.Plan(w.scene.n, w.scene.sh_degree, view_wh, tile=tile, lds_batch=args.lds_batch,
+                    flags=flags, pair_capacity=cap)
+    it = gsr.Iteration(plan, params, cams, target_rgb=trgb, target_depth=tdep, adam_lrs=LRS,
+                       pose_grad=pose)
+    stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        for _ in range(args.steps):
-            plain_iter()
-    torch.cuda.synchronize()
-    ms_p = (time.perf_counter() - t0) * 1e3 / args.steps
-    out = {"workload": w.name,
-           "views": view_wh, "visible_per_view": vis, "visible_total": vis_total,
-           "batched_persistent_graph_iters_per_s": round(1e3 / ms_b, 2),
-           "plain_per_view_iters_per_s": round(1e3 / ms_p, 2),
-           "speedup": round(ms_p / ms_b, 3),
-           ("autotune_best" if search else "config"): best,
-           "autotune_top": sorted(table, key=lambda r: r["ms"])[:5]}
-    log(f"batched: {out}")
+        it.capture(stream)
+    trials = time_replays(lambda: it.replay(stream), stream, args.warmup, args.steps, args.trials)
+    ms_g = float(np.median(trials))
+    trials_e = time_replays(lambda: it.enqueue(stream), stream, args.warmup, args.steps,
+                            max(1, args.trials // 2))
+    fl = plan.flags_of(it.ws)
+    assert fl[L.F_OVERFLOW] == 0
+    c = {"gaussians": w.scene.n, "views": 1, "visible_records": int(fl[L.F_VISIBLE]),
+         "pairs": int(fl[L.F_PAIRS]), "pixels": plan.total_pixels,
+         "bwd_positions": int(it.frame.last.to(torch.int64).sum().item())}
+    with torch.cuda.stream(stream):
+        per = it.time_marks(stream, warmup=2, reps=max(10, args.steps))
+    spans = {k: trimmed_mean(per[:, j]) for j, k in enumerate(gsr.Iteration.MARKS)}
+    it.close()
+    by = stage_bytes(c, (w.scene.sh_degree + 1) ** 2)
+    total = sum(by[k] for k in by if k not in ("bin_short_sort",))
+    out = {"workload": w.name, "iters_per_s_graph": round(1e3 / ms_g, 2),
+           "iters_per_s_eager": round(1e3 / float(np.median(trials_e)), 2),
+           "ms_per_iter": round(ms_g, 4), "counts": c,
+           "span_ms": {k: round(v, 4) for k, v in spans.items()},
+           "hbm_gbs_algorithmic": round(total / (ms_g * 1e-3) / 1e9, 1)}
+    log(f"{workload}: {out}")
     return out
 
 
-def cpu_baseline(w, budget_s: float = 10.0):
-    """The FP64 oracle on the host: full mapping iterations of the same
-    workload (projection, sort, forward, L1 loss, backward, chain rule, Adam),
-    repeated until about budget_s seconds of wall clock have passed."""
-    import oracle
+# ---------------------------------------------------------------- oracle on the host
 
-    cam = w.cameras[0]
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    tgt = oracle.render(w.target_scene, cam)
-    iters, t0 = 0, time.perf_counter()
+def _omp_threads(n):
+    """Thread count of the oracle's OpenMP regions (same libgomp instance)."""
+    import ctypes
+    import oracle
+    oracle.lib()
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+    except OSError:
+        pass
+
+
+def oracle_iteration(oracle, scene, cams, targets, lambda_depth=0.1):
+    """One FP64 mapping iteration of the oracle over `cams`: render, L1 loss,
+    backward, chain rule summed over views, Adam on every parameter."""
+    acc = None
+    for cam, (trgb, tdep) in zip(cams, targets):
+        fwd = oracle.render(scene, cam, (8, 8))
+        _, gC, gD = oracle.l1_loss_and_grads(fwd["color"], fwd["depth"], trgb, tdep, lambda_depth)
+        g2d = oracle.backward_2d(scene, cam, gC, gD, (8, 8), fwd=fwd)
+        acc, _ = oracle.project_backward(scene, cam, g2d, (8, 8), accum=acc)
+    for f in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        p = getattr(scene, f).astype(np.float64)
+        oracle.adam_step(p, acc[f], np.zeros_like(p), np.zeros_like(p), 1, LRS[f])
+
+
+def cpu_baseline(w16, w2):
+    """The FP64 oracle on the host cores: full mapping iterations of two of
+    the 16 large-scene views on all cores (extrapolated to the 16-view
+    iteration by the views' pair counts), and one-view iterations of the
+    1200x680 / 300k room on one thread."""
+    import oracle
+    threads = os.cpu_count() or 1
+    _omp_threads(threads)
+    sub = [w16.cameras[0], w16.cameras[8]]
+    tgt = []
+    for cam in sub:  # untimed: the oracle's own target renders
+        r = oracle.render(w16.target_scene, cam, (8, 8))
+        tgt.append((r["color"], r["depth"]))
+    pairs_all = [int(oracle.preprocess(w16.scene, c, (8, 8))["tiles_touched"].sum())
+                 for c in w16.cameras]
+    pairs_sub = pairs_all[0] + pairs_all[8]
+    reps, t0 = 0, time.perf_counter()
     while True:
-        fwd = oracle.render(w.scene, cam)
-        loss, gC, gD = oracle.l1_loss_and_grads(fwd["color"], fwd["depth"], tgt["color"],
-                                                tgt["depth"], 0.1)
-        g2d = oracle.backward_2d(w.scene, cam, gC, gD, fwd=fwd)
-        grads, _ = oracle.project_backward(w.scene, cam, g2d)
-        for f in ("means", "log_scales", "quats", "opacity_logits", "sh"):
-            p = getattr(w.scene, f).astype(np.float64)
-            oracle.adam_step(p, grads[f], np.zeros_like(p), np.zeros_like(p), 1, LRS[f])
-        iters += 1
+        oracle_iteration(oracle, w16.scene, sub, tgt)
+        reps += 1
         dt = time.perf_counter() - t0
-        if dt >= budget_s:
+        if dt >= 10.0 or reps >= 3:
             break
-    log(f"oracle: {iters} iterations in {dt:.2f}s on {threads} threads")
-    return {"value": round(iters / dt, 4), "unit": "iters/s", "cores": threads, "kind": "oracle",
-            "sample": f"{iters} full mapping iterations of the same 1200x680 / 300k SH3 view "
-                      f"({dt:.1f} s wall clock, FP64, OpenMP)"}
+    s_sub = dt / reps
+    s_full = s_sub * sum(pairs_all) / pairs_sub
+    log(f"oracle: {reps} two-view iterations in {dt:.1f}s on {threads} threads; "
+        f"16-view estimate {s_full:.1f}s")
+    # one thread, one 1200x680 view of the 300k room
+    _omp_threads(1)
+    cam = w2.cameras[0]
+    r = oracle.render(w2.target_scene, cam, (8, 8))
+    t2 = [(r["color"], r["depth"])]
+    reps1, t0 = 0, time.perf_counter()
+    while True:
+        oracle_iteration(oracle, w2.scene, [cam], t2)
+        reps1 += 1
+        dt1 = time.perf_counter() - t0
+        if dt1 >= 8.0:
+            break
+    _omp_threads(threads)
+    log(f"oracle: {reps1} one-view iterations in {dt1:.1f}s on 1 thread")
+    return {"value": round(1.0 / s_full, 5), "unit": "iters/s", "cores": threads, "kind": "oracle",
+            "sample": (f"{reps} FP64 iterations (render, L1, backward, Adam on all 2M Gaussians) of "
+                       f"views 0 and 8 of the 16-view 2M-Gaussian batch, {s_sub:.2f} s each on "
+                       f"{threads} threads; extrapolated to all 16 views by pair count "
+                       f"({sum(pairs_all)} vs {pairs_sub} pairs): {s_full:.1f} s per iteration"),
+            "ms_per_iter_two_views": round(s_sub * 1e3, 1),
+            "single_thread": {"value": round(reps1 / dt1, 5), "unit": "iters/s", "cores": 1,
+                              "sample": f"{reps1} one-view iterations of the 1200x680 / 300k "
+                                        f"room ({dt1:.1f} s)"}}
+
+
+# ---------------------------------------------------------------- main
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--trials", type=int, default=5)
+    ap.add_argument("--workload", default="keyframes16_1200x680",
+                    choices=["keyframes16_1200x680", "keyframes8_mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline batched vs per-view comparison")
+    # defaults: the configuration the autotuner selects for the batched
+    # workloads on MI355X; --autotune reruns the search
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--tile", default="8x8")
+    ap.add_argument("--lds-batch", type=int, default=64)
+    ap.add_argument("--chunk", type=int, default=1)
+    ap.add_argument("--bwd", default="splat", choices=["pixel", "splat"])
+    ap.add_argument("--no-marks", action="store_true",
+                    help="skip the per-launch event timing (for profiler runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a 1 GiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the "
+              "keyframes over several GPUs is a documented design, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4,
+                          "copy_bytes_written": dst.numel() * 4, "launches": 5}))
+        return
+
+    head = bench_batched(args, dev, args.workload, search=args.autotune,
+                         marks=not args.no_marks)
+    c = dict(head["counts"])
+    tile = head["tile"]
+    c["tiles"] = head["plan"].total_tiles
+    ms_b, ms_p = head["ms_batched"], head["ms_per_view"]
+    n_views = c["views"]
+    result = {
+        "metric": METRIC,
+        "value": round(1e3 / ms_b, 2),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_b, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (quadratic form and projection in f64)",
+        "data": "synthetic (seeded indoor rooms shaped like the paper's RGB-D sequences)",
+        "config": {"workload": f"{head['workload']}: {n_views} views "
+                               f"{head['views'][0][0]}x{head['views'][0][1]} over one pool of "
+                               f"{c['gaussians']} Gaussians (SH 3), L1 RGB + 0.1 L1 depth, "
+                               "forward + backward + Adam per iteration, one persistent "
+                               "whole-iteration HIP graph",
+                   "tile": f"{tile[0]}x{tile[1]}", "lds_batch": head["config"]["lds_batch"],
+                   "chunk": head["config"]["chunk"], "persistent": True,
+                   "backward": head["config"]["backward"]},
+        "trials": args.trials,
+        "timing": "median over trials of HIP events around --steps graph replays",
+        "views_per_s": round(n_views * 1e3 / ms_b, 1),
+        "per_view_form": {"iters_per_s": round(1e3 / ms_p, 2),
+                          "views_per_s": round(n_views * 1e3 / ms_p, 1),
+                          "ms_per_iter": round(ms_p, 4)},
+        "batched_speedup": round(ms_p / ms_b, 3),
+        "counts": head["counts"],
+        "visible_per_view": head["visible_per_view"],
+    }
+    if head["autotune_top"]:
+        result["autotune_top"] = head["autotune_top"]
+    spans = head["spans"]
+    if spans is not None:
+        by = stage_bytes(c)
+        result["span_ms"] = {k: round(v, 4) for k, v in spans.items()}
+        result["span_sum_ms"] = round(sum(spans.values()), 4)
+        dom = max((k for k in spans if k != "loss"), key=lambda k: spans[k])
+        result["roofline"] = roofline_of(dom, spans[dom], c, args.workload, tile)
+        result["roofline_raster"] = {
+            k: roofline_of(k, spans[k], c, args.workload, tile)
+            for k in ("forward", "raster_bwd") if k != dom}
+        total = sum(by[k] for k in by if spans.get(k, 0) > 0)
+        result["hbm_gbs_algorithmic"] = round(total / (ms_b * 1e-3) / 1e9, 1)
+        result["hbm_frac"] = round(result["hbm_gbs_algorithmic"] / HBM_PEAK_GBS, 4)
+    w16 = head["scene"]
+    del head
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+    w2 = None
+    if not args.no_extras:
+        other = "keyframes8_mixed" if args.workload != "keyframes8_mixed" else "keyframes16_1200x680"
+        b8 = bench_batched(args, dev, other, search=False, marks=True)
+        result["other_batched"] = {
+            "workload": b8["workload"], "views": b8["views"],
+            "visible_per_view": b8["visible_per_view"], "counts": b8["counts"],
+            "batched_iters_per_s": round(1e3 / b8["ms_batched"], 2),
+            "per_view_iters_per_s": round(1e3 / b8["ms_per_view"], 2),
+            "speedup": round(b8["ms_per_view"] / b8["ms_batched"], 3),
+            "span_ms": {k: round(v, 4) for k, v in b8["spans"].items()}}
+        del b8
+        torch.cuda.empty_cache()
+        singles = {}
+        for name, pose in (("slab_128x96", False), ("room_1200x680", False),
+                           ("room_640x480_pose", True)):
+            singles[name] = bench_single(args, dev, name, pose=pose)
+        result["single_view"] = singles
+    if not args.no_cpu_baseline:
+        from synth import scenes
+        w2 = scenes.room_1200x680()
+        if w16.target_scene is None:
+            raise SystemExit("the headline workload has no target scene for the oracle")
+        result["cpu_baseline"] = cpu_baseline(w16, w2)
+    print(json.dumps(result))
 
 
 if __name__ == "__main__":

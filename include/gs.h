@@ -406,6 +406,29 @@ gs_status gs_graph_destroy(gs_graph* graph);
 gs_status gs_graph_time(gs_graph* graph, void* stream, int32_t warmup, int32_t reps,
                         float* ms_per_replay);
 
+/* Per-launch timing of one eagerly enqueued iteration (measurement call, not
+ * for the iteration loop, never under capture).  Enqueues `warmup`
+ * iterations of `it`, then `reps` iterations with a HIP event recorded on
+ * `stream` at each mark below, synchronises, and writes the milliseconds
+ * between consecutive marks: ms[r * (GS_N_MARKS - 1) + k] is the span from
+ * mark k to mark k + 1 of rep r (host array of reps * (GS_N_MARKS - 1)).
+ * A span whose launches the iteration does not make (no SSIM term, short
+ * lists sorted by the forward) is the empty span between two marks. */
+#define GS_MARK_START 0
+#define GS_MARK_PREPROCESS 1       /* after the counter clear and the projection */
+#define GS_MARK_BIN_SCAN 2         /* after the binning's scans */
+#define GS_MARK_BIN_SCATTER 3      /* after the pair scatter */
+#define GS_MARK_BIN_SHORT_SORT 4   /* after the per-tile sorts of short lists */
+#define GS_MARK_BIN_LONG_SORT 5    /* after the long-list sorts */
+#define GS_MARK_FORWARD 6          /* after compositing (and the L1 loss sums) */
+#define GS_MARK_LOSS 7             /* after the SSIM loss kernels */
+#define GS_MARK_RASTER_BWD 8       /* after the raster backward */
+#define GS_MARK_PROJECT_BWD 9      /* after the projection backward */
+#define GS_MARK_ADAM 10            /* after Adam and its step advance */
+#define GS_N_MARKS 11
+gs_status gs_iteration_time_marks(const gs_iteration* it, void* stream, int32_t warmup,
+                                  int32_t reps, float* ms);
+
 /* Adaptive keyframe selection, host only (Sec. III-C-2, Eqs. (5)-(8)).
  * A keyframe enters the pool with r0 remaining optimisations and loss +inf;
  * gs_sched_select draws `batch` distinct keyframes uniformly among those

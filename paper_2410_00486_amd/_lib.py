@@ -125,6 +125,8 @@ SIGNATURES = {
     "gs_graph_launch": (i32, [vp, vp]),
     "gs_graph_destroy": (i32, [vp]),
     "gs_graph_time": (i32, [vp, vp, i32, i32, ctypes.POINTER(f32)]),
+    "gs_iteration_time_marks": (i32, [ctypes.POINTER(GsIteration), vp, i32, i32,
+                                      ctypes.POINTER(f32)]),
     "gs_sched_init": (i32, [ctypes.POINTER(GsScheduler), ctypes.POINTER(i32),
                             ctypes.POINTER(ctypes.c_double), i32, i32, i32]),
     "gs_sched_add_keyframe": (i32, [ctypes.POINTER(GsScheduler), ctypes.POINTER(i32)]),

@@ -15,7 +15,7 @@ namespace gs {
 hipError_t launch_preprocess(const Plan& P, const gs_gaussians& g, const float* cams, void* ws,
                              hipStream_t s);
 hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_short_sorts = false,
-                           const StepAdvance* step = nullptr);
+                           const StepAdvance* step = nullptr, const Marks* marks = nullptr);
 TileSortArgs tile_sort_args(const Plan& P, void* ws);
 hipError_t launch_radix_sort(uint64_t* keys0, uint64_t* keys1, uint32_t* vals0, uint32_t* vals1,
                              const int32_t* cnt, uint32_t* hist, uint32_t* digit_tot,
@@ -514,38 +514,45 @@ gs_status gs_densify_prune(const gs_gaussians* g, const gs_gaussian_grads* m,
                    "gs_densify_prune");
 }
 
-size_t gs_sort_tmp_bytes(int64_t n) {
-  if (n < 0) return 0;
-  const int64_t nb = std::max<int64_t>(1, (n + kSortTile - 1) / kSortTile);
-  size_t o = 0;
-  o = align_up(o + (size_t)n * 8 + 8, 256);
-  o = align_up(o + (size_t)n * 4 + 4, 256);
-  o = align_up(o + (size_t)kRadix * nb * 4, 256);
-  o = align_up(o + kRadix * 4, 256);
-  o = align_up(o + 16, 256);
-  return o;
+}  // extern "C"
+
+namespace {
+
+// Scratch of the stand-alone sort for n pairs: second key and value buffers,
+// the per-block digit histograms, the digit totals and the pair count.
+struct SortTmp {
+  size_t k1, v1, hist, dtot, cnt, bytes;
+};
+
+constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+constexpr SortTmp sort_tmp_layout(int64_t n) {
+  const int64_t nb = n > kSortTile ? (n + kSortTile - 1) / kSortTile : 1;
+  SortTmp t{};
+  t.k1 = 0;
+  t.v1 = align256(t.k1 + (size_t)n * 8 + 8);
+  t.hist = align256(t.v1 + (size_t)n * 4 + 4);
+  t.dtot = align256(t.hist + (size_t)kRadix * nb * 4);
+  t.cnt = align256(t.dtot + kRadix * 4);
+  t.bytes = align256(t.cnt + 16);
+  return t;
 }
 
-gs_status gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits, void* tmp,
-                        void* stream) {
-  if (n < 0 || n > INT32_MAX) return fail(GS_ERR_INVALID_ARG, "n must be 0..2^31-1");
-  if (key_bits < 1 || key_bits > 64) return fail(GS_ERR_INVALID_ARG, "key_bits must be 1..64");
-  if (n == 0) return GS_OK;
-  if (!keys || !vals || !tmp) return fail(GS_ERR_INVALID_ARG, "null pointer");
-  if (!aligned(tmp, 256)) return fail(GS_ERR_INVALID_ARG, "tmp must be 256-byte aligned");
+// Sort with caller-provided scratch `tmp` (sort_tmp_layout(n).bytes, 256-byte
+// aligned); n >= 1 and the arguments already checked.
+gs_status sort_pairs_in(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits, void* tmp,
+                        hipStream_t s, const char* what) {
   const int64_t nb = std::max<int64_t>(1, (n + kSortTile - 1) / kSortTile);
-  size_t o = 0;
+  const SortTmp L = sort_tmp_layout(n);
   char* base = static_cast<char*>(tmp);
-  uint64_t* k1 = reinterpret_cast<uint64_t*>(base + o);
-  o = align_up(o + (size_t)n * 8 + 8, 256);
-  uint32_t* v1 = reinterpret_cast<uint32_t*>(base + o);
-  o = align_up(o + (size_t)n * 4 + 4, 256);
-  uint32_t* hist = reinterpret_cast<uint32_t*>(base + o);
-  o = align_up(o + (size_t)kRadix * nb * 4, 256);
-  uint32_t* dtot = reinterpret_cast<uint32_t*>(base + o);
-  o = align_up(o + kRadix * 4, 256);
-  int32_t* cnt = reinterpret_cast<int32_t*>(base + o);
-  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint64_t* k1 = reinterpret_cast<uint64_t*>(base + L.k1);
+  uint32_t* v1 = reinterpret_cast<uint32_t*>(base + L.v1);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(base + L.hist);
+  uint32_t* dtot = reinterpret_cast<uint32_t*>(base + L.dtot);
+  int32_t* cnt = reinterpret_cast<int32_t*>(base + L.cnt);
+  // the pair count is written by a kernel on every call, every histogram
+  // entry the passes read is written by the same call: nothing in the
+  // scratch has to start at zero
   hipError_t e = launch_set_i32(cnt, (int32_t)n, s);
   int which = 0;
   if (e == hipSuccess)
@@ -554,10 +561,43 @@ gs_status gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_b
     e = hipMemcpyAsync(keys, k1, (size_t)n * 8, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(vals, v1, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
   }
-  return hip_check(e, "gs_sort_pairs");
+  return hip_check(e, what);
 }
 
-gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
+gs_status check_sort_args(const uint64_t* keys, const uint32_t* vals, int64_t n, int64_t n_max,
+                          int32_t key_bits) {
+  if (n < 0 || n > n_max) return fail(GS_ERR_INVALID_ARG, "n must be 0..%lld", (long long)n_max);
+  if (key_bits < 1 || key_bits > 64) return fail(GS_ERR_INVALID_ARG, "key_bits must be 1..64");
+  if (n > 0 && (!keys || !vals)) return fail(GS_ERR_INVALID_ARG, "null pointer");
+  return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gs_sort_tmp_bytes(int64_t n) {
+  if (n < 0) return 0;
+  return sort_tmp_layout(n).bytes;
+}
+
+gs_status gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits, void* tmp,
+                        void* stream) {
+  gs_status st = check_sort_args(keys, vals, n, INT32_MAX, key_bits);
+  if (st != GS_OK || n == 0) return st;
+  if (!tmp) return fail(GS_ERR_INVALID_ARG, "null pointer");
+  if (!aligned(tmp, 256)) return fail(GS_ERR_INVALID_ARG, "tmp must be 256-byte aligned");
+  return sort_pairs_in(keys, vals, n, key_bits, tmp, static_cast<hipStream_t>(stream),
+                       "gs_sort_pairs");
+}
+
+}  // extern "C"
+
+// One mapping iteration; `marks` (optional) records the timing events of
+// gs_iteration_time_marks between the launches.
+static gs_status iteration_enqueue(const gs_iteration* it, void* stream, const Marks* marks) {
+  const Marks none{};
+  const Marks& mk = marks ? *marks : none;
   if (!it) return fail(GS_ERR_INVALID_ARG, "iteration is null");
   if (!it->plan || check_plan(it->plan) != GS_OK) return fail(GS_ERR_INVALID_ARG, "bad plan");
   if (it->n_adam_groups < 0 || (it->n_adam_groups > 0 && !it->adam_groups))
@@ -578,15 +618,21 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
   // fill, no read).  The gradient buffers are left unspecified for those.
   const bool sparse = it->n_adam_groups > 0 && it->n_adam_groups <= kAdamFoldGroups && P.vt.n_views == 1 &&
                       !(P.cfg.flags & GS_ACCUMULATE_GRADS) && P.n > 0;
+  hipStream_t strm = static_cast<hipStream_t>(stream);
   if (!sparse) {
-    gs_status st = gs_preprocess(it->plan, &it->gaussians, it->cams_dev, it->ws, stream);
+    gs_status st = hip_check(mk.at(GS_MARK_START, strm), "timing mark");
     if (st != GS_OK) return st;
-    st = gs_bin_sort(it->plan, it->ws, stream);
+    st = gs_preprocess(it->plan, &it->gaussians, it->cams_dev, it->ws, stream);
+    if (st != GS_OK) return st;
+    if ((st = hip_check(mk.at(GS_MARK_PREPROCESS, strm), "timing mark")) != GS_OK) return st;
+    if ((st = check_ws(P, it->ws)) != GS_OK) return st;
+    st = hip_check(launch_bin_sort(P, it->ws, strm, false, nullptr, marks), "gs_bin_sort");
     if (st != GS_OK) return st;
     st = gs_render_fwd(it->plan, it->ws, it->cams_dev, it->color, it->depth, it->T_final, it->last,
                        ssim ? nullptr : it->target_rgb, ssim ? nullptr : it->target_depth,
                        ssim ? nullptr : it->loss_per_view, stream);
     if (st != GS_OK) return st;
+    if ((st = hip_check(mk.at(GS_MARK_FORWARD, strm), "timing mark")) != GS_OK) return st;
     const float* gC = it->dL_dcolor;
     const float* gD = it->dL_ddepth;
     if (ssim) {
@@ -597,10 +643,19 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
       gC = it->loss_grad_color;
       gD = it->loss_grad_depth;
     }
-    st = gs_render_bwd(it->plan, &it->gaussians, it->cams_dev, it->ws, it->color, it->depth,
-                       it->T_final, it->last, gC, gD, it->target_rgb, it->target_depth,
-                       &it->grads, it->dL_dpose, stream);
+    if ((st = hip_check(mk.at(GS_MARK_LOSS, strm), "timing mark")) != GS_OK) return st;
+    // gs_render_bwd as its two halves, with a mark between them
+    if ((st = check_gaussians(P, &it->gaussians)) != GS_OK) return st;
+    const gs_gaussian_grads* out = &it->grads;
+    if (P.n > 0 && (!out->means || !out->log_scales || !out->quats || !out->opacity_logits || !out->sh))
+      return fail(GS_ERR_INVALID_ARG, "gradient output pointers must be non-null");
+    st = gs_render_bwd_raster(it->plan, it->ws, it->cams_dev, it->color, it->depth, it->T_final,
+                              it->last, gC, gD, it->target_rgb, it->target_depth, stream);
     if (st != GS_OK) return st;
+    if ((st = hip_check(mk.at(GS_MARK_RASTER_BWD, strm), "timing mark")) != GS_OK) return st;
+    st = gs_project_bwd(it->plan, &it->gaussians, it->cams_dev, it->ws, out, it->dL_dpose, stream);
+    if (st != GS_OK) return st;
+    if ((st = hip_check(mk.at(GS_MARK_PROJECT_BWD, strm), "timing mark")) != GS_OK) return st;
     if (it->n_adam_groups > 0) {
       // the Adam launch (and the step advance after it) do nothing when the
       // binning of this iteration overflowed
@@ -612,8 +667,9 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
                                  static_cast<hipStream_t>(stream), nullptr, nullptr,
                                  ws_at<int32_t>(it->ws, P.off_flags) + F_OVERFLOW),
                      "gs_iteration_enqueue (Adam)");
+      if (st != GS_OK) return st;
     }
-    return st;
+    return hip_check(mk.at(GS_MARK_ADAM, strm), "timing mark");
   }
 
   // Sparse path: everything is checked before anything is enqueued.
@@ -671,13 +727,15 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
   }
   // no clearing launch: the counters were left zero by the last binning on
   // this workspace (or the workspace is fresh, zero-filled)
+  if ((st = hip_check(mk.at(GS_MARK_START, s), "timing mark")) != GS_OK) return st;
   st = preprocess_enqueue(it->plan, &it->gaussians, it->cams_dev, it->ws, s, false);
   if (st != GS_OK) return st;
+  if ((st = hip_check(mk.at(GS_MARK_PREPROCESS, s), "timing mark")) != GS_OK) return st;
   // the binning leaves the short lists to the forward, which sorts each
   // tile's list right before compositing it (one launch fewer; the sort's
   // memory latency hides behind other wavefronts' compositing); its scan
   // advances the Adam step unless the pairs overflow
-  hipError_t e = launch_bin_sort(P, it->ws, s, true, it->step_dev ? &adv : nullptr);
+  hipError_t e = launch_bin_sort(P, it->ws, s, true, it->step_dev ? &adv : nullptr, marks);
   TileSortArgs fwd_sort = tile_sort_args(P, it->ws);
   fwd_sort.long_after = false;  // the long lists were sorted by the binning
   if (e != hipSuccess) return hip_check(e, "gs_iteration_enqueue (binning)");
@@ -689,6 +747,7 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
       (ssim || fold_loss) ? nullptr : it->loss_per_view,
       ws_at<uint32_t>(it->ws, P.off_order), pers ? fl + F_QUEUE_FWD : nullptr,
       pers ? persistent_grid(P, false) : P.vt.total_tiles, s, fwd_sort);
+  if (e == hipSuccess) e = mk.at(GS_MARK_FORWARD, s);
   if (e != hipSuccess) return hip_check(e, "gs_iteration_enqueue (forward)");
   const float* gC = it->dL_dcolor;
   const float* gD = it->dL_ddepth;
@@ -700,10 +759,13 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
     gC = it->loss_grad_color;
     gD = it->loss_grad_depth;
   }
+  if ((st = hip_check(mk.at(GS_MARK_LOSS, s), "timing mark")) != GS_OK) return st;
   st = gs_render_bwd_raster(it->plan, it->ws, it->cams_dev, it->color, it->depth, it->T_final,
                             it->last, gC, gD, it->target_rgb, it->target_depth, stream);
   if (st != GS_OK) return st;
+  if ((st = hip_check(mk.at(GS_MARK_RASTER_BWD, s), "timing mark")) != GS_OK) return st;
   e = launch_project_bwd(P, it->gaussians, it->cams_dev, it->ws, gr, it->dL_dpose, 0, true, s);
+  if (e == hipSuccess) e = mk.at(GS_MARK_PROJECT_BWD, s);
   if (e != hipSuccess) return hip_check(e, "gs_iteration_enqueue (projection backward)");
   const uint32_t* vis[16];
   int32_t per[16];
@@ -724,7 +786,47 @@ gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
   e = launch_adam(it->adam_groups, it->n_adam_groups, 1, it->beta1, it->beta2, it->eps,
                   it->lambda_o, it->reg_count, it->step_dev, s, vis, per,
                   ws_at<int32_t>(it->ws, P.off_flags) + F_OVERFLOW, &fold);
+  if (e == hipSuccess) e = mk.at(GS_MARK_ADAM, s);
   return hip_check(e, "gs_iteration_enqueue (Adam)");
+}
+
+extern "C" {
+
+gs_status gs_iteration_enqueue(const gs_iteration* it, void* stream) {
+  return iteration_enqueue(it, stream, nullptr);
+}
+
+gs_status gs_iteration_time_marks(const gs_iteration* it, void* stream, int32_t warmup,
+                                  int32_t reps, float* ms) {
+  if (!it || !ms || warmup < 0 || reps < 1)
+    return fail(GS_ERR_INVALID_ARG, "bad gs_iteration_time_marks arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cap);
+  if (e != hipSuccess) return hip_check(e, "gs_iteration_time_marks");
+  if (cap != hipStreamCaptureStatusNone)
+    return fail(GS_ERR_INVALID_ARG, "gs_iteration_time_marks cannot run under stream capture");
+  gs_status st = GS_OK;
+  for (int i = 0; st == GS_OK && i < warmup; ++i) st = iteration_enqueue(it, stream, nullptr);
+  if (st != GS_OK) return st;
+  std::vector<hipEvent_t> ev((size_t)reps * GS_N_MARKS, nullptr);
+  for (size_t k = 0; e == hipSuccess && k < ev.size(); ++k) e = hipEventCreate(&ev[k]);
+  for (int r = 0; e == hipSuccess && st == GS_OK && r < reps; ++r) {
+    Marks m;
+    m.ev = ev.data() + (size_t)r * GS_N_MARKS;
+    st = iteration_enqueue(it, stream, &m);
+  }
+  if (e == hipSuccess && st == GS_OK) e = hipStreamSynchronize(s);
+  for (int r = 0; e == hipSuccess && st == GS_OK && r < reps; ++r)
+    for (int k = 0; e == hipSuccess && k + 1 < GS_N_MARKS; ++k) {
+      float t = 0.0f;
+      e = hipEventElapsedTime(&t, ev[(size_t)r * GS_N_MARKS + k], ev[(size_t)r * GS_N_MARKS + k + 1]);
+      ms[(size_t)r * (GS_N_MARKS - 1) + k] = t;
+    }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (st != GS_OK) return st;
+  return hip_check(e, "gs_iteration_time_marks");
 }
 
 struct gs_graph {

@@ -10,7 +10,7 @@
 // list at an atomically taken slot with the key (depth bits << 32 |
 // generation index); a per-tile sort orders those keys (one wavefront per
 // tile: ranks in registers up to 64 keys, a bitonic network in LDS up to
-// 512; longer lists go to 1024-thread blocks, in LDS up to 16384 keys and in
+// 128; longer lists go to 1024-thread blocks, in LDS up to 8192 keys and in
 // global memory beyond).  Four launches whatever the pair count, no
 // spin-waits; graph-capturable.
 //
@@ -684,7 +684,9 @@ TileSortArgs tile_sort_args(const Plan& P, void* ws) {
 // the forward (a whole iteration), which sorts each tile before compositing
 // it; the long lists are sorted here in either case.
 hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_short_sorts,
-                           const StepAdvance* step) {
+                           const StepAdvance* step, const Marks* marks) {
+  const Marks none{};
+  const Marks& mk = marks ? *marks : none;
   int32_t* fl = ws_at<int32_t>(ws, P.off_flags);
   uint32_t* tt = ws_at<uint32_t>(ws, P.off_tt);
   uint32_t* poff = ws_at<uint32_t>(ws, P.off_poff);
@@ -703,6 +705,8 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_sh
   // always launched, so that the flags are always set
   hipLaunchKernelGGL(k_scans, dim3(1), dim3(kScanBlock), 0, s, sa, P.pair_cap, fl,
                      step ? *step : StepAdvance{});
+  hipError_t e = mk.at(GS_MARK_BIN_SCAN, s);
+  if (e != hipSuccess) return e;
   uint64_t* skey = ws_at<uint64_t>(ws, P.off_scatter);
   uint32_t* pair_rec = ws_at<uint32_t>(ws, P.off_pair_rec);
   if (P.n_chunks > 0) {
@@ -712,16 +716,21 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_sh
                        ws_at<Rec>(ws, P.off_rec), P.n, P.vt, fl, tstart, tcnt, skey, pair_rec,
                        ws_at<uint32_t>(ws, P.off_vis_list));
   }
+  if ((e = mk.at(GS_MARK_BIN_SCATTER, s)) != hipSuccess) return e;
   if (T > 0) {
     // the per-tile pass (here, or the forward's when deferred) and the
     // long-list kernel each zero the counters they consume, so that every
     // counter is zero again after the binning of an iteration
     const TileSortArgs A = tile_sort_args(P, ws);
     if (!defer_short_sorts) hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)T), dim3(kWave), 0, s, A);
+    if ((e = mk.at(GS_MARK_BIN_SHORT_SORT, s)) != hipSuccess) return e;
     const int long_grid = (int)std::min<int64_t>(T, 512);  // two blocks per CU
     hipLaunchKernelGGL(k_tile_sort_long, dim3((unsigned)long_grid), dim3(kLongThreads), 0, s,
                        tcnt, fl, long_list, skey, A.out, defer_short_sorts ? 0 : 1);
+  } else if ((e = mk.at(GS_MARK_BIN_SHORT_SORT, s)) != hipSuccess) {
+    return e;
   }
+  if ((e = mk.at(GS_MARK_BIN_LONG_SORT, s)) != hipSuccess) return e;
   return hipGetLastError();
 }
 

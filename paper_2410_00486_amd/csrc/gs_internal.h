@@ -217,6 +217,14 @@ struct AdamStepFactors {
   int32_t step;
   float step_size[kAdamFoldGroups];
 };
+// Timing marks of an eagerly enqueued iteration: event `k` (a GS_MARK_*
+// index) is recorded on the launch stream after the launches before it.
+struct Marks {
+  hipEvent_t* ev = nullptr;  // GS_N_MARKS events, or null (no marks)
+  hipError_t at(int k, hipStream_t s) const {
+    return ev ? hipEventRecord(ev[k], s) : hipSuccess;
+  }
+};
 struct StepAdvance {
   int32_t* step;
   double beta1, beta2;

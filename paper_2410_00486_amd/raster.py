@@ -429,6 +429,20 @@ class Iteration:
                                       ctypes.byref(ms)))
         return float(ms.value)
 
+    MARKS = ["preprocess", "bin_scan", "bin_scatter", "bin_short_sort", "bin_long_sort",
+             "forward", "loss", "raster_bwd", "project_bwd", "adam"]
+
+    def time_marks(self, stream=None, warmup: int = 2, reps: int = 10):
+        """Milliseconds of each launch group of an eagerly enqueued iteration
+        (gs_iteration_time_marks: HIP events on the launch stream), as a
+        [reps, len(MARKS)] float64 array; synchronises."""
+        import numpy as np
+        n = len(self.MARKS)
+        buf = (ctypes.c_float * (reps * n))()
+        L.check(L.lib().gs_iteration_time_marks(ctypes.byref(self.c), _stream(stream),
+                                                int(warmup), int(reps), buf))
+        return np.frombuffer(buf, dtype=np.float32).astype(np.float64).reshape(reps, n)
+
     def close(self):
         if self._graph is not None:
             L.check(L.lib().gs_graph_destroy(self._graph))
@@ -551,13 +565,18 @@ class Rasterizer:
 
     def __call__(self, means, log_scales, quats, opacity_logits, sh, cams: torch.Tensor,
                  pose_tangent: Optional[torch.Tensor] = None):
+        # a backward will come only when autograd records this call; otherwise
+        # the forward hands its workspace back to the pool at once
+        keep = torch.is_grad_enabled() and any(
+            t is not None and t.requires_grad
+            for t in (means, log_scales, quats, opacity_logits, sh, pose_tangent))
         return _Rasterize.apply(means, log_scales, quats, opacity_logits, sh, pose_tangent,
-                                cams, self)
+                                cams, self, keep)
 
 
 class _Rasterize(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, means, log_scales, quats, opacity_logits, sh, pose_tangent, cams, rz):
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, pose_tangent, cams, rz, keep):
         g = Gaussians(means.detach().contiguous(), log_scales.detach().contiguous(),
                       quats.detach().contiguous(), opacity_logits.detach().contiguous(),
                       sh.detach().contiguous(), rz.sh_degree)
@@ -567,7 +586,7 @@ class _Rasterize(torch.autograd.Function):
             xi = pose_tangent.detach().contiguous()
             cams = pose_retract(cams, xi)
         plan, ws, fr = rz.forward_buffers(g, cams)
-        if any(ctx.needs_input_grad):
+        if keep:
             ctx.rz, ctx.plan, ctx.ws, ctx.frame, ctx.g, ctx.cams, ctx.xi = (
                 rz, plan, ws, fr, g, cams, xi)
         else:
@@ -590,7 +609,7 @@ class _Rasterize(torch.autograd.Function):
         ctx.ws = None
         dxi = pose_tangent_vjp(ctx.xi, dpose) if want_pose else None
         return (grads.means, grads.log_scales, grads.quats, grads.opacity_logits,
-                grads.sh.view_as(g.sh), dxi, None, None)
+                grads.sh.view_as(g.sh), dxi, None, None, None)
 
 
 _RASTERIZERS = {}

@@ -96,6 +96,20 @@ def oracle_reference(scene, cams, gcs, gds, tile=(16, 16), alt_gcs=None, alt_gds
     return grads, poses, exclude, poses_f
 
 
+def decided_target(rendered, target, margin=1e-4):
+    """`target` with every residual against the oracle's render `rendered`
+    pushed out to at least `margin` (same sign, zero counted as positive):
+    the L1 sign of every pixel is then decided at FP32 accuracy, since the
+    GPU image is within 1e-5 relative (in practice 1e-6) of the oracle's."""
+    rendered = np.asarray(rendered, np.float64)
+    target = np.asarray(target, np.float64)
+    r = target - rendered
+    sgn = np.where(r >= 0.0, 1.0, -1.0)
+    out = np.where(np.abs(r) < margin, rendered + sgn * margin, target).astype(np.float32)
+    assert (np.abs(out.astype(np.float64) - rendered) >= 0.9 * margin).all()
+    return out
+
+
 def visible_count(scene, cams, tile=(16, 16)):
     """Gaussians visible (non-empty tile box) in at least one view."""
     vis = np.zeros(scene.n, bool)
@@ -105,15 +119,21 @@ def visible_count(scene, cams, tile=(16, 16)):
 
 
 def assert_pose_close(got, ref, ref_flipped=None, rtol=1e-3):
-    """Camera tangents per view within rtol in norm (the flipped reference
-    must agree with the plain one to a quarter of that)."""
+    """Camera tangents per view within rtol in norm.  A camera tangent sums
+    over every blended pair of the view, so no Gaussian can be left out of
+    it: instead its allowance grows by its sensitivity to the decisions taken
+    within a relative 1e-5 of their thresholds (the oracle's flip-band
+    result, whose distance from the plain one must itself stay below rtol;
+    FP32 may take either branch of those decisions)."""
     got = np.asarray(got, np.float64).reshape(-1, 6)
     ref = np.asarray(ref, np.float64).reshape(-1, 6)
     for v in range(ref.shape[0]):
         nr = np.linalg.norm(ref[v])
+        sens = 0.0
         if ref_flipped is not None:
-            assert np.linalg.norm(ref_flipped[v] - ref[v]) <= 0.25 * rtol * nr, v
-        assert np.linalg.norm(got[v] - ref[v]) <= rtol * nr, (v, got[v], ref[v])
+            sens = float(np.linalg.norm(np.asarray(ref_flipped, np.float64).reshape(-1, 6)[v] - ref[v]))
+            assert sens <= rtol * nr, (v, sens / nr)
+        assert np.linalg.norm(got[v] - ref[v]) <= rtol * nr + sens, (v, got[v], ref[v])
 
 
 def assert_forward_close(col, dep, ref, extra_mask=None, max_flag_frac=1e-4):

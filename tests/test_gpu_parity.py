@@ -20,7 +20,7 @@ from paper_2410_00486_amd import _lib as L
 from synth import scenes
 
 from gpu_common import (DEV, assert_forward_close, assert_grads_close, assert_pose_close,
-                        grads_np, oracle_reference, run_gpu, t32, view_images, visible_count,
+                        decided_target, grads_np, oracle_reference, run_gpu, t32, view_images, visible_count,
                         workload)
 
 pytestmark = pytest.mark.gpu
@@ -57,6 +57,36 @@ def test_preprocess_records_match_oracle(cfg):
     np.testing.assert_allclose(f[:, 2:5], ref["rgb"][vis], rtol=1.2e-7, atol=1e-12)
     flags = plan.flags_of(ws)
     assert flags[L.F_VISIBLE] == vis.sum() and flags[L.F_NONFINITE] == 0
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_three_sigma_cutoff_matches_oracle(tile):
+    """The comparison-only 3-sigma tile box (GS_CUTOFF_3SIGMA): boxes and
+    pair counts bit-exact, the image within the forward tolerance and `last`
+    bit-exact against the oracle's 3-sigma branch."""
+    w = workload(1)
+    cam = w.cameras[0]
+    ref = oracle.render(w.scene, cam, tile, cutoff="3sigma")
+    pre = ref["pre"]
+    print(f"3-sigma cutoff, tile {tile}", flush=True)
+    it = run_gpu(w.scene, [cam], tile=tile, flags=L.GS_CUTOFF_3SIGMA,
+                 capacity=int(pre["tiles_touched"].astype(np.int64).sum()) + 64)
+    plan, ws = it.plan, it.ws
+    n = w.scene.n
+    assert plan.flags_of(ws)[L.F_OVERFLOW] == 0
+    rects = plan.region(ws, L.GS_WS_RECTS, torch.int16, 4 * n).cpu().numpy().reshape(n, 4).view(np.uint16)
+    tt = plan.region(ws, L.GS_WS_TILES_TOUCHED, torch.int32, n).cpu().numpy()
+    vis = pre["status"] == 1
+    ok = vis & (pre["near_edge"] == 0)
+    np.testing.assert_array_equal(tt > 0, vis)
+    np.testing.assert_array_equal(rects[ok].astype(np.int32), pre["rect"][ok])
+    np.testing.assert_array_equal(tt[ok], pre["tiles_touched"][ok])
+    ex = oracle.preprocess(w.scene, cam, tile)
+    assert int(pre["tiles_touched"].sum()) != int(ex["tiles_touched"].sum())
+    col, dep, _, last = view_images(it, 0)
+    assert_forward_close(col, dep, ref)
+    okp = ref["flag"] == 0
+    np.testing.assert_array_equal(last[okp], ref["last"][okp])
 
 
 # ------------------------------------------------------------------ sort
@@ -240,25 +270,24 @@ def test_pose_gradient_matches_oracle():
 
 
 def test_fused_l1_matches_oracle():
+    """The fused L1 RGB + 0.1 L1 depth loss and its gradients against the
+    oracle, with a target whose every residual is decided at FP32 accuracy
+    (the render of the perturbed scene, residuals under 1e-4 pushed out to
+    1e-4), so that no L1 sign is ambiguous."""
     w = workload(2)
     cam = w.cameras[0]
     tgt = oracle.render(w.target_scene, cam)
-    trgb, tdep = tgt["color"].astype(np.float32), tgt["depth"].astype(np.float32)
+    ref = oracle.render(w.scene, cam)
+    trgb = decided_target(ref["color"], tgt["color"])
+    tdep = decided_target(ref["depth"], tgt["depth"])
     it = run_gpu(w.scene, [cam], flags=L.GS_FUSED_L1, target_rgb=[trgb], target_depth=[tdep],
                  lambda_depth=0.1)
-    ref = oracle.render(w.scene, cam)
     loss, gC, gD = oracle.l1_loss_and_grads(ref["color"], ref["depth"], trgb, tdep, 0.1)
     got_loss = float(it.frame.loss.cpu()[0])
     assert abs(got_loss - loss) <= 1e-5 * abs(loss)
-    # residual signs not decided at FP32 accuracy: the other sign is as valid
-    ambc = np.abs(ref["color"] - trgb) <= 1e-5 * np.abs(trgb) + 1e-6
-    ambd = np.abs(ref["depth"] - tdep) <= 1e-5 * np.abs(tdep) + 1e-6
-    col_alt = np.where(ambc, 2.0 * trgb - ref["color"], ref["color"])
-    dep_alt = np.where(ambd, 2.0 * tdep - ref["depth"], ref["depth"])
-    _, gC_alt, gD_alt = oracle.l1_loss_and_grads(col_alt, dep_alt, trgb, tdep, 0.1)
-    grads, _, exclude, _ = oracle_reference(w.scene, [cam], [gC], [gD], alt_gcs=[gC_alt],
-                                            alt_gds=[gD_alt])
-    assert_grads_close(grads_np(it), grads, exclude, visible=visible_count(w.scene, [cam]))
+    grads, _, exclude, _ = oracle_reference(w.scene, [cam], [gC], [gD])
+    rep = assert_grads_close(grads_np(it), grads, exclude, visible=visible_count(w.scene, [cam]))
+    print(f"excluded {int(exclude.sum())}; (max err/tol, rel norm) {rep}")
 
 
 # ------------------------------------------------------------------ Adam
@@ -395,7 +424,9 @@ def test_iteration_sparse_adam_equals_separate_calls(lambda_o, degree):
     tgt = t32(rng.uniform(0.0, 1.0, (3, cam.height, cam.width)).reshape(-1))
     cams = gsr.cameras_tensor([cam], DEV)
     g1 = gsr.Gaussians.from_scene(scene, DEV)
-    cap = gsr.required_pairs(*g1.tensors(), cams, [(cam.width, cam.height)], degree, (16, 16)) + 7
+    # headroom for the second iteration, whose parameters Adam has moved
+    cap = int(gsr.required_pairs(*g1.tensors(), cams, [(cam.width, cam.height)], degree,
+                                 (16, 16)) * 1.2) + 64
     plan = gsr.Plan(scene.n, degree, [(cam.width, cam.height)], flags=L.GS_FUSED_L1,
                     pair_capacity=cap)
     it = gsr.Iteration(plan, g1, cams, target_rgb=tgt, adam_lrs=lrs, lambda_o=lambda_o)
@@ -425,12 +456,13 @@ def test_iteration_sparse_adam_equals_separate_calls(lambda_o, degree):
     assert int(it.step_dev.item()) == 1
     it.enqueue()
     torch.cuda.synchronize()
+    assert int(plan.flags_of(it.ws)[L.F_OVERFLOW]) == 0
     assert int(it.step_dev.item()) == 2
 
 
 @pytest.mark.parametrize("n,extra", [(300, 0), (3000, 0), (300, L.GS_SPLAT_BWD), (3000, L.GS_SPLAT_BWD)])
 def test_iteration_sorting_in_forward_equals_separate_calls(n, extra):
-    """A whole iteration lets the forward sort each tile's list (up to 512
+    """A whole iteration lets the forward sort each tile's list (up to 128
     pairs; longer lists by the long-list kernel before it).  Against the
     separate calls, whose binning sorts every list itself: the sorted lists,
     the images, the loss and the Adam step bit for bit, on a view with lists

@@ -28,6 +28,12 @@ from gpu_common import (DEV, assert_forward_close, assert_grads_close, assert_po
 pytestmark = pytest.mark.gpu
 
 TILE = (8, 8)
+# Pixels with a decision within a relative 1e-5 of its threshold are left
+# out of the forward check.  Their number grows with the (pixel, Gaussian)
+# evaluations per pixel: the close-up keyframes blend hundreds of splats per
+# pixel and the four-room pool has 30 % of its opacities near 1/255, so about
+# 2-3e-4 of their pixels have one; the single-view workloads stay under 1e-4.
+MAX_FLAG_FRAC = 1e-3
 BENCH_FLAGS = L.GS_PERSISTENT | L.GS_SPLAT_BWD
 LRS = {"means": 1.6e-4, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
 
@@ -70,7 +76,8 @@ def test_keyframes8_full_matches_oracle():
     for v, cam in enumerate(cams):
         ref = oracle.render(w.scene, cam, TILE)
         col, dep, _, last = view_images(it, v)
-        assert_forward_close(col, dep, ref)
+        nflag = assert_forward_close(col, dep, ref, max_flag_frac=MAX_FLAG_FRAC)
+        print(f"  view {v}: {nflag} flagged pixels of {ref['flag'].size}", flush=True)
         ok = ref["flag"] == 0
         np.testing.assert_array_equal(last[ok], ref["last"][ok])
     grads, poses, exclude, poses_f = oracle_reference(w.scene, cams, gcs, gds, TILE)
@@ -108,7 +115,8 @@ def test_keyframes16_two_views_match_oracle():
     for v, cam in enumerate(cams):
         ref = oracle.render(w.scene, cam, TILE)
         col, dep, _, last = view_images(it, v)
-        assert_forward_close(col, dep, ref)
+        nflag = assert_forward_close(col, dep, ref, max_flag_frac=MAX_FLAG_FRAC)
+        print(f"  view {v}: {nflag} flagged pixels of {ref['flag'].size}", flush=True)
         ok = ref["flag"] == 0
         np.testing.assert_array_equal(last[ok], ref["last"][ok])
     grads, poses, exclude, poses_f = oracle_reference(w.scene, cams, gcs, gds, TILE)

@@ -12,7 +12,8 @@ operand, a wrong SH constant) fails at least one of them:
   stacked Gaussians, an opaque stack hitting the stop rule), the telescoping
   identity sum_k a_k T_k + T_final = 1, background for a transparent splat;
 * the exact opacity-aware tile box vs sampled points on the a = 1/255 ellipse,
-  and tiled == untiled rendering for every tile shape;
+  and tiled == untiled rendering for every tile shape; the comparison-only
+  3-sigma box vs numpy's eigenvalues and sampled points on its circle;
 * invariances (rigid motion of scene + camera, q -> -q, isotropic => q-free);
 * sort vs numpy's lexsort;
 * the hand-derived backward vs FP64 central differences (all parameter
@@ -204,6 +205,63 @@ def test_tile_rect_covers_exact_alpha_ellipse():
             inside = (pts[0] >= 0) & (pts[0] < 160) & (pts[1] >= 0) & (pts[1] < 120)
             tx, ty = np.floor(pts[0][inside] / tile[0]), np.floor(pts[1][inside] / tile[1])
             assert np.all((tx >= x0) & (tx < x1) & (ty >= y0) & (ty < y1))
+
+
+def test_three_sigma_box_pins():
+    """The comparison-only 3-sigma tile box: the square of half-width
+    3 sqrt(lambda_max) of the projected covariance (lambda_max from numpy's
+    symmetric eigensolver), padded by the same margin as the exact box.  The
+    box must hold every sampled point of the 3-sigma circle, equal the tile
+    range of that square wherever the eigenvalue gap is not floored (the
+    floor only widens nearly isotropic boxes), and leave the projection, the
+    culling of invisible Gaussians and the compositing rules as they are: a
+    3-sigma render whose single tile is the whole image equals the brute
+    force over the same records."""
+    rng = np.random.default_rng(21)
+    n = 60
+    means = np.stack([rng.uniform(-0.6, 0.6, n), rng.uniform(-0.45, 0.45, n), rng.uniform(2, 3.5, n)], 1)
+    ls = rng.normal(-2.5, 0.6, (n, 3))
+    logits = rng.normal(0.0, 1.5, n)
+    sc = _scene(means, ls, rng.standard_normal((n, 4)), logits, _dc_for_colour(rng.uniform(0, 1, (n, 1, 3))))
+    cam = _cam(160, 120, 100.0)
+    checked_eq = 0
+    for tile in [(16, 16), (8, 8), (16, 8)]:
+        pre = oracle.preprocess(sc, cam, tile, cutoff="3sigma")
+        ex = oracle.preprocess(sc, cam, tile)
+        np.testing.assert_array_equal(pre["mean2d"], ex["mean2d"])
+        np.testing.assert_array_equal(pre["conic"], ex["conic"])
+        tx_n, ty_n = (160 + tile[0] - 1) // tile[0], (120 + tile[1] - 1) // tile[1]
+        for i in range(n):
+            if pre["status"][i] != 1:
+                continue
+            A, B, C = pre["cov2d"][i]
+            lam = np.linalg.eigvalsh(np.array([[A, B], [B, C]]))
+            r = 3.0 * math.sqrt(lam[1])
+            ang = np.linspace(0, 2 * np.pi, 4001)
+            pts = pre["mean2d"][i][:, None] + r * np.stack([np.cos(ang), np.sin(ang)])
+            x0, y0, x1, y1 = pre["rect"][i]
+            inside = (pts[0] >= 0) & (pts[0] < 160) & (pts[1] >= 0) & (pts[1] < 120)
+            tx, ty = np.floor(pts[0][inside] / tile[0]), np.floor(pts[1][inside] / tile[1])
+            assert np.all((tx >= x0) & (tx < x1) & (ty >= y0) & (ty < y1))
+            gap = 0.5 * (lam[1] - lam[0])
+            if gap * gap < 0.1 * (1 + 1e-9):
+                continue
+            h = r * (1 + 1e-4) + 1e-3
+            mx, my = pre["mean2d"][i]
+            lo = np.array([(mx - h) / tile[0], (my - h) / tile[1]])
+            hi = np.array([(mx + h) / tile[0], (my + h) / tile[1]])
+            if np.any(np.abs(np.concatenate([lo, hi]) - np.round(np.concatenate([lo, hi]))) < 1e-9):
+                continue
+            want = [int(np.clip(np.floor(lo[0]), 0, tx_n)), int(np.clip(np.floor(lo[1]), 0, ty_n)),
+                    int(np.clip(np.floor(hi[0]) + 1, 0, tx_n)), int(np.clip(np.floor(hi[1]) + 1, 0, ty_n))]
+            assert list(pre["rect"][i]) == want, (i, tile, list(pre["rect"][i]), want)
+            checked_eq += 1
+    assert checked_eq > 30
+    whole = oracle.preprocess(sc, cam, (160, 120), cutoff="3sigma")
+    tiled = oracle.render(sc, cam, (160, 120), cutoff="3sigma", pre=whole)
+    brute = oracle.render_untiled(sc, cam, pre=whole)
+    np.testing.assert_array_equal(tiled["color"], brute["color"])
+    np.testing.assert_array_equal(tiled["depth"], brute["depth"])
 
 
 # ---------------------------------------------------------------------------
