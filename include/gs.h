@@ -347,6 +347,20 @@ size_t gs_sort_tmp_bytes(int64_t n);
 gs_status gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits,
                         void* tmp, void* stream);
 
+/* Allocation-free form of gs_sort_pairs, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, hosts that
+ * forbid hipMalloc).  Same arguments and result as gs_sort_pairs without
+ * tmp: the scratch is a device array inside the library, one per GPU, of
+ * GS_SORT_NOALLOC_MAX pairs (about 12.9 MB), held from the first call on
+ * that GPU until the process ends.  n above GS_SORT_NOALLOC_MAX is
+ * rejected with GS_ERR_INVALID_ARG before any GPU work.  No hipMalloc,
+ * hipFree or allocating library routine is called.  Every call on one GPU
+ * shares that GPU's scratch: calls that overlap in time on one GPU (two
+ * streams, two host threads) race and must be ordered by the caller. */
+#define GS_SORT_NOALLOC_MAX (1 << 20)
+gs_status gs_sort_pairs_noalloc(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits,
+                                void* stream);
+
 /* a8. Whole-iteration hipGraph.  The mapping back-end re-optimises keyframes
  * of a growing pool again and again (Sec. III-C-2, Eqs. (5)-(8)); the paper
  * takes one keyframe per iteration, this form takes a batch of keyframes of

@@ -120,6 +120,7 @@ SIGNATURES = {
                                ctypes.POINTER(GsGaussianGrads), i64, vp, vp, vp]),
     "gs_sort_tmp_bytes": (sz, [i64]),
     "gs_sort_pairs": (i32, [vp, vp, i64, i32, vp, vp]),
+    "gs_sort_pairs_noalloc": (i32, [vp, vp, i64, i32, vp]),
     "gs_iteration_enqueue": (i32, [ctypes.POINTER(GsIteration), vp]),
     "gs_graph_create": (i32, [ctypes.POINTER(GsIteration), vp, ctypes.POINTER(vp)]),
     "gs_graph_launch": (i32, [vp, vp]),

@@ -572,6 +572,37 @@ gs_status check_sort_args(const uint64_t* keys, const uint32_t* vals, int64_t n,
   return GS_OK;
 }
 
+// Allocation-free variant: the scratch of GS_SORT_NOALLOC_MAX pairs is a
+// file-scope device array, one copy per GPU, held until the process ends.
+// Host code never passes the array's own name to a kernel or a copy (on the
+// host it is only a stand-in for the symbol): each device's address comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+constexpr SortTmp kNoallocLayout = sort_tmp_layout(GS_SORT_NOALLOC_MAX);
+static __device__ __align__(256) unsigned char scratch[kNoallocLayout.bytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+gs_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_check(e, "gs_sort_pairs_noalloc (hipGetDevice)");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(GS_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_check(e, "gs_sort_pairs_noalloc (hipGetSymbolAddress)");
+    if (!p || !aligned(p, 256))
+      return fail(GS_ERR_HIP, "gs_sort_pairs_noalloc: bad scratch address on device %d", dev);
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -589,6 +620,16 @@ gs_status gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_b
   if (!aligned(tmp, 256)) return fail(GS_ERR_INVALID_ARG, "tmp must be 256-byte aligned");
   return sort_pairs_in(keys, vals, n, key_bits, tmp, static_cast<hipStream_t>(stream),
                        "gs_sort_pairs");
+}
+
+gs_status gs_sort_pairs_noalloc(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits,
+                                void* stream) {
+  gs_status st = check_sort_args(keys, vals, n, GS_SORT_NOALLOC_MAX, key_bits);
+  if (st != GS_OK || n == 0) return st;
+  void* tmp = nullptr;
+  if ((st = scratch_of_current_device(&tmp)) != GS_OK) return st;
+  return sort_pairs_in(keys, vals, n, key_bits, tmp, static_cast<hipStream_t>(stream),
+                       "gs_sort_pairs_noalloc");
 }
 
 }  // extern "C"

@@ -308,6 +308,18 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, key_bits: int, stream=Non
                                   _stream(stream)))
 
 
+SORT_NOALLOC_MAX = 1 << 20
+
+
+def sort_pairs_noalloc(keys: torch.Tensor, vals: torch.Tensor, key_bits: int, stream=None):
+    """sort_pairs without any allocation: the library's own per-GPU scratch
+    (at most SORT_NOALLOC_MAX pairs; overlapping calls on one GPU race)."""
+    if keys.dtype != torch.int64 or vals.dtype != torch.int32 or keys.numel() != vals.numel():
+        raise ValueError("keys must be int64 and vals int32 of equal length")
+    L.check(L.lib().gs_sort_pairs_noalloc(_ptr(keys), _ptr(vals), keys.numel(), int(key_bits),
+                                          _stream(stream)))
+
+
 def grad_stats(plan: Plan, ws: torch.Tensor, accum: torch.Tensor, denom: torch.Tensor,
                stream=None):
     """Accumulate the densification statistics of the last backward."""
