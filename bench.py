@@ -179,7 +179,71 @@ def time_replays(fn, stream, warmup, steps, trials):
 
 # ---------------------------------------------------------------- batched vs per view
 
-def bench_batched(args, dev, workload, search=False, marks=True):
+def bench_scheduled(args, dev, w, cams, target_rgb, target_depth, tile, best, flags, stream):
+    """The keyframe scheduler in the loop: the workload's views are a pool of
+    keyframes, every iteration renders a batch of half of them chosen by the
+    adaptive selection (Eqs. (5)-(8), r0 = 8, d = 4) -- host selection, ids
+    copied to the device, one replay of the captured gathered graph, the
+    batch's losses read back and reported."""
+    import torch
+
+    import paper_2410_00486_amd as gsr
+    K = len(w.cameras)
+    B = K // 2
+    W, H = w.cameras[0].width, w.cameras[0].height
+    pool = gsr.KeyframePool(cams.view(K, -1), target_rgb.view(K, -1),
+                            None if target_depth is None else target_depth.view(K, -1), B)
+    params = gsr.Gaussians.from_scene(w.scene, dev)
+    # any batch holds at most the pairs of the whole pool
+    cap = int(gsr.required_pairs(*params.tensors(), cams, [(W, H)] * K, 3, tile) * 1.1) + 4096
+    plan = gsr.Plan(w.scene.n, 3, [(W, H)] * B, tile=tile, flags=flags, chunk=best["chunk"],
+                    lds_batch=best["lds_batch"], pair_capacity=cap)
+    bc = torch.zeros(B * 20, dtype=torch.float32, device=dev)
+    bt = torch.zeros(3 * plan.total_pixels, dtype=torch.float32, device=dev)
+    bd = None if target_depth is None else torch.zeros(plan.total_pixels, dtype=torch.float32,
+                                                        device=dev)
+    it = gsr.Iteration(plan, params, bc, target_rgb=bt, target_depth=bd, adam_lrs=LRS, gather=pool)
+    with torch.cuda.stream(stream):
+        it.capture(stream)
+    ks = gsr.KeyframeScheduler(capacity=64, r0=8, d=4)
+    for _ in range(K):
+        ks.add_keyframe()
+    rng = np.random.default_rng(11)
+
+    def step():
+        ids = ks.select_batch(rng.uniform(size=B).tolist())
+        pool.select(ids, stream)
+        with torch.cuda.stream(stream):
+            it.replay(stream)
+        stream.synchronize()
+        for i, l in zip(ids, it.frame.loss.cpu().tolist()):
+            ks.report(i, l)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = max(args.steps, 10)
+    for _ in range(n):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / n
+    over = int(plan.flags_of(it.ws)[gsr._lib.F_OVERFLOW])
+    if over:
+        raise SystemExit("scheduled batch: pair capacity overflow")
+    # the same gathered graph replayed back to back without the host loop
+    trials = time_replays(lambda: it.replay(stream), stream, 2, args.steps, 1)
+    it.close()
+    out = {"pool": K, "batch": B, "iters_per_s": round(1e3 / ms, 2),
+           "views_per_s": round(B * 1e3 / ms, 1), "ms_per_iter": round(ms, 4),
+           "graph_only_ms_per_iter": round(trials[0], 4), "refills": int(ks.refills),
+           "loop": "host selection + id copy + graph replay + loss read-back, synchronised "
+                   "every iteration (wall clock)"}
+    log(f"scheduled: {out}")
+    return out
+
+
+def bench_batched(args, dev, workload, search=False, marks=True, scheduled=False):
     """One persistent whole-iteration graph for all views vs the same kernels
     and tile shape launched view by view (one plan per view, gradients
     accumulated, one Adam step).  With `search` the configuration comes from
@@ -237,6 +301,10 @@ def bench_batched(args, dev, workload, search=False, marks=True):
     it.close()
     grads = it.grads
     del it
+    sched = None
+    if scheduled and len(cams_l) >= 2 and len(set(view_wh)) == 1:
+        sched = bench_scheduled(args, dev, w, cams, target_rgb, target_depth, tile, best, flags,
+                                stream)
     # the plain form starts from the same initial parameters
     params = gsr.Gaussians.from_scene(w.scene, dev)
     adam_m, adam_v = params.zeros_like(), params.zeros_like()
@@ -275,6 +343,7 @@ def bench_batched(args, dev, workload, search=False, marks=True):
     del per_view
     torch.cuda.synchronize()
     return {"workload": w.name, "scene": w, "plan": plan, "tile": tile, "config": best,
+            "scheduled": sched,
             "autotune_top": sorted(table, key=lambda r: r["ms"])[:5] if table else None,
             "views": view_wh, "visible_per_view": vis, "counts": counts,
             "ms_batched": ms_b, "ms_batched_trials": trials_b,
@@ -489,7 +558,7 @@ def main():
         return
 
     head = bench_batched(args, dev, args.workload, search=args.autotune,
-                         marks=not args.no_marks)
+                         marks=not args.no_marks, scheduled=not args.no_extras)
     c = dict(head["counts"])
     tile = head["tile"]
     c["tiles"] = head["plan"].total_tiles
@@ -528,6 +597,8 @@ def main():
     }
     if head["autotune_top"]:
         result["autotune_top"] = head["autotune_top"]
+    if head["scheduled"]:
+        result["scheduled"] = head["scheduled"]
     spans = head["spans"]
     if spans is not None:
         by = stage_bytes(c)

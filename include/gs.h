@@ -376,6 +376,28 @@ gs_status gs_sort_pairs_noalloc(uint64_t* keys, uint32_t* vals, int64_t n, int32
  * buffers are written for the Gaussians that have pairs only: Adam takes the
  * others' gradients as zero, so their entries in `grads` are left as they
  * were (the parameters and moments are those of a fully written gradient). */
+/* Keyframe pool of a scheduled batch (gs_iteration.gather,
+ * gs_gather_views): every keyframe has the resolution of every view of the
+ * plan.  Device pointers: pool_cams [n_pool][GS_CAMERA_FLOATS], pool_rgb
+ * [n_pool][3][H][W], pool_depth [n_pool][H][W] (nullable: no depth target),
+ * sel [n_views] keyframe ids (an id outside [0, n_pool) leaves its slot as
+ * it was). */
+typedef struct gs_view_gather {
+  const float* pool_cams;
+  const float* pool_rgb;
+  const float* pool_depth;
+  const int32_t* sel;
+  int32_t n_pool;
+} gs_view_gather;
+
+/* Copies the selected keyframes into the batch slots (the first launch of an
+ * iteration with `gather`): cams_out [n_views][GS_CAMERA_FLOATS], rgb_out
+ * [n_views][3][H][W], depth_out [n_views][H][W] (null iff pool_depth is).
+ * Errors: GS_ERR_INVALID_ARG (null pointer, n_pool < 1, views of differing
+ * sizes). */
+gs_status gs_gather_views(const gs_plan* plan, const gs_view_gather* g, float* cams_out,
+                          float* rgb_out, float* depth_out, void* stream);
+
 typedef struct gs_iteration {
   const gs_plan* plan;
   void* ws;
@@ -404,6 +426,13 @@ typedef struct gs_iteration {
   double lambda_ssim;
   float* loss_grad_color;
   float* loss_grad_depth;
+  /* Optional (null: off): the batch's views are keyframes of a pool, chosen
+   * per iteration by the keyframe scheduler (Sec. III-C-2, Eqs. (5)-(8)).
+   * The iteration first copies, for every batch slot b, keyframe sel[b]'s
+   * camera record into cams_dev[b] and its target images into target_rgb /
+   * target_depth slot b (those buffers are overwritten), so a captured graph
+   * renders whatever ids the caller last wrote to sel -- no re-capture. */
+  const struct gs_view_gather* gather;
 } gs_iteration;
 
 typedef struct gs_graph gs_graph;

@@ -71,6 +71,11 @@ class GsParamGroup(ctypes.Structure):
                 ("opacity_reg", i32)]
 
 
+class GsViewGather(ctypes.Structure):
+    _fields_ = [("pool_cams", vp), ("pool_rgb", vp), ("pool_depth", vp), ("sel", vp),
+                ("n_pool", i32)]
+
+
 class GsIteration(ctypes.Structure):
     _fields_ = [("plan", ctypes.POINTER(GsPlan)), ("ws", vp), ("gaussians", GsGaussians),
                 ("cams_dev", vp), ("color", vp), ("depth", vp), ("T_final", vp), ("last", vp),
@@ -79,7 +84,8 @@ class GsIteration(ctypes.Structure):
                 ("dL_dpose", vp), ("adam_groups", ctypes.POINTER(GsParamGroup)),
                 ("n_adam_groups", i32), ("step_dev", vp), ("beta1", f64), ("beta2", f64),
                 ("eps", f64), ("lambda_o", f64), ("reg_count", i64), ("lambda_ssim", f64),
-                ("loss_grad_color", vp), ("loss_grad_depth", vp)]
+                ("loss_grad_color", vp), ("loss_grad_depth", vp),
+                ("gather", ctypes.POINTER(GsViewGather))]
 
 
 class GsScheduler(ctypes.Structure):
@@ -121,6 +127,8 @@ SIGNATURES = {
     "gs_sort_tmp_bytes": (sz, [i64]),
     "gs_sort_pairs": (i32, [vp, vp, i64, i32, vp, vp]),
     "gs_sort_pairs_noalloc": (i32, [vp, vp, i64, i32, vp]),
+    "gs_gather_views": (i32, [ctypes.POINTER(GsPlan), ctypes.POINTER(GsViewGather), vp, vp, vp,
+                              vp]),
     "gs_iteration_enqueue": (i32, [ctypes.POINTER(GsIteration), vp]),
     "gs_graph_create": (i32, [ctypes.POINTER(GsIteration), vp, ctypes.POINTER(vp)]),
     "gs_graph_launch": (i32, [vp, vp]),

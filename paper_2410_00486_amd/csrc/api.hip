@@ -17,6 +17,7 @@ hipError_t launch_preprocess(const Plan& P, const gs_gaussians& g, const float* 
 hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_short_sorts = false,
                            const StepAdvance* step = nullptr, const Marks* marks = nullptr);
 TileSortArgs tile_sort_args(const Plan& P, void* ws);
+int64_t scan_rounds(const Plan& P);
 hipError_t launch_radix_sort(uint64_t* keys0, uint64_t* keys1, uint32_t* vals0, uint32_t* vals1,
                              const int32_t* cnt, uint32_t* hist, uint32_t* digit_tot,
                              int64_t nb_cap, int key_bits, bool iota, int* which, hipStream_t s);
@@ -53,6 +54,8 @@ hipError_t launch_densify(const gs_gaussians& g, const gs_gaussian_grads& m,
                           float extent, const gs_gaussian_grads& out, const gs_gaussian_grads& out_m,
                           const gs_gaussian_grads& out_v, int64_t cap, int32_t* n_out, void* tmp,
                           hipStream_t s);
+hipError_t launch_gather_views(const Plan& P, const gs_view_gather& g, float* cams_out,
+                               float* rgb_out, float* depth_out, hipStream_t s);
 hipError_t launch_pose_retract(const float* cams_in, const float* xi, float* cams_out,
                                int n_views, hipStream_t s);
 hipError_t launch_pose_vjp(const float* xi, const float* g_delta, float* g_xi, int n_views,
@@ -240,6 +243,8 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_full_start = take(splat ? T * 4 : 0);
   P->off_half_start = take(splat ? T * 4 : 0);
   P->off_ckpt = take((size_t)P->ckpt_slots * tw * th * kStateFloats * 4);
+  P->scan_rounds = scan_rounds(*P);
+  P->off_scan_part = take((size_t)P->scan_rounds * 64);
   P->ws_size = o;
   P->magic = kPlanMagic;
   return GS_OK;
@@ -632,6 +637,31 @@ gs_status gs_sort_pairs_noalloc(uint64_t* keys, uint32_t* vals, int64_t n, int32
                        "gs_sort_pairs_noalloc");
 }
 
+static gs_status check_gather(const Plan& P, const gs_view_gather* g, const float* cams_out,
+                              const float* rgb_out, const float* depth_out) {
+  if (!g || !g->pool_cams || !g->pool_rgb || !g->sel)
+    return fail(GS_ERR_INVALID_ARG, "gather: null pool or selection pointer");
+  if (g->n_pool < 1) return fail(GS_ERR_INVALID_ARG, "gather: n_pool must be >= 1");
+  if (!cams_out || !rgb_out) return fail(GS_ERR_INVALID_ARG, "gather: null camera or colour slots");
+  if ((g->pool_depth != nullptr) != (depth_out != nullptr))
+    return fail(GS_ERR_INVALID_ARG, "gather: depth pool and depth slots go together");
+  for (int v = 1; v < P.vt.n_views; ++v)
+    if (P.vt.v[v].W != P.vt.v[0].W || P.vt.v[v].H != P.vt.v[0].H)
+      return fail(GS_ERR_INVALID_ARG, "gather: every view must have the keyframes' size");
+  return GS_OK;
+}
+
+gs_status gs_gather_views(const gs_plan* plan, const gs_view_gather* g, float* cams_out,
+                          float* rgb_out, float* depth_out, void* stream) {
+  gs_status st;
+  if ((st = check_plan(plan)) != GS_OK) return st;
+  const Plan& P = *plan_of(plan);
+  if ((st = check_gather(P, g, cams_out, rgb_out, depth_out)) != GS_OK) return st;
+  return hip_check(launch_gather_views(P, *g, cams_out, rgb_out, depth_out,
+                                       static_cast<hipStream_t>(stream)),
+                   "gs_gather_views");
+}
+
 }  // extern "C"
 
 // One mapping iteration; `marks` (optional) records the timing events of
@@ -654,6 +684,19 @@ static gs_status iteration_enqueue(const gs_iteration* it, void* stream, const M
     if (!it->target_rgb || !it->loss_grad_color || !it->loss_grad_depth)
       return fail(GS_ERR_INVALID_ARG, "lambda_ssim > 0 needs target_rgb and loss gradient buffers");
   }
+  if (it->gather) {
+    gs_status st = check_gather(P, it->gather, it->cams_dev, it->target_rgb, it->target_depth);
+    if (st != GS_OK) return st;
+  }
+  // the scheduled keyframes into the batch slots, before anything reads them
+  auto gather = [&]() -> gs_status {
+    if (!it->gather) return GS_OK;
+    return hip_check(launch_gather_views(P, *it->gather, const_cast<float*>(it->cams_dev),
+                                         const_cast<float*>(it->target_rgb),
+                                         const_cast<float*>(it->target_depth),
+                                         static_cast<hipStream_t>(stream)),
+                     "gs_iteration_enqueue (gather)");
+  };
   // One view with Adam: the projection backward writes the gradients of the
   // Gaussians with pairs only, and Adam takes the others as zero (no zero
   // fill, no read).  The gradient buffers are left unspecified for those.
@@ -661,8 +704,9 @@ static gs_status iteration_enqueue(const gs_iteration* it, void* stream, const M
                       !(P.cfg.flags & GS_ACCUMULATE_GRADS) && P.n > 0;
   hipStream_t strm = static_cast<hipStream_t>(stream);
   if (!sparse) {
-    gs_status st = hip_check(mk.at(GS_MARK_START, strm), "timing mark");
+    gs_status st = gather();
     if (st != GS_OK) return st;
+    if ((st = hip_check(mk.at(GS_MARK_START, strm), "timing mark")) != GS_OK) return st;
     st = gs_preprocess(it->plan, &it->gaussians, it->cams_dev, it->ws, stream);
     if (st != GS_OK) return st;
     if ((st = hip_check(mk.at(GS_MARK_PREPROCESS, strm), "timing mark")) != GS_OK) return st;
@@ -768,6 +812,7 @@ static gs_status iteration_enqueue(const gs_iteration* it, void* stream, const M
   }
   // no clearing launch: the counters were left zero by the last binning on
   // this workspace (or the workspace is fresh, zero-filled)
+  if ((st = gather()) != GS_OK) return st;
   if ((st = hip_check(mk.at(GS_MARK_START, s), "timing mark")) != GS_OK) return st;
   st = preprocess_enqueue(it->plan, &it->gaussians, it->cams_dev, it->ws, s, false);
   if (st != GS_OK) return st;

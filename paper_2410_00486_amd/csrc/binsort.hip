@@ -206,94 +206,103 @@ __device__ __forceinline__ void store4(uint32_t* __restrict__ a, int64_t i, int6
   if (i + 2 < n) a[i + 2] = x.z;
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_scans(ScanArgs A, int64_t cap,
-                                                      int32_t* __restrict__ fl, StepAdvance st) {
-  constexpr int NW = kScanBlock / kWave;
-  constexpr int NT = 4 * kScanVec, NC = 2 * kScanVec;  // tiles, chunks per thread and round
-  // channels: 64-bit tile pairs, chunk pairs; 32-bit buckets, half buckets,
-  // visible records (full buckets = buckets - half buckets), long tiles
-  __shared__ uint64_t w64[2 * (NW + 1)];
-  __shared__ uint32_t w32[4 * (NW + 1)];
-  __shared__ uint32_t n_long;
-  if (threadIdx.x == 0) n_long = 0u;
-  __syncthreads();
-  uint64_t c64[2] = {0, 0};
-  uint32_t c32[4] = {0, 0, 0, 0};
+// Per-thread inputs of one round: 4 * kScanVec tiles and 2 * kScanVec
+// chunks, and the thread's sums over them.  Channels: 64-bit tile pairs and
+// chunk pairs; 32-bit buckets, half buckets, visible records, tiles with at
+// least kLongTile pairs (work order), lists longer than kTileSortSmall
+// (long-list sort).
+constexpr int kScanN32 = 5;
+struct ScanRound {
+  static constexpr int NT = 4 * kScanVec, NC = 2 * kScanVec;
+  int64_t it, ic;  // first tile and first chunk of the thread
+  uint32_t tc[NT], nb[NT], h[NT], cp[NC], cv[NC];
+  uint64_t s64[2];
+  uint32_t s32[kScanN32];
+};
+
+__device__ __forceinline__ void scan_load(const ScanArgs& A, int64_t r, ScanRound& R) {
   const int64_t T = A.n_tiles, C = A.n_chunks;
-  const int64_t rt = (T + kTileRound - 1) / kTileRound, rc = (C + kChunkRound - 1) / kChunkRound;
-  const int64_t rounds = rt > rc ? rt : rc;
+  R.it = r * kTileRound + (int64_t)ScanRound::NT * threadIdx.x;
+  R.ic = r * kChunkRound + (int64_t)ScanRound::NC * threadIdx.x;
   const uint32_t* chunk_in = reinterpret_cast<const uint32_t*>(A.chunk_cnt);
-  uint32_t* chunk_out = reinterpret_cast<uint32_t*>(A.chunk_pre);
-  for (int64_t r = 0; r < rounds; ++r) {
-    const int64_t it = r * kTileRound + (int64_t)NT * threadIdx.x;
-    const int64_t ic = r * kChunkRound + (int64_t)NC * threadIdx.x;
-    uint32_t tc[NT], cp[NC], cv[NC];
 #pragma unroll
-    for (int k = 0; k < kScanVec; ++k) {
-      const uint4 x = load4(A.cnt, it + 4 * k, T);
-      tc[4 * k] = x.x; tc[4 * k + 1] = x.y; tc[4 * k + 2] = x.z; tc[4 * k + 3] = x.w;
-      const uint4 y = load4(chunk_in, 2 * (ic + 2 * k), 2 * C);
-      cp[2 * k] = y.x; cv[2 * k] = y.y; cp[2 * k + 1] = y.z; cv[2 * k + 1] = y.w;
-    }
-    uint32_t nb[NT], h[NT];
-    uint64_t s64[2] = {0, 0};
-    uint32_t s32[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < NT; ++k) {
-      uint32_t f;
-      bucket_split(tc[k], nb[k], f, h[k]);
-      s64[0] += tc[k];
-      s32[0] += nb[k];
-      s32[1] += h[k];
-      s32[3] += tc[k] >= kLongTile ? 1u : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      s64[1] += cp[k];
-      s32[2] += cv[k];
-    }
-    block_exscan<2, 4>(s64, s32, c64, c32, w64, w32);
-#pragma unroll
-    for (int k = 0; k < kScanVec; ++k) {
-      uint32_t ts[4], bs[4], hs[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t t = it + 4 * k + e;
-        const uint32_t c = tc[4 * k + e];
-        // work order: long tiles from the front, the others from the back
-        // (both positions follow from the long tiles before t)
-        if (t < T)
-          A.order[c >= kLongTile ? s32[3] : (uint32_t)(T - 1 - (t - s32[3]))] = (uint32_t)t;
-        // lists too long for one wavefront (rare): listed for the long-list sort
-        if (t < T && c > kTileSortSmall)
-          A.long_list[atomicAdd(&n_long, 1u)] = make_uint4((uint32_t)t, (uint32_t)s64[0], c, 0u);
-        ts[e] = (uint32_t)s64[0];
-        bs[e] = s32[0];
-        hs[e] = s32[1];
-        s64[0] += c;
-        s32[0] += nb[4 * k + e];
-        s32[1] += h[4 * k + e];
-        s32[3] += c >= kLongTile ? 1u : 0u;
-      }
-      store4(A.tstart, it + 4 * k, T, make_uint4(ts[0], ts[1], ts[2], ts[3]));
-      store4(A.cnt, it + 4 * k, T, make_uint4(0u, 0u, 0u, 0u));
-      if (A.boff) {
-        store4(A.boff, it + 4 * k, T, make_uint4(bs[0], bs[1], bs[2], bs[3]));
-        store4(A.fstart, it + 4 * k, T,
-               make_uint4(bs[0] - hs[0], bs[1] - hs[1], bs[2] - hs[2], bs[3] - hs[3]));
-        store4(A.hstart, it + 4 * k, T, make_uint4(hs[0], hs[1], hs[2], hs[3]));
-      }
-      const uint32_t p0 = (uint32_t)s64[1], v0 = s32[2];
-      const uint32_t p1 = p0 + cp[2 * k], v1 = v0 + cv[2 * k];
-      store4(chunk_out, 2 * (ic + 2 * k), 2 * C, make_uint4(p0, v0, p1, v1));
-      s64[1] = p1 + cp[2 * k + 1];
-      s32[2] = v1 + cv[2 * k + 1];
-    }
+  for (int k = 0; k < kScanVec; ++k) {
+    const uint4 x = load4(A.cnt, R.it + 4 * k, T);
+    R.tc[4 * k] = x.x; R.tc[4 * k + 1] = x.y; R.tc[4 * k + 2] = x.z; R.tc[4 * k + 3] = x.w;
+    const uint4 y = load4(chunk_in, 2 * (R.ic + 2 * k), 2 * C);
+    R.cp[2 * k] = y.x; R.cv[2 * k] = y.y; R.cp[2 * k + 1] = y.z; R.cv[2 * k + 1] = y.w;
   }
-  __syncthreads();  // n_long complete
-  if (threadIdx.x != 0) return;
-  // Both pair totals count the same pairs; a mismatch is reported as an
-  // overflow so that nothing is scattered.
+  R.s64[0] = R.s64[1] = 0;
+#pragma unroll
+  for (int c = 0; c < kScanN32; ++c) R.s32[c] = 0;
+#pragma unroll
+  for (int k = 0; k < ScanRound::NT; ++k) {
+    uint32_t f;
+    bucket_split(R.tc[k], R.nb[k], f, R.h[k]);
+    R.s64[0] += R.tc[k];
+    R.s32[0] += R.nb[k];
+    R.s32[1] += R.h[k];
+    R.s32[3] += R.tc[k] >= kLongTile ? 1u : 0u;
+    R.s32[4] += R.tc[k] > kTileSortSmall ? 1u : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < ScanRound::NC; ++k) {
+    R.s64[1] += R.cp[k];
+    R.s32[2] += R.cv[k];
+  }
+}
+
+// Writes the round's outputs from the thread's exclusive starts (R.s64 /
+// R.s32 after the block scan): list starts, bucket offsets and queue
+// positions, work order, long-list entries (in tile order), chunk offsets;
+// and clears the tile counters (the scatter's cursors).
+__device__ __forceinline__ void scan_emit(const ScanArgs& A, ScanRound& R) {
+  const int64_t T = A.n_tiles, C = A.n_chunks;
+  uint32_t* chunk_out = reinterpret_cast<uint32_t*>(A.chunk_pre);
+#pragma unroll
+  for (int k = 0; k < kScanVec; ++k) {
+    uint32_t ts[4], bs[4], hs[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t t = R.it + 4 * k + e;
+      const uint32_t c = R.tc[4 * k + e];
+      // work order: long tiles from the front, the others from the back
+      // (both positions follow from the long tiles before t)
+      if (t < T)
+        A.order[c >= kLongTile ? R.s32[3] : (uint32_t)(T - 1 - (t - R.s32[3]))] = (uint32_t)t;
+      // lists too long for one wavefront: listed for the long-list sort
+      if (t < T && c > kTileSortSmall)
+        A.long_list[R.s32[4]] = make_uint4((uint32_t)t, (uint32_t)R.s64[0], c, 0u);
+      ts[e] = (uint32_t)R.s64[0];
+      bs[e] = R.s32[0];
+      hs[e] = R.s32[1];
+      R.s64[0] += c;
+      R.s32[0] += R.nb[4 * k + e];
+      R.s32[1] += R.h[4 * k + e];
+      R.s32[3] += c >= kLongTile ? 1u : 0u;
+      R.s32[4] += c > kTileSortSmall ? 1u : 0u;
+    }
+    store4(A.tstart, R.it + 4 * k, T, make_uint4(ts[0], ts[1], ts[2], ts[3]));
+    store4(A.cnt, R.it + 4 * k, T, make_uint4(0u, 0u, 0u, 0u));
+    if (A.boff) {
+      store4(A.boff, R.it + 4 * k, T, make_uint4(bs[0], bs[1], bs[2], bs[3]));
+      store4(A.fstart, R.it + 4 * k, T,
+             make_uint4(bs[0] - hs[0], bs[1] - hs[1], bs[2] - hs[2], bs[3] - hs[3]));
+      store4(A.hstart, R.it + 4 * k, T, make_uint4(hs[0], hs[1], hs[2], hs[3]));
+    }
+    const uint32_t p0 = (uint32_t)R.s64[1], v0 = R.s32[2];
+    const uint32_t p1 = p0 + R.cp[2 * k], v1 = v0 + R.cv[2 * k];
+    store4(chunk_out, 2 * (R.ic + 2 * k), 2 * C, make_uint4(p0, v0, p1, v1));
+    R.s64[1] = p1 + R.cp[2 * k + 1];
+    R.s32[2] = v1 + R.cv[2 * k + 1];
+  }
+}
+
+// Totals -> flags (one thread).  Both pair totals count the same pairs; a
+// mismatch is reported as an overflow so that nothing is scattered.
+__device__ __forceinline__ void scan_finish(const ScanArgs& A, const uint64_t (&c64)[2],
+                                            const uint32_t (&c32)[kScanN32], int64_t cap,
+                                            int32_t* __restrict__ fl, const StepAdvance& st) {
   const uint64_t tile_pairs = c64[0], chunk_pairs = c64[1];
   const bool over = tile_pairs > (uint64_t)cap || tile_pairs != chunk_pairs;
   fl[F_OVERFLOW] = over ? 1 : 0;
@@ -304,17 +313,115 @@ __global__ void __launch_bounds__(kScanBlock) k_scans(ScanArgs A, int64_t cap,
   fl[F_NF_ACC] = 0;
   // the bucket queues are filled by the tile sort at the positions scanned
   // here; the long lists are sorted by their own kernel (none on overflow)
-  fl[F_LONG_TILES] = (int32_t)n_long;
+  fl[F_LONG_TILES] = (int32_t)c32[4];
   const bool splat = A.boff != nullptr;
   fl[F_BQ_FULL] = (over || !splat) ? 0 : (int32_t)(c32[0] - c32[1]);
   fl[F_BQ_HALF] = (over || !splat) ? 0 : (int32_t)c32[1];
-  if (splat) A.boff[T] = c32[0];
+  if (splat) A.boff[A.n_tiles] = c32[0];
   // a whole iteration with Adam advances its step here, once the pairs are
   // known to fit: after an overflow the iteration's Adam launch changes
   // nothing, and neither does the step counter
   if (st.step && !over) advance_step(st);
 }
 
+// One block, all rounds in sequence (small plans: no extra launches).
+__global__ void __launch_bounds__(kScanBlock) k_scans(ScanArgs A, int64_t cap,
+                                                      int32_t* __restrict__ fl, StepAdvance st) {
+  constexpr int NW = kScanBlock / kWave;
+  __shared__ uint64_t w64[2 * (NW + 1)];
+  __shared__ uint32_t w32[kScanN32 * (NW + 1)];
+  uint64_t c64[2] = {0, 0};
+  uint32_t c32[kScanN32] = {0, 0, 0, 0, 0};
+  const int64_t rt = (A.n_tiles + kTileRound - 1) / kTileRound;
+  const int64_t rc = (A.n_chunks + kChunkRound - 1) / kChunkRound;
+  const int64_t rounds = rt > rc ? rt : rc;
+  for (int64_t r = 0; r < rounds; ++r) {
+    ScanRound R;
+    scan_load(A, r, R);
+    block_exscan<2, kScanN32>(R.s64, R.s32, c64, c32, w64, w32);
+    scan_emit(A, R);
+  }
+  if (threadIdx.x == 0) scan_finish(A, c64, c32, cap, fl, st);
+}
+
+// Larger plans: one block per round in three launches.  Per-round totals of
+// every channel (reduce), their exclusive scan and the flags (top, one
+// block), then every round again from its carry (down).
+struct ScanPart {
+  uint64_t p64[2];
+  uint32_t p32[kScanN32];
+  uint32_t pad;
+};
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_reduce(ScanArgs A,
+                                                            ScanPart* __restrict__ part) {
+  constexpr int NW = kScanBlock / kWave;
+  __shared__ uint64_t w64[2 * (NW + 1)];
+  __shared__ uint32_t w32[kScanN32 * (NW + 1)];
+  uint64_t c64[2] = {0, 0};
+  uint32_t c32[kScanN32] = {0, 0, 0, 0, 0};
+  ScanRound R;
+  scan_load(A, blockIdx.x, R);
+  block_exscan<2, kScanN32>(R.s64, R.s32, c64, c32, w64, w32);  // c64 / c32: block totals
+  if (threadIdx.x == 0) {
+    ScanPart p;
+    p.p64[0] = c64[0];
+    p.p64[1] = c64[1];
+#pragma unroll
+    for (int c = 0; c < kScanN32; ++c) p.p32[c] = c32[c];
+    p.pad = 0u;
+    part[blockIdx.x] = p;
+  }
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_top(ScanArgs A, ScanPart* __restrict__ part,
+                                                         int64_t n_parts, int64_t cap,
+                                                         int32_t* __restrict__ fl, StepAdvance st) {
+  constexpr int NW = kScanBlock / kWave;
+  __shared__ uint64_t w64[2 * (NW + 1)];
+  __shared__ uint32_t w32[kScanN32 * (NW + 1)];
+  uint64_t c64[2] = {0, 0};
+  uint32_t c32[kScanN32] = {0, 0, 0, 0, 0};
+  for (int64_t base = 0; base < n_parts; base += kScanBlock) {
+    const int64_t i = base + threadIdx.x;
+    uint64_t s64[2] = {0, 0};
+    uint32_t s32[kScanN32] = {0, 0, 0, 0, 0};
+    if (i < n_parts) {
+      const ScanPart p = part[i];
+      s64[0] = p.p64[0];
+      s64[1] = p.p64[1];
+#pragma unroll
+      for (int c = 0; c < kScanN32; ++c) s32[c] = p.p32[c];
+    }
+    block_exscan<2, kScanN32>(s64, s32, c64, c32, w64, w32);
+    if (i < n_parts) {
+      ScanPart p;
+      p.p64[0] = s64[0];
+      p.p64[1] = s64[1];
+#pragma unroll
+      for (int c = 0; c < kScanN32; ++c) p.p32[c] = s32[c];
+      p.pad = 0u;
+      part[i] = p;
+    }
+  }
+  if (threadIdx.x == 0) scan_finish(A, c64, c32, cap, fl, st);
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_down(ScanArgs A,
+                                                          const ScanPart* __restrict__ part) {
+  constexpr int NW = kScanBlock / kWave;
+  __shared__ uint64_t w64[2 * (NW + 1)];
+  __shared__ uint32_t w32[kScanN32 * (NW + 1)];
+  const ScanPart p = part[blockIdx.x];  // exclusive carry of this round
+  uint64_t c64[2] = {p.p64[0], p.p64[1]};
+  uint32_t c32[kScanN32];
+#pragma unroll
+  for (int c = 0; c < kScanN32; ++c) c32[c] = p.p32[c];
+  ScanRound R;
+  scan_load(A, blockIdx.x, R);
+  block_exscan<2, kScanN32>(R.s64, R.s32, c64, c32, w64, w32);
+  scan_emit(A, R);
+}
 
 // ---------------------------------------------------------------- scatter
 // One wavefront per chunk (64 Gaussians of one view, the projection's
@@ -403,6 +510,60 @@ __global__ void __launch_bounds__(kWave) k_tile_sort(TileSortArgs A) {
   (void)sort_tile_wave(A, blockIdx.x, threadIdx.x, sk);
 }
 
+// Lists of kTileSortSmall + 1 .. kTileSortMid pairs: one wavefront per list
+// (four per workgroup, each with its own LDS), bitonic network with
+// wavefront-level syncs, then the sorted outputs with the record ids of all
+// of a lane's positions looked up in one round trip.
+constexpr int kMidWaves = 4;
+__global__ void __launch_bounds__(kMidWaves * kWave) k_tile_sort_mid(
+    uint32_t* __restrict__ cnt, const int32_t* __restrict__ fl, const uint4* __restrict__ long_list,
+    const uint64_t* __restrict__ skey, TileSortOut out, int clear) {
+  __shared__ uint64_t sk_all[kMidWaves][kTileSortMid];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  uint64_t* sk = sk_all[w];
+  const int n_long = fl[F_OVERFLOW] ? 0 : fl[F_LONG_TILES];
+  constexpr int KMAX = kTileSortMid / kWave;
+  for (int li = blockIdx.x * kMidWaves + w; li < n_long; li += gridDim.x * kMidWaves) {
+    const uint4 e = long_list[li];  // (tile, list start, pairs, -)
+    const uint32_t n = e.z;
+    if (n > kTileSortMid) continue;  // uniform: the long-list kernel's
+    const int t = (int)e.x;
+    const uint32_t start = e.y;
+    const uint64_t tkey = (uint64_t)(uint32_t)t << 32;
+    for (uint32_t k = lane; k < n; k += kWave) sk[k] = skey[start + k];
+    wave_lds_sync();
+    bitonic_sort_wave(sk, n, (uint32_t)lane);
+    uint32_t r[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+      const uint32_t k = (uint32_t)lane + (uint32_t)q * kWave;
+      r[q] = 0u;
+      if (k < n) {
+        const uint64_t key = sk[k];
+        const uint32_t g = (uint32_t)key;
+        out.keys[start + k] = tkey | (key >> 32);
+        out.vals[start + k] = g;
+        r[q] = out.pair_rec[g];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+      const uint32_t k = (uint32_t)lane + (uint32_t)q * kWave;
+      if (k < n) {
+        const uint32_t rk = r[q];
+        out.sorted_rec[start + k] = rk;
+        const float4* src = reinterpret_cast<const float4*>(out.rec + rk);
+        float4* dst = reinterpret_cast<float4*>(out.lrec + start + k);
+        const float4 a0 = src[0], a1 = src[1], a2 = src[2], a3 = src[3];
+        dst[0] = a0; dst[1] = a1; dst[2] = a2; dst[3] = a3;
+      }
+    }
+    wave_lds_sync();  // every key read before the next list overwrites them
+    // counter consumed (when the per-tile pass ran before this kernel)
+    if (clear && lane == 0) cnt[t] = 0u;
+  }
+}
+
 __global__ void __launch_bounds__(kLongThreads) k_tile_sort_long(
     uint32_t* __restrict__ cnt, const int32_t* __restrict__ fl, const uint4* __restrict__ long_list,
     uint64_t* __restrict__ skey, TileSortOut out, int clear) {
@@ -412,6 +573,7 @@ __global__ void __launch_bounds__(kLongThreads) k_tile_sort_long(
     const uint4 e = long_list[li];  // the scan recorded the list's start and length
     const int t = (int)e.x;
     const uint32_t start = e.y, n = e.z;
+    if (n <= kTileSortMid) continue;  // uniform: sorted by k_tile_sort_mid
     const uint64_t tkey = (uint64_t)(uint32_t)t << 32;
     if (n <= kTileSortLong) {
       for (uint32_t k = threadIdx.x; k < n; k += kLongThreads) sk[k] = skey[start + k];
@@ -702,9 +864,20 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_sh
   ScanArgs sa{chunk_cnt, chunk_pre, P.n_chunks, tcnt, tstart, (int64_t)T,
               splat ? ws_at<uint32_t>(ws, P.off_boff) : nullptr, fstart, hstart,
               ws_at<uint32_t>(ws, P.off_order), long_list};
-  // always launched, so that the flags are always set
-  hipLaunchKernelGGL(k_scans, dim3(1), dim3(kScanBlock), 0, s, sa, P.pair_cap, fl,
-                     step ? *step : StepAdvance{});
+  // always launched, so that the flags are always set: one block for a
+  // plan of one round, one block per round in three launches beyond
+  const StepAdvance adv = step ? *step : StepAdvance{};
+  if (P.scan_rounds <= 1) {
+    hipLaunchKernelGGL(k_scans, dim3(1), dim3(kScanBlock), 0, s, sa, P.pair_cap, fl, adv);
+  } else {
+    static_assert(sizeof(ScanPart) <= 64, "scan partial slot");
+    ScanPart* part = ws_at<ScanPart>(ws, P.off_scan_part);
+    const unsigned rounds = (unsigned)P.scan_rounds;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(rounds), dim3(kScanBlock), 0, s, sa, part);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, sa, part, P.scan_rounds,
+                       P.pair_cap, fl, adv);
+    hipLaunchKernelGGL(k_scan_down, dim3(rounds), dim3(kScanBlock), 0, s, sa, part);
+  }
   hipError_t e = mk.at(GS_MARK_BIN_SCAN, s);
   if (e != hipSuccess) return e;
   uint64_t* skey = ws_at<uint64_t>(ws, P.off_scatter);
@@ -724,6 +897,13 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_sh
     const TileSortArgs A = tile_sort_args(P, ws);
     if (!defer_short_sorts) hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)T), dim3(kWave), 0, s, A);
     if ((e = mk.at(GS_MARK_BIN_SHORT_SORT, s)) != hipSuccess) return e;
+    // lists up to kTileSortMid pairs: a wavefront each; longer: a block each
+    // (at most one long list per kTileSortSmall + 1 pairs of capacity; five
+    // workgroups per CU are resident, the waves loop over the lists)
+    const int64_t max_long = std::min<int64_t>(T, P.pair_cap / (kTileSortSmall + 1) + 1);
+    const int mid_grid = (int)std::min<int64_t>((max_long + kMidWaves - 1) / kMidWaves, 1280);
+    hipLaunchKernelGGL(k_tile_sort_mid, dim3((unsigned)mid_grid), dim3(kMidWaves * kWave), 0, s,
+                       tcnt, fl, long_list, skey, A.out, defer_short_sorts ? 0 : 1);
     const int long_grid = (int)std::min<int64_t>(T, 512);  // two blocks per CU
     hipLaunchKernelGGL(k_tile_sort_long, dim3((unsigned)long_grid), dim3(kLongThreads), 0, s,
                        tcnt, fl, long_list, skey, A.out, defer_short_sorts ? 0 : 1);
@@ -732,6 +912,13 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_sh
   }
   if ((e = mk.at(GS_MARK_BIN_LONG_SORT, s)) != hipSuccess) return e;
   return hipGetLastError();
+}
+
+// Rounds of the binning scan for a plan (a round = one block's share).
+int64_t scan_rounds(const Plan& P) {
+  const int64_t rt = ((int64_t)P.vt.total_tiles + kTileRound - 1) / kTileRound;
+  const int64_t rc = (P.n_chunks + kChunkRound - 1) / kChunkRound;
+  return std::max<int64_t>(1, std::max(rt, rc));
 }
 
 // Sorted pair values (generation indices) after launch_bin_sort.

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 SOURCES = ["api.hip", "preprocess.hip", "binsort.hip", "render.hip", "project_bwd.hip", "adam.hip",
-           "loss.hip", "densify.hip", "pose.hip"]
+           "loss.hip", "densify.hip", "pose.hip", "gather.hip"]
 LIB = os.path.join(PKG, "libgs.so")
 BUILD = os.path.join(HERE, "_build")
 
@@ -48,7 +48,8 @@ def build(verbose: bool = False) -> str:
         if w and verbose:
             print(w)
     objs = [o for o, _ in results]
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    # -z defs: an unresolved symbol fails the link instead of the first load
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,-z,defs", "-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -94,6 +94,10 @@ struct Plan {
   // positions, pixel states
   size_t off_boff, off_bq, off_ckpt, off_full_start, off_half_start;
   int64_t ckpt_slots;
+  // binning scan: rounds (one block each when more than one) and their
+  // per-channel partial sums
+  int64_t scan_rounds;
+  size_t off_scan_part;
   size_t ws_size;
 };
 static_assert(sizeof(Plan) <= sizeof(gs_plan), "plan does not fit gs_plan");

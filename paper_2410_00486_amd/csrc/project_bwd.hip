@@ -75,6 +75,98 @@ __device__ __forceinline__ void sh_backward(double x, double y, double z, const 
   }
 }
 
+// Projection chain of one (view, Gaussian) record: from the summed pair
+// partials g2[3..9] (depth, opacity, conic a b c, mean x y) and the world
+// covariance S to the camera-space mean gradient gt and this view's term of
+// dL/dSigma (dS: 00 11 22 01 02 12).  Also returns what the camera tangent
+// needs (X = dL/dSigma', J's entries).
+struct ProjTerm {
+  double gt0, gt1, gt2;
+  double dS[6];
+  double X00, X01, X11, j00, j02, j11, j12;
+};
+__device__ __forceinline__ void proj_term(const double* W, double fx, double fy, double limx,
+                                          double limy, double tx, double ty, double tz,
+                                          double S00, double S01, double S02, double S11,
+                                          double S12, double S22, const double* g2, ProjTerm& o) {
+  const double ux = tx / tz, vy = ty / tz;
+  const bool cu = (ux < -limx) || (ux > limx), cv = (vy < -limy) || (vy > limy);
+  const double u = fmin(limx, fmax(-limx, ux)), wv = fmin(limy, fmax(-limy, vy));
+  const double j00 = fx / tz, j02 = -fx * u / tz, j11 = fy / tz, j12 = -fy * wv / tz;
+  const double a0 = j00 * W[0] + j02 * W[6], a1 = j00 * W[1] + j02 * W[7], a2 = j00 * W[2] + j02 * W[8];
+  const double b0 = j11 * W[3] + j12 * W[6], b1 = j11 * W[4] + j12 * W[7], b2 = j11 * W[5] + j12 * W[8];
+  const double Sa0 = S00 * a0 + S01 * a1 + S02 * a2, Sa1 = S01 * a0 + S11 * a1 + S12 * a2,
+               Sa2 = S02 * a0 + S12 * a1 + S22 * a2;
+  const double Sb0 = S00 * b0 + S01 * b1 + S02 * b2, Sb1 = S01 * b0 + S11 * b1 + S12 * b2,
+               Sb2 = S02 * b0 + S12 * b1 + S22 * b2;
+  const double A = a0 * Sa0 + a1 * Sa1 + a2 * Sa2 + 0.3;
+  const double B = 0.5 * ((a0 * Sb0 + a1 * Sb1 + a2 * Sb2) + (b0 * Sa0 + b1 * Sa1 + b2 * Sa2));
+  const double C = b0 * Sb0 + b1 * Sb1 + b2 * Sb2 + 0.3;
+  const double det = A * C - B * B;
+  const double ya = C / det, yb = -B / det, yc = A / det;  // conic
+  // dL/dX = -Y G_Y Y with G_Y = [[ga, gb/2], [gb/2, gc]]
+  const double ga = g2[5], gbh = 0.5 * g2[6], gc = g2[7];
+  const double M00 = ya * ga + yb * gbh, M01 = ya * gbh + yb * gc;
+  const double M10 = yb * ga + yc * gbh, M11 = yb * gbh + yc * gc;
+  const double X00 = -(M00 * ya + M01 * yb);
+  const double X01 = -(M00 * yb + M01 * yc);
+  const double X11 = -(M10 * yb + M11 * yc);
+  // G_Sigma += X00 a a^T + X01 (a b^T + b a^T) + X11 b b^T
+  o.dS[0] = X00 * a0 * a0 + 2.0 * X01 * a0 * b0 + X11 * b0 * b0;
+  o.dS[1] = X00 * a1 * a1 + 2.0 * X01 * a1 * b1 + X11 * b1 * b1;
+  o.dS[2] = X00 * a2 * a2 + 2.0 * X01 * a2 * b2 + X11 * b2 * b2;
+  o.dS[3] = X00 * a0 * a1 + X01 * (a0 * b1 + b0 * a1) + X11 * b0 * b1;
+  o.dS[4] = X00 * a0 * a2 + X01 * (a0 * b2 + b0 * a2) + X11 * b0 * b2;
+  o.dS[5] = X00 * a1 * a2 + X01 * (a1 * b2 + b1 * a2) + X11 * b1 * b2;
+  // G_T2 rows: 2 (X00 Sa + X01 Sb), 2 (X01 Sa + X11 Sb);  G_J = G_T2 W^T
+  const double r00 = 2 * (X00 * Sa0 + X01 * Sb0), r01 = 2 * (X00 * Sa1 + X01 * Sb1),
+               r02 = 2 * (X00 * Sa2 + X01 * Sb2);
+  const double r10 = 2 * (X01 * Sa0 + X11 * Sb0), r11 = 2 * (X01 * Sa1 + X11 * Sb1),
+               r12 = 2 * (X01 * Sa2 + X11 * Sb2);
+  const double GJ00 = r00 * W[0] + r01 * W[1] + r02 * W[2];
+  const double GJ02 = r00 * W[6] + r01 * W[7] + r02 * W[8];
+  const double GJ11 = r10 * W[3] + r11 * W[4] + r12 * W[5];
+  const double GJ12 = r10 * W[6] + r11 * W[7] + r12 * W[8];
+  const double tz2 = tz * tz, tz3 = tz2 * tz;
+  double gt0 = 0, gt1 = 0, gt2;
+  gt2 = -GJ00 * fx / tz2 - GJ11 * fy / tz2;
+  if (!cu) { gt0 += -GJ02 * fx / tz2; gt2 += GJ02 * 2.0 * fx * tx / tz3; }
+  else { gt2 += GJ02 * fx * u / tz2; }
+  if (!cv) { gt1 += -GJ12 * fy / tz2; gt2 += GJ12 * 2.0 * fy * ty / tz3; }
+  else { gt2 += GJ12 * fy * wv / tz2; }
+  const double gmx = g2[8], gmy = g2[9];
+  gt0 += gmx * fx / tz;
+  gt1 += gmy * fy / tz;
+  gt2 += -(gmx * fx * tx + gmy * fy * ty) / tz2 + g2[3];
+  o.gt0 = gt0; o.gt1 = gt1; o.gt2 = gt2;
+  o.X00 = X00; o.X01 = X01; o.X11 = X11;
+  o.j00 = j00; o.j02 = j02; o.j11 = j11; o.j12 = j12;
+}
+
+// Colour chain of one record: SH-coefficient gradients added into gsh[] and
+// the view-direction part gv of the mean gradient, from the colour partials
+// g2[0..2] (channels clamped at 0 by the forward projection carry none).
+template <int DEG>
+__device__ __forceinline__ void colour_term(const double* W, double t0, double t1, double t2,
+                                            const double* p, uint32_t cmask, const double* g2,
+                                            const float* shv, float* gsh, double& gv0,
+                                            double& gv1, double& gv2) {
+  const double cxw = -(W[0] * t0 + W[3] * t1 + W[6] * t2);
+  const double cyw = -(W[1] * t0 + W[4] * t1 + W[7] * t2);
+  const double czw = -(W[2] * t0 + W[5] * t1 + W[8] * t2);
+  const double dv0 = p[0] - cxw, dv1 = p[1] - cyw, dv2 = p[2] - czw;
+  const double dist = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
+  const double d0 = dv0 / dist, d1 = dv1 / dist, d2 = dv2 / dist;
+  double gcr[3];
+  for (int ch = 0; ch < 3; ++ch) gcr[ch] = ((cmask >> ch) & 1u) ? 0.0 : g2[ch];
+  double gd0 = 0, gd1 = 0, gd2 = 0;
+  sh_backward<DEG>(d0, d1, d2, gcr, shv, gsh, gd0, gd1, gd2);
+  const double dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
+  gv0 = (gd0 - dd * d0) / dist;
+  gv1 = (gd1 - dd * d1) / dist;
+  gv2 = (gd2 - dd * d2) / dist;
+}
+
 // COMPACT (one view): threads take the visible Gaussians from the list the
 // binning wrote, in index order, so that the long chain runs on full
 // wavefronts; the other Gaussians' gradients are zeroed beforehand.
@@ -268,75 +360,21 @@ __global__ void __launch_bounds__((SPLIT && COMPACT) ? kSumWaves * kWave : kProj
         if (DP) {
           const double limx = 1.3 * (double)vt.v[v].W / (2.0 * fx);
           const double limy = 1.3 * (double)vt.v[v].H / (2.0 * fy);
-          const double ux = tx / tz, vy = ty / tz;
-          const bool cu = (ux < -limx) || (ux > limx), cv = (vy < -limy) || (vy > limy);
-          const double u = fmin(limx, fmax(-limx, ux)), wv = fmin(limy, fmax(-limy, vy));
-          j00 = fx / tz; j02 = -fx * u / tz; j11 = fy / tz; j12 = -fy * wv / tz;
-          const double a0 = j00 * W[0] + j02 * W[6], a1 = j00 * W[1] + j02 * W[7], a2 = j00 * W[2] + j02 * W[8];
-          const double b0 = j11 * W[3] + j12 * W[6], b1 = j11 * W[4] + j12 * W[7], b2 = j11 * W[5] + j12 * W[8];
-          const double Sa0 = S00 * a0 + S01 * a1 + S02 * a2, Sa1 = S01 * a0 + S11 * a1 + S12 * a2,
-                       Sa2 = S02 * a0 + S12 * a1 + S22 * a2;
-          const double Sb0 = S00 * b0 + S01 * b1 + S02 * b2, Sb1 = S01 * b0 + S11 * b1 + S12 * b2,
-                       Sb2 = S02 * b0 + S12 * b1 + S22 * b2;
-          const double A = a0 * Sa0 + a1 * Sa1 + a2 * Sa2 + 0.3;
-          const double B = 0.5 * ((a0 * Sb0 + a1 * Sb1 + a2 * Sb2) + (b0 * Sa0 + b1 * Sa1 + b2 * Sa2));
-          const double C = b0 * Sb0 + b1 * Sb1 + b2 * Sb2 + 0.3;
-          const double det = A * C - B * B;
-          const double ya = C / det, yb = -B / det, yc = A / det;  // conic
-          // dL/dX = -Y G_Y Y with G_Y = [[ga, gb/2], [gb/2, gc]]
-          const double ga = g2[5], gbh = 0.5 * g2[6], gc = g2[7];
-          const double M00 = ya * ga + yb * gbh, M01 = ya * gbh + yb * gc;
-          const double M10 = yb * ga + yc * gbh, M11 = yb * gbh + yc * gc;
-          X00 = -(M00 * ya + M01 * yb);
-          X01 = -(M00 * yb + M01 * yc);
-          X11 = -(M10 * yb + M11 * yc);
-          // G_Sigma += X00 a a^T + X01 (a b^T + b a^T) + X11 b b^T
-          GS00 += X00 * a0 * a0 + 2.0 * X01 * a0 * b0 + X11 * b0 * b0;
-          GS11 += X00 * a1 * a1 + 2.0 * X01 * a1 * b1 + X11 * b1 * b1;
-          GS22 += X00 * a2 * a2 + 2.0 * X01 * a2 * b2 + X11 * b2 * b2;
-          GS01 += X00 * a0 * a1 + X01 * (a0 * b1 + b0 * a1) + X11 * b0 * b1;
-          GS02 += X00 * a0 * a2 + X01 * (a0 * b2 + b0 * a2) + X11 * b0 * b2;
-          GS12 += X00 * a1 * a2 + X01 * (a1 * b2 + b1 * a2) + X11 * b1 * b2;
-          // G_T2 rows: 2 (X00 Sa + X01 Sb), 2 (X01 Sa + X11 Sb);  G_J = G_T2 W^T
-          const double r00 = 2 * (X00 * Sa0 + X01 * Sb0), r01 = 2 * (X00 * Sa1 + X01 * Sb1),
-                       r02 = 2 * (X00 * Sa2 + X01 * Sb2);
-          const double r10 = 2 * (X01 * Sa0 + X11 * Sb0), r11 = 2 * (X01 * Sa1 + X11 * Sb1),
-                       r12 = 2 * (X01 * Sa2 + X11 * Sb2);
-          const double GJ00 = r00 * W[0] + r01 * W[1] + r02 * W[2];
-          const double GJ02 = r00 * W[6] + r01 * W[7] + r02 * W[8];
-          const double GJ11 = r10 * W[3] + r11 * W[4] + r12 * W[5];
-          const double GJ12 = r10 * W[6] + r11 * W[7] + r12 * W[8];
-          const double tz2 = tz * tz, tz3 = tz2 * tz;
-          gt2 = -GJ00 * fx / tz2 - GJ11 * fy / tz2;
-          if (!cu) { gt0 += -GJ02 * fx / tz2; gt2 += GJ02 * 2.0 * fx * tx / tz3; }
-          else { gt2 += GJ02 * fx * u / tz2; }
-          if (!cv) { gt1 += -GJ12 * fy / tz2; gt2 += GJ12 * 2.0 * fy * ty / tz3; }
-          else { gt2 += GJ12 * fy * wv / tz2; }
-          const double gmx = g2[8], gmy = g2[9];
-          gt0 += gmx * fx / tz;
-          gt1 += gmy * fy / tz;
-          gt2 += -(gmx * fx * tx + gmy * fy * ty) / tz2 + g2[3];
+          ProjTerm pt;
+          proj_term(W, fx, fy, limx, limy, tx, ty, tz, S00, S01, S02, S11, S12, S22, g2, pt);
+          GS00 += pt.dS[0];
+          GS11 += pt.dS[1];
+          GS22 += pt.dS[2];
+          GS01 += pt.dS[3];
+          GS02 += pt.dS[4];
+          GS12 += pt.dS[5];
+          gt0 = pt.gt0; gt1 = pt.gt1; gt2 = pt.gt2;
+          X00 = pt.X00; X01 = pt.X01; X11 = pt.X11;
+          j00 = pt.j00; j02 = pt.j02; j11 = pt.j11; j12 = pt.j12;
         }
 
         double gv0 = 0, gv1 = 0, gv2 = 0;
-        if (DS) {
-          // colour: SH coefficients and view direction
-          const double cxw = -(W[0] * t0 + W[3] * t1 + W[6] * t2);
-          const double cyw = -(W[1] * t0 + W[4] * t1 + W[7] * t2);
-          const double czw = -(W[2] * t0 + W[5] * t1 + W[8] * t2);
-          const double dv0 = p[0] - cxw, dv1 = p[1] - cyw, dv2 = p[2] - czw;
-          const double dist = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
-          const double d0 = dv0 / dist, d1 = dv1 / dist, d2 = dv2 / dist;
-          // colour clamp decided by the forward projection (record bit per channel)
-          double gcr[3];
-          for (int ch = 0; ch < 3; ++ch) gcr[ch] = ((cmask >> ch) & 1u) ? 0.0 : g2[ch];
-          double gd0 = 0, gd1 = 0, gd2 = 0;
-          sh_backward<DEG>(d0, d1, d2, gcr, shv, gsh, gd0, gd1, gd2);
-          const double dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
-          gv0 = (gd0 - dd * d0) / dist;
-          gv1 = (gd1 - dd * d1) / dist;
-          gv2 = (gd2 - dd * d2) / dist;
-        }
+        if (DS) colour_term<DEG>(W, t0, t1, t2, p, cmask, g2, shv, gsh, gv0, gv1, gv2);
         // mean: W^T g_t + g_v (the colour wavefront of SPLIT sums g_v alone)
         gp0 += W[0] * gt0 + W[3] * gt1 + W[6] * gt2 + gv0;
         gp1 += W[1] * gt0 + W[4] * gt1 + W[7] * gt2 + gv1;
@@ -473,6 +511,293 @@ __global__ void __launch_bounds__((SPLIT && COMPACT) ? kSumWaves * kWave : kProj
   else run(F{}, T{});
 }
 
+// Several views, no camera tangent: the (view, Gaussian) records that have
+// pairs are spread over the lanes.  A workgroup takes 64 Gaussians in two
+// wavefronts (projection chain, colour chain); each wavefront lists the
+// records of its 64 Gaussians (Gaussian-major, views ascending) and runs
+// one record per lane, 64 at a time, so that no lane idles in a view where
+// its own Gaussian has no pairs.  Each record's terms go to LDS and the
+// owner lane adds its records' terms in view order: the same operations in
+// the same order as one thread looping over the views, so the gradients
+// are bit-identical to that form.
+constexpr int kMvItems = kMaxViews * kWave;  // records of 64 Gaussians at most
+template <int DEG>
+__global__ void __launch_bounds__(2 * kWave) k_project_bwd_mv(
+    const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, int64_t n, const float* __restrict__ cams, ViewTable vt,
+    const Rec* __restrict__ recs, const uint32_t* __restrict__ tt, const uint32_t* __restrict__ poff,
+    const float* __restrict__ grad_pair, const int32_t* __restrict__ fl, int accumulate,
+    float* __restrict__ g_means, float* __restrict__ g_ls, float* __restrict__ g_q,
+    float* __restrict__ g_logit, float* __restrict__ g_sh) {
+  constexpr int K = (DEG + 1) * (DEG + 1), K3 = 3 * K;
+  const int lane = lane_id();
+  const int role = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int64_t g0 = (int64_t)blockIdx.x * kWave;
+  const int64_t i = g0 + lane;
+  const bool valid = i < n;
+  const int64_t ic = valid ? i : 0;
+  const bool overflow = fl[F_OVERFLOW] != 0;
+  const int V = vt.n_views;
+
+  __shared__ uint16_t s_item[kMvItems];           // (lane << 6 | view) per record
+  __shared__ double s_lim[kMaxViews][2];          // FOV clamp limits per view
+  __shared__ float s_p[kWave][3];                 // means of the 64 Gaussians
+  __shared__ double s_S[kWave][6];                // world covariances (projection chain)
+  __shared__ float s_sh[kWave][K3];               // SH coefficients (colour chain)
+  __shared__ double s_out0[kWave][10];            // record terms, projection chain
+  __shared__ double s_gv[kWave][3];               // record terms, colour chain (mean part)
+  __shared__ float s_gsh[kWave][K3];              // record terms, colour chain (SH part)
+  __shared__ double s_hand[3][kWave];             // colour -> projection hand-over
+
+  // records with pairs of this lane's Gaussian: one bit per view
+  uint64_t mask = 0;
+  if (valid && !overflow) {
+    for (int v = 0; v < V; ++v)
+      if (tt[(int64_t)v * n + i] > 0u) mask |= 1ull << v;
+  }
+  const uint32_t cnt = (uint32_t)__popcll(mask);
+  uint32_t incl = cnt;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  const uint32_t start = incl - cnt;
+  const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+  if (role == 0) {
+    uint32_t j = start;
+    for (uint64_t m = mask; m; m &= m - 1) s_item[j++] = (uint16_t)((lane << 6) | __builtin_ctzll(m));
+    for (int v = 0; v < V; ++v)
+      if (lane == 0) {
+        const float* c = cams + (int64_t)v * GS_CAMERA_FLOATS;
+        s_lim[v][0] = 1.3 * (double)vt.v[v].W / (2.0 * (double)c[0]);
+        s_lim[v][1] = 1.3 * (double)vt.v[v].H / (2.0 * (double)c[1]);
+      }
+  }
+  // the Gaussian's own data for the record lanes
+  const float mf0 = means[3 * ic], mf1 = means[3 * ic + 1], mf2 = means[3 * ic + 2];
+  s_p[lane][0] = mf0;
+  s_p[lane][1] = mf1;
+  s_p[lane][2] = mf2;
+  float qf0 = 0, qf1 = 0, qf2 = 0, qf3 = 0, lf0 = 0, lf1 = 0, lf2 = 0, logit = 0;
+  if (role == 0) {
+    qf0 = quats[4 * ic]; qf1 = quats[4 * ic + 1]; qf2 = quats[4 * ic + 2]; qf3 = quats[4 * ic + 3];
+    lf0 = log_scales[3 * ic]; lf1 = log_scales[3 * ic + 1]; lf2 = log_scales[3 * ic + 2];
+    logit = logits[ic];
+    double S00 = 0, S01 = 0, S02 = 0, S11 = 0, S12 = 0, S22 = 0;
+    if (valid) {
+      double q[4] = {qf0, qf1, qf2, qf3};
+      const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+      if (qn > 0.0)
+        for (int k = 0; k < 4; ++k) q[k] /= qn;
+      const double w = q[0], x = q[1], y = q[2], z = q[3];
+      const double R00 = 1 - 2 * (y * y + z * z), R01 = 2 * (x * y - w * z), R02 = 2 * (x * z + w * y);
+      const double R10 = 2 * (x * y + w * z), R11 = 1 - 2 * (x * x + z * z), R12 = 2 * (y * z - w * x);
+      const double R20 = 2 * (x * z - w * y), R21 = 2 * (y * z + w * x), R22 = 1 - 2 * (x * x + y * y);
+      const double s0 = exp(2.0 * (double)lf0), s1 = exp(2.0 * (double)lf1), s2 = exp(2.0 * (double)lf2);
+      S00 = R00 * R00 * s0 + R01 * R01 * s1 + R02 * R02 * s2;
+      S01 = R00 * R10 * s0 + R01 * R11 * s1 + R02 * R12 * s2;
+      S02 = R00 * R20 * s0 + R01 * R21 * s1 + R02 * R22 * s2;
+      S11 = R10 * R10 * s0 + R11 * R11 * s1 + R12 * R12 * s2;
+      S12 = R10 * R20 * s0 + R11 * R21 * s1 + R12 * R22 * s2;
+      S22 = R20 * R20 * s0 + R21 * R21 * s1 + R22 * R22 * s2;
+    }
+    s_S[lane][0] = S00; s_S[lane][1] = S01; s_S[lane][2] = S02;
+    s_S[lane][3] = S11; s_S[lane][4] = S12; s_S[lane][5] = S22;
+  } else {
+#pragma unroll
+    for (int k = 0; k < K3; ++k) s_sh[lane][k] = sh[ic * K3 + k];
+  }
+  __syncthreads();  // item list and view limits (wavefront 0) for both
+
+  double gp0 = 0, gp1 = 0, gp2 = 0, gop = 0;
+  double GS00 = 0, GS01 = 0, GS02 = 0, GS11 = 0, GS12 = 0, GS22 = 0;
+  float acc_sh[K3];
+#pragma unroll
+  for (int k = 0; k < K3; ++k) acc_sh[k] = 0.0f;
+
+  for (uint32_t base = 0; base < total; base += kWave) {
+    const uint32_t k = base + (uint32_t)lane;
+    if (k < total) {
+      const uint32_t it = s_item[k];
+      const int o = (int)(it >> 6), v = (int)(it & 63u);
+      const int64_t ri = (int64_t)v * n + g0 + o;
+      const uint32_t np = tt[ri];
+      const float4* gp4 = reinterpret_cast<const float4*>(grad_pair + (int64_t)poff[ri] * kPairGrad);
+      // fixed-order sum of the record's pair partials (the colour chain
+      // needs the first three, the projection chain the rest)
+      double g2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      if (role == 1) {
+        double s0 = 0, s1 = 0, s2 = 0;
+        uint32_t q = 0;
+        for (; q + 8 <= np; q += 8) {
+          float4 a[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) a[u] = gp4[3 * (q + u)];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) { s0 += a[u].x; s1 += a[u].y; s2 += a[u].z; }
+        }
+        for (; q < np; ++q) {
+          const float4 a = gp4[3 * q];
+          s0 += a.x; s1 += a.y; s2 += a.z;
+        }
+        g2[0] = s0; g2[1] = s1; g2[2] = s2;
+      } else {
+        double s3 = 0, s4 = 0, s5 = 0, s6 = 0, s7 = 0, s8 = 0, s9 = 0;
+        uint32_t q = 0;
+        for (; q + 8 <= np; q += 8) {
+          float4 a[8], b[8], c[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            a[u] = gp4[3 * (q + u)];
+            b[u] = gp4[3 * (q + u) + 1];
+            c[u] = gp4[3 * (q + u) + 2];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            s3 += a[u].w;
+            s4 += b[u].x; s5 += b[u].y; s6 += b[u].z; s7 += b[u].w;
+            s8 += c[u].x; s9 += c[u].y;
+          }
+        }
+        for (; q < np; ++q) {
+          const float4 a = gp4[3 * q], b = gp4[3 * q + 1], c = gp4[3 * q + 2];
+          s3 += a.w;
+          s4 += b.x; s5 += b.y; s6 += b.z; s7 += b.w;
+          s8 += c.x; s9 += c.y;
+        }
+        g2[3] = s3; g2[4] = s4; g2[5] = s5; g2[6] = s6; g2[7] = s7; g2[8] = s8; g2[9] = s9;
+      }
+      const float* c = cams + (int64_t)v * GS_CAMERA_FLOATS;
+      const double fx = c[0], fy = c[1];
+      double W[9];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) W[e] = c[4 + e];
+      const double t0 = c[13], t1 = c[14], t2 = c[15];
+      const double p[3] = {(double)s_p[o][0], (double)s_p[o][1], (double)s_p[o][2]};
+      if (role == 0) {
+        const double tx = W[0] * p[0] + W[1] * p[1] + W[2] * p[2] + t0;
+        const double ty = W[3] * p[0] + W[4] * p[1] + W[5] * p[2] + t1;
+        const double tz = W[6] * p[0] + W[7] * p[1] + W[8] * p[2] + t2;
+        ProjTerm pt;
+        proj_term(W, fx, fy, s_lim[v][0], s_lim[v][1], tx, ty, tz, s_S[o][0], s_S[o][1],
+                  s_S[o][2], s_S[o][3], s_S[o][4], s_S[o][5], g2, pt);
+        s_out0[lane][0] = W[0] * pt.gt0 + W[3] * pt.gt1 + W[6] * pt.gt2 + 0.0;
+        s_out0[lane][1] = W[1] * pt.gt0 + W[4] * pt.gt1 + W[7] * pt.gt2 + 0.0;
+        s_out0[lane][2] = W[2] * pt.gt0 + W[5] * pt.gt1 + W[8] * pt.gt2 + 0.0;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) s_out0[lane][3 + e] = pt.dS[e];
+        s_out0[lane][9] = g2[4];
+      } else {
+        const uint32_t cmask = recs[ri].clamp;
+        float* gi = s_gsh[lane];
+#pragma unroll
+        for (int e = 0; e < K3; ++e) gi[e] = 0.0f;
+        double gv0, gv1, gv2;
+        colour_term<DEG>(W, t0, t1, t2, p, cmask, g2, s_sh[o], gi, gv0, gv1, gv2);
+        // (the projection terms are zero in this wavefront)
+        s_gv[lane][0] = W[0] * 0.0 + W[3] * 0.0 + W[6] * 0.0 + gv0;
+        s_gv[lane][1] = W[1] * 0.0 + W[4] * 0.0 + W[7] * 0.0 + gv1;
+        s_gv[lane][2] = W[2] * 0.0 + W[5] * 0.0 + W[8] * 0.0 + gv2;
+      }
+    }
+    wave_lds_sync();
+    // each owner adds the terms of its records in this batch, views ascending
+    const uint32_t lo = start > base ? start : base;
+    const uint32_t hi = (start + cnt) < (base + kWave) ? (start + cnt) : (base + kWave);
+    for (uint32_t r = lo; r < hi; ++r) {
+      const uint32_t sl = r - base;
+      if (role == 0) {
+        gp0 += s_out0[sl][0];
+        gp1 += s_out0[sl][1];
+        gp2 += s_out0[sl][2];
+        GS00 += s_out0[sl][3];
+        GS11 += s_out0[sl][4];
+        GS22 += s_out0[sl][5];
+        GS01 += s_out0[sl][6];
+        GS02 += s_out0[sl][7];
+        GS12 += s_out0[sl][8];
+        gop += s_out0[sl][9];
+      } else {
+        gp0 += s_gv[sl][0];
+        gp1 += s_gv[sl][1];
+        gp2 += s_gv[sl][2];
+#pragma unroll
+        for (int e = 0; e < K3; ++e) acc_sh[e] += s_gsh[sl][e];
+      }
+    }
+    wave_lds_sync();  // before the next batch rewrites the terms
+  }
+
+  if (role == 1) {
+    if (valid) {
+      float* gdst = g_sh + i * K3;
+      if (accumulate) {
+        float old[K3];
+#pragma unroll
+        for (int e = 0; e < K3; ++e) old[e] = gdst[e];
+#pragma unroll
+        for (int e = 0; e < K3; ++e) gdst[e] = old[e] + acc_sh[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < K3; ++e) gdst[e] = acc_sh[e];
+      }
+    }
+    s_hand[0][lane] = gp0;
+    s_hand[1][lane] = gp1;
+    s_hand[2][lane] = gp2;
+    __syncthreads();
+    return;
+  }
+  __syncthreads();
+  gp0 += s_hand[0][lane];
+  gp1 += s_hand[1][lane];
+  gp2 += s_hand[2][lane];
+  if (!valid) return;
+  double q[4] = {qf0, qf1, qf2, qf3};
+  const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  if (qn > 0.0)
+    for (int k = 0; k < 4; ++k) q[k] /= qn;
+  const double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+  const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
+                       2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
+                       2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
+  double GR[9], gl[3];
+  for (int j = 0; j < 3; ++j) {
+    const double Rj0 = R[j], Rj1 = R[3 + j], Rj2 = R[6 + j];
+    const double G0 = GS00 * Rj0 + GS01 * Rj1 + GS02 * Rj2;
+    const double G1 = GS01 * Rj0 + GS11 * Rj1 + GS12 * Rj2;
+    const double G2 = GS02 * Rj0 + GS12 * Rj1 + GS22 * Rj2;
+    const double s2 = exp(2.0 * (double)(j == 0 ? lf0 : (j == 1 ? lf1 : lf2)));
+    gl[j] = 2.0 * s2 * (Rj0 * G0 + Rj1 * G1 + Rj2 * G2);
+    GR[j] = 2.0 * s2 * G0;
+    GR[3 + j] = 2.0 * s2 * G1;
+    GR[6 + j] = 2.0 * s2 * G2;
+  }
+  const double dw = GR[1] * (-2 * qz) + GR[2] * (2 * qy) + GR[3] * (2 * qz) + GR[5] * (-2 * qx) +
+                    GR[6] * (-2 * qy) + GR[7] * (2 * qx);
+  const double dx = GR[1] * (2 * qy) + GR[2] * (2 * qz) + GR[3] * (2 * qy) + GR[4] * (-4 * qx) +
+                    GR[5] * (-2 * qw) + GR[6] * (2 * qz) + GR[7] * (2 * qw) + GR[8] * (-4 * qx);
+  const double dy = GR[0] * (-4 * qy) + GR[1] * (2 * qx) + GR[2] * (2 * qw) + GR[3] * (2 * qx) +
+                    GR[5] * (2 * qz) + GR[6] * (-2 * qw) + GR[7] * (2 * qz) + GR[8] * (-4 * qy);
+  const double dz = GR[0] * (-4 * qz) + GR[1] * (-2 * qw) + GR[2] * (2 * qx) + GR[3] * (2 * qw) +
+                    GR[4] * (-4 * qz) + GR[5] * (2 * qy) + GR[6] * (2 * qx) + GR[7] * (2 * qy);
+  const double dot = dw * qw + dx * qx + dy * qy + dz * qz;
+  const double o = 1.0 / (1.0 + exp(-(double)logit));
+  auto put = [&](float* dst, double val) { *dst = accumulate ? *dst + (float)val : (float)val; };
+  put(&g_means[3 * i], gp0);
+  put(&g_means[3 * i + 1], gp1);
+  put(&g_means[3 * i + 2], gp2);
+  for (int r = 0; r < 3; ++r) put(&g_ls[3 * i + r], gl[r]);
+  const double qnn = qn > 0.0 ? qn : 1.0;
+  put(&g_q[4 * i], (dw - dot * qw) / qnn);
+  put(&g_q[4 * i + 1], (dx - dot * qx) / qnn);
+  put(&g_q[4 * i + 2], (dy - dot * qy) / qnn);
+  put(&g_q[4 * i + 3], (dz - dot * qz) / qnn);
+  put(&g_logit[i], gop * o * (1.0 - o));
+}
+
 // Zero of the five gradient arrays (59 floats per Gaussian at degree 3).
 __global__ void __launch_bounds__(256) k_zero_grads(float* __restrict__ a, int64_t na,
                                                     float* __restrict__ b, int64_t nb,
@@ -554,6 +879,13 @@ hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float*
                      ws_at<float>(ws, P.off_grad_pair), ws_at<int32_t>(ws, P.off_flags),          \
                      ws_at<uint32_t>(ws, P.off_vis_list), accumulate, out.means, out.log_scales,  \
                      out.quats, out.opacity_logits, out.sh, pose_part, blocks)
+#define GS_PBMV(D)                                                                              \
+  hipLaunchKernelGGL((k_project_bwd_mv<D>), dim3((unsigned)split_blocks), dim3(2 * kWave), 0, s,  \
+                     g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, P.n, cams, P.vt,     \
+                     ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_tt),                   \
+                     ws_at<uint32_t>(ws, P.off_poff), ws_at<float>(ws, P.off_grad_pair),         \
+                     ws_at<int32_t>(ws, P.off_flags), accumulate, out.means, out.log_scales,      \
+                     out.quats, out.opacity_logits, out.sh)
 #define GS_PB(D)                \
   if (pose_part) {              \
     if (compact)                \
@@ -564,7 +896,7 @@ hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float*
     if (compact)                \
       GS_PB1(D, false, true);   \
     else                        \
-      GS_PB1(D, false, false);  \
+      GS_PBMV(D);               \
   }
   switch (P.deg) {
     case 0: GS_PB(0); break;
@@ -573,6 +905,7 @@ hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float*
     default: GS_PB(3); break;
   }
 #undef GS_PB
+#undef GS_PBMV
 #undef GS_PB1
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

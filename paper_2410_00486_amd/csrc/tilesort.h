@@ -29,6 +29,8 @@
 namespace gs {
 
 constexpr uint32_t kTileSortSmall = 128;
+// lists of kTileSortSmall + 1 .. kTileSortMid pairs: one wavefront each
+constexpr uint32_t kTileSortMid = 1024;
 constexpr uint32_t kTileSortLong = 8192;
 constexpr int kLongThreads = 1024;
 
@@ -99,6 +101,29 @@ __device__ inline void bitonic_sort(uint64_t* k, uint32_t n, uint32_t tid, uint3
         cmp_swap(k, a, a + stride, n);
       }
       __syncthreads();
+    }
+  }
+}
+
+// Sorts k[0, n) ascending in LDS with the 64 lanes of one wavefront and
+// wavefront-level syncs only (the other wavefronts of its workgroup sort
+// their own lists meanwhile).
+__device__ inline void bitonic_sort_wave(uint64_t* k, uint32_t n, uint32_t lane) {
+  uint32_t m = 1;
+  while (m < n) m <<= 1;
+  for (uint32_t size = 2; size <= m; size <<= 1) {
+    const uint32_t half = size >> 1;
+    for (uint32_t idx = lane; idx < m / 2; idx += kWave) {
+      const uint32_t blk = idx / half, off = idx % half;
+      cmp_swap(k, blk * size + off, blk * size + size - 1 - off, n);
+    }
+    wave_lds_sync();
+    for (uint32_t stride = size >> 2; stride > 0; stride >>= 1) {
+      for (uint32_t idx = lane; idx < m / 2; idx += kWave) {
+        const uint32_t a = 2 * idx - (idx & (stride - 1));
+        cmp_swap(k, a, a + stride, n);
+      }
+      wave_lds_sync();
     }
   }
 }

@@ -371,7 +371,7 @@ class Iteration:
     def __init__(self, plan: Plan, g: Gaussians, cams: torch.Tensor, target_rgb=None,
                  target_depth=None, dL_dcolor=None, dL_ddepth=None, pose_grad=False,
                  adam_lrs: Optional[dict] = None, lambda_o: float = 0.0, lambda_ssim: float = 0.0,
-                 device="cuda"):
+                 device="cuda", gather: Optional["KeyframePool"] = None):
         self.plan, self.g, self.cams = plan, g, cams
         _check_cams(plan, cams)
         if g.n != plan.n or g.sh_degree != plan.sh_degree:
@@ -421,6 +421,15 @@ class Iteration:
             it.lambda_ssim = float(lambda_ssim)
             it.loss_grad_color = self.loss_grad_color.data_ptr()
             it.loss_grad_depth = self.loss_grad_depth.data_ptr()
+        self.gather = gather
+        if gather is not None:
+            # the iteration copies the keyframes of gather.sel into cams and
+            # the targets first (they must be this iteration's own buffers)
+            if target_rgb is None:
+                raise ValueError("a gathered iteration needs target_rgb slots")
+            if (gather.depth is None) != (target_depth is None):
+                raise ValueError("the pool and the iteration must both have depth targets or neither")
+            it.gather = ctypes.pointer(gather.c())
         self.c = it
 
     def enqueue(self, stream=None):
@@ -468,6 +477,42 @@ class Iteration:
 
 
 # ---------------------------------------------------------------- autograd
+
+class KeyframePool:
+    """Keyframes of one camera size on the device -- camera records [K, 20],
+    target colour [K, 3*H*W], target depth [K, H*W] (optional) -- and the
+    batch selection `sel` [B] (int32, device) that a gathered Iteration
+    renders: set it with select(ids) before each replay (an asynchronous
+    copy on the stream)."""
+
+    def __init__(self, cams: torch.Tensor, rgb: torch.Tensor, depth: Optional[torch.Tensor],
+                 batch: int):
+        _need(cams, "cams")
+        _need(rgb, "rgb")
+        if depth is not None:
+            _need(depth, "depth")
+        self.cams, self.rgb, self.depth = cams, rgb, depth
+        self.n = cams.numel() // L.GS_CAMERA_FLOATS
+        self.sel = torch.zeros(int(batch), dtype=torch.int32, device=cams.device)
+        self._host = torch.zeros(int(batch), dtype=torch.int32).pin_memory()
+
+    def c(self) -> "L.GsViewGather":
+        g = L.GsViewGather()
+        g.pool_cams, g.pool_rgb = self.cams.data_ptr(), self.rgb.data_ptr()
+        g.pool_depth = None if self.depth is None else self.depth.data_ptr()
+        g.sel, g.n_pool = self.sel.data_ptr(), self.n
+        self._c = g
+        return g
+
+    def select(self, ids: Sequence[int], stream=None):
+        if len(ids) != self.sel.numel() or not all(0 <= int(i) < self.n for i in ids):
+            raise ValueError(f"need {self.sel.numel()} keyframe ids in [0, {self.n})")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        s.synchronize()  # the pinned staging buffer is reused
+        self._host.copy_(torch.tensor([int(i) for i in ids], dtype=torch.int32))
+        with torch.cuda.stream(s):
+            self.sel.copy_(self._host, non_blocking=True)
+
 
 def pose_retract(cams: torch.Tensor, xi: torch.Tensor, out: Optional[torch.Tensor] = None,
                  stream=None) -> torch.Tensor:

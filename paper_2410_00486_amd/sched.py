@@ -37,6 +37,18 @@ class KeyframeScheduler:
         self._check(L.lib().gs_sched_select(ctypes.byref(self.c), b, u, ids, ctypes.byref(n)))
         return list(ids[:n.value])
 
+    def select_batch(self, uniforms: Sequence[float]) -> List[int]:
+        """Fill a batch of len(uniforms) slots by successive draws: when the
+        eligible keyframes run out part-way, the next draw refills the counts
+        by Eq. (8) first, so a keyframe may take two slots of one batch."""
+        ids = self.select(uniforms)
+        while len(ids) < len(uniforms):
+            more = self.select(uniforms[len(ids):])
+            if not more:
+                break
+            ids += more
+        return ids
+
     def report(self, i: int, loss: float):
         self._check(L.lib().gs_sched_report(ctypes.byref(self.c), int(i), float(loss)))
 

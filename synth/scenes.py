@@ -396,6 +396,20 @@ def keyframes16_1200x680(seed: int = 1005, n: int = 2_000_000, n_views: int = 16
                     notes="large scene; forward + backward + Adam per iteration")
 
 
+def keyframe_pool_640x480(seed: int = 1006, n: int = 150_000, n_keyframes: int = 6) -> Workload:
+    """A pool of keyframes of one 640x480 camera inside the room (the
+    keyframes a scheduled batch draws from); targets are renders of
+    perturbed parameters."""
+    rng = np.random.default_rng(seed)
+    faces = _room_faces(0.0, 0.0) + _box_faces(rng, 0.0, 0.0, 20)
+    scene = _room_gaussians(rng, n, faces, -4.5, 0.4, 3)
+    cams = [_inside_room_camera(rng, 640, 480, 525.0) for _ in range(n_keyframes)]
+    target_scene = _perturbed(rng, scene)
+    return Workload("keyframe_pool_640x480_150k_sh3", scene, cams, None, None, 0.1,
+                    target_scene=target_scene,
+                    notes="keyframe pool for scheduled batches")
+
+
 def tiny_scene(seed: int, n: int = 8, width: int = 32, height: int = 24,
                degree: int = 0, f: float = 30.0) -> Workload:
     """Small scene for finite-difference checks: Gaussians in front of an
