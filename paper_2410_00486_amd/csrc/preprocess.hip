@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(256) k_preprocess(
   double qw = qf.x, qx = qf.y, qy = qf.z, qz = qf.w;
   const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   ok = ok && (qn > 0.0);
-  double S00 = 0, S01 = 0, S02 = 0, S11 = 0, S12 = 0, S22 = 0, o = 0;
+  double S00 = 0, S01 = 0, S02 = 0, S11 = 0, S12 = 0, S22 = 0, o = 0, s2max = 0;
   const double p[3] = {pf[0], pf[1], pf[2]};
   if (ok) {
     // FP64 quotients by a shared denominator as products with its reciprocal
@@ -99,6 +99,7 @@ __global__ void __launch_bounds__(256) k_preprocess(
     S12 = R10 * R20 * s0 + R11 * R21 * s1 + R12 * R22 * s2;
     S22 = R20 * R20 * s0 + R21 * R21 * s1 + R22 * R22 * s2;
     o = 1.0 / (1.0 + exp(-(double)bf));
+    s2max = fmax(s0, fmax(s1, s2));
   }
   const bool sigma3 = (flags & GS_CUTOFF_3SIGMA) != 0;
   bool sh_loaded = false;
@@ -120,6 +121,7 @@ __global__ void __launch_bounds__(256) k_preprocess(
       const double tz = W6 * p[0] + W7 * p[1] + W8 * p[2] + t2;
       bool vis = tz > near_z;
       double mx = 0, my = 0, A = 0, B = 0, C = 0, det = 0;
+      double j00 = 0, j02 = 0, j11 = 0, j12 = 0;
       if (vis) {
         const double itz = 1.0 / tz;
         mx = fx * tx * itz + cx;
@@ -129,7 +131,24 @@ __global__ void __launch_bounds__(256) k_preprocess(
         const double u = fmin(limx, fmax(-limx, tx * itz));
         const double w = fmin(limy, fmax(-limy, ty * itz));
         // rows of T2 = J W
-        const double j00 = fx * itz, j02 = -fx * u * itz, j11 = fy * itz, j12 = -fy * w * itz;
+        j00 = fx * itz; j02 = -fx * u * itz; j11 = fy * itz; j12 = -fy * w * itz;
+        if (!sigma3) {
+          // Cheap rejection of a Gaussian whose exact tile box cannot reach
+          // the image: its half extents are at most kappa_max sqrt(s_max^2
+          // |a|^2 + 0.3) (|a|^2 = j00^2 + j02^2 for the orthonormal rows of
+          // W, kappa <= sqrt(2 ln 255) < 3.33), taken 1 % and 1 px wider
+          // here (plus the float rounding of the mean); the box test below
+          // would find the same empty box.
+          const float fmx = (float)mx, fmy = (float)my;
+          const float hxb = 3.33f * sqrtf((float)(s2max * (j00 * j00 + j02 * j02)) + 0.3f) * 1.01f +
+                            1.0f + 1e-5f * fabsf(fmx);
+          const float hyb = 3.33f * sqrtf((float)(s2max * (j11 * j11 + j12 * j12)) + 0.3f) * 1.01f +
+                            1.0f + 1e-5f * fabsf(fmy);
+          const float xmax = (float)(vi.tiles_x * vt.tw), ymax = (float)(vi.tiles_y * vt.th);
+          vis = !(fmx + hxb < 0.0f || fmx - hxb > xmax || fmy + hyb < 0.0f || fmy - hyb > ymax);
+        }
+      }
+      if (vis) {
         const double a0 = j00 * W0 + j02 * W6, a1 = j00 * W1 + j02 * W7, a2 = j00 * W2 + j02 * W8;
         const double b0 = j11 * W3 + j12 * W6, b1 = j11 * W4 + j12 * W7, b2 = j11 * W5 + j12 * W8;
         // Sigma a, Sigma b

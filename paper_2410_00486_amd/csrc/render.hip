@@ -252,16 +252,19 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec
           const double pw1 = fma(dx1, fma(r1.ca, dx1, r1.cb * dy1), (r1.cc * dy1) * dy1);
           const float a0 = fminf(kAlphaMax, r0.o * __builtin_amdgcn_exp2f((float)(pw0 * kLog2e)));
           const float a1 = fminf(kAlphaMax, r1.o * __builtin_amdgcn_exp2f((float)(pw1 * kLog2e)));
+          // a splat that is not blended gets weight 0: colour, depth are
+          // non-negative and finite, so fma(x, 0, acc) leaves acc as it is
+          // and one select replaces four
           {
             const bool hit = !done[k] && !(pw0 > 0.0) && a0 >= kAlphaMin;
             const float Tn = T[k] * (1.0f - a0);
             const bool stop = Tn < kTMin;
             const bool blend = hit && !stop;
-            const float w = a0 * T[k];
-            c0[k] = blend ? fmaf(r0.r, w, c0[k]) : c0[k];
-            c1[k] = blend ? fmaf(r0.g, w, c1[k]) : c1[k];
-            c2[k] = blend ? fmaf(r0.b, w, c2[k]) : c2[k];
-            D[k] = blend ? fmaf(r0.z, w, D[k]) : D[k];
+            const float w = blend ? a0 * T[k] : 0.0f;
+            c0[k] = fmaf(r0.r, w, c0[k]);
+            c1[k] = fmaf(r0.g, w, c1[k]);
+            c2[k] = fmaf(r0.b, w, c2[k]);
+            D[k] = fmaf(r0.z, w, D[k]);
             T[k] = blend ? Tn : T[k];
             lastpos[k] = blend ? pos0 : lastpos[k];
             done[k] = done[k] || (hit && stop);
@@ -271,11 +274,11 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec
             const float Tn = T[k] * (1.0f - a1);
             const bool stop = Tn < kTMin;
             const bool blend = hit && !stop;
-            const float w = a1 * T[k];
-            c0[k] = blend ? fmaf(r1.r, w, c0[k]) : c0[k];
-            c1[k] = blend ? fmaf(r1.g, w, c1[k]) : c1[k];
-            c2[k] = blend ? fmaf(r1.b, w, c2[k]) : c2[k];
-            D[k] = blend ? fmaf(r1.z, w, D[k]) : D[k];
+            const float w = blend ? a1 * T[k] : 0.0f;
+            c0[k] = fmaf(r1.r, w, c0[k]);
+            c1[k] = fmaf(r1.g, w, c1[k]);
+            c2[k] = fmaf(r1.b, w, c2[k]);
+            D[k] = fmaf(r1.z, w, D[k]);
             T[k] = blend ? Tn : T[k];
             lastpos[k] = blend ? pos0 + 1u : lastpos[k];
             done[k] = done[k] || (hit && stop);
