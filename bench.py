@@ -152,6 +152,16 @@ def load_workload(name, dev):
     return w, view_wh, cams, trgb, tdep
 
 
+def pool_params(gsr, scene, dev, order):
+    """The pool on the device: in the generated order, or sorted by the
+    Morton code of the means (the layout the mapping loop keeps: it
+    re-orders the pool whenever it re-plans after densification)."""
+    g = gsr.Gaussians.from_scene(scene, dev)
+    if order == "spatial":
+        g = gsr.permute(g, gsr.spatial_order(g.means))
+    return g
+
+
 def time_replays(fn, stream, warmup, steps, trials):
     """ms per call of fn() (which enqueues on `stream`): `warmup` untimed
     calls, then `trials` runs of `steps` calls, each bracketed by HIP events
@@ -193,7 +203,7 @@ def bench_scheduled(args, dev, w, cams, target_rgb, target_depth, tile, best, fl
     W, H = w.cameras[0].width, w.cameras[0].height
     pool = gsr.KeyframePool(cams.view(K, -1), target_rgb.view(K, -1),
                             None if target_depth is None else target_depth.view(K, -1), B)
-    params = gsr.Gaussians.from_scene(w.scene, dev)
+    params = pool_params(gsr, w.scene, dev, args.order)
     # any batch holds at most the pairs of the whole pool
     cap = int(gsr.required_pairs(*params.tensors(), cams, [(W, H)] * K, 3, tile) * 1.1) + 4096
     plan = gsr.Plan(w.scene.n, 3, [(W, H)] * B, tile=tile, flags=flags, chunk=best["chunk"],
@@ -257,7 +267,7 @@ def bench_batched(args, dev, workload, search=False, marks=True, scheduled=False
     t_setup = time.time()
     w, view_wh, cams, target_rgb, target_depth = load_workload(workload, dev)
     cams_l = w.cameras
-    params = gsr.Gaussians.from_scene(w.scene, dev)
+    params = pool_params(gsr, w.scene, dev, args.order)
     table = []
     if search:
         best, table = tune.autotune(params, cams, view_wh, target_rgb, target_depth, adam_lrs=LRS,
@@ -306,7 +316,7 @@ def bench_batched(args, dev, workload, search=False, marks=True, scheduled=False
         sched = bench_scheduled(args, dev, w, cams, target_rgb, target_depth, tile, best, flags,
                                 stream)
     # the plain form starts from the same initial parameters
-    params = gsr.Gaussians.from_scene(w.scene, dev)
+    params = pool_params(gsr, w.scene, dev, args.order)
     adam_m, adam_v = params.zeros_like(), params.zeros_like()
     groups = gsr.adam_groups(params, grads, adam_m, adam_v, LRS)
     per_view = []
@@ -436,6 +446,84 @@ def bench_single(args, dev, workload, pose=False):
     return out
 
 
+def bench_extras(args, dev):
+    """The other rows of the path on the 1200x680 / 300k room: the full
+    Eq. (9) loss with SSIM (stand-alone and inside the graphed iteration),
+    the densification statistics, clone / split / prune of the pool, and
+    the mapping loop with densification every 10 iterations (re-plan and
+    re-capture included in its rate)."""
+    import torch
+
+    import paper_2410_00486_amd as gsr
+    from paper_2410_00486_amd import _lib as L
+    w, view_wh, cams, trgb, tdep = load_workload("room_1200x680", dev)
+    tile = tuple(int(x) for x in args.tile.split("x"))
+    params = gsr.Gaussians.from_scene(w.scene, dev)
+    cap = int(gsr.required_pairs(*params.tensors(), cams, view_wh, 3, tile) * 1.5) + 4096
+    splat = L.GS_SPLAT_BWD if args.bwd == "splat" else 0
+    stream = torch.cuda.Stream()
+    out = {}
+
+    def ev_time(fn, reps):
+        return float(np.median(time_replays(fn, stream, 2, reps, 1)))
+
+    plan = gsr.Plan(w.scene.n, 3, view_wh, tile=tile, lds_batch=args.lds_batch,
+                    flags=L.GS_FUSED_L1 | splat, pair_capacity=cap)
+    it = gsr.Iteration(plan, params, cams, target_rgb=trgb, target_depth=tdep, adam_lrs=LRS)
+    it.enqueue(stream)
+    npx = plan.total_pixels
+    dLc = torch.empty(3 * npx, dtype=torch.float32, device=dev)
+    dLd = torch.empty(npx, dtype=torch.float32, device=dev)
+    out["ssim_loss_ms"] = round(ev_time(lambda: gsr.render_loss(
+        plan, it.ws, it.frame, trgb, tdep, 0.2, dLc, dLd, stream), 20), 4)
+    accum = torch.zeros(params.n, dtype=torch.float32, device=dev)
+    denom = torch.zeros(params.n, dtype=torch.float32, device=dev)
+    out["grad_stats_ms"] = round(ev_time(lambda: gsr.grad_stats(plan, it.ws, accum, denom,
+                                                                 stream), 20), 4)
+    it.close()
+    p2 = gsr.Gaussians(*[t.clone() for t in params.tensors()], params.sh_degree)
+    m2, v2 = p2.zeros_like(), p2.zeros_like()
+    normals = torch.randn(params.n, 2, 3, generator=torch.Generator().manual_seed(5)).to(dev)
+    times = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = gsr.densify_prune(p2, m2, v2, accum, denom, normals)  # reads its count
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    out["densify_prune_ms"] = round(float(np.median(times)), 4)
+    out["densify_prune_out"] = int(res[0].n)
+    del res, p2, m2, v2
+    # graphed iteration with the SSIM term (lambda_ssim 0.2): the loss
+    # gradients come from the loss kernels, so the plan drops the fused L1
+    plan_s = plan.replace(flags=plan.flags & ~L.GS_FUSED_L1)
+    it2 = gsr.Iteration(plan_s, gsr.Gaussians(*[t.clone() for t in params.tensors()],
+                                            params.sh_degree), cams, target_rgb=trgb,
+                        target_depth=tdep, adam_lrs=LRS, lambda_ssim=0.2)
+    with torch.cuda.stream(stream):
+        it2.capture(stream)
+    ms = float(np.median(time_replays(lambda: it2.replay(stream), stream, args.warmup,
+                                      args.steps, 1)))
+    out["iters_per_s_with_ssim"] = round(1e3 / ms, 2)
+    it2.close()
+    # the mapping loop: densify every 10 iterations (tau_p 0.001, eps_alpha 0.02)
+    mp = gsr.Mapper(gsr.Gaussians(*[t.clone() for t in params.tensors()], params.sh_degree),
+                    cams, view_wh, trgb, tdep, LRS, tile=tile, lds_batch=args.lds_batch,
+                    flags=splat, densify_every=10, extent=6.0, seed=1, stream=stream)
+    n0 = mp.g.n
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(30):
+        mp.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["mapping_loop"] = {"iterations": 30, "densify_every": 10, "replans": mp.replans,
+                           "gaussians": [n0, mp.g.n], "iters_per_s": round(30 / dt, 2)}
+    mp.close()
+    log(f"extras: {out}")
+    return out
+
+
 # ---------------------------------------------------------------- oracle on the host
 
 def _omp_threads(n):
@@ -535,6 +623,9 @@ def main():
     ap.add_argument("--lds-batch", type=int, default=64)
     ap.add_argument("--chunk", type=int, default=1)
     ap.add_argument("--bwd", default="splat", choices=["pixel", "splat"])
+    ap.add_argument("--order", default="generated", choices=["generated", "spatial"],
+                    help="layout of the batched workloads' pools: as generated (random "
+                         "order) or sorted by the Morton code of the means")
     ap.add_argument("--no-marks", action="store_true",
                     help="skip the per-launch event timing (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -635,6 +726,7 @@ def main():
                            ("room_640x480_pose", True)):
             singles[name] = bench_single(args, dev, name, pose=pose)
         result["single_view"] = singles
+        result["extras"] = bench_extras(args, dev)
     if not args.no_cpu_baseline:
         from synth import scenes
         w2 = scenes.room_1200x680()

@@ -361,6 +361,21 @@ gs_status gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_b
 gs_status gs_sort_pairs_noalloc(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits,
                                 void* stream);
 
+/* Spatial layout of a Gaussian pool (a data-layout step between iterations,
+ * e.g. when the mapping loop re-plans after densification, Sec. IV-A).
+ * gs_spatial_order writes the permutation perm [n] (device int32) that
+ * sorts the means [n][3] by their Morton code in the pool's bounding box
+ * (10 bits per axis; ties keep the index order; a NaN mean goes last);
+ * tmp is device scratch of gs_spatial_order_tmp_bytes(n) bytes, 256-byte
+ * aligned.  gs_permute_gaussians writes dst[j] = src[perm[j]] for the five
+ * parameter arrays (use it for the Adam moments too; dst must not alias
+ * src).  Rendering a permuted pool gives the same images up to the order
+ * of exact depth ties. */
+size_t gs_spatial_order_tmp_bytes(int64_t n);
+gs_status gs_spatial_order(const float* means, int64_t n, int32_t* perm, void* tmp, void* stream);
+gs_status gs_permute_gaussians(const gs_gaussians* src, const int32_t* perm,
+                               const gs_gaussian_grads* dst, void* stream);
+
 /* a8. Whole-iteration hipGraph.  The mapping back-end re-optimises keyframes
  * of a growing pool again and again (Sec. III-C-2, Eqs. (5)-(8)); the paper
  * takes one keyframe per iteration, this form takes a batch of keyframes of

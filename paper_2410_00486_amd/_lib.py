@@ -127,6 +127,10 @@ SIGNATURES = {
     "gs_sort_tmp_bytes": (sz, [i64]),
     "gs_sort_pairs": (i32, [vp, vp, i64, i32, vp, vp]),
     "gs_sort_pairs_noalloc": (i32, [vp, vp, i64, i32, vp]),
+    "gs_spatial_order_tmp_bytes": (sz, [i64]),
+    "gs_spatial_order": (i32, [vp, i64, vp, vp, vp]),
+    "gs_permute_gaussians": (i32, [ctypes.POINTER(GsGaussians), vp,
+                                   ctypes.POINTER(GsGaussianGrads), vp]),
     "gs_gather_views": (i32, [ctypes.POINTER(GsPlan), ctypes.POINTER(GsViewGather), vp, vp, vp,
                               vp]),
     "gs_iteration_enqueue": (i32, [ctypes.POINTER(GsIteration), vp]),

@@ -56,6 +56,11 @@ hipError_t launch_densify(const gs_gaussians& g, const gs_gaussian_grads& m,
                           hipStream_t s);
 hipError_t launch_gather_views(const Plan& P, const gs_view_gather& g, float* cams_out,
                                float* rgb_out, float* depth_out, hipStream_t s);
+size_t spatial_order_tmp_bytes(int64_t n);
+hipError_t launch_spatial_order(const float* means, int64_t n, int32_t* perm, void* tmp,
+                                hipStream_t s);
+hipError_t launch_gather_rows(const float* src, const int32_t* perm, int64_t n, int width,
+                              float* dst, hipStream_t s);
 hipError_t launch_pose_retract(const float* cams_in, const float* xi, float* cams_out,
                                int n_views, hipStream_t s);
 hipError_t launch_pose_vjp(const float* xi, const float* g_delta, float* g_xi, int n_views,
@@ -461,6 +466,36 @@ gs_status gs_adam_step(const gs_param_group* groups, int32_t n_groups, int32_t s
   return hip_check(launch_adam(groups, n_groups, step, beta1, beta2, eps, lambda_o, reg_count,
                                step_dev, s),
                    "gs_adam_step");
+}
+
+size_t gs_spatial_order_tmp_bytes(int64_t n) { return spatial_order_tmp_bytes(n); }
+
+gs_status gs_spatial_order(const float* means, int64_t n, int32_t* perm, void* tmp, void* stream) {
+  if (n < 0 || n > INT32_MAX) return fail(GS_ERR_INVALID_ARG, "n must be 0..2^31-1");
+  if (n == 0) return GS_OK;
+  if (!means || !perm || !tmp) return fail(GS_ERR_INVALID_ARG, "null pointer");
+  if (!aligned(tmp, 256)) return fail(GS_ERR_INVALID_ARG, "tmp must be 256-byte aligned");
+  return hip_check(launch_spatial_order(means, n, perm, tmp, static_cast<hipStream_t>(stream)),
+                   "gs_spatial_order");
+}
+
+gs_status gs_permute_gaussians(const gs_gaussians* src, const int32_t* perm,
+                               const gs_gaussian_grads* dst, void* stream) {
+  if (!src || !dst || (src->n > 0 && !perm)) return fail(GS_ERR_INVALID_ARG, "null argument");
+  if (src->n < 0 || src->n > INT32_MAX) return fail(GS_ERR_INVALID_ARG, "n must be 0..2^31-1");
+  if (src->sh_degree < 0 || src->sh_degree > 3) return fail(GS_ERR_UNSUPPORTED, "sh_degree must be 0..3");
+  if (src->n == 0) return GS_OK;
+  if (!src->means || !src->log_scales || !src->quats || !src->opacity_logits || !src->sh ||
+      !dst->means || !dst->log_scales || !dst->quats || !dst->opacity_logits || !dst->sh)
+    return fail(GS_ERR_INVALID_ARG, "null parameter pointer");
+  const int K3 = 3 * (src->sh_degree + 1) * (src->sh_degree + 1);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_gather_rows(src->means, perm, src->n, 3, dst->means, s);
+  if (e == hipSuccess) e = launch_gather_rows(src->log_scales, perm, src->n, 3, dst->log_scales, s);
+  if (e == hipSuccess) e = launch_gather_rows(src->quats, perm, src->n, 4, dst->quats, s);
+  if (e == hipSuccess) e = launch_gather_rows(src->opacity_logits, perm, src->n, 1, dst->opacity_logits, s);
+  if (e == hipSuccess) e = launch_gather_rows(src->sh, perm, src->n, K3, dst->sh, s);
+  return hip_check(e, "gs_permute_gaussians");
 }
 
 gs_status gs_pose_retract(const float* cams_in, const float* xi, float* cams_out,

@@ -371,7 +371,8 @@ class Iteration:
     def __init__(self, plan: Plan, g: Gaussians, cams: torch.Tensor, target_rgb=None,
                  target_depth=None, dL_dcolor=None, dL_ddepth=None, pose_grad=False,
                  adam_lrs: Optional[dict] = None, lambda_o: float = 0.0, lambda_ssim: float = 0.0,
-                 device="cuda", gather: Optional["KeyframePool"] = None):
+                 device="cuda", gather: Optional["KeyframePool"] = None,
+                 adam_state: Optional[Tuple["Gaussians", "Gaussians", torch.Tensor]] = None):
         self.plan, self.g, self.cams = plan, g, cams
         _check_cams(plan, cams)
         if g.n != plan.n or g.sh_degree != plan.sh_degree:
@@ -391,7 +392,11 @@ class Iteration:
         self._graph = None
         self._groups = None
         if adam_lrs is not None:
-            self.m, self.v = g.zeros_like(), g.zeros_like()
+            if adam_state is not None:
+                # moments and step counter carried over (e.g. across a re-plan)
+                self.m, self.v, self.step_dev = adam_state
+            else:
+                self.m, self.v = g.zeros_like(), g.zeros_like()
             self._groups = adam_groups(g, self.grads, self.m, self.v, adam_lrs, lambda_o != 0.0)
         it = L.GsIteration()
         it.plan = ctypes.pointer(plan.c)
@@ -477,6 +482,113 @@ class Iteration:
 
 
 # ---------------------------------------------------------------- autograd
+
+def spatial_order(means: torch.Tensor, stream=None) -> torch.Tensor:
+    """Permutation (int32 [n], device) sorting the pool by the Morton code of
+    its means (gs_spatial_order)."""
+    _need(means, "means")
+    n = means.shape[0]
+    perm = torch.empty(n, dtype=torch.int32, device=means.device)
+    tmp = torch.empty(max(int(L.lib().gs_spatial_order_tmp_bytes(n)), 256), dtype=torch.uint8,
+                      device=means.device)
+    L.check(L.lib().gs_spatial_order(_ptr(means), n, _ptr(perm), _ptr(tmp), _stream(stream)))
+    return perm
+
+
+def permute(g: "Gaussians", perm: torch.Tensor, stream=None) -> "Gaussians":
+    """New Gaussians with row j = g's row perm[j] (gs_permute_gaussians)."""
+    out = Gaussians(*[torch.empty_like(x) for x in g.tensors()], g.sh_degree)
+    gc, oc = g.c(), out.grads_c()
+    L.check(L.lib().gs_permute_gaussians(ctypes.byref(gc), _ptr(perm), ctypes.byref(oc),
+                                         _stream(stream)))
+    return out
+
+
+spatial_order_ = spatial_order
+
+
+class Mapper:
+    """The mapping loop over one batch of views (Sec. IV-A): every iteration
+    is one replay of the captured whole-iteration graph followed by the
+    densification statistics; every `densify_every` iterations the pool is
+    cloned / split / pruned (tau_p, eps_alpha), the moments follow their
+    Gaussians, and the plan is rebuilt for the new count and captured again
+    (the pair capacity with 30 % headroom over the new pool's pairs).  The
+    split directions are drawn on the device from a seeded generator.  With
+    spatial_order the pool (and the moments with it) is kept sorted by the
+    Morton code of the means: re-ordered at the start and at every re-plan."""
+
+    def __init__(self, g: Gaussians, cams: torch.Tensor, view_wh, target_rgb, target_depth,
+                 lrs: dict, tile=(8, 8), lds_batch: int = 64, flags: int = 0,
+                 densify_every: int = 500, tau_p: float = 0.001, eps_alpha: float = 0.02,
+                 percent_dense: float = 0.01, extent: float = 1.0, seed: int = 0,
+                 lambda_depth: float = 0.1, stream: Optional[torch.cuda.Stream] = None,
+                 spatial_order: bool = False):
+        self.cams, self.view_wh = cams, [tuple(v) for v in view_wh]
+        self.target_rgb, self.target_depth, self.lrs = target_rgb, target_depth, lrs
+        self.tile, self.lds_batch = tuple(tile), int(lds_batch)
+        self.flags = int(flags) | L.GS_FUSED_L1
+        self.densify_every, self.tau_p, self.eps_alpha = int(densify_every), tau_p, eps_alpha
+        self.percent_dense, self.extent, self.lambda_depth = percent_dense, extent, lambda_depth
+        self.gen = torch.Generator(device=g.means.device)
+        self.gen.manual_seed(int(seed))
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=g.means.device)
+        self.iterations, self.replans = 0, 0
+        self.spatial_order = bool(spatial_order)
+        if self.spatial_order:
+            with torch.cuda.stream(self.stream):
+                g = permute(g, spatial_order_(g.means, self.stream), self.stream)
+            self.stream.synchronize()
+        self._build(g, None)
+
+    def _build(self, g: Gaussians, adam_state):
+        dev = g.means.device
+        cap = int(required_pairs(*g.tensors(), self.cams, self.view_wh, g.sh_degree, self.tile)
+                  * 1.3) + 4096
+        self.plan = Plan(g.n, g.sh_degree, self.view_wh, tile=self.tile,
+                         lds_batch=self.lds_batch, flags=self.flags, pair_capacity=cap,
+                         lambda_depth=self.lambda_depth)
+        self.it = Iteration(self.plan, g, self.cams, target_rgb=self.target_rgb,
+                            target_depth=self.target_depth, adam_lrs=self.lrs,
+                            adam_state=adam_state)
+        self.accum = torch.zeros(g.n, dtype=torch.float32, device=dev)
+        self.denom = torch.zeros(g.n, dtype=torch.float32, device=dev)
+        with torch.cuda.stream(self.stream):
+            self.it.capture(self.stream)
+
+    @property
+    def g(self) -> Gaussians:
+        return self.it.g
+
+    def step(self):
+        """One mapping iteration (and a densification when it is due)."""
+        with torch.cuda.stream(self.stream):
+            self.it.replay(self.stream)
+            grad_stats(self.plan, self.it.ws, self.accum, self.denom, self.stream)
+        self.iterations += 1
+        if self.densify_every > 0 and self.iterations % self.densify_every == 0:
+            self.densify()
+
+    def densify(self):
+        it = self.it
+        with torch.cuda.stream(self.stream):
+            normals = torch.randn(it.g.n, 2, 3, generator=self.gen, device=it.g.means.device)
+            g, m, v = densify_prune(it.g, it.m, it.v, self.accum, self.denom, normals,
+                                    tau_p=self.tau_p, eps_alpha=self.eps_alpha,
+                                    percent_dense=self.percent_dense, extent=self.extent,
+                                    stream=self.stream)
+            if self.spatial_order:
+                perm = spatial_order_(g.means, self.stream)
+                g, m, v = (permute(x, perm, self.stream) for x in (g, m, v))
+        self.stream.synchronize()
+        step_dev = it.step_dev
+        it.close()
+        self._build(g, (m, v, step_dev))
+        self.replans += 1
+
+    def close(self):
+        self.it.close()
+
 
 class KeyframePool:
     """Keyframes of one camera size on the device -- camera records [K, 20],
