@@ -62,41 +62,156 @@ SPAN_KERNELS = {
     "adam": "k_adam",
 }
 # HBM counter summaries (rocprofv3 FETCH_SIZE / WRITE_SIZE per dispatch,
-# scaled by a 1 GiB copy), used only while the kernel sources still hash to
-# the value recorded with the counters
+# scaled by a 1 GiB copy), used for a kernel only while the sources it is
+# built from still hash to the values recorded with the counters
 COUNTER_FILES = {
     "keyframes16_1200x680": os.path.join(ROOT, "profiles", "batched_16views_2M_hbm_counters.txt"),
-    "room_1200x680": os.path.join(ROOT, "profiles", "iteration_1200x680_300k_hbm_counters.txt"),
+    "keyframes8_mixed": os.path.join(ROOT, "profiles", "batched_8views_500k_hbm_counters.txt"),
 }
-KERNEL_SOURCES = ["gs_internal.h", "tilesort.h", "api.hip", "preprocess.hip", "binsort.hip",
-                  "render.hip", "project_bwd.hip", "adam.hip", "loss.hip", "densify.hip"]
+CSRC = os.path.join(ROOT, "paper_2410_00486_amd", "csrc")
+# kernel-name prefix -> the source files its code comes from
+KERNEL_SOURCES = {
+    "k_preprocess": ["preprocess.hip", "gs_internal.h"],
+    "k_scan": ["binsort.hip", "tilesort.h", "gs_internal.h"],
+    "k_scatter": ["binsort.hip", "tilesort.h", "gs_internal.h"],
+    "k_tile_sort": ["binsort.hip", "tilesort.h", "gs_internal.h"],
+    "k_bin_": ["binsort.hip", "tilesort.h", "gs_internal.h"],
+    "k_render": ["render.hip", "tilesort.h", "gs_internal.h"],
+    "k_project_bwd": ["project_bwd.hip", "gs_internal.h"],
+    "k_adam": ["adam.hip", "gs_internal.h"],
+}
 
 
-def kernel_source_hash() -> str:
+def source_hashes(files=None) -> dict:
     import hashlib
-    h = hashlib.sha1()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2410_00486_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    files = files or sorted({f for v in KERNEL_SOURCES.values() for f in v})
+    out = {}
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            out[f] = hashlib.sha1(fh.read()).hexdigest()
+    return out
+
+
+def kernel_files(kernel: str):
+    for pre, files in KERNEL_SOURCES.items():
+        if kernel.startswith(pre):
+            return files
+    return None
 
 
 def measured_traffic(workload: str, kernel: str):
     """Scaled HBM bytes per dispatch of `kernel` from the committed counter
-    summary of `workload`, or None if there is none or the kernel sources
+    summary of `workload`, or None if there is none or the kernel's sources
     changed since the counters were taken."""
     path = COUNTER_FILES.get(workload)
-    if not path or not os.path.exists(path):
+    files = kernel_files(kernel)
+    if not path or not os.path.exists(path) or not files:
         return None
     text = open(path).read().splitlines()
-    src = [ln.split(":", 1)[1].strip() for ln in text if ln.startswith("kernel source sha1:")]
-    if not src or src[0] != kernel_source_hash():
+    rec = {}
+    for ln in text:
+        if ln.startswith("source sha1 "):
+            f, h = ln[len("source sha1 "):].split(":", 1)
+            rec[f.strip()] = h.strip()
+    now = source_hashes(files)
+    if any(rec.get(f) != h for f, h in now.items()):
         return None
     for ln in text:
         parts = ln.split()
         if parts and parts[0] == kernel:
             return float(parts[-1]) * 1e6
     return None
+
+
+# ---------------------------------------------------------------- profile summaries
+
+def _short_kernel(name):
+    import re
+    n = name.replace("(anonymous namespace)::", "").replace("void ", "").replace("gs::", "")
+    n = re.sub(r"\(.*$", "", n).strip()
+    if n.startswith("at::native::"):
+        n = "torch:" + n.split("<")[0].split("::")[-1]
+    return n.replace(" ", "")
+
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "*" + suffix))):
+        with open(f) as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def profile_summary(kind, dirs):
+    """Text summary of rocprofv3 csv output (median per dispatch, so that the
+    few dispatches of the set-up do not move the figures of the timed
+    iterations).  kind 'trace': <dir> of a --kernel-trace run; 'hbm': <fetch
+    dir> <write dir> <copy fetch dir> <copy write dir>; 'sq': <dir> of a
+    --pmc run with SQ counters."""
+    import collections
+    lines = []
+    if kind == "trace":
+        by = collections.defaultdict(list)
+        for r in _csv_rows(dirs[0], "_kernel_trace.csv"):
+            by[_short_kernel(r["Kernel_Name"])].append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        tot = sum(sum(v) for v in by.values())
+        lines.append(f"{'kernel':42s} {'calls':>6s} {'median_us':>10s} {'mean_us':>10s} "
+                     f"{'total_us':>11s} {'pct':>6s}")
+        for k, v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+            lines.append(f"{k:42s} {len(v):6d} {np.median(v):10.2f} {np.mean(v):10.2f} "
+                         f"{sum(v):11.1f} {100 * sum(v) / tot:6.2f}")
+        return "\n".join(lines)
+    if kind == "hbm":
+        def per_kernel(d, counter):
+            by = collections.defaultdict(list)
+            for r in _csv_rows(d, "_counter_collection.csv"):
+                if r["Counter_Name"] == counter:
+                    by[_short_kernel(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+            return by
+        fetch, write = per_kernel(dirs[0], "FETCH_SIZE"), per_kernel(dirs[1], "WRITE_SIZE")
+        cf = per_kernel(dirs[2], "FETCH_SIZE")
+        cw = per_kernel(dirs[3], "WRITE_SIZE")
+        copy_bytes = 1 << 30
+        cfk = max(cf.items(), key=lambda kv: len(kv[1]))
+        cwk = max(cw.items(), key=lambda kv: len(kv[1]))
+        f_kib, w_kib = float(np.median(cfk[1])), float(np.median(cwk[1]))
+        sf, sw = copy_bytes / 1024 / f_kib, copy_bytes / 1024 / w_kib
+        for f, h in source_hashes().items():
+            lines.append(f"source sha1 {f}: {h}")
+        lines.append("")
+        lines.append(f"calibration: a 1 GiB device copy ({cfk[0]}) reads FETCH_SIZE {f_kib:.0f} KiB "
+                     f"and WRITE_SIZE {w_kib:.0f} KiB per dispatch -> scale factors fetch "
+                     f"x{sf:.3f}, write x{sw:.3f}")
+        lines.append("")
+        lines.append(f"{'kernel':42s} {'n':>4s} {'FETCH_KiB':>11s} {'WRITE_KiB':>11s} "
+                     f"{'scaled_MB':>10s}")
+        rows = []
+        for k in fetch:
+            if k not in write:
+                continue
+            fk, wk = float(np.median(fetch[k])), float(np.median(write[k]))
+            mb = (fk * sf + wk * sw) * 1024 / 1e6
+            rows.append((mb, f"{k:42s} {len(fetch[k]):4d} {fk:11.0f} {wk:11.0f} {mb:10.2f}"))
+        lines.extend(r for _, r in sorted(rows, reverse=True))
+        return "\n".join(lines)
+    if kind == "sq":
+        by = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in _csv_rows(dirs[0], "_counter_collection.csv"):
+            by[_short_kernel(r["Kernel_Name"])][r["Counter_Name"]].append(
+                float(r["Counter_Value"]))
+        names = sorted({c for v in by.values() for c in v})
+        lines.append("median per dispatch")
+        for k, cs in sorted(by.items(), key=lambda kv: -np.median(
+                kv[1].get("SQ_BUSY_CYCLES", [0]))):
+            lines.append(f"{k}  (n={len(next(iter(cs.values())))})")
+            for c in names:
+                if c in cs:
+                    lines.append(f"    {c:24s} {np.median(cs[c]):16.0f}")
+        return "\n".join(lines)
+    raise SystemExit(f"unknown summary kind {kind}")
 
 
 def log(msg):
@@ -312,6 +427,13 @@ def bench_batched(args, dev, workload, search=False, marks=True, scheduled=False
     grads = it.grads
     del it
     sched = None
+    if getattr(args, "no_per_view", False):
+        torch.cuda.synchronize()
+        return {"workload": w.name, "scene": w, "plan": plan, "tile": tile, "config": best,
+                "scheduled": None, "autotune_top": None, "views": view_wh,
+                "visible_per_view": None, "counts": counts, "ms_batched": ms_b,
+                "ms_batched_trials": trials_b, "ms_per_view": None, "ms_per_view_trials": None,
+                "spans": spans}
     if scheduled and len(cams_l) >= 2 and len(set(view_wh)) == 1:
         sched = bench_scheduled(args, dev, w, cams, target_rgb, target_depth, tile, best, flags,
                                 stream)
@@ -608,8 +730,8 @@ def cpu_baseline(w16, w2):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--trials", type=int, default=5)
     ap.add_argument("--workload", default="keyframes16_1200x680",
                     choices=["keyframes16_1200x680", "keyframes8_mixed"])
@@ -630,7 +752,15 @@ def main():
                     help="skip the per-launch event timing (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--no-per-view", action="store_true",
+                    help="time only the batched form (for profiler runs)")
+    ap.add_argument("--profile-summary", nargs="+", metavar=("KIND", "DIR"),
+                    help="print a summary of rocprofv3 csv output and exit: trace DIR | "
+                         "hbm FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR | sq DIR")
     args = ap.parse_args()
+    if args.profile_summary:
+        print(profile_summary(args.profile_summary[0], args.profile_summary[1:]))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the "
               "keyframes over several GPUs is a documented design, not built", file=sys.stderr)
@@ -655,6 +785,8 @@ def main():
     c["tiles"] = head["plan"].total_tiles
     ms_b, ms_p = head["ms_batched"], head["ms_per_view"]
     n_views = c["views"]
+    if ms_p is None:  # profiler runs: the batched form alone
+        ms_p = float("nan")
     result = {
         "metric": METRIC,
         "value": round(1e3 / ms_b, 2),
@@ -709,7 +841,7 @@ def main():
     torch.cuda.empty_cache()
 
     w2 = None
-    if not args.no_extras:
+    if not args.no_extras and not args.no_per_view:
         other = "keyframes8_mixed" if args.workload != "keyframes8_mixed" else "keyframes16_1200x680"
         b8 = bench_batched(args, dev, other, search=False, marks=True)
         result["other_batched"] = {
@@ -727,7 +859,7 @@ def main():
             singles[name] = bench_single(args, dev, name, pose=pose)
         result["single_view"] = singles
         result["extras"] = bench_extras(args, dev)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.no_per_view:
         from synth import scenes
         w2 = scenes.room_1200x680()
         if w16.target_scene is None:
