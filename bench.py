@@ -198,10 +198,19 @@ def profile_summary(kind, dirs):
         lines.extend(r for _, r in sorted(rows, reverse=True))
         return "\n".join(lines)
     if kind == "sq":
+        # optional second dir: a kernel trace of the same command, for the
+        # VALU busy fraction = SQ_ACTIVE_INST_VALU * 4 / (1024 SIMDs *
+        # duration * 2.4 GHz) (the counter adds cycles over the SIMDs of the
+        # chip; 4 cycles per wave64 VALU issue)
         by = collections.defaultdict(lambda: collections.defaultdict(list))
         for r in _csv_rows(dirs[0], "_counter_collection.csv"):
             by[_short_kernel(r["Kernel_Name"])][r["Counter_Name"]].append(
                 float(r["Counter_Value"]))
+        dur = collections.defaultdict(list)
+        if len(dirs) > 1:
+            for r in _csv_rows(dirs[1], "_kernel_trace.csv"):
+                dur[_short_kernel(r["Kernel_Name"])].append(
+                    (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
         names = sorted({c for v in by.values() for c in v})
         lines.append("median per dispatch")
         for k, cs in sorted(by.items(), key=lambda kv: -np.median(
@@ -210,6 +219,14 @@ def profile_summary(kind, dirs):
             for c in names:
                 if c in cs:
                     lines.append(f"    {c:24s} {np.median(cs[c]):16.0f}")
+            if dur.get(k) and "SQ_ACTIVE_INST_VALU" in cs:
+                t = float(np.median(dur[k]))
+                busy = np.median(cs["SQ_ACTIVE_INST_VALU"]) * 4 / (1024 * t * 2.4e9)
+                lines.append(f"    {'duration_us':24s} {t * 1e6:16.1f}")
+                lines.append(f"    {'valu_busy':24s} {busy:16.3f}")
+            if "SQ_INSTS_LDS" in cs and "SQ_INSTS_VALU" in cs:
+                lines.append(f"    {'lds_per_valu':24s} "
+                             f"{np.median(cs['SQ_INSTS_LDS']) / np.median(cs['SQ_INSTS_VALU']):16.3f}")
         return "\n".join(lines)
     raise SystemExit(f"unknown summary kind {kind}")
 
