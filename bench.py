@@ -72,10 +72,10 @@ CSRC = os.path.join(ROOT, "paper_2410_00486_amd", "csrc")
 # kernel-name prefix -> the source files its code comes from
 KERNEL_SOURCES = {
     "k_preprocess": ["preprocess.hip", "gs_internal.h"],
-    "k_scan": ["binsort.hip", "tilesort.h", "gs_internal.h"],
-    "k_scatter": ["binsort.hip", "tilesort.h", "gs_internal.h"],
-    "k_tile_sort": ["binsort.hip", "tilesort.h", "gs_internal.h"],
-    "k_bin_": ["binsort.hip", "tilesort.h", "gs_internal.h"],
+    "k_scan": ["binsort.hip", "wavescan.h", "tilesort.h", "gs_internal.h"],
+    "k_scatter": ["binsort.hip", "wavescan.h", "tilesort.h", "gs_internal.h"],
+    "k_tile_sort": ["binsort.hip", "wavescan.h", "tilesort.h", "gs_internal.h"],
+    "k_rb_": ["binradix.hip", "wavescan.h", "tilesort.h", "gs_internal.h"],
     "k_render": ["render.hip", "tilesort.h", "gs_internal.h"],
     "k_project_bwd": ["project_bwd.hip", "gs_internal.h"],
     "k_adam": ["adam.hip", "gs_internal.h"],
@@ -87,7 +87,11 @@ def source_hashes(files=None) -> dict:
     files = files or sorted({f for v in KERNEL_SOURCES.values() for f in v})
     out = {}
     for f in files:
-        with open(os.path.join(CSRC, f), "rb") as fh:
+        path = os.path.join(CSRC, f)
+        if not os.path.exists(path):
+            out[f] = "absent"
+            continue
+        with open(path, "rb") as fh:
             out[f] = hashlib.sha1(fh.read()).hexdigest()
     return out
 
@@ -411,7 +415,11 @@ def bench_batched(args, dev, workload, search=False, marks=True, scheduled=False
                 "backward": args.bwd}
     tile = tuple(int(x) for x in best["tile"].split("x"))
     cap0 = gsr.required_pairs(*params.tensors(), cams, view_wh, 3, tile)
-    flags = L.GS_FUSED_L1 | L.GS_PERSISTENT | (L.GS_SPLAT_BWD if best["backward"] == "splat" else 0)
+    binning = best.get("binning", args.binning)
+    radix = L.GS_RADIX_BIN if binning == "radix" else 0
+    best["binning"] = binning
+    flags = (L.GS_FUSED_L1 | L.GS_PERSISTENT | radix |
+             (L.GS_SPLAT_BWD if best["backward"] == "splat" else 0))
     plan = gsr.Plan(w.scene.n, 3, view_wh, tile=tile, flags=flags, chunk=best["chunk"],
                     lds_batch=best["lds_batch"], pair_capacity=int(cap0 * 1.3) + 4096)
     it = gsr.Iteration(plan, params, cams, target_rgb=target_rgb, target_depth=target_depth,
@@ -463,7 +471,8 @@ def bench_batched(args, dev, workload, search=False, marks=True, scheduled=False
         cv = cams[v:v + 1].contiguous()
         capv = gsr.required_pairs(*params.tensors(), cv, [view_wh[v]], 3, tile)
         pv = gsr.Plan(w.scene.n, 3, [view_wh[v]], tile=tile, lds_batch=best["lds_batch"],
-                      flags=L.GS_FUSED_L1 | L.GS_ACCUMULATE_GRADS | (flags & L.GS_SPLAT_BWD),
+                      flags=L.GS_FUSED_L1 | L.GS_ACCUMULATE_GRADS |
+                      (flags & (L.GS_SPLAT_BWD | L.GS_RADIX_BIN)),
                       pair_capacity=int(capv * 1.3) + 4096)
         off, npx = plan.pixel_offsets[v], view_wh[v][0] * view_wh[v][1]
         per_view.append((pv, pv.new_workspace(dev), cv, gsr.Frame(pv, dev),
@@ -762,6 +771,8 @@ def main():
     ap.add_argument("--lds-batch", type=int, default=64)
     ap.add_argument("--chunk", type=int, default=1)
     ap.add_argument("--bwd", default="splat", choices=["pixel", "splat"])
+    ap.add_argument("--binning", default="tiles", choices=["tiles", "radix"],
+                    help="tile binning: per-tile slot claims and sorts, or the two radix sorts")
     ap.add_argument("--order", default="generated", choices=["generated", "spatial"],
                     help="layout of the batched workloads' pools: as generated (random "
                          "order) or sorted by the Morton code of the means")
@@ -824,6 +835,7 @@ def main():
                                "whole-iteration HIP graph",
                    "tile": f"{tile[0]}x{tile[1]}", "lds_batch": head["config"]["lds_batch"],
                    "chunk": head["config"]["chunk"], "persistent": True,
+                   "binning": head["config"]["binning"],
                    "backward": head["config"]["backward"]},
         "trials": args.trials,
         "timing": "median over trials of HIP events around --steps graph replays",

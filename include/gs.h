@@ -75,6 +75,13 @@ typedef int32_t gs_status;
                                          at every 64th splat of a tile; the backward
                                          gives each lane one splat of a 64-splat bucket
                                          and streams pixel states across the lanes */
+#define GS_RADIX_BIN (1u << 5)        /* gs_bin_sort by two stable radix sorts (the
+                                         visible records by depth, then their pairs,
+                                         generated in depth order, by tile id) instead
+                                         of per-tile slot claims and per-tile sorts;
+                                         same lists, bit for bit.  Needs about
+                                         16 B per record and 16 B per pair of
+                                         capacity more workspace */
 
 /* Gaussian parameters (Sec. III-B): SoA, float32, device pointers. */
 typedef struct gs_gaussians {
@@ -475,9 +482,12 @@ gs_status gs_graph_time(gs_graph* graph, void* stream, int32_t warmup, int32_t r
 #define GS_MARK_START 0
 #define GS_MARK_PREPROCESS 1       /* after the counter clear and the projection */
 #define GS_MARK_BIN_SCAN 2         /* after the binning's scans */
-#define GS_MARK_BIN_SCATTER 3      /* after the pair scatter */
+#define GS_MARK_BIN_SCATTER 3      /* after the pair scatter (GS_RADIX_BIN: after the
+                                      depth sort of the records and the pair
+                                      generation) */
 #define GS_MARK_BIN_SHORT_SORT 4   /* after the per-tile sorts of short lists */
-#define GS_MARK_BIN_LONG_SORT 5    /* after the long-list sorts */
+#define GS_MARK_BIN_LONG_SORT 5    /* after the long-list sorts (GS_RADIX_BIN: after
+                                      the tile-id passes) */
 #define GS_MARK_FORWARD 6          /* after compositing (and the L1 loss sums) */
 #define GS_MARK_LOSS 7             /* after the SSIM loss kernels */
 #define GS_MARK_RASTER_BWD 8       /* after the raster backward */

@@ -25,6 +25,7 @@ GS_FUSED_L1 = 1 << 1
 GS_ACCUMULATE_GRADS = 1 << 2
 GS_PERSISTENT = 1 << 3
 GS_SPLAT_BWD = 1 << 4
+GS_RADIX_BIN = 1 << 5
 
 GS_WS_RECORDS = 0
 GS_WS_RECTS = 1

@@ -18,6 +18,9 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_sh
                            const StepAdvance* step = nullptr, const Marks* marks = nullptr);
 TileSortArgs tile_sort_args(const Plan& P, void* ws);
 int64_t scan_rounds(const Plan& P);
+int64_t rb_blocks(int64_t count);
+int64_t rb_gen_blocks(int64_t records);
+int rb_max_radix();
 hipError_t launch_radix_sort(uint64_t* keys0, uint64_t* keys1, uint32_t* vals0, uint32_t* vals1,
                              const int32_t* cnt, uint32_t* hist, uint32_t* digit_tot,
                              int64_t nb_cap, int key_bits, bool iota, int* which, hipStream_t s);
@@ -236,6 +239,8 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_grad_pair = take(cap * kPairGrad * 4);
   P->off_pose_part = take((size_t)n_views * std::max<int64_t>(P->proj_blocks, 1) * 6 * 8);
   P->off_order = take(T * 4);
+  P->off_rec_terms = take(n_views > 1 ? nrec * 14 * 8 : 0);
+  P->off_gp_tmp = take(n_views > 1 ? (size_t)n * 3 * 8 : 0);
   P->off_ssim_maps = take((size_t)pix * 9 * 4);
   P->off_ssim_part = take((size_t)ssim_tiles(*P) * 12 * 4);
   // splat-wise backward: bucket k of tile t uses checkpoint slot boff[t] + k,
@@ -250,6 +255,21 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_ckpt = take((size_t)P->ckpt_slots * tw * th * kStateFloats * 4);
   P->scan_rounds = scan_rounds(*P);
   P->off_scan_part = take((size_t)P->scan_rounds * 64);
+  // radix binning buffers, only when the plan asks for that binning
+  const bool radix = (cfg->flags & GS_RADIX_BIN) != 0;
+  P->rb_rec_blocks = radix ? rb_blocks(P->n_rec) : 0;
+  P->rb_pair_blocks = radix ? rb_blocks(pair_capacity) : 0;
+  const size_t rrec = radix ? nrec * 4 : 0, rpair = radix ? cap * 4 : 0;
+  for (int k = 0; k < 2; ++k) {
+    P->off_rb_dkey[k] = take(rrec);
+    P->off_rb_rid[k] = take(rrec);
+    P->off_rb_tkey[k] = take(rpair);
+    P->off_rb_gidx[k] = take(rpair);
+  }
+  P->off_rb_hist = take(radix ? (size_t)rb_max_radix() * 4 *
+                                    std::max(P->rb_rec_blocks, P->rb_pair_blocks) : 0);
+  P->off_rb_dtot = take(radix ? (size_t)rb_max_radix() * 4 : 0);
+  P->off_rb_part = take(radix ? (size_t)rb_gen_blocks(P->n_rec) * 4 : 0);
   P->ws_size = o;
   P->magic = kPlanMagic;
   return GS_OK;

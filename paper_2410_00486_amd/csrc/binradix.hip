@@ -1,0 +1,512 @@
+// a2, second form (GS_RADIX_BIN): tile binning by two stable radix sorts,
+// with no per-tile atomics and no per-tile sorts.
+//
+// The lists must be ordered by (tile, depth, generation index) (Sec.
+// III-C-1: per-tile lists in depth order).  A record meets a tile at most
+// once, and its pairs carry consecutive generation indices that grow with
+// the record index, so the order within a tile is also (depth, record
+// index).  Hence:
+//   1. the visible records are listed in record order with their depth
+//      bits as keys (positive floats: the bits order like the values);
+//   2. a stable LSD radix sort orders them by depth (ties keep record
+//      order);
+//   3. their pairs are generated in that order (a scan of the pair counts
+//      gives each record its first slot), key = global tile id, value =
+//      generation index; the pair -> record table is written on the way;
+//   4. a stable LSD radix sort by tile id (only the bits the plan's tile
+//      count needs) then leaves every tile's pairs contiguous, in depth
+//      order, at exactly the list starts the binning scan computed; its
+//      last pass writes the sorted outputs (keys, values, record ids and
+//      the records in list order) directly.
+// Every pass is an upsweep (per-block digit counts), a per-digit scan over
+// the blocks and a downsweep that ranks a block's keys (stable: wave64
+// ballots, in index order), reorders them in LDS and writes each digit's
+// run contiguously.  Counts are read on the device (flags), grids are sized
+// for the plan's capacities; graph-capturable, no spin-waits.
+#include "tilesort.h"
+#include "wavescan.h"
+
+namespace gs {
+namespace {
+
+constexpr int kRbThreads = 256;
+constexpr int kRbItems = 16;
+constexpr int kRbTile = kRbThreads * kRbItems;  // keys per block
+constexpr int kRbWaves = kRbThreads / kWave;
+constexpr int kRbMaxBits = 8;
+constexpr int kRbMaxRadix = 1 << kRbMaxBits;
+// depth-sorted records per block of the pair generation (4 per thread)
+constexpr int kGenRecs = 1024;
+constexpr int kGenPer = kGenRecs / kRbThreads;
+
+static_assert(kRbThreads == kRbMaxRadix, "one thread per digit in the block scans");
+
+// Number of keys a pass sorts: a flag of the workspace, zero after a pair
+// overflow (then nothing is generated or written).
+__device__ __forceinline__ int64_t rb_count(const int32_t* fl, int which) {
+  return fl[F_OVERFLOW] ? 0 : (int64_t)fl[which];
+}
+
+// Lanes of the wavefront whose digit equals this lane's (among `valid`
+// lanes), from one ballot per digit bit.
+__device__ __forceinline__ uint64_t rb_peers(uint32_t d, bool valid, int bits) {
+  uint64_t peers = ballot64(valid);
+  for (int b = 0; b < bits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bb = ballot64(bit);
+    peers &= bit ? bb : ~bb;
+  }
+  return peers;
+}
+
+// Exclusive scan over the block's 256 threads of one value each; every
+// thread of the block must call.  ws: kRbWaves words of LDS.
+__device__ __forceinline__ uint32_t rb_block_exscan(uint32_t x, uint32_t* ws) {
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const uint32_t incl = scan_dpp<6>(x);
+  if (lane == kWave - 1) ws[w] = incl;
+  __syncthreads();
+  uint32_t off = 0;
+  for (int k = 0; k < w; ++k) off += ws[k];
+  __syncthreads();  // ws is reused by the caller's next scan
+  return off + incl - x;
+}
+
+// 1. Visible records in record order: pair offset (first generation index),
+// visible-list entry and depth key.  One wavefront per chunk of 64
+// Gaussians of a view, at the positions the binning scan gave the chunk.
+__global__ void __launch_bounds__(256) k_rb_visible(
+    const uint32_t* __restrict__ tt, uint32_t* __restrict__ poff,
+    const uint2* __restrict__ chunk_pre, int64_t chunks_per_view, int64_t n_chunks,
+    const Rec* __restrict__ rec, int64_t n, const int32_t* __restrict__ fl,
+    uint32_t* __restrict__ vis_list, uint32_t* __restrict__ dkey) {
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t gw = (int64_t)blockIdx.x * (256 / kWave) + w;  // chunk
+  if (gw >= n_chunks) return;
+  const int v = (int)(gw / chunks_per_view);
+  const int64_t gi = (gw - (int64_t)v * chunks_per_view) * kWave + lane;
+  const int64_t ri = (int64_t)v * n + gi;
+  const bool over = fl[F_OVERFLOW] != 0;
+  const uint32_t c = (gi < n && !over) ? tt[ri] : 0u;
+  float z = 0.0f;
+  if (c > 0) z = rec[ri].z;
+  const uint32_t incl = scan_dpp<6>(c);
+  const uint2 cp = chunk_pre[gw];
+  const uint64_t vmask = ballot64(c > 0);
+  if (c > 0) {
+    poff[ri] = cp.x + (incl - c);
+    const uint32_t vp = cp.y + (uint32_t)__popcll(vmask & lanemask_lt());
+    vis_list[vp] = (uint32_t)ri;
+    dkey[vp] = __float_as_uint(z);
+  }
+}
+
+// Upsweep: per-block counts of the digit (key >> shift) & (2^bits - 1),
+// stored digit-major: hist[d * nb_cap + block].
+__global__ void __launch_bounds__(kRbThreads) k_rb_hist(const uint32_t* __restrict__ keys,
+                                                        const int32_t* __restrict__ fl, int which,
+                                                        uint32_t* __restrict__ hist,
+                                                        int64_t nb_cap, int shift, int bits) {
+  const int64_t cnt = rb_count(fl, which);
+  const int64_t base = (int64_t)blockIdx.x * kRbTile;
+  if (base >= cnt) return;
+  __shared__ uint32_t h[kRbWaves][kRbMaxRadix];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  for (int k = threadIdx.x; k < kRbWaves * kRbMaxRadix; k += kRbThreads) (&h[0][0])[k] = 0u;
+  __syncthreads();
+  const uint32_t mask = (1u << bits) - 1u;
+  const uint64_t lt = lanemask_lt();
+#pragma unroll 4
+  for (int r = 0; r < kRbItems; ++r) {
+    const int64_t idx = base + (int64_t)w * (kWave * kRbItems) + r * kWave + lane;
+    const bool valid = idx < cnt;
+    const uint32_t d = valid ? (keys[idx] >> shift) & mask : 0u;
+    const uint64_t peers = rb_peers(d, valid, bits);
+    // one lane per distinct digit adds the digit's lanes (no two lanes of a
+    // wavefront touch the same word; each wavefront has its own row)
+    if (valid && (peers & lt) == 0) h[w][d] += (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  const int d = threadIdx.x;
+  if (d <= (int)mask) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kRbWaves; ++k) s += h[k][d];
+    hist[(int64_t)d * nb_cap + blockIdx.x] = s;
+  }
+}
+
+// One block per digit: exclusive scan of the digit's counts over the active
+// blocks (in place); the digit's total to dtot.
+__global__ void __launch_bounds__(kRbThreads) k_rb_digit_scan(uint32_t* __restrict__ hist,
+                                                              const int32_t* __restrict__ fl,
+                                                              int which,
+                                                              uint32_t* __restrict__ dtot,
+                                                              int64_t nb_cap) {
+  const int64_t cnt = rb_count(fl, which);
+  const int64_t nb = (cnt + kRbTile - 1) / kRbTile;
+  uint32_t* row = hist + (int64_t)blockIdx.x * nb_cap;
+  __shared__ uint32_t ws[kRbWaves];
+  __shared__ uint32_t tot;
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += kRbThreads) {
+    const int64_t b = b0 + threadIdx.x;
+    const uint32_t x = b < nb ? row[b] : 0u;
+    const uint32_t ex = rb_block_exscan(x, ws);
+    if (b < nb) row[b] = carry + ex;
+    if (threadIdx.x == kRbThreads - 1) tot = ex + x;
+    __syncthreads();
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
+}
+
+// Outputs of the last tile pass: the sorted lists.
+struct RbEmit {
+  uint64_t* keys;          // tile << 32 | depth bits
+  uint32_t* vals;          // generation index
+  uint32_t* sorted_rec;    // record id
+  const uint32_t* pair_rec;
+  const Rec* rec;
+  Rec* lrec;               // records in list order
+};
+
+// Downsweep: stable ranking of the block's keys by digit, reorder in LDS,
+// then each digit's run written contiguously at the digit's global offset
+// (digit totals scanned over digits + the block's offset within the digit).
+// EMIT: the last pass of the tile sort (keys are tile ids, values
+// generation indices): writes the sorted lists instead of keys / values.
+template <bool EMIT>
+__global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, RbEmit E,
+    const int32_t* __restrict__ fl, int which, const uint32_t* __restrict__ hist,
+    const uint32_t* __restrict__ dtot, int64_t nb_cap, int shift, int bits) {
+  const int64_t cnt = rb_count(fl, which);
+  const int64_t base = (int64_t)blockIdx.x * kRbTile;
+  if (base >= cnt) return;
+  __shared__ uint32_t wcnt[kRbWaves][kRbMaxRadix];
+  __shared__ uint32_t lstart[kRbMaxRadix];
+  __shared__ uint32_t gofs[kRbMaxRadix];
+  __shared__ uint32_t ws[kRbWaves];
+  __shared__ uint32_t sk[kRbTile], sv[kRbTile];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int d_own = threadIdx.x;  // the digit this thread handles in the block scans
+  const uint32_t mask = (1u << bits) - 1u;
+  for (int k = threadIdx.x; k < kRbWaves * kRbMaxRadix; k += kRbThreads) (&wcnt[0][0])[k] = 0u;
+  {
+    const uint32_t x = d_own <= (int)mask ? dtot[d_own] : 0u;
+    const uint32_t ex = rb_block_exscan(x, ws);  // (its barrier also orders the clear)
+    if (d_own <= (int)mask) gofs[d_own] = ex + hist[(int64_t)d_own * nb_cap + blockIdx.x];
+  }
+  uint32_t key[kRbItems], val[kRbItems], rank[kRbItems];
+  const uint64_t lt = lanemask_lt();
+#pragma unroll
+  for (int r = 0; r < kRbItems; ++r) {
+    const int64_t idx = base + (int64_t)w * (kWave * kRbItems) + r * kWave + lane;
+    const bool valid = idx < cnt;
+    key[r] = valid ? keys_in[idx] : 0u;
+    val[r] = valid ? vals_in[idx] : 0u;
+    const uint32_t d = (key[r] >> shift) & mask;
+    const uint64_t peers = rb_peers(d, valid, bits);
+    const uint64_t below = peers & lt;
+    uint32_t old = 0;
+    if (valid) old = wcnt[w][d];
+    if (valid && below == 0) wcnt[w][d] = old + (uint32_t)__popcll(peers);
+    rank[r] = valid ? old + (uint32_t)__popcll(below) : 0xFFFFFFFFu;
+  }
+  __syncthreads();
+  {
+    // per digit: exclusive prefix over the waves, then the block-local
+    // start of the digit's run
+    uint32_t tot = 0;
+    if (d_own <= (int)mask) {
+#pragma unroll
+      for (int k = 0; k < kRbWaves; ++k) {
+        const uint32_t c = wcnt[k][d_own];
+        wcnt[k][d_own] = tot;
+        tot += c;
+      }
+    }
+    const uint32_t ex = rb_block_exscan(tot, ws);
+    if (d_own <= (int)mask) lstart[d_own] = ex;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRbItems; ++r) {
+    if (rank[r] != 0xFFFFFFFFu) {
+      const uint32_t d = (key[r] >> shift) & mask;
+      const uint32_t lp = lstart[d] + wcnt[w][d] + rank[r];
+      sk[lp] = key[r];
+      sv[lp] = val[r];
+    }
+  }
+  __syncthreads();
+  const int nloc = (int)((cnt - base) < kRbTile ? (cnt - base) : kRbTile);
+  if (!EMIT) {
+    for (int i = threadIdx.x; i < nloc; i += kRbThreads) {
+      const uint32_t k = sk[i];
+      const uint32_t d = (k >> shift) & mask;
+      const uint32_t pos = gofs[d] + (uint32_t)i - lstart[d];
+      keys_out[pos] = k;
+      vals_out[pos] = sv[i];
+    }
+  } else {
+    // record ids of all of the thread's positions first (one round trip),
+    // then the record copies, four records in flight at a time
+    uint32_t rid[kRbItems];
+#pragma unroll
+    for (int q = 0; q < kRbItems; ++q) {
+      const int i = threadIdx.x + q * kRbThreads;
+      rid[q] = i < nloc ? E.pair_rec[sv[i]] : 0u;
+    }
+    constexpr int G = 4;
+#pragma unroll
+    for (int q0 = 0; q0 < kRbItems; q0 += G) {
+      float4 a[G][4];
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int i = threadIdx.x + (q0 + u) * kRbThreads;
+        if (i < nloc) {
+          const float4* src = reinterpret_cast<const float4*>(E.rec + rid[q0 + u]);
+          a[u][0] = src[0]; a[u][1] = src[1]; a[u][2] = src[2]; a[u][3] = src[3];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int i = threadIdx.x + (q0 + u) * kRbThreads;
+        if (i < nloc) {
+          const uint32_t t = sk[i];
+          const uint32_t d = (t >> shift) & mask;
+          const uint32_t pos = gofs[d] + (uint32_t)i - lstart[d];
+          float4* dst = reinterpret_cast<float4*>(E.lrec + pos);
+          dst[0] = a[u][0]; dst[1] = a[u][1]; dst[2] = a[u][2]; dst[3] = a[u][3];
+          E.keys[pos] = ((uint64_t)t << 32) | __float_as_uint(a[u][2].w);  // .w of the third: depth
+          E.vals[pos] = sv[i];
+          E.sorted_rec[pos] = rid[q0 + u];
+        }
+      }
+    }
+  }
+}
+
+// 3a. Pairs of each block of kGenRecs depth-sorted records.
+__global__ void __launch_bounds__(kRbThreads) k_rb_gen_count(const uint32_t* __restrict__ rid,
+                                                             const uint32_t* __restrict__ tt,
+                                                             const int32_t* __restrict__ fl,
+                                                             uint32_t* __restrict__ part) {
+  const int64_t V = rb_count(fl, F_VISIBLE);
+  const int64_t base = (int64_t)blockIdx.x * kGenRecs;
+  if (base >= V) return;
+  __shared__ uint32_t ws[kRbWaves];
+  uint32_t s = 0;
+#pragma unroll
+  for (int q = 0; q < kGenPer; ++q) {
+    const int64_t j = base + q * kRbThreads + threadIdx.x;
+    if (j < V) s += tt[rid[j]];
+  }
+  s = scan_dpp<6>(s);
+  if (lane_id() == kWave - 1) ws[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < kRbWaves; ++k) t += ws[k];
+    part[blockIdx.x] = t;
+  }
+}
+
+// 3b. One block: exclusive scan of the block pair counts (in place).
+__global__ void __launch_bounds__(kRbThreads) k_rb_gen_scan(const int32_t* __restrict__ fl,
+                                                            uint32_t* __restrict__ part) {
+  const int64_t V = rb_count(fl, F_VISIBLE);
+  const int64_t nb = (V + kGenRecs - 1) / kGenRecs;
+  __shared__ uint32_t ws[kRbWaves];
+  __shared__ uint32_t tot;
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += kRbThreads) {
+    const int64_t b = b0 + threadIdx.x;
+    const uint32_t x = b < nb ? part[b] : 0u;
+    const uint32_t ex = rb_block_exscan(x, ws);
+    if (b < nb) part[b] = carry + ex;
+    if (threadIdx.x == kRbThreads - 1) tot = ex + x;
+    __syncthreads();
+    carry += tot;
+    __syncthreads();
+  }
+}
+
+// 3c. Pair generation in depth order: the block's records (4 consecutive
+// per thread) get their first slots from a block scan plus the block's
+// offset; the block's pairs are then spread evenly over the threads (each
+// finds its record by binary search of the slots in LDS), so one large
+// footprint does not serialise on one thread.  Writes the tile key and the
+// generation index of every pair, and pair -> record.
+__global__ void __launch_bounds__(kRbThreads) k_rb_generate(
+    const uint32_t* __restrict__ rid, const uint32_t* __restrict__ tt,
+    const uint32_t* __restrict__ poff, const ushort4* __restrict__ rect, int64_t n, ViewTable vt,
+    const int32_t* __restrict__ fl, const uint32_t* __restrict__ part,
+    uint32_t* __restrict__ tkey, uint32_t* __restrict__ gidx, uint32_t* __restrict__ pair_rec) {
+  const int64_t V = rb_count(fl, F_VISIBLE);
+  const int64_t base = (int64_t)blockIdx.x * kGenRecs;
+  if (base >= V) return;
+  __shared__ uint32_t s_pre[kGenRecs], s_p0[kGenRecs], s_t0[kGenRecs], s_rid[kGenRecs];
+  __shared__ uint32_t s_bw[kGenRecs], s_tx[kGenRecs];
+  __shared__ uint32_t ws[kRbWaves];
+  __shared__ uint32_t s_total;
+  uint32_t c[kGenPer], sum = 0;
+#pragma unroll
+  for (int q = 0; q < kGenPer; ++q) {
+    const int64_t j = base + (int64_t)threadIdx.x * kGenPer + q;
+    const int l = threadIdx.x * kGenPer + q;
+    c[q] = 0u;
+    if (j < V) {
+      const uint32_t r = rid[j];
+      const ushort4 b = rect[r];
+      const int v = (int)(r / (uint64_t)n);
+      const ViewInfo& vi = vt.v[v];
+      c[q] = tt[r];
+      s_rid[l] = r;
+      s_p0[l] = poff[r];
+      s_bw[l] = (uint32_t)(b.z - b.x);
+      s_tx[l] = (uint32_t)vi.tiles_x;
+      s_t0[l] = (uint32_t)(vi.tile_off + (int)b.y * vi.tiles_x + (int)b.x);
+    }
+    sum += c[q];
+  }
+  uint32_t run = rb_block_exscan(sum, ws);
+#pragma unroll
+  for (int q = 0; q < kGenPer; ++q) {
+    // records past the end keep the block total: never chosen below
+    s_pre[threadIdx.x * kGenPer + q] = run;
+    run += c[q];
+  }
+  if (threadIdx.x == kRbThreads - 1) s_total = run;
+  __syncthreads();
+  const uint32_t total = s_total;
+  const uint32_t q0 = part[blockIdx.x];
+  for (uint32_t q = threadIdx.x; q < total; q += kRbThreads) {
+    // owner: the last record whose first slot is <= q (every record here
+    // has at least one pair, so the slots strictly increase)
+    int lo = 0, hi = kGenRecs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_pre[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t k = q - s_pre[lo];
+    const uint32_t bw = s_bw[lo];
+    const uint32_t row = k / bw;
+    const uint32_t t = s_t0[lo] + row * s_tx[lo] + (k - row * bw);
+    const uint32_t g = s_p0[lo] + k;
+    tkey[q0 + q] = t;
+    gidx[q0 + q] = g;
+    pair_rec[g] = s_rid[lo];
+  }
+}
+
+}  // namespace
+
+namespace {
+
+struct RbBuffers {
+  const int32_t* fl;
+  uint32_t *tt, *poff, *vis, *dk[2], *rid[2], *tk[2], *gx[2], *hist, *dtot, *part, *pair_rec;
+  RbEmit emit;
+};
+
+RbBuffers rb_buffers(const Plan& P, void* ws) {
+  RbBuffers B;
+  B.fl = ws_at<int32_t>(ws, P.off_flags);
+  B.tt = ws_at<uint32_t>(ws, P.off_tt);
+  B.poff = ws_at<uint32_t>(ws, P.off_poff);
+  B.vis = ws_at<uint32_t>(ws, P.off_vis_list);
+  for (int k = 0; k < 2; ++k) {
+    B.dk[k] = ws_at<uint32_t>(ws, P.off_rb_dkey[k]);
+    B.rid[k] = ws_at<uint32_t>(ws, P.off_rb_rid[k]);
+    B.tk[k] = ws_at<uint32_t>(ws, P.off_rb_tkey[k]);
+    B.gx[k] = ws_at<uint32_t>(ws, P.off_rb_gidx[k]);
+  }
+  B.hist = ws_at<uint32_t>(ws, P.off_rb_hist);
+  B.dtot = ws_at<uint32_t>(ws, P.off_rb_dtot);
+  B.part = ws_at<uint32_t>(ws, P.off_rb_part);
+  B.pair_rec = ws_at<uint32_t>(ws, P.off_pair_rec);
+  B.emit = RbEmit{ws_at<uint64_t>(ws, P.off_keys), ws_at<uint32_t>(ws, P.off_vals),
+                  ws_at<uint32_t>(ws, P.off_sorted_rec), B.pair_rec, ws_at<Rec>(ws, P.off_rec),
+                  ws_at<Rec>(ws, P.off_srec)};
+  return B;
+}
+
+// One stable pass over the keys counted by flag `which`.
+void rb_pass(const RbBuffers& B, hipStream_t s, const uint32_t* kin, const uint32_t* vin,
+             uint32_t* kout, uint32_t* vout, bool emit, int which, int64_t nb_cap, int shift,
+             int bits) {
+  const dim3 grid((unsigned)nb_cap), block(kRbThreads);
+  hipLaunchKernelGGL(k_rb_hist, grid, block, 0, s, kin, B.fl, which, B.hist, nb_cap, shift, bits);
+  hipLaunchKernelGGL(k_rb_digit_scan, dim3(1u << bits), block, 0, s, B.hist, B.fl, which, B.dtot,
+                     nb_cap);
+  if (emit) {
+    hipLaunchKernelGGL(k_rb_scatter<true>, grid, block, 0, s, kin, vin, kout, vout, B.emit, B.fl,
+                       which, B.hist, B.dtot, nb_cap, shift, bits);
+  } else {
+    hipLaunchKernelGGL(k_rb_scatter<false>, grid, block, 0, s, kin, vin, kout, vout, RbEmit{},
+                       B.fl, which, B.hist, B.dtot, nb_cap, shift, bits);
+  }
+}
+
+}  // namespace
+
+// Workspace blocks of the radix binning: (record blocks, pair blocks, gen
+// blocks) for a plan's record and pair capacities.
+int64_t rb_blocks(int64_t count) { return (count + kRbTile - 1) / kRbTile; }
+int64_t rb_gen_blocks(int64_t records) { return (records + kGenRecs - 1) / kGenRecs; }
+int rb_max_radix() { return kRbMaxRadix; }
+
+// Steps 1-3 of the radix binning (after the binning scan, which kept the
+// per-tile counters): visible records, their depth sort, pair generation.
+hipError_t launch_rb_generate(const Plan& P, void* ws, hipStream_t s) {
+  const RbBuffers B = rb_buffers(P, ws);
+  if (P.n_chunks <= 0 || P.rb_rec_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rb_visible, dim3((unsigned)((P.n_chunks + 3) / 4)), dim3(256), 0, s, B.tt,
+                     B.poff, ws_at<uint2>(ws, P.off_chunk_pre), P.chunks_per_view, P.n_chunks,
+                     ws_at<Rec>(ws, P.off_rec), P.n, B.fl, B.vis, B.dk[0]);
+  // depth bits in four 8-bit passes; values: record ids (the visible list
+  // feeds the first pass and is left as it is)
+  // (dk0, vis) -> (dk1, rid1) -> (dk0, rid0) -> (dk1, rid1) -> (dk0, rid0)
+  for (int p = 0; p < 4; ++p) {
+    const uint32_t* kin = B.dk[p & 1];
+    const uint32_t* vin = p == 0 ? B.vis : B.rid[p & 1];
+    rb_pass(B, s, kin, vin, B.dk[(p + 1) & 1], B.rid[(p + 1) & 1], false, F_VISIBLE,
+            P.rb_rec_blocks, 8 * p, 8);
+  }
+  const int64_t gb = rb_gen_blocks(P.n_rec);
+  hipLaunchKernelGGL(k_rb_gen_count, dim3((unsigned)gb), dim3(kRbThreads), 0, s, B.rid[0], B.tt,
+                     B.fl, B.part);
+  hipLaunchKernelGGL(k_rb_gen_scan, dim3(1), dim3(kRbThreads), 0, s, B.fl, B.part);
+  hipLaunchKernelGGL(k_rb_generate, dim3((unsigned)gb), dim3(kRbThreads), 0, s, B.rid[0], B.tt,
+                     B.poff, ws_at<ushort4>(ws, P.off_rect), P.n, P.vt, B.fl, B.part, B.tk[0],
+                     B.gx[0], B.pair_rec);
+  return hipGetLastError();
+}
+
+// Step 4: the pairs by tile id, as many passes of at most 8 bits as the
+// plan's tile bits need (equal widths); the last writes the sorted lists.
+hipError_t launch_rb_tile_sort(const Plan& P, void* ws, hipStream_t s) {
+  const RbBuffers B = rb_buffers(P, ws);
+  if (P.rb_pair_blocks <= 0) return hipSuccess;
+  const int tb = P.tile_bits;
+  const int passes = (tb + kRbMaxBits - 1) / kRbMaxBits;
+  const int width = (tb + passes - 1) / passes;
+  int cur = 0;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * width;
+    const int bits = std::min(width, tb - shift);
+    const bool last = p == passes - 1;
+    rb_pass(B, s, B.tk[cur], B.gx[cur], last ? nullptr : B.tk[cur ^ 1],
+            last ? nullptr : B.gx[cur ^ 1], last, F_PAIRS, P.rb_pair_blocks, shift, bits);
+    cur ^= 1;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gs

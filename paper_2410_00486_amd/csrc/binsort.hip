@@ -19,6 +19,7 @@
 // radix sort (8-bit digits, wave64 ballot ranking) below serves the
 // standalone key/value sort.
 #include "tilesort.h"
+#include "wavescan.h"
 
 namespace gs {
 namespace {
@@ -71,6 +72,7 @@ struct ScanArgs {
   uint32_t* hstart;        // position of the tile's half bucket in queue 1
   uint32_t* order;         // work order of the render kernels, longest tiles first
   uint4* long_list;        // (tile, list start, pairs, -) of the lists for the long-list sort
+  int keep_counts;         // radix binning: the counters stay (no scatter cursors)
 };
 
 // Work order of the render kernels: tiles with at least kLongTile pairs
@@ -78,54 +80,6 @@ struct ScanArgs {
 // the long lists start in the first round of the dispatch and the tail is
 // made of short ones.  Both positions come out of the scan.
 constexpr uint32_t kLongTile = 32;
-
-// Inclusive wavefront scans with DPP (full-rate VALU, no LDS traffic): row
-// shifts by 1, 2, 4, 8 within each 16-lane row, then the last lane of row 0
-// and 2 into rows 1 and 3 (row_bcast:15) and of row 1 into rows 2 and 3
-// (row_bcast:31).  Lanes shifted in from outside a row add 0.
-template <int CTRL, int ROW_MASK = 0xF>
-__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xF, false);
-}
-template <int CTRL, int ROW_MASK = 0xF>
-__device__ __forceinline__ uint64_t dpp_u64(uint64_t x) {
-  const uint32_t lo = dpp_u32<CTRL, ROW_MASK>((uint32_t)x);
-  const uint32_t hi = dpp_u32<CTRL, ROW_MASK>((uint32_t)(x >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
-template <typename U, int STEP>
-__device__ __forceinline__ U dpp_step(U x) {
-  if constexpr (sizeof(U) == 8) {
-    if constexpr (STEP == 0) return dpp_u64<0x111>(x);
-    else if constexpr (STEP == 1) return dpp_u64<0x112>(x);
-    else if constexpr (STEP == 2) return dpp_u64<0x114>(x);
-    else if constexpr (STEP == 3) return dpp_u64<0x118>(x);
-    else if constexpr (STEP == 4) return dpp_u64<0x142, 0xA>(x);
-    else return dpp_u64<0x143, 0xC>(x);
-  } else {
-    if constexpr (STEP == 0) return dpp_u32<0x111>(x);
-    else if constexpr (STEP == 1) return dpp_u32<0x112>(x);
-    else if constexpr (STEP == 2) return dpp_u32<0x114>(x);
-    else if constexpr (STEP == 3) return dpp_u32<0x118>(x);
-    else if constexpr (STEP == 4) return dpp_u32<0x142, 0xA>(x);
-    else return dpp_u32<0x143, 0xC>(x);
-  }
-}
-
-// Inclusive scan over the first 16 lanes (STEPS = 4) or the whole
-// wavefront (STEPS = 6).
-template <int STEPS, typename U>
-__device__ __forceinline__ U scan_dpp(U x) {
-  x += dpp_step<U, 0>(x);
-  x += dpp_step<U, 1>(x);
-  x += dpp_step<U, 2>(x);
-  x += dpp_step<U, 3>(x);
-  if constexpr (STEPS > 4) {
-    x += dpp_step<U, 4>(x);
-    x += dpp_step<U, 5>(x);
-  }
-  return x;
-}
 
 // Block-wide exclusive scan of N64 64-bit and N32 32-bit per-thread sums
 // (replaced by the thread's start); the carries (uniform) are added and
@@ -283,7 +237,7 @@ __device__ __forceinline__ void scan_emit(const ScanArgs& A, ScanRound& R) {
       R.s32[4] += c > kTileSortSmall ? 1u : 0u;
     }
     store4(A.tstart, R.it + 4 * k, T, make_uint4(ts[0], ts[1], ts[2], ts[3]));
-    store4(A.cnt, R.it + 4 * k, T, make_uint4(0u, 0u, 0u, 0u));
+    if (!A.keep_counts) store4(A.cnt, R.it + 4 * k, T, make_uint4(0u, 0u, 0u, 0u));
     if (A.boff) {
       store4(A.boff, R.it + 4 * k, T, make_uint4(bs[0], bs[1], bs[2], bs[3]));
       store4(A.fstart, R.it + 4 * k, T,
@@ -806,6 +760,9 @@ hipError_t launch_radix_sort(uint64_t* keys0, uint64_t* keys1, uint32_t* vals0,
   return hipGetLastError();
 }
 
+hipError_t launch_rb_generate(const Plan& P, void* ws, hipStream_t s);
+hipError_t launch_rb_tile_sort(const Plan& P, void* ws, hipStream_t s);
+
 hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, p, v);
   return hipGetLastError();
@@ -838,7 +795,8 @@ TileSortArgs tile_sort_args(const Plan& P, void* ws) {
   A.hstart = splat ? ws_at<uint32_t>(ws, P.off_half_start) : nullptr;
   A.bq = splat ? ws_at<uint2>(ws, P.off_bq) : nullptr;
   A.bq_stride = P.ckpt_slots;
-  A.long_after = true;
+  A.presorted = (P.cfg.flags & GS_RADIX_BIN) != 0;
+  A.long_after = !A.presorted;
   return A;
 }
 
@@ -861,9 +819,10 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_sh
   const uint2* chunk_cnt = ws_at<uint2>(ws, P.off_chunk_cnt);
   uint2* chunk_pre = ws_at<uint2>(ws, P.off_chunk_pre);
   uint4* long_list = ws_at<uint4>(ws, P.off_long);
+  const bool radix = (P.cfg.flags & GS_RADIX_BIN) != 0;
   ScanArgs sa{chunk_cnt, chunk_pre, P.n_chunks, tcnt, tstart, (int64_t)T,
               splat ? ws_at<uint32_t>(ws, P.off_boff) : nullptr, fstart, hstart,
-              ws_at<uint32_t>(ws, P.off_order), long_list};
+              ws_at<uint32_t>(ws, P.off_order), long_list, radix ? 1 : 0};
   // always launched, so that the flags are always set: one block for a
   // plan of one round, one block per round in three launches beyond
   const StepAdvance adv = step ? *step : StepAdvance{};
@@ -880,6 +839,20 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_sh
   }
   hipError_t e = mk.at(GS_MARK_BIN_SCAN, s);
   if (e != hipSuccess) return e;
+  if (radix) {
+    // records by depth, their pairs in that order, then the pairs by tile;
+    // the per-tile pass (here, or the forward's when deferred) writes the
+    // ranges and queue entries and zeroes the counters
+    if ((e = launch_rb_generate(P, ws, s)) != hipSuccess) return e;
+    if ((e = mk.at(GS_MARK_BIN_SCATTER, s)) != hipSuccess) return e;
+    if (T > 0 && !defer_short_sorts) {
+      hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)T), dim3(kWave), 0, s, tile_sort_args(P, ws));
+    }
+    if ((e = mk.at(GS_MARK_BIN_SHORT_SORT, s)) != hipSuccess) return e;
+    if ((e = launch_rb_tile_sort(P, ws, s)) != hipSuccess) return e;
+    if ((e = mk.at(GS_MARK_BIN_LONG_SORT, s)) != hipSuccess) return e;
+    return hipGetLastError();
+  }
   uint64_t* skey = ws_at<uint64_t>(ws, P.off_scatter);
   uint32_t* pair_rec = ws_at<uint32_t>(ws, P.off_pair_rec);
   if (P.n_chunks > 0) {

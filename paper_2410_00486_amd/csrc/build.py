@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 SOURCES = ["api.hip", "preprocess.hip", "binsort.hip", "render.hip", "project_bwd.hip", "adam.hip",
-           "loss.hip", "densify.hip", "pose.hip", "gather.hip", "order.hip"]
+           "loss.hip", "densify.hip", "pose.hip", "gather.hip", "order.hip", "binradix.hip"]
 LIB = os.path.join(PKG, "libgs.so")
 BUILD = os.path.join(HERE, "_build")
 

@@ -89,6 +89,9 @@ struct Plan {
   size_t off_keys, off_scatter, off_vals, off_pair_rec, off_sorted_rec, off_srec;
   size_t off_ranges, off_tile_last, off_tile_loss;
   size_t off_grad_pair, off_pose_part, off_order;
+  // several views: per record, its projection-backward terms; per
+  // Gaussian, the projection half's mean gradient
+  size_t off_rec_terms, off_gp_tmp;
   size_t off_ssim_maps, off_ssim_part;
   // splat-wise backward: bucket offsets, bucket queues and their per-tile
   // positions, pixel states
@@ -98,6 +101,13 @@ struct Plan {
   // per-channel partial sums
   int64_t scan_rounds;
   size_t off_scan_part;
+  // radix binning (GS_RADIX_BIN): depth keys and record ids of the visible
+  // records (two buffers each), tile keys and generation indices of the
+  // pairs (two each), per-block digit counts, digit totals, and the pair
+  // offsets of blocks of depth-sorted records
+  size_t off_rb_dkey[2], off_rb_rid[2], off_rb_tkey[2], off_rb_gidx[2];
+  size_t off_rb_hist, off_rb_dtot, off_rb_part;
+  int64_t rb_rec_blocks, rb_pair_blocks;
   size_t ws_size;
 };
 static_assert(sizeof(Plan) <= sizeof(gs_plan), "plan does not fit gs_plan");

@@ -511,250 +511,149 @@ __global__ void __launch_bounds__((SPLIT && COMPACT) ? kSumWaves * kWave : kProj
   else run(F{}, T{});
 }
 
-// Several views, no camera tangent: the (view, Gaussian) records that have
-// pairs are spread over the lanes.  A workgroup takes 64 Gaussians in two
-// wavefronts (projection chain, colour chain); each wavefront lists the
-// records of its 64 Gaussians (Gaussian-major, views ascending) and runs
-// one record per lane, 64 at a time, so that no lane idles in a view where
-// its own Gaussian has no pairs.  Each record's terms go to LDS and the
-// owner lane adds its records' terms in view order: the same operations in
-// the same order as one thread looping over the views, so the gradients
-// are bit-identical to that form.
-constexpr int kMvItems = kMaxViews * kWave;  // records of 64 Gaussians at most
+// Several views, no camera tangent: two launches, each on full wavefronts
+// whatever the visibility pattern.
+//   k_project_rec: one thread per visible (view, Gaussian) record (the
+//     visible list): the record's pair partials summed in pair order, then
+//     that view's projection chain; the record's terms (mean and covariance
+//     parts, opacity), its summed colour partials and clamp bits go to the
+//     record's slot.
+//   k_project_gauss: one thread per Gaussian: its records' terms added in
+//     view order, the colour chain of each view (SH coefficients held in
+//     registers), then the covariance -> scale / rotation chain.
+// The operations and their order are those of one thread looping over the
+// views (projection sums, colour sums, then their total), so the gradients
+// do not depend on how the records are spread over threads.
+constexpr int kTermWords = 14;  // doubles per record slot (112 bytes)
+constexpr int kRecThreads = 256;
+constexpr int kGaussThreads = 128;
+
 template <int DEG>
-__global__ void __launch_bounds__(2 * kWave) k_project_bwd_mv(
+__global__ void __launch_bounds__(kRecThreads) k_project_rec(
     const float* __restrict__ means, const float* __restrict__ log_scales,
-    const float* __restrict__ quats, const float* __restrict__ logits,
-    const float* __restrict__ sh, int64_t n, const float* __restrict__ cams, ViewTable vt,
-    const Rec* __restrict__ recs, const uint32_t* __restrict__ tt, const uint32_t* __restrict__ poff,
-    const float* __restrict__ grad_pair, const int32_t* __restrict__ fl, int accumulate,
-    float* __restrict__ g_means, float* __restrict__ g_ls, float* __restrict__ g_q,
-    float* __restrict__ g_logit, float* __restrict__ g_sh) {
-  constexpr int K = (DEG + 1) * (DEG + 1), K3 = 3 * K;
-  const int lane = lane_id();
-  const int role = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-  const int64_t g0 = (int64_t)blockIdx.x * kWave;
-  const int64_t i = g0 + lane;
-  const bool valid = i < n;
-  const int64_t ic = valid ? i : 0;
-  const bool overflow = fl[F_OVERFLOW] != 0;
-  const int V = vt.n_views;
-
-  __shared__ uint16_t s_item[kMvItems];           // (lane << 6 | view) per record
-  __shared__ double s_lim[kMaxViews][2];          // FOV clamp limits per view
-  __shared__ float s_p[kWave][3];                 // means of the 64 Gaussians
-  __shared__ double s_S[kWave][6];                // world covariances (projection chain)
-  __shared__ float s_sh[kWave][K3];               // SH coefficients (colour chain)
-  __shared__ double s_out0[kWave][10];            // record terms, projection chain
-  __shared__ double s_gv[kWave][3];               // record terms, colour chain (mean part)
-  __shared__ float s_gsh[kWave][K3];              // record terms, colour chain (SH part)
-  __shared__ double s_hand[3][kWave];             // colour -> projection hand-over
-
-  // records with pairs of this lane's Gaussian: one bit per view
-  uint64_t mask = 0;
-  if (valid && !overflow) {
-    for (int v = 0; v < V; ++v)
-      if (tt[(int64_t)v * n + i] > 0u) mask |= 1ull << v;
-  }
-  const uint32_t cnt = (uint32_t)__popcll(mask);
-  uint32_t incl = cnt;
+    const float* __restrict__ quats, int64_t n, const float* __restrict__ cams, ViewTable vt,
+    const Rec* __restrict__ recs, const uint32_t* __restrict__ tt,
+    const uint32_t* __restrict__ poff, const float* __restrict__ grad_pair,
+    const int32_t* __restrict__ fl, const uint32_t* __restrict__ vis_list,
+    double* __restrict__ terms) {
+  const int64_t j = (int64_t)blockIdx.x * kRecThreads + threadIdx.x;
+  const int64_t nv = fl[F_OVERFLOW] ? 0 : (int64_t)fl[F_VISIBLE];
+  if (j >= nv) return;
+  const uint32_t ri = vis_list[j];
+  const int v = (int)(ri / (uint64_t)n);
+  const int64_t i = (int64_t)ri - (int64_t)v * n;
+  const uint32_t np = tt[ri];
+  const float4* gp4 = reinterpret_cast<const float4*>(grad_pair + (int64_t)poff[ri] * kPairGrad);
+  // fixed-order sums of the pair partials: colour 0..2, projection 3..9
+  double g2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  uint32_t q = 0;
+  for (; q + 4 <= np; q += 4) {
+    float4 a[4], b[4], c[4];
 #pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const uint32_t y = __shfl_up(incl, o, kWave);
-    if (lane >= o) incl += y;
-  }
-  const uint32_t start = incl - cnt;
-  const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
-  if (role == 0) {
-    uint32_t j = start;
-    for (uint64_t m = mask; m; m &= m - 1) s_item[j++] = (uint16_t)((lane << 6) | __builtin_ctzll(m));
-    for (int v = 0; v < V; ++v)
-      if (lane == 0) {
-        const float* c = cams + (int64_t)v * GS_CAMERA_FLOATS;
-        s_lim[v][0] = 1.3 * (double)vt.v[v].W / (2.0 * (double)c[0]);
-        s_lim[v][1] = 1.3 * (double)vt.v[v].H / (2.0 * (double)c[1]);
-      }
-  }
-  // the Gaussian's own data for the record lanes
-  const float mf0 = means[3 * ic], mf1 = means[3 * ic + 1], mf2 = means[3 * ic + 2];
-  s_p[lane][0] = mf0;
-  s_p[lane][1] = mf1;
-  s_p[lane][2] = mf2;
-  float qf0 = 0, qf1 = 0, qf2 = 0, qf3 = 0, lf0 = 0, lf1 = 0, lf2 = 0, logit = 0;
-  if (role == 0) {
-    qf0 = quats[4 * ic]; qf1 = quats[4 * ic + 1]; qf2 = quats[4 * ic + 2]; qf3 = quats[4 * ic + 3];
-    lf0 = log_scales[3 * ic]; lf1 = log_scales[3 * ic + 1]; lf2 = log_scales[3 * ic + 2];
-    logit = logits[ic];
-    double S00 = 0, S01 = 0, S02 = 0, S11 = 0, S12 = 0, S22 = 0;
-    if (valid) {
-      double q[4] = {qf0, qf1, qf2, qf3};
-      const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-      if (qn > 0.0)
-        for (int k = 0; k < 4; ++k) q[k] /= qn;
-      const double w = q[0], x = q[1], y = q[2], z = q[3];
-      const double R00 = 1 - 2 * (y * y + z * z), R01 = 2 * (x * y - w * z), R02 = 2 * (x * z + w * y);
-      const double R10 = 2 * (x * y + w * z), R11 = 1 - 2 * (x * x + z * z), R12 = 2 * (y * z - w * x);
-      const double R20 = 2 * (x * z - w * y), R21 = 2 * (y * z + w * x), R22 = 1 - 2 * (x * x + y * y);
-      const double s0 = exp(2.0 * (double)lf0), s1 = exp(2.0 * (double)lf1), s2 = exp(2.0 * (double)lf2);
-      S00 = R00 * R00 * s0 + R01 * R01 * s1 + R02 * R02 * s2;
-      S01 = R00 * R10 * s0 + R01 * R11 * s1 + R02 * R12 * s2;
-      S02 = R00 * R20 * s0 + R01 * R21 * s1 + R02 * R22 * s2;
-      S11 = R10 * R10 * s0 + R11 * R11 * s1 + R12 * R12 * s2;
-      S12 = R10 * R20 * s0 + R11 * R21 * s1 + R12 * R22 * s2;
-      S22 = R20 * R20 * s0 + R21 * R21 * s1 + R22 * R22 * s2;
+    for (int u = 0; u < 4; ++u) {
+      a[u] = gp4[3 * (q + u)];
+      b[u] = gp4[3 * (q + u) + 1];
+      c[u] = gp4[3 * (q + u) + 2];
     }
-    s_S[lane][0] = S00; s_S[lane][1] = S01; s_S[lane][2] = S02;
-    s_S[lane][3] = S11; s_S[lane][4] = S12; s_S[lane][5] = S22;
-  } else {
 #pragma unroll
-    for (int k = 0; k < K3; ++k) s_sh[lane][k] = sh[ic * K3 + k];
+    for (int u = 0; u < 4; ++u) {
+      g2[0] += a[u].x; g2[1] += a[u].y; g2[2] += a[u].z; g2[3] += a[u].w;
+      g2[4] += b[u].x; g2[5] += b[u].y; g2[6] += b[u].z; g2[7] += b[u].w;
+      g2[8] += c[u].x; g2[9] += c[u].y;
+    }
   }
-  __syncthreads();  // item list and view limits (wavefront 0) for both
+  for (; q < np; ++q) {
+    const float4 a = gp4[3 * q], b = gp4[3 * q + 1], c = gp4[3 * q + 2];
+    g2[0] += a.x; g2[1] += a.y; g2[2] += a.z; g2[3] += a.w;
+    g2[4] += b.x; g2[5] += b.y; g2[6] += b.z; g2[7] += b.w;
+    g2[8] += c.x; g2[9] += c.y;
+  }
+  // world covariance of the Gaussian
+  double qv[4] = {quats[4 * i], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3]};
+  const double qn = sqrt(qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3]);
+  if (qn > 0.0)
+    for (int k = 0; k < 4; ++k) qv[k] /= qn;
+  const double w = qv[0], x = qv[1], y = qv[2], z = qv[3];
+  const double R00 = 1 - 2 * (y * y + z * z), R01 = 2 * (x * y - w * z), R02 = 2 * (x * z + w * y);
+  const double R10 = 2 * (x * y + w * z), R11 = 1 - 2 * (x * x + z * z), R12 = 2 * (y * z - w * x);
+  const double R20 = 2 * (x * z - w * y), R21 = 2 * (y * z + w * x), R22 = 1 - 2 * (x * x + y * y);
+  const double s0 = exp(2.0 * (double)log_scales[3 * i]);
+  const double s1 = exp(2.0 * (double)log_scales[3 * i + 1]);
+  const double s2 = exp(2.0 * (double)log_scales[3 * i + 2]);
+  const double S00 = R00 * R00 * s0 + R01 * R01 * s1 + R02 * R02 * s2;
+  const double S01 = R00 * R10 * s0 + R01 * R11 * s1 + R02 * R12 * s2;
+  const double S02 = R00 * R20 * s0 + R01 * R21 * s1 + R02 * R22 * s2;
+  const double S11 = R10 * R10 * s0 + R11 * R11 * s1 + R12 * R12 * s2;
+  const double S12 = R10 * R20 * s0 + R11 * R21 * s1 + R12 * R22 * s2;
+  const double S22 = R20 * R20 * s0 + R21 * R21 * s1 + R22 * R22 * s2;
+  const float* c = cams + (int64_t)v * GS_CAMERA_FLOATS;
+  const double fx = c[0], fy = c[1];
+  double W[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) W[e] = c[4 + e];
+  const double limx = 1.3 * (double)vt.v[v].W / (2.0 * (double)c[0]);
+  const double limy = 1.3 * (double)vt.v[v].H / (2.0 * (double)c[1]);
+  const double p0 = means[3 * i], p1 = means[3 * i + 1], p2 = means[3 * i + 2];
+  const double tx = W[0] * p0 + W[1] * p1 + W[2] * p2 + c[13];
+  const double ty = W[3] * p0 + W[4] * p1 + W[5] * p2 + c[14];
+  const double tz = W[6] * p0 + W[7] * p1 + W[8] * p2 + c[15];
+  ProjTerm pt;
+  proj_term(W, fx, fy, limx, limy, tx, ty, tz, S00, S01, S02, S11, S12, S22, g2, pt);
+  double o[kTermWords];
+  o[0] = W[0] * pt.gt0 + W[3] * pt.gt1 + W[6] * pt.gt2 + 0.0;
+  o[1] = W[1] * pt.gt0 + W[4] * pt.gt1 + W[7] * pt.gt2 + 0.0;
+  o[2] = W[2] * pt.gt0 + W[5] * pt.gt1 + W[8] * pt.gt2 + 0.0;
+#pragma unroll
+  for (int e = 0; e < 6; ++e) o[3 + e] = pt.dS[e];
+  o[9] = g2[4];
+  o[10] = g2[0];
+  o[11] = g2[1];
+  o[12] = g2[2];
+  o[13] = (double)recs[ri].clamp;
+  double2* dst = reinterpret_cast<double2*>(terms + (int64_t)ri * kTermWords);
+#pragma unroll
+  for (int e = 0; e < kTermWords / 2; ++e) dst[e] = make_double2(o[2 * e], o[2 * e + 1]);
+}
 
+// Projection half per Gaussian: the records' mean, covariance and opacity
+// terms added in view order, then the covariance -> scale / rotation chain;
+// the mean sum waits in gp_tmp for the colour half.
+__global__ void __launch_bounds__(kGaussThreads) k_project_gauss(
+    const float* __restrict__ log_scales, const float* __restrict__ quats,
+    const float* __restrict__ logits, int64_t n, int n_views, const uint32_t* __restrict__ tt,
+    const double* __restrict__ terms, const int32_t* __restrict__ fl, int accumulate,
+    double* __restrict__ gp_tmp, float* __restrict__ g_ls, float* __restrict__ g_q,
+    float* __restrict__ g_logit) {
+  const int64_t i = (int64_t)blockIdx.x * kGaussThreads + threadIdx.x;
+  if (i >= n) return;
+  const bool overflow = fl[F_OVERFLOW] != 0;
+  uint64_t mask = 0;
+  if (!overflow)
+    for (int v = 0; v < n_views; ++v)
+      if (tt[(int64_t)v * n + i] > 0u) mask |= 1ull << v;
   double gp0 = 0, gp1 = 0, gp2 = 0, gop = 0;
   double GS00 = 0, GS01 = 0, GS02 = 0, GS11 = 0, GS12 = 0, GS22 = 0;
-  float acc_sh[K3];
-#pragma unroll
-  for (int k = 0; k < K3; ++k) acc_sh[k] = 0.0f;
-
-  for (uint32_t base = 0; base < total; base += kWave) {
-    const uint32_t k = base + (uint32_t)lane;
-    if (k < total) {
-      const uint32_t it = s_item[k];
-      const int o = (int)(it >> 6), v = (int)(it & 63u);
-      const int64_t ri = (int64_t)v * n + g0 + o;
-      const uint32_t np = tt[ri];
-      const float4* gp4 = reinterpret_cast<const float4*>(grad_pair + (int64_t)poff[ri] * kPairGrad);
-      // fixed-order sum of the record's pair partials (the colour chain
-      // needs the first three, the projection chain the rest)
-      double g2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-      if (role == 1) {
-        double s0 = 0, s1 = 0, s2 = 0;
-        uint32_t q = 0;
-        for (; q + 8 <= np; q += 8) {
-          float4 a[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) a[u] = gp4[3 * (q + u)];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) { s0 += a[u].x; s1 += a[u].y; s2 += a[u].z; }
-        }
-        for (; q < np; ++q) {
-          const float4 a = gp4[3 * q];
-          s0 += a.x; s1 += a.y; s2 += a.z;
-        }
-        g2[0] = s0; g2[1] = s1; g2[2] = s2;
-      } else {
-        double s3 = 0, s4 = 0, s5 = 0, s6 = 0, s7 = 0, s8 = 0, s9 = 0;
-        uint32_t q = 0;
-        for (; q + 8 <= np; q += 8) {
-          float4 a[8], b[8], c[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            a[u] = gp4[3 * (q + u)];
-            b[u] = gp4[3 * (q + u) + 1];
-            c[u] = gp4[3 * (q + u) + 2];
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            s3 += a[u].w;
-            s4 += b[u].x; s5 += b[u].y; s6 += b[u].z; s7 += b[u].w;
-            s8 += c[u].x; s9 += c[u].y;
-          }
-        }
-        for (; q < np; ++q) {
-          const float4 a = gp4[3 * q], b = gp4[3 * q + 1], c = gp4[3 * q + 2];
-          s3 += a.w;
-          s4 += b.x; s5 += b.y; s6 += b.z; s7 += b.w;
-          s8 += c.x; s9 += c.y;
-        }
-        g2[3] = s3; g2[4] = s4; g2[5] = s5; g2[6] = s6; g2[7] = s7; g2[8] = s8; g2[9] = s9;
-      }
-      const float* c = cams + (int64_t)v * GS_CAMERA_FLOATS;
-      const double fx = c[0], fy = c[1];
-      double W[9];
-#pragma unroll
-      for (int e = 0; e < 9; ++e) W[e] = c[4 + e];
-      const double t0 = c[13], t1 = c[14], t2 = c[15];
-      const double p[3] = {(double)s_p[o][0], (double)s_p[o][1], (double)s_p[o][2]};
-      if (role == 0) {
-        const double tx = W[0] * p[0] + W[1] * p[1] + W[2] * p[2] + t0;
-        const double ty = W[3] * p[0] + W[4] * p[1] + W[5] * p[2] + t1;
-        const double tz = W[6] * p[0] + W[7] * p[1] + W[8] * p[2] + t2;
-        ProjTerm pt;
-        proj_term(W, fx, fy, s_lim[v][0], s_lim[v][1], tx, ty, tz, s_S[o][0], s_S[o][1],
-                  s_S[o][2], s_S[o][3], s_S[o][4], s_S[o][5], g2, pt);
-        s_out0[lane][0] = W[0] * pt.gt0 + W[3] * pt.gt1 + W[6] * pt.gt2 + 0.0;
-        s_out0[lane][1] = W[1] * pt.gt0 + W[4] * pt.gt1 + W[7] * pt.gt2 + 0.0;
-        s_out0[lane][2] = W[2] * pt.gt0 + W[5] * pt.gt1 + W[8] * pt.gt2 + 0.0;
-#pragma unroll
-        for (int e = 0; e < 6; ++e) s_out0[lane][3 + e] = pt.dS[e];
-        s_out0[lane][9] = g2[4];
-      } else {
-        const uint32_t cmask = recs[ri].clamp;
-        float* gi = s_gsh[lane];
-#pragma unroll
-        for (int e = 0; e < K3; ++e) gi[e] = 0.0f;
-        double gv0, gv1, gv2;
-        colour_term<DEG>(W, t0, t1, t2, p, cmask, g2, s_sh[o], gi, gv0, gv1, gv2);
-        // (the projection terms are zero in this wavefront)
-        s_gv[lane][0] = W[0] * 0.0 + W[3] * 0.0 + W[6] * 0.0 + gv0;
-        s_gv[lane][1] = W[1] * 0.0 + W[4] * 0.0 + W[7] * 0.0 + gv1;
-        s_gv[lane][2] = W[2] * 0.0 + W[5] * 0.0 + W[8] * 0.0 + gv2;
-      }
-    }
-    wave_lds_sync();
-    // each owner adds the terms of its records in this batch, views ascending
-    const uint32_t lo = start > base ? start : base;
-    const uint32_t hi = (start + cnt) < (base + kWave) ? (start + cnt) : (base + kWave);
-    for (uint32_t r = lo; r < hi; ++r) {
-      const uint32_t sl = r - base;
-      if (role == 0) {
-        gp0 += s_out0[sl][0];
-        gp1 += s_out0[sl][1];
-        gp2 += s_out0[sl][2];
-        GS00 += s_out0[sl][3];
-        GS11 += s_out0[sl][4];
-        GS22 += s_out0[sl][5];
-        GS01 += s_out0[sl][6];
-        GS02 += s_out0[sl][7];
-        GS12 += s_out0[sl][8];
-        gop += s_out0[sl][9];
-      } else {
-        gp0 += s_gv[sl][0];
-        gp1 += s_gv[sl][1];
-        gp2 += s_gv[sl][2];
-#pragma unroll
-        for (int e = 0; e < K3; ++e) acc_sh[e] += s_gsh[sl][e];
-      }
-    }
-    wave_lds_sync();  // before the next batch rewrites the terms
+  for (uint64_t m = mask; m; m &= m - 1) {
+    const int v = __builtin_ctzll(m);
+    const double2* src = reinterpret_cast<const double2*>(terms + ((int64_t)v * n + i) * kTermWords);
+    const double2 a = src[0], b = src[1], c = src[2], d = src[3], e = src[4];
+    gp0 += a.x;
+    gp1 += a.y;
+    gp2 += b.x;
+    GS00 += b.y;
+    GS11 += c.x;
+    GS22 += c.y;
+    GS01 += d.x;
+    GS02 += d.y;
+    GS12 += e.x;
+    gop += e.y;
   }
-
-  if (role == 1) {
-    if (valid) {
-      float* gdst = g_sh + i * K3;
-      if (accumulate) {
-        float old[K3];
-#pragma unroll
-        for (int e = 0; e < K3; ++e) old[e] = gdst[e];
-#pragma unroll
-        for (int e = 0; e < K3; ++e) gdst[e] = old[e] + acc_sh[e];
-      } else {
-#pragma unroll
-        for (int e = 0; e < K3; ++e) gdst[e] = acc_sh[e];
-      }
-    }
-    s_hand[0][lane] = gp0;
-    s_hand[1][lane] = gp1;
-    s_hand[2][lane] = gp2;
-    __syncthreads();
-    return;
-  }
-  __syncthreads();
-  gp0 += s_hand[0][lane];
-  gp1 += s_hand[1][lane];
-  gp2 += s_hand[2][lane];
-  if (!valid) return;
+  gp_tmp[3 * i] = gp0;
+  gp_tmp[3 * i + 1] = gp1;
+  gp_tmp[3 * i + 2] = gp2;
+  const float qf0 = quats[4 * i], qf1 = quats[4 * i + 1], qf2 = quats[4 * i + 2], qf3 = quats[4 * i + 3];
+  const float lf0 = log_scales[3 * i], lf1 = log_scales[3 * i + 1], lf2 = log_scales[3 * i + 2];
+  const float logit = logits[i];
   double q[4] = {qf0, qf1, qf2, qf3};
   const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
   if (qn > 0.0)
@@ -786,9 +685,6 @@ __global__ void __launch_bounds__(2 * kWave) k_project_bwd_mv(
   const double dot = dw * qw + dx * qx + dy * qy + dz * qz;
   const double o = 1.0 / (1.0 + exp(-(double)logit));
   auto put = [&](float* dst, double val) { *dst = accumulate ? *dst + (float)val : (float)val; };
-  put(&g_means[3 * i], gp0);
-  put(&g_means[3 * i + 1], gp1);
-  put(&g_means[3 * i + 2], gp2);
   for (int r = 0; r < 3; ++r) put(&g_ls[3 * i + r], gl[r]);
   const double qnn = qn > 0.0 ? qn : 1.0;
   put(&g_q[4 * i], (dw - dot * qw) / qnn);
@@ -796,6 +692,64 @@ __global__ void __launch_bounds__(2 * kWave) k_project_bwd_mv(
   put(&g_q[4 * i + 2], (dy - dot * qy) / qnn);
   put(&g_q[4 * i + 3], (dz - dot * qz) / qnn);
   put(&g_logit[i], gop * o * (1.0 - o));
+}
+
+// Colour half per Gaussian: each view's colour chain (SH coefficients in
+// LDS, their gradient sums in registers) in view order; the mean gradient
+// is the projection half's sum plus the colour sum.
+template <int DEG>
+__global__ void __launch_bounds__(kGaussThreads) k_project_colour(
+    const float* __restrict__ means, const float* __restrict__ sh, int64_t n,
+    const float* __restrict__ cams, int n_views, const uint32_t* __restrict__ tt,
+    const double* __restrict__ terms, const int32_t* __restrict__ fl, int accumulate,
+    const double* __restrict__ gp_tmp, float* __restrict__ g_means, float* __restrict__ g_sh) {
+  constexpr int K = (DEG + 1) * (DEG + 1), K3 = 3 * K;
+  const int64_t i = (int64_t)blockIdx.x * kGaussThreads + threadIdx.x;
+  if (i >= n) return;
+  const bool overflow = fl[F_OVERFLOW] != 0;
+  uint64_t mask = 0;
+  if (!overflow)
+    for (int v = 0; v < n_views; ++v)
+      if (tt[(int64_t)v * n + i] > 0u) mask |= 1ull << v;
+  __shared__ float s_shv[kGaussThreads][K3 + 1];
+  float* shv = s_shv[threadIdx.x];
+  float acc_sh[K3];
+#pragma unroll
+  for (int k = 0; k < K3; ++k) {
+    shv[k] = sh[i * K3 + k];
+    acc_sh[k] = 0.0f;
+  }
+  const double p[3] = {(double)means[3 * i], (double)means[3 * i + 1], (double)means[3 * i + 2]};
+  double gc0 = 0, gc1 = 0, gc2 = 0;
+  for (uint64_t m = mask; m; m &= m - 1) {
+    const int v = __builtin_ctzll(m);
+    const double2* src = reinterpret_cast<const double2*>(terms + ((int64_t)v * n + i) * kTermWords);
+    const double2 a = src[5], b = src[6];
+    const float* c = cams + (int64_t)v * GS_CAMERA_FLOATS;
+    double W[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) W[e] = c[4 + e];
+    const double g2c[3] = {a.x, a.y, b.x};
+    double gv0, gv1, gv2;
+    colour_term<DEG>(W, c[13], c[14], c[15], p, (uint32_t)b.y, g2c, shv, acc_sh, gv0, gv1, gv2);
+    gc0 += W[0] * 0.0 + W[3] * 0.0 + W[6] * 0.0 + gv0;
+    gc1 += W[1] * 0.0 + W[4] * 0.0 + W[7] * 0.0 + gv1;
+    gc2 += W[2] * 0.0 + W[5] * 0.0 + W[8] * 0.0 + gv2;
+  }
+  float* gdst = g_sh + i * K3;
+  if (accumulate) {
+#pragma unroll
+    for (int e = 0; e < K3; ++e) gdst[e] = gdst[e] + acc_sh[e];
+  } else {
+#pragma unroll
+    for (int e = 0; e < K3; ++e) gdst[e] = acc_sh[e];
+  }
+  const double gp0 = gp_tmp[3 * i] + gc0, gp1 = gp_tmp[3 * i + 1] + gc1,
+               gp2 = gp_tmp[3 * i + 2] + gc2;
+  auto put = [&](float* dst, double val) { *dst = accumulate ? *dst + (float)val : (float)val; };
+  put(&g_means[3 * i], gp0);
+  put(&g_means[3 * i + 1], gp1);
+  put(&g_means[3 * i + 2], gp2);
 }
 
 // Zero of the five gradient arrays (59 floats per Gaussian at degree 3).
@@ -866,6 +820,10 @@ hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float*
   const int64_t split_blocks = (P.n + kWave - 1) / kWave;
   double* pose_part = dL_dpose ? ws_at<double>(ws, P.off_pose_part) : nullptr;
   const bool compact = P.vt.n_views == 1;
+  // several views without a camera tangent: a thread per visible record
+  // (grid for all records; the count is on the device), then per Gaussian
+  const int64_t rec_blocks = (P.n_rec + kRecThreads - 1) / kRecThreads;
+  const int64_t gauss_blocks = (P.n + kGaussThreads - 1) / kGaussThreads;
   if (project_bwd_zeroes(P, accumulate) && !zeroed) {
     const hipError_t e = launch_zero_grads(P, out, s);
     if (e != hipSuccess) return e;
@@ -879,13 +837,26 @@ hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float*
                      ws_at<float>(ws, P.off_grad_pair), ws_at<int32_t>(ws, P.off_flags),          \
                      ws_at<uint32_t>(ws, P.off_vis_list), accumulate, out.means, out.log_scales,  \
                      out.quats, out.opacity_logits, out.sh, pose_part, blocks)
-#define GS_PBMV(D)                                                                              \
-  hipLaunchKernelGGL((k_project_bwd_mv<D>), dim3((unsigned)split_blocks), dim3(2 * kWave), 0, s,  \
-                     g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, P.n, cams, P.vt,     \
-                     ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_tt),                   \
-                     ws_at<uint32_t>(ws, P.off_poff), ws_at<float>(ws, P.off_grad_pair),         \
-                     ws_at<int32_t>(ws, P.off_flags), accumulate, out.means, out.log_scales,      \
-                     out.quats, out.opacity_logits, out.sh)
+// (one statement: the three launches of the several-view form)
+#define GS_PBMV(D)                                                                                \
+  do {                                                                                            \
+    hipLaunchKernelGGL((k_project_rec<D>), dim3((unsigned)rec_blocks), dim3(kRecThreads), 0, s,    \
+                       g.means, g.log_scales, g.quats, P.n, cams, P.vt, ws_at<Rec>(ws, P.off_rec), \
+                       ws_at<uint32_t>(ws, P.off_tt), ws_at<uint32_t>(ws, P.off_poff),             \
+                       ws_at<float>(ws, P.off_grad_pair), ws_at<int32_t>(ws, P.off_flags),         \
+                       ws_at<uint32_t>(ws, P.off_vis_list), ws_at<double>(ws, P.off_rec_terms));   \
+    hipLaunchKernelGGL(k_project_gauss, dim3((unsigned)gauss_blocks), dim3(kGaussThreads), 0, s,   \
+                       g.log_scales, g.quats, g.opacity_logits, P.n, P.vt.n_views,                  \
+                       ws_at<uint32_t>(ws, P.off_tt), ws_at<double>(ws, P.off_rec_terms),          \
+                       ws_at<int32_t>(ws, P.off_flags), accumulate,                                 \
+                       ws_at<double>(ws, P.off_gp_tmp), out.log_scales, out.quats,                  \
+                       out.opacity_logits);                                                         \
+    hipLaunchKernelGGL((k_project_colour<D>), dim3((unsigned)gauss_blocks), dim3(kGaussThreads),   \
+                       0, s, g.means, g.sh, P.n, cams, P.vt.n_views,                                \
+                       ws_at<uint32_t>(ws, P.off_tt), ws_at<double>(ws, P.off_rec_terms),          \
+                       ws_at<int32_t>(ws, P.off_flags), accumulate,                                 \
+                       ws_at<double>(ws, P.off_gp_tmp), out.means, out.sh);                         \
+  } while (0)
 #define GS_PB(D)                \
   if (pose_part) {              \
     if (compact)                \
@@ -898,6 +869,9 @@ hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float*
     else                        \
       GS_PBMV(D);               \
   }
+  // the several-view form writes per-record slots and per-Gaussian sums that
+  // only plans of several views allocate
+  if (!pose_part && !compact && P.vt.n_views < 2) return hipErrorInvalidValue;
   switch (P.deg) {
     case 0: GS_PB(0); break;
     case 1: GS_PB(1); break;

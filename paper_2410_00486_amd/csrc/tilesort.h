@@ -143,6 +143,9 @@ struct TileSortArgs {
   // the long-list kernel runs after this one (it then clears the counters of
   // the long lists itself) rather than before
   bool long_after;
+  // the lists were sorted by the radix binning: ranges, queue entries and
+  // counter clears only
+  bool presorted;
 };
 
 // What a wavefront that sorted a tile knows about its list: the range
@@ -187,7 +190,7 @@ __device__ inline TileList sort_tile_wave(const TileSortArgs& A, int t, int lane
     if (half && lane == 0) A.bq[A.bq_stride + A.hstart[t]] = make_uint2((uint32_t)t, nb - 1);
   }
   TileList L{ok ? (uint32_t)start64 : 0u, ok ? (uint32_t)(start64 + n) : 0u, false, false};
-  if (!ok || n > kTileSortSmall) return L;  // uniform
+  if (!ok || n > kTileSortSmall || A.presorted) return L;  // uniform
   L.fresh = true;
   const uint32_t start = (uint32_t)start64;
   const uint64_t tkey = (uint64_t)(uint32_t)t << 32;

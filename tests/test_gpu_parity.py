@@ -362,6 +362,26 @@ def test_batched_matches_oracle_multi_view():
     assert_pose_close(it.dL_dpose.cpu().numpy(), poses, poses_f)
 
 
+def test_multi_view_without_pose_matches_pose_path_and_oracle():
+    """Several views without the camera tangent take the projection
+    backward in three launches (a thread per visible record, then the
+    projection and colour halves per Gaussian).  Against the one-thread-per-
+    Gaussian form that also computes the tangent: the same sums in the same
+    view order, only the mean gradient adds its two halves in another order
+    (within a few ulp); and against the oracle."""
+    scene, cams = _multi_view_workload()
+    gcs, gds = scenes.linear_loss_weights(48, cams)
+    print("4 views 120k without camera tangent: against the tangent form and the oracle", flush=True)
+    a = run_gpu(scene, cams, dL_dcolor=gcs, dL_ddepth=gds)
+    b = run_gpu(scene, cams, dL_dcolor=gcs, dL_ddepth=gds, pose=True)
+    ga, gb = grads_np(a), grads_np(b)
+    for f in ga:
+        scale = float(np.abs(gb[f]).max())
+        np.testing.assert_allclose(ga[f], gb[f], rtol=1e-6, atol=1e-9 * scale, err_msg=f)
+    grads, _, exclude, _ = oracle_reference(scene, cams, gcs, gds)
+    assert_grads_close(ga, grads, exclude, visible=visible_count(scene, cams))
+
+
 def test_persistent_equals_plain():
     scene, cams = _multi_view_workload()
     gcs, gds = scenes.linear_loss_weights(46, cams)
@@ -566,6 +586,22 @@ def test_empty_scene_and_empty_view():
     np.testing.assert_allclose(col[0], 0.1, rtol=0, atol=1e-7)
     g = grads_np(it)
     assert all((g[f] == 0).all() for f in g)
+
+
+@pytest.mark.parametrize("views,tile", [(1, (16, 16)), (1, (16, 8)), (2, (8, 8))])
+def test_zero_upstream_gradient_gives_zero_gradients(views, tile):
+    """With dL/dC = dL/dD = 0 every parameter gradient is exactly zero (one
+    view: the compact projection backward alone; two views: the per-record
+    and per-Gaussian launches).  A launch of the several-view form on a
+    one-view plan would write its per-Gaussian sums far outside that plan's
+    workspace and leave non-zero values here."""
+    w = workload(3)
+    cams = [w.cameras[0]] if views == 1 else [w.cameras[0], w.gt_cameras[0]]
+    print(f"zero upstream gradient: {views} view(s), tile {tile}", flush=True)
+    it = run_gpu(w.scene, cams, tile=tile)
+    g = grads_np(it)
+    for f in g:
+        assert int(np.count_nonzero(g[f])) == 0, f
 
 
 def test_nonfinite_gaussians_are_culled_and_counted():

@@ -38,10 +38,10 @@ BENCH_FLAGS = L.GS_PERSISTENT | L.GS_SPLAT_BWD
 LRS = {"means": 1.6e-4, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
 
 
-def _batched(scene, cams, seed, flags=BENCH_FLAGS):
+def _batched(scene, cams, seed, flags=BENCH_FLAGS, pose=True):
     gcs, gds = scenes.linear_loss_weights(seed, cams)
     it = run_gpu(scene, cams, tile=TILE, lds=64, chunk=1, dL_dcolor=gcs, dL_ddepth=gds,
-                 pose=True, flags=flags)
+                 pose=pose, flags=flags)
     return it, gcs, gds
 
 
@@ -174,3 +174,45 @@ def test_keyframes16_graph_with_adam_equals_eager():
         assert bool(torch.isfinite(graphed.frame.loss).all())
     assert int(graphed.step_dev.item()) == 2
     graphed.close()
+
+
+@pytest.mark.parametrize("cfg", [4, 5])
+def test_full_size_radix_binning_equals_per_tile_binning(cfg):
+    """The radix binning at the full batched sizes (8 keyframes over 500k,
+    16 views over 2M): lists, images, gradients and camera tangents bit for
+    bit against the per-tile binning."""
+    w = workload(cfg)
+    print(f"workload {cfg} full size: radix binning against the per-tile binning", flush=True)
+    a, _, _ = _batched(w.scene, w.cameras, 600 + cfg, flags=BENCH_FLAGS | L.GS_RADIX_BIN)
+    b, _, _ = _batched(w.scene, w.cameras, 600 + cfg)
+    fa, fb = a.plan.flags_of(a.ws), b.plan.flags_of(b.ws)
+    assert fa[L.F_OVERFLOW] == 0 and fa[L.F_PAIRS] == fb[L.F_PAIRS]
+    P, T = int(fa[L.F_PAIRS]), a.plan.total_tiles
+    for region, dt, cnt in ((L.GS_WS_SORTED_KEYS, torch.int64, P),
+                            (L.GS_WS_SORTED_VALS, torch.int32, P),
+                            (L.GS_WS_SORTED_RECS, torch.int32, P),
+                            (L.GS_WS_RANGES, torch.int32, 2 * T)):
+        assert torch.equal(a.plan.region(a.ws, region, dt, cnt),
+                           b.plan.region(b.ws, region, dt, cnt)), region
+    for x, y in ((a.frame.color, b.frame.color), (a.frame.depth, b.frame.depth),
+                 (a.frame.T_final, b.frame.T_final), (a.frame.last, b.frame.last)):
+        assert torch.equal(x, y)
+    for x, y in zip(a.grads.tensors(), b.grads.tensors()):
+        assert torch.equal(x, y)
+    assert torch.equal(a.dL_dpose, b.dL_dpose)
+
+
+def test_keyframes16_without_pose_matches_pose_path():
+    """The benchmark's projection backward (several views, no camera
+    tangent: per-record and per-Gaussian launches) at full size against the
+    one-thread-per-Gaussian form with the tangent."""
+    w = workload(5)
+    print("16 views 1200x680, 2M pool: no-tangent projection backward against the tangent form",
+          flush=True)
+    a, _, _ = _batched(w.scene, w.cameras, 700, pose=False)
+    b, _, _ = _batched(w.scene, w.cameras, 700, pose=True)
+    for f, x, y in zip(gsr.Gaussians.FIELDS, a.grads.tensors(), b.grads.tensors()):
+        x, y = x.double(), y.double()
+        scale = float(y.abs().max())
+        err = (x - y).abs()
+        assert bool((err <= 1e-6 * y.abs() + 1e-9 * scale).all()), (f, float(err.max()), scale)
