@@ -79,9 +79,11 @@ typedef int32_t gs_status;
                                          visible records by depth, then their pairs,
                                          generated in depth order, by tile id) instead
                                          of per-tile slot claims and per-tile sorts;
-                                         same lists, bit for bit.  Needs about
-                                         16 B per record and 16 B per pair of
-                                         capacity more workspace */
+                                         the projection then counts no pairs per
+                                         tile (the lists give the counts); same
+                                         lists, bit for bit.  Needs about 16 B per
+                                         record and 16 B per pair of capacity
+                                         more workspace */
 
 /* Gaussian parameters (Sec. III-B): SoA, float32, device pointers. */
 typedef struct gs_gaussians {
@@ -485,9 +487,11 @@ gs_status gs_graph_time(gs_graph* graph, void* stream, int32_t warmup, int32_t r
 #define GS_MARK_BIN_SCATTER 3      /* after the pair scatter (GS_RADIX_BIN: after the
                                       depth sort of the records and the pair
                                       generation) */
-#define GS_MARK_BIN_SHORT_SORT 4   /* after the per-tile sorts of short lists */
+#define GS_MARK_BIN_SHORT_SORT 4   /* after the per-tile sorts of short lists
+                                      (GS_RADIX_BIN: after the tile-id passes) */
 #define GS_MARK_BIN_LONG_SORT 5    /* after the long-list sorts (GS_RADIX_BIN: after
-                                      the tile-id passes) */
+                                      the per-tile counts, their scan and the
+                                      per-tile pass) */
 #define GS_MARK_FORWARD 6          /* after compositing (and the L1 loss sums) */
 #define GS_MARK_LOSS 7             /* after the SSIM loss kernels */
 #define GS_MARK_RASTER_BWD 8       /* after the raster backward */

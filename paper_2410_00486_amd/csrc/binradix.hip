@@ -405,6 +405,21 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_generate(
   }
 }
 
+// 5. Per-tile list bounds from the sorted keys (tile << 32 | depth): the
+// first position of each tile's run to tstart, one past its last to cnt.
+// Tiles without pairs keep cnt = 0 (the per-tile pass zeroed it).
+__global__ void __launch_bounds__(kRbThreads) k_rb_runs(const uint64_t* __restrict__ keys,
+                                                        const int32_t* __restrict__ fl,
+                                                        uint32_t* __restrict__ tstart,
+                                                        uint32_t* __restrict__ tend) {
+  const int64_t P = rb_count(fl, F_PAIRS);
+  const int64_t q = (int64_t)blockIdx.x * kRbThreads + threadIdx.x;
+  if (q >= P) return;
+  const uint32_t t = (uint32_t)(keys[q] >> 32);
+  if (q == 0 || (uint32_t)(keys[q - 1] >> 32) != t) tstart[t] = (uint32_t)q;
+  if (q == P - 1 || (uint32_t)(keys[q + 1] >> 32) != t) tend[t] = (uint32_t)(q + 1);
+}
+
 }  // namespace
 
 namespace {
@@ -506,6 +521,16 @@ hipError_t launch_rb_tile_sort(const Plan& P, void* ws, hipStream_t s) {
             last ? nullptr : B.gx[cur ^ 1], last, F_PAIRS, P.rb_pair_blocks, shift, bits);
     cur ^= 1;
   }
+  return hipGetLastError();
+}
+
+// Step 5: list bounds per tile from the sorted keys (for the tile scan).
+hipError_t launch_rb_runs(const Plan& P, void* ws, hipStream_t s) {
+  if (P.rb_pair_blocks <= 0) return hipSuccess;
+  const int64_t blocks = P.rb_pair_blocks * (kRbTile / kRbThreads);
+  hipLaunchKernelGGL(k_rb_runs, dim3((unsigned)blocks), dim3(kRbThreads), 0, s,
+                     ws_at<uint64_t>(ws, P.off_keys), ws_at<int32_t>(ws, P.off_flags),
+                     ws_at<uint32_t>(ws, P.off_tile_start), ws_at<uint32_t>(ws, P.off_tile_cnt));
   return hipGetLastError();
 }
 

@@ -72,8 +72,13 @@ struct ScanArgs {
   uint32_t* hstart;        // position of the tile's half bucket in queue 1
   uint32_t* order;         // work order of the render kernels, longest tiles first
   uint4* long_list;        // (tile, list start, pairs, -) of the lists for the long-list sort
-  int keep_counts;         // radix binning: the counters stay (no scatter cursors)
+  // kScanBoth: chunks and tile counts (the projection's); kScanChunks: the
+  // chunks alone (radix binning, before the pairs exist); kScanTiles: the
+  // tiles alone from the list ends (cnt) and starts (tstart) that the radix
+  // binning found in its sorted keys, with the counts written back to cnt
+  int mode;
 };
+constexpr int kScanBoth = 0, kScanChunks = 1, kScanTiles = 2;
 
 // Work order of the render kernels: tiles with at least kLongTile pairs
 // first (in tile order), then the others (in reverse tile order), so that
@@ -181,7 +186,12 @@ __device__ __forceinline__ void scan_load(const ScanArgs& A, int64_t r, ScanRoun
   const uint32_t* chunk_in = reinterpret_cast<const uint32_t*>(A.chunk_cnt);
 #pragma unroll
   for (int k = 0; k < kScanVec; ++k) {
-    const uint4 x = load4(A.cnt, R.it + 4 * k, T);
+    uint4 x = load4(A.cnt, R.it + 4 * k, T);
+    if (A.mode == kScanTiles) {  // list end (0: no pairs) minus list start
+      const uint4 st = load4(A.tstart, R.it + 4 * k, T);
+      x = make_uint4(x.x ? x.x - st.x : 0u, x.y ? x.y - st.y : 0u, x.z ? x.z - st.z : 0u,
+                     x.w ? x.w - st.w : 0u);
+    }
     R.tc[4 * k] = x.x; R.tc[4 * k + 1] = x.y; R.tc[4 * k + 2] = x.z; R.tc[4 * k + 3] = x.w;
     const uint4 y = load4(chunk_in, 2 * (R.ic + 2 * k), 2 * C);
     R.cp[2 * k] = y.x; R.cv[2 * k] = y.y; R.cp[2 * k + 1] = y.z; R.cv[2 * k + 1] = y.w;
@@ -237,7 +247,12 @@ __device__ __forceinline__ void scan_emit(const ScanArgs& A, ScanRound& R) {
       R.s32[4] += c > kTileSortSmall ? 1u : 0u;
     }
     store4(A.tstart, R.it + 4 * k, T, make_uint4(ts[0], ts[1], ts[2], ts[3]));
-    if (!A.keep_counts) store4(A.cnt, R.it + 4 * k, T, make_uint4(0u, 0u, 0u, 0u));
+    // the scatter's cursors start at zero; the radix binning's per-tile
+    // pass reads the counts
+    store4(A.cnt, R.it + 4 * k, T,
+           A.mode == kScanTiles ? make_uint4(R.tc[4 * k], R.tc[4 * k + 1], R.tc[4 * k + 2],
+                                             R.tc[4 * k + 3])
+                                : make_uint4(0u, 0u, 0u, 0u));
     if (A.boff) {
       store4(A.boff, R.it + 4 * k, T, make_uint4(bs[0], bs[1], bs[2], bs[3]));
       store4(A.fstart, R.it + 4 * k, T,
@@ -257,21 +272,34 @@ __device__ __forceinline__ void scan_emit(const ScanArgs& A, ScanRound& R) {
 __device__ __forceinline__ void scan_finish(const ScanArgs& A, const uint64_t (&c64)[2],
                                             const uint32_t (&c32)[kScanN32], int64_t cap,
                                             int32_t* __restrict__ fl, const StepAdvance& st) {
+  const bool splat = A.boff != nullptr;
+  if (A.mode == kScanTiles) {
+    // the pair totals were settled by the chunk scan before
+    const bool over = fl[F_OVERFLOW] != 0;
+    fl[F_LONG_TILES] = over ? 0 : (int32_t)c32[4];
+    fl[F_BQ_FULL] = (over || !splat) ? 0 : (int32_t)(c32[0] - c32[1]);
+    fl[F_BQ_HALF] = (over || !splat) ? 0 : (int32_t)c32[1];
+    if (splat) A.boff[A.n_tiles] = c32[0];
+    return;
+  }
   const uint64_t tile_pairs = c64[0], chunk_pairs = c64[1];
-  const bool over = tile_pairs > (uint64_t)cap || tile_pairs != chunk_pairs;
+  const bool chunks_only = A.mode == kScanChunks;
+  const uint64_t pairs = chunks_only ? chunk_pairs : tile_pairs;
+  const bool over = pairs > (uint64_t)cap || (!chunks_only && tile_pairs != chunk_pairs);
   fl[F_OVERFLOW] = over ? 1 : 0;
-  fl[F_PAIRS] = over ? 0 : (int32_t)tile_pairs;
-  fl[F_PAIRS_WANTED] = tile_pairs > 0x7FFFFFFFull ? 0x7FFFFFFF : (int32_t)tile_pairs;
+  fl[F_PAIRS] = over ? 0 : (int32_t)pairs;
+  fl[F_PAIRS_WANTED] = pairs > 0x7FFFFFFFull ? 0x7FFFFFFF : (int32_t)pairs;
   fl[F_VISIBLE] = (int32_t)c32[2];
   fl[F_NONFINITE] = fl[F_NF_ACC];  // counted by the projection
   fl[F_NF_ACC] = 0;
-  // the bucket queues are filled by the tile sort at the positions scanned
-  // here; the long lists are sorted by their own kernel (none on overflow)
-  fl[F_LONG_TILES] = (int32_t)c32[4];
-  const bool splat = A.boff != nullptr;
-  fl[F_BQ_FULL] = (over || !splat) ? 0 : (int32_t)(c32[0] - c32[1]);
-  fl[F_BQ_HALF] = (over || !splat) ? 0 : (int32_t)c32[1];
-  if (splat) A.boff[A.n_tiles] = c32[0];
+  if (!chunks_only) {
+    // the bucket queues are filled by the tile sort at the positions scanned
+    // here; the long lists are sorted by their own kernel (none on overflow)
+    fl[F_LONG_TILES] = (int32_t)c32[4];
+    fl[F_BQ_FULL] = (over || !splat) ? 0 : (int32_t)(c32[0] - c32[1]);
+    fl[F_BQ_HALF] = (over || !splat) ? 0 : (int32_t)c32[1];
+    if (splat) A.boff[A.n_tiles] = c32[0];
+  }
   // a whole iteration with Adam advances its step here, once the pairs are
   // known to fit: after an overflow the iteration's Adam launch changes
   // nothing, and neither does the step counter
@@ -762,6 +790,7 @@ hipError_t launch_radix_sort(uint64_t* keys0, uint64_t* keys1, uint32_t* vals0,
 
 hipError_t launch_rb_generate(const Plan& P, void* ws, hipStream_t s);
 hipError_t launch_rb_tile_sort(const Plan& P, void* ws, hipStream_t s);
+hipError_t launch_rb_runs(const Plan& P, void* ws, hipStream_t s);
 
 hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, p, v);
@@ -822,34 +851,51 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_sh
   const bool radix = (P.cfg.flags & GS_RADIX_BIN) != 0;
   ScanArgs sa{chunk_cnt, chunk_pre, P.n_chunks, tcnt, tstart, (int64_t)T,
               splat ? ws_at<uint32_t>(ws, P.off_boff) : nullptr, fstart, hstart,
-              ws_at<uint32_t>(ws, P.off_order), long_list, radix ? 1 : 0};
+              ws_at<uint32_t>(ws, P.off_order), long_list, kScanBoth};
   // always launched, so that the flags are always set: one block for a
   // plan of one round, one block per round in three launches beyond
   const StepAdvance adv = step ? *step : StepAdvance{};
-  if (P.scan_rounds <= 1) {
-    hipLaunchKernelGGL(k_scans, dim3(1), dim3(kScanBlock), 0, s, sa, P.pair_cap, fl, adv);
+  auto scan = [&](const ScanArgs& a, const StepAdvance& st) {
+    if (P.scan_rounds <= 1) {
+      hipLaunchKernelGGL(k_scans, dim3(1), dim3(kScanBlock), 0, s, a, P.pair_cap, fl, st);
+    } else {
+      static_assert(sizeof(ScanPart) <= 64, "scan partial slot");
+      ScanPart* part = ws_at<ScanPart>(ws, P.off_scan_part);
+      const unsigned rounds = (unsigned)P.scan_rounds;
+      hipLaunchKernelGGL(k_scan_reduce, dim3(rounds), dim3(kScanBlock), 0, s, a, part);
+      hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, a, part, P.scan_rounds,
+                         P.pair_cap, fl, st);
+      hipLaunchKernelGGL(k_scan_down, dim3(rounds), dim3(kScanBlock), 0, s, a, part);
+    }
+  };
+  if (radix) {
+    ScanArgs sc = sa;
+    sc.n_tiles = 0;
+    sc.mode = kScanChunks;
+    scan(sc, adv);
   } else {
-    static_assert(sizeof(ScanPart) <= 64, "scan partial slot");
-    ScanPart* part = ws_at<ScanPart>(ws, P.off_scan_part);
-    const unsigned rounds = (unsigned)P.scan_rounds;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(rounds), dim3(kScanBlock), 0, s, sa, part);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, sa, part, P.scan_rounds,
-                       P.pair_cap, fl, adv);
-    hipLaunchKernelGGL(k_scan_down, dim3(rounds), dim3(kScanBlock), 0, s, sa, part);
+    scan(sa, adv);
   }
   hipError_t e = mk.at(GS_MARK_BIN_SCAN, s);
   if (e != hipSuccess) return e;
   if (radix) {
     // records by depth, their pairs in that order, then the pairs by tile;
+    // the list starts and ends found in the sorted keys give the per-tile
+    // counts (the projection counted none), scanned like the projection's;
     // the per-tile pass (here, or the forward's when deferred) writes the
     // ranges and queue entries and zeroes the counters
     if ((e = launch_rb_generate(P, ws, s)) != hipSuccess) return e;
     if ((e = mk.at(GS_MARK_BIN_SCATTER, s)) != hipSuccess) return e;
+    if ((e = launch_rb_tile_sort(P, ws, s)) != hipSuccess) return e;
+    if ((e = mk.at(GS_MARK_BIN_SHORT_SORT, s)) != hipSuccess) return e;
+    if ((e = launch_rb_runs(P, ws, s)) != hipSuccess) return e;
+    ScanArgs st = sa;
+    st.n_chunks = 0;
+    st.mode = kScanTiles;
+    scan(st, StepAdvance{});
     if (T > 0 && !defer_short_sorts) {
       hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)T), dim3(kWave), 0, s, tile_sort_args(P, ws));
     }
-    if ((e = mk.at(GS_MARK_BIN_SHORT_SORT, s)) != hipSuccess) return e;
-    if ((e = launch_rb_tile_sort(P, ws, s)) != hipSuccess) return e;
     if ((e = mk.at(GS_MARK_BIN_LONG_SORT, s)) != hipSuccess) return e;
     return hipGetLastError();
   }

@@ -262,7 +262,8 @@ __global__ void __launch_bounds__(256) k_preprocess(
       const int64_t chunk = (int64_t)blockIdx.x * (256 / kWave) + w;
       if (lane == 0 && chunk < chunks_per_view)
         chunk_cnt[(int64_t)v * chunks_per_view + chunk] = make_uint2(total, n_vis);
-      if (total > 0) {  // uniform over the wavefront
+      // (the radix binning finds the per-tile counts in its sorted lists)
+      if (total > 0 && !(flags & GS_RADIX_BIN)) {  // uniform over the wavefront
         s_pre[w][lane] = incl - count;
         s_xy[w][lane] = box_xy;
         s_w[w][lane] = box_w;
