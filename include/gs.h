@@ -82,7 +82,7 @@ typedef int32_t gs_status;
                                          the projection then counts no pairs per
                                          tile (the lists give the counts); same
                                          lists, bit for bit.  Needs about 16 B per
-                                         record and 16 B per pair of capacity
+                                         record and 24 B per pair of capacity
                                          more workspace */
 
 /* Gaussian parameters (Sec. III-B): SoA, float32, device pointers. */

@@ -265,6 +265,7 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
     P->off_rb_rid[k] = take(rrec);
     P->off_rb_tkey[k] = take(rpair);
     P->off_rb_gidx[k] = take(rpair);
+    P->off_rb_ridx[k] = take(rpair);
   }
   P->off_rb_hist = take(radix ? (size_t)rb_max_radix() * 4 *
                                     std::max(P->rb_rec_blocks, P->rb_pair_blocks) : 0);

@@ -167,7 +167,6 @@ struct RbEmit {
   uint64_t* keys;          // tile << 32 | depth bits
   uint32_t* vals;          // generation index
   uint32_t* sorted_rec;    // record id
-  const uint32_t* pair_rec;
   const Rec* rec;
   Rec* lrec;               // records in list order
 };
@@ -177,10 +176,11 @@ struct RbEmit {
 // (digit totals scanned over digits + the block's offset within the digit).
 // EMIT: the last pass of the tile sort (keys are tile ids, values
 // generation indices): writes the sorted lists instead of keys / values.
-template <bool EMIT>
+template <bool EMIT, bool TWO>
 __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, RbEmit E,
+    const uint32_t* __restrict__ vals2_in, uint32_t* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out, uint32_t* __restrict__ vals2_out, RbEmit E,
     const int32_t* __restrict__ fl, int which, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ dtot, int64_t nb_cap, int shift, int bits) {
   const int64_t cnt = rb_count(fl, which);
@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
   __shared__ uint32_t lstart[kRbMaxRadix];
   __shared__ uint32_t gofs[kRbMaxRadix];
   __shared__ uint32_t ws[kRbWaves];
-  __shared__ uint32_t sk[kRbTile], sv[kRbTile];
+  __shared__ uint32_t sk[kRbTile], sv[kRbTile], sv2[TWO ? kRbTile : 1];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int d_own = threadIdx.x;  // the digit this thread handles in the block scans
   const uint32_t mask = (1u << bits) - 1u;
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
     const uint32_t ex = rb_block_exscan(x, ws);  // (its barrier also orders the clear)
     if (d_own <= (int)mask) gofs[d_own] = ex + hist[(int64_t)d_own * nb_cap + blockIdx.x];
   }
-  uint32_t key[kRbItems], val[kRbItems], rank[kRbItems];
+  uint32_t key[kRbItems], val[kRbItems], val2[kRbItems], rank[kRbItems];
   const uint64_t lt = lanemask_lt();
 #pragma unroll
   for (int r = 0; r < kRbItems; ++r) {
@@ -208,6 +208,7 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
     const bool valid = idx < cnt;
     key[r] = valid ? keys_in[idx] : 0u;
     val[r] = valid ? vals_in[idx] : 0u;
+    val2[r] = (TWO && valid) ? vals2_in[idx] : 0u;
     const uint32_t d = (key[r] >> shift) & mask;
     const uint64_t peers = rb_peers(d, valid, bits);
     const uint64_t below = peers & lt;
@@ -240,26 +241,29 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
       const uint32_t lp = lstart[d] + wcnt[w][d] + rank[r];
       sk[lp] = key[r];
       sv[lp] = val[r];
+      if (TWO) sv2[lp] = val2[r];
     }
   }
   __syncthreads();
   const int nloc = (int)((cnt - base) < kRbTile ? (cnt - base) : kRbTile);
-  if (!EMIT) {
+  if constexpr (!EMIT) {
     for (int i = threadIdx.x; i < nloc; i += kRbThreads) {
       const uint32_t k = sk[i];
       const uint32_t d = (k >> shift) & mask;
       const uint32_t pos = gofs[d] + (uint32_t)i - lstart[d];
       keys_out[pos] = k;
       vals_out[pos] = sv[i];
+      if (TWO) vals2_out[pos] = sv2[i];
     }
   } else {
-    // record ids of all of the thread's positions first (one round trip),
-    // then the record copies, four records in flight at a time
+    // the record ids came along as second values; the record copies go
+    // four records in flight at a time
+    static_assert(TWO, "the last tile pass carries the record ids");
     uint32_t rid[kRbItems];
 #pragma unroll
     for (int q = 0; q < kRbItems; ++q) {
       const int i = threadIdx.x + q * kRbThreads;
-      rid[q] = i < nloc ? E.pair_rec[sv[i]] : 0u;
+      rid[q] = i < nloc ? sv2[i] : 0u;
     }
     constexpr int G = 4;
 #pragma unroll
@@ -341,13 +345,13 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_gen_scan(const int32_t* __res
 // per thread) get their first slots from a block scan plus the block's
 // offset; the block's pairs are then spread evenly over the threads (each
 // finds its record by binary search of the slots in LDS), so one large
-// footprint does not serialise on one thread.  Writes the tile key and the
-// generation index of every pair, and pair -> record.
+// footprint does not serialise on one thread.  Writes the tile key, the
+// generation index and the record id of every pair.
 __global__ void __launch_bounds__(kRbThreads) k_rb_generate(
     const uint32_t* __restrict__ rid, const uint32_t* __restrict__ tt,
     const uint32_t* __restrict__ poff, const ushort4* __restrict__ rect, int64_t n, ViewTable vt,
     const int32_t* __restrict__ fl, const uint32_t* __restrict__ part,
-    uint32_t* __restrict__ tkey, uint32_t* __restrict__ gidx, uint32_t* __restrict__ pair_rec) {
+    uint32_t* __restrict__ tkey, uint32_t* __restrict__ gidx, uint32_t* __restrict__ ridx) {
   const int64_t V = rb_count(fl, F_VISIBLE);
   const int64_t base = (int64_t)blockIdx.x * kGenRecs;
   if (base >= V) return;
@@ -401,7 +405,7 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_generate(
     const uint32_t g = s_p0[lo] + k;
     tkey[q0 + q] = t;
     gidx[q0 + q] = g;
-    pair_rec[g] = s_rid[lo];
+    ridx[q0 + q] = s_rid[lo];
   }
 }
 
@@ -426,7 +430,7 @@ namespace {
 
 struct RbBuffers {
   const int32_t* fl;
-  uint32_t *tt, *poff, *vis, *dk[2], *rid[2], *tk[2], *gx[2], *hist, *dtot, *part, *pair_rec;
+  uint32_t *tt, *poff, *vis, *dk[2], *rid[2], *tk[2], *gx[2], *rx[2], *hist, *dtot, *part;
   RbEmit emit;
 };
 
@@ -441,32 +445,36 @@ RbBuffers rb_buffers(const Plan& P, void* ws) {
     B.rid[k] = ws_at<uint32_t>(ws, P.off_rb_rid[k]);
     B.tk[k] = ws_at<uint32_t>(ws, P.off_rb_tkey[k]);
     B.gx[k] = ws_at<uint32_t>(ws, P.off_rb_gidx[k]);
+    B.rx[k] = ws_at<uint32_t>(ws, P.off_rb_ridx[k]);
   }
   B.hist = ws_at<uint32_t>(ws, P.off_rb_hist);
   B.dtot = ws_at<uint32_t>(ws, P.off_rb_dtot);
   B.part = ws_at<uint32_t>(ws, P.off_rb_part);
-  B.pair_rec = ws_at<uint32_t>(ws, P.off_pair_rec);
   B.emit = RbEmit{ws_at<uint64_t>(ws, P.off_keys), ws_at<uint32_t>(ws, P.off_vals),
-                  ws_at<uint32_t>(ws, P.off_sorted_rec), B.pair_rec, ws_at<Rec>(ws, P.off_rec),
+                  ws_at<uint32_t>(ws, P.off_sorted_rec), ws_at<Rec>(ws, P.off_rec),
                   ws_at<Rec>(ws, P.off_srec)};
   return B;
 }
 
-// One stable pass over the keys counted by flag `which`.
+// One stable pass over the keys counted by flag `which`; vin2 / vout2: a
+// second value array carried along (null: none).
 void rb_pass(const RbBuffers& B, hipStream_t s, const uint32_t* kin, const uint32_t* vin,
-             uint32_t* kout, uint32_t* vout, bool emit, int which, int64_t nb_cap, int shift,
-             int bits) {
+             const uint32_t* vin2, uint32_t* kout, uint32_t* vout, uint32_t* vout2, bool emit,
+             int which, int64_t nb_cap, int shift, int bits) {
   const dim3 grid((unsigned)nb_cap), block(kRbThreads);
   hipLaunchKernelGGL(k_rb_hist, grid, block, 0, s, kin, B.fl, which, B.hist, nb_cap, shift, bits);
   hipLaunchKernelGGL(k_rb_digit_scan, dim3(1u << bits), block, 0, s, B.hist, B.fl, which, B.dtot,
                      nb_cap);
-  if (emit) {
-    hipLaunchKernelGGL(k_rb_scatter<true>, grid, block, 0, s, kin, vin, kout, vout, B.emit, B.fl,
-                       which, B.hist, B.dtot, nb_cap, shift, bits);
+#define GS_RB_SCATTER(E, T, OUT)                                                                \
+  hipLaunchKernelGGL((k_rb_scatter<E, T>), grid, block, 0, s, kin, vin, vin2, kout, vout, vout2, \
+                     OUT, B.fl, which, B.hist, B.dtot, nb_cap, shift, bits)
+  if (emit) {  // (the lists' record ids come along as second values)
+    GS_RB_SCATTER(true, true, B.emit);
   } else {
-    hipLaunchKernelGGL(k_rb_scatter<false>, grid, block, 0, s, kin, vin, kout, vout, RbEmit{},
-                       B.fl, which, B.hist, B.dtot, nb_cap, shift, bits);
+    if (vin2) GS_RB_SCATTER(false, true, RbEmit{});
+    else GS_RB_SCATTER(false, false, RbEmit{});
   }
+#undef GS_RB_SCATTER
 }
 
 }  // namespace
@@ -491,8 +499,8 @@ hipError_t launch_rb_generate(const Plan& P, void* ws, hipStream_t s) {
   for (int p = 0; p < 4; ++p) {
     const uint32_t* kin = B.dk[p & 1];
     const uint32_t* vin = p == 0 ? B.vis : B.rid[p & 1];
-    rb_pass(B, s, kin, vin, B.dk[(p + 1) & 1], B.rid[(p + 1) & 1], false, F_VISIBLE,
-            P.rb_rec_blocks, 8 * p, 8);
+    rb_pass(B, s, kin, vin, nullptr, B.dk[(p + 1) & 1], B.rid[(p + 1) & 1], nullptr, false,
+            F_VISIBLE, P.rb_rec_blocks, 8 * p, 8);
   }
   const int64_t gb = rb_gen_blocks(P.n_rec);
   hipLaunchKernelGGL(k_rb_gen_count, dim3((unsigned)gb), dim3(kRbThreads), 0, s, B.rid[0], B.tt,
@@ -500,7 +508,7 @@ hipError_t launch_rb_generate(const Plan& P, void* ws, hipStream_t s) {
   hipLaunchKernelGGL(k_rb_gen_scan, dim3(1), dim3(kRbThreads), 0, s, B.fl, B.part);
   hipLaunchKernelGGL(k_rb_generate, dim3((unsigned)gb), dim3(kRbThreads), 0, s, B.rid[0], B.tt,
                      B.poff, ws_at<ushort4>(ws, P.off_rect), P.n, P.vt, B.fl, B.part, B.tk[0],
-                     B.gx[0], B.pair_rec);
+                     B.gx[0], B.rx[0]);
   return hipGetLastError();
 }
 
@@ -517,8 +525,9 @@ hipError_t launch_rb_tile_sort(const Plan& P, void* ws, hipStream_t s) {
     const int shift = p * width;
     const int bits = std::min(width, tb - shift);
     const bool last = p == passes - 1;
-    rb_pass(B, s, B.tk[cur], B.gx[cur], last ? nullptr : B.tk[cur ^ 1],
-            last ? nullptr : B.gx[cur ^ 1], last, F_PAIRS, P.rb_pair_blocks, shift, bits);
+    rb_pass(B, s, B.tk[cur], B.gx[cur], B.rx[cur], last ? nullptr : B.tk[cur ^ 1],
+            last ? nullptr : B.gx[cur ^ 1], last ? nullptr : B.rx[cur ^ 1], last, F_PAIRS,
+            P.rb_pair_blocks, shift, bits);
     cur ^= 1;
   }
   return hipGetLastError();

@@ -102,10 +102,10 @@ struct Plan {
   int64_t scan_rounds;
   size_t off_scan_part;
   // radix binning (GS_RADIX_BIN): depth keys and record ids of the visible
-  // records (two buffers each), tile keys and generation indices of the
-  // pairs (two each), per-block digit counts, digit totals, and the pair
-  // offsets of blocks of depth-sorted records
-  size_t off_rb_dkey[2], off_rb_rid[2], off_rb_tkey[2], off_rb_gidx[2];
+  // records (two buffers each), tile keys, generation indices and record
+  // ids of the pairs (two each), per-block digit counts, digit totals, and
+  // the pair offsets of blocks of depth-sorted records
+  size_t off_rb_dkey[2], off_rb_rid[2], off_rb_tkey[2], off_rb_gidx[2], off_rb_ridx[2];
   size_t off_rb_hist, off_rb_dtot, off_rb_part;
   int64_t rb_rec_blocks, rb_pair_blocks;
   size_t ws_size;
