@@ -409,7 +409,7 @@ def bench_batched(args, dev, workload, search=False, marks=True, scheduled=False
         best, table = tune.autotune(params, cams, view_wh, target_rgb, target_depth, adam_lrs=LRS,
                                     persistent=True, tiles=[(8, 8), (16, 8), (16, 16)],
                                     lds_batches=[64, 128], chunks=[1, 2], backwards=["splat"],
-                                    reps=4)
+                                    binnings=["tiles", "radix"], reps=4)
     else:
         best = {"tile": args.tile, "lds_batch": args.lds_batch, "chunk": args.chunk,
                 "backward": args.bwd}
@@ -771,9 +771,9 @@ def main():
     ap.add_argument("--lds-batch", type=int, default=64)
     ap.add_argument("--chunk", type=int, default=1)
     ap.add_argument("--bwd", default="splat", choices=["pixel", "splat"])
-    ap.add_argument("--binning", default="tiles", choices=["tiles", "radix"],
+    ap.add_argument("--binning", default="radix", choices=["tiles", "radix"],
                     help="tile binning: per-tile slot claims and sorts, or the two radix sorts")
-    ap.add_argument("--order", default="generated", choices=["generated", "spatial"],
+    ap.add_argument("--order", default="spatial", choices=["generated", "spatial"],
                     help="layout of the batched workloads' pools: as generated (random "
                          "order) or sorted by the Morton code of the means")
     ap.add_argument("--no-marks", action="store_true",
@@ -836,6 +836,9 @@ def main():
                    "tile": f"{tile[0]}x{tile[1]}", "lds_batch": head["config"]["lds_batch"],
                    "chunk": head["config"]["chunk"], "persistent": True,
                    "binning": head["config"]["binning"],
+                   "pool_order": ("sorted by the Morton code of the means (the mapping loop's "
+                                  "layout; untimed set-up)" if args.order == "spatial"
+                                  else "as generated"),
                    "backward": head["config"]["backward"]},
         "trials": args.trials,
         "timing": "median over trials of HIP events around --steps graph replays",

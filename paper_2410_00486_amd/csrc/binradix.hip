@@ -33,13 +33,13 @@ constexpr int kRbThreads = 256;
 constexpr int kRbItems = 16;
 constexpr int kRbTile = kRbThreads * kRbItems;  // keys per block
 constexpr int kRbWaves = kRbThreads / kWave;
-constexpr int kRbMaxBits = 8;
+constexpr int kRbMaxBits = 9;  // tile passes: 18 bits of tile id in two
 constexpr int kRbMaxRadix = 1 << kRbMaxBits;
 // depth-sorted records per block of the pair generation (4 per thread)
 constexpr int kGenRecs = 1024;
 constexpr int kGenPer = kGenRecs / kRbThreads;
 
-static_assert(kRbThreads == kRbMaxRadix, "one thread per digit in the block scans");
+static_assert(kRbMaxRadix == 2 * kRbThreads, "two digits per thread in the block scans");
 
 // Number of keys a pass sorts: a flag of the workspace, zero after a pair
 // overflow (then nothing is generated or written).
@@ -127,8 +127,7 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_hist(const uint32_t* __restri
     if (valid && (peers & lt) == 0) h[w][d] += (uint32_t)__popcll(peers);
   }
   __syncthreads();
-  const int d = threadIdx.x;
-  if (d <= (int)mask) {
+  for (int d = threadIdx.x; d <= (int)mask; d += kRbThreads) {
     uint32_t s = 0;
 #pragma unroll
     for (int k = 0; k < kRbWaves; ++k) s += h[k][d];
@@ -192,13 +191,16 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
   __shared__ uint32_t ws[kRbWaves];
   __shared__ uint32_t sk[kRbTile], sv[kRbTile], sv2[TWO ? kRbTile : 1];
   const int w = threadIdx.x / kWave, lane = lane_id();
-  const int d_own = threadIdx.x;  // the digit this thread handles in the block scans
+  // the two consecutive digits this thread handles in the block scans
+  const int d0 = 2 * (int)threadIdx.x, d1 = d0 + 1;
   const uint32_t mask = (1u << bits) - 1u;
+  const bool h0 = d0 <= (int)mask, h1 = d1 <= (int)mask;
   for (int k = threadIdx.x; k < kRbWaves * kRbMaxRadix; k += kRbThreads) (&wcnt[0][0])[k] = 0u;
   {
-    const uint32_t x = d_own <= (int)mask ? dtot[d_own] : 0u;
-    const uint32_t ex = rb_block_exscan(x, ws);  // (its barrier also orders the clear)
-    if (d_own <= (int)mask) gofs[d_own] = ex + hist[(int64_t)d_own * nb_cap + blockIdx.x];
+    const uint32_t x0 = h0 ? dtot[d0] : 0u, x1 = h1 ? dtot[d1] : 0u;
+    const uint32_t ex = rb_block_exscan(x0 + x1, ws);  // (its barrier also orders the clear)
+    if (h0) gofs[d0] = ex + hist[(int64_t)d0 * nb_cap + blockIdx.x];
+    if (h1) gofs[d1] = ex + x0 + hist[(int64_t)d1 * nb_cap + blockIdx.x];
   }
   uint32_t key[kRbItems], val[kRbItems], val2[kRbItems], rank[kRbItems];
   const uint64_t lt = lanemask_lt();
@@ -221,17 +223,23 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
   {
     // per digit: exclusive prefix over the waves, then the block-local
     // start of the digit's run
-    uint32_t tot = 0;
-    if (d_own <= (int)mask) {
+    uint32_t t0 = 0, t1 = 0;
 #pragma unroll
-      for (int k = 0; k < kRbWaves; ++k) {
-        const uint32_t c = wcnt[k][d_own];
-        wcnt[k][d_own] = tot;
-        tot += c;
+    for (int k = 0; k < kRbWaves; ++k) {
+      if (h0) {
+        const uint32_t c = wcnt[k][d0];
+        wcnt[k][d0] = t0;
+        t0 += c;
+      }
+      if (h1) {
+        const uint32_t c = wcnt[k][d1];
+        wcnt[k][d1] = t1;
+        t1 += c;
       }
     }
-    const uint32_t ex = rb_block_exscan(tot, ws);
-    if (d_own <= (int)mask) lstart[d_own] = ex;
+    const uint32_t ex = rb_block_exscan(t0 + t1, ws);
+    if (h0) lstart[d0] = ex;
+    if (h1) lstart[d1] = ex + t0;
   }
   __syncthreads();
 #pragma unroll
@@ -512,7 +520,7 @@ hipError_t launch_rb_generate(const Plan& P, void* ws, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Step 4: the pairs by tile id, as many passes of at most 8 bits as the
+// Step 4: the pairs by tile id, as many passes of at most 9 bits as the
 // plan's tile bits need (equal widths); the last writes the sorted lists.
 hipError_t launch_rb_tile_sort(const Plan& P, void* ws, hipStream_t s) {
   const RbBuffers B = rb_buffers(P, ws);

@@ -192,3 +192,21 @@ def test_radix_bin_overflow_and_empty_inputs():
     np.testing.assert_allclose(col[0], 0.1, rtol=0, atol=1e-7)
     g = grads_np(it)
     assert all((g[f] == 0).all() for f in g)
+
+
+def test_autotuner_searches_the_binning():
+    """The autotuner times both binnings (and the other dimensions it is
+    given) as captured graphs and returns the fastest, with its binning."""
+    from paper_2410_00486_amd import tune
+    w = workload(1)
+    cam = w.cameras[0]
+    tgt = t32(w.target_rgb[0].reshape(-1))
+    g = gsr.Gaussians.from_scene(w.scene, DEV)
+    print("autotuner over tiles / radix binning", flush=True)
+    best, table = tune.autotune(g, gsr.cameras_tensor([cam], DEV), [(cam.width, cam.height)],
+                                target_rgb=tgt, adam_lrs=LRS, tiles=[(16, 16)], lds_batches=[64],
+                                chunks=[1], backwards=["splat"], binnings=["tiles", "radix"],
+                                reps=2)
+    assert sorted(r["binning"] for r in table) == ["radix", "tiles"]
+    assert all(r["overflow"] == 0 and r["ms"] > 0 for r in table)
+    assert best["binning"] in ("tiles", "radix") and best["ms"] == min(r["ms"] for r in table)
