@@ -657,7 +657,9 @@ def bench_extras(args, dev):
     # the mapping loop: densify every 10 iterations (tau_p 0.001, eps_alpha 0.02)
     mp = gsr.Mapper(gsr.Gaussians(*[t.clone() for t in params.tensors()], params.sh_degree),
                     cams, view_wh, trgb, tdep, LRS, tile=tile, lds_batch=args.lds_batch,
-                    flags=splat, densify_every=10, extent=6.0, seed=1, stream=stream)
+                    flags=splat | (L.GS_RADIX_BIN if args.binning == "radix" else 0),
+                    densify_every=10, extent=6.0, seed=1, stream=stream,
+                    spatial_order=args.order == "spatial")
     n0 = mp.g.n
     torch.cuda.synchronize()
     t0 = time.perf_counter()
