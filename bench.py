@@ -742,6 +742,36 @@ def cpu_baseline(w16, w2):
             break
     _omp_threads(threads)
     log(f"oracle: {reps1} one-view iterations in {dt1:.1f}s on 1 thread")
+    # every configuration on all cores (the batched ones on two views, one
+    # close-up and one overview, extrapolated by pair count)
+    from synth import scenes
+    per_config = {}
+    for name, w, idx in (("slab_128x96", scenes.slab_128x96(), [0]), ("room_1200x680", w2, [0]),
+                         ("room_640x480_pose", scenes.room_640x480_pose(), [0]),
+                         ("keyframes8_mixed", scenes.keyframes8_mixed(), [1, 0]),
+                         ("keyframes16_1200x680", w16, [0, 8])):
+        cams = [w.cameras[i] for i in idx]
+        src = w.target_scene if w.target_scene is not None else w.scene
+        tg = []
+        for cam in cams:
+            r = oracle.render(src, cam, (8, 8))
+            tg.append((r["color"], r["depth"]))
+        reps_c, t0 = 0, time.perf_counter()
+        while True:
+            oracle_iteration(oracle, w.scene, cams, tg)
+            reps_c += 1
+            dtc = time.perf_counter() - t0
+            if dtc >= 2.0 or reps_c >= 5:
+                break
+        ms = dtc / reps_c * 1e3
+        entry = {"ms_per_iter": round(ms, 1), "views_timed": len(cams)}
+        if len(cams) < len(w.cameras):
+            pa = [int(oracle.preprocess(w.scene, c, (8, 8))["tiles_touched"].sum())
+                  for c in w.cameras]
+            entry["ms_per_iter_extrapolated"] = round(ms * sum(pa) / sum(pa[i] for i in idx), 1)
+            entry["extrapolation"] = "by pair count over all views"
+        per_config[name] = entry
+    log(f"oracle per configuration on {threads} threads: {per_config}")
     return {"value": round(1.0 / s_full, 5), "unit": "iters/s", "cores": threads, "kind": "oracle",
             "sample": (f"{reps} FP64 iterations (render, L1, backward, Adam on all 2M Gaussians) of "
                        f"views 0 and 8 of the 16-view 2M-Gaussian batch, {s_sub:.2f} s each on "
@@ -750,7 +780,8 @@ def cpu_baseline(w16, w2):
             "ms_per_iter_two_views": round(s_sub * 1e3, 1),
             "single_thread": {"value": round(reps1 / dt1, 5), "unit": "iters/s", "cores": 1,
                               "sample": f"{reps1} one-view iterations of the 1200x680 / 300k "
-                                        f"room ({dt1:.1f} s)"}}
+                                        f"room ({dt1:.1f} s)"},
+            "per_config_all_cores": per_config}
 
 
 # ---------------------------------------------------------------- main
