@@ -686,10 +686,17 @@ __device__ __forceinline__ void splat_wave(
   double2* sc = pxc + seg * NPX;  // sample point of each pixel
 
   // pixel table of the segment's tile: loss gradients, P, last position,
-  // stored state (T, Q); an inactive segment gets last = 0 (nothing blended)
-  for (int j = ls; j < NPX; j += SEG) {
+  // stored state (T, Q), kept only for the pixels whose last position lies
+  // past the bucket's first splat.  At any other pixel no lane of the bucket
+  // is blended, so every term it adds is zero: the table holds the others
+  // in pixel order, and the loop below runs over them alone.
+  const uint64_t segmask = SEG == 64 ? ~0ull : (0xFFFFFFFFull << (32 * seg));
+  const uint64_t below = lanemask_lt() & segmask;
+  uint32_t kept = 0;
+  for (int j = ls; j < NPX; j += SEG) {  // (NPX is a multiple of SEG: uniform)
     const int px = tx0 + (j & (TW - 1)), py = ty0 + (j >> LOG_TW);
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 1.f, 0.f);
+    bool keep = false;
     if (active && px < vi.W && py < vi.H) {
       const float* cp = ckpt + (int64_t)(boff[gtile] + k) * (kStateFloats * NPX);
       const int64_t pl = (int64_t)py * vi.W + px;
@@ -717,16 +724,34 @@ __device__ __forceinline__ void splat_wave(
         a.w = dL_ddepth ? dL_ddepth[pix] : 0.0f;
       }
       b.x = a.x * o0 + a.y * o1 + a.z * o2 + a.w * od;
-      b.y = __uint_as_float(last[pix]);
-      if (k > 0) {  // the first bucket starts from T = 1 and nothing accumulated
+      const uint32_t lp = last[pix];
+      b.y = __uint_as_float(lp);
+      keep = lp > q0;
+      if (keep && k > 0) {  // the first bucket starts from T = 1 and nothing accumulated
         b.z = cp[j];
         b.w = a.x * cp[NPX + j] + a.y * cp[2 * NPX + j] + a.z * cp[3 * NPX + j] + a.w * cp[4 * NPX + j];
       }
     }
-    sa[j] = a;
-    sb[j] = b;
-    sc[j] = make_double2((double)px + 0.5, (double)py + 0.5);
+    const uint64_t m = ballot64(keep) & segmask;
+    if (keep) {
+      const uint32_t e = kept + (uint32_t)__popcll(m & below);
+      sa[e] = a;
+      sb[e] = b;
+      sc[e] = make_double2((double)px + 0.5, (double)py + 0.5);
+    }
+    kept += (uint32_t)__popcll(m);
   }
+  // two half-wave segments step together, two pixels a step: a table with
+  // fewer entries is padded with pixels at which nothing is blended (last = 0)
+  const uint32_t most = SEG == 64 ? kept : max(kept, (uint32_t)__shfl_xor((int)kept, 32));
+  const uint32_t steps = (most + 1u) & ~1u;
+  for (uint32_t e = kept + (uint32_t)ls; e < steps; e += SEG) {
+    sa[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    sb[e] = make_float4(0.f, 0.f, 1.f, 0.f);
+    sc[e] = make_double2(0.5, 0.5);
+  }
+  const int nsteps = __builtin_amdgcn_readfirstlane((int)steps);
+  __builtin_assume((nsteps & 1) == 0);
   __syncthreads();
 
   Rec r;
@@ -744,8 +769,8 @@ __device__ __forceinline__ void splat_wave(
 #pragma unroll
   for (int f = 0; f < 10; ++f) g[f] = 0.0f;
 #pragma unroll 2
-  for (int j = 0; j < NPX; ++j) {
-    const float4 b = sb[j];  // P, last, T_in, Q_in of the segment's pixel j
+  for (int j = 0; j < nsteps; ++j) {
+    const float4 b = sb[j];  // P, last, T_in, Q_in of the segment's j-th kept pixel
     const double2 sxy = sc[j];
     // alpha as in the forward (same bits)
     const double dx = r.mx - sxy.x, dy = r.my - sxy.y;
@@ -794,7 +819,7 @@ __device__ __forceinline__ void splat_wave(
 // Grid-stride over the work of the two queues: one bucket per wave from
 // the first, two per wave from the second.
 template <int TW, int TH>
-__global__ void __launch_bounds__(kWave) k_render_bwd_splat(
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) k_render_bwd_splat(
     const Rec* __restrict__ lrec,
     const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ tile_last, const uint32_t* __restrict__ boff,
