@@ -81,9 +81,11 @@ typedef int32_t gs_status;
                                          of per-tile slot claims and per-tile sorts;
                                          the projection then counts no pairs per
                                          tile (the lists give the counts); same
-                                         lists, bit for bit.  Needs about 16 B per
-                                         record and 24 B per pair of capacity
-                                         more workspace */
+                                         lists, bit for bit.  The raster kernels
+                                         then read each pair's record through its
+                                         record id (no copy of the records in list
+                                         order).  About 16 B per record more and
+                                         52 B per pair of capacity less workspace */
 
 /* Gaussian parameters (Sec. III-B): SoA, float32, device pointers. */
 typedef struct gs_gaussians {

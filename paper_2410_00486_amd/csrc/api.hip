@@ -227,12 +227,17 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_tile_cnt = take(T * 4);
   P->off_tile_start = take(T * 4);
   P->off_long = take(T * 16);  // (tile, list start, pairs, -) per long list
+  // the per-tile binning's scattered keys, pair records and record copies
+  // in list order; the radix binning has buffers of its own (below) and
+  // its lists name their records
+  const bool radix = (cfg->flags & GS_RADIX_BIN) != 0;
+  const size_t tcap = radix ? 0 : cap;
   P->off_keys = take(cap * 8);
-  P->off_scatter = take(cap * 8);
+  P->off_scatter = take(tcap * 8);
   P->off_vals = take(cap * 4);
-  P->off_pair_rec = take(cap * 4);
+  P->off_pair_rec = take(tcap * 4);
   P->off_sorted_rec = take(cap * 4);
-  P->off_srec = take(cap * sizeof(Rec));
+  P->off_srec = take(tcap * sizeof(Rec));
   P->off_ranges = take(T * 2 * 4);
   P->off_tile_last = take(T * 4);
   P->off_tile_loss = take(T * 2 * 4);
@@ -256,7 +261,6 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->scan_rounds = scan_rounds(*P);
   P->off_scan_part = take((size_t)P->scan_rounds * 64);
   // radix binning buffers, only when the plan asks for that binning
-  const bool radix = (cfg->flags & GS_RADIX_BIN) != 0;
   P->rb_rec_blocks = radix ? rb_blocks(P->n_rec) : 0;
   P->rb_pair_blocks = radix ? rb_blocks(pair_capacity) : 0;
   const size_t rrec = radix ? nrec * 4 : 0, rpair = radix ? cap * 4 : 0;

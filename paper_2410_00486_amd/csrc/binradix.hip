@@ -166,8 +166,7 @@ struct RbEmit {
   uint64_t* keys;          // tile << 32 | depth bits
   uint32_t* vals;          // generation index
   uint32_t* sorted_rec;    // record id
-  const Rec* rec;
-  Rec* lrec;               // records in list order
+  const Rec* rec;          // (read for the depth of each pair's record)
 };
 
 // Downsweep: stable ranking of the block's keys by digit, reorder in LDS,
@@ -264,26 +263,18 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
       if (TWO) vals2_out[pos] = sv2[i];
     }
   } else {
-    // the record ids came along as second values; the record copies go
-    // four records in flight at a time
+    // the record ids came along as second values; each pair's key takes
+    // the depth of its record, gathered G records in flight at a time
     static_assert(TWO, "the last tile pass carries the record ids");
-    uint32_t rid[kRbItems];
-#pragma unroll
-    for (int q = 0; q < kRbItems; ++q) {
-      const int i = threadIdx.x + q * kRbThreads;
-      rid[q] = i < nloc ? sv2[i] : 0u;
-    }
-    constexpr int G = 4;
+    constexpr int G = 8;
 #pragma unroll
     for (int q0 = 0; q0 < kRbItems; q0 += G) {
-      float4 a[G][4];
+      uint32_t rid[G], zb[G];
 #pragma unroll
       for (int u = 0; u < G; ++u) {
         const int i = threadIdx.x + (q0 + u) * kRbThreads;
-        if (i < nloc) {
-          const float4* src = reinterpret_cast<const float4*>(E.rec + rid[q0 + u]);
-          a[u][0] = src[0]; a[u][1] = src[1]; a[u][2] = src[2]; a[u][3] = src[3];
-        }
+        rid[u] = i < nloc ? sv2[i] : 0u;
+        zb[u] = i < nloc ? __float_as_uint(E.rec[rid[u]].z) : 0u;
       }
 #pragma unroll
       for (int u = 0; u < G; ++u) {
@@ -292,11 +283,9 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
           const uint32_t t = sk[i];
           const uint32_t d = (t >> shift) & mask;
           const uint32_t pos = gofs[d] + (uint32_t)i - lstart[d];
-          float4* dst = reinterpret_cast<float4*>(E.lrec + pos);
-          dst[0] = a[u][0]; dst[1] = a[u][1]; dst[2] = a[u][2]; dst[3] = a[u][3];
-          E.keys[pos] = ((uint64_t)t << 32) | __float_as_uint(a[u][2].w);  // .w of the third: depth
+          E.keys[pos] = ((uint64_t)t << 32) | zb[u];
           E.vals[pos] = sv[i];
-          E.sorted_rec[pos] = rid[q0 + u];
+          E.sorted_rec[pos] = rid[u];
         }
       }
     }
@@ -459,8 +448,7 @@ RbBuffers rb_buffers(const Plan& P, void* ws) {
   B.dtot = ws_at<uint32_t>(ws, P.off_rb_dtot);
   B.part = ws_at<uint32_t>(ws, P.off_rb_part);
   B.emit = RbEmit{ws_at<uint64_t>(ws, P.off_keys), ws_at<uint32_t>(ws, P.off_vals),
-                  ws_at<uint32_t>(ws, P.off_sorted_rec), ws_at<Rec>(ws, P.off_rec),
-                  ws_at<Rec>(ws, P.off_srec)};
+                  ws_at<uint32_t>(ws, P.off_sorted_rec), ws_at<Rec>(ws, P.off_rec)};
   return B;
 }
 

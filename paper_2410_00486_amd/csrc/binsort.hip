@@ -815,16 +815,18 @@ TileSortArgs tile_sort_args(const Plan& P, void* ws) {
   A.cnt = ws_at<uint32_t>(ws, P.off_tile_cnt);
   A.tstart = ws_at<uint32_t>(ws, P.off_tile_start);
   A.fl = ws_at<int32_t>(ws, P.off_flags);
-  A.skey = ws_at<uint64_t>(ws, P.off_scatter);
+  const bool radix = (P.cfg.flags & GS_RADIX_BIN) != 0;  // (no scattered keys, no copies)
+  A.skey = radix ? nullptr : ws_at<uint64_t>(ws, P.off_scatter);
   A.out = TileSortOut{ws_at<uint64_t>(ws, P.off_keys), ws_at<uint32_t>(ws, P.off_vals),
-                      ws_at<uint32_t>(ws, P.off_sorted_rec), ws_at<uint32_t>(ws, P.off_pair_rec),
-                      ws_at<Rec>(ws, P.off_rec), ws_at<Rec>(ws, P.off_srec)};
+                      ws_at<uint32_t>(ws, P.off_sorted_rec),
+                      radix ? nullptr : ws_at<uint32_t>(ws, P.off_pair_rec),
+                      ws_at<Rec>(ws, P.off_rec), radix ? nullptr : ws_at<Rec>(ws, P.off_srec)};
   A.ranges = ws_at<uint32_t>(ws, P.off_ranges);
   A.fstart = splat ? ws_at<uint32_t>(ws, P.off_full_start) : nullptr;
   A.hstart = splat ? ws_at<uint32_t>(ws, P.off_half_start) : nullptr;
   A.bq = splat ? ws_at<uint2>(ws, P.off_bq) : nullptr;
   A.bq_stride = P.ckpt_slots;
-  A.presorted = (P.cfg.flags & GS_RADIX_BIN) != 0;
+  A.presorted = radix;
   A.long_after = !A.presorted;
   return A;
 }

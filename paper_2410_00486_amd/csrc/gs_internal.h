@@ -65,6 +65,18 @@ struct __align__(16) Rec {
 };
 static_assert(sizeof(Rec) == 64, "record must be 64 bytes");
 
+// Where the raster kernels read the records of the tile lists: a copy in
+// list order written by the binning (idx null: list position k is base[k]),
+// or the per-view record array itself, through each pair's record id
+// (base[idx[k]]).
+struct RecSrc {
+  const Rec* base;
+  const uint32_t* idx;
+  __device__ __forceinline__ const Rec* at(uint32_t k) const {
+    return idx ? base + idx[k] : base + k;
+  }
+};
+
 // Per-pair gradient partial written by the backward raster kernel:
 // rgb(3), depth, opacity, conic a b c, mean x y (+2 pad), 48 bytes.
 constexpr int kPairGrad = 12;

@@ -125,18 +125,19 @@ __device__ __forceinline__ int find_view(const ViewTable& vt, int gtile) {
   return v;
 }
 
-// Records of a tile list are stored in list order (written by the
-// binning), so a batch is one contiguous, coalesced read.  fresh: the
-// records were written by this wavefront in this kernel, so they are read
-// at device scope, past the vector L1 (which may hold an older copy of the
-// line, loaded for a neighbouring tile).
-__device__ __forceinline__ void stage(Rec* srec, uint32_t* sval, const Rec* __restrict__ lrec,
+// Records of a tile list: a copy in list order written by the per-tile
+// binning, so that a batch is one contiguous, coalesced read, or (radix
+// binning) gathered from the record array by record id.  fresh (a copy
+// only): the records were written by this wavefront in this kernel, so they
+// are read at device scope, past the vector L1 (which may hold an older copy
+// of the line, loaded for a neighbouring tile).
+__device__ __forceinline__ void stage(Rec* srec, uint32_t* sval, RecSrc lrec,
                                       const uint32_t* __restrict__ sorted_vals, uint32_t first,
                                       int count, int lane, bool fresh = false) {
   for (int k = lane; k < count; k += kWave) {
     uint64_t* dst = reinterpret_cast<uint64_t*>(srec + k);
     if (fresh) {
-      const uint64_t* src = reinterpret_cast<const uint64_t*>(lrec + first + k);
+      const uint64_t* src = reinterpret_cast<const uint64_t*>(lrec.base + first + k);
       uint64_t w[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q)
@@ -144,7 +145,7 @@ __device__ __forceinline__ void stage(Rec* srec, uint32_t* sval, const Rec* __re
 #pragma unroll
       for (int q = 0; q < 8; ++q) dst[q] = w[q];
     } else {
-      const float4* src = reinterpret_cast<const float4*>(lrec + first + k);
+      const float4* src = reinterpret_cast<const float4*>(lrec.at(first + k));
       float4* d4 = reinterpret_cast<float4*>(dst);
       const float4 a0 = src[0], a1 = src[1], a2 = src[2], a3 = src[3];
       d4[0] = a0; d4[1] = a1; d4[2] = a2; d4[3] = a3;
@@ -155,7 +156,7 @@ __device__ __forceinline__ void stage(Rec* srec, uint32_t* sval, const Rec* __re
 
 // ------------------------------------------------------------------ forward
 template <int TW, int TH, bool CKPT>
-__device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec,
+__device__ __forceinline__ void fwd_tile(int gtile, RecSrc lrec,
                                          const uint32_t* __restrict__ ranges,
                                          const float* __restrict__ cams, const ViewTable& vt,
                                          int B, float* __restrict__ color,
@@ -333,7 +334,7 @@ __device__ __forceinline__ void fwd_tile(int gtile, const Rec* __restrict__ lrec
 
 template <int TW, int TH, bool CKPT>
 __global__ void __launch_bounds__(kWave) k_render_fwd(
-    const Rec* __restrict__ lrec,
+    RecSrc lrec,
     const uint32_t* __restrict__ ranges, const float* __restrict__ cams, ViewTable vt, int B,
     float* __restrict__ color, float* __restrict__ depth, float* __restrict__ T_final,
     uint32_t* __restrict__ last, uint32_t* __restrict__ tile_last,
@@ -394,7 +395,7 @@ __global__ void __launch_bounds__(kLossThreads) k_loss_reduce(const float* __res
 // ------------------------------------------------------------------ backward
 template <int TW, int TH>
 __device__ __forceinline__ void bwd_tile(
-    int gtile, const Rec* __restrict__ lrec,
+    int gtile, RecSrc lrec,
     const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ tile_last, const float* __restrict__ cams, const ViewTable& vt,
     int B, const float* __restrict__ color, const float* __restrict__ depth,
@@ -537,7 +538,7 @@ __device__ __forceinline__ void bwd_tile(
 
 template <int TW, int TH>
 __global__ void __launch_bounds__(kWave) k_render_bwd(
-    const Rec* __restrict__ lrec,
+    RecSrc lrec,
     const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ tile_last, const float* __restrict__ cams, ViewTable vt, int B,
     const float* __restrict__ color, const float* __restrict__ depth,
@@ -641,7 +642,7 @@ __device__ __forceinline__ float seg_scan_add(float x) {
 template <int TW, int TH, int SEG>
 __device__ __forceinline__ void splat_wave(
     const uint2* __restrict__ queue, uint32_t q_first, uint32_t q_count,
-    const Rec* __restrict__ lrec,
+    RecSrc lrec,
     const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ tile_last, const uint32_t* __restrict__ boff,
     const float* __restrict__ ckpt, const ViewTable& vt, const float* __restrict__ color,
@@ -756,7 +757,7 @@ __device__ __forceinline__ void splat_wave(
 
   Rec r;
   if (live) {
-    const float4* src = reinterpret_cast<const float4*>(lrec + s + pos);
+    const float4* src = reinterpret_cast<const float4*>(lrec.at(s + pos));
     float4* dst = reinterpret_cast<float4*>(&r);
     dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2]; dst[3] = src[3];
   } else {
@@ -820,7 +821,7 @@ __device__ __forceinline__ void splat_wave(
 // the first, two per wave from the second.
 template <int TW, int TH>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) k_render_bwd_splat(
-    const Rec* __restrict__ lrec,
+    RecSrc lrec,
     const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ tile_last, const uint32_t* __restrict__ boff,
     const float* __restrict__ ckpt, const uint2* __restrict__ bq, int64_t bq_stride,
@@ -846,6 +847,13 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7)))
   }
 }
 
+// The radix binning writes no record copy: its lists name their records.
+RecSrc rec_src(const Plan& P, void* ws) {
+  if (P.cfg.flags & GS_RADIX_BIN)
+    return RecSrc{ws_at<Rec>(ws, P.off_rec), ws_at<uint32_t>(ws, P.off_sorted_rec)};
+  return RecSrc{ws_at<Rec>(ws, P.off_srec), nullptr};
+}
+
 template <int TW, int TH>
 hipError_t bwd_splat_launch(const Plan& P, void* ws, const float* cams, const float* color,
                             const float* depth, const uint32_t* last, const float* dL_dcolor,
@@ -854,7 +862,7 @@ hipError_t bwd_splat_launch(const Plan& P, void* ws, const float* cams, const fl
                             int grid, hipStream_t s) {
   (void)cams;
   hipLaunchKernelGGL((k_render_bwd_splat<TW, TH>), dim3(grid), dim3(kWave), 0, s,
-                     ws_at<Rec>(ws, P.off_srec), sorted_vals,
+                     rec_src(P, ws), sorted_vals,
                      ws_at<uint32_t>(ws, P.off_ranges), ws_at<uint32_t>(ws, P.off_tile_last),
                      ws_at<uint32_t>(ws, P.off_boff), ws_at<float>(ws, P.off_ckpt),
                      ws_at<uint2>(ws, P.off_bq), P.ckpt_slots, ws_at<int32_t>(ws, P.off_flags),
@@ -873,14 +881,14 @@ hipError_t fwd_launch(const Plan& P, void* ws, const float* cams, float* color, 
                               sort.cnt ? (size_t)kTileSortSmall * sizeof(uint64_t) : (size_t)0);
   if (P.cfg.flags & GS_SPLAT_BWD) {
     hipLaunchKernelGGL((k_render_fwd<TW, TH, true>), dim3(grid), dim3(kWave), lds, s,
-                       ws_at<Rec>(ws, P.off_srec),
+                       rec_src(P, ws),
                        ws_at<uint32_t>(ws, P.off_ranges), cams, P.vt, B, color, depth, T_final,
                        last, ws_at<uint32_t>(ws, P.off_tile_last), target_rgb, target_depth,
                        ws_at<float>(ws, P.off_tile_loss), order, queue, P.cfg.chunk,
                        ws_at<uint32_t>(ws, P.off_boff), ws_at<float>(ws, P.off_ckpt), sort);
   } else {
     hipLaunchKernelGGL((k_render_fwd<TW, TH, false>), dim3(grid), dim3(kWave), lds, s,
-                       ws_at<Rec>(ws, P.off_srec),
+                       rec_src(P, ws),
                        ws_at<uint32_t>(ws, P.off_ranges), cams, P.vt, B, color, depth, T_final,
                        last, ws_at<uint32_t>(ws, P.off_tile_last), target_rgb, target_depth,
                        ws_at<float>(ws, P.off_tile_loss), order, queue, P.cfg.chunk,
@@ -898,7 +906,7 @@ hipError_t bwd_launch(const Plan& P, void* ws, const float* cams, const float* c
   const int B = P.cfg.lds_batch;
   const size_t lds = (size_t)B * (sizeof(Rec) + sizeof(uint32_t));
   hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(grid), dim3(kWave), lds, s,
-                     ws_at<Rec>(ws, P.off_srec), sorted_vals,
+                     rec_src(P, ws), sorted_vals,
                      ws_at<uint32_t>(ws, P.off_ranges), ws_at<uint32_t>(ws, P.off_tile_last), cams,
                      P.vt, B, color, depth, T_final, last, dL_dcolor, dL_ddepth, target_rgb,
                      target_depth, fused, P.cfg.lambda_depth,
