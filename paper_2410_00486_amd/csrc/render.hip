@@ -820,7 +820,7 @@ __device__ __forceinline__ void splat_wave(
 // Grid-stride over the work of the two queues: one bucket per wave from
 // the first, two per wave from the second.
 template <int TW, int TH>
-__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) k_render_bwd_splat(
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(TW * TH == 64 ? 7 : 1))) k_render_bwd_splat(
     RecSrc lrec,
     const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ tile_last, const uint32_t* __restrict__ boff,
