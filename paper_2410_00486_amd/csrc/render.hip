@@ -583,10 +583,10 @@ __global__ void __launch_bounds__(kWave) k_render_bwd(
 // the same skip decisions; the forward's stop rule is its stored last
 // position).  What lies in front of lane l's splat at the pixel is the
 // segment's stored state advanced over the blended splats of lanes < l: the
-// transmittance is T_in times an exclusive prefix product of (1 - alpha), and
-// the front part of the loss-weighted output Q = gC . C + gD . D an
-// inclusive prefix sum of alpha T gC . c, both taken across the lanes with
-// DPP.  What lies behind the splat is the final pixel minus the front part,
+// transmittance is T_in times the product of (1 - alpha) over those lanes
+// (the inclusive prefix product divided by the lane's own factor), and the
+// front part of the loss-weighted output Q = gC . C + gD . D an inclusive
+// prefix sum of alpha T gC . c, both taken across the lanes with DPP.  What lies behind the splat is the final pixel minus the front part,
 // P - Q with P = gC . (colour output) + gD . (depth output).  A bucket thus
 // costs one step per pixel, with no pipeline to fill or drain.  Each lane
 // accumulates its own splat's ten partial gradients over the tile's pixels
@@ -595,13 +595,6 @@ __global__ void __launch_bounds__(kWave) k_render_bwd(
 // Buckets with at most 32 pairs share a wavefront: each 32-lane half runs
 // its own bucket (the scans stop at the half), two buckets per NPX steps.
 // The binning queues buckets by size (more than 32 pairs / at most 32).
-
-// DPP move in which a lane without a source (or in a masked row) gets `old`.
-template <int CTRL, int ROW_MASK = 0xF>
-__device__ __forceinline__ float dpp_or(float old, float x) {
-  return __int_as_float(
-      __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), CTRL, ROW_MASK, 0xF, false));
-}
 
 // Inclusive product / sum over segments of SEG (64 or 32) lanes, in place:
 // steps in rows of 16 (row_shr 1, 2, 4, 8), then the ends of rows 0 and 2
@@ -619,12 +612,11 @@ __device__ __forceinline__ float dpp_or(float old, float x) {
   GS_DPP_STEP(OP, "row_bcast:15 row_mask:0xa")
 template <int SEG>
 __device__ __forceinline__ float seg_scan_mul(float x) {
-  // (the trailing wait states cover a DPP read of the result right after)
   if (SEG == 64)
     asm volatile(GS_SEG_SCAN32("v_mul_f32_dpp") GS_DPP_STEP("v_mul_f32_dpp", "row_bcast:31 row_mask:0xc")
-                 "s_nop 1" : "+v"(x));
+                 : "+v"(x));
   else
-    asm volatile(GS_SEG_SCAN32("v_mul_f32_dpp") "s_nop 1" : "+v"(x));
+    asm volatile(GS_SEG_SCAN32("v_mul_f32_dpp") : "+v"(x));
   return x;
 }
 template <int SEG>
@@ -769,8 +761,7 @@ __device__ __forceinline__ void splat_wave(
   float g[10];
 #pragma unroll
   for (int f = 0; f < 10; ++f) g[f] = 0.0f;
-#pragma unroll 2
-  for (int j = 0; j < nsteps; ++j) {
+  auto pixel = [&](int j) {
     const float4 b = sb[j];  // P, last, T_in, Q_in of the segment's j-th kept pixel
     const double2 sxy = sc[j];
     // alpha as in the forward (same bits)
@@ -779,39 +770,48 @@ __device__ __forceinline__ void splat_wave(
     const float G = __builtin_amdgcn_exp2f((float)(pw * kLog2e));
     const float oG = r.o * G;
     const float a = fminf(kAlphaMax, oG);
-    const bool hit = live && pos < __float_as_uint(b.y) && !(pw > 0.0) && a >= kAlphaMin;
+    // (no short-circuit: every term is evaluated, so nothing branches)
+    const bool hit = live & (pos < __float_as_uint(b.y)) & !(pw > 0.0) & (a >= kAlphaMin);
     // (no early exit when no lane is blended at this pixel: rare, and its test costs two VALU per step)
     const float4 gc = sa[j];
     const float om = 1.0f - a;
-    // transmittance in front of the splat
-    const float Tf = b.z * dpp_or<0x138>(1.0f, seg_scan_mul<SEG>(hit ? om : 1.0f));
-    const float Tl = (SEG == 32 && ls == 0) ? b.z : Tf;  // wave_shr crosses the halves
+    const float inv_om = __builtin_amdgcn_rcpf(om);
+    // transmittance in front of the splat: the segment's inclusive product
+    // over its blended splats with the lane's own factor taken out again
+    // (read by blended lanes only, whose factor 1 - alpha >= 0.01)
+    const float Tl = (b.z * seg_scan_mul<SEG>(hit ? om : 1.0f)) * inv_om;
     const float wgt = hit ? a * Tl : 0.0f;
     const float front = fmaf(gc.w, r.z, fmaf(gc.z, r.b, fmaf(gc.y, r.g, gc.x * r.r)));
     const float Qn = b.w + seg_scan_add<SEG>(wgt * front);  // front part after the splat
-    const float inv_om = __builtin_amdgcn_rcpf(om);
     const float g_alpha = fmaf(-(b.x - Qn), inv_om, Tl * front);
     g[0] = fmaf(wgt, gc.x, g[0]);
     g[1] = fmaf(wgt, gc.y, g[1]);
     g[2] = fmaf(wgt, gc.z, g[2]);
     g[3] = fmaf(wgt, gc.w, g[3]);
-    // moments of t = gpow dx, u = gpow dy; the conic and mean partials are
-    // formed from them once, after the pixels
-    const bool open = hit && oG <= kAlphaMax;
+    // moments of gpow = dL/dpower = alpha dL/dalpha (unclamped splats) and
+    // of t = gpow dx, u = gpow dy; the opacity, conic and mean partials are
+    // formed from them once, after the pixels (dL/do = sum gpow / o)
+    const bool open = hit & (oG <= kAlphaMax);
     const float gpow = open ? a * g_alpha : 0.0f;
     const float fx = (float)dx, fy = (float)dy;
     const float t = gpow * fx, u = gpow * fy;
-    g[4] = fmaf(open ? G : 0.0f, g_alpha, g[4]);
+    g[4] += gpow;
     g[5] = fmaf(t, fx, g[5]);
     g[6] = fmaf(t, fy, g[6]);
     g[7] = fmaf(u, fy, g[7]);
     g[8] += t;
     g[9] += u;
+  };
+  // two pixels per iteration (the step count is even): their alpha chains
+  // overlap, the accumulation keeps pixel order
+  for (int j = 0; j < nsteps; j += 2) {
+    pixel(j);
+    pixel(j + 1);
   }
   if (live) {
     float4* gp = reinterpret_cast<float4*>(grad_pair + (int64_t)sorted_vals[s + pos] * kPairGrad);
     gp[0] = make_float4(g[0], g[1], g[2], g[3]);
-    gp[1] = make_float4(g[4], -0.5f * g[5], -g[6], -0.5f * g[7]);
+    gp[1] = make_float4(r.o > 0.0f ? g[4] / r.o : 0.0f, -0.5f * g[5], -g[6], -0.5f * g[7]);
     gp[2] = make_float4(-(ca * g[8] + cb * g[9]), -(cb * g[8] + cc * g[9]), 0.0f, 0.0f);
   }
   __syncthreads();  // the pixel tables are rewritten by the next wave's work

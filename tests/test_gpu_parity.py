@@ -480,6 +480,56 @@ def test_iteration_sparse_adam_equals_separate_calls(lambda_o, degree):
     assert int(it.step_dev.item()) == 2
 
 
+@pytest.mark.parametrize("lambda_o,degree,extra", [
+    (0.0, 3, 0), (0.001, 3, L.GS_RADIX_BIN | L.GS_SPLAT_BWD | L.GS_PERSISTENT),
+    (0.001, 1, L.GS_SPLAT_BWD), (0.0, 0, L.GS_RADIX_BIN)])
+def test_iteration_several_view_adam_equals_separate_calls(lambda_o, degree, extra):
+    """Several views with Adam (the per-record and per-Gaussian projection
+    backward, then one Adam launch over every Gaussian) against the separate
+    calls, two steps: parameters and moments bit for bit, the loss, the
+    step counter once per iteration."""
+    scene0, cams_l = _multi_view_workload()
+    K = (degree + 1) ** 2
+    scene = scenes.Scene(scene0.means, scene0.log_scales, scene0.quats, scene0.opacity_logits,
+                         np.ascontiguousarray(scene0.sh[:, :K]), degree)
+    lrs = {"means": 1e-3, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
+    wh = [(c.width, c.height) for c in cams_l]
+    cams = gsr.cameras_tensor(cams_l, DEV)
+    rng = np.random.default_rng(31)
+    npx = sum(w * h for w, h in wh)
+    tgt = t32(rng.uniform(0.0, 1.0, 3 * npx))
+    tdep = t32(rng.uniform(0.5, 4.0, npx))
+    g1 = gsr.Gaussians.from_scene(scene, DEV)
+    cap = int(gsr.required_pairs(*g1.tensors(), cams, wh, degree, (16, 16)) * 1.3) + 4096
+    flags = L.GS_FUSED_L1 | extra
+    plan = gsr.Plan(scene.n, degree, wh, flags=flags, pair_capacity=cap)
+    print(f"several-view iteration with Adam: lambda_o {lambda_o} degree {degree} flags {flags}",
+          flush=True)
+    it = gsr.Iteration(plan, g1, cams, target_rgb=tgt, target_depth=tdep, adam_lrs=lrs,
+                       lambda_o=lambda_o)
+    g2 = gsr.Gaussians.from_scene(scene, DEV)
+    ws = plan.new_workspace(DEV)
+    fr = gsr.Frame(plan, DEV)
+    grads, m, v = g2.zeros_like(), g2.zeros_like(), g2.zeros_like()
+    groups = gsr.adam_groups(g2, grads, m, v, lrs, lambda_o != 0.0)
+    for step in (1, 2):
+        it.enqueue()
+        gsr.preprocess(plan, ws, g2, cams)
+        gsr.bin_sort(plan, ws)
+        gsr.render_fwd(plan, ws, cams, fr, tgt, tdep)
+        gsr.render_bwd(plan, ws, g2, cams, fr, grads, target_rgb=tgt, target_depth=tdep)
+        gsr.adam_step(groups, step, lambda_o=lambda_o, reg_count=g2.n)
+        torch.cuda.synchronize()
+        assert int(plan.flags_of(it.ws)[L.F_OVERFLOW]) == 0
+        assert int(it.step_dev.item()) == step
+        assert torch.equal(it.frame.loss, fr.loss), step
+        for f in gsr.Gaussians.FIELDS:
+            assert torch.equal(getattr(g1, f), getattr(g2, f)), (step, f)
+            assert torch.equal(getattr(it.m, f), getattr(m, f)), (step, f)
+            assert torch.equal(getattr(it.v, f), getattr(v, f)), (step, f)
+        assert all(bool((x != 0).any()) for x in m.tensors())  # every group stepped
+
+
 @pytest.mark.parametrize("n,extra", [(300, 0), (3000, 0), (300, L.GS_SPLAT_BWD), (3000, L.GS_SPLAT_BWD)])
 def test_iteration_sorting_in_forward_equals_separate_calls(n, extra):
     """A whole iteration lets the forward sort each tile's list (up to 128
