@@ -159,7 +159,8 @@ int32_t* gs_flags_ptr(const gs_plan* plan, void* ws);
 /* Byte offset inside the workspace of an intermediate array, for
  * inspection by tests and tools (-1 for an unknown region):
  *   GS_WS_RECORDS       [n_views*n] 64-byte records: f64 mean x, y; f64
- *                       -a/2, -b, -c/2 of the conic [[a,b],[b,c]]; f32
+ *                       log2(e) times -a/2, -b, -c/2 of the conic
+ *                       [[a,b],[b,c]] (the base-2 exponent's form); f32
  *                       opacity, depth, r, g, b, pad
  *   GS_WS_RECTS         [n_views*n] u16 x0, y0, x1, y1 (tile box, exclusive)
  *   GS_WS_TILES_TOUCHED [n_views*n] u32

@@ -53,8 +53,10 @@ struct ViewTable {
 // kept in FP64: the per-pixel quadratic form d^T Sigma'^-1 d is evaluated in
 // FP64 (full rate on CDNA), which removes the cancellation of an FP32
 // evaluation at large pixel coordinates and for elongated footprints.  The
-// conic is stored pre-scaled so that power = ca dx^2 + cb dx dy + cc dy^2,
-// i.e. ca = -a/2, cb = -b, cc = -c/2 for the conic [[a, b], [b, c]].
+// conic is stored pre-scaled so that the base-2 exponent of the Gaussian is
+// ca dx^2 + cb dx dy + cc dy^2 (G = 2^that, no rescaling per evaluation),
+// i.e. ca = -a/2 log2(e), cb = -b log2(e), cc = -c/2 log2(e) for the conic
+// [[a, b], [b, c]].
 struct __align__(16) Rec {
   double mx, my;
   double ca, cb;
@@ -64,6 +66,8 @@ struct __align__(16) Rec {
   uint32_t clamp;    // bit ch set: channel ch was clamped at 0 (no gradient)
 };
 static_assert(sizeof(Rec) == 64, "record must be 64 bytes");
+constexpr double kLog2e = 1.4426950408889634;  // log2(e): the records' conic scale
+constexpr double kLn2 = 0.6931471805599453;    // ln(2), its inverse
 
 // Where the raster kernels read the records of the tile lists: a copy in
 // list order written by the binning (idx null: list position k is base[k]),
@@ -157,7 +161,9 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return (l == 0) ? 0ull : (~0ull >> (64 - l));
 }
 
-__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+// (the builtin on the bool itself: HIP's __ballot takes an int, whose round
+// trip through a VGPR costs two VALU per vote)
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // Orders a wavefront's LDS writes before its own later LDS reads (the lanes
 // of one wavefront, no block barrier).

@@ -226,9 +226,9 @@ __global__ void __launch_bounds__(256) k_preprocess(
         r.mx = mx;
         r.my = my;
         const double idet = 1.0 / det;
-        r.ca = -0.5 * (C * idet);
-        r.cb = B * idet;
-        r.cc = -0.5 * (A * idet);
+        r.ca = (-0.5 * (C * idet)) * kLog2e;  // (base-2 exponent)
+        r.cb = (B * idet) * kLog2e;
+        r.cc = (-0.5 * (A * idet)) * kLog2e;
         r.o = (float)o;
         r.z = (float)tz;
         r.r = rgb[0];

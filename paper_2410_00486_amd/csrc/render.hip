@@ -23,7 +23,6 @@
 namespace gs {
 namespace {
 
-constexpr double kLog2e = 1.4426950408889634;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTMin = 1e-4f;
@@ -37,7 +36,7 @@ __device__ __forceinline__ bool eval_alpha(const Rec& r, double sx, double sy, d
   dy = r.my - sy;
   const double pw = fma(dx, fma(r.ca, dx, r.cb * dy), (r.cc * dy) * dy);
   if (pw > 0.0) return false;
-  G = __builtin_amdgcn_exp2f((float)(pw * kLog2e));
+  G = __builtin_amdgcn_exp2f((float)pw);
   oG = r.o * G;
   a = fminf(kAlphaMax, oG);
   return a >= kAlphaMin;
@@ -251,36 +250,38 @@ __device__ __forceinline__ void fwd_tile(int gtile, RecSrc lrec,
           const double dx1 = r1.mx - sx[k], dy1 = r1.my - sy[k];
           const double pw0 = fma(dx0, fma(r0.ca, dx0, r0.cb * dy0), (r0.cc * dy0) * dy0);
           const double pw1 = fma(dx1, fma(r1.ca, dx1, r1.cb * dy1), (r1.cc * dy1) * dy1);
-          const float a0 = fminf(kAlphaMax, r0.o * __builtin_amdgcn_exp2f((float)(pw0 * kLog2e)));
-          const float a1 = fminf(kAlphaMax, r1.o * __builtin_amdgcn_exp2f((float)(pw1 * kLog2e)));
+          const float a0 = fminf(kAlphaMax, r0.o * __builtin_amdgcn_exp2f((float)pw0));
+          const float a1 = fminf(kAlphaMax, r1.o * __builtin_amdgcn_exp2f((float)pw1));
           // a splat that is not blended gets weight 0: colour, depth are
           // non-negative and finite, so fma(x, 0, acc) leaves acc as it is
           // and one select replaces four
           {
             const bool hit = !done[k] && !(pw0 > 0.0) && a0 >= kAlphaMin;
-            const float Tn = T[k] * (1.0f - a0);
+            const float w0 = a0 * T[k];
+            const float Tn = T[k] - w0;  // T (1 - alpha)
             const bool stop = Tn < kTMin;
             const bool blend = hit && !stop;
-            const float w = blend ? a0 * T[k] : 0.0f;
+            const float w = blend ? w0 : 0.0f;
             c0[k] = fmaf(r0.r, w, c0[k]);
             c1[k] = fmaf(r0.g, w, c1[k]);
             c2[k] = fmaf(r0.b, w, c2[k]);
             D[k] = fmaf(r0.z, w, D[k]);
-            T[k] = blend ? Tn : T[k];
+            T[k] -= w;
             lastpos[k] = blend ? pos0 : lastpos[k];
             done[k] = done[k] || (hit && stop);
           }
           {
             const bool hit = has1 && !done[k] && !(pw1 > 0.0) && a1 >= kAlphaMin;
-            const float Tn = T[k] * (1.0f - a1);
+            const float w0 = a1 * T[k];
+            const float Tn = T[k] - w0;  // T (1 - alpha)
             const bool stop = Tn < kTMin;
             const bool blend = hit && !stop;
-            const float w = blend ? a1 * T[k] : 0.0f;
+            const float w = blend ? w0 : 0.0f;
             c0[k] = fmaf(r1.r, w, c0[k]);
             c1[k] = fmaf(r1.g, w, c1[k]);
             c2[k] = fmaf(r1.b, w, c2[k]);
             D[k] = fmaf(r1.z, w, D[k]);
-            T[k] = blend ? Tn : T[k];
+            T[k] -= w;
             lastpos[k] = blend ? pos0 + 1u : lastpos[k];
             done[k] = done[k] || (hit && stop);
           }
@@ -512,7 +513,7 @@ __device__ __forceinline__ void bwd_tile(
             const bool open = oG <= kAlphaMax;
             const float gpow = open ? a * g_alpha : 0.0f;
             const float fx = (float)dx, fy = (float)dy;
-            const float ca = (float)(-2.0 * r.ca), cb = (float)(-r.cb), cc = (float)(-2.0 * r.cc);
+            const float ca = (float)(-2.0 * kLn2 * r.ca), cb = (float)(-kLn2 * r.cb), cc = (float)(-2.0 * kLn2 * r.cc);
             const float t = gpow * fx, u = gpow * fy;
             g[4] = fmaf(open ? G : 0.0f, g_alpha, g[4]);
             g[5] = fmaf(t, fx, g[5]);
@@ -757,7 +758,7 @@ __device__ __forceinline__ void splat_wave(
     r.o = r.z = r.r = r.g = r.b = 0.0f;
     r.clamp = 0u;
   }
-  const float ca = (float)(-2.0 * r.ca), cb = (float)(-r.cb), cc = (float)(-2.0 * r.cc);
+  const float ca = (float)(-2.0 * kLn2 * r.ca), cb = (float)(-kLn2 * r.cb), cc = (float)(-2.0 * kLn2 * r.cc);
   float g[10];
 #pragma unroll
   for (int f = 0; f < 10; ++f) g[f] = 0.0f;
@@ -767,7 +768,7 @@ __device__ __forceinline__ void splat_wave(
     // alpha as in the forward (same bits)
     const double dx = r.mx - sxy.x, dy = r.my - sxy.y;
     const double pw = fma(dx, fma(r.ca, dx, r.cb * dy), (r.cc * dy) * dy);
-    const float G = __builtin_amdgcn_exp2f((float)(pw * kLog2e));
+    const float G = __builtin_amdgcn_exp2f((float)pw);
     const float oG = r.o * G;
     const float a = fminf(kAlphaMax, oG);
     // (no short-circuit: every term is evaluated, so nothing branches)

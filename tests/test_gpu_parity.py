@@ -48,7 +48,7 @@ def test_preprocess_records_match_oracle(cfg):
     d = rec[vis, :40].copy().view(np.float64).reshape(-1, 5)
     f = rec[vis, 40:60].copy().view(np.float32).reshape(-1, 5)
     np.testing.assert_allclose(d[:, 0:2], ref["mean2d"][vis], rtol=1e-12, atol=1e-9)
-    con = ref["conic"][vis]
+    con = ref["conic"][vis] * np.log2(np.e)  # (stored as the base-2 exponent's form)
     np.testing.assert_allclose(d[:, 2], -0.5 * con[:, 0], rtol=1e-9)
     np.testing.assert_allclose(d[:, 3], -con[:, 1], rtol=1e-9, atol=1e-12 * np.abs(con).max())
     np.testing.assert_allclose(d[:, 4], -0.5 * con[:, 2], rtol=1e-9)
