@@ -188,7 +188,10 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
   __shared__ uint32_t lstart[kRbMaxRadix];
   __shared__ uint32_t gofs[kRbMaxRadix];
   __shared__ uint32_t ws[kRbWaves];
-  __shared__ uint32_t sk[kRbTile], sv[kRbTile], sv2[TWO ? kRbTile : 1];
+  // one staging buffer, reused for the keys, the values and the second
+  // values in turn (a third of the LDS of staging all three, so more
+  // workgroups per CU hide the memory latency)
+  __shared__ uint32_t sbuf[kRbTile];
   const int w = threadIdx.x / kWave, lane = lane_id();
   // the two consecutive digits this thread handles in the block scans
   const int d0 = 2 * (int)threadIdx.x, d1 = d0 + 1;
@@ -201,15 +204,16 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
     if (h0) gofs[d0] = ex + hist[(int64_t)d0 * nb_cap + blockIdx.x];
     if (h1) gofs[d1] = ex + x0 + hist[(int64_t)d1 * nb_cap + blockIdx.x];
   }
-  uint32_t key[kRbItems], val[kRbItems], val2[kRbItems], rank[kRbItems];
+  // (the values are loaded only when they are staged: fewer registers held
+  // through the ranking)
+  uint32_t key[kRbItems], rank[kRbItems];
   const uint64_t lt = lanemask_lt();
+  const int64_t ibase = base + (int64_t)w * (kWave * kRbItems) + lane;
 #pragma unroll
   for (int r = 0; r < kRbItems; ++r) {
-    const int64_t idx = base + (int64_t)w * (kWave * kRbItems) + r * kWave + lane;
+    const int64_t idx = ibase + r * kWave;
     const bool valid = idx < cnt;
     key[r] = valid ? keys_in[idx] : 0u;
-    val[r] = valid ? vals_in[idx] : 0u;
-    val2[r] = (TWO && valid) ? vals2_in[idx] : 0u;
     const uint32_t d = (key[r] >> shift) & mask;
     const uint64_t peers = rb_peers(d, valid, bits);
     const uint64_t below = peers & lt;
@@ -241,54 +245,92 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
     if (h1) lstart[d1] = ex + t0;
   }
   __syncthreads();
+  // each item's slot in the block's digit order (kRbTile: none)
 #pragma unroll
   for (int r = 0; r < kRbItems; ++r) {
     if (rank[r] != 0xFFFFFFFFu) {
       const uint32_t d = (key[r] >> shift) & mask;
-      const uint32_t lp = lstart[d] + wcnt[w][d] + rank[r];
-      sk[lp] = key[r];
-      sv[lp] = val[r];
-      if (TWO) sv2[lp] = val2[r];
+      rank[r] = lstart[d] + wcnt[w][d] + rank[r];
+    } else {
+      rank[r] = kRbTile;
     }
   }
-  __syncthreads();
   const int nloc = (int)((cnt - base) < kRbTile ? (cnt - base) : kRbTile);
-  if constexpr (!EMIT) {
-    for (int i = threadIdx.x; i < nloc; i += kRbThreads) {
-      const uint32_t k = sk[i];
-      const uint32_t d = (k >> shift) & mask;
-      const uint32_t pos = gofs[d] + (uint32_t)i - lstart[d];
-      keys_out[pos] = k;
-      vals_out[pos] = sv[i];
-      if (TWO) vals2_out[pos] = sv2[i];
+  // keys: staged, then each slot's global position (kept for the values)
+  // and the key itself (kept by the last pass for its output keys)
+#pragma unroll
+  for (int r = 0; r < kRbItems; ++r)
+    if (rank[r] < (uint32_t)kRbTile) sbuf[rank[r]] = key[r];
+  __syncthreads();
+  uint32_t opos[kRbItems], okey[kRbItems];
+#pragma unroll
+  for (int q = 0; q < kRbItems; ++q) {
+    const int i = threadIdx.x + q * kRbThreads;
+    okey[q] = i < nloc ? sbuf[i] : 0u;
+    const uint32_t d = (okey[q] >> shift) & mask;
+    opos[q] = i < nloc ? gofs[d] + (uint32_t)i - lstart[d] : 0u;
+    if (!EMIT && i < nloc) keys_out[opos[q]] = okey[q];
+  }
+  __syncthreads();
+  // values
+  {
+    uint32_t val[kRbItems];
+#pragma unroll
+    for (int r = 0; r < kRbItems; ++r)
+      val[r] = rank[r] < (uint32_t)kRbTile ? vals_in[ibase + r * kWave] : 0u;
+#pragma unroll
+    for (int r = 0; r < kRbItems; ++r)
+      if (rank[r] < (uint32_t)kRbTile) sbuf[rank[r]] = val[r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kRbItems; ++q) {
+    const int i = threadIdx.x + q * kRbThreads;
+    if (i < nloc) {
+      if constexpr (EMIT) E.vals[opos[q]] = sbuf[i];
+      else vals_out[opos[q]] = sbuf[i];
     }
-  } else {
-    // the record ids came along as second values; each pair's key takes
-    // the depth of its record, gathered G records in flight at a time
-    static_assert(TWO, "the last tile pass carries the record ids");
-    constexpr int G = 8;
+  }
+  if constexpr (TWO) {
+    {
+      uint32_t val2[kRbItems];
 #pragma unroll
-    for (int q0 = 0; q0 < kRbItems; q0 += G) {
-      uint32_t rid[G], zb[G];
+      for (int r = 0; r < kRbItems; ++r)
+        val2[r] = rank[r] < (uint32_t)kRbTile ? vals2_in[ibase + r * kWave] : 0u;
+      __syncthreads();
 #pragma unroll
-      for (int u = 0; u < G; ++u) {
-        const int i = threadIdx.x + (q0 + u) * kRbThreads;
-        rid[u] = i < nloc ? sv2[i] : 0u;
-        zb[u] = i < nloc ? __float_as_uint(E.rec[rid[u]].z) : 0u;
+      for (int r = 0; r < kRbItems; ++r)
+        if (rank[r] < (uint32_t)kRbTile) sbuf[rank[r]] = val2[r];
+    }
+    __syncthreads();
+    if constexpr (!EMIT) {
+#pragma unroll
+      for (int q = 0; q < kRbItems; ++q) {
+        const int i = threadIdx.x + q * kRbThreads;
+        if (i < nloc) vals2_out[opos[q]] = sbuf[i];
+      }
+    } else {
+      // the record ids came along as second values; each pair's key takes
+      // the depth of its record (all of the thread's gathers in flight
+      // before its stores)
+      uint32_t rid[kRbItems], zb[kRbItems];
+#pragma unroll
+      for (int q = 0; q < kRbItems; ++q) {
+        const int i = threadIdx.x + q * kRbThreads;
+        rid[q] = i < nloc ? sbuf[i] : 0u;
+        zb[q] = i < nloc ? __float_as_uint(E.rec[rid[q]].z) : 0u;
       }
 #pragma unroll
-      for (int u = 0; u < G; ++u) {
-        const int i = threadIdx.x + (q0 + u) * kRbThreads;
+      for (int q = 0; q < kRbItems; ++q) {
+        const int i = threadIdx.x + q * kRbThreads;
         if (i < nloc) {
-          const uint32_t t = sk[i];
-          const uint32_t d = (t >> shift) & mask;
-          const uint32_t pos = gofs[d] + (uint32_t)i - lstart[d];
-          E.keys[pos] = ((uint64_t)t << 32) | zb[u];
-          E.vals[pos] = sv[i];
-          E.sorted_rec[pos] = rid[u];
+          E.keys[opos[q]] = ((uint64_t)okey[q] << 32) | zb[q];
+          E.sorted_rec[opos[q]] = rid[q];
         }
       }
     }
+  } else {
+    static_assert(TWO || !EMIT, "the last tile pass carries the record ids");
   }
 }
 
