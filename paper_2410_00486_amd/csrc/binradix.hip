@@ -7,17 +7,19 @@
 // the record index, so the order within a tile is also (depth, record
 // index).  Hence:
 //   1. the visible records are listed in record order with their depth
-//      bits as keys (positive floats: the bits order like the values);
-//   2. a stable LSD radix sort orders them by depth (ties keep record
-//      order);
+//      bits as keys (positive floats: the bits order like the values) and
+//      a 16-byte generation payload each (tile box, first generation
+//      index, record id);
+//   2. a stable LSD radix sort orders their list positions by depth (ties
+//      keep record order);
 //   3. their pairs are generated in that order (a scan of the pair counts
-//      gives each record its first slot), key = global tile id, value =
-//      generation index; the pair -> record table is written on the way;
+//      gives each record its first slot), key = global tile id, values =
+//      generation index and record id;
 //   4. a stable LSD radix sort by tile id (only the bits the plan's tile
 //      count needs) then leaves every tile's pairs contiguous, in depth
 //      order, at exactly the list starts the binning scan computed; its
-//      last pass writes the sorted outputs (keys, values, record ids and
-//      the records in list order) directly.
+//      last pass writes the sorted outputs (keys, values and record ids)
+//      directly.
 // Every pass is an upsweep (per-block digit counts), a per-digit scan over
 // the blocks and a downsweep that ranks a block's keys (stable: wave64
 // ballots, in index order), reorders them in LDS and writes each digit's
@@ -72,14 +74,24 @@ __device__ __forceinline__ uint32_t rb_block_exscan(uint32_t x, uint32_t* ws) {
   return off + incl - x;
 }
 
+// What the pair generation needs of a visible record, in one 16-byte word
+// (one random read per record once the records are in depth order): its
+// tile box (x0 | y0 << 16, x1 | y1 << 16), first generation index and
+// record id.
+__device__ __forceinline__ uint32_t pay_tiles(const uint4 p) {
+  return ((p.y & 0xFFFFu) - (p.x & 0xFFFFu)) * ((p.y >> 16) - (p.x >> 16));
+}
+
 // 1. Visible records in record order: pair offset (first generation index),
-// visible-list entry and depth key.  One wavefront per chunk of 64
-// Gaussians of a view, at the positions the binning scan gave the chunk.
+// visible-list entry, depth key and generation payload.  One wavefront per
+// chunk of 64 Gaussians of a view, at the positions the binning scan gave
+// the chunk.
 __global__ void __launch_bounds__(256) k_rb_visible(
     const uint32_t* __restrict__ tt, uint32_t* __restrict__ poff,
     const uint2* __restrict__ chunk_pre, int64_t chunks_per_view, int64_t n_chunks,
-    const Rec* __restrict__ rec, int64_t n, const int32_t* __restrict__ fl,
-    uint32_t* __restrict__ vis_list, uint32_t* __restrict__ dkey) {
+    const Rec* __restrict__ rec, const uint2* __restrict__ rect, int64_t n,
+    const int32_t* __restrict__ fl, uint32_t* __restrict__ vis_list,
+    uint32_t* __restrict__ dkey, uint4* __restrict__ pay) {
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t gw = (int64_t)blockIdx.x * (256 / kWave) + w;  // chunk
   if (gw >= n_chunks) return;
@@ -94,10 +106,13 @@ __global__ void __launch_bounds__(256) k_rb_visible(
   const uint2 cp = chunk_pre[gw];
   const uint64_t vmask = ballot64(c > 0);
   if (c > 0) {
-    poff[ri] = cp.x + (incl - c);
+    const uint32_t p0 = cp.x + (incl - c);
+    poff[ri] = p0;
     const uint32_t vp = cp.y + (uint32_t)__popcll(vmask & lanemask_lt());
     vis_list[vp] = (uint32_t)ri;
     dkey[vp] = __float_as_uint(z);
+    const uint2 b = rect[ri];
+    pay[vp] = make_uint4(b.x, b.y, p0, (uint32_t)ri);
   }
 }
 
@@ -277,7 +292,9 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
     uint32_t val[kRbItems];
 #pragma unroll
     for (int r = 0; r < kRbItems; ++r)
-      val[r] = rank[r] < (uint32_t)kRbTile ? vals_in[ibase + r * kWave] : 0u;
+      val[r] = rank[r] < (uint32_t)kRbTile
+                   ? (vals_in ? vals_in[ibase + r * kWave] : (uint32_t)(ibase + r * kWave))
+                   : 0u;
 #pragma unroll
     for (int r = 0; r < kRbItems; ++r)
       if (rank[r] < (uint32_t)kRbTile) sbuf[rank[r]] = val[r];
@@ -335,8 +352,8 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
 }
 
 // 3a. Pairs of each block of kGenRecs depth-sorted records.
-__global__ void __launch_bounds__(kRbThreads) k_rb_gen_count(const uint32_t* __restrict__ rid,
-                                                             const uint32_t* __restrict__ tt,
+__global__ void __launch_bounds__(kRbThreads) k_rb_gen_count(const uint32_t* __restrict__ vid,
+                                                             const uint4* __restrict__ pay,
                                                              const int32_t* __restrict__ fl,
                                                              uint32_t* __restrict__ part) {
   const int64_t V = rb_count(fl, F_VISIBLE);
@@ -347,7 +364,7 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_gen_count(const uint32_t* __r
 #pragma unroll
   for (int q = 0; q < kGenPer; ++q) {
     const int64_t j = base + q * kRbThreads + threadIdx.x;
-    if (j < V) s += tt[rid[j]];
+    if (j < V) s += pay_tiles(pay[vid[j]]);
   }
   s = scan_dpp<6>(s);
   if (lane_id() == kWave - 1) ws[threadIdx.x / kWave] = s;
@@ -387,8 +404,7 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_gen_scan(const int32_t* __res
 // footprint does not serialise on one thread.  Writes the tile key, the
 // generation index and the record id of every pair.
 __global__ void __launch_bounds__(kRbThreads) k_rb_generate(
-    const uint32_t* __restrict__ rid, const uint32_t* __restrict__ tt,
-    const uint32_t* __restrict__ poff, const ushort4* __restrict__ rect, int64_t n, ViewTable vt,
+    const uint32_t* __restrict__ vid, const uint4* __restrict__ pay, int64_t n, ViewTable vt,
     const int32_t* __restrict__ fl, const uint32_t* __restrict__ part,
     uint32_t* __restrict__ tkey, uint32_t* __restrict__ gidx, uint32_t* __restrict__ ridx) {
   const int64_t V = rb_count(fl, F_VISIBLE);
@@ -405,16 +421,16 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_generate(
     const int l = threadIdx.x * kGenPer + q;
     c[q] = 0u;
     if (j < V) {
-      const uint32_t r = rid[j];
-      const ushort4 b = rect[r];
+      const uint4 p = pay[vid[j]];
+      const uint32_t r = p.w;
       const int v = (int)(r / (uint64_t)n);
       const ViewInfo& vi = vt.v[v];
-      c[q] = tt[r];
+      c[q] = pay_tiles(p);
       s_rid[l] = r;
-      s_p0[l] = poff[r];
-      s_bw[l] = (uint32_t)(b.z - b.x);
+      s_p0[l] = p.z;
+      s_bw[l] = (p.y & 0xFFFFu) - (p.x & 0xFFFFu);
       s_tx[l] = (uint32_t)vi.tiles_x;
-      s_t0[l] = (uint32_t)(vi.tile_off + (int)b.y * vi.tiles_x + (int)b.x);
+      s_t0[l] = (uint32_t)(vi.tile_off + (int)(p.x >> 16) * vi.tiles_x + (int)(p.x & 0xFFFFu));
     }
     sum += c[q];
   }
@@ -470,6 +486,7 @@ namespace {
 struct RbBuffers {
   const int32_t* fl;
   uint32_t *tt, *poff, *vis, *dk[2], *rid[2], *tk[2], *gx[2], *rx[2], *hist, *dtot, *part;
+  uint4* pay;
   RbEmit emit;
 };
 
@@ -489,13 +506,15 @@ RbBuffers rb_buffers(const Plan& P, void* ws) {
   B.hist = ws_at<uint32_t>(ws, P.off_rb_hist);
   B.dtot = ws_at<uint32_t>(ws, P.off_rb_dtot);
   B.part = ws_at<uint32_t>(ws, P.off_rb_part);
+  B.pay = ws_at<uint4>(ws, P.off_rb_pay);
   B.emit = RbEmit{ws_at<uint64_t>(ws, P.off_keys), ws_at<uint32_t>(ws, P.off_vals),
                   ws_at<uint32_t>(ws, P.off_sorted_rec), ws_at<Rec>(ws, P.off_rec)};
   return B;
 }
 
-// One stable pass over the keys counted by flag `which`; vin2 / vout2: a
-// second value array carried along (null: none).
+// One stable pass over the keys counted by flag `which`; vin null: each
+// key's value is its own position; vin2 / vout2: a second value array
+// carried along (null: none).
 void rb_pass(const RbBuffers& B, hipStream_t s, const uint32_t* kin, const uint32_t* vin,
              const uint32_t* vin2, uint32_t* kout, uint32_t* vout, uint32_t* vout2, bool emit,
              int which, int64_t nb_cap, int shift, int bits) {
@@ -530,23 +549,23 @@ hipError_t launch_rb_generate(const Plan& P, void* ws, hipStream_t s) {
   if (P.n_chunks <= 0 || P.rb_rec_blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rb_visible, dim3((unsigned)((P.n_chunks + 3) / 4)), dim3(256), 0, s, B.tt,
                      B.poff, ws_at<uint2>(ws, P.off_chunk_pre), P.chunks_per_view, P.n_chunks,
-                     ws_at<Rec>(ws, P.off_rec), P.n, B.fl, B.vis, B.dk[0]);
-  // depth bits in four 8-bit passes; values: record ids (the visible list
-  // feeds the first pass and is left as it is)
-  // (dk0, vis) -> (dk1, rid1) -> (dk0, rid0) -> (dk1, rid1) -> (dk0, rid0)
+                     ws_at<Rec>(ws, P.off_rec), ws_at<uint2>(ws, P.off_rect), P.n, B.fl, B.vis,
+                     B.dk[0], B.pay);
+  // depth bits in four 8-bit passes; values: visible-list positions (the
+  // first pass takes each key's own position)
+  // (dk0, -) -> (dk1, rid1) -> (dk0, rid0) -> (dk1, rid1) -> (dk0, rid0)
   for (int p = 0; p < 4; ++p) {
     const uint32_t* kin = B.dk[p & 1];
-    const uint32_t* vin = p == 0 ? B.vis : B.rid[p & 1];
+    const uint32_t* vin = p == 0 ? nullptr : B.rid[p & 1];
     rb_pass(B, s, kin, vin, nullptr, B.dk[(p + 1) & 1], B.rid[(p + 1) & 1], nullptr, false,
             F_VISIBLE, P.rb_rec_blocks, 8 * p, 8);
   }
   const int64_t gb = rb_gen_blocks(P.n_rec);
-  hipLaunchKernelGGL(k_rb_gen_count, dim3((unsigned)gb), dim3(kRbThreads), 0, s, B.rid[0], B.tt,
+  hipLaunchKernelGGL(k_rb_gen_count, dim3((unsigned)gb), dim3(kRbThreads), 0, s, B.rid[0], B.pay,
                      B.fl, B.part);
   hipLaunchKernelGGL(k_rb_gen_scan, dim3(1), dim3(kRbThreads), 0, s, B.fl, B.part);
-  hipLaunchKernelGGL(k_rb_generate, dim3((unsigned)gb), dim3(kRbThreads), 0, s, B.rid[0], B.tt,
-                     B.poff, ws_at<ushort4>(ws, P.off_rect), P.n, P.vt, B.fl, B.part, B.tk[0],
-                     B.gx[0], B.rx[0]);
+  hipLaunchKernelGGL(k_rb_generate, dim3((unsigned)gb), dim3(kRbThreads), 0, s, B.rid[0], B.pay,
+                     P.n, P.vt, B.fl, B.part, B.tk[0], B.gx[0], B.rx[0]);
   return hipGetLastError();
 }
 
