@@ -597,40 +597,41 @@ __global__ void __launch_bounds__(kWave) k_render_bwd(
 // its own bucket (the scans stop at the half), two buckets per NPX steps.
 // The binning queues buckets by size (more than 32 pairs / at most 32).
 
-// Inclusive product / sum over segments of SEG (64 or 32) lanes, in place:
-// steps in rows of 16 (row_shr 1, 2, 4, 8), then the ends of rows 0 and 2
-// into rows 1 and 3 (row_bcast:15), and for 64 lanes the end of row 1 into
-// rows 2 and 3 (row_bcast:31).  Each step is one DPP multiply or add whose
-// lanes without a source (or outside the row mask) are not written, i.e.
-// keep their value; each is preceded by the two wait states a DPP read of a
-// VGPR written by the previous VALU instruction needs.
-#define GS_DPP_STEP(OP, CTRL) "s_nop 1\n\t" OP " %0, %0, %0 " CTRL " bank_mask:0xf\n\t"
-#define GS_SEG_SCAN32(OP)                              \
-  GS_DPP_STEP(OP, "row_shr:1 row_mask:0xf")            \
-  GS_DPP_STEP(OP, "row_shr:2 row_mask:0xf")            \
-  GS_DPP_STEP(OP, "row_shr:4 row_mask:0xf")            \
-  GS_DPP_STEP(OP, "row_shr:8 row_mask:0xf")            \
-  GS_DPP_STEP(OP, "row_bcast:15 row_mask:0xa")
+// Inclusive product / sum over segments of SEG (64 or 32) lanes, in place,
+// of two independent values at once (two pixels): steps in rows of 16
+// (row_shr 1, 2, 4, 8), then the ends of rows 0 and 2 into rows 1 and 3
+// (row_bcast:15), and for 64 lanes the end of row 1 into rows 2 and 3
+// (row_bcast:31).  Each step is one DPP multiply or add whose lanes
+// without a source (or outside the row mask) are not written, i.e. keep
+// their value.  A DPP read of a VGPR written by the previous VALU
+// instruction needs two wait states: the two scans' steps alternate, so
+// one wait state plus the other scan's step covers it (two before the
+// first step, whose inputs the compiler's code has just written).
+#define GS_DPP2(OP, CTRL) OP " %0, %0, %0 " CTRL " bank_mask:0xf\n\t" OP " %1, %1, %1 " CTRL " bank_mask:0xf\n\t"
+#define GS_SEG_SCAN32_2(OP)                                          \
+  "s_nop 1\n\t" GS_DPP2(OP, "row_shr:1 row_mask:0xf")              \
+  "s_nop 0\n\t" GS_DPP2(OP, "row_shr:2 row_mask:0xf")              \
+  "s_nop 0\n\t" GS_DPP2(OP, "row_shr:4 row_mask:0xf")              \
+  "s_nop 0\n\t" GS_DPP2(OP, "row_shr:8 row_mask:0xf")              \
+  "s_nop 0\n\t" GS_DPP2(OP, "row_bcast:15 row_mask:0xa")
 template <int SEG>
-__device__ __forceinline__ float seg_scan_mul(float x) {
+__device__ __forceinline__ void seg_scan_mul2(float& x, float& y) {
   if (SEG == 64)
-    asm volatile(GS_SEG_SCAN32("v_mul_f32_dpp") GS_DPP_STEP("v_mul_f32_dpp", "row_bcast:31 row_mask:0xc")
-                 : "+v"(x));
+    asm volatile(GS_SEG_SCAN32_2("v_mul_f32_dpp") "s_nop 0\n\t"
+                 GS_DPP2("v_mul_f32_dpp", "row_bcast:31 row_mask:0xc") : "+v"(x), "+v"(y));
   else
-    asm volatile(GS_SEG_SCAN32("v_mul_f32_dpp") : "+v"(x));
-  return x;
+    asm volatile(GS_SEG_SCAN32_2("v_mul_f32_dpp") : "+v"(x), "+v"(y));
 }
 template <int SEG>
-__device__ __forceinline__ float seg_scan_add(float x) {
+__device__ __forceinline__ void seg_scan_add2(float& x, float& y) {
   if (SEG == 64)
-    asm volatile(GS_SEG_SCAN32("v_add_f32_dpp") GS_DPP_STEP("v_add_f32_dpp", "row_bcast:31 row_mask:0xc")
-                 : "+v"(x));
+    asm volatile(GS_SEG_SCAN32_2("v_add_f32_dpp") "s_nop 0\n\t"
+                 GS_DPP2("v_add_f32_dpp", "row_bcast:31 row_mask:0xc") : "+v"(x), "+v"(y));
   else
-    asm volatile(GS_SEG_SCAN32("v_add_f32_dpp") : "+v"(x));
-  return x;
+    asm volatile(GS_SEG_SCAN32_2("v_add_f32_dpp") : "+v"(x), "+v"(y));
 }
-#undef GS_SEG_SCAN32
-#undef GS_DPP_STEP
+#undef GS_SEG_SCAN32_2
+#undef GS_DPP2
 
 template <int TW, int TH, int SEG>
 __device__ __forceinline__ void splat_wave(
@@ -762,52 +763,67 @@ __device__ __forceinline__ void splat_wave(
   float g[10];
 #pragma unroll
   for (int f = 0; f < 10; ++f) g[f] = 0.0f;
-  auto pixel = [&](int j) {
-    const float4 b = sb[j];  // P, last, T_in, Q_in of the segment's j-th kept pixel
-    const double2 sxy = sc[j];
-    // alpha as in the forward (same bits)
-    const double dx = r.mx - sxy.x, dy = r.my - sxy.y;
-    const double pw = fma(dx, fma(r.ca, dx, r.cb * dy), (r.cc * dy) * dy);
-    const float G = __builtin_amdgcn_exp2f((float)pw);
-    const float oG = r.o * G;
-    const float a = fminf(kAlphaMax, oG);
-    // (no short-circuit: every term is evaluated, so nothing branches)
-    const bool hit = live & (pos < __float_as_uint(b.y)) & !(pw > 0.0) & (a >= kAlphaMin);
-    // (no early exit when no lane is blended at this pixel: rare, and its test costs two VALU per step)
-    const float4 gc = sa[j];
-    const float om = 1.0f - a;
-    const float inv_om = __builtin_amdgcn_rcpf(om);
+  // two pixels per iteration (the step count is even), their scans
+  // interleaved; each lane accumulates pixel j before pixel j + 1
+  for (int j = 0; j < nsteps; j += 2) {
+    float4 b[2], gc[2];
+    float dxf[2], dyf[2], G[2], oG[2], a[2], inv_om[2], f[2];
+    bool hit[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      b[u] = sb[j + u];  // P, last, T_in, Q_in of the segment's kept pixel
+      const double2 sxy = sc[j + u];
+      // alpha as in the forward (same bits)
+      const double dx = r.mx - sxy.x, dy = r.my - sxy.y;
+      const double pw = fma(dx, fma(r.ca, dx, r.cb * dy), (r.cc * dy) * dy);
+      G[u] = __builtin_amdgcn_exp2f((float)pw);
+      oG[u] = r.o * G[u];
+      a[u] = fminf(kAlphaMax, oG[u]);
+      // (no short-circuit: every term is evaluated, so nothing branches; no
+      // early exit when no lane is blended at a pixel: rare, and its test
+      // costs two VALU per step)
+      hit[u] = live & (pos < __float_as_uint(b[u].y)) & !(pw > 0.0) & (a[u] >= kAlphaMin);
+      gc[u] = sa[j + u];
+      const float om = 1.0f - a[u];
+      inv_om[u] = __builtin_amdgcn_rcpf(om);
+      f[u] = hit[u] ? om : 1.0f;
+      dxf[u] = (float)dx;
+      dyf[u] = (float)dy;
+    }
     // transmittance in front of the splat: the segment's inclusive product
     // over its blended splats with the lane's own factor taken out again
     // (read by blended lanes only, whose factor 1 - alpha >= 0.01)
-    const float Tl = (b.z * seg_scan_mul<SEG>(hit ? om : 1.0f)) * inv_om;
-    const float wgt = hit ? a * Tl : 0.0f;
-    const float front = fmaf(gc.w, r.z, fmaf(gc.z, r.b, fmaf(gc.y, r.g, gc.x * r.r)));
-    const float Qn = b.w + seg_scan_add<SEG>(wgt * front);  // front part after the splat
-    const float g_alpha = fmaf(-(b.x - Qn), inv_om, Tl * front);
-    g[0] = fmaf(wgt, gc.x, g[0]);
-    g[1] = fmaf(wgt, gc.y, g[1]);
-    g[2] = fmaf(wgt, gc.z, g[2]);
-    g[3] = fmaf(wgt, gc.w, g[3]);
-    // moments of gpow = dL/dpower = alpha dL/dalpha (unclamped splats) and
-    // of t = gpow dx, u = gpow dy; the opacity, conic and mean partials are
-    // formed from them once, after the pixels (dL/do = sum gpow / o)
-    const bool open = hit & (oG <= kAlphaMax);
-    const float gpow = open ? a * g_alpha : 0.0f;
-    const float fx = (float)dx, fy = (float)dy;
-    const float t = gpow * fx, u = gpow * fy;
-    g[4] += gpow;
-    g[5] = fmaf(t, fx, g[5]);
-    g[6] = fmaf(t, fy, g[6]);
-    g[7] = fmaf(u, fy, g[7]);
-    g[8] += t;
-    g[9] += u;
-  };
-  // two pixels per iteration (the step count is even): their alpha chains
-  // overlap, the accumulation keeps pixel order
-  for (int j = 0; j < nsteps; j += 2) {
-    pixel(j);
-    pixel(j + 1);
+    seg_scan_mul2<SEG>(f[0], f[1]);
+    float Tl[2], wgt[2], front[2], q[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      Tl[u] = (b[u].z * f[u]) * inv_om[u];
+      wgt[u] = hit[u] ? a[u] * Tl[u] : 0.0f;
+      front[u] = fmaf(gc[u].w, r.z, fmaf(gc[u].z, r.b, fmaf(gc[u].y, r.g, gc[u].x * r.r)));
+      q[u] = wgt[u] * front[u];
+    }
+    seg_scan_add2<SEG>(q[0], q[1]);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const float Qn = b[u].w + q[u];  // front part after the splat
+      const float g_alpha = fmaf(-(b[u].x - Qn), inv_om[u], Tl[u] * front[u]);
+      g[0] = fmaf(wgt[u], gc[u].x, g[0]);
+      g[1] = fmaf(wgt[u], gc[u].y, g[1]);
+      g[2] = fmaf(wgt[u], gc[u].z, g[2]);
+      g[3] = fmaf(wgt[u], gc[u].w, g[3]);
+      // moments of gpow = dL/dpower = alpha dL/dalpha (unclamped splats) and
+      // of t = gpow dx, u = gpow dy; the opacity, conic and mean partials are
+      // formed from them once, after the pixels (dL/do = sum gpow / o)
+      const bool open = hit[u] & (oG[u] <= kAlphaMax);
+      const float gpow = open ? a[u] * g_alpha : 0.0f;
+      const float t = gpow * dxf[u], v = gpow * dyf[u];
+      g[4] += gpow;
+      g[5] = fmaf(t, dxf[u], g[5]);
+      g[6] = fmaf(t, dyf[u], g[6]);
+      g[7] = fmaf(v, dyf[u], g[7]);
+      g[8] += t;
+      g[9] += v;
+    }
   }
   if (live) {
     float4* gp = reinterpret_cast<float4*>(grad_pair + (int64_t)sorted_vals[s + pos] * kPairGrad);
@@ -821,7 +837,7 @@ __device__ __forceinline__ void splat_wave(
 // Grid-stride over the work of the two queues: one bucket per wave from
 // the first, two per wave from the second.
 template <int TW, int TH>
-__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(TW * TH == 64 ? 7 : 1))) k_render_bwd_splat(
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(TW * TH == 64 ? 6 : 1))) k_render_bwd_splat(
     RecSrc lrec,
     const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ tile_last, const uint32_t* __restrict__ boff,
