@@ -154,6 +154,8 @@ __device__ __forceinline__ void stage(Rec* srec, uint32_t* sval, RecSrc lrec,
 }
 
 // ------------------------------------------------------------------ forward
+// Splats per step of the forward's compositing loop.
+constexpr int kFwdSplats = 4;
 template <int TW, int TH, bool CKPT>
 __device__ __forceinline__ void fwd_tile(int gtile, RecSrc lrec,
                                          const uint32_t* __restrict__ ranges,
@@ -236,53 +238,46 @@ __device__ __forceinline__ void fwd_tile(int gtile, RecSrc lrec,
         }
       }
       const int jend = min(nb, j + (int)(kBucket - (q0 & (kBucket - 1))));
-      for (; j < jend; j += 2) {
-        // two records at once (whole records, broadcast LDS reads): their
-        // alphas are independent, only the blends are ordered.  Every
+      for (; j < jend; j += kFwdSplats) {
+        // kFwdSplats records at once (whole records, broadcast LDS reads):
+        // their alphas are independent, only the blends are ordered.  Every
         // decision of eval_alpha is a select: no divergent branches.
-        const bool has1 = j + 1 < jend;
-        const Rec r0 = srec[j];
-        const Rec r1 = srec[has1 ? j + 1 : j];
+        constexpr int NS = kFwdSplats;
+        Rec rr[NS];
+        bool hasu[NS];
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+          hasu[u] = j + u < jend;
+          rr[u] = srec[hasu[u] ? j + u : j];
+        }
         const uint32_t pos0 = b - s + (uint32_t)j + 1u;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
-          const double dx0 = r0.mx - sx[k], dy0 = r0.my - sy[k];
-          const double dx1 = r1.mx - sx[k], dy1 = r1.my - sy[k];
-          const double pw0 = fma(dx0, fma(r0.ca, dx0, r0.cb * dy0), (r0.cc * dy0) * dy0);
-          const double pw1 = fma(dx1, fma(r1.ca, dx1, r1.cb * dy1), (r1.cc * dy1) * dy1);
-          const float a0 = fminf(kAlphaMax, r0.o * __builtin_amdgcn_exp2f((float)pw0));
-          const float a1 = fminf(kAlphaMax, r1.o * __builtin_amdgcn_exp2f((float)pw1));
+          double pw[NS];
+          float au[NS];
+#pragma unroll
+          for (int u = 0; u < NS; ++u) {
+            const double dx = rr[u].mx - sx[k], dy = rr[u].my - sy[k];
+            pw[u] = fma(dx, fma(rr[u].ca, dx, rr[u].cb * dy), (rr[u].cc * dy) * dy);
+            au[u] = fminf(kAlphaMax, rr[u].o * __builtin_amdgcn_exp2f((float)pw[u]));
+          }
           // a splat that is not blended gets weight 0: colour, depth are
           // non-negative and finite, so fma(x, 0, acc) leaves acc as it is
           // and one select replaces four
-          {
-            const bool hit = !done[k] && !(pw0 > 0.0) && a0 >= kAlphaMin;
-            const float w0 = a0 * T[k];
+#pragma unroll
+          for (int u = 0; u < NS; ++u) {
+            const bool hit = hasu[u] && !done[k] && !(pw[u] > 0.0) && au[u] >= kAlphaMin;
+            const float w0 = au[u] * T[k];
             const float Tn = T[k] - w0;  // T (1 - alpha)
             const bool stop = Tn < kTMin;
             const bool blend = hit && !stop;
             const float w = blend ? w0 : 0.0f;
-            c0[k] = fmaf(r0.r, w, c0[k]);
-            c1[k] = fmaf(r0.g, w, c1[k]);
-            c2[k] = fmaf(r0.b, w, c2[k]);
-            D[k] = fmaf(r0.z, w, D[k]);
+            c0[k] = fmaf(rr[u].r, w, c0[k]);
+            c1[k] = fmaf(rr[u].g, w, c1[k]);
+            c2[k] = fmaf(rr[u].b, w, c2[k]);
+            D[k] = fmaf(rr[u].z, w, D[k]);
             T[k] -= w;
-            lastpos[k] = blend ? pos0 : lastpos[k];
-            done[k] = done[k] || (hit && stop);
-          }
-          {
-            const bool hit = has1 && !done[k] && !(pw1 > 0.0) && a1 >= kAlphaMin;
-            const float w0 = a1 * T[k];
-            const float Tn = T[k] - w0;  // T (1 - alpha)
-            const bool stop = Tn < kTMin;
-            const bool blend = hit && !stop;
-            const float w = blend ? w0 : 0.0f;
-            c0[k] = fmaf(r1.r, w, c0[k]);
-            c1[k] = fmaf(r1.g, w, c1[k]);
-            c2[k] = fmaf(r1.b, w, c2[k]);
-            D[k] = fmaf(r1.z, w, D[k]);
-            T[k] -= w;
-            lastpos[k] = blend ? pos0 + 1u : lastpos[k];
+            lastpos[k] = blend ? pos0 + (uint32_t)u : lastpos[k];
             done[k] = done[k] || (hit && stop);
           }
         }
@@ -291,6 +286,9 @@ __device__ __forceinline__ void fwd_tile(int gtile, RecSrc lrec,
           break;
         }
       }
+      // the next segment starts at jend, whatever the step: a step of
+      // kFwdSplats may pass it (its splats past jend are masked off)
+      if (more) j = jend;
     }
   }
   const float* cam = cams + (int64_t)v * GS_CAMERA_FLOATS;
