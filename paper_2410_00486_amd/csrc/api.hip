@@ -275,7 +275,8 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
                                     std::max(P->rb_rec_blocks, P->rb_pair_blocks) : 0);
   P->off_rb_dtot = take(radix ? (size_t)rb_max_radix() * 4 : 0);
   P->off_rb_part = take(radix ? (size_t)rb_gen_blocks(P->n_rec) * 4 : 0);
-  P->off_rb_pay = take(rrec * 4);  // 16 bytes per visible record
+  P->off_rb_pay = take(rrec * 4);   // 16 bytes per visible record, list order
+  P->off_rb_spay = take(rrec * 4);  // the same in depth order
   P->ws_size = o;
   P->magic = kPlanMagic;
   return GS_OK;

@@ -11,7 +11,8 @@
 //      a 16-byte generation payload each (tile box, first generation
 //      index, record id);
 //   2. a stable LSD radix sort orders their list positions by depth (ties
-//      keep record order);
+//      keep record order); its last pass writes the records' payloads in
+//      that order, so the generation reads them in sequence;
 //   3. their pairs are generated in that order (a scan of the pair counts
 //      gives each record its first slot), key = global tile id, values =
 //      generation index and record id;
@@ -182,6 +183,10 @@ struct RbEmit {
   uint32_t* vals;          // generation index
   uint32_t* sorted_rec;    // record id
   const Rec* rec;          // (read for the depth of each pair's record)
+  // the last depth pass instead (spay non-null): the generation payload of
+  // each value's record in sorted order, no keys or values
+  const uint4* pay;
+  uint4* spay;
 };
 
 // Downsweep: stable ranking of the block's keys by digit, reorder in LDS,
@@ -284,7 +289,7 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
     okey[q] = i < nloc ? sbuf[i] : 0u;
     const uint32_t d = (okey[q] >> shift) & mask;
     opos[q] = i < nloc ? gofs[d] + (uint32_t)i - lstart[d] : 0u;
-    if (!EMIT && i < nloc) keys_out[opos[q]] = okey[q];
+    if (!EMIT && keys_out && i < nloc) keys_out[opos[q]] = okey[q];
   }
   __syncthreads();
   // values
@@ -300,12 +305,32 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
       if (rank[r] < (uint32_t)kRbTile) sbuf[rank[r]] = val[r];
   }
   __syncthreads();
+  if (!EMIT && E.spay) {
+    // the records' payloads in depth order: gathered four per thread in
+    // flight, stored in place of the values
+    constexpr int G = 4;
 #pragma unroll
-  for (int q = 0; q < kRbItems; ++q) {
-    const int i = threadIdx.x + q * kRbThreads;
-    if (i < nloc) {
-      if constexpr (EMIT) E.vals[opos[q]] = sbuf[i];
-      else vals_out[opos[q]] = sbuf[i];
+    for (int q0 = 0; q0 < kRbItems; q0 += G) {
+      uint4 pv[G];
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int i = threadIdx.x + (q0 + u) * kRbThreads;
+        pv[u] = i < nloc ? E.pay[sbuf[i]] : make_uint4(0u, 0u, 0u, 0u);
+      }
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int i = threadIdx.x + (q0 + u) * kRbThreads;
+        if (i < nloc) E.spay[opos[q0 + u]] = pv[u];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kRbItems; ++q) {
+      const int i = threadIdx.x + q * kRbThreads;
+      if (i < nloc) {
+        if constexpr (EMIT) E.vals[opos[q]] = sbuf[i];
+        else vals_out[opos[q]] = sbuf[i];
+      }
     }
   }
   if constexpr (TWO) {
@@ -352,8 +377,7 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
 }
 
 // 3a. Pairs of each block of kGenRecs depth-sorted records.
-__global__ void __launch_bounds__(kRbThreads) k_rb_gen_count(const uint32_t* __restrict__ vid,
-                                                             const uint4* __restrict__ pay,
+__global__ void __launch_bounds__(kRbThreads) k_rb_gen_count(const uint4* __restrict__ spay,
                                                              const int32_t* __restrict__ fl,
                                                              uint32_t* __restrict__ part) {
   const int64_t V = rb_count(fl, F_VISIBLE);
@@ -364,7 +388,7 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_gen_count(const uint32_t* __r
 #pragma unroll
   for (int q = 0; q < kGenPer; ++q) {
     const int64_t j = base + q * kRbThreads + threadIdx.x;
-    if (j < V) s += pay_tiles(pay[vid[j]]);
+    if (j < V) s += pay_tiles(spay[j]);
   }
   s = scan_dpp<6>(s);
   if (lane_id() == kWave - 1) ws[threadIdx.x / kWave] = s;
@@ -404,7 +428,7 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_gen_scan(const int32_t* __res
 // footprint does not serialise on one thread.  Writes the tile key, the
 // generation index and the record id of every pair.
 __global__ void __launch_bounds__(kRbThreads) k_rb_generate(
-    const uint32_t* __restrict__ vid, const uint4* __restrict__ pay, int64_t n, ViewTable vt,
+    const uint4* __restrict__ spay, int64_t n, ViewTable vt,
     const int32_t* __restrict__ fl, const uint32_t* __restrict__ part,
     uint32_t* __restrict__ tkey, uint32_t* __restrict__ gidx, uint32_t* __restrict__ ridx) {
   const int64_t V = rb_count(fl, F_VISIBLE);
@@ -421,7 +445,7 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_generate(
     const int l = threadIdx.x * kGenPer + q;
     c[q] = 0u;
     if (j < V) {
-      const uint4 p = pay[vid[j]];
+      const uint4 p = spay[j];
       const uint32_t r = p.w;
       const int v = (int)(r / (uint64_t)n);
       const ViewInfo& vi = vt.v[v];
@@ -486,7 +510,7 @@ namespace {
 struct RbBuffers {
   const int32_t* fl;
   uint32_t *tt, *poff, *vis, *dk[2], *rid[2], *tk[2], *gx[2], *rx[2], *hist, *dtot, *part;
-  uint4* pay;
+  uint4 *pay, *spay;
   RbEmit emit;
 };
 
@@ -507,17 +531,20 @@ RbBuffers rb_buffers(const Plan& P, void* ws) {
   B.dtot = ws_at<uint32_t>(ws, P.off_rb_dtot);
   B.part = ws_at<uint32_t>(ws, P.off_rb_part);
   B.pay = ws_at<uint4>(ws, P.off_rb_pay);
+  B.spay = ws_at<uint4>(ws, P.off_rb_spay);
   B.emit = RbEmit{ws_at<uint64_t>(ws, P.off_keys), ws_at<uint32_t>(ws, P.off_vals),
-                  ws_at<uint32_t>(ws, P.off_sorted_rec), ws_at<Rec>(ws, P.off_rec)};
+                  ws_at<uint32_t>(ws, P.off_sorted_rec), ws_at<Rec>(ws, P.off_rec), nullptr,
+                  nullptr};
   return B;
 }
 
 // One stable pass over the keys counted by flag `which`; vin null: each
 // key's value is its own position; vin2 / vout2: a second value array
-// carried along (null: none).
+// carried along (null: none); spay (no emit): write the payloads of the
+// values' records in sorted order instead of keys and values.
 void rb_pass(const RbBuffers& B, hipStream_t s, const uint32_t* kin, const uint32_t* vin,
              const uint32_t* vin2, uint32_t* kout, uint32_t* vout, uint32_t* vout2, bool emit,
-             int which, int64_t nb_cap, int shift, int bits) {
+             int which, int64_t nb_cap, int shift, int bits, uint4* spay = nullptr) {
   const dim3 grid((unsigned)nb_cap), block(kRbThreads);
   hipLaunchKernelGGL(k_rb_hist, grid, block, 0, s, kin, B.fl, which, B.hist, nb_cap, shift, bits);
   hipLaunchKernelGGL(k_rb_digit_scan, dim3(1u << bits), block, 0, s, B.hist, B.fl, which, B.dtot,
@@ -529,7 +556,7 @@ void rb_pass(const RbBuffers& B, hipStream_t s, const uint32_t* kin, const uint3
     GS_RB_SCATTER(true, true, B.emit);
   } else {
     if (vin2) GS_RB_SCATTER(false, true, RbEmit{});
-    else GS_RB_SCATTER(false, false, RbEmit{});
+    else GS_RB_SCATTER(false, false, (RbEmit{nullptr, nullptr, nullptr, nullptr, B.pay, spay}));
   }
 #undef GS_RB_SCATTER
 }
@@ -552,20 +579,23 @@ hipError_t launch_rb_generate(const Plan& P, void* ws, hipStream_t s) {
                      ws_at<Rec>(ws, P.off_rec), ws_at<uint2>(ws, P.off_rect), P.n, B.fl, B.vis,
                      B.dk[0], B.pay);
   // depth bits in four 8-bit passes; values: visible-list positions (the
-  // first pass takes each key's own position)
-  // (dk0, -) -> (dk1, rid1) -> (dk0, rid0) -> (dk1, rid1) -> (dk0, rid0)
+  // first pass takes each key's own position); the last pass writes the
+  // records' generation payloads in depth order instead
+  // (dk0, -) -> (dk1, rid1) -> (dk0, rid0) -> (dk1, rid1) -> spay
   for (int p = 0; p < 4; ++p) {
     const uint32_t* kin = B.dk[p & 1];
     const uint32_t* vin = p == 0 ? nullptr : B.rid[p & 1];
-    rb_pass(B, s, kin, vin, nullptr, B.dk[(p + 1) & 1], B.rid[(p + 1) & 1], nullptr, false,
-            F_VISIBLE, P.rb_rec_blocks, 8 * p, 8);
+    const bool last = p == 3;
+    rb_pass(B, s, kin, vin, nullptr, last ? nullptr : B.dk[(p + 1) & 1],
+            last ? nullptr : B.rid[(p + 1) & 1], nullptr, false, F_VISIBLE, P.rb_rec_blocks,
+            8 * p, 8, last ? B.spay : nullptr);
   }
   const int64_t gb = rb_gen_blocks(P.n_rec);
-  hipLaunchKernelGGL(k_rb_gen_count, dim3((unsigned)gb), dim3(kRbThreads), 0, s, B.rid[0], B.pay,
-                     B.fl, B.part);
+  hipLaunchKernelGGL(k_rb_gen_count, dim3((unsigned)gb), dim3(kRbThreads), 0, s, B.spay, B.fl,
+                     B.part);
   hipLaunchKernelGGL(k_rb_gen_scan, dim3(1), dim3(kRbThreads), 0, s, B.fl, B.part);
-  hipLaunchKernelGGL(k_rb_generate, dim3((unsigned)gb), dim3(kRbThreads), 0, s, B.rid[0], B.pay,
-                     P.n, P.vt, B.fl, B.part, B.tk[0], B.gx[0], B.rx[0]);
+  hipLaunchKernelGGL(k_rb_generate, dim3((unsigned)gb), dim3(kRbThreads), 0, s, B.spay, P.n,
+                     P.vt, B.fl, B.part, B.tk[0], B.gx[0], B.rx[0]);
   return hipGetLastError();
 }
 
