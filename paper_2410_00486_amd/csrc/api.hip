@@ -224,6 +224,7 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_chunk_cnt = take((size_t)P->n_chunks * 8);
   P->off_chunk_pre = take((size_t)P->n_chunks * 8);
   P->off_vis_list = take(nrec * 4);
+  P->off_vis_clamp = take(nrec * 4);
   P->off_tile_cnt = take(T * 4);
   P->off_tile_start = take(T * 4);
   P->off_long = take(T * 16);  // (tile, list start, pairs, -) per long list

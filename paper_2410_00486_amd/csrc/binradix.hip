@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(256) k_rb_visible(
     const uint2* __restrict__ chunk_pre, int64_t chunks_per_view, int64_t n_chunks,
     const Rec* __restrict__ rec, const uint2* __restrict__ rect, int64_t n,
     const int32_t* __restrict__ fl, uint32_t* __restrict__ vis_list,
-    uint32_t* __restrict__ dkey, uint4* __restrict__ pay) {
+    uint32_t* __restrict__ vis_clamp, uint32_t* __restrict__ dkey, uint4* __restrict__ pay) {
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t gw = (int64_t)blockIdx.x * (256 / kWave) + w;  // chunk
   if (gw >= n_chunks) return;
@@ -102,7 +102,11 @@ __global__ void __launch_bounds__(256) k_rb_visible(
   const bool over = fl[F_OVERFLOW] != 0;
   const uint32_t c = (gi < n && !over) ? tt[ri] : 0u;
   float z = 0.0f;
-  if (c > 0) z = rec[ri].z;
+  uint32_t cbits = 0;
+  if (c > 0) {
+    z = rec[ri].z;
+    cbits = rec[ri].clamp;  // (same line as the depth)
+  }
   const uint32_t incl = scan_dpp<6>(c);
   const uint2 cp = chunk_pre[gw];
   const uint64_t vmask = ballot64(c > 0);
@@ -111,6 +115,7 @@ __global__ void __launch_bounds__(256) k_rb_visible(
     poff[ri] = p0;
     const uint32_t vp = cp.y + (uint32_t)__popcll(vmask & lanemask_lt());
     vis_list[vp] = (uint32_t)ri;
+    vis_clamp[vp] = cbits;
     dkey[vp] = __float_as_uint(z);
     const uint2 b = rect[ri];
     pay[vp] = make_uint4(b.x, b.y, p0, (uint32_t)ri);
@@ -577,7 +582,7 @@ hipError_t launch_rb_generate(const Plan& P, void* ws, hipStream_t s) {
   hipLaunchKernelGGL(k_rb_visible, dim3((unsigned)((P.n_chunks + 3) / 4)), dim3(256), 0, s, B.tt,
                      B.poff, ws_at<uint2>(ws, P.off_chunk_pre), P.chunks_per_view, P.n_chunks,
                      ws_at<Rec>(ws, P.off_rec), ws_at<uint2>(ws, P.off_rect), P.n, B.fl, B.vis,
-                     B.dk[0], B.pay);
+                     ws_at<uint32_t>(ws, P.off_vis_clamp), B.dk[0], B.pay);
   // depth bits in four 8-bit passes; values: visible-list positions (the
   // first pass takes each key's own position); the last pass writes the
   // records' generation payloads in depth order instead

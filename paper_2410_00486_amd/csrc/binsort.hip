@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(256) k_scatter(
     const ushort4* __restrict__ rect, const Rec* __restrict__ rec, int64_t n, ViewTable vt,
     const int32_t* __restrict__ fl, const uint32_t* __restrict__ tstart,
     uint32_t* __restrict__ cursor, uint64_t* __restrict__ skey, uint32_t* __restrict__ pair_rec,
-    uint32_t* __restrict__ vis_list) {
+    uint32_t* __restrict__ vis_list, uint32_t* __restrict__ vis_clamp) {
   constexpr int NW = 256 / kWave;
   __shared__ uint32_t s_pre[NW][kWave];
   __shared__ uint32_t s_p0[NW][kWave], s_dbits[NW][kWave], s_x0y0[NW][kWave];
@@ -438,10 +438,11 @@ __global__ void __launch_bounds__(256) k_scatter(
   // the record's tile box and depth are fetched before the scan of the
   // counts, which then runs while they are in flight (DPP, no LDS)
   ushort4 r = make_ushort4(0, 0, 0, 0);
-  uint32_t dbits = 0;
+  uint32_t dbits = 0, cbits = 0;
   if (c > 0) {
     r = rect[ri];
     dbits = __float_as_uint(rec[ri].z);
+    cbits = rec[ri].clamp;  // (same line as the depth)
   }
   const uint32_t incl = scan_dpp<6>(c);
   const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
@@ -452,7 +453,9 @@ __global__ void __launch_bounds__(256) k_scatter(
   if (c > 0) {
     p0 = (uint32_t)base64;
     poff[ri] = p0;
-    vis_list[cp.y + (uint32_t)__popcll(vmask & lanemask_lt())] = (uint32_t)ri;
+    const uint32_t vp = cp.y + (uint32_t)__popcll(vmask & lanemask_lt());
+    vis_list[vp] = (uint32_t)ri;
+    vis_clamp[vp] = cbits;
     x0y0 = (uint32_t)r.x | ((uint32_t)r.y << 16);
     tile0 = (uint32_t)(r.z - r.x);  // box width in tiles
   }
@@ -908,7 +911,7 @@ hipError_t launch_bin_sort(const Plan& P, void* ws, hipStream_t s, bool defer_sh
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(256), 0, s, tt, poff, chunk_pre,
                        P.chunks_per_view, P.n_chunks, ws_at<ushort4>(ws, P.off_rect),
                        ws_at<Rec>(ws, P.off_rec), P.n, P.vt, fl, tstart, tcnt, skey, pair_rec,
-                       ws_at<uint32_t>(ws, P.off_vis_list));
+                       ws_at<uint32_t>(ws, P.off_vis_list), ws_at<uint32_t>(ws, P.off_vis_clamp));
   }
   if ((e = mk.at(GS_MARK_BIN_SCATTER, s)) != hipSuccess) return e;
   if (T > 0) {

@@ -101,6 +101,7 @@ struct Plan {
   size_t off_flags, off_rec, off_rect, off_tt, off_poff;
   size_t off_chunk_cnt, off_chunk_pre;  // per chunk: (pairs, visible) counts and offsets
   size_t off_vis_list;                  // visible records in index order
+  size_t off_vis_clamp;                 // their colour clamp bits, same order
   size_t off_tile_cnt, off_tile_start, off_long;
   size_t off_keys, off_scatter, off_vals, off_pair_rec, off_sorted_rec, off_srec;
   size_t off_ranges, off_tile_last, off_tile_loss;

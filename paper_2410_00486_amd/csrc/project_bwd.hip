@@ -532,9 +532,9 @@ template <int DEG>
 __global__ void __launch_bounds__(kRecThreads) k_project_rec(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, int64_t n, const float* __restrict__ cams, ViewTable vt,
-    const Rec* __restrict__ recs, const uint32_t* __restrict__ tt,
-    const uint32_t* __restrict__ poff, const float* __restrict__ grad_pair,
-    const int32_t* __restrict__ fl, const uint32_t* __restrict__ vis_list,
+    const uint32_t* __restrict__ tt, const uint32_t* __restrict__ poff,
+    const float* __restrict__ grad_pair, const int32_t* __restrict__ fl,
+    const uint32_t* __restrict__ vis_list, const uint32_t* __restrict__ vis_clamp,
     double* __restrict__ terms) {
   const int64_t j = (int64_t)blockIdx.x * kRecThreads + threadIdx.x;
   const int64_t nv = fl[F_OVERFLOW] ? 0 : (int64_t)fl[F_VISIBLE];
@@ -609,7 +609,7 @@ __global__ void __launch_bounds__(kRecThreads) k_project_rec(
   o[10] = g2[0];
   o[11] = g2[1];
   o[12] = g2[2];
-  o[13] = (double)recs[ri].clamp;
+  o[13] = (double)vis_clamp[j];
   double2* dst = reinterpret_cast<double2*>(terms + (int64_t)ri * kTermWords);
 #pragma unroll
   for (int e = 0; e < kTermWords / 2; ++e) dst[e] = make_double2(o[2 * e], o[2 * e + 1]);
@@ -841,10 +841,11 @@ hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float*
 #define GS_PBMV(D)                                                                                \
   do {                                                                                            \
     hipLaunchKernelGGL((k_project_rec<D>), dim3((unsigned)rec_blocks), dim3(kRecThreads), 0, s,    \
-                       g.means, g.log_scales, g.quats, P.n, cams, P.vt, ws_at<Rec>(ws, P.off_rec), \
+                       g.means, g.log_scales, g.quats, P.n, cams, P.vt,                           \
                        ws_at<uint32_t>(ws, P.off_tt), ws_at<uint32_t>(ws, P.off_poff),             \
                        ws_at<float>(ws, P.off_grad_pair), ws_at<int32_t>(ws, P.off_flags),         \
-                       ws_at<uint32_t>(ws, P.off_vis_list), ws_at<double>(ws, P.off_rec_terms));   \
+                       ws_at<uint32_t>(ws, P.off_vis_list), ws_at<uint32_t>(ws, P.off_vis_clamp),  \
+                       ws_at<double>(ws, P.off_rec_terms));                                        \
     hipLaunchKernelGGL(k_project_gauss, dim3((unsigned)gauss_blocks), dim3(kGaussThreads), 0, s,   \
                        g.log_scales, g.quats, g.opacity_logits, P.n, P.vt.n_views,                  \
                        ws_at<uint32_t>(ws, P.off_tt), ws_at<double>(ws, P.off_rec_terms),          \
