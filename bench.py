@@ -521,8 +521,8 @@ def stage_bytes(c, K=16):
         "bin_short_sort": 24 * P,
         "bin_long_sort": 24 * P,
         "forward": 64 * P + 40 * npx,
-        "raster_bwd": 116 * P + 40 * npx,
-        "project_bwd": 44 * N + 12 * K * V + 236 * N + 8 * N + 48 * P,
+        "raster_bwd": 108 * P + 40 * npx,
+        "project_bwd": 44 * N + 12 * K * V + 236 * N + 8 * N + 40 * P,
         "adam": 28 * 59 * N,
     }
 

@@ -82,8 +82,32 @@ struct RecSrc {
 };
 
 // Per-pair gradient partial written by the backward raster kernel:
-// rgb(3), depth, opacity, conic a b c, mean x y (+2 pad), 48 bytes.
-constexpr int kPairGrad = 12;
+// rgb(3), depth, opacity, conic a b c, mean x y: ten floats, 40 bytes, so
+// slots are 8-byte aligned and move as five float2.
+constexpr int kPairGrad = 10;
+struct PairSlot {
+  float4 a, b;  // rgb, depth | opacity, conic a b c
+  float2 c;     // mean x y
+};
+__device__ __forceinline__ PairSlot load_pair(const float* gp, int64_t k) {
+  const float2* p = reinterpret_cast<const float2*>(gp + k * kPairGrad);
+  const float2 p0 = p[0], p1 = p[1], p2 = p[2], p3 = p[3], p4 = p[4];
+  return PairSlot{make_float4(p0.x, p0.y, p1.x, p1.y), make_float4(p2.x, p2.y, p3.x, p3.y), p4};
+}
+// the colour partials alone (the first two float2)
+__device__ __forceinline__ float4 load_pair_colour(const float* gp, int64_t k) {
+  const float2* p = reinterpret_cast<const float2*>(gp + k * kPairGrad);
+  const float2 p0 = p[0], p1 = p[1];
+  return make_float4(p0.x, p0.y, p1.x, p1.y);
+}
+__device__ __forceinline__ void store_pair(float* gp, int64_t k, float4 a, float4 b, float2 c) {
+  float2* p = reinterpret_cast<float2*>(gp + k * kPairGrad);
+  p[0] = make_float2(a.x, a.y);
+  p[1] = make_float2(a.z, a.w);
+  p[2] = make_float2(b.x, b.y);
+  p[3] = make_float2(b.z, b.w);
+  p[4] = c;
+}
 
 struct Plan {
   uint32_t magic;

@@ -223,25 +223,21 @@ __global__ void __launch_bounds__((SPLIT && COMPACT) ? kSumWaves * kWave : kProj
     const uint32_t hi = (uint32_t)(((uint64_t)cnt * (uint32_t)(w + 1)) / kSumWaves);
     double s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (hi > lo) {
-      const float4* gpp = reinterpret_cast<const float4*>(grad_pair + (int64_t)poff[ig] * kPairGrad);
-      auto add = [&](const float4& a, const float4& b, const float4& c) {
-        s[0] += a.x; s[1] += a.y; s[2] += a.z; s[3] += a.w;
-        s[4] += b.x; s[5] += b.y; s[6] += b.z; s[7] += b.w;
-        s[8] += c.x; s[9] += c.y;
+      const float* gpp = grad_pair + (int64_t)poff[ig] * kPairGrad;
+      auto add = [&](const PairSlot& p) {
+        s[0] += p.a.x; s[1] += p.a.y; s[2] += p.a.z; s[3] += p.a.w;
+        s[4] += p.b.x; s[5] += p.b.y; s[6] += p.b.z; s[7] += p.b.w;
+        s[8] += p.c.x; s[9] += p.c.y;
       };
       uint32_t k = lo;
       for (; k + 8 <= hi; k += 8) {
-        float4 a[8], b[8], c[8];
+        PairSlot a[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          a[u] = gpp[3 * (k + u)];
-          b[u] = gpp[3 * (k + u) + 1];
-          c[u] = gpp[3 * (k + u) + 2];
-        }
+        for (int u = 0; u < 8; ++u) a[u] = load_pair(gpp, k + u);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) add(a[u], b[u], c[u]);
+        for (int u = 0; u < 8; ++u) add(a[u]);
       }
-      for (; k < hi; ++k) add(gpp[3 * k], gpp[3 * k + 1], gpp[3 * k + 2]);
+      for (; k < hi; ++k) add(load_pair(gpp, k));
     }
 #pragma unroll
     for (int c = 0; c < 10; ++c) ssum[w][c][lane] = s[c];
@@ -320,31 +316,32 @@ __global__ void __launch_bounds__((SPLIT && COMPACT) ? kSumWaves * kWave : kProj
             if ((DS && c < 3) || (DP && c >= 3))
               g2[c] = ((ssum[0][c][lane] + ssum[1][c][lane]) + ssum[2][c][lane]) + ssum[3][c][lane];
         } else {
-          const float4* gpp = reinterpret_cast<const float4*>(grad_pair + (int64_t)poff_v * kPairGrad);
-          auto add = [&](const float4& a, const float4& b, const float4& c) {
-            if (DS) { g2[0] += a.x; g2[1] += a.y; g2[2] += a.z; }
+          const float* gpp = grad_pair + (int64_t)poff_v * kPairGrad;
+          auto add = [&](const PairSlot& p) {
+            if (DS) { g2[0] += p.a.x; g2[1] += p.a.y; g2[2] += p.a.z; }
             if (DP) {
-              g2[3] += a.w;
-              g2[4] += b.x; g2[5] += b.y; g2[6] += b.z; g2[7] += b.w;
-              g2[8] += c.x; g2[9] += c.y;
+              g2[3] += p.a.w;
+              g2[4] += p.b.x; g2[5] += p.b.y; g2[6] += p.b.z; g2[7] += p.b.w;
+              g2[8] += p.c.x; g2[9] += p.c.y;
             }
           };
-          const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+          // (the colour chain alone reads the colour partials only)
+          auto load = [&](uint32_t kk) {
+            if (DP) return load_pair(gpp, kk);
+            return PairSlot{load_pair_colour(gpp, kk), make_float4(0.f, 0.f, 0.f, 0.f),
+                            make_float2(0.f, 0.f)};
+          };
           // loads of eight pairs are issued before their (in-order) additions,
           // so a large Gaussian does not pay one memory round trip per tile
           uint32_t k = 0;
           for (; k + 8 <= cnt; k += 8) {
-            float4 a[8], b[8], c[8];
+            PairSlot a[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              a[u] = gpp[3 * (k + u)];
-              b[u] = DP ? gpp[3 * (k + u) + 1] : z4;
-              c[u] = DP ? gpp[3 * (k + u) + 2] : z4;
-            }
+            for (int u = 0; u < 8; ++u) a[u] = load(k + u);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) add(a[u], b[u], c[u]);
+            for (int u = 0; u < 8; ++u) add(a[u]);
           }
-          for (; k < cnt; ++k) add(gpp[3 * k], DP ? gpp[3 * k + 1] : z4, DP ? gpp[3 * k + 2] : z4);
+          for (; k < cnt; ++k) add(load(k));
         }
         gop += g2[4];
         const float* c = cams + (int64_t)v * GS_CAMERA_FLOATS;
@@ -543,31 +540,23 @@ __global__ void __launch_bounds__(kRecThreads) k_project_rec(
   const int v = (int)(ri / (uint64_t)n);
   const int64_t i = (int64_t)ri - (int64_t)v * n;
   const uint32_t np = tt[ri];
-  const float4* gp4 = reinterpret_cast<const float4*>(grad_pair + (int64_t)poff[ri] * kPairGrad);
+  const float* gp = grad_pair + (int64_t)poff[ri] * kPairGrad;
   // fixed-order sums of the pair partials: colour 0..2, projection 3..9
   double g2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  auto add = [&](const PairSlot& p) {
+    g2[0] += p.a.x; g2[1] += p.a.y; g2[2] += p.a.z; g2[3] += p.a.w;
+    g2[4] += p.b.x; g2[5] += p.b.y; g2[6] += p.b.z; g2[7] += p.b.w;
+    g2[8] += p.c.x; g2[9] += p.c.y;
+  };
   uint32_t q = 0;
   for (; q + 4 <= np; q += 4) {
-    float4 a[4], b[4], c[4];
+    PairSlot a[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = gp4[3 * (q + u)];
-      b[u] = gp4[3 * (q + u) + 1];
-      c[u] = gp4[3 * (q + u) + 2];
-    }
+    for (int u = 0; u < 4; ++u) a[u] = load_pair(gp, q + u);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      g2[0] += a[u].x; g2[1] += a[u].y; g2[2] += a[u].z; g2[3] += a[u].w;
-      g2[4] += b[u].x; g2[5] += b[u].y; g2[6] += b[u].z; g2[7] += b[u].w;
-      g2[8] += c[u].x; g2[9] += c[u].y;
-    }
+    for (int u = 0; u < 4; ++u) add(a[u]);
   }
-  for (; q < np; ++q) {
-    const float4 a = gp4[3 * q], b = gp4[3 * q + 1], c = gp4[3 * q + 2];
-    g2[0] += a.x; g2[1] += a.y; g2[2] += a.z; g2[3] += a.w;
-    g2[4] += b.x; g2[5] += b.y; g2[6] += b.z; g2[7] += b.w;
-    g2[8] += c.x; g2[9] += c.y;
-  }
+  for (; q < np; ++q) add(load_pair(gp, q));
   // world covariance of the Gaussian
   double qv[4] = {quats[4 * i], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3]};
   const double qn = sqrt(qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3]);

@@ -416,9 +416,8 @@ __device__ __forceinline__ void bwd_tile(
 
   // pairs beyond the last used position get zero gradients
   for (uint32_t k = tl + (uint32_t)lane; k < e - s; k += kWave) {
-    float4* gp = reinterpret_cast<float4*>(grad_pair + (int64_t)sorted_vals[s + k] * kPairGrad);
     const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-    gp[0] = z; gp[1] = z; gp[2] = z;
+    store_pair(grad_pair, sorted_vals[s + k], z, z, make_float2(0.f, 0.f));
   }
 
   // lanes of the first row write the scattered sums of the ten partials;
@@ -527,9 +526,8 @@ __device__ __forceinline__ void bwd_tile(
         const float z = reduce_scatter10(g);
         if (my_idx >= 0) gpf[my_idx] = z * my_scale;
       } else if (lane == 0) {
-        float4* gp = reinterpret_cast<float4*>(gpf);
         const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-        gp[0] = z; gp[1] = z; gp[2] = z;
+        store_pair(gpf, 0, z, z, make_float2(0.f, 0.f));
       }
     }
   }
@@ -662,9 +660,8 @@ __device__ __forceinline__ void splat_wave(
   const uint32_t pos = q0 + (uint32_t)ls;
   const bool live = has && pos < tl;
   if (has && pos < npairs && !live) {  // pairs behind the last used position: zero gradient
-    float4* gp = reinterpret_cast<float4*>(grad_pair + (int64_t)sorted_vals[s + pos] * kPairGrad);
     const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-    gp[0] = z; gp[1] = z; gp[2] = z;
+    store_pair(grad_pair, sorted_vals[s + pos], z, z, make_float2(0.f, 0.f));
   }
   const bool active = has && q0 < tl;  // uniform over the segment
   if (ballot64(active) == 0) return;   // uniform
@@ -824,10 +821,9 @@ __device__ __forceinline__ void splat_wave(
     }
   }
   if (live) {
-    float4* gp = reinterpret_cast<float4*>(grad_pair + (int64_t)sorted_vals[s + pos] * kPairGrad);
-    gp[0] = make_float4(g[0], g[1], g[2], g[3]);
-    gp[1] = make_float4(r.o > 0.0f ? g[4] / r.o : 0.0f, -0.5f * g[5], -g[6], -0.5f * g[7]);
-    gp[2] = make_float4(-(ca * g[8] + cb * g[9]), -(cb * g[8] + cc * g[9]), 0.0f, 0.0f);
+    store_pair(grad_pair, sorted_vals[s + pos], make_float4(g[0], g[1], g[2], g[3]),
+               make_float4(r.o > 0.0f ? g[4] / r.o : 0.0f, -0.5f * g[5], -g[6], -0.5f * g[7]),
+               make_float2(-(ca * g[8] + cb * g[9]), -(cb * g[8] + cc * g[9])));
   }
   __syncthreads();  // the pixel tables are rewritten by the next wave's work
 }
