@@ -726,7 +726,7 @@ __device__ __forceinline__ void splat_wave(
     if (keep) {
       const uint32_t e = kept + (uint32_t)__popcll(m & below);
       sa[e] = a;
-      sb[e] = b;
+      sb[e] = make_float4(b.x - b.w, b.y, b.z, 0.0f);  // (P - Q_in, last, T_in)
       sc[e] = make_double2((double)px + 0.5, (double)py + 0.5);
     }
     kept += (uint32_t)__popcll(m);
@@ -766,7 +766,7 @@ __device__ __forceinline__ void splat_wave(
     bool hit[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      b[u] = sb[j + u];  // P, last, T_in, Q_in of the segment's kept pixel
+      b[u] = sb[j + u];  // P - Q_in, last, T_in of the segment's kept pixel
       const double2 sxy = sc[j + u];
       // alpha as in the forward (same bits)
       const double dx = r.mx - sxy.x, dy = r.my - sxy.y;
@@ -779,9 +779,11 @@ __device__ __forceinline__ void splat_wave(
       // costs two VALU per step)
       hit[u] = live & (pos < __float_as_uint(b[u].y)) & !(pw > 0.0) & (a[u] >= kAlphaMin);
       gc[u] = sa[j + u];
-      const float om = 1.0f - a[u];
-      inv_om[u] = __builtin_amdgcn_rcpf(om);
-      f[u] = hit[u] ? om : 1.0f;
+      // alpha of a blended splat, 0 otherwise: its 1 - alpha is the scan's
+      // factor and alpha T the blend weight, with no further selects
+      a[u] = hit[u] ? a[u] : 0.0f;
+      f[u] = 1.0f - a[u];
+      inv_om[u] = __builtin_amdgcn_rcpf(f[u]);
       dxf[u] = (float)dx;
       dyf[u] = (float)dy;
     }
@@ -793,15 +795,15 @@ __device__ __forceinline__ void splat_wave(
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       Tl[u] = (b[u].z * f[u]) * inv_om[u];
-      wgt[u] = hit[u] ? a[u] * Tl[u] : 0.0f;
+      wgt[u] = a[u] * Tl[u];
       front[u] = fmaf(gc[u].w, r.z, fmaf(gc[u].z, r.b, fmaf(gc[u].y, r.g, gc[u].x * r.r)));
       q[u] = wgt[u] * front[u];
     }
     seg_scan_add2<SEG>(q[0], q[1]);
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const float Qn = b[u].w + q[u];  // front part after the splat
-      const float g_alpha = fmaf(-(b[u].x - Qn), inv_om[u], Tl[u] * front[u]);
+      // behind the splat: P - (Q_in + the front part after the splat)
+      const float g_alpha = fmaf(-(b[u].x - q[u]), inv_om[u], Tl[u] * front[u]);
       g[0] = fmaf(wgt[u], gc[u].x, g[0]);
       g[1] = fmaf(wgt[u], gc[u].y, g[1]);
       g[2] = fmaf(wgt[u], gc[u].z, g[2]);
