@@ -84,7 +84,7 @@ typedef int32_t gs_status;
                                          lists, bit for bit.  The raster kernels
                                          then read each pair's record through its
                                          record id (no copy of the records in list
-                                         order).  About 16 B per record more and
+                                         order).  About 20 B per record more and
                                          52 B per pair of capacity less workspace */
 
 /* Gaussian parameters (Sec. III-B): SoA, float32, device pointers. */

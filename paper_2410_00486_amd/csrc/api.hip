@@ -246,7 +246,7 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_pose_part = take((size_t)n_views * std::max<int64_t>(P->proj_blocks, 1) * 6 * 8);
   P->off_order = take(T * 4);
   P->off_rec_terms = take(n_views > 1 ? nrec * 14 * 8 : 0);
-  P->off_gp_tmp = take(n_views > 1 ? (size_t)n * 3 * 8 : 0);
+  P->off_gp_tmp = take(n_views > 1 ? (size_t)n * 4 * 8 : 0);
   P->off_ssim_maps = take((size_t)pix * 9 * 4);
   P->off_ssim_part = take((size_t)ssim_tiles(*P) * 12 * 4);
   // splat-wise backward: bucket k of tile t uses checkpoint slot boff[t] + k,
@@ -278,6 +278,7 @@ gs_status gs_plan_init(gs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_vi
   P->off_rb_part = take(radix ? (size_t)rb_gen_blocks(P->n_rec) * 4 : 0);
   P->off_rb_pay = take(rrec * 4);   // 16 bytes per visible record, list order
   P->off_rb_spay = take(rrec * 4);  // the same in depth order
+  P->off_rb_zrec = take(rrec);      // depth bits by record id
   P->ws_size = o;
   P->magic = kPlanMagic;
   return GS_OK;

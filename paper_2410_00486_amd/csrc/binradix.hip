@@ -33,7 +33,7 @@ namespace gs {
 namespace {
 
 constexpr int kRbThreads = 256;
-constexpr int kRbItems = 16;
+constexpr int kRbItems = 12;
 constexpr int kRbTile = kRbThreads * kRbItems;  // keys per block
 constexpr int kRbWaves = kRbThreads / kWave;
 constexpr int kRbMaxBits = 9;  // tile passes: 18 bits of tile id in two
@@ -92,7 +92,8 @@ __global__ void __launch_bounds__(256) k_rb_visible(
     const uint2* __restrict__ chunk_pre, int64_t chunks_per_view, int64_t n_chunks,
     const Rec* __restrict__ rec, const uint2* __restrict__ rect, int64_t n,
     const int32_t* __restrict__ fl, uint32_t* __restrict__ vis_list,
-    uint32_t* __restrict__ vis_clamp, uint32_t* __restrict__ dkey, uint4* __restrict__ pay) {
+    uint32_t* __restrict__ vis_clamp, uint32_t* __restrict__ dkey, uint4* __restrict__ pay,
+    uint32_t* __restrict__ zrec) {
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t gw = (int64_t)blockIdx.x * (256 / kWave) + w;  // chunk
   if (gw >= n_chunks) return;
@@ -117,6 +118,7 @@ __global__ void __launch_bounds__(256) k_rb_visible(
     vis_list[vp] = (uint32_t)ri;
     vis_clamp[vp] = cbits;
     dkey[vp] = __float_as_uint(z);
+    zrec[ri] = __float_as_uint(z);
     const uint2 b = rect[ri];
     pay[vp] = make_uint4(b.x, b.y, p0, (uint32_t)ri);
   }
@@ -187,7 +189,7 @@ struct RbEmit {
   uint64_t* keys;          // tile << 32 | depth bits
   uint32_t* vals;          // generation index
   uint32_t* sorted_rec;    // record id
-  const Rec* rec;          // (read for the depth of each pair's record)
+  const uint32_t* zrec;    // depth bits by record id (gathered per pair)
   // the last depth pass instead (spay non-null): the generation payload of
   // each value's record in sorted order, no keys or values
   const uint4* pay;
@@ -365,7 +367,7 @@ __global__ void __launch_bounds__(kRbThreads) k_rb_scatter(
       for (int q = 0; q < kRbItems; ++q) {
         const int i = threadIdx.x + q * kRbThreads;
         rid[q] = i < nloc ? sbuf[i] : 0u;
-        zb[q] = i < nloc ? __float_as_uint(E.rec[rid[q]].z) : 0u;
+        zb[q] = i < nloc ? E.zrec[rid[q]] : 0u;
       }
 #pragma unroll
       for (int q = 0; q < kRbItems; ++q) {
@@ -538,8 +540,8 @@ RbBuffers rb_buffers(const Plan& P, void* ws) {
   B.pay = ws_at<uint4>(ws, P.off_rb_pay);
   B.spay = ws_at<uint4>(ws, P.off_rb_spay);
   B.emit = RbEmit{ws_at<uint64_t>(ws, P.off_keys), ws_at<uint32_t>(ws, P.off_vals),
-                  ws_at<uint32_t>(ws, P.off_sorted_rec), ws_at<Rec>(ws, P.off_rec), nullptr,
-                  nullptr};
+                  ws_at<uint32_t>(ws, P.off_sorted_rec), ws_at<uint32_t>(ws, P.off_rb_zrec),
+                  nullptr, nullptr};
   return B;
 }
 
@@ -582,7 +584,8 @@ hipError_t launch_rb_generate(const Plan& P, void* ws, hipStream_t s) {
   hipLaunchKernelGGL(k_rb_visible, dim3((unsigned)((P.n_chunks + 3) / 4)), dim3(256), 0, s, B.tt,
                      B.poff, ws_at<uint2>(ws, P.off_chunk_pre), P.chunks_per_view, P.n_chunks,
                      ws_at<Rec>(ws, P.off_rec), ws_at<uint2>(ws, P.off_rect), P.n, B.fl, B.vis,
-                     ws_at<uint32_t>(ws, P.off_vis_clamp), B.dk[0], B.pay);
+                     ws_at<uint32_t>(ws, P.off_vis_clamp), B.dk[0], B.pay,
+                     ws_at<uint32_t>(ws, P.off_rb_zrec));
   // depth bits in four 8-bit passes; values: visible-list positions (the
   // first pass takes each key's own position); the last pass writes the
   // records' generation payloads in depth order instead

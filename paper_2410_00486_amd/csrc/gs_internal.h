@@ -147,7 +147,7 @@ struct Plan {
   // ids of the pairs (two each), per-block digit counts, digit totals, and
   // the pair offsets of blocks of depth-sorted records
   size_t off_rb_dkey[2], off_rb_rid[2], off_rb_tkey[2], off_rb_gidx[2], off_rb_ridx[2];
-  size_t off_rb_hist, off_rb_dtot, off_rb_part, off_rb_pay, off_rb_spay;
+  size_t off_rb_hist, off_rb_dtot, off_rb_part, off_rb_pay, off_rb_spay, off_rb_zrec;
   int64_t rb_rec_blocks, rb_pair_blocks;
   size_t ws_size;
 };

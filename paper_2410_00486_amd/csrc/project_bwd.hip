@@ -606,7 +606,8 @@ __global__ void __launch_bounds__(kRecThreads) k_project_rec(
 
 // Projection half per Gaussian: the records' mean, covariance and opacity
 // terms added in view order, then the covariance -> scale / rotation chain;
-// the mean sum waits in gp_tmp for the colour half.
+// the mean sum and the mask of views that see the Gaussian wait in gp_tmp
+// (four words per Gaussian) for the colour half.
 __global__ void __launch_bounds__(kGaussThreads) k_project_gauss(
     const float* __restrict__ log_scales, const float* __restrict__ quats,
     const float* __restrict__ logits, int64_t n, int n_views, const uint32_t* __restrict__ tt,
@@ -637,9 +638,10 @@ __global__ void __launch_bounds__(kGaussThreads) k_project_gauss(
     GS12 += e.x;
     gop += e.y;
   }
-  gp_tmp[3 * i] = gp0;
-  gp_tmp[3 * i + 1] = gp1;
-  gp_tmp[3 * i + 2] = gp2;
+  gp_tmp[4 * i] = gp0;
+  gp_tmp[4 * i + 1] = gp1;
+  gp_tmp[4 * i + 2] = gp2;
+  reinterpret_cast<uint64_t*>(gp_tmp)[4 * i + 3] = mask;
   const float qf0 = quats[4 * i], qf1 = quats[4 * i + 1], qf2 = quats[4 * i + 2], qf3 = quats[4 * i + 3];
   const float lf0 = log_scales[3 * i], lf1 = log_scales[3 * i + 1], lf2 = log_scales[3 * i + 2];
   const float logit = logits[i];
@@ -689,17 +691,12 @@ __global__ void __launch_bounds__(kGaussThreads) k_project_gauss(
 template <int DEG>
 __global__ void __launch_bounds__(kGaussThreads) k_project_colour(
     const float* __restrict__ means, const float* __restrict__ sh, int64_t n,
-    const float* __restrict__ cams, int n_views, const uint32_t* __restrict__ tt,
-    const double* __restrict__ terms, const int32_t* __restrict__ fl, int accumulate,
+    const float* __restrict__ cams, const double* __restrict__ terms, int accumulate,
     const double* __restrict__ gp_tmp, float* __restrict__ g_means, float* __restrict__ g_sh) {
   constexpr int K = (DEG + 1) * (DEG + 1), K3 = 3 * K;
   const int64_t i = (int64_t)blockIdx.x * kGaussThreads + threadIdx.x;
   if (i >= n) return;
-  const bool overflow = fl[F_OVERFLOW] != 0;
-  uint64_t mask = 0;
-  if (!overflow)
-    for (int v = 0; v < n_views; ++v)
-      if (tt[(int64_t)v * n + i] > 0u) mask |= 1ull << v;
+  const uint64_t mask = reinterpret_cast<const uint64_t*>(gp_tmp)[4 * i + 3];
   __shared__ float s_shv[kGaussThreads][K3 + 1];
   float* shv = s_shv[threadIdx.x];
   float acc_sh[K3];
@@ -733,8 +730,8 @@ __global__ void __launch_bounds__(kGaussThreads) k_project_colour(
 #pragma unroll
     for (int e = 0; e < K3; ++e) gdst[e] = acc_sh[e];
   }
-  const double gp0 = gp_tmp[3 * i] + gc0, gp1 = gp_tmp[3 * i + 1] + gc1,
-               gp2 = gp_tmp[3 * i + 2] + gc2;
+  const double gp0 = gp_tmp[4 * i] + gc0, gp1 = gp_tmp[4 * i + 1] + gc1,
+               gp2 = gp_tmp[4 * i + 2] + gc2;
   auto put = [&](float* dst, double val) { *dst = accumulate ? *dst + (float)val : (float)val; };
   put(&g_means[3 * i], gp0);
   put(&g_means[3 * i + 1], gp1);
@@ -842,10 +839,8 @@ hipError_t launch_project_bwd(const Plan& P, const gs_gaussians& g, const float*
                        ws_at<double>(ws, P.off_gp_tmp), out.log_scales, out.quats,                  \
                        out.opacity_logits);                                                         \
     hipLaunchKernelGGL((k_project_colour<D>), dim3((unsigned)gauss_blocks), dim3(kGaussThreads),   \
-                       0, s, g.means, g.sh, P.n, cams, P.vt.n_views,                                \
-                       ws_at<uint32_t>(ws, P.off_tt), ws_at<double>(ws, P.off_rec_terms),          \
-                       ws_at<int32_t>(ws, P.off_flags), accumulate,                                 \
-                       ws_at<double>(ws, P.off_gp_tmp), out.means, out.sh);                         \
+                       0, s, g.means, g.sh, P.n, cams, ws_at<double>(ws, P.off_rec_terms),         \
+                       accumulate, ws_at<double>(ws, P.off_gp_tmp), out.means, out.sh);             \
   } while (0)
 #define GS_PB(D)                \
   if (pose_part) {              \
