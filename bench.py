@@ -40,14 +40,16 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 LRS = {"means": 1.6e-4, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
 # algorithmic FP32 work per (pixel, Gaussian) position revisited by the
-# backward raster pass: alpha recomputation (quadratic form 9, exponent and
-# clamp 4), transmittance undo 2, colour/depth weights 5, front/behind sums
-# 14, alpha gradient 3, behind-sum update 8, opacity/exponent gradient 2,
-# conic and mean gradients 13  -> 60 flops (exp and rcp counted as one each)
-BWD_FLOPS_PER_POS = 60
-# forward: alpha (quadratic form 9, exponent and clamp 4), transmittance 2,
-# weight and colour/depth blend 9, stop test 1 -> 25 flops per position
-FWD_FLOPS_PER_POS = 25
+# backward raster pass: alpha recomputation (exponent's sum of squares 12:
+# two offsets, two axis projections, two scalings, two fused squares; exp,
+# clamp and skip test 3), transmittance undo 2, colour/depth weights 5,
+# front/behind sums 14, alpha gradient 3, behind-sum update 8,
+# opacity/exponent gradient 2, conic and mean gradients 13 -> 62 flops (exp
+# and rcp counted as one each)
+BWD_FLOPS_PER_POS = 62
+# forward: alpha (sum of squares 12; exp, clamp and skip test 3),
+# transmittance 2, weight and colour/depth blend 9, stop test 1 -> 27 flops
+FWD_FLOPS_PER_POS = 27
 # span of gs_iteration_time_marks -> the kernel(s) it holds
 SPAN_KERNELS = {
     "preprocess": "k_preprocess<3>",
@@ -859,7 +861,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (quadratic form and projection in f64)",
+        "dtype": "f32 (2D offsets and projection in f64)",
         "data": "synthetic (seeded indoor rooms shaped like the paper's RGB-D sequences)",
         "config": {"workload": f"{head['workload']}: {n_views} views "
                                f"{head['views'][0][0]}x{head['views'][0][1]} over one pool of "

@@ -158,10 +158,14 @@ int32_t* gs_flags_ptr(const gs_plan* plan, void* ws);
 
 /* Byte offset inside the workspace of an intermediate array, for
  * inspection by tests and tools (-1 for an unknown region):
- *   GS_WS_RECORDS       [n_views*n] 64-byte records: f64 mean x, y; f64
- *                       log2(e) times -a/2, -b, -c/2 of the conic
- *                       [[a,b],[b,c]] (the base-2 exponent's form); f32
- *                       opacity, depth, r, g, b, pad
+ *   GS_WS_RECORDS       [n_views*n] 64-byte records: f64 mean x, y;
+ *                       f32 t, s1, s2, lo, depth, r, g, b, opacity;
+ *                       u32 clamp bits, pad.  With the conic
+ *                       Q = [[a,b],[b,c]] and d = mean - pixel, the
+ *                       splat's opacity x Gaussian is 2^e with
+ *                       e = lo - s1 (dx + t dy)^2 - s2 (dy - t dx)^2
+ *                       = log2(opacity) - log2(e)/2 d^T Q d ((1, t): the
+ *                       footprint axis nearer to x, |t| <= 1)
  *   GS_WS_RECTS         [n_views*n] u16 x0, y0, x1, y1 (tile box, exclusive)
  *   GS_WS_TILES_TOUCHED [n_views*n] u32
  *   GS_WS_PAIR_OFFSETS  [n_views*n] u32, first pair of each visible record

@@ -49,25 +49,46 @@ struct ViewTable {
   ViewInfo v[kMaxViews];
 };
 
-// Projected (view, Gaussian) record, 64 bytes.  The 2D mean and the conic are
-// kept in FP64: the per-pixel quadratic form d^T Sigma'^-1 d is evaluated in
-// FP64 (full rate on CDNA), which removes the cancellation of an FP32
-// evaluation at large pixel coordinates and for elongated footprints.  The
-// conic is stored pre-scaled so that the base-2 exponent of the Gaussian is
-// ca dx^2 + cb dx dy + cc dy^2 (G = 2^that, no rescaling per evaluation),
-// i.e. ca = -a/2 log2(e), cb = -b log2(e), cc = -c/2 log2(e) for the conic
-// [[a, b], [b, c]].
+// Projected (view, Gaussian) record, 64 bytes.  The splat's base-2
+// exponent at offset d = (dx, dy) = mean - sample point is kept in the
+// eigen form of its conic Q = [[a, b], [b, c]]:
+//   log2(o) - log2(e)/2 d^T Q d = lo - s1 (dx + t dy)^2 - s2 (dy - t dx)^2
+// (1, t) is the footprint axis nearer to x (|t| <= 1), (-t, 1) the other,
+// s1, s2 the eigenvalues times log2(e)/2 / (1 + t^2), lo = log2(o).  The
+// offset is formed in FP64 (no cancellation at large pixel coordinates),
+// the rest in FP32 as a sum of squares (no cancellation for elongated
+// footprints).  The forward reads the first 48 bytes of a record per splat.
 struct __align__(16) Rec {
-  double mx, my;
-  double ca, cb;
-  double cc;
-  float o, z;        // opacity, camera-space depth
+  double mx, my;     // 2D mean, pixels
+  float t, s1, s2;   // first axis slope; exponent scales along (1, t), (-t, 1)
+  float lo;          // log2(opacity)
+  float z;           // camera-space depth
   float r, g, b;     // colour after the clamp at 0
+  float o;           // opacity
   uint32_t clamp;    // bit ch set: channel ch was clamped at 0 (no gradient)
+  uint32_t pad[2];
 };
 static_assert(sizeof(Rec) == 64, "record must be 64 bytes");
-constexpr double kLog2e = 1.4426950408889634;  // log2(e): the records' conic scale
+constexpr double kLog2e = 1.4426950408889634;  // log2(e)
 constexpr double kLn2 = 0.6931471805599453;    // ln(2), its inverse
+
+// Base-2 exponent of record r at offset (dx, dy) = mean - sample point (the
+// FP64 difference rounded to FP32): the splat's opacity times its Gaussian
+// is 2^that.  Never above lo <= 0.
+__device__ __forceinline__ float rec_exponent(const Rec& r, float dx, float dy) {
+  const float p = fmaf(r.t, dy, dx), q = fmaf(-r.t, dx, dy);
+  const float u = r.s1 * p, w = r.s2 * q;
+  return fmaf(-u, p, fmaf(-w, q, r.lo));
+}
+
+// The conic [[a, b], [b, c]] of record r (natural exponent -d^T Q d / 2),
+// for the mean gradient.
+__device__ __forceinline__ void rec_conic(const Rec& r, float& a, float& b, float& c) {
+  const float sc = (float)(2.0 * kLn2), tt = r.t * r.t;  // 1 / (log2(e) / 2)
+  a = sc * fmaf(r.s2, tt, r.s1);
+  b = sc * (r.t * (r.s1 - r.s2));
+  c = sc * fmaf(r.s1, tt, r.s2);
+}
 
 // Where the raster kernels read the records of the tile lists: a copy in
 // list order written by the binning (idx null: list position k is base[k]),

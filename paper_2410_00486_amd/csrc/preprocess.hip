@@ -52,8 +52,9 @@ __device__ __forceinline__ void sh_basis(double x, double y, double z, double* Y
 __device__ __forceinline__ bool finite_f(float v) { return __builtin_isfinite(v); }
 
 
+// (three waves per SIMD: at most 168 VGPRs)
 template <int DEG>
-__global__ void __launch_bounds__(256) k_preprocess(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_preprocess(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, int64_t n, const float* __restrict__ cams, ViewTable vt,
@@ -225,11 +226,23 @@ __global__ void __launch_bounds__(256) k_preprocess(
         Rec r;
         r.mx = mx;
         r.my = my;
-        const double idet = 1.0 / det;
-        r.ca = (-0.5 * (C * idet)) * kLog2e;  // (base-2 exponent)
-        r.cb = (B * idet) * kLog2e;
-        r.cc = (-0.5 * (A * idet)) * kLog2e;
+        // eigen form of the conic Q = Sigma'^-1 (FP32 from the FP64
+        // covariance): the covariance's eigenvalues sp >= sm = det / sp; the
+        // axis (1, t) nearer to x has Q's eigenvalue 1/sp when A >= C, else
+        // 1/sm, the other axis the other one
+        const float hc = (float)(0.5 * (A - C)), bf = (float)B;
+        const float rc = sqrtf(fmaf(hc, hc, bf * bf));
+        const float sp = (float)(0.5 * (A + C)) + rc, df = (float)det;
+        const bool xl = hc >= 0.0f;
+        const float t = rc > 0.0f ? bf / (xl ? hc + rc : hc - rc) : 0.0f;
+        // log2(e)/2 / (1 + t^2) / (sp det): 1/sp = that x det, 1/sm = that x sp^2
+        const float g = (float)(0.5 * kLog2e) / (fmaf(t, t, 1.0f) * (sp * df));
+        r.t = t;
+        r.s1 = xl ? g * df : g * (sp * sp);
+        r.s2 = xl ? g * (sp * sp) : g * df;
+        r.lo = log2f((float)o);
         r.o = (float)o;
+        r.pad[0] = r.pad[1] = 0u;
         r.z = (float)tz;
         r.r = rgb[0];
         r.g = rgb[1];

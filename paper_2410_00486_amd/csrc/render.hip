@@ -27,17 +27,14 @@ constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTMin = 1e-4f;
 
-// alpha of record r at sample point (sx, sy).  Returns false when the
-// Gaussian is skipped (positive exponent or alpha < 1/255).  The quadratic
-// form is evaluated in FP64; the exponential in FP32.
+// alpha of record r at sample point (sx, sy): oG = opacity x Gaussian, a =
+// oG clamped at 0.99.  Returns false when the Gaussian is skipped (alpha
+// below 1/255; its exponent is never positive).
 __device__ __forceinline__ bool eval_alpha(const Rec& r, double sx, double sy, double& dx,
-                                           double& dy, float& G, float& oG, float& a) {
+                                           double& dy, float& oG, float& a) {
   dx = r.mx - sx;
   dy = r.my - sy;
-  const double pw = fma(dx, fma(r.ca, dx, r.cb * dy), (r.cc * dy) * dy);
-  if (pw > 0.0) return false;
-  G = __builtin_amdgcn_exp2f((float)pw);
-  oG = r.o * G;
+  oG = __builtin_amdgcn_exp2f(rec_exponent(r, (float)dx, (float)dy));
   a = fminf(kAlphaMax, oG);
   return a >= kAlphaMin;
 }
@@ -253,20 +250,19 @@ __device__ __forceinline__ void fwd_tile(int gtile, RecSrc lrec,
         const uint32_t pos0 = b - s + (uint32_t)j + 1u;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
-          double pw[NS];
           float au[NS];
 #pragma unroll
           for (int u = 0; u < NS; ++u) {
             const double dx = rr[u].mx - sx[k], dy = rr[u].my - sy[k];
-            pw[u] = fma(dx, fma(rr[u].ca, dx, rr[u].cb * dy), (rr[u].cc * dy) * dy);
-            au[u] = fminf(kAlphaMax, rr[u].o * __builtin_amdgcn_exp2f((float)pw[u]));
+            au[u] = fminf(kAlphaMax,
+                          __builtin_amdgcn_exp2f(rec_exponent(rr[u], (float)dx, (float)dy)));
           }
           // a splat that is not blended gets weight 0: colour, depth are
           // non-negative and finite, so fma(x, 0, acc) leaves acc as it is
           // and one select replaces four
 #pragma unroll
           for (int u = 0; u < NS; ++u) {
-            const bool hit = hasu[u] && !done[k] && !(pw[u] > 0.0) && au[u] >= kAlphaMin;
+            const bool hit = hasu[u] && !done[k] && au[u] >= kAlphaMin;
             const float w0 = au[u] * T[k];
             const float Tn = T[k] - w0;  // T (1 - alpha)
             const bool stop = Tn < kTMin;
@@ -478,6 +474,8 @@ __device__ __forceinline__ void bwd_tile(
     for (int j = nb - 1; j >= 0; --j) {
       const uint32_t pos = (uint32_t)(bstart + j);
       const Rec& r = srec[j];
+      float ca, cb, cc;
+      rec_conic(r, ca, cb, cc);
       float g[10];
 #pragma unroll
       for (int f = 0; f < 10; ++f) g[f] = 0.0f;
@@ -486,8 +484,8 @@ __device__ __forceinline__ void bwd_tile(
       for (int k = 0; k < PPL; ++k) {
         if (pos < L[k]) {
           double dx, dy;
-          float G, oG, a;
-          if (eval_alpha(r, sx[k], sy[k], dx, dy, G, oG, a)) {
+          float oG, a;
+          if (eval_alpha(r, sx[k], sy[k], dx, dy, oG, a)) {
             contrib = true;
             const float inv_om = __builtin_amdgcn_rcpf(1.0f - a);
             const float Tk = T[k] * inv_om;
@@ -510,9 +508,8 @@ __device__ __forceinline__ void bwd_tile(
             const bool open = oG <= kAlphaMax;
             const float gpow = open ? a * g_alpha : 0.0f;
             const float fx = (float)dx, fy = (float)dy;
-            const float ca = (float)(-2.0 * kLn2 * r.ca), cb = (float)(-kLn2 * r.cb), cc = (float)(-2.0 * kLn2 * r.cc);
             const float t = gpow * fx, u = gpow * fy;
-            g[4] = fmaf(open ? G : 0.0f, g_alpha, g[4]);
+            g[4] += gpow;  // (divided by the opacity at the store)
             g[5] = fmaf(t, fx, g[5]);
             g[6] = fmaf(t, fy, g[6]);
             g[7] = fmaf(u, fy, g[7]);
@@ -524,7 +521,8 @@ __device__ __forceinline__ void bwd_tile(
       float* gpf = grad_pair + (int64_t)sval[j] * kPairGrad;
       if (ballot64(contrib) != 0) {
         const float z = reduce_scatter10(g);
-        if (my_idx >= 0) gpf[my_idx] = z * my_scale;
+        const float sc = my_idx == 4 ? (r.o > 0.0f ? 1.0f / r.o : 0.0f) : my_scale;
+        if (my_idx >= 0) gpf[my_idx] = z * sc;
       } else if (lane == 0) {
         const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
         store_pair(gpf, 0, z, z, make_float2(0.f, 0.f));
@@ -750,11 +748,13 @@ __device__ __forceinline__ void splat_wave(
     float4* dst = reinterpret_cast<float4*>(&r);
     dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2]; dst[3] = src[3];
   } else {
-    r.mx = r.my = 0.0; r.ca = r.cb = r.cc = 0.0;
+    r.mx = r.my = 0.0;
+    r.t = r.s1 = r.s2 = r.lo = 0.0f;
     r.o = r.z = r.r = r.g = r.b = 0.0f;
-    r.clamp = 0u;
+    r.clamp = r.pad[0] = r.pad[1] = 0u;
   }
-  const float ca = (float)(-2.0 * kLn2 * r.ca), cb = (float)(-kLn2 * r.cb), cc = (float)(-2.0 * kLn2 * r.cc);
+  float ca, cb, cc;
+  rec_conic(r, ca, cb, cc);
   float g[10];
 #pragma unroll
   for (int f = 0; f < 10; ++f) g[f] = 0.0f;
@@ -762,30 +762,27 @@ __device__ __forceinline__ void splat_wave(
   // interleaved; each lane accumulates pixel j before pixel j + 1
   for (int j = 0; j < nsteps; j += 2) {
     float4 b[2], gc[2];
-    float dxf[2], dyf[2], G[2], oG[2], a[2], inv_om[2], f[2];
+    float dxf[2], dyf[2], oG[2], a[2], inv_om[2], f[2];
     bool hit[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       b[u] = sb[j + u];  // P - Q_in, last, T_in of the segment's kept pixel
       const double2 sxy = sc[j + u];
       // alpha as in the forward (same bits)
-      const double dx = r.mx - sxy.x, dy = r.my - sxy.y;
-      const double pw = fma(dx, fma(r.ca, dx, r.cb * dy), (r.cc * dy) * dy);
-      G[u] = __builtin_amdgcn_exp2f((float)pw);
-      oG[u] = r.o * G[u];
+      dxf[u] = (float)(r.mx - sxy.x);
+      dyf[u] = (float)(r.my - sxy.y);
+      oG[u] = __builtin_amdgcn_exp2f(rec_exponent(r, dxf[u], dyf[u]));
       a[u] = fminf(kAlphaMax, oG[u]);
       // (no short-circuit: every term is evaluated, so nothing branches; no
       // early exit when no lane is blended at a pixel: rare, and its test
       // costs two VALU per step)
-      hit[u] = live & (pos < __float_as_uint(b[u].y)) & !(pw > 0.0) & (a[u] >= kAlphaMin);
+      hit[u] = live & (pos < __float_as_uint(b[u].y)) & (a[u] >= kAlphaMin);
       gc[u] = sa[j + u];
       // alpha of a blended splat, 0 otherwise: its 1 - alpha is the scan's
       // factor and alpha T the blend weight, with no further selects
       a[u] = hit[u] ? a[u] : 0.0f;
       f[u] = 1.0f - a[u];
       inv_om[u] = __builtin_amdgcn_rcpf(f[u]);
-      dxf[u] = (float)dx;
-      dyf[u] = (float)dy;
     }
     // transmittance in front of the splat: the segment's inclusive product
     // over its blended splats with the lane's own factor taken out again

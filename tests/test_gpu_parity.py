@@ -45,16 +45,23 @@ def test_preprocess_records_match_oracle(cfg):
     np.testing.assert_array_equal((tt > 0), vis)
     np.testing.assert_array_equal(tt[~edge], ref["tiles_touched"][~edge])
     np.testing.assert_array_equal(rects[vis & ~edge].astype(np.int32), ref["rect"][vis & ~edge])
-    d = rec[vis, :40].copy().view(np.float64).reshape(-1, 5)
-    f = rec[vis, 40:60].copy().view(np.float32).reshape(-1, 5)
-    np.testing.assert_allclose(d[:, 0:2], ref["mean2d"][vis], rtol=1e-12, atol=1e-9)
-    con = ref["conic"][vis] * np.log2(np.e)  # (stored as the base-2 exponent's form)
-    np.testing.assert_allclose(d[:, 2], -0.5 * con[:, 0], rtol=1e-9)
-    np.testing.assert_allclose(d[:, 3], -con[:, 1], rtol=1e-9, atol=1e-12 * np.abs(con).max())
-    np.testing.assert_allclose(d[:, 4], -0.5 * con[:, 2], rtol=1e-9)
-    np.testing.assert_array_equal(f[:, 1], ref["depth32"][vis])
-    np.testing.assert_allclose(f[:, 0], ref["opacity"][vis], rtol=1.2e-7)
-    np.testing.assert_allclose(f[:, 2:5], ref["rgb"][vis], rtol=1.2e-7, atol=1e-12)
+    d = rec[vis, :16].copy().view(np.float64).reshape(-1, 2)
+    f = rec[vis, 16:52].copy().view(np.float32).reshape(-1, 9).astype(np.float64)
+    np.testing.assert_allclose(d, ref["mean2d"][vis], rtol=1e-12, atol=1e-9)
+    # the exponent's eigen form, in FP32: with the oracle's conic
+    # [[a, b], [b, c]], log2(e)/2 d^T Q d = s1 (dx + t dy)^2 + s2 (dy - t dx)^2,
+    # |t| <= 1; the conic it stands for is compared (the form is not unique
+    # when the footprint's axes lie at 45 degrees), to a few FP32 roundings
+    con = ref["conic"][vis]
+    t, s1, s2 = f[:, 0], f[:, 1], f[:, 2]
+    assert (np.abs(t) <= 1.0).all() and (s1 > 0).all() and (s2 > 0).all()
+    got = np.stack([s1 + s2 * t * t, t * (s1 - s2), s1 * t * t + s2], axis=1) / (0.5 * np.log2(np.e))
+    err = np.abs(got - con) / np.abs(con).max(axis=1, keepdims=True)
+    assert err.max() <= 1e-6, err.max()
+    np.testing.assert_allclose(f[:, 3], np.log2(ref["opacity"][vis]), rtol=2e-7, atol=1e-7)
+    np.testing.assert_array_equal(f[:, 4], ref["depth32"][vis])
+    np.testing.assert_allclose(f[:, 5:8], ref["rgb"][vis], rtol=1.2e-7, atol=1e-12)
+    np.testing.assert_allclose(f[:, 8], ref["opacity"][vis], rtol=1.2e-7)
     flags = plan.flags_of(ws)
     assert flags[L.F_VISIBLE] == vis.sum() and flags[L.F_NONFINITE] == 0
 
@@ -717,6 +724,29 @@ def test_overflow_iteration_leaves_optimizer_state_unchanged(views, graph):
             assert torch.equal(a, b), rep
         assert int(it.step_dev.item()) == 5
     it.close()
+
+
+@pytest.mark.parametrize("flags", [0, L.GS_SPLAT_BWD])
+def test_elongated_footprints_match_oracle(flags):
+    """Needle-like Gaussians (axis ratios near 100, so 2D conics with
+    eigenvalue ratios in the thousands, long axes tens of pixels, every
+    orientation): forward and gradients within the same tolerances.  The
+    exponent is a sum of squares along the footprint's axes, so its error
+    does not grow with the elongation."""
+    w = scenes.tiny_scene(41, n=40, width=128, height=96, degree=1, f=120.0)
+    sc = w.scene.copy()
+    sc.log_scales[:, 0] += np.float32(2.5)
+    sc.log_scales[:, 1] -= np.float32(2.0)
+    sc.log_scales[:, 2] -= np.float32(2.0)
+    cam = w.cameras[0]
+    gc, gd = scenes.linear_loss_weights(42, [cam])
+    print(f"elongated footprints, flags {flags}", flush=True)
+    it = run_gpu(sc, [cam], tile=(8, 8), dL_dcolor=gc, dL_ddepth=gd, flags=flags)
+    ref = oracle.render(sc, cam, (8, 8))
+    col, dep, _, _ = view_images(it, 0)
+    assert_forward_close(col, dep, ref)
+    grads, _, exclude, _ = oracle_reference(sc, [cam], gc, gd, (8, 8))
+    assert_grads_close(grads_np(it), grads, exclude)
 
 
 def test_ragged_view_and_large_gaussian_and_sh_degrees():
