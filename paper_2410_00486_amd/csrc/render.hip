@@ -328,7 +328,7 @@ __device__ __forceinline__ void fwd_tile(int gtile, RecSrc lrec,
 }
 
 template <int TW, int TH, bool CKPT>
-__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(TW * TH == 64 ? 6 : 1))) k_render_fwd(
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(TW * TH == 64 ? 7 : 1))) k_render_fwd(
     RecSrc lrec,
     const uint32_t* __restrict__ ranges, const float* __restrict__ cams, ViewTable vt, int B,
     float* __restrict__ color, float* __restrict__ depth, float* __restrict__ T_final,
